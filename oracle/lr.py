@@ -1,0 +1,213 @@
+"""Oracle for the encrypted logistic-regression gradient step.
+
+TEST INFRASTRUCTURE ONLY (see package docstring).
+
+What is computed (paper Sec. 4): the linear-model gradient of eq. (obj)
+linearised as in eq. (appr), sum_i y_i * p(y_i w.x_i) * x_i with the Table 2
+polynomial p, followed by the update of eq. (update); Alg. 1 runs it on
+encrypted data packed into blocks (Sec. 3, the packing of Han et al.).
+
+Readings where the paper is silent (each listed in the design notes):
+  * p approximates -L'(m) (Table 2's rows are positive at 0), so the step adds:
+    w' = w + g,  g = (eta/n) sum_i p(m_i) z_i,  z_i = y_i x_i,  m_i = w.z_i.
+  * packing: block b holds rows b*r .. b*r+r-1 of Z = y (.) X row-major, slot
+    i*c + j = z_{b*r+i, j}; columns padded to c = 2^ceil(log2 d); W holds w in
+    every row.
+  * the per-block circuit is: u = Z (x) W; column sum by rotations 1..c/2;
+    mask column 0; replicate by rotations -1..-c/2 (M holds m_i in row i);
+    A = M^2, B3 = M * (a3 Z), B1 = M * (a1 Z); C = A * B3;
+    G_b = C + a1-term + a0 Z; cross-block sum; row sum by rotations c..(r/2)c.
+  * eta/n enters through the scale bookkeeping (an exact FP64 change of the
+    declared scale), and W is brought to the gradient's scale by one integer
+    multiplication and rescale, both fixed by plan_lr_step below.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+
+from . import ckks as O
+
+
+# ---------------------------------------------------------------- plaintext reference
+def sigmoid(x):
+    return 1.0 / (1.0 + np.exp(-x))
+
+
+def ls_fit(f, bound, degree, nodes=400):
+    """Least-squares polynomial fit of f on [-bound, bound] (eq. (3) with the
+    sample points' uniform law taken to its continuous limit): minimise
+    int (f - p)^2 dx over polynomials of the given degree.  Gram matrix of the
+    monomials in closed form; right-hand side by Gauss-Legendre quadrature.
+    Returns coefficients a_0..a_degree (lowest first)."""
+    B = float(bound)
+    G = np.zeros((degree + 1, degree + 1))
+    for i in range(degree + 1):
+        for j in range(degree + 1):
+            k = i + j
+            G[i, j] = 0.0 if k % 2 else 2.0 * B ** (k + 1) / (k + 1)
+    x, w = np.polynomial.legendre.leggauss(nodes)
+    x = x * B
+    w = w * B
+    fx = f(x)
+    rhs = np.array([np.sum(w * fx * x ** i) for i in range(degree + 1)])
+    return np.linalg.solve(G, rhs)
+
+
+def grad_poly_binomial(bound=8.0):
+    """Degree-3 least-squares fit of sigma(-m) = -L'(m) for the binomial
+    deviance L(m) = log(1 + exp(-m)) (Table 1 / Table 2)."""
+    return ls_fit(lambda x: sigmoid(-x), bound, 3)
+
+
+def lr_gradient_fp64(X, y, w, coef, eta_over_n):
+    """g = (eta/n) sum_i p(m_i) y_i x_i with m_i = y_i w.x_i (FP64)."""
+    z = y[:, None] * X
+    m = z @ w
+    p = coef[0] + coef[1] * m + coef[2] * m * m + coef[3] * m * m * m
+    return eta_over_n * (p[:, None] * z).sum(axis=0)
+
+
+# ---------------------------------------------------------------- packing
+def pack_blocks(X, y, S):
+    """Row-major block packing of Z = y (.) X.  Returns (blocks [B][S] float64, c, r)."""
+    n, d = X.shape
+    c = 1 << max(0, math.ceil(math.log2(d)))
+    r = S // c
+    B = (n + r - 1) // r
+    Z = np.zeros((B * r, c))
+    Z[:n, :d] = y[:, None] * X
+    return Z.reshape(B, r * c), c, r
+
+
+def pack_weights(w, S, c):
+    v = np.zeros(c)
+    v[: w.shape[0]] = w
+    return np.tile(v, S // c)
+
+
+def column_mask(S, c):
+    m = np.zeros(S)
+    m[::c] = 1.0
+    return m
+
+
+# ---------------------------------------------------------------- scale plan
+class ScaleError(ValueError):
+    pass
+
+
+class LevelError(ValueError):
+    pass
+
+
+def llround(x):
+    """C llround: nearest integer, halves away from zero (exact on FP64)."""
+    fx = Fraction(x)
+    fl = math.floor(fx)
+    fr = fx - fl
+    if fr > Fraction(1, 2) or (fr == Fraction(1, 2) and fx > 0):
+        fl += 1
+    return int(fl)
+
+
+K_MAX = 2 ** 62
+
+
+def term_scale(coef):
+    """Target scale T of the gradient terms: the power of two with
+    T * min(|a1|, |a3|) in [2^22, 2^23) (a nonzero coefficient is required)."""
+    nz = [abs(a) for a in (coef[1], coef[3]) if a != 0.0]
+    if not nz:
+        raise ScaleError("polynomial needs a nonzero a1 or a3")
+    _, e = math.frexp(min(nz))
+    return math.ldexp(1.0, 23 - e)
+
+
+def plan_lr_step(q, level, s_Z, s_W, coef, eta_over_n):
+    """FP64 scale schedule of one gradient step at W's level `level`.
+    Every expression is evaluated left to right exactly as written."""
+    if level < 4:
+        raise LevelError("a gradient step needs 4 levels; W is at level %d" % level)
+    if coef[2] != 0.0:
+        raise ScaleError("a nonzero x^2 coefficient is not supported by this circuit")
+    ql = float(q[level])
+    ql1 = float(q[level - 1])
+    ql2 = float(q[level - 2])
+    ql3 = float(q[level - 3])
+    s1 = s_Z * s_W / ql
+    s_mask = ql2 * ql1 / s1
+    sM = s1 * s_mask / ql1
+    sA = sM * sM / ql2
+    T = term_scale(coef)
+    sZ3 = T * ql3 / sA * ql2 / sM
+    k3 = llround(coef[3] * sZ3 * ql1 / s_Z)
+    sB3 = sM * sZ3 / ql2
+    sC = sA * sB3 / ql3
+    sZ1 = sZ3
+    k1 = llround(coef[1] * sZ1 * ql1 / s_Z)
+    sB1 = sM * sZ1 / ql2
+    kB1 = llround(sC * ql3 / sB1)
+    k0 = llround(coef[0] * sC * ql3 / s_Z)
+    s_g = sC / eta_over_n
+    kW = llround(s_g * ql3 / s_W)
+    for name, k in (("k0", k0), ("k1", k1), ("k3", k3), ("kB1", kB1), ("kW", kW)):
+        if abs(k) >= K_MAX:
+            raise ScaleError("%s = %d out of range" % (name, k))
+    return dict(level=level, s1=s1, s_mask=s_mask, sM=sM, sA=sA, T=T, sZ3=sZ3, k3=k3, sB3=sB3,
+                sC=sC, sZ1=sZ1, k1=k1, sB1=sB1, kB1=kB1, k0=k0, s_g=s_g, kW=kW,
+                level_out=level - 4)
+
+
+def rotation_steps(c, r):
+    """Rotation steps used by the step: +-2^k (k < log2 c) and c*2^k (k < log2 r)."""
+    st = []
+    t = 1
+    while t < c:
+        st += [t, -t]
+        t *= 2
+    t = 1
+    while t < r:
+        st.append(t * c)
+        t *= 2
+    return st
+
+
+# ---------------------------------------------------------------- encrypted step
+def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None):
+    """One step of eq. (appr) + eq. (update) on ciphertexts (coefficient form).
+    Z: list of block ciphertexts (same level >= W.level, same scale);
+    W: weight ciphertext; mask_m: integer plaintext of column_mask at scale
+    plan['s_mask'].  Returns (W', g)."""
+    l = W.level
+    pl = plan or plan_lr_step(P.q, l, Z[0].scale, W.scale, coef, eta_over_n)
+    G = None
+    for zb in Z:
+        zl = O.drop(zb, l)
+        u = O.rescale(P, O.mul(P, zl, W, keys), scale=pl["s1"])
+        t = 1
+        while t < c:
+            u = O.add(P, u, O.rotate(P, u, t, keys))
+            t *= 2
+        M = O.rescale(P, O.mul_plain(P, u, mask_m, pl["s_mask"]), scale=pl["sM"])
+        t = 1
+        while t < c:
+            M = O.add(P, M, O.rotate(P, M, -t, keys))
+            t *= 2
+        A = O.rescale(P, O.mul(P, M, M, keys), scale=pl["sA"])
+        Z3 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 1), pl["k3"]), scale=pl["sZ3"])
+        B3 = O.rescale(P, O.mul(P, M, Z3, keys), scale=pl["sB3"])
+        Z1 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 1), pl["k1"]), scale=pl["sZ1"])
+        B1 = O.rescale(P, O.mul(P, M, Z1, keys), scale=pl["sB1"])
+        C = O.rescale(P, O.mul(P, A, B3, keys), scale=pl["sC"])
+        B1p = O.rescale(P, O.mul_int(P, B1, pl["kB1"]), scale=pl["sC"])
+        Z0p = O.rescale(P, O.mul_int(P, O.drop(zb, l - 3), pl["k0"]), scale=pl["sC"])
+        Gb = O.add(P, O.add(P, C, B1p), Z0p)
+        G = Gb if G is None else O.add(P, G, Gb)
+    t = 1
+    while t < r:
+        G = O.add(P, G, O.rotate(P, G, t * c, keys))
+        t *= 2
+    g = O.CT(G.data, G.level, pl["s_g"])
+    Wn = O.rescale(P, O.mul_int(P, O.drop(W, l - 3), pl["kW"]), scale=pl["s_g"])
+    return O.add(P, Wn, g), g
