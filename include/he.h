@@ -1,0 +1,253 @@
+/*
+ * he.h -- C ABI of libhe: RNS-CKKS arithmetic and the encrypted logistic-
+ * regression gradient step on one AMD Instinct MI355X (gfx950).
+ *
+ * What it implements.  The paper (Li & Huang, "Faster Secure Data Mining via
+ * Distributed Homomorphic Encryption", KDD'20) trains linear models on data
+ * that a parameter server encrypted with HEAAN; each worker evaluates the
+ * linearised gradient step of eq. (appr) + eq. (update) on its encrypted shard
+ * (Alg. 1) and sends the encrypted weights back for a refresh every l steps
+ * (Alg. 2).  The library provides the operations Sec. 3 ("Preliminary") lists --
+ * encode/decode, key generation, encrypt/decrypt, add, multiply, rescale --
+ * plus the rotation the block packing needs, and the whole step of eq. (appr)
+ * on one worker's shard.
+ *
+ * Conventions shared by every entry point.
+ *   Memory.   Ciphertexts, plaintexts and key buffers are device memory OWNED
+ *             BY THE CALLER (allocated, for example, with torch); the library
+ *             never frees them.  The context owns only its precomputed tables
+ *             and a scratch workspace (hipMalloc, grown on demand outside any
+ *             graph capture, freed by he_ctx_destroy).
+ *   Layout.   A ciphertext at level l is uint64 [2][l+1][N], limb-major (limb i
+ *             of component c at element offset (c*(l+1)+i)*N), values in
+ *             [0, q_i), in the library's private NTT order.  A plaintext at
+ *             level l is uint64 [l+1][N] in the same order.  The canonical
+ *             exchange form (he_ct_download / he_ct_upload) is coefficient
+ *             order, residues in [0, q_i).
+ *   Streams.  Every call is asynchronous on the context's HIP stream
+ *             (he_ctx_set_stream); outputs are valid after that stream is
+ *             synchronised.  Calls that return host data synchronise it.
+ *   Threads.  One context per stream; a context is not thread-safe.
+ *   Errors.   No exception crosses the ABI.  Every metadata check (levels,
+ *             scales, keys, sizes) is made on the host BEFORE any launch, so a
+ *             call that returns an error has launched nothing.
+ *   In place. he_rescale and he_add accept out == in.
+ */
+#ifndef HE_H
+#define HE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HE_OK = 0,
+    HE_EINVAL = 1,  /* bad argument, size or layout */
+    HE_ENOMEM = 2,  /* device or host allocation failed */
+    HE_ELEVEL = 3,  /* not enough levels / level mismatch */
+    HE_ESCALE = 4,  /* scale mismatch or scale plan out of range */
+    HE_EKEY = 5,    /* required evaluation key absent */
+    HE_EDEVICE = 6  /* HIP runtime error */
+} he_status;
+
+/*
+ * Scheme parameters (the paper fixes none; it names only the ring order N and
+ * the modulus magnitude M and their trade-off, Sec. 3).
+ *   log_n      ring degree N = 2^log_n, 10 <= log_n <= 16
+ *   n_q        ciphertext primes q_0..q_{n_q-1} (top level L = n_q-1), 2..40
+ *   n_special  special primes for key switching, 1..12
+ *   alpha      primes per key-switching digit (dnum = ceil(n_q/alpha)), alpha <= n_special
+ *   log_delta  log2 of the default scale, 20..50
+ * Prime rule: every prime is 1 mod 2^17; specials are the n_special largest
+ * below 2^60; q_0 the largest below 2^min(60, log_delta+20); q_1.. the n_q-1
+ * closest to 2^log_delta by increasing distance (ties: smaller first).
+ */
+typedef struct {
+    int32_t log_n;
+    int32_t n_q;
+    int32_t n_special;
+    int32_t alpha;
+    int32_t log_delta;
+} he_params;
+
+typedef struct he_ctx he_ctx;
+typedef struct he_keys he_keys;
+
+/* Ciphertext (Sec. 3: a pair of ring elements).  data: device [2][level+1][N]. */
+typedef struct {
+    uint64_t *data;
+    int32_t level;
+    int32_t reserved;
+    double scale;
+} he_ct;
+
+/* Plaintext: device [level+1][N], NTT order, with its encoding scale. */
+typedef struct {
+    uint64_t *data;
+    int32_t level;
+    int32_t reserved;
+    double scale;
+} he_pt;
+
+/* Degree-2 ciphertext (d0, d1, d2) of a product before relinearisation. */
+typedef struct {
+    uint64_t *data; /* device [3][level+1][N] */
+    int32_t level;
+    int32_t reserved;
+    double scale;
+} he_ct3;
+
+/* Scale schedule of one gradient step (pure host; see he_plan_lr_step). */
+typedef struct {
+    int32_t level_in, level_out;
+    double s1, s_mask, s_m, s_a, t, s_z3, s_b3, s_c, s_z1, s_b1, s_g;
+    int64_t k0, k1, k3, kb1, kw;
+} he_lr_plan;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context: prime chain, roots, twiddle and basis-conversion tables
+ * (device).  hip_stream: a hipStream_t (NULL = default stream).  Errors:
+ * HE_EINVAL on parameters out of range, HE_EDEVICE/HE_ENOMEM from HIP. */
+he_status he_ctx_create(const he_params *prm, void *hip_stream, he_ctx **out);
+he_status he_ctx_destroy(he_ctx *ctx);
+he_status he_ctx_set_stream(he_ctx *ctx, void *hip_stream);
+/* Copy the prime chain (q_0..q_{n_q-1}, then the specials) to host memory;
+ * n must be >= n_q + n_special. */
+he_status he_ctx_primes(const he_ctx *ctx, uint64_t *out, int n);
+/* Pure host (no device): the prime chain the parameters select, as above;
+ * n must be >= n_q + n_special.  HE_EINVAL on parameters out of range. */
+he_status he_params_primes(const he_params *prm, uint64_t *out, int n);
+/* Release the context's scratch workspace (it is re-grown on demand). */
+he_status he_ctx_trim(he_ctx *ctx);
+
+/* Bytes of a ciphertext / plaintext / degree-2 ciphertext at a level. */
+size_t he_ct_bytes(const he_ctx *ctx, int level);
+size_t he_pt_bytes(const he_ctx *ctx, int level);
+size_t he_ct3_bytes(const he_ctx *ctx, int level);
+
+/* ---------------------------------------------------------------- keys */
+
+/* Bytes of the key buffer for n_rot rotation keys (secret key, relinearisation
+ * key and the rotation keys, each evaluation key [dnum][2][n_q+n_special][N]). */
+size_t he_keys_bytes(const he_ctx *ctx, int n_rot);
+
+/* Key generation (Alg. 2, initialisation: the server generates the keys).
+ * The secret is ternary with 64 nonzero coefficients; the relinearisation key
+ * is for s^2 and one rotation key is made per entry of rot_steps (a left
+ * rotation of the slot vector by that many slots, Galois element 5^t mod 2N).
+ * Randomness: ChaCha20 keyed by seed.  key_buf: caller device memory of at
+ * least he_keys_bytes(ctx, n_rot) bytes; *out is a host handle referencing it
+ * (free with he_keys_destroy; the buffer stays the caller's). */
+he_status he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *rot_steps, int n_rot,
+                    void *key_buf, size_t key_buf_bytes, he_keys **out);
+he_status he_keys_destroy(he_keys *keys);
+/* Download a key for inspection, coefficient order: which = -2 secret
+ * ([n_q+n_special][N]), -1 relinearisation key, else the Galois element of a
+ * rotation key ([dnum][2][n_q+n_special][N]).  host must hold the size. */
+he_status he_keys_download(he_ctx *ctx, const he_keys *keys, int64_t which, uint64_t *host);
+
+/* ---------------------------------------------------------------- encoding (host FP64) */
+
+/* Canonical-embedding encode (Sec. 3, encode/decode): slot j of the complex
+ * vector (re[j] + i*im[j], j < n_slots <= N/2, the rest zero) is the value at
+ * the root zeta^(5^j), zeta = exp(i*pi/N); coefficients are scale*m rounded half
+ * away from zero into coeffs[N] (host).  im may be NULL.  HE_EINVAL when a
+ * coefficient does not fit in int64. */
+he_status he_encode(he_ctx *ctx, const double *re, const double *im, int n_slots, double scale,
+                    int64_t *coeffs);
+/* Decode host integer coefficients (as doubles) at a scale into n_slots slots. */
+he_status he_decode(he_ctx *ctx, const double *coeffs, double scale, int n_slots, double *re,
+                    double *im);
+
+/* Integer coefficients (host int64[N]) -> plaintext at a level (device, NTT). */
+he_status he_pt_load(he_ctx *ctx, const int64_t *coeffs, int level, double scale, he_pt *out);
+
+/* ---------------------------------------------------------------- encryption */
+
+/* Secret-key encryption (Alg. 2: the server encrypts data and weights with sk):
+ * (-a*s + e + m, a), a uniform, e centered binomial (21 pairs); stream index
+ * `index` separates ciphertexts made with one seed.  Output level = pt level. */
+he_status he_encrypt(he_ctx *ctx, const he_pt *pt, const he_keys *keys, uint64_t seed,
+                     uint32_t index, he_ct *out);
+/* Decrypt (Alg. 2: the server decrypts the worker's weights): residues of
+ * b + a*s at every limb, coefficient order, to host [level+1][N]. */
+he_status he_decrypt(he_ctx *ctx, const he_ct *ct, const he_keys *keys, uint64_t *host_residues);
+/* Decrypt and decode n_slots slots (host).  The message's coefficients must
+ * satisfy |m| < q_0*q_1/2 (lifted from limbs 0 and 1; 0 alone at level 0). */
+he_status he_decrypt_decode(he_ctx *ctx, const he_ct *ct, const he_keys *keys, int n_slots,
+                            double *re, double *im);
+
+/* Ciphertext <-> canonical coefficient form (host [2][level+1][N]). */
+he_status he_ct_download(he_ctx *ctx, const he_ct *ct, uint64_t *host);
+he_status he_ct_upload(he_ctx *ctx, const uint64_t *host, int level, double scale, he_ct *out);
+
+/* ---------------------------------------------------------------- homomorphic operations */
+
+/* Tensor product of two ciphertexts at one level (Sec. 3, multiplication):
+ * (b1 b2, b1 a2 + a1 b2, a1 a2); scale = product of scales. */
+he_status he_mul(he_ctx *ctx, const he_ct *x, const he_ct *y, he_ct3 *out);
+/* Relinearisation: hybrid key switch of d2 from s^2 to s (ModUp per digit,
+ * inner product with the relinearisation key, ModDown by the special primes). */
+he_status he_relin(he_ctx *ctx, const he_ct3 *in, const he_keys *keys, he_ct *out);
+/* Rescale (Sec. 3, "scaling": the homomorphic rounding): divide by q_l with
+ * rounding and drop limb l; scale /= q_l.  HE_ELEVEL at level 0. */
+he_status he_rescale(he_ctx *ctx, const he_ct *in, he_ct *out);
+/* Left rotation of the slots by `steps` (automorphism X -> X^(5^steps) and a key
+ * switch back to s).  HE_EKEY if that rotation key was not generated. */
+he_status he_rotate(he_ctx *ctx, const he_ct *in, int steps, const he_keys *keys, he_ct *out);
+/* out = x + y (same level; HE_ESCALE unless the scales are equal). */
+he_status he_add(he_ctx *ctx, const he_ct *x, const he_ct *y, he_ct *out);
+/* out = k * x for an integer k, |k| < 2^62; out->scale = out_scale (the caller
+ * states how the integer is interpreted). */
+he_status he_mul_int(he_ctx *ctx, const he_ct *x, int64_t k, double out_scale, he_ct *out);
+/* out = x * pt (plaintext at x's level); scale multiplies. */
+he_status he_mul_plain(he_ctx *ctx, const he_ct *x, const he_pt *pt, he_ct *out);
+/* out = x restricted to its first level+1 limbs (same scale). */
+he_status he_drop_level(he_ctx *ctx, const he_ct *x, int level, he_ct *out);
+
+/* ---------------------------------------------------------------- the gradient step */
+
+/* Pure host scale schedule of one gradient step at W's level (no device use).
+ * HE_ELEVEL when fewer than 4 levels remain, HE_ESCALE when an integer constant
+ * leaves |k| < 2^62 or coef[2] != 0.  q: the prime chain (he_ctx_primes). */
+he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, double s_w,
+                          const double coef[4], double eta_over_n, he_lr_plan *out);
+
+/*
+ * One encrypted gradient step on one worker's shard: eq. (appr) with the
+ * Table 2 polynomial p(m) = coef[0] + coef[1] m + coef[3] m^3 (coef[2] = 0),
+ * followed by eq. (update), written as W' = W + g,
+ *   g = (eta/n) sum_i p(y_i w.x_i) y_i x_i   (p approximates -L').
+ * Inputs: Z[0..n_blocks) -- the data blocks, row-major r x c (slot i*c + j holds
+ * y_i x_ij; c*r = N/2), all at one level >= W's and one scale; W -- the weights,
+ * w replicated in every row; mask -- plaintext of the column-0 indicator at
+ * W's level - 1 and the scale he_plan_lr_step gives as s_mask; keys with the
+ * relinearisation key and rotations +-2^k (2^k < c) and c*2^k (2^k < r).
+ * Outputs (caller memory, W's level - 4): W_out, and G_out (nullable) = g.
+ * mode 0: plain form (one he_* operation per block per step, one kernel
+ * sequence each); mode 1: batched form (every block in one launch per
+ * operation, key streams shared across blocks); mode 2: batched form replayed
+ * from a captured HIP graph (captured on first use for these buffers).
+ * All modes give bit-identical ciphertexts.
+ */
+he_status he_lr_grad_step(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct *W,
+                          const he_pt *mask, const double coef[4], double eta_over_n, int c,
+                          int r, const he_keys *keys, int mode, he_ct *W_out, he_ct *G_out);
+
+/* ---------------------------------------------------------------- NTT (measurement) */
+
+/* Forward (dir=+1) or inverse (dir=-1) NTT in place over n_limbs consecutive
+ * limbs of `data` (device, [n_limbs][N]); limb i uses prime index
+ * prime_idx0 + (i % prime_period) of the chain.  Exposed for benchmarking. */
+he_status he_ntt(he_ctx *ctx, uint64_t *data, int n_limbs, int prime_idx0, int prime_period, int dir);
+
+const char *he_strerror(he_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HE_H */

@@ -1,0 +1,1020 @@
+// api.hip -- the C ABI of libhe (include/he.h): context and tables, keys,
+// encryption, the homomorphic operations and the encrypted gradient step.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <sstream>
+
+#include "he_internal.h"
+
+namespace {
+
+// ------------------------------------------------------------------ helpers
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0, off = 0;
+    u64 *take(size_t n_u64)
+    {
+        size_t bytes = (n_u64 * 8 + 255) & ~(size_t)255;
+        if (off + bytes > cap) return nullptr;
+        u64 *p = (u64 *)(base + off);
+        off += bytes;
+        return p;
+    }
+};
+
+inline size_t al(size_t n_u64) { return ((n_u64 * 8 + 255) & ~(size_t)255) / 8; }
+
+he_status ensure_ws(he_ctx *c, size_t bytes)
+{
+    if (c->ws_bytes >= bytes) return HE_OK;
+    if (c->capturing) return HE_ENOMEM;
+    if (c->ws) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipFree(c->ws));
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+    }
+    if (hipMalloc(&c->ws, bytes) != hipSuccess) {
+        c->ws = nullptr;
+        return HE_ENOMEM;
+    }
+    c->ws_bytes = bytes;
+    return HE_OK;
+}
+
+Arena arena(he_ctx *c)
+{
+    Arena a;
+    a.base = (char *)c->ws;
+    a.cap = c->ws_bytes;
+    return a;
+}
+
+inline int beta_at(const he_ctx *c, int level) { return (level + 1 + c->alpha - 1) / c->alpha; }
+
+// scratch (uint64 elements) of one key switch of B entries at a level
+size_t ks_scratch(const he_ctx *c, int l, int B)
+{
+    const size_t N = c->N;
+    const int nb = l + 1 + c->nk;
+    return al(B * (l + 1) * N) + al((size_t)B * beta_at(c, l) * nb * N) + al((size_t)B * 2 * nb * N) +
+           al((size_t)B * 2 * (l + 1) * N);
+}
+size_t rescale_scratch(const he_ctx *c, int l, int B) { return al((size_t)B * 2 * c->N) + al((size_t)B * 2 * l * c->N); }
+size_t rotate_scratch(const he_ctx *c, int l, int B) { return al((size_t)B * 2 * (l + 1) * c->N) + ks_scratch(c, l, B); }
+
+he_status last_error()
+{
+    return hipGetLastError() == hipSuccess ? HE_OK : HE_EDEVICE;
+}
+
+// ------------------------------------------------------------------ core batched operations
+// Key switch of d2 (B entries, NTT, limbs 0..l, batch stride d2s) with key;
+// out = base + KS(d2) on the first nbase components.
+he_status ks_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d2, long long d2s, const u64 *key,
+                   const u64 *base, long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs)
+{
+    const size_t N = c->N;
+    const int nb = l + 1 + c->nk, beta = beta_at(c, l);
+    const size_t mark = ar.off;
+    u64 *y = ar.take((size_t)B * (l + 1) * N);
+    u64 *ext = ar.take((size_t)B * beta * nb * N);
+    u64 *acc = ar.take((size_t)B * 2 * nb * N);
+    u64 *conv = ar.take((size_t)B * 2 * (l + 1) * N);
+    if (!y || !ext || !acc || !conv) return HE_ENOMEM;
+    const long long ys = (long long)(l + 1) * N, ds = (long long)nb * N, es = (long long)beta * ds;
+    const long long as = 2LL * nb * N, cs = 2LL * (l + 1) * N;
+    // digits to coefficient form, scaled by N^{-1} [qhat_i^{-1}]_{q_i}
+    hek::ewise(c, 4, l, B, 1, d2, d2s, 0, nullptr, 0, 0, y, ys, 0, 0);
+    hek::ntt_batch(c, y, ys, 0, B, 1, 0, l + 1, l, -1, c->t.up_scale + (size_t)l * c->nq * 2, false);
+    hek::modup_b(c, l, B, y, ys, ext, es, ds);
+    hek::ntt_batch(c, ext, es, ds, B, beta, 0, nb, l, +1, nullptr, true);
+    hek::ks_inner_b(c, l, B, d2, d2s, ext, es, ds, key, acc, as);
+    // special-prime limbs to coefficient form, scaled by N^{-1} [phat_p^{-1}]_p
+    hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
+    hek::moddown_conv_b(c, l, B, acc, as, conv, cs);
+    hek::ntt_batch(c, conv, cs, (long long)(l + 1) * N, B, 2, 0, l + 1, l, +1, nullptr, false);
+    hek::moddown_finish_b(c, l, B, acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs);
+    ar.off = mark;
+    return last_error();
+}
+
+// relinearise B degree-2 ciphertexts d3 [B][3][l+1][N] (batch stride d3s) -> out [B][2][l+1][N]
+he_status relin_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d3, long long d3s, const u64 *rlk, u64 *out,
+                      long long os)
+{
+    const long long lc = (long long)(l + 1) * c->N;
+    return ks_apply(c, ar, l, B, d3 + 2 * lc, d3s, rlk, d3, d3s, lc, 2, out, os, lc);
+}
+
+// rescale B ciphertexts at level l -> level l-1 (out may equal in only for B == 1)
+he_status rescale_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long long is, u64 *out, long long os)
+{
+    const size_t N = c->N;
+    const size_t mark = ar.off;
+    u64 *lastc = ar.take((size_t)B * 2 * N);
+    u64 *tmp = ar.take((size_t)B * 2 * l * N);
+    if (!lastc || !tmp) return HE_ENOMEM;
+    const long long lc = (long long)(l + 1) * N;
+    hek::ewise(c, 4, 0, B, 2, in + (long long)l * N, is, lc, nullptr, 0, 0, lastc, 2LL * N, (long long)N, 0);
+    // the limbs use prime q_l: address them as position l of a shifted base
+    hek::ntt_batch(c, lastc - (long long)l * N, 2LL * N, (long long)N, B, 2, l, 1, l, -1, nullptr, false);
+    hek::rescale_bcast_b(c, l, B, lastc, tmp);
+    hek::ntt_batch(c, tmp, 2LL * l * N, (long long)l * N, B, 2, 0, l, l - 1, +1, nullptr, false);
+    hek::rescale_finish_b(c, l, B, in, is, tmp, out, os);
+    ar.off = mark;
+    return last_error();
+}
+
+// rotate B ciphertexts at level l by the Galois element g
+he_status rotate_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long long is, u64 g, const u64 *key,
+                       u64 *out, long long os)
+{
+    const size_t N = c->N;
+    const size_t mark = ar.off;
+    const long long lc = (long long)(l + 1) * N;
+    u64 *rot = ar.take((size_t)B * 2 * lc);
+    if (!rot) return HE_ENOMEM;
+    hek::automorph_b(c, B, l + 1, in, is, lc, rot, 2 * lc, lc, g);
+    he_status st = ks_apply(c, ar, l, B, rot + lc, 2 * lc, key, rot, 2 * lc, lc, 1, out, os, lc);
+    ar.off = mark;
+    return st;
+}
+
+u64 galois_of(const he_ctx *c, long long steps)
+{
+    const long long S = c->N / 2;
+    long long t = ((steps % S) + S) % S;
+    return hehost::powmod(5, (u64)t, 2 * (u64)c->N);
+}
+
+const u64 *find_rot_key(const he_keys *k, u64 g)
+{
+    auto it = k->rot.find(g);
+    return it == k->rot.end() ? nullptr : it->second;
+}
+
+bool ct_ok(const he_ctx *c, const he_ct *x) { return x && x->data && x->level >= 0 && x->level < c->nq; }
+
+// ------------------------------------------------------------------ tables
+template <class T>
+T *dev_upload(he_ctx *c, const std::vector<T> &h)
+{
+    void *p = nullptr;
+    if (hipMalloc(&p, h.size() * sizeof(T)) != hipSuccess) return nullptr;
+    if (hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    c->owned.push_back(p);
+    return (T *)p;
+}
+
+he_status build_tables(he_ctx *c)
+{
+    using namespace hehost;
+    const int np = c->np, nq = c->nq, nk = c->nk, N = c->N, A = c->alpha;
+    std::vector<PrimeInfo> pi(np);
+    for (int i = 0; i < np; ++i) {
+        u64 q = c->q[i];
+        PrimeInfo &p = pi[i];
+        p.q = q;
+        p.k = 64 - __builtin_clzll(q);
+        p.mu = (u64)(((u128)1 << (2 * p.k)) / q);
+        p.ninv = invmod((u64)N % q, q);
+        p.ninv_sh = shoup(p.ninv, q);
+        p.r64 = (u64)(((u128)1 << 64) % q);
+        p.r64_sh = shoup(p.r64, q);
+        p.one_sh = shoup(1, q);
+        p.pad = 0;
+    }
+    std::vector<u64> psi((size_t)np * N), psis((size_t)np * N), ipsi((size_t)np * N), ipsis((size_t)np * N);
+    for (int i = 0; i < np; ++i) {
+        u64 q = c->q[i], w = c->psi[i], wi = invmod(w, q);
+        std::vector<u64> pw(N), ipw(N);
+        pw[0] = ipw[0] = 1;
+        for (int k = 1; k < N; ++k) {
+            pw[k] = mulmod(pw[k - 1], w, q);
+            ipw[k] = mulmod(ipw[k - 1], wi, q);
+        }
+        for (int k = 0; k < N; ++k) {
+            unsigned r = 0;
+            for (int b = 0; b < c->logN; ++b)
+                if (k >> b & 1) r |= 1u << (c->logN - 1 - b);
+            size_t o = (size_t)i * N + k;
+            psi[o] = pw[r];
+            psis[o] = shoup(pw[r], q);
+            ipsi[o] = ipw[r];
+            ipsis[o] = shoup(ipw[r], q);
+        }
+    }
+    std::vector<u64> up_scale((size_t)nq * nq * 2, 0), up_conv((size_t)nq * HE_MAXDIG * A * np * 2, 0),
+        up_qd((size_t)nq * HE_MAXDIG * np * 2, 0);
+    for (int l = 0; l < nq; ++l) {
+        for (int j = 0; j < beta_at(c, l); ++j) {
+            int d0 = j * A, d1 = std::min(d0 + A, l + 1);
+            for (int i = d0; i < d1; ++i) {
+                u64 qi = c->q[i], qhat = 1;
+                for (int i2 = d0; i2 < d1; ++i2)
+                    if (i2 != i) qhat = mulmod(qhat, c->q[i2] % qi, qi);
+                u64 sc = mulmod(invmod((u64)N % qi, qi), invmod(qhat, qi), qi);
+                up_scale[((size_t)l * nq + i) * 2] = sc;
+                up_scale[((size_t)l * nq + i) * 2 + 1] = shoup(sc, qi);
+                for (int t = 0; t < np; ++t) {
+                    u64 qt = c->q[t], v = 1;
+                    for (int i2 = d0; i2 < d1; ++i2)
+                        if (i2 != i) v = mulmod(v, c->q[i2] % qt, qt);
+                    size_t o = ((((size_t)l * HE_MAXDIG + j) * A + (i - d0)) * np + t) * 2;
+                    up_conv[o] = v;
+                    up_conv[o + 1] = shoup(v, qt);
+                }
+            }
+            for (int t = 0; t < np; ++t) {
+                u64 qt = c->q[t], v = 1;
+                for (int i2 = d0; i2 < d1; ++i2) v = mulmod(v, c->q[i2] % qt, qt);
+                size_t o = (((size_t)l * HE_MAXDIG + j) * np + t) * 2;
+                up_qd[o] = v;
+                up_qd[o + 1] = shoup(v, qt);
+            }
+        }
+    }
+    std::vector<u64> dn_scale((size_t)nk * 2), dn_conv((size_t)nk * nq * 2), dn_p((size_t)nq * 2),
+        dn_pinv((size_t)nq * 2);
+    for (int k = 0; k < nk; ++k) {
+        u64 pk = c->q[nq + k], phat = 1;
+        for (int k2 = 0; k2 < nk; ++k2)
+            if (k2 != k) phat = mulmod(phat, c->q[nq + k2] % pk, pk);
+        u64 sc = mulmod(invmod((u64)N % pk, pk), invmod(phat, pk), pk);
+        dn_scale[2 * k] = sc;
+        dn_scale[2 * k + 1] = shoup(sc, pk);
+        for (int i = 0; i < nq; ++i) {
+            u64 qi = c->q[i], v = 1;
+            for (int k2 = 0; k2 < nk; ++k2)
+                if (k2 != k) v = mulmod(v, c->q[nq + k2] % qi, qi);
+            dn_conv[((size_t)k * nq + i) * 2] = v;
+            dn_conv[((size_t)k * nq + i) * 2 + 1] = shoup(v, qi);
+        }
+    }
+    for (int i = 0; i < nq; ++i) {
+        u64 qi = c->q[i], P = 1;
+        for (int k = 0; k < nk; ++k) P = mulmod(P, c->q[nq + k] % qi, qi);
+        dn_p[2 * i] = P;
+        dn_p[2 * i + 1] = shoup(P, qi);
+        u64 Pi = invmod(P, qi);
+        dn_pinv[2 * i] = Pi;
+        dn_pinv[2 * i + 1] = shoup(Pi, qi);
+    }
+    std::vector<u64> rs_qinv((size_t)nq * nq * 2, 0), rs_ql((size_t)nq * nq, 0);
+    for (int l = 1; l < nq; ++l)
+        for (int i = 0; i < l; ++i) {
+            u64 qi = c->q[i], v = invmod(c->q[l] % qi, qi);
+            rs_qinv[((size_t)l * nq + i) * 2] = v;
+            rs_qinv[((size_t)l * nq + i) * 2 + 1] = shoup(v, qi);
+            rs_ql[(size_t)l * nq + i] = c->q[l] % qi;
+        }
+    DeviceTables &t = c->t;
+    t.pinfo = dev_upload(c, pi);
+    t.psi = dev_upload(c, psi);
+    t.psi_sh = dev_upload(c, psis);
+    t.ipsi = dev_upload(c, ipsi);
+    t.ipsi_sh = dev_upload(c, ipsis);
+    t.up_scale = dev_upload(c, up_scale);
+    t.up_conv = dev_upload(c, up_conv);
+    t.up_qd = dev_upload(c, up_qd);
+    t.dn_scale = dev_upload(c, dn_scale);
+    t.dn_conv = dev_upload(c, dn_conv);
+    t.dn_p = dev_upload(c, dn_p);
+    t.dn_pinv = dev_upload(c, dn_pinv);
+    t.rs_qinv = dev_upload(c, rs_qinv);
+    t.rs_ql = dev_upload(c, rs_ql);
+    if (!t.pinfo || !t.psi || !t.psi_sh || !t.ipsi || !t.ipsi_sh || !t.up_scale || !t.up_conv || !t.up_qd ||
+        !t.dn_scale || !t.dn_conv || !t.dn_p || !t.dn_pinv || !t.rs_qinv || !t.rs_ql)
+        return HE_ENOMEM;
+    return HE_OK;
+}
+
+std::vector<int> identity_positions(int n)
+{
+    std::vector<int> v(n);
+    for (int i = 0; i < n; ++i) v[i] = i;
+    return v;
+}
+
+// one evaluation key for s' (NTT, [np][N]) into dst [dnum][2][np][N]
+he_status make_evk(he_ctx *c, Arena &ar, u64 seed, uint32_t key_id, const u64 *sk, const u64 *sp, u64 *dst)
+{
+    const size_t N = c->N;
+    const int np = c->np;
+    const size_t mark = ar.off;
+    u64 *e = ar.take((size_t)np * N);
+    if (!e) return HE_ENOMEM;
+    std::vector<int> ids = identity_positions(np);
+    for (int j = 0; j < c->dnum; ++j) {
+        u64 *b = dst + (size_t)j * 2 * np * N;
+        u64 *a = b + (size_t)np * N;
+        hek::sample_uniform(c, seed, ST_EVK_A, key_id, (uint32_t)(j * 256), np, ids.data(), a);
+        hek::ntt_batch(c, a, 0, 0, 1, 1, 0, np, c->nq - 1, +1, nullptr, false);
+        hek::sample_cbd(c, seed, ST_EVK_E, key_id, (uint32_t)j, np, ids.data(), e);
+        hek::ntt_batch(c, e, 0, 0, 1, 1, 0, np, c->nq - 1, +1, nullptr, false);
+        hek::evk_combine(c, a, sk, e, sp, j, b);
+    }
+    ar.off = mark;
+    return last_error();
+}
+
+// ------------------------------------------------------------------ the gradient step
+struct StepBufs {
+    u64 *T3, *U0, *U, *R, *M, *Y, *Z3, *Z1, *A, *B3, *B1, *C, *B1p, *Z0p, *G, *Rg, *Y1;
+};
+
+size_t step_bytes(const he_ctx *c, int l, int nb)
+{
+    const size_t N = c->N;
+    size_t n = 0;
+    n += al((size_t)nb * 3 * (l + 1) * N);                 // T3
+    n += al((size_t)nb * 2 * (l + 1) * N);                 // U0
+    n += 2 * al((size_t)nb * 2 * l * N);                   // U, R
+    n += al((size_t)nb * 2 * (l - 1) * N);                 // M
+    n += al((size_t)nb * 2 * l * N);                       // Y
+    n += 2 * al((size_t)nb * 2 * (l - 1) * N);             // Z3, Z1
+    n += 3 * al((size_t)nb * 2 * (l - 2) * N);             // A, B3, B1
+    n += 3 * al((size_t)nb * 2 * (l - 3) * N);             // C, B1p, Z0p
+    n += 2 * al((size_t)2 * (l - 3) * N);                  // G, Rg
+    n += al((size_t)2 * (l - 2) * N);                      // Y1
+    size_t scratch = std::max(rotate_scratch(c, l, nb), rescale_scratch(c, l, nb));
+    n += std::max(scratch, rotate_scratch(c, l - 4, 1));
+    return n * 8 + 4096;
+}
+
+he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, StepBufs &s)
+{
+    const size_t N = c->N;
+    s.T3 = ar.take((size_t)nb * 3 * (l + 1) * N);
+    s.U0 = ar.take((size_t)nb * 2 * (l + 1) * N);
+    s.U = ar.take((size_t)nb * 2 * l * N);
+    s.R = ar.take((size_t)nb * 2 * l * N);
+    s.M = ar.take((size_t)nb * 2 * (l - 1) * N);
+    s.Y = ar.take((size_t)nb * 2 * l * N);
+    s.Z3 = ar.take((size_t)nb * 2 * (l - 1) * N);
+    s.Z1 = ar.take((size_t)nb * 2 * (l - 1) * N);
+    s.A = ar.take((size_t)nb * 2 * (l - 2) * N);
+    s.B3 = ar.take((size_t)nb * 2 * (l - 2) * N);
+    s.B1 = ar.take((size_t)nb * 2 * (l - 2) * N);
+    s.C = ar.take((size_t)nb * 2 * (l - 3) * N);
+    s.B1p = ar.take((size_t)nb * 2 * (l - 3) * N);
+    s.Z0p = ar.take((size_t)nb * 2 * (l - 3) * N);
+    s.G = ar.take((size_t)2 * (l - 3) * N);
+    s.Rg = ar.take((size_t)2 * (l - 3) * N);
+    s.Y1 = ar.take((size_t)2 * (l - 2) * N);
+    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Y, s.Z3, s.Z1, s.A, s.B3, s.B1, s.C, s.B1p, s.Z0p, s.G, s.Rg, s.Y1};
+    for (u64 *p : all)
+        if (!p) return HE_ENOMEM;
+    return HE_OK;
+}
+
+#define TRY(x)                          \
+    do {                                \
+        he_status st_ = (x);            \
+        if (st_ != HE_OK) return st_;   \
+    } while (0)
+
+// ct x ct -> relin -> rescale for nb entries at level l (inputs [nb][2][*] with
+// batch/component strides), output [nb][2][l][N]
+he_status mul_relin_rescale(he_ctx *c, Arena &ar, StepBufs &s, int l, int nb, const u64 *x, long long xb,
+                            long long xc, const u64 *y, long long yb, long long yc, const u64 *rlk, u64 *out)
+{
+    const long long N = c->N, lc = (l + 1) * N;
+    hek::tensor_b(c, l, nb, x, xb, xc, y, yb, yc, s.T3, 3 * lc, lc);
+    TRY(relin_apply(c, ar, l, nb, s.T3, 3 * lc, rlk, s.U0, 2 * lc));
+    return rescale_apply(c, ar, l, nb, s.U0, 2 * lc, out, 2LL * l * N);
+}
+
+// per-block part of the step for blocks [b0, b0+nb); G (+)= sum of their terms
+he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, const he_ct *Z, long long zbs, int b0,
+                      int nb, const he_ct *W, const he_pt *mask, int cols, const he_keys *keys, bool accumulate)
+{
+    const long long N = c->N;
+    const int l = W->level;
+    const int lz = Z[b0].level;
+    const u64 *zp = Z[b0].data;
+    const long long zc = (lz + 1) * N;
+    const long long wc = (l + 1) * N;
+    // D1: u = RS(relin(Z (x) W)), level l-1
+    TRY(mul_relin_rescale(c, ar, s, l, nb, zp, zbs, zc, W->data, 0, wc, keys->rlk, s.U));
+    const long long u1 = (long long)l * N;  // component stride at level l-1
+    // column sum: u += Rot(u, t), t = 1, 2, .., cols/2
+    for (int t = 1; t < cols; t <<= 1) {
+        const u64 *key = find_rot_key(keys, galois_of(c, t));
+        if (!key) return HE_EKEY;
+        TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, galois_of(c, t), key, s.R, 2 * u1));
+        hek::ewise(c, 0, l - 1, nb, 2, s.U, 2 * u1, u1, s.R, 2 * u1, u1, s.U, 2 * u1, u1, 0);
+    }
+    // mask column 0, rescale: M at level l-2
+    hek::ewise(c, 3, l - 1, nb, 2, s.U, 2 * u1, u1, mask->data, 0, 0, s.U, 2 * u1, u1, 0);
+    TRY(rescale_apply(c, ar, l - 1, nb, s.U, 2 * u1, s.M, 2 * (l - 1) * N));
+    const long long m1 = (long long)(l - 1) * N;
+    for (int t = 1; t < cols; t <<= 1) {
+        const u64 *key = find_rot_key(keys, galois_of(c, -t));
+        if (!key) return HE_EKEY;
+        TRY(rotate_apply(c, ar, l - 2, nb, s.M, 2 * m1, galois_of(c, -t), key, s.R, 2 * m1));
+        hek::ewise(c, 0, l - 2, nb, 2, s.M, 2 * m1, m1, s.R, 2 * m1, m1, s.M, 2 * m1, m1, 0);
+    }
+    // A = M^2 ; Z3 = RS(k3 Z), B3 = M Z3 ; Z1 = RS(k1 Z), B1 = M Z1   (level l-3)
+    TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.M, 2 * m1, m1, keys->rlk, s.A));
+    const long long y1 = (long long)l * N;
+    hek::ewise(c, 2, l - 1, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * y1, y1, pl.k3);
+    TRY(rescale_apply(c, ar, l - 1, nb, s.Y, 2 * y1, s.Z3, 2 * m1));
+    TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.Z3, 2 * m1, m1, keys->rlk, s.B3));
+    hek::ewise(c, 2, l - 1, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * y1, y1, pl.k1);
+    TRY(rescale_apply(c, ar, l - 1, nb, s.Y, 2 * y1, s.Z1, 2 * m1));
+    TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.Z1, 2 * m1, m1, keys->rlk, s.B1));
+    // C = A B3 (level l-4)
+    const long long a1 = (long long)(l - 2) * N, c1 = (long long)(l - 3) * N;
+    TRY(mul_relin_rescale(c, ar, s, l - 3, nb, s.A, 2 * a1, a1, s.B3, 2 * a1, a1, keys->rlk, s.C));
+    // B1' = RS(kB1 B1), Z0' = RS(k0 Z)
+    hek::ewise(c, 2, l - 3, nb, 2, s.B1, 2 * a1, a1, nullptr, 0, 0, s.B1, 2 * a1, a1, pl.kb1);
+    TRY(rescale_apply(c, ar, l - 3, nb, s.B1, 2 * a1, s.B1p, 2 * c1));
+    hek::ewise(c, 2, l - 3, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * a1, a1, pl.k0);
+    TRY(rescale_apply(c, ar, l - 3, nb, s.Y, 2 * a1, s.Z0p, 2 * c1));
+    // G_b = C + B1' + Z0'; G (+)= sum_b G_b
+    hek::ewise(c, 0, l - 4, nb, 2, s.C, 2 * c1, c1, s.B1p, 2 * c1, c1, s.C, 2 * c1, c1, 0);
+    hek::ewise(c, 0, l - 4, nb, 2, s.C, 2 * c1, c1, s.Z0p, 2 * c1, c1, s.C, 2 * c1, c1, 0);
+    hek::batch_sum(c, l - 4, nb, s.C, 2 * c1, c1, s.G, c1, accumulate);
+    return last_error();
+}
+
+// the whole step; nchunk = 1 (plain: per-block operations) or n_blocks (batched)
+he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_blocks, long long zbs, const he_ct *W,
+                    const he_pt *mask, int cols, int rows, const he_keys *keys, int chunk, he_ct *W_out,
+                    he_ct *G_out)
+{
+    const long long N = c->N;
+    const int l = W->level;
+    Arena ar = arena(c);
+    StepBufs s;
+    TRY(step_alloc(c, ar, l, chunk, s));
+    for (int b0 = 0; b0 < n_blocks; b0 += chunk) {
+        int nb = std::min(chunk, n_blocks - b0);
+        long long bs = zbs;
+        if (chunk == 1) bs = 0;
+        TRY(step_blocks(c, ar, s, pl, Z, bs, b0, nb, W, mask, cols, keys, b0 > 0));
+    }
+    // row sum: G += Rot(G, t * cols), t = 1, 2, .., rows/2   (level l-4)
+    const long long g1 = (long long)(l - 3) * N;
+    for (int t = 1; t < rows; t <<= 1) {
+        u64 gal = galois_of(c, (long long)t * cols);
+        const u64 *key = find_rot_key(keys, gal);
+        if (!key) return HE_EKEY;
+        TRY(rotate_apply(c, ar, l - 4, 1, s.G, 2 * g1, gal, key, s.Rg, 2 * g1));
+        hek::ewise(c, 0, l - 4, 1, 2, s.G, 2 * g1, g1, s.Rg, 2 * g1, g1, s.G, 2 * g1, g1, 0);
+    }
+    if (G_out) hek::ewise(c, 4, l - 4, 1, 2, s.G, 2 * g1, g1, nullptr, 0, 0, G_out->data, 2 * g1, g1, 0);
+    // W' = RS(kW W) + g
+    const long long w2 = (long long)(l - 2) * N;
+    hek::ewise(c, 2, l - 3, 1, 2, W->data, 0, (l + 1) * N, nullptr, 0, 0, s.Y1, 2 * w2, w2, pl.kw);
+    TRY(rescale_apply(c, ar, l - 3, 1, s.Y1, 2 * w2, W_out->data, 2 * g1));
+    hek::ewise(c, 0, l - 4, 1, 2, W_out->data, 2 * g1, g1, s.G, 2 * g1, g1, W_out->data, 2 * g1, g1, 0);
+    return last_error();
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *he_strerror(he_status s)
+{
+    switch (s) {
+    case HE_OK: return "ok";
+    case HE_EINVAL: return "invalid argument";
+    case HE_ENOMEM: return "out of memory";
+    case HE_ELEVEL: return "level out of range or mismatched";
+    case HE_ESCALE: return "scale mismatch or scale plan out of range";
+    case HE_EKEY: return "required evaluation key absent";
+    case HE_EDEVICE: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+he_status he_ctx_create(const he_params *prm, void *hip_stream, he_ctx **out)
+{
+    if (!prm || !out) return HE_EINVAL;
+    *out = nullptr;
+    if (prm->log_n < 10 || prm->log_n > 16 || prm->n_q < 2 || prm->n_q > 40 || prm->n_special < 1 ||
+        prm->n_special > 12 || prm->alpha < 1 || prm->alpha > prm->n_special || prm->log_delta < 20 ||
+        prm->log_delta > 50 || prm->n_q + prm->n_special > HE_MAXP)
+        return HE_EINVAL;
+    int dnum = (prm->n_q + prm->alpha - 1) / prm->alpha;
+    if (dnum > HE_MAXBETA) return HE_EINVAL;
+    std::unique_ptr<he_ctx> c(new (std::nothrow) he_ctx());
+    if (!c) return HE_ENOMEM;
+    c->prm = *prm;
+    c->logN = prm->log_n;
+    c->N = 1 << prm->log_n;
+    c->nq = prm->n_q;
+    c->nk = prm->n_special;
+    c->np = c->nq + c->nk;
+    c->alpha = prm->alpha;
+    c->dnum = dnum;
+    c->stream = (hipStream_t)hip_stream;
+    c->q.assign(c->np, 0);
+    if (hehost::gen_primes(c->nq, c->nk, prm->log_delta, c->q.data()) != 0) return HE_EINVAL;
+    c->psi.resize(c->np);
+    for (int i = 0; i < c->np; ++i) c->psi[i] = hehost::find_psi(c->q[i], c->logN);
+    he_status st = build_tables(c.get());
+    if (st != HE_OK) {
+        he_ctx_destroy(c.release());
+        return st;
+    }
+    *out = c.release();
+    return HE_OK;
+}
+
+he_status he_params_primes(const he_params *prm, uint64_t *out, int n)
+{
+    if (!prm || !out || prm->n_q < 1 || prm->n_special < 0 || n < prm->n_q + prm->n_special) return HE_EINVAL;
+    return hehost::gen_primes(prm->n_q, prm->n_special, prm->log_delta, out) == 0 ? HE_OK : HE_EINVAL;
+}
+
+he_status he_ctx_destroy(he_ctx *c)
+{
+    if (!c) return HE_EINVAL;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : c->graphs) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    for (void *p : c->owned) (void)hipFree(p);
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    delete c;
+    return HE_OK;
+}
+
+he_status he_ctx_set_stream(he_ctx *c, void *s)
+{
+    if (!c) return HE_EINVAL;
+    c->stream = (hipStream_t)s;
+    return HE_OK;
+}
+
+he_status he_ctx_primes(const he_ctx *c, uint64_t *out, int n)
+{
+    if (!c || !out || n < c->np) return HE_EINVAL;
+    std::copy(c->q.begin(), c->q.end(), out);
+    return HE_OK;
+}
+
+he_status he_ctx_trim(he_ctx *c)
+{
+    if (!c) return HE_EINVAL;
+    if (c->ws) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipFree(c->ws));
+    }
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    return HE_OK;
+}
+
+size_t he_ct_bytes(const he_ctx *c, int level) { return c ? (size_t)2 * (level + 1) * c->N * 8 : 0; }
+size_t he_pt_bytes(const he_ctx *c, int level) { return c ? (size_t)(level + 1) * c->N * 8 : 0; }
+size_t he_ct3_bytes(const he_ctx *c, int level) { return c ? (size_t)3 * (level + 1) * c->N * 8 : 0; }
+
+size_t he_keys_bytes(const he_ctx *c, int n_rot)
+{
+    if (!c || n_rot < 0) return 0;
+    const size_t evk = (size_t)c->dnum * 2 * c->np * c->N * 8;
+    return (size_t)c->np * c->N * 8 + evk * (1 + (size_t)n_rot);
+}
+
+he_status he_keygen(he_ctx *c, uint64_t seed, const int32_t *rot_steps, int n_rot, void *key_buf,
+                    size_t key_buf_bytes, he_keys **out)
+{
+    if (!c || !out || !key_buf || n_rot < 0 || (n_rot > 0 && !rot_steps)) return HE_EINVAL;
+    if (key_buf_bytes < he_keys_bytes(c, n_rot)) return HE_EINVAL;
+    *out = nullptr;
+    const size_t N = c->N;
+    const int np = c->np;
+    const size_t evk_n = (size_t)c->dnum * 2 * np * N;
+    TRY(ensure_ws(c, (al((size_t)np * N) * 3) * 8 + 4096));
+    std::unique_ptr<he_keys> k(new (std::nothrow) he_keys());
+    if (!k) return HE_ENOMEM;
+    k->ctx = c;
+    k->sk = (u64 *)key_buf;
+    k->rlk = k->sk + (size_t)np * N;
+    // secret: ternary, 64 nonzero coefficients (host ChaCha20), residues, NTT
+    std::vector<i64> s(N);
+    hehost::sample_hwt(seed, c->logN, std::min(64, (int)N), s.data());
+    Arena ar = arena(c);
+    u64 *sd = ar.take(N);
+    u64 *sp = ar.take((size_t)np * N);
+    if (!sd || !sp) return HE_ENOMEM;
+    HIPCHK(hipMemcpyAsync(sd, s.data(), N * 8, hipMemcpyHostToDevice, c->stream));
+    std::vector<int> ids = identity_positions(np);
+    hek::int_to_rns(c, (const i64 *)sd, np, ids.data(), k->sk);
+    hek::ntt_batch(c, k->sk, 0, 0, 1, 1, 0, np, c->nq - 1, +1, nullptr, false);
+    // relinearisation key: s' = s^2
+    hek::ewise(c, 3, np - 1, 1, 1, k->sk, 0, 0, k->sk, 0, 0, sp, 0, 0, 0);
+    TRY(make_evk(c, ar, seed, 0, k->sk, sp, k->rlk));
+    u64 *next = k->rlk + evk_n;
+    for (int r = 0; r < n_rot; ++r) {
+        u64 g = galois_of(c, rot_steps[r]);
+        if (g == 1 || k->rot.count(g)) continue;
+        hek::automorph_b(c, 1, np, k->sk, 0, 0, sp, 0, 0, g);  // s(X^g): one component only is used
+        TRY(make_evk(c, ar, seed, (uint32_t)g, k->sk, sp, next));
+        k->rot[g] = next;
+        next += evk_n;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));  // the host secret buffer is released below
+    TRY(last_error());
+    *out = k.release();
+    return HE_OK;
+}
+
+he_status he_keys_destroy(he_keys *k)
+{
+    if (!k) return HE_EINVAL;
+    delete k;
+    return HE_OK;
+}
+
+he_status he_keys_download(he_ctx *c, const he_keys *k, int64_t which, uint64_t *host)
+{
+    if (!c || !k || !host) return HE_EINVAL;
+    const size_t N = c->N;
+    const int np = c->np;
+    const u64 *src;
+    int npoly;
+    if (which == -2) {
+        src = k->sk;
+        npoly = 1;
+    } else {
+        src = which == -1 ? k->rlk : find_rot_key(k, (u64)which);
+        if (!src) return HE_EKEY;
+        npoly = c->dnum * 2;
+    }
+    const size_t n = (size_t)npoly * np * N;
+    TRY(ensure_ws(c, al(n) * 8 + 4096));
+    Arena ar = arena(c);
+    u64 *t = ar.take(n);
+    HIPCHK(hipMemcpyAsync(t, src, n * 8, hipMemcpyDeviceToDevice, c->stream));
+    hek::ntt_batch(c, t, (long long)np * N, 0, npoly, 1, 0, np, c->nq - 1, -1, nullptr, false);
+    HIPCHK(hipMemcpyAsync(host, t, n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return last_error();
+}
+
+he_status he_encode(he_ctx *c, const double *re, const double *im, int n, double scale, int64_t *coeffs)
+{
+    if (!c || !re || !coeffs || n < 0 || n > c->N / 2 || !(scale > 0)) return HE_EINVAL;
+    return hehost::encode(c->logN, re, im, n, scale, coeffs) == 0 ? HE_OK : HE_EINVAL;
+}
+
+he_status he_decode(he_ctx *c, const double *coeffs, double scale, int n, double *re, double *im)
+{
+    if (!c || !coeffs || !re || n < 0 || n > c->N / 2 || !(scale > 0)) return HE_EINVAL;
+    hehost::decode(c->logN, coeffs, scale, n, re, im);
+    return HE_OK;
+}
+
+he_status he_pt_load(he_ctx *c, const int64_t *coeffs, int level, double scale, he_pt *out)
+{
+    if (!c || !coeffs || !out || !out->data || level < 0 || level >= c->nq) return HE_EINVAL;
+    const size_t N = c->N;
+    TRY(ensure_ws(c, al(N) * 8 + 4096));
+    Arena ar = arena(c);
+    u64 *m = ar.take(N);
+    HIPCHK(hipMemcpyAsync(m, coeffs, N * 8, hipMemcpyHostToDevice, c->stream));
+    std::vector<int> ids = identity_positions(level + 1);
+    hek::int_to_rns(c, (const i64 *)m, level + 1, ids.data(), out->data);
+    hek::ntt_batch(c, out->data, 0, 0, 1, 1, 0, level + 1, level, +1, nullptr, false);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    out->level = level;
+    out->scale = scale;
+    return last_error();
+}
+
+he_status he_encrypt(he_ctx *c, const he_pt *pt, const he_keys *k, uint64_t seed, uint32_t index, he_ct *out)
+{
+    if (!c || !pt || !k || !out || !pt->data || !out->data || pt->level < 0 || pt->level >= c->nq) return HE_EINVAL;
+    const int l = pt->level;
+    const size_t N = c->N;
+    TRY(ensure_ws(c, al((size_t)(l + 1) * N) * 8 + 4096));
+    Arena ar = arena(c);
+    u64 *e = ar.take((size_t)(l + 1) * N);
+    u64 *b = out->data, *a = out->data + (size_t)(l + 1) * N;
+    std::vector<int> ids = identity_positions(l + 1);
+    hek::sample_uniform(c, seed, ST_ENC_A, index, 0, l + 1, ids.data(), a);
+    hek::ntt_batch(c, a, 0, 0, 1, 1, 0, l + 1, l, +1, nullptr, false);
+    hek::sample_cbd(c, seed, ST_ENC_E0, index, 0, l + 1, ids.data(), e);
+    hek::ntt_batch(c, e, 0, 0, 1, 1, 0, l + 1, l, +1, nullptr, false);
+    hek::enc_combine(c, l, a, k->sk, e, pt->data, b);
+    out->level = l;
+    out->scale = pt->scale;
+    return last_error();
+}
+
+he_status he_decrypt(he_ctx *c, const he_ct *ct, const he_keys *k, uint64_t *host)
+{
+    if (!c || !ct_ok(c, ct) || !k || !host) return HE_EINVAL;
+    const int l = ct->level;
+    const size_t N = c->N;
+    TRY(ensure_ws(c, al((size_t)(l + 1) * N) * 8 + 4096));
+    Arena ar = arena(c);
+    u64 *m = ar.take((size_t)(l + 1) * N);
+    hek::dec_combine(c, l, ct->data, k->sk, m);
+    hek::ntt_batch(c, m, 0, 0, 1, 1, 0, l + 1, l, -1, nullptr, false);
+    HIPCHK(hipMemcpyAsync(host, m, (size_t)(l + 1) * N * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return last_error();
+}
+
+he_status he_decrypt_decode(he_ctx *c, const he_ct *ct, const he_keys *k, int n, double *re, double *im)
+{
+    if (!c || !ct_ok(c, ct) || !k || !re || n < 0 || n > c->N / 2) return HE_EINVAL;
+    const size_t N = c->N;
+    std::vector<u64> res((size_t)(ct->level + 1) * N);
+    TRY(he_decrypt(c, ct, k, res.data()));
+    std::vector<double> m(N);
+    const u64 q0 = c->q[0];
+    if (ct->level == 0) {
+        for (size_t x = 0; x < N; ++x) m[x] = res[x] > q0 / 2 ? -(double)(q0 - res[x]) : (double)res[x];
+    } else {
+        const u64 q1 = c->q[1];
+        const u64 q0inv = hehost::invmod(q0 % q1, q1);
+        const u128 Q = (u128)q0 * q1;
+        for (size_t x = 0; x < N; ++x) {
+            u64 r0 = res[x], r1 = res[N + x];
+            u64 d = hehost::mulmod((r1 + q1 - r0 % q1) % q1, q0inv, q1);
+            u128 v = (u128)r0 + (u128)q0 * d;
+            m[x] = v > Q / 2 ? -(double)(Q - v) : (double)v;
+        }
+    }
+    hehost::decode(c->logN, m.data(), ct->scale, n, re, im);
+    return HE_OK;
+}
+
+he_status he_ct_download(he_ctx *c, const he_ct *ct, uint64_t *host)
+{
+    if (!c || !ct_ok(c, ct) || !host) return HE_EINVAL;
+    const size_t n = (size_t)2 * (ct->level + 1) * c->N;
+    TRY(ensure_ws(c, al(n) * 8 + 4096));
+    Arena ar = arena(c);
+    u64 *t = ar.take(n);
+    HIPCHK(hipMemcpyAsync(t, ct->data, n * 8, hipMemcpyDeviceToDevice, c->stream));
+    const long long lc = (long long)(ct->level + 1) * c->N;
+    hek::ntt_batch(c, t, 0, lc, 1, 2, 0, ct->level + 1, ct->level, -1, nullptr, false);
+    HIPCHK(hipMemcpyAsync(host, t, n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return last_error();
+}
+
+he_status he_ct_upload(he_ctx *c, const uint64_t *host, int level, double scale, he_ct *out)
+{
+    if (!c || !host || !out || !out->data || level < 0 || level >= c->nq) return HE_EINVAL;
+    const size_t n = (size_t)2 * (level + 1) * c->N;
+    HIPCHK(hipMemcpyAsync(out->data, host, n * 8, hipMemcpyHostToDevice, c->stream));
+    const long long lc = (long long)(level + 1) * c->N;
+    hek::ntt_batch(c, out->data, 0, lc, 1, 2, 0, level + 1, level, +1, nullptr, false);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    out->level = level;
+    out->scale = scale;
+    return last_error();
+}
+
+he_status he_mul(he_ctx *c, const he_ct *x, const he_ct *y, he_ct3 *out)
+{
+    if (!c || !ct_ok(c, x) || !ct_ok(c, y) || !out || !out->data) return HE_EINVAL;
+    if (x->level != y->level) return HE_ELEVEL;
+    const int l = x->level;
+    const long long lc = (long long)(l + 1) * c->N;
+    hek::tensor_b(c, l, 1, x->data, 0, lc, y->data, 0, lc, out->data, 0, lc);
+    out->level = l;
+    out->scale = x->scale * y->scale;
+    return last_error();
+}
+
+he_status he_relin(he_ctx *c, const he_ct3 *in, const he_keys *k, he_ct *out)
+{
+    if (!c || !in || !in->data || !k || !out || !out->data || in->level < 0 || in->level >= c->nq) return HE_EINVAL;
+    const int l = in->level;
+    TRY(ensure_ws(c, ks_scratch(c, l, 1) * 8 + 4096));
+    Arena ar = arena(c);
+    TRY(relin_apply(c, ar, l, 1, in->data, 0, k->rlk, out->data, 0));
+    out->level = l;
+    out->scale = in->scale;
+    return HE_OK;
+}
+
+he_status he_rescale(he_ctx *c, const he_ct *in, he_ct *out)
+{
+    if (!c || !ct_ok(c, in)) return HE_EINVAL;
+    if (in->level < 1) return HE_ELEVEL;
+    if (!out || !out->data) return HE_EINVAL;
+    const int l = in->level;
+    const double sc = in->scale / (double)c->q[l];
+    TRY(ensure_ws(c, rescale_scratch(c, l, 1) * 8 + 4096));
+    Arena ar = arena(c);
+    TRY(rescale_apply(c, ar, l, 1, in->data, 0, out->data, 0));
+    out->level = l - 1;
+    out->scale = sc;
+    return HE_OK;
+}
+
+he_status he_rotate(he_ctx *c, const he_ct *in, int steps, const he_keys *k, he_ct *out)
+{
+    if (!c || !ct_ok(c, in) || !k || !out || !out->data || out->data == in->data) return HE_EINVAL;
+    const int l = in->level;
+    const u64 g = galois_of(c, steps);
+    const double sc = in->scale;
+    if (g == 1) {
+        const long long lc = (long long)(l + 1) * c->N;
+        hek::ewise(c, 4, l, 1, 2, in->data, 0, lc, nullptr, 0, 0, out->data, 0, lc, 0);
+    } else {
+        const u64 *key = find_rot_key(k, g);
+        if (!key) return HE_EKEY;
+        TRY(ensure_ws(c, rotate_scratch(c, l, 1) * 8 + 4096));
+        Arena ar = arena(c);
+        TRY(rotate_apply(c, ar, l, 1, in->data, 0, g, key, out->data, 0));
+    }
+    out->level = l;
+    out->scale = sc;
+    return last_error();
+}
+
+he_status he_add(he_ctx *c, const he_ct *x, const he_ct *y, he_ct *out)
+{
+    if (!c || !ct_ok(c, x) || !ct_ok(c, y) || !out || !out->data) return HE_EINVAL;
+    if (x->level != y->level) return HE_ELEVEL;
+    if (x->scale != y->scale) return HE_ESCALE;
+    const int l = x->level;
+    const double sc = x->scale;
+    const long long lc = (long long)(l + 1) * c->N;
+    hek::ewise(c, 0, l, 1, 2, x->data, 0, lc, y->data, 0, lc, out->data, 0, lc, 0);
+    out->level = l;
+    out->scale = sc;
+    return last_error();
+}
+
+he_status he_mul_int(he_ctx *c, const he_ct *x, int64_t k, double out_scale, he_ct *out)
+{
+    if (!c || !ct_ok(c, x) || !out || !out->data) return HE_EINVAL;
+    if (k >= ((int64_t)1 << 62) || k <= -((int64_t)1 << 62)) return HE_ESCALE;
+    const int l = x->level;
+    const long long lc = (long long)(l + 1) * c->N;
+    hek::ewise(c, 2, l, 1, 2, x->data, 0, lc, nullptr, 0, 0, out->data, 0, lc, k);
+    out->level = l;
+    out->scale = out_scale;
+    return last_error();
+}
+
+he_status he_mul_plain(he_ctx *c, const he_ct *x, const he_pt *pt, he_ct *out)
+{
+    if (!c || !ct_ok(c, x) || !pt || !pt->data || !out || !out->data) return HE_EINVAL;
+    if (pt->level != x->level) return HE_ELEVEL;
+    const int l = x->level;
+    const double sc = x->scale * pt->scale;
+    const long long lc = (long long)(l + 1) * c->N;
+    hek::ewise(c, 3, l, 1, 2, x->data, 0, lc, pt->data, 0, 0, out->data, 0, lc, 0);
+    out->level = l;
+    out->scale = sc;
+    return last_error();
+}
+
+he_status he_drop_level(he_ctx *c, const he_ct *x, int level, he_ct *out)
+{
+    if (!c || !ct_ok(c, x) || !out || !out->data) return HE_EINVAL;
+    if (level < 0 || level > x->level) return HE_ELEVEL;
+    const long long xc = (long long)(x->level + 1) * c->N, oc = (long long)(level + 1) * c->N;
+    const double sc = x->scale;
+    if (out->data == x->data && level != x->level) {
+        // component 1 moves down; one thread per coefficient walks limbs upward
+        TRY(ensure_ws(c, al((size_t)(level + 1) * c->N) * 8 + 4096));
+        Arena ar = arena(c);
+        u64 *t = ar.take((size_t)(level + 1) * c->N);
+        hek::ewise(c, 4, level, 1, 1, x->data + xc, 0, 0, nullptr, 0, 0, t, 0, 0, 0);
+        hek::ewise(c, 4, level, 1, 1, t, 0, 0, nullptr, 0, 0, out->data + oc, 0, 0, 0);
+    } else {
+        hek::ewise(c, 4, level, 1, 2, x->data, 0, xc, nullptr, 0, 0, out->data, 0, oc, 0);
+    }
+    out->level = level;
+    out->scale = sc;
+    return last_error();
+}
+
+he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, double s_w, const double coef[4],
+                          double eta_over_n, he_lr_plan *out)
+{
+    if (!q || !coef || !out || n_q < 1) return HE_EINVAL;
+    return hehost::plan_lr_step(q, n_q, level, s_z, s_w, coef, eta_over_n, out);
+}
+
+he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, const he_pt *mask,
+                          const double coef[4], double eta_over_n, int cols, int rows, const he_keys *k, int mode,
+                          he_ct *W_out, he_ct *G_out)
+{
+    if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !mask || !mask->data || !coef || !k || mode < 0 || mode > 2)
+        return HE_EINVAL;
+    if (W->level < 4) return HE_ELEVEL;
+    if (!W_out || !W_out->data || (G_out && !G_out->data)) return HE_EINVAL;
+    if (cols < 1 || rows < 1 || (cols & (cols - 1)) || (rows & (rows - 1)) || (long long)cols * rows != c->N / 2)
+        return HE_EINVAL;
+    const int l = W->level;
+    if (l < 4) return HE_ELEVEL;
+    if (mask->level != l - 1) return HE_ELEVEL;
+    const int lz = Z[0].level;
+    const double sz = Z[0].scale;
+    long long zbs = 0;
+    for (int b = 0; b < n_blocks; ++b) {
+        if (!ct_ok(c, &Z[b]) || Z[b].level != lz || Z[b].scale != sz) return Z[b].level != lz ? HE_ELEVEL : HE_EINVAL;
+        if (b == 1) zbs = Z[1].data - Z[0].data;
+        if (b > 1 && Z[b].data - Z[b - 1].data != zbs) return HE_EINVAL;  // one uniform block stride
+    }
+    if (lz < l) return HE_ELEVEL;
+    if (mode > 0 && n_blocks > 1 && zbs < 2LL * (lz + 1) * c->N) return HE_EINVAL;
+    he_lr_plan pl;
+    TRY(hehost::plan_lr_step(c->q.data(), c->nq, l, sz, W->scale, coef, eta_over_n, &pl));
+    if (mask->scale != pl.s_mask) return HE_ESCALE;
+    // every key the step needs, checked before any launch
+    for (int t = 1; t < cols; t <<= 1)
+        if (!find_rot_key(k, galois_of(c, t)) || !find_rot_key(k, galois_of(c, -t))) return HE_EKEY;
+    for (int t = 1; t < rows; t <<= 1)
+        if (!find_rot_key(k, galois_of(c, (long long)t * cols))) return HE_EKEY;
+    const int chunk = mode == 0 ? 1 : n_blocks;
+    TRY(ensure_ws(c, step_bytes(c, l, chunk)));
+    if (mode == 2) {
+        // capture and replay on a private stream ordered after / before the caller's
+        if (!c->gstream) {
+            HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+        }
+        std::ostringstream key;
+        key << (const void *)Z[0].data << ':' << zbs << ':' << n_blocks << ':' << lz << ':' << (const void *)W->data
+            << ':' << l << ':' << (const void *)mask->data << ':' << cols << ':' << (const void *)k << ':'
+            << (const void *)W_out->data << ':' << (const void *)(G_out ? G_out->data : nullptr) << ':' << pl.k0
+            << ':' << pl.k1 << ':' << pl.k3 << ':' << pl.kb1 << ':' << pl.kw << ':' << (const void *)c->ws;
+        GraphEntry &ge = c->graphs[key.str()];
+        hipStream_t user = c->stream;
+        HIPCHK(hipEventRecord(c->ev_in, user));
+        HIPCHK(hipStreamWaitEvent(c->gstream, c->ev_in, 0));
+        if (!ge.exec) {
+            c->stream = c->gstream;
+            hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess) {
+                c->stream = user;
+                c->graphs.erase(key.str());
+                return HE_EDEVICE;
+            }
+            c->capturing = true;
+            he_status st = step_impl(c, pl, Z, n_blocks, zbs, W, mask, cols, rows, k, chunk, W_out, G_out);
+            c->capturing = false;
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(c->stream, &g);
+            c->stream = user;
+            if (st != HE_OK || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                c->graphs.erase(key.str());
+                return st != HE_OK ? st : HE_EDEVICE;
+            }
+            ge.graph = g;
+            if (hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                c->graphs.erase(key.str());
+                return HE_EDEVICE;
+            }
+        }
+        HIPCHK(hipGraphLaunch(ge.exec, c->gstream));
+        HIPCHK(hipEventRecord(c->ev_out, c->gstream));
+        HIPCHK(hipStreamWaitEvent(user, c->ev_out, 0));
+    } else {
+        TRY(step_impl(c, pl, Z, n_blocks, zbs, W, mask, cols, rows, k, chunk, W_out, G_out));
+    }
+    W_out->level = l - 4;
+    W_out->scale = pl.s_g;
+    if (G_out) {
+        G_out->level = l - 4;
+        G_out->scale = pl.s_g;
+    }
+    return last_error();
+}
+
+he_status he_ntt(he_ctx *c, uint64_t *data, int n_limbs, int prime_idx0, int prime_period, int dir)
+{
+    if (!c || !data || n_limbs < 1 || prime_period < 1 || prime_idx0 < 0 || prime_idx0 + prime_period > c->np ||
+        (dir != 1 && dir != -1))
+        return HE_EINVAL;
+    // limbs [n_limbs] = batches of prime_period consecutive positions
+    if (n_limbs % prime_period) return HE_EINVAL;
+    const int nbatch = n_limbs / prime_period;
+    // positions prime_idx0 .. +period of a poly whose prime map is the identity
+    hek::ntt_batch(c, data - (long long)prime_idx0 * c->N, (long long)prime_period * c->N, 0, nbatch, 1, prime_idx0,
+                   prime_period, c->nq - 1, dir, nullptr, false);
+    return last_error();
+}
+
+}  // extern "C"

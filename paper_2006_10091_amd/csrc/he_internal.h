@@ -1,0 +1,141 @@
+// he_internal.h -- context, tables and launcher interfaces of libhe.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "he.h"
+#include "modarith.h"
+
+typedef unsigned __int128 u128;
+typedef int64_t i64;
+
+#define HE_MAXP 64    // primes in a chain (ciphertext + special)
+#define HE_MAXDIG 40  // key-switching digits (table bound)
+#define HE_MAXBETA 12 // digits a key may have (register bound of the inner product)
+
+struct DeviceTables {
+    PrimeInfo *pinfo;        // [np]
+    u64 *psi, *psi_sh;       // [np][N] psi^bitrev(k)
+    u64 *ipsi, *ipsi_sh;     // [np][N] psi^-bitrev(k)
+    // ModUp, per level l and digit j: for each member i of the digit:
+    //   up_scale[l][i]           = N^{-1} [qhat_i^{-1}]_{q_i} (+ Shoup)   (i < n_q)
+    //   up_conv[l][j][ii][t]     = qhat_i mod prime t (+ Shoup)          (t < np)
+    //   up_qd[l][j][t]           = Q_D mod prime t (+ Shoup)
+    u64 *up_scale;           // [nq][nq][2]
+    u64 *up_conv;            // [nq][HE_MAXDIG][alpha][np][2]
+    u64 *up_qd;              // [nq][HE_MAXDIG][np][2]
+    // ModDown (independent of the level):
+    u64 *dn_scale;           // [nk][2]  N^{-1} [phat_p^{-1}]_p
+    u64 *dn_conv;            // [nk][nq][2] phat_p mod q_i
+    u64 *dn_p;               // [nq][2]  P mod q_i
+    u64 *dn_pinv;            // [nq][2]  P^{-1} mod q_i
+    // Rescale: rs_qinv[l][i] = q_l^{-1} mod q_i, rs_ql[l][i] = q_l mod q_i  (i < l)
+    u64 *rs_qinv;            // [nq][nq][2]
+    u64 *rs_ql;              // [nq][nq]
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct he_ctx {
+    he_params prm;
+    int N, logN, nq, nk, np, alpha, dnum;
+    std::vector<u64> q, psi;
+    hipStream_t stream;
+    DeviceTables t;
+    std::vector<void *> owned;  // device allocations of the tables
+    void *ws = nullptr;         // scratch workspace
+    size_t ws_bytes = 0;
+    std::map<std::string, GraphEntry> graphs;
+    bool capturing = false;
+    hipStream_t gstream = nullptr;  // private stream of the captured step
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+struct he_keys {
+    he_ctx *ctx;
+    u64 *sk;                        // [np][N] NTT
+    u64 *rlk;                       // [dnum][2][np][N] NTT
+    std::map<uint64_t, u64 *> rot;  // Galois element -> key
+};
+
+// ------------------------------------------------------------------ host math (host.cpp)
+namespace hehost {
+u64 mulmod(u64 a, u64 b, u64 q);
+u64 powmod(u64 b, u64 e, u64 q);
+u64 invmod(u64 a, u64 q);
+u64 shoup(u64 w, u64 q);
+int gen_primes(int nq, int nk, int log_delta, u64 *out);
+u64 find_psi(u64 q, int logN);
+void chacha20_block(const uint32_t key[8], uint32_t counter, const uint32_t nonce[3], uint32_t out[16]);
+void sample_hwt(u64 seed, int logN, int h, i64 *out);
+int encode(int logN, const double *re, const double *im, int n, double scale, i64 *out);
+void decode(int logN, const double *m, double scale, int n, double *re, double *im);
+he_status plan_lr_step(const u64 *q, int n_q, int level, double s_z, double s_w, const double coef[4],
+                       double eta_over_n, he_lr_plan *out);
+}  // namespace hehost
+
+enum { ST_SECRET = 1, ST_PK_A = 2, ST_PK_E = 3, ST_EVK_A = 4, ST_EVK_E = 5, ST_ENC_A = 6, ST_ENC_E0 = 7 };
+
+// ------------------------------------------------------------------ launchers (kernels.hip)
+// Batched operands are addressed as base + b * (batch stride) + c * (component
+// stride) + pos * N; strides are in uint64 elements.
+namespace hek {
+// NTT in place over positions [pos0, pos0+npos) of nbatch x ncomp polys;
+// dir +1 forward, -1 inverse.  Inverse only: post (nullable) is a table of
+// (value, shoup) pairs, indexed from pos0, multiplied into the output in place
+// of N^{-1}.  skip_digit: component c skips the positions of digit c.
+void ntt_batch(he_ctx *c, u64 *base, long long bstride, long long cstride, int nbatch, int ncomp, int pos0,
+               int npos, int ell, int dir, const u64 *post, bool skip_digit);
+// op 0 add, 1 sub, 2 multiply by integer k, 3 multiply by plaintext y ([pos][N]), 4 copy;
+// positions 0..level of nbatch x ncomp polys.
+void ewise(he_ctx *c, int op, int level, int nbatch, int ncomp, const u64 *x, long long xb, long long xc,
+           const u64 *y, long long yb, long long yc, u64 *o, long long ob, long long oc, i64 k);
+// tensor product of B pairs at a level (output components d0, d1, d2)
+void tensor_b(he_ctx *c, int level, int B, const u64 *x, long long xb, long long xc, const u64 *y, long long yb,
+              long long yc, u64 *o, long long ob, long long oc);
+// ModUp basis conversion of every digit: y [B][l+1][N] scaled iNTT output,
+// ext [B][beta][l+1+nk][N] (positions outside each digit written)
+void modup_b(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, long long es, long long ds);
+// inner product with one key shared by the batch: acc [B][2][l+1+nk][N]
+void ks_inner_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const u64 *ext, long long es,
+                long long ds, const u64 *key, u64 *acc, long long as);
+// ModDown conversion from the special primes: conv [B][2][l+1][N] (coefficient)
+void moddown_conv_b(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs);
+// out = base + (acc - conv) P^{-1} on the first nbase components (else no base)
+void moddown_finish_b(he_ctx *c, int level, int B, const u64 *acc, long long as, const u64 *conv, long long cs,
+                      const u64 *base, long long bs, long long bcs, int nbase, u64 *out, long long os,
+                      long long ocs);
+// rescale pieces: lastc [B][2][N] (coefficient) -> tmp [B][2][l][N]; finish
+void rescale_bcast_b(he_ctx *c, int level, int B, const u64 *lastc, u64 *tmp);
+void rescale_finish_b(he_ctx *c, int level, int B, const u64 *in, long long is, const u64 *tmp, u64 *out,
+                      long long os);
+// NTT-order automorphism X -> X^g of B two-component entries of nl limbs
+void automorph_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,
+                 long long oc, u64 g);
+// out[c] (+)= sum over B entries of in[b][c], positions 0..level, both components
+void batch_sum(he_ctx *c, int level, int B, const u64 *in, long long ib, long long ic, u64 *out, long long oc,
+               bool accumulate);
+// PRNG and samplers (coefficient form), positions -> primes given on the host
+void sample_uniform(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp_base, int n_pos,
+                    const int *prime_of_pos, u64 *out);
+void sample_cbd(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp, int n_pos,
+                const int *prime_of_pos, u64 *out);
+void int_to_rns(he_ctx *c, const i64 *m, int n_pos, const int *prime_of_pos, u64 *out);
+// key generation / encryption / decryption combines (NTT domain)
+void evk_combine(he_ctx *c, const u64 *a, const u64 *s, const u64 *e, const u64 *sp, int digit, u64 *b);
+void enc_combine(he_ctx *c, int level, const u64 *a, const u64 *s, const u64 *e, const u64 *m, u64 *b);
+void dec_combine(he_ctx *c, int level, const u64 *ct, const u64 *s, u64 *out);
+}  // namespace hek
+
+#define HIPCHK(x)                                        \
+    do {                                                 \
+        hipError_t e_ = (x);                             \
+        if (e_ != hipSuccess) return HE_EDEVICE;         \
+    } while (0)

@@ -1,0 +1,270 @@
+// host.cpp -- host-side arithmetic of libhe: prime chain, roots, Shoup
+// companions, the ChaCha20 stream and the secret sampler (keygen runs it once
+// on the host), FP64 canonical-embedding encode/decode, and the FP64 scale
+// schedule of the gradient step.
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <vector>
+
+#include "he_internal.h"
+
+namespace hehost {
+
+u64 mulmod(u64 a, u64 b, u64 q) { return (u64)(((u128)a * b) % q); }
+
+u64 powmod(u64 b, u64 e, u64 q)
+{
+    u64 r = 1 % q;
+    b %= q;
+    for (; e; e >>= 1) {
+        if (e & 1) r = mulmod(r, b, q);
+        b = mulmod(b, b, q);
+    }
+    return r;
+}
+
+u64 invmod(u64 a, u64 q) { return powmod(a, q - 2, q); }  // q prime
+
+u64 shoup(u64 w, u64 q) { return (u64)(((u128)w << 64) / q); }
+
+static bool miller_rabin(u64 n)
+{
+    if (n < 2) return false;
+    const u64 base[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+    for (u64 p : base) {
+        if (n % p == 0) return n == p;
+    }
+    u64 d = n - 1;
+    int s = 0;
+    for (; !(d & 1); d >>= 1) ++s;
+    for (u64 a : base) {
+        u64 x = powmod(a, d, n);
+        if (x == 1 || x == n - 1) continue;
+        bool witness = true;
+        for (int i = 1; i < s && witness; ++i) {
+            x = mulmod(x, x, n);
+            if (x == n - 1) witness = false;
+        }
+        if (witness) return false;
+    }
+    return true;
+}
+
+// Prime chain: every prime 1 mod 2^17 (one chain for all N <= 2^16);
+// specials = n_special largest below 2^60; q_0 = largest below
+// 2^min(60, log_delta+20) that is not special; q_1.. = the primes closest to
+// 2^log_delta, by increasing distance, ties to the smaller.
+int gen_primes(int nq, int nk, int log_delta, u64 *out)
+{
+    const u64 step = (u64)1 << 17;
+    if (nq < 1 || nk < 0 || nq + nk > HE_MAXP || log_delta < 18 || log_delta > 58) return -1;
+    u64 c = ((((u64)1 << 60) - 1) / step) * step + 1;
+    for (int got = 0; got < nk; c -= step)
+        if (miller_rabin(c)) out[nq + got++] = c;
+    int b0 = std::min(60, log_delta + 20);
+    c = ((((u64)1 << b0) - 1) / step) * step + 1;
+    for (;; c -= step) {
+        bool special = false;
+        for (int i = 0; i < nk; ++i) special |= out[nq + i] == c;
+        if (!special && miller_rabin(c)) break;
+    }
+    out[0] = c;
+    const u64 D = (u64)1 << log_delta;
+    u64 below = (D / step) * step + 1;
+    if (below > D) below -= step;
+    u64 above = below + step;
+    for (int k = 1; k < nq; ++k) {
+        while (!miller_rabin(below)) below -= step;
+        while (!miller_rabin(above)) above += step;
+        if (D - below <= above - D) {
+            out[k] = below;
+            below -= step;
+        } else {
+            out[k] = above;
+            above += step;
+        }
+    }
+    return 0;
+}
+
+u64 find_psi(u64 q, int logN)
+{
+    const u64 N = (u64)1 << logN;
+    for (u64 x = 2;; ++x) {
+        u64 y = powmod(x, (q - 1) / (2 * N), q);
+        if (powmod(y, N, q) == q - 1) return y;
+    }
+}
+
+static inline uint32_t rotl(uint32_t v, int n) { return (v << n) | (v >> (32 - n)); }
+
+// RFC 8439, Sec. 2.3
+void chacha20_block(const uint32_t key[8], uint32_t counter, const uint32_t nonce[3], uint32_t out[16])
+{
+    uint32_t s[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u, key[0], key[1], key[2], key[3],
+                      key[4],      key[5],      key[6],      key[7],      counter, nonce[0], nonce[1], nonce[2]};
+    uint32_t x[16];
+    std::memcpy(x, s, sizeof x);
+    auto qr = [&](int a, int b, int c, int d) {
+        x[a] += x[b]; x[d] = rotl(x[d] ^ x[a], 16);
+        x[c] += x[d]; x[b] = rotl(x[b] ^ x[c], 12);
+        x[a] += x[b]; x[d] = rotl(x[d] ^ x[a], 8);
+        x[c] += x[d]; x[b] = rotl(x[b] ^ x[c], 7);
+    };
+    for (int r = 0; r < 10; ++r) {
+        qr(0, 4, 8, 12); qr(1, 5, 9, 13); qr(2, 6, 10, 14); qr(3, 7, 11, 15);
+        qr(0, 5, 10, 15); qr(1, 6, 11, 12); qr(2, 7, 8, 13); qr(3, 4, 9, 14);
+    }
+    for (int i = 0; i < 16; ++i) out[i] = x[i] + s[i];
+}
+
+// 64-bit word w of the stream (seed; type, index, comp): block w/8, words
+// 2(w%8) (low) and 2(w%8)+1 (high) of that block.
+static void stream_words(u64 seed, uint32_t type, uint32_t index, uint32_t comp, size_t count, u64 *out)
+{
+    const uint32_t key[8] = {(uint32_t)seed, (uint32_t)(seed >> 32), 0, 0, 0, 0, 0, 0};
+    const uint32_t nonce[3] = {type, index, comp};
+    uint32_t blk[16];
+    for (size_t b = 0; b * 8 < count; ++b) {
+        chacha20_block(key, (uint32_t)b, nonce, blk);
+        for (int t = 0; t < 8 && b * 8 + t < count; ++t) out[b * 8 + t] = blk[2 * t] | ((u64)blk[2 * t + 1] << 32);
+    }
+}
+
+// Ternary secret with h nonzero entries: partial Fisher-Yates; step k draws
+// word 2k (offset mod N-k) and word 2k+1 (low bit set -> -1).
+void sample_hwt(u64 seed, int logN, int h, i64 *out)
+{
+    const u64 N = (u64)1 << logN;
+    std::vector<u64> w(2 * (size_t)h), perm(N);
+    stream_words(seed, ST_SECRET, 0, 0, w.size(), w.data());
+    for (u64 i = 0; i < N; ++i) {
+        perm[i] = i;
+        out[i] = 0;
+    }
+    for (int k = 0; k < h; ++k) {
+        u64 j = (u64)k + w[2 * k] % (N - (u64)k);
+        std::swap(perm[k], perm[j]);
+        out[perm[k]] = (w[2 * k + 1] & 1) ? -1 : 1;
+    }
+}
+
+// In-place radix-2 complex FFT of size M (power of two):
+// A[k] = sum_n a[n] exp(sign * 2 pi i k n / M).
+static void fft(std::vector<std::complex<double>> &a, int sign)
+{
+    const size_t M = a.size();
+    for (size_t i = 1, j = 0; i < M; ++i) {
+        size_t bit = M >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (size_t len = 2; len <= M; len <<= 1) {
+        const size_t half = len / 2;
+        std::vector<std::complex<double>> w(half);
+        for (size_t k = 0; k < half; ++k) w[k] = std::polar(1.0, sign * 2.0 * M_PI * (double)k / (double)len);
+        for (size_t s = 0; s < M; s += len)
+            for (size_t k = 0; k < half; ++k) {
+                std::complex<double> u = a[s + k], v = a[s + k + half] * w[k];
+                a[s + k] = u + v;
+                a[s + k + half] = u - v;
+            }
+    }
+}
+
+// slot j <-> root zeta^(5^j), zeta = exp(i pi / N).  m_i = (1/N) sum over the
+// 2N-th roots of unity of the slot values at odd exponents, conjugates at -5^j.
+int encode(int logN, const double *re, const double *im, int n, double scale, i64 *out)
+{
+    const size_t N = (size_t)1 << logN, M = 2 * N;
+    std::vector<std::complex<double>> V(M, 0.0);
+    size_t e = 1;
+    for (int j = 0; j < n; ++j) {
+        std::complex<double> z(re[j], im ? im[j] : 0.0);
+        V[e] = z * scale;
+        V[M - e] = std::conj(z) * scale;
+        e = (e * 5) % M;
+    }
+    fft(V, -1);
+    for (size_t i = 0; i < N; ++i) {
+        double v = V[i].real() / (double)N;
+        if (!(std::fabs(v) < 4.611686018427388e18)) return -1;  // 2^62
+        out[i] = (i64)std::llround(v);
+    }
+    return 0;
+}
+
+void decode(int logN, const double *m, double scale, int n, double *re, double *im)
+{
+    const size_t N = (size_t)1 << logN, M = 2 * N;
+    std::vector<std::complex<double>> A(M, 0.0);
+    for (size_t i = 0; i < N; ++i) A[i] = m[i];
+    fft(A, +1);
+    size_t e = 1;
+    for (int j = 0; j < n; ++j) {
+        re[j] = A[e].real() / scale;
+        if (im) im[j] = A[e].imag() / scale;
+        e = (e * 5) % M;
+    }
+}
+
+// Target scale of the gradient terms: power of two T with
+// T * min(|a1|, |a3|) in [2^22, 2^23).
+static bool term_scale(const double coef[4], double *T)
+{
+    double amin = 0.0;
+    for (int k : {1, 3}) {
+        double a = std::fabs(coef[k]);
+        if (a != 0.0 && (amin == 0.0 || a < amin)) amin = a;
+    }
+    if (amin == 0.0) return false;
+    int e;
+    std::frexp(amin, &e);
+    *T = std::ldexp(1.0, 23 - e);
+    return true;
+}
+
+// FP64 schedule of one step; each expression is evaluated left to right as
+// written (the library is built with floating-point contraction off).
+he_status plan_lr_step(const u64 *q, int n_q, int level, double s_z, double s_w, const double coef[4],
+                       double eta_over_n, he_lr_plan *o)
+{
+    if (level < 4 || level >= n_q) return HE_ELEVEL;
+    if (coef[2] != 0.0 || !(eta_over_n > 0.0) || !(s_z > 0.0) || !(s_w > 0.0)) return HE_ESCALE;
+    double T;
+    if (!term_scale(coef, &T)) return HE_ESCALE;
+    const double ql = (double)q[level], ql1 = (double)q[level - 1], ql2 = (double)q[level - 2],
+                 ql3 = (double)q[level - 3];
+    std::memset(o, 0, sizeof *o);
+    o->level_in = level;
+    o->level_out = level - 4;
+    o->s1 = s_z * s_w / ql;
+    o->s_mask = ql2 * ql1 / o->s1;
+    o->s_m = o->s1 * o->s_mask / ql1;
+    o->s_a = o->s_m * o->s_m / ql2;
+    o->t = T;
+    o->s_z3 = T * ql3 / o->s_a * ql2 / o->s_m;
+    double k3 = coef[3] * o->s_z3 * ql1 / s_z;
+    o->s_b3 = o->s_m * o->s_z3 / ql2;
+    o->s_c = o->s_a * o->s_b3 / ql3;
+    o->s_z1 = o->s_z3;
+    double k1 = coef[1] * o->s_z1 * ql1 / s_z;
+    o->s_b1 = o->s_m * o->s_z1 / ql2;
+    double kb1 = o->s_c * ql3 / o->s_b1;
+    double k0 = coef[0] * o->s_c * ql3 / s_z;
+    o->s_g = o->s_c / eta_over_n;
+    double kw = o->s_g * ql3 / s_w;
+    const double kmax = 4.611686018427388e18;  // 2^62
+    for (double k : {k0, k1, k3, kb1, kw})
+        if (!(std::fabs(k) < kmax)) return HE_ESCALE;
+    o->k0 = std::llround(k0);
+    o->k1 = std::llround(k1);
+    o->k3 = std::llround(k3);
+    o->kb1 = std::llround(kb1);
+    o->kw = std::llround(kw);
+    return HE_OK;
+}
+
+}  // namespace hehost

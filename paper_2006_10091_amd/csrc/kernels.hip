@@ -1,0 +1,779 @@
+// kernels.hip -- HIP kernels of libhe for gfx950 (CDNA4, wave64).
+//
+// All arithmetic is exact modular integer arithmetic on uint64 limbs (no
+// MFMA: there is no dense floating-point contraction on this path).
+// Layout: a limb is N consecutive uint64; limbs of a polynomial are
+// consecutive; launches address limbs through LimbBatch / (pointer, stride).
+#include <algorithm>
+
+#include "he_internal.h"
+
+namespace {
+
+constexpr int NTT_THREADS = 256;
+constexpr int NTT_TILE = 4096;  // uint64 elements staged in LDS per workgroup (32 KiB)
+
+__device__ __forceinline__ int prime_of(int pos, int ell, int nq) { return pos <= ell ? pos : nq + pos - ell - 1; }
+
+__device__ __forceinline__ unsigned brev_n(unsigned x, int bits) { return __brev(x) >> (32 - bits); }
+
+struct NttArgs {
+    u64 *base;
+    long long bstride;  // between batch entries
+    long long cstride;  // between components within an entry
+    int ncomp;
+    int pos0;
+    int skip_digit;  // 1: component c skips positions [c*alpha, min(c*alpha+alpha, ell+1))
+    int alpha;
+    int ell, nq;
+    int logN, logN1;
+};
+
+__device__ __forceinline__ bool ntt_locate(const NttArgs &a, u64 *&limb, int &pidx)
+{
+    const int pos = a.pos0 + (int)blockIdx.y;
+    const int z = (int)blockIdx.z;
+    const int b = z / a.ncomp, c = z % a.ncomp;
+    if (a.skip_digit) {
+        int s0 = c * a.alpha, s1 = min(s0 + a.alpha, a.ell + 1);
+        if (pos >= s0 && pos < s1) return false;
+    }
+    limb = a.base + (long long)b * a.bstride + (long long)c * a.cstride + ((long long)pos << a.logN);
+    pidx = prime_of(pos, a.ell, a.nq);
+    return true;
+}
+
+// Pass over the N1 "rows" (stride N2 = N/N1) for a tile of C consecutive
+// columns: the stages m = 1 .. N1/2 of the Cooley-Tukey forward transform
+// (inverse: Gentleman-Sande stages m = N1/2 .. 1, then the output scaling).
+template <bool INV>
+__global__ __launch_bounds__(NTT_THREADS) void ntt_cols(NttArgs a, const PrimeInfo *__restrict__ pinfo,
+                                                        const u64 *__restrict__ tw, const u64 *__restrict__ tws,
+                                                        const u64 *__restrict__ post)
+{
+    __shared__ u64 lds[NTT_TILE];
+    u64 *limb;
+    int pidx;
+    if (!ntt_locate(a, limb, pidx)) return;
+    const int N = 1 << a.logN, N1 = 1 << a.logN1, N2 = N >> a.logN1;
+    const int C = min(NTT_TILE >> a.logN1, N2);
+    const int col0 = blockIdx.x * C;
+    const PrimeInfo p = pinfo[pidx];
+    const u64 q = p.q;
+    const u64 *W = tw + ((long long)pidx << a.logN);
+    const u64 *Ws = tws + ((long long)pidx << a.logN);
+    const int tot = N1 * C;
+    for (int e = threadIdx.x; e < tot; e += NTT_THREADS) {
+        int h = e / C, cc = e - h * C;
+        lds[e] = limb[(long long)h * N2 + col0 + cc];
+    }
+    __syncthreads();
+    if (!INV) {
+        for (int m = 1; m < N1; m <<= 1) {
+            const int th = N1 / (2 * m);
+            for (int bf = threadIdx.x; bf < tot / 2; bf += NTT_THREADS) {
+                int cc = bf % C, bi = bf / C;
+                int g = bi / th, jj = bi - g * th;
+                int h = g * 2 * th + jj;
+                u64 w = W[m + g], ws = Ws[m + g];
+                u64 u = lds[h * C + cc];
+                u64 v = mul_shoup(lds[(h + th) * C + cc], w, ws, q);
+                lds[h * C + cc] = add_mod(u, v, q);
+                lds[(h + th) * C + cc] = sub_mod(u, v, q);
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int m = N1 / 2; m >= 1; m >>= 1) {
+            const int th = N1 / (2 * m);
+            for (int bf = threadIdx.x; bf < tot / 2; bf += NTT_THREADS) {
+                int cc = bf % C, bi = bf / C;
+                int g = bi / th, jj = bi - g * th;
+                int h = g * 2 * th + jj;
+                u64 w = W[m + g], ws = Ws[m + g];
+                u64 x = lds[h * C + cc], y = lds[(h + th) * C + cc];
+                lds[h * C + cc] = add_mod(x, y, q);
+                lds[(h + th) * C + cc] = mul_shoup(sub_mod(x, y, q), w, ws, q);
+            }
+            __syncthreads();
+        }
+    }
+    u64 sc = 0, scs = 0;
+    if (INV) {
+        if (post) {  // indexed from the first position of the launch
+            sc = post[2 * blockIdx.y];
+            scs = post[2 * blockIdx.y + 1];
+        } else {
+            sc = p.ninv;
+            scs = p.ninv_sh;
+        }
+    }
+    for (int e = threadIdx.x; e < tot; e += NTT_THREADS) {
+        int h = e / C, cc = e - h * C;
+        u64 v = lds[e];
+        if (INV) v = mul_shoup(v, sc, scs, q);
+        limb[(long long)h * N2 + col0 + cc] = v;
+    }
+}
+
+// Pass over R consecutive rows of N2 contiguous elements: forward stages
+// m = N1 .. N/2 (inverse: N/2 .. N1).  Stage m = N1 m', half-width t = N2/(2m'),
+// twiddle index N1 m' + h m' + l/(2t) for row h, column l.
+template <bool INV>
+__global__ __launch_bounds__(NTT_THREADS) void ntt_rows(NttArgs a, const PrimeInfo *__restrict__ pinfo,
+                                                        const u64 *__restrict__ tw, const u64 *__restrict__ tws)
+{
+    __shared__ u64 lds[NTT_TILE];
+    u64 *limb;
+    int pidx;
+    if (!ntt_locate(a, limb, pidx)) return;
+    const int N = 1 << a.logN, N1 = 1 << a.logN1, N2 = N >> a.logN1;
+    const int R = min(NTT_TILE / N2, N1);
+    const int h0 = blockIdx.x * R;
+    const u64 q = pinfo[pidx].q;
+    const u64 *W = tw + ((long long)pidx << a.logN);
+    const u64 *Ws = tws + ((long long)pidx << a.logN);
+    const int tot = R * N2;
+    u64 *src = limb + (long long)h0 * N2;
+    for (int e = threadIdx.x; e < tot; e += NTT_THREADS) lds[e] = src[e];
+    __syncthreads();
+    const int half = N2 / 2;
+    if (!INV) {
+        for (int mp = 1; mp < N2; mp <<= 1) {
+            const int t = N2 / (2 * mp);
+            for (int bf = threadIdx.x; bf < tot / 2; bf += NTT_THREADS) {
+                int rr = bf / half, bi = bf - rr * half;
+                int g = bi / t, jj = bi - g * t;
+                int l = g * 2 * t + jj;
+                int idx = N1 * mp + (h0 + rr) * mp + g;
+                u64 *row = lds + rr * N2;
+                u64 u = row[l];
+                u64 v = mul_shoup(row[l + t], W[idx], Ws[idx], q);
+                row[l] = add_mod(u, v, q);
+                row[l + t] = sub_mod(u, v, q);
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int mp = N2 / 2; mp >= 1; mp >>= 1) {
+            const int t = N2 / (2 * mp);
+            for (int bf = threadIdx.x; bf < tot / 2; bf += NTT_THREADS) {
+                int rr = bf / half, bi = bf - rr * half;
+                int g = bi / t, jj = bi - g * t;
+                int l = g * 2 * t + jj;
+                int idx = N1 * mp + (h0 + rr) * mp + g;
+                u64 *row = lds + rr * N2;
+                u64 x = row[l], y = row[l + t];
+                row[l] = add_mod(x, y, q);
+                row[l + t] = mul_shoup(sub_mod(x, y, q), W[idx], Ws[idx], q);
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = threadIdx.x; e < tot; e += NTT_THREADS) src[e] = lds[e];
+}
+
+// ------------------------------------------------------------------ elementwise
+struct EwArgs {
+    u64 *x, *y, *o;
+    long long xb, xc, yb, yc, ob, oc;  // batch / component strides
+    int ncomp, pos0, ell, nq, logN;
+};
+
+__device__ __forceinline__ long long ew_off(long long bs, long long cs, int b, int c, int pos, int logN)
+{
+    return (long long)b * bs + (long long)c * cs + ((long long)pos << logN);
+}
+
+// op: 0 add, 1 sub, 2 mul by integer, 3 mul by plaintext (y: [pos][N], no batch/comp), 4 copy
+template <int OP>
+__global__ __launch_bounds__(256) void ew_kernel(EwArgs a, const PrimeInfo *__restrict__ pinfo, i64 k)
+{
+    const int pos = a.pos0 + (int)blockIdx.y;
+    const int z = (int)blockIdx.z;
+    const int b = z / a.ncomp, c = z % a.ncomp;
+    const int N = 1 << a.logN;
+    const PrimeInfo p = pinfo[prime_of(pos, a.ell, a.nq)];
+    const u64 *x = a.x + ew_off(a.xb, a.xc, b, c, pos, a.logN);
+    u64 *o = a.o + ew_off(a.ob, a.oc, b, c, pos, a.logN);
+    const u64 *y = nullptr;
+    if (OP == 0 || OP == 1) y = a.y + ew_off(a.yb, a.yc, b, c, pos, a.logN);
+    if (OP == 3) y = a.y + ((long long)pos << a.logN);
+    u64 kq = 0;
+    if (OP == 2) {
+        u64 mag = k < 0 ? (u64)(-(k + 1)) + 1 : (u64)k;
+        kq = reduce64(mag, p);
+        if (k < 0) kq = neg_mod(kq, p.q);
+    }
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += gridDim.x * 256) {
+        u64 v;
+        if (OP == 0) v = add_mod(x[i], y[i], p.q);
+        else if (OP == 1) v = sub_mod(x[i], y[i], p.q);
+        else if (OP == 2) v = mul_mod(x[i], kq, p);
+        else if (OP == 3) v = mul_mod(x[i], y[i], p);
+        else v = x[i];
+        o[i] = v;
+    }
+}
+
+// tensor: out0 = x0 y0, out1 = x0 y1 + x1 y0, out2 = x1 y1 (limbs 0..l)
+__global__ __launch_bounds__(256) void tensor_kernel(const u64 *__restrict__ x, long long xb, long long xc,
+                                                     const u64 *__restrict__ y, long long yb, long long yc,
+                                                     u64 *__restrict__ o, long long ob, long long oc,
+                                                     const PrimeInfo *__restrict__ pinfo, int logN)
+{
+    const int i = blockIdx.y, b = blockIdx.z;
+    const PrimeInfo p = pinfo[i];
+    const long long li = (long long)i << logN;
+    const u64 *x0 = x + b * xb + li, *x1 = x0 + xc;
+    const u64 *y0 = y + b * yb + li, *y1 = y0 + yc;
+    u64 *o0 = o + b * ob + li, *o1 = o0 + oc, *o2 = o1 + oc;
+    const int N = 1 << logN;
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < N; t += gridDim.x * 256) {
+        u64 a0 = x0[t], a1 = x1[t], b0 = y0[t], b1 = y1[t];
+        o0[t] = mul_mod(a0, b0, p);
+        o1[t] = add_mod(mul_mod(a0, b1, p), mul_mod(a1, b0, p), p.q);
+        o2[t] = mul_mod(a1, b1, p);
+    }
+}
+
+// ModUp conversion: ext[b][j][t] for positions t outside digit j.
+// y[b][i] holds [d_i qhat_i^{-1}]_{q_i} (coefficient form).
+__global__ __launch_bounds__(256) void modup_kernel(const u64 *__restrict__ y, long long ys, u64 *__restrict__ ext,
+                                                    long long es, long long ds, const PrimeInfo *__restrict__ pinfo,
+                                                    const u64 *__restrict__ conv, const u64 *__restrict__ qd,
+                                                    int level, int alpha, int nq, int np, int nk, int beta, int logN)
+{
+    const int t = blockIdx.y;  // basis position 0 .. level+nk
+    const int z = blockIdx.z;
+    const int b = z / beta, j = z % beta;
+    const int d0 = j * alpha, d1 = min(d0 + alpha, level + 1);
+    if (t >= d0 && t < d1) return;
+    const int tp = prime_of(t, level, nq);
+    const PrimeInfo pt = pinfo[tp];
+    const int N = 1 << logN;
+    const u64 *yb = y + b * ys;
+    u64 *o = ext + b * es + j * ds + ((long long)t << logN);
+    // conv layout: [level][HE_MAXDIG][alpha][np][2]; qd: [level][HE_MAXDIG][np][2]
+    const u64 *cv = conv + ((((long long)level * HE_MAXDIG + j) * alpha) * np) * 2;
+    const u64 *qq = qd + (((long long)level * HE_MAXDIG + j) * np + tp) * 2;
+    const u64 qdt = qq[0], qdts = qq[1];
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
+        u64 acc = 0;
+        u64 cnt = 0;
+        for (int i = d0; i < d1; ++i) {
+            const u64 qi = pinfo[i].q;
+            u64 v = yb[((long long)i << logN) + x];
+            cnt += v > (qi >> 1);
+            const u64 *c2 = cv + ((long long)(i - d0) * np + tp) * 2;
+            acc = add_mod(acc, mul_shoup(v, c2[0], c2[1], pt.q), pt.q);
+        }
+        acc = sub_mod(acc, mul_shoup(cnt, qdt, qdts, pt.q), pt.q);
+        o[x] = acc;
+    }
+}
+
+// Key-switching inner product for B entries sharing one key: each thread keeps
+// its key coefficients in registers and loops over the batch.
+__global__ __launch_bounds__(256) void ks_inner_kernel(const u64 *__restrict__ d2, long long d2s,
+                                                       const u64 *__restrict__ ext, long long es, long long ds,
+                                                       const u64 *__restrict__ key, u64 *__restrict__ acc,
+                                                       long long as, const PrimeInfo *__restrict__ pinfo, int B,
+                                                       int level, int alpha, int nq, int np, int beta, int logN)
+{
+    const int t = blockIdx.y;
+    const int tp = prime_of(t, level, nq);
+    const PrimeInfo p = pinfo[tp];
+    const int N = 1 << logN;
+    const int nb = level + 1 + (np - nq);
+    const long long keylimb = (long long)np << logN;  // one key component
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
+        u64 kb[HE_MAXBETA], ka[HE_MAXBETA];
+        for (int j = 0; j < beta; ++j) {
+            const u64 *kj = key + (long long)j * 2 * keylimb + ((long long)tp << logN) + x;
+            kb[j] = kj[0];
+            ka[j] = kj[keylimb];
+        }
+        for (int b = 0; b < B; ++b) {
+            u64 s0 = 0, s1 = 0;
+            for (int j = 0; j < beta; ++j) {
+                const int d0 = j * alpha, d1 = min(d0 + alpha, level + 1);
+                u64 X = (t >= d0 && t < d1) ? d2[b * d2s + ((long long)t << logN) + x]
+                                            : ext[b * es + j * ds + ((long long)t << logN) + x];
+                s0 = add_mod(s0, mul_mod(X, kb[j], p), p.q);
+                s1 = add_mod(s1, mul_mod(X, ka[j], p), p.q);
+            }
+            u64 *o = acc + b * as + ((long long)t << logN) + x;
+            o[0] = s0;
+            o[(long long)nb << logN] = s1;
+        }
+    }
+}
+
+// ModDown conversion: acc[b][comp] positions level+1.. hold scaled iNTT
+// outputs y_p (coefficient); conv[b][comp][i] = sum_p y~_p (phat_p mod q_i).
+__global__ __launch_bounds__(256) void moddown_conv_kernel(const u64 *__restrict__ acc, long long as,
+                                                           u64 *__restrict__ conv, long long cs,
+                                                           const PrimeInfo *__restrict__ pinfo,
+                                                           const u64 *__restrict__ dconv, const u64 *__restrict__ dp,
+                                                           int level, int nq, int nk, int logN)
+{
+    const int i = blockIdx.y;
+    const int z = blockIdx.z;  // b*2 + comp
+    const int b = z >> 1, comp = z & 1;
+    const int N = 1 << logN;
+    const int nb = level + 1 + nk;
+    const PrimeInfo p = pinfo[i];
+    const u64 *src = acc + b * as + ((long long)comp * nb << logN);
+    u64 *o = conv + b * cs + ((long long)(comp * (level + 1) + i) << logN);
+    const u64 pm = dp[2 * i], pms = dp[2 * i + 1];
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
+        u64 s = 0, cnt = 0;
+        for (int k = 0; k < nk; ++k) {
+            const u64 pk = pinfo[nq + k].q;
+            u64 v = src[((long long)(level + 1 + k) << logN) + x];
+            cnt += v > (pk >> 1);
+            const u64 *c2 = dconv + ((long long)k * nq + i) * 2;
+            s = add_mod(s, mul_shoup(v, c2[0], c2[1], p.q), p.q);
+        }
+        o[x] = sub_mod(s, mul_shoup(cnt, pm, pms, p.q), p.q);
+    }
+}
+
+// out[b][comp][i] = base + (acc - conv) P^{-1}   (NTT domain)
+__global__ __launch_bounds__(256) void moddown_finish_kernel(const u64 *__restrict__ acc, long long as,
+                                                             const u64 *__restrict__ conv, long long cs,
+                                                             const u64 *__restrict__ base, long long bs,
+                                                             long long bcs, int nbase, u64 *__restrict__ out,
+                                                             long long os, long long ocs,
+                                                             const PrimeInfo *__restrict__ pinfo,
+                                                             const u64 *__restrict__ pinv, int level, int nk,
+                                                             int logN)
+{
+    const int i = blockIdx.y;
+    const int z = blockIdx.z;
+    const int b = z >> 1, comp = z & 1;
+    const int N = 1 << logN;
+    const int nb = level + 1 + nk;
+    const u64 q = pinfo[i].q;
+    const u64 w = pinv[2 * i], ws = pinv[2 * i + 1];
+    const long long li = (long long)i << logN;
+    const u64 *a = acc + b * as + ((long long)comp * nb << logN) + li;
+    const u64 *c = conv + b * cs + ((long long)comp * (level + 1) << logN) + li;
+    const u64 *bb = (comp < nbase) ? base + b * bs + comp * bcs + li : nullptr;
+    u64 *o = out + b * os + comp * ocs + li;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
+        u64 v = mul_shoup(sub_mod(a[x], c[x], q), w, ws, q);
+        if (bb) v = add_mod(v, bb[x], q);
+        o[x] = v;
+    }
+}
+
+// tmp[b][c][i] = [last]_centered mod q_i  (coefficient) for i < level
+__global__ __launch_bounds__(256) void rescale_bcast_kernel(const u64 *__restrict__ lastc, u64 *__restrict__ tmp,
+                                                            const PrimeInfo *__restrict__ pinfo,
+                                                            const u64 *__restrict__ rs_ql, int level, int nq,
+                                                            int logN)
+{
+    const int i = blockIdx.y;
+    const int z = blockIdx.z;  // b*2+c
+    const int N = 1 << logN;
+    const PrimeInfo p = pinfo[i];
+    const u64 ql = pinfo[level].q;
+    const u64 qlmod = rs_ql[(long long)level * nq + i];
+    const u64 *src = lastc + ((long long)z << logN);
+    u64 *o = tmp + ((long long)(z * level + i) << logN);
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
+        u64 v = src[x];
+        u64 r = reduce64(v, p);
+        if (v > (ql >> 1)) r = sub_mod(r, qlmod, p.q);
+        o[x] = r;
+    }
+}
+
+// out[b][c][i] = (in[b][c][i] - tmp[b][c][i]) q_l^{-1}; one thread walks the
+// limbs of one coefficient in order, so out may alias in (it trails by N).
+__global__ __launch_bounds__(256) void rescale_finish_kernel(const u64 *in, long long is, const u64 *__restrict__ tmp,
+                                                             u64 *out, long long os,
+                                                             const PrimeInfo *__restrict__ pinfo,
+                                                             const u64 *__restrict__ rs_qinv, int level, int nq,
+                                                             int logN)
+{
+    const int b = blockIdx.y;
+    const int N = 1 << logN;
+    const u64 *qi_tab = rs_qinv + (long long)level * nq * 2;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
+        for (int c = 0; c < 2; ++c) {
+            const u64 *src = in + b * is + ((long long)c * (level + 1) << logN);
+            const u64 *tp = tmp + ((long long)(b * 2 + c) * level << logN);
+            u64 *dst = out + b * os + ((long long)c * level << logN);
+            for (int i = 0; i < level; ++i) {
+                const u64 q = pinfo[i].q;
+                long long off = ((long long)i << logN) + x;
+                u64 v = sub_mod(src[off], tp[off], q);
+                dst[off] = mul_shoup(v, qi_tab[2 * i], qi_tab[2 * i + 1], q);
+            }
+        }
+    }
+}
+
+// NTT-order automorphism: output index k holds the value at the root
+// psi^(2 br(k) + 1); sigma_g(a) there equals a at psi^((2 br(k)+1) g).
+__global__ __launch_bounds__(256) void automorph_kernel(const u64 *__restrict__ in, long long ib, long long ic,
+                                                        u64 *__restrict__ out, long long ob, long long oc, u64 g,
+                                                        int logN)
+{
+    const int limb = blockIdx.y;
+    const int b = blockIdx.z >> 1, c = blockIdx.z & 1;
+    const int N = 1 << logN;
+    const u64 mask2n = 2 * (u64)N - 1;
+    const u64 *src = in + b * ib + c * ic + ((long long)limb << logN);
+    u64 *dst = out + b * ob + c * oc + ((long long)limb << logN);
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < N; k += gridDim.x * 256) {
+        u64 e = 2 * (u64)brev_n(k, logN) + 1;
+        u64 e2 = (e * g) & mask2n;
+        unsigned k2 = brev_n((unsigned)((e2 - 1) >> 1), logN);
+        dst[k] = src[k2];
+    }
+}
+
+// out[c][i] = sum_b in[b][c][i]  (mod q_i), positions 0..level
+__global__ __launch_bounds__(256) void batch_sum_kernel(const u64 *__restrict__ in, long long ib, long long ic,
+                                                        int B, u64 *__restrict__ out, long long oc, int accumulate,
+                                                        const PrimeInfo *__restrict__ pinfo, int logN)
+{
+    const int i = blockIdx.y, c = blockIdx.z;
+    const int N = 1 << logN;
+    const u64 q = pinfo[i].q;
+    const long long li = (long long)i << logN;
+    u64 *o = out + c * oc + li;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
+        u64 s = accumulate ? o[x] : 0;
+        for (int b = 0; b < B; ++b) s = add_mod(s, in[b * ib + c * ic + li + x], q);
+        o[x] = s;
+    }
+}
+
+// ------------------------------------------------------------------ ChaCha20 (RFC 8439, Sec. 2.3)
+__device__ __forceinline__ uint32_t rotl32(uint32_t v, int n) { return (v << n) | (v >> (32 - n)); }
+
+__device__ void chacha_block(uint32_t seed_lo, uint32_t seed_hi, uint32_t counter, uint32_t n0, uint32_t n1,
+                             uint32_t n2, uint32_t out[16])
+{
+    uint32_t s[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u, seed_lo, seed_hi, 0, 0,
+                      0,           0,           0,           0,           counter, n0,      n1, n2};
+    uint32_t x[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = s[i];
+#define QR(a, b, c, d)                                   \
+    x[a] += x[b]; x[d] = rotl32(x[d] ^ x[a], 16);        \
+    x[c] += x[d]; x[b] = rotl32(x[b] ^ x[c], 12);        \
+    x[a] += x[b]; x[d] = rotl32(x[d] ^ x[a], 8);         \
+    x[c] += x[d]; x[b] = rotl32(x[b] ^ x[c], 7);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        QR(0, 4, 8, 12) QR(1, 5, 9, 13) QR(2, 6, 10, 14) QR(3, 7, 11, 15)
+        QR(0, 5, 10, 15) QR(1, 6, 11, 12) QR(2, 7, 8, 13) QR(3, 4, 9, 14)
+    }
+#undef QR
+#pragma unroll
+    for (int i = 0; i < 16; ++i) out[i] = x[i] + s[i];
+}
+
+struct PosPrimes {
+    int n;
+    int prime[HE_MAXP];
+};
+
+// uniform residues: coefficient x of position pos uses words 2x (high) and
+// 2x+1 (low) of stream (seed; type, index, comp_base + pos).
+__global__ __launch_bounds__(256) void uniform_kernel(u64 seed, uint32_t type, uint32_t index, uint32_t comp_base,
+                                                      PosPrimes pp, const PrimeInfo *__restrict__ pinfo,
+                                                      u64 *__restrict__ out, int logN)
+{
+    const int pos = blockIdx.y;
+    const int N = 1 << logN;
+    const PrimeInfo p = pinfo[pp.prime[pos]];
+    u64 *o = out + ((long long)pos << logN);
+    const int nblk = N / 4;  // 4 coefficients per ChaCha block
+    for (int blk = blockIdx.x * 256 + threadIdx.x; blk < nblk; blk += gridDim.x * 256) {
+        uint32_t w[16];
+        chacha_block((uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)blk, type, index, comp_base + pos, w);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            u64 hi = w[4 * c] | ((u64)w[4 * c + 1] << 32);
+            u64 lo = w[4 * c + 2] | ((u64)w[4 * c + 3] << 32);
+            o[4 * blk + c] = reduce128(hi, lo, p);
+        }
+    }
+}
+
+// centered binomial (21 pairs) from word x; residues on every position
+__global__ __launch_bounds__(256) void cbd_kernel(u64 seed, uint32_t type, uint32_t index, uint32_t comp, PosPrimes pp,
+                                                  const PrimeInfo *__restrict__ pinfo, u64 *__restrict__ out,
+                                                  int logN)
+{
+    const int N = 1 << logN;
+    const int nblk = N / 8;
+    for (int blk = blockIdx.x * 256 + threadIdx.x; blk < nblk; blk += gridDim.x * 256) {
+        uint32_t w[16];
+        chacha_block((uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)blk, type, index, comp, w);
+        for (int c = 0; c < 8; ++c) {
+            u64 v = w[2 * c] | ((u64)w[2 * c + 1] << 32);
+            int e = __popcll(v & 0x1FFFFFull) - __popcll((v >> 21) & 0x1FFFFFull);
+            for (int pos = 0; pos < pp.n; ++pos) {
+                u64 q = pinfo[pp.prime[pos]].q;
+                out[((long long)pos << logN) + 8 * blk + c] = e >= 0 ? (u64)e : q - (u64)(-e);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void int_to_rns_kernel(const i64 *__restrict__ m, PosPrimes pp,
+                                                         const PrimeInfo *__restrict__ pinfo, u64 *__restrict__ out,
+                                                         int logN)
+{
+    const int pos = blockIdx.y;
+    const int N = 1 << logN;
+    const PrimeInfo p = pinfo[pp.prime[pos]];
+    u64 *o = out + ((long long)pos << logN);
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
+        i64 v = m[x];
+        u64 mag = v < 0 ? (u64)(-(v + 1)) + 1 : (u64)v;
+        u64 r = reduce64(mag, p);
+        o[x] = v < 0 ? neg_mod(r, p.q) : r;
+    }
+}
+
+// evaluation key: b = -a s + e + [pos in digit] (P mod q_pos) s'
+__global__ __launch_bounds__(256) void evk_kernel(const u64 *__restrict__ a, const u64 *__restrict__ s,
+                                                  const u64 *__restrict__ e, const u64 *__restrict__ sp,
+                                                  const u64 *__restrict__ dp, const PrimeInfo *__restrict__ pinfo,
+                                                  int d0, int d1, u64 *__restrict__ b, int logN)
+{
+    const int pos = blockIdx.y;
+    const int N = 1 << logN;
+    const PrimeInfo p = pinfo[pos];
+    const long long off = (long long)pos << logN;
+    const bool gad = pos >= d0 && pos < d1;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
+        u64 v = sub_mod(e[off + x], mul_mod(a[off + x], s[off + x], p), p.q);
+        if (gad) v = add_mod(v, mul_shoup(sp[off + x], dp[2 * pos], dp[2 * pos + 1], p.q), p.q);
+        b[off + x] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void enc_kernel(const u64 *__restrict__ a, const u64 *__restrict__ s,
+                                                  const u64 *__restrict__ e, const u64 *__restrict__ m,
+                                                  const PrimeInfo *__restrict__ pinfo, u64 *__restrict__ b, int logN)
+{
+    const int i = blockIdx.y;
+    const int N = 1 << logN;
+    const PrimeInfo p = pinfo[i];
+    const long long off = (long long)i << logN;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256)
+        b[off + x] = add_mod(sub_mod(e[off + x], mul_mod(a[off + x], s[off + x], p), p.q), m[off + x], p.q);
+}
+
+__global__ __launch_bounds__(256) void dec_kernel(const u64 *__restrict__ ct, const u64 *__restrict__ s,
+                                                  const PrimeInfo *__restrict__ pinfo, u64 *__restrict__ out,
+                                                  int level, int logN)
+{
+    const int i = blockIdx.y;
+    const int N = 1 << logN;
+    const PrimeInfo p = pinfo[i];
+    const long long off = (long long)i << logN;
+    const long long a_off = (long long)(level + 1) << logN;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256)
+        out[off + x] = add_mod(ct[off + x], mul_mod(ct[a_off + off + x], s[off + x], p), p.q);
+}
+
+inline int xblocks(int N, int per_thread = 4)
+{
+    int blocks = N / (256 * per_thread);
+    return blocks < 1 ? 1 : blocks;
+}
+
+PosPrimes make_pp(int n, const int *prime_of_pos)
+{
+    PosPrimes pp;
+    pp.n = n;
+    for (int i = 0; i < n; ++i) pp.prime[i] = prime_of_pos[i];
+    return pp;
+}
+
+}  // namespace
+
+namespace hek {
+
+static void ntt_launch(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, const u64 *post)
+{
+    const int N1 = 1 << a.logN1, N2 = 1 << (a.logN - a.logN1);
+    const int C = std::min(NTT_TILE >> a.logN1, N2);
+    const int R = std::min(NTT_TILE / N2, N1);
+    dim3 gc(N2 / C, npos, nbatch * a.ncomp), gr(N1 / R, npos, nbatch * a.ncomp);
+    if (dir > 0) {
+        ntt_cols<false><<<gc, NTT_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh, nullptr);
+        ntt_rows<false><<<gr, NTT_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh);
+    } else {
+        ntt_rows<true><<<gr, NTT_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh);
+        ntt_cols<true><<<gc, NTT_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh, post);
+    }
+}
+
+void ntt_batch(he_ctx *c, u64 *base, long long bstride, long long cstride, int nbatch, int ncomp, int pos0,
+               int npos, int ell, int dir, const u64 *post, bool skip_digit)
+{
+    NttArgs a;
+    a.base = base;
+    a.bstride = bstride;
+    a.cstride = cstride;
+    a.ncomp = ncomp;
+    a.pos0 = pos0;
+    a.skip_digit = skip_digit ? 1 : 0;
+    a.alpha = c->alpha;
+    a.ell = ell;
+    a.nq = c->nq;
+    a.logN = c->logN;
+    a.logN1 = (c->logN + 1) / 2;
+    ntt_launch(c, a, nbatch, npos, dir, post);
+}
+
+static void ew(he_ctx *c, int op, const EwArgs &a, int npos, int nbatch, i64 k)
+{
+    dim3 g(xblocks(c->N), npos, nbatch * a.ncomp);
+    switch (op) {
+    case 0: ew_kernel<0><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
+    case 1: ew_kernel<1><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
+    case 2: ew_kernel<2><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
+    case 3: ew_kernel<3><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
+    default: ew_kernel<4><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
+    }
+}
+
+void ewise(he_ctx *c, int op, int level, int nbatch, int ncomp, const u64 *x, long long xb, long long xc,
+           const u64 *y, long long yb, long long yc, u64 *o, long long ob, long long oc, i64 k)
+{
+    EwArgs a;
+    a.x = const_cast<u64 *>(x);
+    a.y = const_cast<u64 *>(y);
+    a.o = o;
+    a.xb = xb; a.xc = xc; a.yb = yb; a.yc = yc; a.ob = ob; a.oc = oc;
+    a.ncomp = ncomp;
+    a.pos0 = 0;
+    a.ell = level;
+    a.nq = c->nq;
+    a.logN = c->logN;
+    ew(c, op, a, level + 1, nbatch, k);
+}
+
+void tensor_b(he_ctx *c, int level, int B, const u64 *x, long long xb, long long xc, const u64 *y, long long yb,
+              long long yc, u64 *o, long long ob, long long oc)
+{
+    dim3 g(xblocks(c->N), level + 1, B);
+    tensor_kernel<<<g, 256, 0, c->stream>>>(x, xb, xc, y, yb, yc, o, ob, oc, c->t.pinfo, c->logN);
+}
+
+void modup_b(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, long long es, long long ds)
+{
+    const int beta = (level + 1 + c->alpha - 1) / c->alpha;
+    dim3 g(xblocks(c->N), level + 1 + c->nk, B * beta);
+    modup_kernel<<<g, 256, 0, c->stream>>>(y, ys, ext, es, ds, c->t.pinfo, c->t.up_conv, c->t.up_qd, level, c->alpha,
+                                           c->nq, c->np, c->nk, beta, c->logN);
+}
+
+void ks_inner_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const u64 *ext, long long es,
+                long long ds, const u64 *key, u64 *acc, long long as)
+{
+    const int beta = (level + 1 + c->alpha - 1) / c->alpha;
+    dim3 g(xblocks(c->N, 2), level + 1 + c->nk, 1);
+    ks_inner_kernel<<<g, 256, 0, c->stream>>>(d2, d2s, ext, es, ds, key, acc, as, c->t.pinfo, B, level, c->alpha,
+                                              c->nq, c->np, beta, c->logN);
+}
+
+void moddown_conv_b(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs)
+{
+    dim3 g(xblocks(c->N), level + 1, B * 2);
+    moddown_conv_kernel<<<g, 256, 0, c->stream>>>(acc, as, conv, cs, c->t.pinfo, c->t.dn_conv, c->t.dn_p, level,
+                                                  c->nq, c->nk, c->logN);
+}
+
+void moddown_finish_b(he_ctx *c, int level, int B, const u64 *acc, long long as, const u64 *conv, long long cs,
+                      const u64 *base, long long bs, long long bcs, int nbase, u64 *out, long long os,
+                      long long ocs)
+{
+    dim3 g(xblocks(c->N), level + 1, B * 2);
+    moddown_finish_kernel<<<g, 256, 0, c->stream>>>(acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs,
+                                                    c->t.pinfo, c->t.dn_pinv, level, c->nk, c->logN);
+}
+
+void rescale_bcast_b(he_ctx *c, int level, int B, const u64 *lastc, u64 *tmp)
+{
+    dim3 g(xblocks(c->N), level, B * 2);
+    rescale_bcast_kernel<<<g, 256, 0, c->stream>>>(lastc, tmp, c->t.pinfo, c->t.rs_ql, level, c->nq, c->logN);
+}
+
+void rescale_finish_b(he_ctx *c, int level, int B, const u64 *in, long long is, const u64 *tmp, u64 *out,
+                      long long os)
+{
+    dim3 g(xblocks(c->N, 1), B, 1);
+    rescale_finish_kernel<<<g, 256, 0, c->stream>>>(in, is, tmp, out, os, c->t.pinfo, c->t.rs_qinv, level, c->nq,
+                                                    c->logN);
+}
+
+void automorph_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,
+                 long long oc, u64 g)
+{
+    dim3 gr(xblocks(c->N), nl, B * 2);
+    automorph_kernel<<<gr, 256, 0, c->stream>>>(in, ib, ic, out, ob, oc, g, c->logN);
+}
+
+void batch_sum(he_ctx *c, int level, int B, const u64 *in, long long ib, long long ic, u64 *out, long long oc,
+               bool accumulate)
+{
+    dim3 g(xblocks(c->N), level + 1, 2);
+    batch_sum_kernel<<<g, 256, 0, c->stream>>>(in, ib, ic, B, out, oc, accumulate ? 1 : 0, c->t.pinfo, c->logN);
+}
+
+void sample_uniform(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp_base, int n_pos,
+                    const int *prime_of_pos, u64 *out)
+{
+    dim3 g(std::max(1, c->N / 4 / 256), n_pos, 1);
+    uniform_kernel<<<g, 256, 0, c->stream>>>(seed, type, index, comp_base, make_pp(n_pos, prime_of_pos), c->t.pinfo,
+                                             out, c->logN);
+}
+
+void sample_cbd(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp, int n_pos,
+                const int *prime_of_pos, u64 *out)
+{
+    dim3 g(std::max(1, c->N / 8 / 256), 1, 1);
+    cbd_kernel<<<g, 256, 0, c->stream>>>(seed, type, index, comp, make_pp(n_pos, prime_of_pos), c->t.pinfo, out,
+                                         c->logN);
+}
+
+void int_to_rns(he_ctx *c, const i64 *m, int n_pos, const int *prime_of_pos, u64 *out)
+{
+    dim3 g(xblocks(c->N), n_pos, 1);
+    int_to_rns_kernel<<<g, 256, 0, c->stream>>>(m, make_pp(n_pos, prime_of_pos), c->t.pinfo, out, c->logN);
+}
+
+void evk_combine(he_ctx *c, const u64 *a, const u64 *s, const u64 *e, const u64 *sp, int digit, u64 *b)
+{
+    int d0 = digit * c->alpha, d1 = std::min(d0 + c->alpha, c->nq);
+    dim3 g(xblocks(c->N), c->np, 1);
+    evk_kernel<<<g, 256, 0, c->stream>>>(a, s, e, sp, c->t.dn_p, c->t.pinfo, d0, d1, b, c->logN);
+}
+
+void enc_combine(he_ctx *c, int level, const u64 *a, const u64 *s, const u64 *e, const u64 *m, u64 *b)
+{
+    dim3 g(xblocks(c->N), level + 1, 1);
+    enc_kernel<<<g, 256, 0, c->stream>>>(a, s, e, m, c->t.pinfo, b, c->logN);
+}
+
+void dec_combine(he_ctx *c, int level, const u64 *ct, const u64 *s, u64 *out)
+{
+    dim3 g(xblocks(c->N), level + 1, 1);
+    dec_kernel<<<g, 256, 0, c->stream>>>(ct, s, c->t.pinfo, out, level, c->logN);
+}
+
+}  // namespace hek

@@ -1,0 +1,394 @@
+"""Python binding of libhe (include/he.h): argument marshalling only.
+
+Device memory for ciphertexts, plaintexts and keys is allocated with torch and
+handed to the library as raw pointers; every computation runs in the HIP
+library.  There is no CPU fallback: importing this module fails loudly when
+libhe.so has not been built.
+"""
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhe.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libhe.so is not built (run __graft_entry__.build() or "
+                      "python -m paper_2006_10091_amd.build); there is no fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+STATUS = {0: "HE_OK", 1: "HE_EINVAL", 2: "HE_ENOMEM", 3: "HE_ELEVEL", 4: "HE_ESCALE", 5: "HE_EKEY",
+          6: "HE_EDEVICE"}
+
+
+class HEError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.he_strerror(status).decode()
+        super().__init__("%s: %s (%s)" % (where, STATUS.get(status, status), msg))
+
+
+class he_params(ctypes.Structure):
+    _fields_ = [("log_n", c_int32), ("n_q", c_int32), ("n_special", c_int32), ("alpha", c_int32),
+                ("log_delta", c_int32)]
+
+
+class he_ct(ctypes.Structure):
+    _fields_ = [("data", c_void_p), ("level", c_int32), ("reserved", c_int32), ("scale", c_double)]
+
+
+he_pt = he_ct
+he_ct3 = he_ct
+
+
+class he_lr_plan(ctypes.Structure):
+    _fields_ = [("level_in", c_int32), ("level_out", c_int32)] + \
+        [(n, c_double) for n in ("s1", "s_mask", "s_m", "s_a", "t", "s_z3", "s_b3", "s_c", "s_z1", "s_b1", "s_g")] + \
+        [(n, c_int64) for n in ("k0", "k1", "k3", "kb1", "kw")]
+
+
+_P = POINTER
+_sig = {
+    "he_strerror": (ctypes.c_char_p, [c_int]),
+    "he_ctx_create": (c_int, [_P(he_params), c_void_p, _P(c_void_p)]),
+    "he_ctx_destroy": (c_int, [c_void_p]),
+    "he_ctx_set_stream": (c_int, [c_void_p, c_void_p]),
+    "he_ctx_primes": (c_int, [c_void_p, _P(c_uint64), c_int]),
+    "he_ctx_trim": (c_int, [c_void_p]),
+    "he_params_primes": (c_int, [_P(he_params), _P(c_uint64), c_int]),
+    "he_ct_bytes": (c_size_t, [c_void_p, c_int]),
+    "he_pt_bytes": (c_size_t, [c_void_p, c_int]),
+    "he_ct3_bytes": (c_size_t, [c_void_p, c_int]),
+    "he_keys_bytes": (c_size_t, [c_void_p, c_int]),
+    "he_keygen": (c_int, [c_void_p, c_uint64, _P(c_int32), c_int, c_void_p, c_size_t, _P(c_void_p)]),
+    "he_keys_destroy": (c_int, [c_void_p]),
+    "he_keys_download": (c_int, [c_void_p, c_void_p, c_int64, _P(c_uint64)]),
+    "he_encode": (c_int, [c_void_p, _P(c_double), _P(c_double), c_int, c_double, _P(c_int64)]),
+    "he_decode": (c_int, [c_void_p, _P(c_double), c_double, c_int, _P(c_double), _P(c_double)]),
+    "he_pt_load": (c_int, [c_void_p, _P(c_int64), c_int, c_double, _P(he_pt)]),
+    "he_encrypt": (c_int, [c_void_p, _P(he_pt), c_void_p, c_uint64, c_uint32, _P(he_ct)]),
+    "he_decrypt": (c_int, [c_void_p, _P(he_ct), c_void_p, _P(c_uint64)]),
+    "he_decrypt_decode": (c_int, [c_void_p, _P(he_ct), c_void_p, c_int, _P(c_double), _P(c_double)]),
+    "he_ct_download": (c_int, [c_void_p, _P(he_ct), _P(c_uint64)]),
+    "he_ct_upload": (c_int, [c_void_p, _P(c_uint64), c_int, c_double, _P(he_ct)]),
+    "he_mul": (c_int, [c_void_p, _P(he_ct), _P(he_ct), _P(he_ct3)]),
+    "he_relin": (c_int, [c_void_p, _P(he_ct3), c_void_p, _P(he_ct)]),
+    "he_rescale": (c_int, [c_void_p, _P(he_ct), _P(he_ct)]),
+    "he_rotate": (c_int, [c_void_p, _P(he_ct), c_int, c_void_p, _P(he_ct)]),
+    "he_add": (c_int, [c_void_p, _P(he_ct), _P(he_ct), _P(he_ct)]),
+    "he_mul_int": (c_int, [c_void_p, _P(he_ct), c_int64, c_double, _P(he_ct)]),
+    "he_mul_plain": (c_int, [c_void_p, _P(he_ct), _P(he_pt), _P(he_ct)]),
+    "he_drop_level": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct)]),
+    "he_plan_lr_step": (c_int, [_P(c_uint64), c_int, c_int, c_double, c_double, _P(c_double), c_double,
+                                _P(he_lr_plan)]),
+    "he_lr_grad_step": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), _P(he_pt), _P(c_double), c_double, c_int,
+                                c_int, c_void_p, c_int, _P(he_ct), _P(he_ct)]),
+    "he_ntt": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
+}
+for _n, (_r, _a) in _sig.items():
+    _f = getattr(_lib, _n)
+    _f.restype = _r
+    _f.argtypes = _a
+
+EXPORTS = sorted(_sig)
+
+
+def _chk(st, where):
+    if st != 0:
+        raise HEError(st, where)
+
+
+def _u64p(a):
+    return a.ctypes.data_as(POINTER(c_uint64))
+
+
+def _f64p(a):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def _i64p(a):
+    return a.ctypes.data_as(POINTER(c_int64))
+
+
+def params_primes(log_n, n_q, n_special, alpha, log_delta):
+    """Pure host: the prime chain selected by the parameters."""
+    p = he_params(log_n, n_q, n_special, alpha, log_delta)
+    out = np.zeros(n_q + n_special, dtype=np.uint64)
+    _chk(_lib.he_params_primes(ctypes.byref(p), _u64p(out), n_q + n_special), "he_params_primes")
+    return [int(v) for v in out]
+
+
+def plan_lr_step(primes, n_q, level, s_z, s_w, coef, eta_over_n):
+    """Pure host scale schedule (no device)."""
+    q = np.ascontiguousarray(primes, dtype=np.uint64)
+    cf = np.ascontiguousarray(coef, dtype=np.float64)
+    out = he_lr_plan()
+    _chk(_lib.he_plan_lr_step(_u64p(q), n_q, level, s_z, s_w, _f64p(cf), eta_over_n, ctypes.byref(out)),
+         "he_plan_lr_step")
+    return {f[0]: getattr(out, f[0]) for f in he_lr_plan._fields_}
+
+
+class Ciphertext:
+    """Device ciphertext (torch storage) + level and scale metadata."""
+
+    def __init__(self, tensor, level, scale, offset=0):
+        self.tensor = tensor
+        self.level = level
+        self.scale = scale
+        self.offset = offset  # in uint64 elements
+
+    @property
+    def ptr(self):
+        return self.tensor.data_ptr() + 8 * self.offset
+
+    def struct(self):
+        return he_ct(self.ptr, self.level, 0, self.scale)
+
+    def update(self, s):
+        self.level, self.scale = s.level, s.scale
+        return self
+
+
+Plaintext = Ciphertext
+
+
+class Keys:
+    def __init__(self, ctx, buf, handle, rot_steps):
+        self.ctx, self.buf, self.handle, self.rot_steps = ctx, buf, handle, list(rot_steps)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.he_keys_destroy(self.handle)
+            self.handle = None
+
+    def download(self, which):
+        c = self.ctx
+        n = c.np * c.N if which == -2 else c.dnum * 2 * c.np * c.N
+        out = np.zeros(n, dtype=np.uint64)
+        _chk(_lib.he_keys_download(c.h, self.handle, which, _u64p(out)), "he_keys_download")
+        return out
+
+
+class Context:
+    def __init__(self, log_n, n_q, n_special, alpha, log_delta, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        p = he_params(log_n, n_q, n_special, alpha, log_delta)
+        h = c_void_p()
+        s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+        _chk(_lib.he_ctx_create(ctypes.byref(p), c_void_p(s), ctypes.byref(h)), "he_ctx_create")
+        self.h = h
+        self.log_n, self.n_q, self.n_special, self.alpha, self.log_delta = log_n, n_q, n_special, alpha, log_delta
+        self.N = 1 << log_n
+        self.S = self.N // 2
+        self.np = n_q + n_special
+        self.dnum = (n_q + alpha - 1) // alpha
+        q = np.zeros(self.np, dtype=np.uint64)
+        _chk(_lib.he_ctx_primes(self.h, _u64p(q), self.np), "he_ctx_primes")
+        self.primes = [int(v) for v in q]
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.he_ctx_destroy(self.h)
+            self.h = None
+
+    @property
+    def delta(self):
+        return float(2 ** self.log_delta)
+
+    # ------------------------------------------------------------ memory
+    def _alloc(self, n_u64):
+        return self.torch.empty(int(n_u64), dtype=self.torch.int64, device=self.device)
+
+    def ct_empty(self, level):
+        return Ciphertext(self._alloc(2 * (level + 1) * self.N), level, 0.0)
+
+    def ct3_empty(self, level):
+        return Ciphertext(self._alloc(3 * (level + 1) * self.N), level, 0.0)
+
+    def pt_empty(self, level):
+        return Ciphertext(self._alloc((level + 1) * self.N), level, 0.0)
+
+    def ct_block(self, count, level):
+        """count ciphertexts at one level in one allocation (uniform stride)."""
+        per = 2 * (level + 1) * self.N
+        t = self._alloc(per * count)
+        return [Ciphertext(t, level, 0.0, offset=i * per) for i in range(count)]
+
+    def trim(self):
+        _chk(_lib.he_ctx_trim(self.h), "he_ctx_trim")
+
+    # ------------------------------------------------------------ keys / encoding
+    def keygen(self, seed, rot_steps=()):
+        steps = np.ascontiguousarray(list(rot_steps), dtype=np.int32)
+        nbytes = _lib.he_keys_bytes(self.h, len(steps))
+        buf = self._alloc((nbytes + 7) // 8)
+        h = c_void_p()
+        _chk(_lib.he_keygen(self.h, seed, steps.ctypes.data_as(POINTER(c_int32)), len(steps), c_void_p(buf.data_ptr()),
+                            nbytes, ctypes.byref(h)), "he_keygen")
+        return Keys(self, buf, h, rot_steps)
+
+    def encode(self, values, scale):
+        v = np.asarray(values)
+        re = np.ascontiguousarray(v.real, dtype=np.float64)
+        im = np.ascontiguousarray(v.imag, dtype=np.float64) if np.iscomplexobj(v) else None
+        out = np.zeros(self.N, dtype=np.int64)
+        _chk(_lib.he_encode(self.h, _f64p(re), _f64p(im) if im is not None else None, re.shape[0], scale,
+                            _i64p(out)), "he_encode")
+        return out
+
+    def decode(self, coeffs, scale, n=None):
+        m = np.ascontiguousarray(coeffs, dtype=np.float64)
+        n = self.S if n is None else n
+        re, im = np.zeros(n), np.zeros(n)
+        _chk(_lib.he_decode(self.h, _f64p(m), scale, n, _f64p(re), _f64p(im)), "he_decode")
+        return re + 1j * im
+
+    def pt_load(self, coeffs, level, scale, out=None):
+        out = out or self.pt_empty(level)
+        m = np.ascontiguousarray(coeffs, dtype=np.int64)
+        s = out.struct()
+        _chk(_lib.he_pt_load(self.h, _i64p(m), level, scale, ctypes.byref(s)), "he_pt_load")
+        return out.update(s)
+
+    # ------------------------------------------------------------ encryption
+    def encrypt(self, pt, keys, seed, index, out=None):
+        out = out or self.ct_empty(pt.level)
+        p, s = pt.struct(), out.struct()
+        _chk(_lib.he_encrypt(self.h, ctypes.byref(p), keys.handle, seed, index, ctypes.byref(s)), "he_encrypt")
+        return out.update(s)
+
+    def decrypt(self, ct, keys):
+        out = np.zeros((ct.level + 1, self.N), dtype=np.uint64)
+        s = ct.struct()
+        _chk(_lib.he_decrypt(self.h, ctypes.byref(s), keys.handle, _u64p(out)), "he_decrypt")
+        return out
+
+    def decrypt_decode(self, ct, keys, n=None):
+        n = self.S if n is None else n
+        re, im = np.zeros(n), np.zeros(n)
+        s = ct.struct()
+        _chk(_lib.he_decrypt_decode(self.h, ctypes.byref(s), keys.handle, n, _f64p(re), _f64p(im)),
+             "he_decrypt_decode")
+        return re + 1j * im
+
+    def download(self, ct):
+        out = np.zeros((2, ct.level + 1, self.N), dtype=np.uint64)
+        s = ct.struct()
+        _chk(_lib.he_ct_download(self.h, ctypes.byref(s), _u64p(out)), "he_ct_download")
+        return out
+
+    def upload(self, arr, level, scale, out=None):
+        out = out or self.ct_empty(level)
+        a = np.ascontiguousarray(arr, dtype=np.uint64)
+        assert a.shape == (2, level + 1, self.N)
+        s = out.struct()
+        _chk(_lib.he_ct_upload(self.h, _u64p(a), level, scale, ctypes.byref(s)), "he_ct_upload")
+        return out.update(s)
+
+    # ------------------------------------------------------------ operations
+    def mul(self, x, y, out=None):
+        out = out or self.ct3_empty(x.level)
+        a, b, o = x.struct(), y.struct(), out.struct()
+        _chk(_lib.he_mul(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(o)), "he_mul")
+        return out.update(o)
+
+    def relin(self, d, keys, out=None):
+        out = out or self.ct_empty(d.level)
+        a, o = d.struct(), out.struct()
+        _chk(_lib.he_relin(self.h, ctypes.byref(a), keys.handle, ctypes.byref(o)), "he_relin")
+        return out.update(o)
+
+    def rescale(self, x, out=None):
+        out = out or self.ct_empty(max(x.level - 1, 0))
+        a, o = x.struct(), out.struct()
+        _chk(_lib.he_rescale(self.h, ctypes.byref(a), ctypes.byref(o)), "he_rescale")
+        return out.update(o)
+
+    def rotate(self, x, steps, keys, out=None):
+        out = out or self.ct_empty(x.level)
+        a, o = x.struct(), out.struct()
+        _chk(_lib.he_rotate(self.h, ctypes.byref(a), steps, keys.handle, ctypes.byref(o)), "he_rotate")
+        return out.update(o)
+
+    def add(self, x, y, out=None):
+        out = out or self.ct_empty(x.level)
+        a, b, o = x.struct(), y.struct(), out.struct()
+        _chk(_lib.he_add(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(o)), "he_add")
+        return out.update(o)
+
+    def mul_int(self, x, k, out_scale, out=None):
+        out = out or self.ct_empty(x.level)
+        a, o = x.struct(), out.struct()
+        _chk(_lib.he_mul_int(self.h, ctypes.byref(a), int(k), out_scale, ctypes.byref(o)), "he_mul_int")
+        return out.update(o)
+
+    def mul_plain(self, x, pt, out=None):
+        out = out or self.ct_empty(x.level)
+        a, p, o = x.struct(), pt.struct(), out.struct()
+        _chk(_lib.he_mul_plain(self.h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(o)), "he_mul_plain")
+        return out.update(o)
+
+    def drop_level(self, x, level, out=None):
+        out = out or self.ct_empty(level)
+        a, o = x.struct(), out.struct()
+        _chk(_lib.he_drop_level(self.h, ctypes.byref(a), level, ctypes.byref(o)), "he_drop_level")
+        return out.update(o)
+
+    def plan_lr_step(self, level, s_z, s_w, coef, eta_over_n):
+        return plan_lr_step(self.primes, self.n_q, level, s_z, s_w, coef, eta_over_n)
+
+    def lr_grad_step(self, Z, W, mask, coef, eta_over_n, cols, rows, keys, mode=1, W_out=None, G_out=None,
+                     want_g=True):
+        """One encrypted gradient step (he_lr_grad_step).  Z: list of block
+        ciphertexts sharing one allocation (ct_block).  Returns (W', g)."""
+        zs = (he_ct * len(Z))(*[z.struct() for z in Z])
+        w, m = W.struct(), mask.struct()
+        lo = max(W.level - 4, 0)
+        W_out = W_out or self.ct_empty(lo)
+        if want_g:
+            G_out = G_out or self.ct_empty(lo)
+        wo = W_out.struct()
+        go = G_out.struct() if want_g else None
+        cf = np.ascontiguousarray(coef, dtype=np.float64)
+        _chk(_lib.he_lr_grad_step(self.h, zs, len(Z), ctypes.byref(w), ctypes.byref(m), _f64p(cf), eta_over_n,
+                                  cols, rows, keys.handle, mode, ctypes.byref(wo),
+                                  ctypes.byref(go) if go is not None else None), "he_lr_grad_step")
+        W_out.update(wo)
+        if want_g:
+            G_out.update(go)
+        return W_out, (G_out if want_g else None)
+
+    def ntt(self, tensor, n_limbs, prime_idx0, period, direction):
+        _chk(_lib.he_ntt(self.h, c_void_p(tensor.data_ptr()), n_limbs, prime_idx0, period, direction), "he_ntt")
+
+
+# ---------------------------------------------------------------- packing (data layout of the step)
+def pack_blocks(X, y, S):
+    """Row-major blocks of Z = y (.) X: slot i*c + j of block b holds
+    y_{b r + i} x_{b r + i, j}; c = next power of two >= d, r = S / c."""
+    n, d = X.shape
+    c = 1
+    while c < d:
+        c *= 2
+    r = S // c
+    nb = -(-n // r)
+    Z = np.zeros((nb * r, c))
+    Z[:n, :d] = y[:, None] * X
+    return Z.reshape(nb, S), c, r
+
+
+def pack_weights(w, S, c):
+    row = np.zeros(c)
+    row[: len(w)] = w
+    return np.tile(row, S // c)
+
+
+def column0_mask(S, c):
+    m = np.zeros(S)
+    m[::c] = 1.0
+    return m

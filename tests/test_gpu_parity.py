@@ -1,0 +1,262 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Ciphertexts, keys and every operation are compared BIT FOR BIT in coefficient
+form on identical integer inputs (the oracle's encodings are fed to both
+sides; no oracle input comes from the GPU).  Decrypted gradients are compared
+with the FP64 plaintext gradient at the benchmark spec's tolerance 2^-20 (relative,
+infinity norm).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import ckks as O  # noqa: E402
+from oracle import lr as LR  # noqa: E402
+from paper_2006_10091_amd import synth  # noqa: E402
+
+TOL = 2.0 ** -20
+
+
+def _H():
+    from paper_2006_10091_amd import he as H
+    return H
+
+
+def _cfg(name):
+    W = synth.WORKLOADS[name]
+    return W, (W["logN"], W["nq"], W["nk"], W["alpha"], W["log_delta"])
+
+
+@pytest.fixture(scope="module")
+def small():
+    """Small workload: oracle params/keys and a GPU context/keys with the same seeds."""
+    W, cfg = _cfg("small")
+    P = O.Params(*cfg)
+    H = _H()
+    ctx = H.Context(*cfg)
+    X, y = synth.small_data()
+    blocks, c, r = LR.pack_blocks(X, y, P.S)
+    steps = LR.rotation_steps(c, r)
+    okeys = O.Keys(P, W["seed_keys"], rot_steps=steps)
+    gkeys = ctx.keygen(W["seed_keys"], steps)
+    return dict(W=W, P=P, ctx=ctx, X=X, y=y, blocks=blocks, c=c, r=r, okeys=okeys, gkeys=gkeys, H=H)
+
+
+def random_ct(ctx, P, level, seed, scale=1.0):
+    data = np.stack([synth.uniform_residues(seed, P.q[: level + 1], P.N),
+                     synth.uniform_residues(seed + 1, P.q[: level + 1], P.N)])
+    return data, ctx.upload(data, level, scale)
+
+
+# ------------------------------------------------------------------ chain, NTT, keys, encryption
+def test_prime_chain_matches(small):
+    assert small["ctx"].primes == small["P"].q
+
+
+def test_upload_download_roundtrip_is_identity(small):
+    ctx, P = small["ctx"], small["P"]
+    for level in (0, 2, P.L):
+        data, ct = random_ct(ctx, P, level, 10 + level)
+        assert np.array_equal(ctx.download(ct), data)
+
+
+def test_ntt_product_matches_oracle(small):
+    """NTT -> pointwise -> iNTT through he_mul equals the oracle's negacyclic products."""
+    ctx, P = small["ctx"], small["P"]
+    xd, x = random_ct(ctx, P, P.L, 21)
+    yd, y = random_ct(ctx, P, P.L, 23)
+    d3 = ctx.mul(x, y)
+    want, _ = O.tensor(P, O.CT(xd, P.L, 1.0), O.CT(yd, P.L, 1.0))
+    H = small["H"]
+    per = 2 * (P.L + 1) * P.N
+    first = ctx.download(H.Ciphertext(d3.tensor, P.L, 1.0))
+    last = ctx.download(H.Ciphertext(d3.tensor, P.L, 1.0, offset=per // 2))
+    assert np.array_equal(first[0], want[0]) and np.array_equal(first[1], want[1])
+    assert np.array_equal(last[1], want[2])
+
+
+def test_keys_bit_exact(small):
+    P, okeys, gkeys = small["P"], small["okeys"], small["gkeys"]
+    nfull = P.nq + P.nk
+    s = gkeys.download(-2).reshape(nfull, P.N)
+    srns = np.array([[int(v) % q for v in okeys.s] for q in P.q], dtype=np.uint64)
+    assert np.array_equal(s, srns)
+    assert np.array_equal(gkeys.download(-1).reshape(okeys.rlk.shape), okeys.rlk)
+    for t in (1, -1, small["c"]):
+        g = O.galois(P, t)
+        assert np.array_equal(gkeys.download(g).reshape(okeys.rot[g].shape), okeys.rot[g])
+
+
+def test_encrypt_bit_exact(small):
+    ctx, P = small["ctx"], small["P"]
+    m = synth.small_poly(5, P.N, 1 << 40)
+    for level, idx in ((P.L, 0), (1, 7)):
+        pt = ctx.pt_load(m, level, P.delta)
+        ct = ctx.encrypt(pt, small["gkeys"], 3001, idx)
+        want = O.encrypt_sk(P, small["okeys"], m, level, P.delta, 3001, idx)
+        assert np.array_equal(ctx.download(ct), want.data)
+        res = ctx.decrypt(ct, small["gkeys"])
+        assert np.array_equal(res, O.decrypt_residues(P, small["okeys"], want))
+
+
+# ------------------------------------------------------------------ operations
+def test_ops_bit_exact_small(small):
+    ctx, P, ok, gk = small["ctx"], small["P"], small["okeys"], small["gkeys"]
+    l = P.L
+    xd, x = random_ct(ctx, P, l, 31)
+    yd, y = random_ct(ctx, P, l, 33)
+    ox, oy = O.CT(xd, l, 1.0), O.CT(yd, l, 1.0)
+    # relinearised product
+    got = ctx.relin(ctx.mul(x, y), gk)
+    want = O.mul(P, ox, oy, ok)
+    assert np.array_equal(ctx.download(got), want.data)
+    # rescale (also in place)
+    r = ctx.rescale(got)
+    assert np.array_equal(ctx.download(r), O.rescale(P, want).data)
+    # rotations, both directions
+    for t in (1, -2, small["c"]):
+        assert np.array_equal(ctx.download(ctx.rotate(x, t, gk)), O.rotate(P, ox, t, ok).data)
+    # add, integer and plaintext products
+    assert np.array_equal(ctx.download(ctx.add(x, y)), O.add(P, ox, oy).data)
+    k = -(1 << 61) + 12345
+    assert np.array_equal(ctx.download(ctx.mul_int(x, k, 1.0)), O.mul_int(P, ox, k).data)
+    m = synth.small_poly(8, P.N, 1 << 30)
+    pt = ctx.pt_load(m, l, 1.0)
+    assert np.array_equal(ctx.download(ctx.mul_plain(x, pt)), O.mul_plain(P, ox, m, 1.0).data)
+    # drop level
+    assert np.array_equal(ctx.download(ctx.drop_level(x, 2)), O.drop(ox, 2).data)
+
+
+def test_rescale_in_place(small):
+    ctx, P = small["ctx"], small["P"]
+    xd, x = random_ct(ctx, P, P.L, 41)
+    want = O.rescale(P, O.CT(xd, P.L, 1.0))
+    ctx.rescale(x, out=x)
+    assert x.level == P.L - 1
+    assert np.array_equal(ctx.download(x), want.data)
+
+
+def test_error_paths(small):
+    ctx, P, gk, H = small["ctx"], small["P"], small["gkeys"], small["H"]
+    _, x = random_ct(ctx, P, 0, 51)
+    with pytest.raises(H.HEError) as e:
+        ctx.rescale(x)
+    assert e.value.status == 3
+    _, a = random_ct(ctx, P, 2, 52, scale=1.0)
+    _, b = random_ct(ctx, P, 2, 53, scale=2.0)
+    with pytest.raises(H.HEError) as e:
+        ctx.add(a, b)
+    assert e.value.status == 4
+    with pytest.raises(H.HEError) as e:
+        ctx.rotate(a, 3, gk)  # no key for step 3
+    assert e.value.status == 5
+
+
+# ------------------------------------------------------------------ the gradient step, small workload
+def _encrypt_small(small, blocks, w0):
+    """Same integer plaintexts and seeds on both sides."""
+    P, ctx, W = small["P"], small["ctx"], small["W"]
+    oZ, gZ = [], ctx.ct_block(blocks.shape[0], P.L)
+    for i in range(blocks.shape[0]):
+        m = O.encode(blocks[i], P.delta, P.N)
+        oZ.append(O.encrypt_sk(P, small["okeys"], m, P.L, P.delta, W["seed_enc"], i))
+        ctx.encrypt(ctx.pt_load(m, P.L, P.delta), small["gkeys"], W["seed_enc"], i, out=gZ[i])
+    mw = O.encode(LR.pack_weights(w0, P.S, small["c"]), P.delta, P.N)
+    oW = O.encrypt_sk(P, small["okeys"], mw, P.L, P.delta, W["seed_enc"], 100000)
+    gW = ctx.encrypt(ctx.pt_load(mw, P.L, P.delta), small["gkeys"], W["seed_enc"], 100000)
+    return oZ, gZ, oW, gW
+
+
+COEF = None
+
+
+def _coef():
+    c = LR.grad_poly_binomial(8.0)
+    c[0], c[2] = 0.5, 0.0
+    return [float(v) for v in c]
+
+
+@pytest.fixture(scope="module")
+def small_step(small):
+    P = small["P"]
+    w0 = synth.initial_weights("small", 16, small["W"]["seed_w"])
+    coef = _coef()
+    eta_n = 1.0 / small["X"].shape[0]
+    oZ, gZ, oW, gW = _encrypt_small(small, small["blocks"], w0)
+    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n)
+    mask_m = O.encode(LR.column_mask(P.S, small["c"]), pl["s_mask"], P.N)
+    oWn, og = LR.lr_grad_step(P, small["okeys"], oZ, oW, mask_m, coef, eta_n, small["c"], small["r"], plan=pl)
+    return dict(w0=w0, coef=coef, eta_n=eta_n, gZ=gZ, gW=gW, oW=oW, pl=pl, mask_m=mask_m, oWn=oWn, og=og)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_lr_step_bit_exact_small(small, small_step, mode):
+    ctx, P, s = small["ctx"], small["P"], small_step
+    mask = ctx.pt_load(s["mask_m"], P.L - 1, s["pl"]["s_mask"])
+    for _ in range(2 if mode == 2 else 1):  # mode 2: capture, then replay
+        Wn, g = ctx.lr_grad_step(s["gZ"], s["gW"], mask, s["coef"], s["eta_n"], small["c"], small["r"],
+                                 small["gkeys"], mode=mode)
+        assert Wn.level == P.L - 4 and Wn.scale == s["pl"]["s_g"]
+        assert np.array_equal(ctx.download(Wn), s["oWn"].data)
+        assert np.array_equal(ctx.download(g), s["og"].data)
+
+
+def test_lr_step_gradient_within_tolerance_small(small, small_step):
+    """End to end on the GPU (library encode): decrypted g vs the FP64 gradient
+    at the decrypted input weights."""
+    ctx, P, gk, s = small["ctx"], small["P"], small["gkeys"], small_step
+    c, r = small["c"], small["r"]
+    Z = ctx.ct_block(small["blocks"].shape[0], P.L)
+    for i in range(len(Z)):
+        ctx.encrypt(ctx.pt_load(ctx.encode(small["blocks"][i], P.delta), P.L, P.delta), gk, 77, i, out=Z[i])
+    Wc = ctx.encrypt(ctx.pt_load(ctx.encode(LR.pack_weights(s["w0"], P.S, c), P.delta), P.L, P.delta), gk, 77,
+                     9999)
+    pl = ctx.plan_lr_step(P.L, P.delta, P.delta, s["coef"], s["eta_n"])
+    mask = ctx.pt_load(ctx.encode(LR.column_mask(P.S, c), pl["s_mask"]), P.L - 1, pl["s_mask"])
+    Wn, g = ctx.lr_grad_step(Z, Wc, mask, s["coef"], s["eta_n"], c, r, gk, mode=1)
+    wdec = ctx.decrypt_decode(Wc, gk).real[:16]
+    gref = LR.lr_gradient_fp64(small["X"], small["y"], wdec, s["coef"], s["eta_n"])
+    gd = ctx.decrypt_decode(g, gk).real.reshape(r, c)[:, :16]
+    for row in (0, r // 3, r - 1):
+        assert np.max(np.abs(gd[row] - gref)) / np.max(np.abs(gref)) < TOL
+    wn = ctx.decrypt_decode(Wn, gk).real.reshape(r, c)[0, :16]
+    assert np.max(np.abs(wn - wdec - gref)) / np.max(np.abs(wdec + gref)) < TOL
+
+
+def test_lr_step_ragged_single_block(small):
+    """300 samples: one block, 44 zero rows; batched form vs oracle, bit for bit."""
+    ctx, P = small["ctx"], small["P"]
+    X, y = synth.small_data(n=300)
+    blocks, c, r = LR.pack_blocks(X, y, P.S)
+    assert blocks.shape[0] == 2 and (300 % r) != 0
+    w0 = synth.initial_weights("small", 16, 4321)
+    coef = _coef()
+    oZ, gZ, oW, gW = _encrypt_small(small, blocks, w0)
+    for nb in (1, 2):
+        pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, 1 / 300)
+        mask_m = O.encode(LR.column_mask(P.S, c), pl["s_mask"], P.N)
+        oWn, og = LR.lr_grad_step(P, small["okeys"], oZ[:nb], oW, mask_m, coef, 1 / 300, c, r, plan=pl)
+        mask = ctx.pt_load(mask_m, P.L - 1, pl["s_mask"])
+        Wn, g = ctx.lr_grad_step(gZ[:nb], gW, mask, coef, 1 / 300, c, r, small["gkeys"], mode=1)
+        assert np.array_equal(ctx.download(Wn), oWn.data)
+        assert np.array_equal(ctx.download(g), og.data)
+
+
+def test_lr_step_error_paths(small, small_step):
+    ctx, P, gk, H, s = small["ctx"], small["P"], small["gkeys"], small["H"], small_step
+    c, r = small["c"], small["r"]
+    mask = ctx.pt_load(s["mask_m"], P.L - 1, s["pl"]["s_mask"])
+    low = ctx.drop_level(s["gW"], 3)
+    with pytest.raises(H.HEError) as e:
+        ctx.lr_grad_step(s["gZ"], low, mask, s["coef"], s["eta_n"], c, r, gk)
+    assert e.value.status == 3  # HE_ELEVEL: fewer than 4 levels
+    bad = ctx.pt_load(s["mask_m"], P.L - 1, s["pl"]["s_mask"] * 2)
+    with pytest.raises(H.HEError) as e:
+        ctx.lr_grad_step(s["gZ"], s["gW"], bad, s["coef"], s["eta_n"], c, r, gk)
+    assert e.value.status == 4  # HE_ESCALE: mask at the wrong scale
+    few = ctx.keygen(2001, [1, -1])
+    with pytest.raises(H.HEError) as e:
+        ctx.lr_grad_step(s["gZ"], s["gW"], mask, s["coef"], s["eta_n"], c, r, few)
+    assert e.value.status == 5  # HE_EKEY: rotations missing
