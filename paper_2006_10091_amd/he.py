@@ -10,6 +10,9 @@ import os
 from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
 
 import numpy as np
+# torch's HIP runtime must be the process's only one: load it before libhe.so,
+# whose libamdhip64.so.7 dependency then resolves to the already-loaded copy.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhe.so")

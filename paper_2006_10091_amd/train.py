@@ -1,0 +1,111 @@
+"""Worker / parameter-server loop of the paper over the C ABI.
+
+Alg. 2 (parameter server): generates the keys, encrypts the data blocks and
+the initial weights with sk, and on a worker's request decrypts the
+weights, takes them as its own copy and sends them back freshly encrypted at
+the top level.  Alg. 1 (worker): evaluates eq. (appr) + eq. (update)
+homomorphically once per iteration and requests a refresh every `l`
+iterations.  On one GPU both roles share the device; the request is a host
+call (the paper's MPI messages carry one ciphertext each way).
+"""
+import numpy as np
+
+from . import he as H
+
+
+class ParameterServer:
+    """Holds sk (inside `keys`) and the plaintext weights; Alg. 2."""
+
+    def __init__(self, ctx, keys, d, cols, seed_enc, first_index=1 << 24):
+        self.ctx, self.keys, self.d, self.cols = ctx, keys, d, cols
+        self.seed_enc = seed_enc
+        self.index = first_index  # ChaCha20 stream index of the next weight encryption
+        self.w = None
+        self._buf = None
+        self._pt = None
+
+    def encrypt_weights(self, w):
+        """Encrypt w at the top level into the server's one weight buffer."""
+        ctx = self.ctx
+        L = ctx.n_q - 1
+        self.w = np.array(w, dtype=np.float64)
+        m = ctx.encode(H.pack_weights(self.w, ctx.S, self.cols), ctx.delta)
+        if self._buf is None:
+            self._buf = ctx.ct_empty(L)
+            self._pt = ctx.pt_empty(L)
+        ct = ctx.encrypt(ctx.pt_load(m, L, ctx.delta, out=self._pt), self.keys, self.seed_enc, self.index,
+                         out=self._buf)
+        self.index += 1
+        return ct
+
+    def refresh(self, W):
+        """Decrypt the worker's weights, update the server's copy, re-encrypt."""
+        slots = self.ctx.decrypt_decode(W, self.keys).real
+        w = slots.reshape(-1, self.cols)[0, : self.d]
+        return self.encrypt_weights(w)
+
+
+class Worker:
+    """Evaluates the encrypted gradient step on its shard; Alg. 1."""
+
+    def __init__(self, ctx, keys, Z, coef, eta_over_n, cols, rows, mode=2):
+        self.ctx, self.keys, self.Z = ctx, keys, Z
+        self.coef, self.eta_over_n = list(coef), eta_over_n
+        self.cols, self.rows, self.mode = cols, rows, mode
+        self._masks = {}
+        self._bufs = {}
+
+    def _mask(self, level, s_mask):
+        key = (level, s_mask)
+        if key not in self._masks:
+            ctx = self.ctx
+            m = ctx.encode(H.column0_mask(ctx.S, self.cols), s_mask)
+            self._masks[key] = ctx.pt_load(m, level - 1, s_mask)
+        return self._masks[key]
+
+    def _out(self, level, slot):
+        key = (level, slot)
+        if key not in self._bufs:
+            self._bufs[key] = self.ctx.ct_empty(level)
+        return self._bufs[key]
+
+    def step(self, W, want_g=False):
+        """One iteration; the output lives in a buffer owned per output level
+        (levels only decrease between refreshes, so it never aliases W)."""
+        ctx = self.ctx
+        pl = ctx.plan_lr_step(W.level, self.Z[0].scale, W.scale, self.coef, self.eta_over_n)
+        mask = self._mask(W.level, pl["s_mask"])
+        lo = W.level - 4
+        W_out = self._out(lo, 0)
+        G_out = self._out(lo, 1) if want_g else None
+        return ctx.lr_grad_step(self.Z, W, mask, self.coef, self.eta_over_n, self.cols, self.rows, self.keys,
+                                mode=self.mode, W_out=W_out, G_out=G_out, want_g=want_g)
+
+
+def encrypt_shard(ctx, keys, X, y, seed_enc):
+    """Alg. 2 initialisation: pack Z = y (.) X into blocks and encrypt each with sk."""
+    blocks, cols, rows = H.pack_blocks(X, y, ctx.S)
+    L = ctx.n_q - 1
+    Z = ctx.ct_block(blocks.shape[0], L)
+    for i in range(blocks.shape[0]):
+        ctx.encrypt(ctx.pt_load(ctx.encode(blocks[i], ctx.delta), L, ctx.delta), keys, seed_enc, i, out=Z[i])
+    return Z, cols, rows
+
+
+def train(ctx, keys, X, y, coef, eta, iterations, refresh_every, w0, seed_enc, mode=2, record=None):
+    """Alg. 1 + Alg. 2 on one GPU.  Returns the server's final plaintext
+    weights (after a last refresh) and, if `record` is a list, appends the
+    decrypted weights after every iteration."""
+    n, d = X.shape
+    Z, cols, rows = encrypt_shard(ctx, keys, X, y, seed_enc)
+    ps = ParameterServer(ctx, keys, d, cols, seed_enc)
+    worker = Worker(ctx, keys, Z, coef, eta / n, cols, rows, mode=mode)
+    W = ps.encrypt_weights(w0)
+    for k in range(1, iterations + 1):
+        W, _ = worker.step(W)
+        if record is not None:
+            record.append(ctx.decrypt_decode(W, keys).real.reshape(-1, cols)[0, :d].copy())
+        if k % refresh_every == 0 or W.level < 4:
+            W = ps.refresh(W)
+    ps.refresh(W)
+    return ps.w

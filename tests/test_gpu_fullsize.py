@@ -1,0 +1,130 @@
+"""Parity at the headline size (N = 2^16, 20 + 4 primes, dnum 5) in the
+launch configuration the bench times.
+
+* every key-switching operation of the step, bit for bit against the oracle,
+  at the levels the step uses;
+* one-block steps (the whole circuit, row sum included) bit for bit against the
+  oracle, in the batched form;
+* the full 47-block shard: the plain, batched and graph-replayed forms agree
+  bit for bit, and the decrypted gradient is within 2^-20 of the FP64 one.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import ckks as O  # noqa: E402
+from oracle import lr as LR  # noqa: E402
+from paper_2006_10091_amd import synth  # noqa: E402
+
+W = synth.WORKLOADS["image"]
+CFG = (W["logN"], W["nq"], W["nk"], W["alpha"], W["log_delta"])
+
+
+def _coef():
+    c = LR.grad_poly_binomial(8.0)
+    return [0.5, float(c[1]), 0.0, float(c[3])]
+
+
+@pytest.fixture(scope="module")
+def env():
+    from paper_2006_10091_amd import he as H
+    P = O.Params(*CFG)
+    ctx = H.Context(*CFG)
+    X, y = synth.image_data(W["seed_data"], W["n"])
+    blocks, c, r = H.pack_blocks(X, y, ctx.S)
+    steps = LR.rotation_steps(c, r)
+    gk = ctx.keygen(W["seed_keys"], steps)
+    return dict(H=H, P=P, ctx=ctx, X=X, y=y, blocks=blocks, c=c, r=r, steps=steps, gk=gk)
+
+
+@pytest.fixture(scope="module")
+def okeys(env):
+    return O.Keys(env["P"], W["seed_keys"], rot_steps=env["steps"])
+
+
+def _rct(env, level, seed):
+    P = env["P"]
+    d = np.stack([synth.uniform_residues(seed, P.q[: level + 1], P.N),
+                  synth.uniform_residues(seed + 1, P.q[: level + 1], P.N)])
+    return d, env["ctx"].upload(d, level, 1.0)
+
+
+def test_full_size_keyswitch_ops_bit_exact(env, okeys):
+    ctx, P, gk = env["ctx"], env["P"], env["gk"]
+    L = P.L
+    xd, x = _rct(env, L, 101)
+    yd, y = _rct(env, L, 103)
+    got = ctx.rescale(ctx.relin(ctx.mul(x, y), gk))
+    want = O.rescale(P, O.mul(P, O.CT(xd, L, 1.0), O.CT(yd, L, 1.0), okeys))
+    assert np.array_equal(ctx.download(got), want.data)
+    for level, t in ((L - 1, 1), (L - 2, -env["c"] // 2), (L - 4, env["c"] * 64)):
+        zd, z = _rct(env, level, 200 + level)
+        assert np.array_equal(ctx.download(ctx.rotate(z, t, gk)), O.rotate(P, O.CT(zd, level, 1.0), t, okeys).data)
+
+
+def test_full_size_one_block_step_bit_exact(env, okeys):
+    """One block of the shard through the whole circuit, GPU batched form vs oracle."""
+    ctx, P, gk = env["ctx"], env["P"], env["gk"]
+    coef = _coef()
+    eta_n = 1.0 / 128
+    m = O.encode(env["blocks"][5], P.delta, P.N)
+    oZ = O.encrypt_sk(P, okeys, m, P.L, P.delta, 9, 5)
+    gZ = ctx.ct_block(1, P.L)
+    ctx.encrypt(ctx.pt_load(m, P.L, P.delta), gk, 9, 5, out=gZ[0])
+    w = np.random.default_rng(5).uniform(-0.05, 0.05, 196)
+    mw = O.encode(LR.pack_weights(w, P.S, env["c"]), P.delta, P.N)
+    oW = O.encrypt_sk(P, okeys, mw, P.L, P.delta, 9, 999)
+    gW = ctx.encrypt(ctx.pt_load(mw, P.L, P.delta), gk, 9, 999)
+    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n)
+    mm = O.encode(LR.column_mask(P.S, env["c"]), pl["s_mask"], P.N)
+    oWn, og = LR.lr_grad_step(P, okeys, [oZ], oW, mm, coef, eta_n, env["c"], env["r"], plan=pl)
+    mask = ctx.pt_load(mm, P.L - 1, pl["s_mask"])
+    Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, env["c"], env["r"], gk, mode=1)
+    assert np.array_equal(ctx.download(Wn), oWn.data)
+    assert np.array_equal(ctx.download(g), og.data)
+
+
+def test_full_shard_forms_agree_and_gradient_within_tolerance(env):
+    ctx, gk, H = env["ctx"], env["gk"], env["H"]
+    L, S, c, r = ctx.n_q - 1, ctx.S, env["c"], env["r"]
+    blocks, X, y = env["blocks"], env["X"], env["y"]
+    Z = ctx.ct_block(blocks.shape[0], L)
+    for i in range(blocks.shape[0]):
+        ctx.encrypt(ctx.pt_load(ctx.encode(blocks[i], ctx.delta), L, ctx.delta), gk, W["seed_enc"], i, out=Z[i])
+    w0 = np.random.default_rng(8).uniform(-0.02, 0.02, X.shape[1])
+    Wc = ctx.encrypt(ctx.pt_load(ctx.encode(H.pack_weights(w0, S, c), ctx.delta), L, ctx.delta), gk, 3, 77777)
+    coef, eta_n = _coef(), 1.0 / X.shape[0]
+    pl = ctx.plan_lr_step(L, ctx.delta, ctx.delta, coef, eta_n)
+    mask = ctx.pt_load(ctx.encode(H.column0_mask(S, c), pl["s_mask"]), L - 1, pl["s_mask"])
+    outs = []
+    for mode in (0, 1, 2, 2):
+        Wn, g = ctx.lr_grad_step(Z, Wc, mask, coef, eta_n, c, r, gk, mode=mode)
+        outs.append((ctx.download(Wn), ctx.download(g)))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+    wdec = ctx.decrypt_decode(Wc, gk).real[: X.shape[1]]
+    gref = LR.lr_gradient_fp64(X, y, wdec, coef, eta_n)
+    gd = ctx.decrypt_decode(g, gk).real.reshape(r, c)
+    for row in (0, r - 1):
+        assert np.max(np.abs(gd[row, : X.shape[1]] - gref)) / np.max(np.abs(gref)) < 2.0 ** -20
+        assert np.max(np.abs(gd[row, X.shape[1]:])) < 2.0 ** -20 * np.max(np.abs(gref))  # padded columns stay 0
+    wn = ctx.decrypt_decode(Wn, gk).real[: X.shape[1]]
+    assert np.max(np.abs(wn - wdec - gref)) / np.max(np.abs(wdec + gref)) < 2.0 ** -20
+
+
+def test_full_size_training_ten_steps_refresh_every_four(env):
+    """The image shard's 10 steps with a refresh every 4 (Alg. 1 / Alg. 2),
+    graph-replayed batched form, against FP64 plaintext training."""
+    from paper_2006_10091_amd import train as T
+    ctx, gk = env["ctx"], env["gk"]
+    X, y = env["X"], env["y"]
+    coef = _coef()
+    rec = []
+    w_final = T.train(ctx, gk, X, y, coef, 1.0, 10, 4, np.zeros(X.shape[1]), 3004, mode=2, record=rec)
+    w = np.zeros(X.shape[1])
+    for k in range(10):
+        w = w + LR.lr_gradient_fp64(X, y, w, coef, 1.0 / X.shape[0])
+        assert np.max(np.abs(rec[k] - w)) / np.max(np.abs(w)) < 2.0 ** -20, k
+    assert np.max(np.abs(w_final - w)) / np.max(np.abs(w)) < 2.0 ** -20

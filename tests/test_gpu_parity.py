@@ -260,3 +260,20 @@ def test_lr_step_error_paths(small, small_step):
     with pytest.raises(H.HEError) as e:
         ctx.lr_grad_step(s["gZ"], s["gW"], mask, s["coef"], s["eta_n"], c, r, few)
     assert e.value.status == 5  # HE_EKEY: rotations missing
+
+
+def test_training_with_refresh_small(small):
+    """Alg. 1 + Alg. 2 on the small workload: one step per refresh (4 levels);
+    the trajectory follows FP64 plaintext training."""
+    from paper_2006_10091_amd import train as T
+    ctx, gk = small["ctx"], small["gkeys"]
+    X, y = small["X"], small["y"]
+    coef = _coef()
+    w0 = synth.initial_weights("small", 16, small["W"]["seed_w"])
+    rec = []
+    w_final = T.train(ctx, gk, X, y, coef, 1.0, 3, 1, w0, 3003, mode=2, record=rec)
+    w = w0.copy()
+    for k in range(3):
+        w = w + LR.lr_gradient_fp64(X, y, w, coef, 1.0 / X.shape[0])
+        assert np.max(np.abs(rec[k] - w)) / np.max(np.abs(w)) < 2.0 ** -16, k
+    assert np.max(np.abs(w_final - w)) / np.max(np.abs(w)) < 2.0 ** -16
