@@ -173,6 +173,240 @@ __global__ __launch_bounds__(NTT_THREADS) void ntt_rows(NttArgs a, const PrimeIn
     for (int e = threadIdx.x; e < tot; e += NTT_THREADS) src[e] = lds[e];
 }
 
+// ------------------------------------------------------------------ register-tiled NTT
+// One pass transforms lines of M = 2^LM elements (pass A: the N1 "rows" of a
+// column, stride N2; pass B: a contiguous row of N2).  A line is held by
+// T = 2^LT threads with E = 2^LE elements each.  Stages whose butterfly
+// half-width t >= T run with the strided layout x = tau + T k; stages with
+// t < T run with the contiguous layout x = E tau + k; one padded LDS exchange
+// switches between them.  Harvey's lazy butterflies keep forward values in
+// [0, 4q) and inverse values in [0, 2q) until the last pass.
+constexpr int LINE_THREADS = 256;
+
+template <int LM>
+struct LineShape {
+    static constexpr int LE = (LM + 1) / 2 < 4 ? (LM + 1) / 2 : 4;
+    static constexpr int LT = LM - LE;
+    static constexpr int E = 1 << LE, T = 1 << LT, M = 1 << LM;
+    static constexpr int LINES = LINE_THREADS / T;
+    static constexpr int PADDED = M + M / E;  // one pad word per E elements
+};
+
+__device__ __forceinline__ u64 shoup_lazy(u64 a, u64 w, u64 wp, u64 q) { return a * w - __umul64hi(a, wp) * q; }
+
+// forward (Cooley-Tukey) butterfly, inputs in [0, 4q), outputs in [0, 4q)
+__device__ __forceinline__ void ct_bfly(u64 &x, u64 &y, u64 w, u64 wp, u64 q, u64 q2)
+{
+    u64 a = x >= q2 ? x - q2 : x;
+    u64 t = shoup_lazy(y, w, wp, q);
+    x = a + t;
+    y = a - t + q2;
+}
+// inverse (Gentleman-Sande) butterfly, inputs in [0, 2q), outputs in [0, 2q)
+__device__ __forceinline__ void gs_bfly(u64 &x, u64 &y, u64 w, u64 wp, u64 q, u64 q2)
+{
+    u64 s = x + y;
+    s = s >= q2 ? s - q2 : s;
+    u64 d = x - y + q2;
+    y = shoup_lazy(d, w, wp, q);
+    x = s;
+}
+
+__device__ __forceinline__ int lds_pad(int x, int LE) { return x + (x >> LE); }
+
+// Twiddle index of a butterfly in line-stage s (m' = 2^s) for line element x:
+// pass A: m' + x/(2t); pass B: N1 m' + h m' + x/(2t), with 2t = M / m'.
+template <int LM, bool PASS_B>
+__device__ __forceinline__ int tw_index(int s, int x, int h, int N1)
+{
+    const int g = x >> (LM - s);
+    return PASS_B ? (N1 << s) + (h << s) + g : (1 << s) + g;
+}
+
+// forward stages s0..s1-1 on the strided layout (x = tau + T k)
+template <int LM, bool PASS_B>
+__device__ __forceinline__ void fwd_strided(u64 (&v)[LineShape<LM>::E], int tau, int h, int N1, const u64 *W,
+                                            const u64 *Ws, u64 q, u64 q2)
+{
+    using S = LineShape<LM>;
+#pragma unroll
+    for (int s = 0; s < S::LE; ++s) {
+        const int hk = 1 << (S::LE - 1 - s);
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) {
+            if (k & hk) continue;
+            const int idx = tw_index<LM, PASS_B>(s, tau + S::T * k, h, N1);
+            ct_bfly(v[k], v[k + hk], W[idx], Ws[idx], q, q2);
+        }
+    }
+}
+// forward stages LE..LM-1 on the contiguous layout (x = E tau + k)
+template <int LM, bool PASS_B>
+__device__ __forceinline__ void fwd_contig(u64 (&v)[LineShape<LM>::E], int tau, int h, int N1, const u64 *W,
+                                           const u64 *Ws, u64 q, u64 q2)
+{
+    using S = LineShape<LM>;
+#pragma unroll
+    for (int s = S::LE; s < LM; ++s) {
+        const int hk = 1 << (LM - 1 - s);
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) {
+            if (k & hk) continue;
+            const int idx = tw_index<LM, PASS_B>(s, S::E * tau + k, h, N1);
+            ct_bfly(v[k], v[k + hk], W[idx], Ws[idx], q, q2);
+        }
+    }
+}
+// inverse stages LM-1..LE on the contiguous layout
+template <int LM, bool PASS_B>
+__device__ __forceinline__ void inv_contig(u64 (&v)[LineShape<LM>::E], int tau, int h, int N1, const u64 *W,
+                                           const u64 *Ws, u64 q, u64 q2)
+{
+    using S = LineShape<LM>;
+#pragma unroll
+    for (int s = LM - 1; s >= S::LE; --s) {
+        const int hk = 1 << (LM - 1 - s);
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) {
+            if (k & hk) continue;
+            const int idx = tw_index<LM, PASS_B>(s, S::E * tau + k, h, N1);
+            gs_bfly(v[k], v[k + hk], W[idx], Ws[idx], q, q2);
+        }
+    }
+}
+// inverse stages LE-1..0 on the strided layout
+template <int LM, bool PASS_B>
+__device__ __forceinline__ void inv_strided(u64 (&v)[LineShape<LM>::E], int tau, int h, int N1, const u64 *W,
+                                            const u64 *Ws, u64 q, u64 q2)
+{
+    using S = LineShape<LM>;
+#pragma unroll
+    for (int s = S::LE - 1; s >= 0; --s) {
+        const int hk = 1 << (S::LE - 1 - s);
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) {
+            if (k & hk) continue;
+            const int idx = tw_index<LM, PASS_B>(s, tau + S::T * k, h, N1);
+            gs_bfly(v[k], v[k + hk], W[idx], Ws[idx], q, q2);
+        }
+    }
+}
+
+// strided <-> contiguous through LDS (line-private region of PADDED words)
+template <int LM>
+__device__ __forceinline__ void to_contig(u64 (&v)[LineShape<LM>::E], u64 *line, int tau)
+{
+    using S = LineShape<LM>;
+#pragma unroll
+    for (int k = 0; k < S::E; ++k) line[lds_pad(tau + S::T * k, S::LE)] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < S::E; ++k) v[k] = line[lds_pad(S::E * tau + k, S::LE)];
+}
+template <int LM>
+__device__ __forceinline__ void to_strided(u64 (&v)[LineShape<LM>::E], u64 *line, int tau)
+{
+    using S = LineShape<LM>;
+#pragma unroll
+    for (int k = 0; k < S::E; ++k) line[lds_pad(S::E * tau + k, S::LE)] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < S::E; ++k) v[k] = line[lds_pad(tau + S::T * k, S::LE)];
+}
+
+__device__ __forceinline__ u64 reduce4q(u64 v, u64 q, u64 q2)
+{
+    v = v >= q2 ? v - q2 : v;
+    return v >= q ? v - q : v;
+}
+
+// pass A: columns.  Thread (tau, cc) with cc fastest; LINES consecutive columns per workgroup.
+template <int LOGN, bool INV>
+__global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
+                                                           const u64 *__restrict__ tw, const u64 *__restrict__ tws,
+                                                           const u64 *__restrict__ post)
+{
+    constexpr int LM = (LOGN + 1) / 2, N2 = 1 << (LOGN - LM);
+    using S = LineShape<LM>;
+    __shared__ u64 lds[S::LINES * S::PADDED];
+    u64 *limb;
+    int pidx;
+    if (!ntt_locate(a, limb, pidx)) return;
+    const int cc = threadIdx.x % S::LINES, tau = threadIdx.x / S::LINES;
+    const int col = blockIdx.x * S::LINES + cc;
+    const PrimeInfo p = pinfo[pidx];
+    const u64 q = p.q, q2 = 2 * q;
+    const u64 *W = tw + ((long long)pidx << LOGN);
+    const u64 *Ws = tws + ((long long)pidx << LOGN);
+    u64 *line = lds + cc * S::PADDED;
+    u64 v[S::E];
+    if (!INV) {
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) v[k] = limb[(long long)(tau + S::T * k) * N2 + col];
+        fwd_strided<LM, false>(v, tau, 0, 0, W, Ws, q, q2);
+        to_contig<LM>(v, line, tau);
+        fwd_contig<LM, false>(v, tau, 0, 0, W, Ws, q, q2);
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) limb[(long long)(S::E * tau + k) * N2 + col] = v[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) v[k] = limb[(long long)(S::E * tau + k) * N2 + col];
+        inv_contig<LM, false>(v, tau, 0, 0, W, Ws, q, q2);
+        to_strided<LM>(v, line, tau);
+        inv_strided<LM, false>(v, tau, 0, 0, W, Ws, q, q2);
+        u64 sc, scs;
+        if (post) {
+            sc = post[2 * blockIdx.y];
+            scs = post[2 * blockIdx.y + 1];
+        } else {
+            sc = p.ninv;
+            scs = p.ninv_sh;
+        }
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) limb[(long long)(tau + S::T * k) * N2 + col] = mul_shoup(v[k], sc, scs, q);
+    }
+}
+
+// pass B: rows.  Thread (line, tau) with tau fastest; LINES consecutive rows per workgroup.
+template <int LOGN, bool INV>
+__global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
+                                                           const u64 *__restrict__ tw, const u64 *__restrict__ tws)
+{
+    constexpr int LM = LOGN - (LOGN + 1) / 2, N1 = 1 << ((LOGN + 1) / 2);
+    using S = LineShape<LM>;
+    __shared__ u64 lds[S::LINES * S::PADDED];
+    u64 *limb;
+    int pidx;
+    if (!ntt_locate(a, limb, pidx)) return;
+    const int tau = threadIdx.x % S::T, ln = threadIdx.x / S::T;
+    const int h = blockIdx.x * S::LINES + ln;
+    const u64 q = pinfo[pidx].q, q2 = 2 * q;
+    const u64 *W = tw + ((long long)pidx << LOGN);
+    const u64 *Ws = tws + ((long long)pidx << LOGN);
+    u64 *row = limb + (long long)h * S::M;
+    u64 *line = lds + ln * S::PADDED;
+    u64 v[S::E];
+#pragma unroll
+    for (int k = 0; k < S::E; ++k) v[k] = row[tau + S::T * k];
+    if (!INV) {
+        fwd_strided<LM, true>(v, tau, h, N1, W, Ws, q, q2);
+        to_contig<LM>(v, line, tau);
+        fwd_contig<LM, true>(v, tau, h, N1, W, Ws, q, q2);
+        __syncthreads();
+        to_strided<LM>(v, line, tau);
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) row[tau + S::T * k] = reduce4q(v[k], q, q2);
+    } else {
+        to_contig<LM>(v, line, tau);
+        inv_contig<LM, true>(v, tau, h, N1, W, Ws, q, q2);
+        __syncthreads();
+        to_strided<LM>(v, line, tau);
+        inv_strided<LM, true>(v, tau, h, N1, W, Ws, q, q2);
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) row[tau + S::T * k] = v[k];
+    }
+}
+
 // ------------------------------------------------------------------ elementwise
 struct EwArgs {
     u64 *x, *y, *o;
@@ -606,8 +840,32 @@ PosPrimes make_pp(int n, const int *prime_of_pos)
 
 namespace hek {
 
+template <int LOGN>
+static void ntt_launch_t(he_ctx *c, const NttArgs &a, int nbatch, int npos, int dir, const u64 *post)
+{
+    constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
+    dim3 gc((1 << (LOGN - LA)) / LineShape<LA>::LINES, npos, nbatch * a.ncomp);
+    dim3 gr((1 << LA) / LineShape<LB>::LINES, npos, nbatch * a.ncomp);
+    if (dir > 0) {
+        ntt_cols_t<LOGN, false><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh, nullptr);
+        ntt_rows_t<LOGN, false><<<gr, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh);
+    } else {
+        ntt_rows_t<LOGN, true><<<gr, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh);
+        ntt_cols_t<LOGN, true><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh, post);
+    }
+}
+
 static void ntt_launch(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, const u64 *post)
 {
+    switch (a.logN) {
+    case 12: return ntt_launch_t<12>(c, a, nbatch, npos, dir, post);
+    case 13: return ntt_launch_t<13>(c, a, nbatch, npos, dir, post);
+    case 14: return ntt_launch_t<14>(c, a, nbatch, npos, dir, post);
+    case 15: return ntt_launch_t<15>(c, a, nbatch, npos, dir, post);
+    case 16: return ntt_launch_t<16>(c, a, nbatch, npos, dir, post);
+    default: break;
+    }
+    // small rings: the stage-per-barrier kernels
     const int N1 = 1 << a.logN1, N2 = 1 << (a.logN - a.logN1);
     const int C = std::min(NTT_TILE >> a.logN1, N2);
     const int R = std::min(NTT_TILE / N2, N1);
