@@ -17,6 +17,15 @@ __device__ __forceinline__ int prime_of(int pos, int ell, int nq) { return pos <
 
 __device__ __forceinline__ unsigned brev_n(unsigned x, int bits) { return __brev(x) >> (32 - bits); }
 
+// v < k q with small k (v < 2^64): v mod q by repeated conditional subtraction of
+// the largest fitting power-of-two multiple of q
+__device__ __forceinline__ u64 reduce_small(u64 v, u64 q, int k)
+{
+    for (u64 m = q << (31 - __clz(k > 1 ? k - 1 : 1)); m >= q; m >>= 1)
+        if (v >= m) v -= m;
+    return v;
+}
+
 struct NttArgs {
     u64 *base;
     long long bstride;  // between batch entries
@@ -472,38 +481,45 @@ __global__ __launch_bounds__(256) void tensor_kernel(const u64 *__restrict__ x, 
 }
 
 // ModUp conversion: ext[b][j][t] for positions t outside digit j.
-// y[b][i] holds [d_i qhat_i^{-1}]_{q_i} (coefficient form).
+// y[b][i] holds [d_i qhat_i^{-1}]_{q_i} (coefficient form).  A thread reads
+// the digit's alpha residues of one coefficient once and writes every target.
+constexpr int MAX_ALPHA = 12;
 __global__ __launch_bounds__(256) void modup_kernel(const u64 *__restrict__ y, long long ys, u64 *__restrict__ ext,
                                                     long long es, long long ds, const PrimeInfo *__restrict__ pinfo,
                                                     const u64 *__restrict__ conv, const u64 *__restrict__ qd,
                                                     int level, int alpha, int nq, int np, int nk, int beta, int logN)
 {
-    const int t = blockIdx.y;  // basis position 0 .. level+nk
-    const int z = blockIdx.z;
+    const int z = blockIdx.y;
     const int b = z / beta, j = z % beta;
     const int d0 = j * alpha, d1 = min(d0 + alpha, level + 1);
-    if (t >= d0 && t < d1) return;
-    const int tp = prime_of(t, level, nq);
-    const PrimeInfo pt = pinfo[tp];
+    const int nd = d1 - d0;
     const int N = 1 << logN;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= N) return;
     const u64 *yb = y + b * ys;
-    u64 *o = ext + b * es + j * ds + ((long long)t << logN);
+    u64 v[MAX_ALPHA];
+    u64 cnt = 0;
+    for (int i = 0; i < nd; ++i) {
+        v[i] = yb[((long long)(d0 + i) << logN) + x];
+        cnt += v[i] > (pinfo[d0 + i].q >> 1);
+    }
     // conv layout: [level][HE_MAXDIG][alpha][np][2]; qd: [level][HE_MAXDIG][np][2]
     const u64 *cv = conv + ((((long long)level * HE_MAXDIG + j) * alpha) * np) * 2;
-    const u64 *qq = qd + (((long long)level * HE_MAXDIG + j) * np + tp) * 2;
-    const u64 qdt = qq[0], qdts = qq[1];
-    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
+    const u64 *qq = qd + (((long long)level * HE_MAXDIG + j) * np) * 2;
+    u64 *o = ext + b * es + j * ds + x;
+    const int nb = level + 1 + nk;
+    for (int t = 0; t < nb; ++t) {
+        if (t >= d0 && t < d1) continue;
+        const int tp = prime_of(t, level, nq);
+        const u64 qt = pinfo[tp].q;
         u64 acc = 0;
-        u64 cnt = 0;
-        for (int i = d0; i < d1; ++i) {
-            const u64 qi = pinfo[i].q;
-            u64 v = yb[((long long)i << logN) + x];
-            cnt += v > (qi >> 1);
-            const u64 *c2 = cv + ((long long)(i - d0) * np + tp) * 2;
-            acc = add_mod(acc, mul_shoup(v, c2[0], c2[1], pt.q), pt.q);
+        for (int i = 0; i < nd; ++i) {
+            const u64 *c2 = cv + ((long long)i * np + tp) * 2;
+            acc += mul_shoup(v[i], c2[0], c2[1], qt);  // < alpha q_t < 2^64
         }
-        acc = sub_mod(acc, mul_shoup(cnt, qdt, qdts, pt.q), pt.q);
-        o[x] = acc;
+        acc = reduce_small(acc, qt, nd);
+        acc = sub_mod(acc, mul_shoup(cnt, qq[2 * tp], qq[2 * tp + 1], qt), qt);
+        o[(long long)t << logN] = acc;
     }
 }
 
@@ -546,31 +562,36 @@ __global__ __launch_bounds__(256) void ks_inner_kernel(const u64 *__restrict__ d
 
 // ModDown conversion: acc[b][comp] positions level+1.. hold scaled iNTT
 // outputs y_p (coefficient); conv[b][comp][i] = sum_p y~_p (phat_p mod q_i).
+// A thread reads the k special residues of one coefficient once.
 __global__ __launch_bounds__(256) void moddown_conv_kernel(const u64 *__restrict__ acc, long long as,
                                                            u64 *__restrict__ conv, long long cs,
                                                            const PrimeInfo *__restrict__ pinfo,
                                                            const u64 *__restrict__ dconv, const u64 *__restrict__ dp,
                                                            int level, int nq, int nk, int logN)
 {
-    const int i = blockIdx.y;
-    const int z = blockIdx.z;  // b*2 + comp
+    const int z = blockIdx.y;  // b*2 + comp
     const int b = z >> 1, comp = z & 1;
     const int N = 1 << logN;
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= N) return;
     const int nb = level + 1 + nk;
-    const PrimeInfo p = pinfo[i];
-    const u64 *src = acc + b * as + ((long long)comp * nb << logN);
-    u64 *o = conv + b * cs + ((long long)(comp * (level + 1) + i) << logN);
-    const u64 pm = dp[2 * i], pms = dp[2 * i + 1];
-    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
-        u64 s = 0, cnt = 0;
+    const u64 *src = acc + b * as + ((long long)comp * nb << logN) + x;
+    u64 *o = conv + b * cs + ((long long)comp * (level + 1) << logN) + x;
+    u64 v[MAX_ALPHA];
+    u64 cnt = 0;
+    for (int k = 0; k < nk; ++k) {
+        v[k] = src[(long long)(level + 1 + k) << logN];
+        cnt += v[k] > (pinfo[nq + k].q >> 1);
+    }
+    for (int i = 0; i <= level; ++i) {
+        const u64 q = pinfo[i].q;
+        u64 s = 0;
         for (int k = 0; k < nk; ++k) {
-            const u64 pk = pinfo[nq + k].q;
-            u64 v = src[((long long)(level + 1 + k) << logN) + x];
-            cnt += v > (pk >> 1);
             const u64 *c2 = dconv + ((long long)k * nq + i) * 2;
-            s = add_mod(s, mul_shoup(v, c2[0], c2[1], p.q), p.q);
+            s += mul_shoup(v[k], c2[0], c2[1], q);
         }
-        o[x] = sub_mod(s, mul_shoup(cnt, pm, pms, p.q), p.q);
+        s = reduce_small(s, q, nk);
+        o[(long long)i << logN] = sub_mod(s, mul_shoup(cnt, dp[2 * i], dp[2 * i + 1], q), q);
     }
 }
 
@@ -935,7 +956,7 @@ void tensor_b(he_ctx *c, int level, int B, const u64 *x, long long xb, long long
 void modup_b(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, long long es, long long ds)
 {
     const int beta = (level + 1 + c->alpha - 1) / c->alpha;
-    dim3 g(xblocks(c->N), level + 1 + c->nk, B * beta);
+    dim3 g((c->N + 255) / 256, B * beta, 1);
     modup_kernel<<<g, 256, 0, c->stream>>>(y, ys, ext, es, ds, c->t.pinfo, c->t.up_conv, c->t.up_qd, level, c->alpha,
                                            c->nq, c->np, c->nk, beta, c->logN);
 }
@@ -951,7 +972,7 @@ void ks_inner_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const
 
 void moddown_conv_b(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs)
 {
-    dim3 g(xblocks(c->N), level + 1, B * 2);
+    dim3 g((c->N + 255) / 256, B * 2, 1);
     moddown_conv_kernel<<<g, 256, 0, c->stream>>>(acc, as, conv, cs, c->t.pinfo, c->t.dn_conv, c->t.dn_p, level,
                                                   c->nq, c->nk, c->logN);
 }
