@@ -30,6 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of one forward NTT over the 5640-limb digit batch, from
+# FETCH_SIZE (x2, copy-calibrated) + WRITE_SIZE (x1) runs of the current
+# kernels (profiles/ntt_forward_5640_limbs_pmc.md).  Set to None whenever the
+# NTT kernels change until the counters are taken again.
+NTT_TRAFFIC_BYTES = {5640: (2889540 + 4059300 + 2 * 2887680) * 1024}
 
 
 def parse():
@@ -211,7 +216,7 @@ def main():
         "ntt_inv_gbs_algorithmic": alg_bytes / t_inv / 1e9,
         "decrypted_grad_rel_err": rel,
         "roofline": {"bound": "hbm", "achieved": ntt_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ntt_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": ntt_gbs / HBM_PEAK_GBS, "traffic": NTT_TRAFFIC_BYTES.get(nlimb),
                      "kernel": "ntt (forward, two passes) over %d limbs of N=2^16" % nlimb},
     }
     if not args.no_cpu:

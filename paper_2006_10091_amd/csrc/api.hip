@@ -279,6 +279,9 @@ he_status build_tables(he_ctx *c)
     t.psi_sh = dev_upload(c, psis);
     t.ipsi = dev_upload(c, ipsi);
     t.ipsi_sh = dev_upload(c, ipsis);
+    std::vector<double> psid(psi.begin(), psi.end()), ipsid(ipsi.begin(), ipsi.end());
+    t.psi_d = dev_upload(c, psid);
+    t.ipsi_d = dev_upload(c, ipsid);
     t.up_scale = dev_upload(c, up_scale);
     t.up_conv = dev_upload(c, up_conv);
     t.up_qd = dev_upload(c, up_qd);
@@ -288,7 +291,7 @@ he_status build_tables(he_ctx *c)
     t.dn_pinv = dev_upload(c, dn_pinv);
     t.rs_qinv = dev_upload(c, rs_qinv);
     t.rs_ql = dev_upload(c, rs_ql);
-    if (!t.pinfo || !t.psi || !t.psi_sh || !t.ipsi || !t.ipsi_sh || !t.up_scale || !t.up_conv || !t.up_qd ||
+    if (!t.pinfo || !t.psi || !t.psi_sh || !t.ipsi || !t.ipsi_sh || !t.psi_d || !t.ipsi_d || !t.up_scale || !t.up_conv || !t.up_qd ||
         !t.dn_scale || !t.dn_conv || !t.dn_p || !t.dn_pinv || !t.rs_qinv || !t.rs_ql)
         return HE_ENOMEM;
     return HE_OK;

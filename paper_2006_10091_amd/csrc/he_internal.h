@@ -21,6 +21,7 @@ struct DeviceTables {
     PrimeInfo *pinfo;        // [np]
     u64 *psi, *psi_sh;       // [np][N] psi^bitrev(k)
     u64 *ipsi, *ipsi_sh;     // [np][N] psi^-bitrev(k)
+    double *psi_d, *ipsi_d;  // [np][N] the same as doubles (used for primes below 2^49)
     // ModUp, per level l and digit j: for each member i of the digit:
     //   up_scale[l][i]           = N^{-1} [qhat_i^{-1}]_{q_i} (+ Shoup)   (i < n_q)
     //   up_conv[l][j][ii][t]     = qhat_i mod prime t (+ Shoup)          (t < np)

@@ -36,12 +36,13 @@ struct NttArgs {
     int alpha;
     int ell, nq;
     int logN, logN1;
+    int zoff;  // first batch x component entry of this launch (chunked launches)
 };
 
 __device__ __forceinline__ bool ntt_locate(const NttArgs &a, u64 *&limb, int &pidx)
 {
     const int pos = a.pos0 + (int)blockIdx.y;
-    const int z = (int)blockIdx.z;
+    const int z = (int)blockIdx.z + a.zoff;
     const int b = z / a.ncomp, c = z % a.ncomp;
     if (a.skip_digit) {
         int s0 = c * a.alpha, s1 = min(s0 + a.alpha, a.ell + 1);
@@ -301,6 +302,65 @@ __device__ __forceinline__ void inv_strided(u64 (&v)[LineShape<LM>::E], int tau,
     }
 }
 
+// ---- exact FP64 variant for primes below 2^49 (values stay integers < 2^51).
+// a*w = hi + lo exactly (FMA); quotient floor(hi / q) is off by at most one,
+// so the remainder hi - Q q + lo lies in [-q, 2q) and is corrected once each way.
+__device__ __forceinline__ double mulmod_d(double a, double w, double q, double qinv)
+{
+    double hi = a * w;
+    double lo = __fma_rn(a, w, -hi);
+    double qt = floor(hi * qinv);
+    double r = __fma_rn(-qt, q, hi) + lo;
+    r = r < 0.0 ? r + q : r;
+    return r >= q ? r - q : r;
+}
+__device__ __forceinline__ void ct_bfly_d(double &x, double &y, double w, double q, double q2, double qinv)
+{
+    double a = x >= q2 ? x - q2 : x;
+    double t = mulmod_d(y, w, q, qinv);
+    x = a + t;
+    y = a - t + q2;
+}
+__device__ __forceinline__ void gs_bfly_d(double &x, double &y, double w, double q, double q2, double qinv)
+{
+    double s = x + y;
+    s = s >= q2 ? s - q2 : s;
+    double d = x - y + q2;
+    y = mulmod_d(d, w, q, qinv);
+    x = s;
+}
+template <int LM, bool PASS_B, bool INV, bool STRIDED>
+__device__ __forceinline__ void stages_d(double (&v)[LineShape<LM>::E], int tau, int h, int N1, const double *W,
+                                         double q, double qinv)
+{
+    using S = LineShape<LM>;
+    const double q2 = 2.0 * q;
+    constexpr int s_lo = STRIDED ? 0 : S::LE, s_hi = STRIDED ? S::LE : LM;
+#pragma unroll
+    for (int si = 0; si < s_hi - s_lo; ++si) {
+        const int s = INV ? s_hi - 1 - si : s_lo + si;
+        const int hk = STRIDED ? 1 << (S::LE - 1 - s) : 1 << (LM - 1 - s);
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) {
+            if (k & hk) continue;
+            const int x = STRIDED ? tau + S::T * k : S::E * tau + k;
+            const double w = W[tw_index<LM, PASS_B>(s, x, h, N1)];
+            if (INV) gs_bfly_d(v[k], v[k + hk], w, q, q2, qinv);
+            else ct_bfly_d(v[k], v[k + hk], w, q, q2, qinv);
+        }
+    }
+}
+template <int LM>
+__device__ __forceinline__ void exch_d(double (&v)[LineShape<LM>::E], double *line, int tau, bool to_contig)
+{
+    using S = LineShape<LM>;
+#pragma unroll
+    for (int k = 0; k < S::E; ++k) line[lds_pad(to_contig ? tau + S::T * k : S::E * tau + k, S::LE)] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < S::E; ++k) v[k] = line[lds_pad(to_contig ? S::E * tau + k : tau + S::T * k, S::LE)];
+}
+
 // strided <-> contiguous through LDS (line-private region of PADDED words)
 template <int LM>
 __device__ __forceinline__ void to_contig(u64 (&v)[LineShape<LM>::E], u64 *line, int tau)
@@ -333,7 +393,7 @@ __device__ __forceinline__ u64 reduce4q(u64 v, u64 q, u64 q2)
 template <int LOGN, bool INV>
 __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
                                                            const u64 *__restrict__ tw, const u64 *__restrict__ tws,
-                                                           const u64 *__restrict__ post)
+                                                           const u64 *__restrict__ post, const double *__restrict__ twd)
 {
     constexpr int LM = (LOGN + 1) / 2, N2 = 1 << (LOGN - LM);
     using S = LineShape<LM>;
@@ -348,6 +408,32 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
     const u64 *W = tw + ((long long)pidx << LOGN);
     const u64 *Ws = tws + ((long long)pidx << LOGN);
     u64 *line = lds + cc * S::PADDED;
+    if (q < (1ull << 49)) {  // exact FP64 path (quotient estimate off by at most one)
+        const double qd = (double)q, qinv = 1.0 / qd;
+        const double *Wd = twd + ((long long)pidx << LOGN);
+        double *dl = reinterpret_cast<double *>(line);
+        double d[S::E];
+        if (!INV) {
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) d[k] = (double)limb[(long long)(tau + S::T * k) * N2 + col];
+            stages_d<LM, false, false, true>(d, tau, 0, 0, Wd, qd, qinv);
+            exch_d<LM>(d, dl, tau, true);
+            stages_d<LM, false, false, false>(d, tau, 0, 0, Wd, qd, qinv);
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) limb[(long long)(S::E * tau + k) * N2 + col] = (u64)d[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) d[k] = (double)limb[(long long)(S::E * tau + k) * N2 + col];
+            stages_d<LM, false, true, false>(d, tau, 0, 0, Wd, qd, qinv);
+            exch_d<LM>(d, dl, tau, false);
+            stages_d<LM, false, true, true>(d, tau, 0, 0, Wd, qd, qinv);
+            u64 sc = post ? post[2 * blockIdx.y] : p.ninv;
+            const double scd = (double)sc;
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) limb[(long long)(tau + S::T * k) * N2 + col] = (u64)mulmod_d(d[k], scd, qd, qinv);
+        }
+        return;
+    }
     u64 v[S::E];
     if (!INV) {
 #pragma unroll
@@ -379,7 +465,8 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
 // pass B: rows.  Thread (line, tau) with tau fastest; LINES consecutive rows per workgroup.
 template <int LOGN, bool INV>
 __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
-                                                           const u64 *__restrict__ tw, const u64 *__restrict__ tws)
+                                                           const u64 *__restrict__ tw, const u64 *__restrict__ tws,
+                                                           const double *__restrict__ twd)
 {
     constexpr int LM = LOGN - (LOGN + 1) / 2, N1 = 1 << ((LOGN + 1) / 2);
     using S = LineShape<LM>;
@@ -394,6 +481,36 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
     const u64 *Ws = tws + ((long long)pidx << LOGN);
     u64 *row = limb + (long long)h * S::M;
     u64 *line = lds + ln * S::PADDED;
+    if (q < (1ull << 49)) {  // exact FP64 path (quotient estimate off by at most one)
+        const double qd = (double)q, qinv = 1.0 / qd;
+        const double *Wd = twd + ((long long)pidx << LOGN);
+        double *dl = reinterpret_cast<double *>(line);
+        double d[S::E];
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) d[k] = (double)row[tau + S::T * k];
+        if (!INV) {
+            stages_d<LM, true, false, true>(d, tau, h, N1, Wd, qd, qinv);
+            exch_d<LM>(d, dl, tau, true);
+            stages_d<LM, true, false, false>(d, tau, h, N1, Wd, qd, qinv);
+            __syncthreads();
+            exch_d<LM>(d, dl, tau, false);
+            const double q2d = 2.0 * qd;
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) {
+                double x = d[k] >= q2d ? d[k] - q2d : d[k];
+                row[tau + S::T * k] = (u64)(x >= qd ? x - qd : x);
+            }
+        } else {
+            exch_d<LM>(d, dl, tau, true);
+            stages_d<LM, true, true, false>(d, tau, h, N1, Wd, qd, qinv);
+            __syncthreads();
+            exch_d<LM>(d, dl, tau, false);
+            stages_d<LM, true, true, true>(d, tau, h, N1, Wd, qd, qinv);
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) row[tau + S::T * k] = (u64)d[k];
+        }
+        return;
+    }
     u64 v[S::E];
 #pragma unroll
     for (int k = 0; k < S::E; ++k) v[k] = row[tau + S::T * k];
@@ -861,18 +978,33 @@ PosPrimes make_pp(int n, const int *prime_of_pos)
 
 namespace hek {
 
+// Launches are split only past this size (grid-z bound); measured: splitting
+// into cache-sized chunks costs more in kernel boundaries than it saves.
+constexpr long long NTT_CHUNK_BYTES = 1ll << 40;
+
 template <int LOGN>
-static void ntt_launch_t(he_ctx *c, const NttArgs &a, int nbatch, int npos, int dir, const u64 *post)
+static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, const u64 *post)
 {
     constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
-    dim3 gc((1 << (LOGN - LA)) / LineShape<LA>::LINES, npos, nbatch * a.ncomp);
-    dim3 gr((1 << LA) / LineShape<LB>::LINES, npos, nbatch * a.ncomp);
-    if (dir > 0) {
-        ntt_cols_t<LOGN, false><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh, nullptr);
-        ntt_rows_t<LOGN, false><<<gr, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh);
-    } else {
-        ntt_rows_t<LOGN, true><<<gr, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh);
-        ntt_cols_t<LOGN, true><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh, post);
+    const int nz = nbatch * a.ncomp;
+    const long long per_z = (long long)npos << (LOGN + 3);
+    int zc = (int)std::max(1LL, NTT_CHUNK_BYTES / per_z);
+    if (zc > nz) zc = nz;
+    for (int z0 = 0; z0 < nz; z0 += zc) {
+        const int nzc = std::min(zc, nz - z0);
+        a.zoff = z0;
+        dim3 gc((1 << (LOGN - LA)) / LineShape<LA>::LINES, npos, nzc);
+        dim3 gr((1 << LA) / LineShape<LB>::LINES, npos, nzc);
+        if (dir > 0) {
+            ntt_cols_t<LOGN, false><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh, nullptr,
+                                                                       c->t.psi_d);
+            ntt_rows_t<LOGN, false><<<gr, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh, c->t.psi_d);
+        } else {
+            ntt_rows_t<LOGN, true><<<gr, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh,
+                                                                      c->t.ipsi_d);
+            ntt_cols_t<LOGN, true><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh, post,
+                                                                      c->t.ipsi_d);
+        }
     }
 }
 
@@ -915,6 +1047,7 @@ void ntt_batch(he_ctx *c, u64 *base, long long bstride, long long cstride, int n
     a.nq = c->nq;
     a.logN = c->logN;
     a.logN1 = (c->logN + 1) / 2;
+    a.zoff = 0;
     ntt_launch(c, a, nbatch, npos, dir, post);
 }
 
