@@ -88,17 +88,30 @@ he_status ks_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d2, long long 
     if (!y || !ext || !acc || !conv) return HE_ENOMEM;
     const long long ys = (long long)(l + 1) * N, ds = (long long)nb * N, es = (long long)beta * ds;
     const long long as = 2LL * nb * N, cs = 2LL * (l + 1) * N;
-    // digits to coefficient form, scaled by N^{-1} [qhat_i^{-1}]_{q_i}
-    hek::ewise(c, 4, l, B, 1, d2, d2s, 0, nullptr, 0, 0, y, ys, 0, 0);
-    hek::ntt_batch(c, y, ys, 0, B, 1, 0, l + 1, l, -1, c->t.up_scale + (size_t)l * c->nq * 2, false);
-    hek::modup_b(c, l, B, y, ys, ext, es, ds);
-    hek::ntt_batch(c, ext, es, ds, B, beta, 0, nb, l, +1, nullptr, true);
-    hek::ks_inner_b(c, l, B, d2, d2s, ext, es, ds, key, acc, as);
-    // special-prime limbs to coefficient form, scaled by N^{-1} [phat_p^{-1}]_p
-    hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
-    hek::moddown_conv_b(c, l, B, acc, as, conv, cs);
-    hek::ntt_batch(c, conv, cs, (long long)(l + 1) * N, B, 2, 0, l + 1, l, +1, nullptr, false);
-    hek::moddown_finish_b(c, l, B, acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs);
+    const u64 *up_post = c->t.up_scale + (size_t)l * c->nq * 2;
+    if (hek::fused_ok(c)) {
+        // digits to coefficient form, scaled by N^{-1} [qhat_i^{-1}]_{q_i} (read from d2)
+        hek::intt_from(c, d2, d2s, y, ys, B, l, up_post);
+        // ModUp conversion (integer-ALU bound: kept out of the NTT passes, measured
+        // slower fused), then the forward NTT of the extended digits
+        hek::modup_b(c, l, B, y, ys, ext, es, ds);
+        hek::ntt_batch(c, ext, es, ds, B, beta, 0, nb, l, +1, nullptr, true);
+        hek::ks_inner_b(c, l, B, d2, d2s, ext, es, ds, key, acc, as);
+        // special-prime limbs to coefficient form, scaled by N^{-1} [phat_p^{-1}]_p
+        hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
+        // ModDown conversion inside the first pass, base + (acc - conv) P^{-1} stored by the second
+        hek::ntt_moddown(c, l, B, acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs);
+    } else {
+        hek::ewise(c, 4, l, B, 1, d2, d2s, 0, nullptr, 0, 0, y, ys, 0, 0);
+        hek::ntt_batch(c, y, ys, 0, B, 1, 0, l + 1, l, -1, up_post, false);
+        hek::modup_b(c, l, B, y, ys, ext, es, ds);
+        hek::ntt_batch(c, ext, es, ds, B, beta, 0, nb, l, +1, nullptr, true);
+        hek::ks_inner_b(c, l, B, d2, d2s, ext, es, ds, key, acc, as);
+        hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
+        hek::moddown_conv_b(c, l, B, acc, as, conv, cs);
+        hek::ntt_batch(c, conv, cs, (long long)(l + 1) * N, B, 2, 0, l + 1, l, +1, nullptr, false);
+        hek::moddown_finish_b(c, l, B, acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs);
+    }
     ar.off = mark;
     return last_error();
 }

@@ -94,6 +94,16 @@ namespace hek {
 // of N^{-1}.  skip_digit: component c skips the positions of digit c.
 void ntt_batch(he_ctx *c, u64 *base, long long bstride, long long cstride, int nbatch, int ncomp, int pos0,
                int npos, int ell, int dir, const u64 *post, bool skip_digit);
+// fused forms (logN >= 12; fused_ok): out-of-place inverse NTT of positions 0..level
+// (src -> dst, output scaled by post); forward NTT of the extended digits whose
+// first pass computes the ModUp conversion from y; forward NTT of the ModDown
+// conversion (from acc's special limbs) whose second pass stores
+// base + (acc - conv) P^{-1} into out.
+bool fused_ok(const he_ctx *c);
+void intt_from(he_ctx *c, const u64 *src, long long sbs, u64 *dst, long long dbs, int B, int level, const u64 *post);
+void ntt_modup(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, long long es, long long ds);
+void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs, const u64 *base,
+                 long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs);
 // op 0 add, 1 sub, 2 multiply by integer k, 3 multiply by plaintext y ([pos][N]), 4 copy;
 // positions 0..level of nbatch x ncomp polys.
 void ewise(he_ctx *c, int op, int level, int nbatch, int ncomp, const u64 *x, long long xb, long long xc,

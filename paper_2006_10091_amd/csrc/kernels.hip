@@ -389,11 +389,106 @@ __device__ __forceinline__ u64 reduce4q(u64 v, u64 q, u64 q2)
     return v >= q ? v - q : v;
 }
 
+// Fusion around the two passes (all optional, chosen per launch):
+//   pass A prologue  PRO_MODUP   : input = ModUp conversion of the scaled digit residues (y)
+//                    PRO_MODDOWN : input = ModDown conversion of the special-prime residues (acc)
+//   pass B (inverse) PRO_SRC     : read the limb from another buffer (out-of-place)
+//   pass B epilogue  EPI_FINISH  : store base + (acc - x) P^{-1} instead of x
+enum { PRO_NONE = 0, PRO_MODUP = 1, PRO_MODDOWN = 2, PRO_SRC = 3 };
+enum { EPI_NONE = 0, EPI_FINISH = 1 };
+
+struct Fuse {
+    const u64 *src;      // y (ModUp) / acc (ModDown) / source limbs (PRO_SRC)
+    long long sbs, scs;  // batch / component strides of src
+    const u64 *cvt;      // ModUp: up_conv of the level; ModDown: dn_conv
+    const u64 *cnt;      // ModUp: up_qd of the level; ModDown: dn_p
+    int alpha, np, nk;
+    const u64 *acc;      // finish: acc [b][comp][pos], strides as / acs
+    long long as, acs;
+    const u64 *base;     // finish: base [b][comp][pos] on the first nbase components
+    long long bs, bcs;
+    int nbase;
+    u64 *out;            // finish: out [b][comp][pos]
+    long long os, ocs;
+    const u64 *pinv;     // finish: P^{-1} mod q_pos (+ Shoup)
+};
+
+constexpr int MAXW = 8;  // digit width / special primes a fused prologue can read
+
+// per-workgroup constants of a conversion prologue
+struct ConvConst {
+    u64 c[MAXW], cs[MAXW], half[MAXW];
+    u64 k, ks;
+    int n;
+    const u64 *src;
+};
+
+template <int PRO>
+__device__ __forceinline__ void conv_setup(const NttArgs &a, const Fuse &f, const PrimeInfo *pinfo, int tp,
+                                           ConvConst &cc)
+{
+    const int z = (int)blockIdx.z + a.zoff;
+    const int b = z / a.ncomp, c = z % a.ncomp;
+    if (PRO == PRO_MODUP) {
+        const int d0 = c * f.alpha;
+        cc.n = min(f.alpha, a.ell + 1 - d0);
+        cc.src = f.src + b * f.sbs + ((long long)d0 << a.logN);
+#pragma unroll
+        for (int i = 0; i < MAXW; ++i) {
+            if (i < cc.n) {
+                const u64 *e = f.cvt + (((long long)c * f.alpha + i) * f.np + tp) * 2;
+                cc.c[i] = e[0];
+                cc.cs[i] = e[1];
+                cc.half[i] = pinfo[d0 + i].q >> 1;
+            }
+        }
+        const u64 *e = f.cnt + ((long long)c * f.np + tp) * 2;
+        cc.k = e[0];
+        cc.ks = e[1];
+    } else {
+        const int pos = a.pos0 + (int)blockIdx.y;  // target q_pos
+        cc.n = f.nk;
+        cc.src = f.src + b * f.sbs + c * f.scs + ((long long)(a.ell + 1) << a.logN);
+#pragma unroll
+        for (int i = 0; i < MAXW; ++i) {
+            if (i < cc.n) {
+                const u64 *e = f.cvt + ((long long)i * a.nq + pos) * 2;
+                cc.c[i] = e[0];
+                cc.cs[i] = e[1];
+                cc.half[i] = pinfo[a.nq + i].q >> 1;
+            }
+        }
+        cc.k = f.cnt[2 * pos];
+        cc.ks = f.cnt[2 * pos + 1];
+    }
+}
+
+// centred fast basis conversion of one coefficient (offset off in the limb) to
+// the prime p: exact 128-bit sum of the products, one reduction, then the
+// centring correction cnt * Q mod p
+__device__ __forceinline__ u64 conv_value(const ConvConst &cc, long long off, const PrimeInfo &p, int logN)
+{
+    u64 lo = 0, hi = 0, cnt = 0;
+#pragma unroll
+    for (int i = 0; i < MAXW; ++i) {
+        if (i < cc.n) {
+            const u64 v = cc.src[((long long)i << logN) + off];
+            cnt += v > cc.half[i];
+            const u64 pl = v * cc.c[i], ph = __umul64hi(v, cc.c[i]);
+            lo += pl;
+            hi += ph + (lo < pl);
+        }
+    }
+    const u64 acc = reduce128(hi, lo, p);
+    return sub_mod(acc, mul_shoup(cnt, cc.k, cc.ks, p.q), p.q);
+}
+
 // pass A: columns.  Thread (tau, cc) with cc fastest; LINES consecutive columns per workgroup.
-template <int LOGN, bool INV>
+template <int LOGN, bool INV, int PRO>
 __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
                                                            const u64 *__restrict__ tw, const u64 *__restrict__ tws,
-                                                           const u64 *__restrict__ post, const double *__restrict__ twd)
+                                                           const u64 *__restrict__ post, const double *__restrict__ twd,
+                                                           Fuse f)
 {
     constexpr int LM = (LOGN + 1) / 2, N2 = 1 << (LOGN - LM);
     using S = LineShape<LM>;
@@ -408,6 +503,13 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
     const u64 *W = tw + ((long long)pidx << LOGN);
     const u64 *Ws = tws + ((long long)pidx << LOGN);
     u64 *line = lds + cc * S::PADDED;
+    ConvConst cv;
+    if (PRO == PRO_MODUP || PRO == PRO_MODDOWN) conv_setup<PRO>(a, f, pinfo, pidx, cv);
+    auto load = [&](int row) -> u64 {
+        const long long off = (long long)row * N2 + col;
+        if (PRO == PRO_MODUP || PRO == PRO_MODDOWN) return conv_value(cv, off, p, LOGN);
+        return limb[off];
+    };
     if (q < (1ull << 49)) {  // exact FP64 path (quotient estimate off by at most one)
         const double qd = (double)q, qinv = 1.0 / qd;
         const double *Wd = twd + ((long long)pidx << LOGN);
@@ -415,7 +517,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
         double d[S::E];
         if (!INV) {
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) d[k] = (double)limb[(long long)(tau + S::T * k) * N2 + col];
+            for (int k = 0; k < S::E; ++k) d[k] = (double)load(tau + S::T * k);
             stages_d<LM, false, false, true>(d, tau, 0, 0, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, true);
             stages_d<LM, false, false, false>(d, tau, 0, 0, Wd, qd, qinv);
@@ -430,14 +532,15 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
             u64 sc = post ? post[2 * blockIdx.y] : p.ninv;
             const double scd = (double)sc;
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) limb[(long long)(tau + S::T * k) * N2 + col] = (u64)mulmod_d(d[k], scd, qd, qinv);
+            for (int k = 0; k < S::E; ++k)
+                limb[(long long)(tau + S::T * k) * N2 + col] = (u64)mulmod_d(d[k], scd, qd, qinv);
         }
         return;
     }
     u64 v[S::E];
     if (!INV) {
 #pragma unroll
-        for (int k = 0; k < S::E; ++k) v[k] = limb[(long long)(tau + S::T * k) * N2 + col];
+        for (int k = 0; k < S::E; ++k) v[k] = load(tau + S::T * k);
         fwd_strided<LM, false>(v, tau, 0, 0, W, Ws, q, q2);
         to_contig<LM>(v, line, tau);
         fwd_contig<LM, false>(v, tau, 0, 0, W, Ws, q, q2);
@@ -463,12 +566,15 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
 }
 
 // pass B: rows.  Thread (line, tau) with tau fastest; LINES consecutive rows per workgroup.
-template <int LOGN, bool INV>
+// MODE: forward EPI_NONE / EPI_FINISH; inverse PRO_NONE / PRO_SRC.
+template <int LOGN, bool INV, int MODE>
 __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
                                                            const u64 *__restrict__ tw, const u64 *__restrict__ tws,
-                                                           const double *__restrict__ twd)
+                                                           const double *__restrict__ twd, Fuse f)
 {
     constexpr int LM = LOGN - (LOGN + 1) / 2, N1 = 1 << ((LOGN + 1) / 2);
+    constexpr bool FIN = !INV && MODE == EPI_FINISH;
+    constexpr bool SRC = INV && MODE == PRO_SRC;
     using S = LineShape<LM>;
     __shared__ u64 lds[S::LINES * S::PADDED];
     u64 *limb;
@@ -476,18 +582,37 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
     if (!ntt_locate(a, limb, pidx)) return;
     const int tau = threadIdx.x % S::T, ln = threadIdx.x / S::T;
     const int h = blockIdx.x * S::LINES + ln;
-    const u64 q = pinfo[pidx].q, q2 = 2 * q;
+    const PrimeInfo p = pinfo[pidx];
+    const u64 q = p.q, q2 = 2 * q;
     const u64 *W = tw + ((long long)pidx << LOGN);
     const u64 *Ws = tws + ((long long)pidx << LOGN);
     u64 *row = limb + (long long)h * S::M;
     u64 *line = lds + ln * S::PADDED;
+    const int z = (int)blockIdx.z + a.zoff;
+    const int b = z / a.ncomp, c = z % a.ncomp;
+    const int pos = a.pos0 + (int)blockIdx.y;
+    const long long roff = ((long long)pos << LOGN) + (long long)h * S::M;
+    const u64 *in = row;
+    if (SRC) in = f.src + b * f.sbs + c * f.scs + roff;
+    // finish epilogue: out = base + (acc - x) P^{-1}
+    auto store = [&](int k, u64 x) {
+        const int e = tau + S::T * k;
+        if (FIN) {
+            const u64 av = f.acc[b * f.as + c * f.acs + roff + e];
+            u64 r = mul_shoup(sub_mod(av, x, q), f.pinv[2 * pos], f.pinv[2 * pos + 1], q);
+            if (c < f.nbase) r = add_mod(r, f.base[b * f.bs + c * f.bcs + roff + e], q);
+            f.out[b * f.os + c * f.ocs + roff + e] = r;
+        } else {
+            row[e] = x;
+        }
+    };
     if (q < (1ull << 49)) {  // exact FP64 path (quotient estimate off by at most one)
         const double qd = (double)q, qinv = 1.0 / qd;
         const double *Wd = twd + ((long long)pidx << LOGN);
         double *dl = reinterpret_cast<double *>(line);
         double d[S::E];
 #pragma unroll
-        for (int k = 0; k < S::E; ++k) d[k] = (double)row[tau + S::T * k];
+        for (int k = 0; k < S::E; ++k) d[k] = (double)in[tau + S::T * k];
         if (!INV) {
             stages_d<LM, true, false, true>(d, tau, h, N1, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, true);
@@ -498,7 +623,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
 #pragma unroll
             for (int k = 0; k < S::E; ++k) {
                 double x = d[k] >= q2d ? d[k] - q2d : d[k];
-                row[tau + S::T * k] = (u64)(x >= qd ? x - qd : x);
+                store(k, (u64)(x >= qd ? x - qd : x));
             }
         } else {
             exch_d<LM>(d, dl, tau, true);
@@ -513,7 +638,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
     }
     u64 v[S::E];
 #pragma unroll
-    for (int k = 0; k < S::E; ++k) v[k] = row[tau + S::T * k];
+    for (int k = 0; k < S::E; ++k) v[k] = in[tau + S::T * k];
     if (!INV) {
         fwd_strided<LM, true>(v, tau, h, N1, W, Ws, q, q2);
         to_contig<LM>(v, line, tau);
@@ -521,7 +646,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
         __syncthreads();
         to_strided<LM>(v, line, tau);
 #pragma unroll
-        for (int k = 0; k < S::E; ++k) row[tau + S::T * k] = reduce4q(v[k], q, q2);
+        for (int k = 0; k < S::E; ++k) store(k, reduce4q(v[k], q, q2));
     } else {
         to_contig<LM>(v, line, tau);
         inv_contig<LM, true>(v, tau, h, N1, W, Ws, q, q2);
@@ -628,51 +753,64 @@ __global__ __launch_bounds__(256) void modup_kernel(const u64 *__restrict__ y, l
     for (int t = 0; t < nb; ++t) {
         if (t >= d0 && t < d1) continue;
         const int tp = prime_of(t, level, nq);
-        const u64 qt = pinfo[tp].q;
-        u64 acc = 0;
+        const PrimeInfo pt = pinfo[tp];
+        // exact 128-bit sum of the alpha products (each < 2^120), one reduction
+        u64 lo = 0, hi = 0;
         for (int i = 0; i < nd; ++i) {
-            const u64 *c2 = cv + ((long long)i * np + tp) * 2;
-            acc += mul_shoup(v[i], c2[0], c2[1], qt);  // < alpha q_t < 2^64
+            const u64 ci = cv[((long long)i * np + tp) * 2];
+            const u64 pl = v[i] * ci, ph = __umul64hi(v[i], ci);
+            lo += pl;
+            hi += ph + (lo < pl);
         }
-        acc = reduce_small(acc, qt, nd);
-        acc = sub_mod(acc, mul_shoup(cnt, qq[2 * tp], qq[2 * tp + 1], qt), qt);
+        u64 acc = reduce128(hi, lo, pt);
+        acc = sub_mod(acc, mul_shoup(cnt, qq[2 * tp], qq[2 * tp + 1], pt.q), pt.q);
         o[(long long)t << logN] = acc;
     }
 }
 
 // Key-switching inner product for B entries sharing one key: each thread keeps
-// its key coefficients in registers and loops over the batch.
+// the key coefficients of two neighbouring positions in registers (16-byte
+// accesses) and loops over the batch.
 __global__ __launch_bounds__(256) void ks_inner_kernel(const u64 *__restrict__ d2, long long d2s,
                                                        const u64 *__restrict__ ext, long long es, long long ds,
                                                        const u64 *__restrict__ key, u64 *__restrict__ acc,
                                                        long long as, const PrimeInfo *__restrict__ pinfo, int B,
                                                        int level, int alpha, int nq, int np, int beta, int logN)
 {
+    typedef __attribute__((ext_vector_type(2))) unsigned long long u64x2;
     const int t = blockIdx.y;
     const int tp = prime_of(t, level, nq);
     const PrimeInfo p = pinfo[tp];
     const int N = 1 << logN;
     const int nb = level + 1 + (np - nq);
     const long long keylimb = (long long)np << logN;  // one key component
-    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
-        u64 kb[HE_MAXBETA], ka[HE_MAXBETA];
+    const long long lt = (long long)t << logN;
+    for (int x = 2 * (blockIdx.x * 256 + threadIdx.x); x < N; x += 2 * gridDim.x * 256) {
+        u64x2 kb[HE_MAXBETA], ka[HE_MAXBETA];
         for (int j = 0; j < beta; ++j) {
             const u64 *kj = key + (long long)j * 2 * keylimb + ((long long)tp << logN) + x;
-            kb[j] = kj[0];
-            ka[j] = kj[keylimb];
+            kb[j] = *reinterpret_cast<const u64x2 *>(kj);
+            ka[j] = *reinterpret_cast<const u64x2 *>(kj + keylimb);
         }
         for (int b = 0; b < B; ++b) {
-            u64 s0 = 0, s1 = 0;
+            u64 s0a = 0, s1a = 0, s0b = 0, s1b = 0;
             for (int j = 0; j < beta; ++j) {
                 const int d0 = j * alpha, d1 = min(d0 + alpha, level + 1);
-                u64 X = (t >= d0 && t < d1) ? d2[b * d2s + ((long long)t << logN) + x]
-                                            : ext[b * es + j * ds + ((long long)t << logN) + x];
-                s0 = add_mod(s0, mul_mod(X, kb[j], p), p.q);
-                s1 = add_mod(s1, mul_mod(X, ka[j], p), p.q);
+                const u64 *src = (t >= d0 && t < d1) ? d2 + b * d2s + lt + x : ext + b * es + j * ds + lt + x;
+                const u64x2 X = *reinterpret_cast<const u64x2 *>(src);
+                s0a = add_mod(s0a, mul_mod(X.x, kb[j].x, p), p.q);
+                s1a = add_mod(s1a, mul_mod(X.x, ka[j].x, p), p.q);
+                s0b = add_mod(s0b, mul_mod(X.y, kb[j].y, p), p.q);
+                s1b = add_mod(s1b, mul_mod(X.y, ka[j].y, p), p.q);
             }
-            u64 *o = acc + b * as + ((long long)t << logN) + x;
-            o[0] = s0;
-            o[(long long)nb << logN] = s1;
+            u64 *o = acc + b * as + lt + x;
+            u64x2 r0, r1;
+            r0.x = s0a;
+            r0.y = s0b;
+            r1.x = s1a;
+            r1.y = s1b;
+            *reinterpret_cast<u64x2 *>(o) = r0;
+            *reinterpret_cast<u64x2 *>(o + ((long long)nb << logN)) = r1;
         }
     }
 }
@@ -983,42 +1121,64 @@ namespace hek {
 constexpr long long NTT_CHUNK_BYTES = 1ll << 40;
 
 template <int LOGN>
-static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, const u64 *post)
+static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, const u64 *post, int pro, int epi,
+                         const Fuse &f)
 {
     constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
     const int nz = nbatch * a.ncomp;
     const long long per_z = (long long)npos << (LOGN + 3);
     int zc = (int)std::max(1LL, NTT_CHUNK_BYTES / per_z);
     if (zc > nz) zc = nz;
+    const PrimeInfo *pi = c->t.pinfo;
     for (int z0 = 0; z0 < nz; z0 += zc) {
         const int nzc = std::min(zc, nz - z0);
         a.zoff = z0;
         dim3 gc((1 << (LOGN - LA)) / LineShape<LA>::LINES, npos, nzc);
         dim3 gr((1 << LA) / LineShape<LB>::LINES, npos, nzc);
+        hipStream_t st = c->stream;
         if (dir > 0) {
-            ntt_cols_t<LOGN, false><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh, nullptr,
-                                                                       c->t.psi_d);
-            ntt_rows_t<LOGN, false><<<gr, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh, c->t.psi_d);
+            if (pro == PRO_MODUP)
+                ntt_cols_t<LOGN, false, PRO_MODUP><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh, nullptr,
+                                                                               c->t.psi_d, f);
+            else if (pro == PRO_MODDOWN)
+                ntt_cols_t<LOGN, false, PRO_MODDOWN><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh,
+                                                                                 nullptr, c->t.psi_d, f);
+            else
+                ntt_cols_t<LOGN, false, PRO_NONE><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh, nullptr,
+                                                                              c->t.psi_d, f);
+            if (epi == EPI_FINISH)
+                ntt_rows_t<LOGN, false, EPI_FINISH><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh,
+                                                                                c->t.psi_d, f);
+            else
+                ntt_rows_t<LOGN, false, EPI_NONE><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh,
+                                                                              c->t.psi_d, f);
         } else {
-            ntt_rows_t<LOGN, true><<<gr, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh,
-                                                                      c->t.ipsi_d);
-            ntt_cols_t<LOGN, true><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh, post,
-                                                                      c->t.ipsi_d);
+            if (pro == PRO_SRC)
+                ntt_rows_t<LOGN, true, PRO_SRC><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.ipsi, c->t.ipsi_sh,
+                                                                            c->t.ipsi_d, f);
+            else
+                ntt_rows_t<LOGN, true, PRO_NONE><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.ipsi, c->t.ipsi_sh,
+                                                                             c->t.ipsi_d, f);
+            ntt_cols_t<LOGN, true, PRO_NONE><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.ipsi, c->t.ipsi_sh, post,
+                                                                         c->t.ipsi_d, f);
         }
     }
 }
 
-static void ntt_launch(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, const u64 *post)
+static void ntt_launch(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, const u64 *post, int pro = PRO_NONE,
+                       int epi = EPI_NONE, const Fuse *fp = nullptr)
 {
+    Fuse f{};
+    if (fp) f = *fp;
     switch (a.logN) {
-    case 12: return ntt_launch_t<12>(c, a, nbatch, npos, dir, post);
-    case 13: return ntt_launch_t<13>(c, a, nbatch, npos, dir, post);
-    case 14: return ntt_launch_t<14>(c, a, nbatch, npos, dir, post);
-    case 15: return ntt_launch_t<15>(c, a, nbatch, npos, dir, post);
-    case 16: return ntt_launch_t<16>(c, a, nbatch, npos, dir, post);
+    case 12: return ntt_launch_t<12>(c, a, nbatch, npos, dir, post, pro, epi, f);
+    case 13: return ntt_launch_t<13>(c, a, nbatch, npos, dir, post, pro, epi, f);
+    case 14: return ntt_launch_t<14>(c, a, nbatch, npos, dir, post, pro, epi, f);
+    case 15: return ntt_launch_t<15>(c, a, nbatch, npos, dir, post, pro, epi, f);
+    case 16: return ntt_launch_t<16>(c, a, nbatch, npos, dir, post, pro, epi, f);
     default: break;
     }
-    // small rings: the stage-per-barrier kernels
+    // small rings: the stage-per-barrier kernels (no fusion)
     const int N1 = 1 << a.logN1, N2 = 1 << (a.logN - a.logN1);
     const int C = std::min(NTT_TILE >> a.logN1, N2);
     const int R = std::min(NTT_TILE / N2, N1);
@@ -1049,6 +1209,79 @@ void ntt_batch(he_ctx *c, u64 *base, long long bstride, long long cstride, int n
     a.logN1 = (c->logN + 1) / 2;
     a.zoff = 0;
     ntt_launch(c, a, nbatch, npos, dir, post);
+}
+
+static NttArgs make_args(he_ctx *c, u64 *base, long long bstride, long long cstride, int ncomp, int pos0, int ell,
+                         bool skip_digit)
+{
+    NttArgs a;
+    a.base = base;
+    a.bstride = bstride;
+    a.cstride = cstride;
+    a.ncomp = ncomp;
+    a.pos0 = pos0;
+    a.skip_digit = skip_digit ? 1 : 0;
+    a.alpha = c->alpha;
+    a.ell = ell;
+    a.nq = c->nq;
+    a.logN = c->logN;
+    a.logN1 = (c->logN + 1) / 2;
+    a.zoff = 0;
+    return a;
+}
+
+bool fused_ok(const he_ctx *c) { return c->logN >= 12 && c->alpha <= MAXW && c->nk <= MAXW; }
+
+void intt_from(he_ctx *c, const u64 *src, long long sbs, u64 *dst, long long dbs, int B, int level, const u64 *post)
+{
+    Fuse f{};
+    f.src = src;
+    f.sbs = sbs;
+    f.scs = 0;
+    NttArgs a = make_args(c, dst, dbs, 0, 1, 0, level, false);
+    ntt_launch(c, a, B, level + 1, -1, post, PRO_SRC, EPI_NONE, &f);
+}
+
+void ntt_modup(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, long long es, long long ds)
+{
+    const int beta = (level + 1 + c->alpha - 1) / c->alpha;
+    Fuse f{};
+    f.src = y;
+    f.sbs = ys;
+    f.cvt = c->t.up_conv + ((long long)level * HE_MAXDIG * c->alpha * c->np) * 2;
+    f.cnt = c->t.up_qd + ((long long)level * HE_MAXDIG * c->np) * 2;
+    f.alpha = c->alpha;
+    f.np = c->np;
+    f.nk = c->nk;
+    NttArgs a = make_args(c, ext, es, ds, beta, 0, level, true);
+    ntt_launch(c, a, B, level + 1 + c->nk, +1, nullptr, PRO_MODUP, EPI_NONE, &f);
+}
+
+void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs, const u64 *base,
+                 long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs)
+{
+    const long long N = c->N, nb = level + 1 + c->nk;
+    Fuse f{};
+    f.src = acc;
+    f.sbs = as;
+    f.scs = nb * N;
+    f.cvt = c->t.dn_conv;
+    f.cnt = c->t.dn_p;
+    f.nk = c->nk;
+    f.np = c->np;
+    f.acc = acc;
+    f.as = as;
+    f.acs = nb * N;
+    f.base = base;
+    f.bs = bs;
+    f.bcs = bcs;
+    f.nbase = nbase;
+    f.out = out;
+    f.os = os;
+    f.ocs = ocs;
+    f.pinv = c->t.dn_pinv;
+    NttArgs a = make_args(c, conv, cs, (level + 1) * N, 2, 0, level, false);
+    ntt_launch(c, a, B, level + 1, +1, nullptr, PRO_MODDOWN, EPI_FINISH, &f);
 }
 
 static void ew(he_ctx *c, int op, const EwArgs &a, int npos, int nbatch, i64 k)
