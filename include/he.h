@@ -105,6 +105,8 @@ typedef struct {
     int32_t level_in, level_out;
     double s1, s_mask, s_m, s_a, t, s_z3, s_b3, s_c, s_z1, s_b1, s_g;
     int64_t k0, k1, k3, kb1, kw;
+    double s_z2;
+    int64_t k2;
 } he_lr_plan;
 
 /* ---------------------------------------------------------------- context */
@@ -212,16 +214,20 @@ he_status he_drop_level(he_ctx *ctx, const he_ct *x, int level, he_ct *out);
 /* ---------------------------------------------------------------- the gradient step */
 
 /* Pure host scale schedule of one gradient step at W's level (no device use).
- * HE_ELEVEL when fewer than 4 levels remain, HE_ESCALE when an integer constant
- * leaves |k| < 2^62 or coef[2] != 0.  q: the prime chain (he_ctx_primes). */
+ * w_decay = eta * lambda of an L2 regulariser R(w) = lambda/2 |w|^2 (eq. (obj);
+ * 0 for none), in [0, 1).  HE_ELEVEL when fewer than 4 levels remain,
+ * HE_ESCALE when an integer constant leaves |k| < 2^62 or no coefficient
+ * a1..a3 is nonzero.  q: the prime chain (he_ctx_primes). */
 he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, double s_w,
-                          const double coef[4], double eta_over_n, he_lr_plan *out);
+                          const double coef[4], double eta_over_n, double w_decay, he_lr_plan *out);
 
 /*
- * One encrypted gradient step on one worker's shard: eq. (appr) with the
- * Table 2 polynomial p(m) = coef[0] + coef[1] m + coef[3] m^3 (coef[2] = 0),
- * followed by eq. (update), written as W' = W + g,
- *   g = (eta/n) sum_i p(y_i w.x_i) y_i x_i   (p approximates -L').
+ * One encrypted gradient step on one worker's shard: eq. (appr) with a Table 2
+ * polynomial p(m) = coef[0] + coef[1] m + coef[2] m^2 + coef[3] m^3 followed by
+ * eq. (update) with an optional L2 regulariser, written as
+ *   W' = (1 - w_decay) W + g,   g = (eta/n) sum_i p(y_i w.x_i) y_i x_i
+ * (p approximates -L'; w_decay = eta lambda; a nonzero coef[2] adds one
+ * product per block).
  * Inputs: Z[0..n_blocks) -- the data blocks, row-major r x c (slot i*c + j holds
  * y_i x_ij; c*r = N/2), all at one level >= W's and one scale; W -- the weights,
  * w replicated in every row; mask -- plaintext of the column-0 indicator at
@@ -235,8 +241,9 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  * All modes give bit-identical ciphertexts.
  */
 he_status he_lr_grad_step(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct *W,
-                          const he_pt *mask, const double coef[4], double eta_over_n, int c,
-                          int r, const he_keys *keys, int mode, he_ct *W_out, he_ct *G_out);
+                          const he_pt *mask, const double coef[4], double eta_over_n,
+                          double w_decay, int c, int r, const he_keys *keys, int mode,
+                          he_ct *W_out, he_ct *G_out);
 
 /* ---------------------------------------------------------------- NTT (measurement) */
 

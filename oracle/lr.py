@@ -15,8 +15,9 @@ Readings where the paper is silent (each listed in the design notes):
     every row.
   * the per-block circuit is: u = Z (x) W; column sum by rotations 1..c/2;
     mask column 0; replicate by rotations -1..-c/2 (M holds m_i in row i);
-    A = M^2, B3 = M * (a3 Z), B1 = M * (a1 Z); C = A * B3;
-    G_b = C + a1-term + a0 Z; cross-block sum; row sum by rotations c..(r/2)c.
+    A = M^2, B3 = M * (a3 Z), B1 = M * (a1 Z); C = A * B3; B2 = A * (a2 Z)
+    when a2 != 0 (Table 2's hinge row); G_b = C + a1-term + a0 Z (+ B2);
+    cross-block sum; row sum by rotations c..(r/2)c.
   * eta/n enters through the scale bookkeeping (an exact FP64 change of the
     declared scale), and W is brought to the gradient's scale by one integer
     multiplication and rescale, both fixed by plan_lr_step below.
@@ -61,7 +62,8 @@ def grad_poly_binomial(bound=8.0):
 
 
 def lr_gradient_fp64(X, y, w, coef, eta_over_n):
-    """g = (eta/n) sum_i p(m_i) y_i x_i with m_i = y_i w.x_i (FP64)."""
+    """g = (eta/n) sum_i p(m_i) y_i x_i with m_i = y_i w.x_i (FP64); the step of
+    eq. (update) with an L2 regulariser is w + g - eta lambda w."""
     z = y[:, None] * X
     m = z @ w
     p = coef[0] + coef[1] * m + coef[2] * m * m + coef[3] * m * m * m
@@ -116,21 +118,23 @@ K_MAX = 2 ** 62
 
 def term_scale(coef):
     """Target scale T of the gradient terms: the power of two with
-    T * min(|a1|, |a3|) in [2^22, 2^23) (a nonzero coefficient is required)."""
-    nz = [abs(a) for a in (coef[1], coef[3]) if a != 0.0]
+    T * min(|a1|, |a2|, |a3|) in [2^22, 2^23) (a nonzero one is required)."""
+    nz = [abs(a) for a in (coef[1], coef[2], coef[3]) if a != 0.0]
     if not nz:
-        raise ScaleError("polynomial needs a nonzero a1 or a3")
+        raise ScaleError("polynomial needs a nonzero a1, a2 or a3")
     _, e = math.frexp(min(nz))
     return math.ldexp(1.0, 23 - e)
 
 
-def plan_lr_step(q, level, s_Z, s_W, coef, eta_over_n):
+def plan_lr_step(q, level, s_Z, s_W, coef, eta_over_n, w_decay=0.0):
     """FP64 scale schedule of one gradient step at W's level `level`.
-    Every expression is evaluated left to right exactly as written."""
+    Every expression is evaluated left to right exactly as written.
+    w_decay = eta * lambda of an L2 regulariser R = lambda/2 |w|^2 (eq. (obj)):
+    its gradient step -eta lambda w is folded into W's renormalisation."""
     if level < 4:
         raise LevelError("a gradient step needs 4 levels; W is at level %d" % level)
-    if coef[2] != 0.0:
-        raise ScaleError("a nonzero x^2 coefficient is not supported by this circuit")
+    if not (0.0 <= w_decay < 1.0):
+        raise ScaleError("w_decay must lie in [0, 1)")
     ql = float(q[level])
     ql1 = float(q[level - 1])
     ql2 = float(q[level - 2])
@@ -149,13 +153,15 @@ def plan_lr_step(q, level, s_Z, s_W, coef, eta_over_n):
     sB1 = sM * sZ1 / ql2
     kB1 = llround(sC * ql3 / sB1)
     k0 = llround(coef[0] * sC * ql3 / s_Z)
+    sZ2 = sC * ql3 / sA
+    k2 = llround(coef[2] * sZ2 * ql2 / s_Z)
     s_g = sC / eta_over_n
-    kW = llround(s_g * ql3 / s_W)
-    for name, k in (("k0", k0), ("k1", k1), ("k3", k3), ("kB1", kB1), ("kW", kW)):
+    kW = llround((1.0 - w_decay) * s_g * ql3 / s_W)
+    for name, k in (("k0", k0), ("k1", k1), ("k2", k2), ("k3", k3), ("kB1", kB1), ("kW", kW)):
         if abs(k) >= K_MAX:
             raise ScaleError("%s = %d out of range" % (name, k))
     return dict(level=level, s1=s1, s_mask=s_mask, sM=sM, sA=sA, T=T, sZ3=sZ3, k3=k3, sB3=sB3,
-                sC=sC, sZ1=sZ1, k1=k1, sB1=sB1, kB1=kB1, k0=k0, s_g=s_g, kW=kW,
+                sC=sC, sZ1=sZ1, k1=k1, sB1=sB1, kB1=kB1, k0=k0, sZ2=sZ2, k2=k2, s_g=s_g, kW=kW,
                 level_out=level - 4)
 
 
@@ -174,13 +180,13 @@ def rotation_steps(c, r):
 
 
 # ---------------------------------------------------------------- encrypted step
-def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None):
+def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_decay=0.0):
     """One step of eq. (appr) + eq. (update) on ciphertexts (coefficient form).
     Z: list of block ciphertexts (same level >= W.level, same scale);
     W: weight ciphertext; mask_m: integer plaintext of column_mask at scale
-    plan['s_mask'].  Returns (W', g)."""
+    plan['s_mask'].  Returns (W', g); g excludes the regulariser's -eta lambda w."""
     l = W.level
-    pl = plan or plan_lr_step(P.q, l, Z[0].scale, W.scale, coef, eta_over_n)
+    pl = plan or plan_lr_step(P.q, l, Z[0].scale, W.scale, coef, eta_over_n, w_decay)
     G = None
     for zb in Z:
         zl = O.drop(zb, l)
@@ -203,6 +209,11 @@ def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None):
         B1p = O.rescale(P, O.mul_int(P, B1, pl["kB1"]), scale=pl["sC"])
         Z0p = O.rescale(P, O.mul_int(P, O.drop(zb, l - 3), pl["k0"]), scale=pl["sC"])
         Gb = O.add(P, O.add(P, C, B1p), Z0p)
+        if pl["k2"] != 0:
+            # a2 m^2 z: A (level l-3) times a2 Z brought to level l-3
+            Z2 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 2), pl["k2"]), scale=pl["sZ2"])
+            B2 = O.rescale(P, O.mul(P, A, Z2, keys), scale=pl["sC"])
+            Gb = O.add(P, Gb, B2)
         G = Gb if G is None else O.add(P, G, Gb)
     t = 1
     while t < r:

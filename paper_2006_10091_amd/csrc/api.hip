@@ -341,7 +341,7 @@ he_status make_evk(he_ctx *c, Arena &ar, u64 seed, uint32_t key_id, const u64 *s
 
 // ------------------------------------------------------------------ the gradient step
 struct StepBufs {
-    u64 *T3, *U0, *U, *R, *M, *Y, *Z3, *Z1, *A, *B3, *B1, *C, *B1p, *Z0p, *G, *Rg, *Y1;
+    u64 *T3, *U0, *U, *R, *M, *Y, *Z3, *Z1, *A, *B3, *B1, *C, *B1p, *Z0p, *G, *Rg, *Y1, *Z2, *B2;
 };
 
 size_t step_bytes(const he_ctx *c, int l, int nb)
@@ -356,6 +356,8 @@ size_t step_bytes(const he_ctx *c, int l, int nb)
     n += 2 * al((size_t)nb * 2 * (l - 1) * N);             // Z3, Z1
     n += 3 * al((size_t)nb * 2 * (l - 2) * N);             // A, B3, B1
     n += 3 * al((size_t)nb * 2 * (l - 3) * N);             // C, B1p, Z0p
+    n += al((size_t)nb * 2 * (l - 2) * N);                 // Z2
+    n += al((size_t)nb * 2 * (l - 3) * N);                 // B2
     n += 2 * al((size_t)2 * (l - 3) * N);                  // G, Rg
     n += al((size_t)2 * (l - 2) * N);                      // Y1
     size_t scratch = std::max(rotate_scratch(c, l, nb), rescale_scratch(c, l, nb));
@@ -383,7 +385,9 @@ he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, StepBufs &s)
     s.G = ar.take((size_t)2 * (l - 3) * N);
     s.Rg = ar.take((size_t)2 * (l - 3) * N);
     s.Y1 = ar.take((size_t)2 * (l - 2) * N);
-    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Y, s.Z3, s.Z1, s.A, s.B3, s.B1, s.C, s.B1p, s.Z0p, s.G, s.Rg, s.Y1};
+    s.Z2 = ar.take((size_t)nb * 2 * (l - 2) * N);
+    s.B2 = ar.take((size_t)nb * 2 * (l - 3) * N);
+    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Y, s.Z3, s.Z1, s.A, s.B3, s.B1, s.C, s.B1p, s.Z0p, s.G, s.Rg, s.Y1, s.Z2, s.B2};
     for (u64 *p : all)
         if (!p) return HE_ENOMEM;
     return HE_OK;
@@ -456,6 +460,13 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
     // G_b = C + B1' + Z0'; G (+)= sum_b G_b
     hek::ewise(c, 0, l - 4, nb, 2, s.C, 2 * c1, c1, s.B1p, 2 * c1, c1, s.C, 2 * c1, c1, 0);
     hek::ewise(c, 0, l - 4, nb, 2, s.C, 2 * c1, c1, s.Z0p, 2 * c1, c1, s.C, 2 * c1, c1, 0);
+    if (pl.k2 != 0) {
+        // a2 m^2 z (Table 2's hinge row): B2 = RS(A (x) RS(k2 Z)) at level l-4
+        hek::ewise(c, 2, l - 2, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * m1, m1, pl.k2);
+        TRY(rescale_apply(c, ar, l - 2, nb, s.Y, 2 * m1, s.Z2, 2 * a1));
+        TRY(mul_relin_rescale(c, ar, s, l - 3, nb, s.A, 2 * a1, a1, s.Z2, 2 * a1, a1, keys->rlk, s.B2));
+        hek::ewise(c, 0, l - 4, nb, 2, s.C, 2 * c1, c1, s.B2, 2 * c1, c1, s.C, 2 * c1, c1, 0);
+    }
     hek::batch_sum(c, l - 4, nb, s.C, 2 * c1, c1, s.G, c1, accumulate);
     return last_error();
 }
@@ -923,15 +934,15 @@ he_status he_drop_level(he_ctx *c, const he_ct *x, int level, he_ct *out)
 }
 
 he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, double s_w, const double coef[4],
-                          double eta_over_n, he_lr_plan *out)
+                          double eta_over_n, double w_decay, he_lr_plan *out)
 {
     if (!q || !coef || !out || n_q < 1) return HE_EINVAL;
-    return hehost::plan_lr_step(q, n_q, level, s_z, s_w, coef, eta_over_n, out);
+    return hehost::plan_lr_step(q, n_q, level, s_z, s_w, coef, eta_over_n, w_decay, out);
 }
 
 he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, const he_pt *mask,
-                          const double coef[4], double eta_over_n, int cols, int rows, const he_keys *k, int mode,
-                          he_ct *W_out, he_ct *G_out)
+                          const double coef[4], double eta_over_n, double w_decay, int cols, int rows,
+                          const he_keys *k, int mode, he_ct *W_out, he_ct *G_out)
 {
     if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !mask || !mask->data || !coef || !k || mode < 0 || mode > 2)
         return HE_EINVAL;
@@ -953,7 +964,7 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
     if (lz < l) return HE_ELEVEL;
     if (mode > 0 && n_blocks > 1 && zbs < 2LL * (lz + 1) * c->N) return HE_EINVAL;
     he_lr_plan pl;
-    TRY(hehost::plan_lr_step(c->q.data(), c->nq, l, sz, W->scale, coef, eta_over_n, &pl));
+    TRY(hehost::plan_lr_step(c->q.data(), c->nq, l, sz, W->scale, coef, eta_over_n, w_decay, &pl));
     if (mask->scale != pl.s_mask) return HE_ESCALE;
     // every key the step needs, checked before any launch
     for (int t = 1; t < cols; t <<= 1)
@@ -973,7 +984,8 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
         key << (const void *)Z[0].data << ':' << zbs << ':' << n_blocks << ':' << lz << ':' << (const void *)W->data
             << ':' << l << ':' << (const void *)mask->data << ':' << cols << ':' << (const void *)k << ':'
             << (const void *)W_out->data << ':' << (const void *)(G_out ? G_out->data : nullptr) << ':' << pl.k0
-            << ':' << pl.k1 << ':' << pl.k3 << ':' << pl.kb1 << ':' << pl.kw << ':' << (const void *)c->ws;
+            << ':' << pl.k1 << ':' << pl.k2 << ':' << pl.k3 << ':' << pl.kb1 << ':' << pl.kw << ':'
+            << (const void *)c->ws;
         GraphEntry &ge = c->graphs[key.str()];
         hipStream_t user = c->stream;
         HIPCHK(hipEventRecord(c->ev_in, user));

@@ -211,11 +211,11 @@ void decode(int logN, const double *m, double scale, int n, double *re, double *
 }
 
 // Target scale of the gradient terms: power of two T with
-// T * min(|a1|, |a3|) in [2^22, 2^23).
+// T * min(|a1|, |a2|, |a3|) over the nonzero ones in [2^22, 2^23).
 static bool term_scale(const double coef[4], double *T)
 {
     double amin = 0.0;
-    for (int k : {1, 3}) {
+    for (int k : {1, 2, 3}) {
         double a = std::fabs(coef[k]);
         if (a != 0.0 && (amin == 0.0 || a < amin)) amin = a;
     }
@@ -229,10 +229,10 @@ static bool term_scale(const double coef[4], double *T)
 // FP64 schedule of one step; each expression is evaluated left to right as
 // written (the library is built with floating-point contraction off).
 he_status plan_lr_step(const u64 *q, int n_q, int level, double s_z, double s_w, const double coef[4],
-                       double eta_over_n, he_lr_plan *o)
+                       double eta_over_n, double w_decay, he_lr_plan *o)
 {
     if (level < 4 || level >= n_q) return HE_ELEVEL;
-    if (coef[2] != 0.0 || !(eta_over_n > 0.0) || !(s_z > 0.0) || !(s_w > 0.0)) return HE_ESCALE;
+    if (!(eta_over_n > 0.0) || !(s_z > 0.0) || !(s_w > 0.0) || !(w_decay >= 0.0 && w_decay < 1.0)) return HE_ESCALE;
     double T;
     if (!term_scale(coef, &T)) return HE_ESCALE;
     const double ql = (double)q[level], ql1 = (double)q[level - 1], ql2 = (double)q[level - 2],
@@ -254,12 +254,15 @@ he_status plan_lr_step(const u64 *q, int n_q, int level, double s_z, double s_w,
     o->s_b1 = o->s_m * o->s_z1 / ql2;
     double kb1 = o->s_c * ql3 / o->s_b1;
     double k0 = coef[0] * o->s_c * ql3 / s_z;
+    o->s_z2 = o->s_c * ql3 / o->s_a;
+    double k2 = coef[2] * o->s_z2 * ql2 / s_z;
     o->s_g = o->s_c / eta_over_n;
-    double kw = o->s_g * ql3 / s_w;
+    double kw = (1.0 - w_decay) * o->s_g * ql3 / s_w;
     const double kmax = 4.611686018427388e18;  // 2^62
-    for (double k : {k0, k1, k3, kb1, kw})
+    for (double k : {k0, k1, k2, k3, kb1, kw})
         if (!(std::fabs(k) < kmax)) return HE_ESCALE;
     o->k0 = std::llround(k0);
+    o->k2 = std::llround(k2);
     o->k1 = std::llround(k1);
     o->k3 = std::llround(k3);
     o->kb1 = std::llround(kb1);

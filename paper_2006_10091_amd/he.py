@@ -50,7 +50,7 @@ he_ct3 = he_ct
 class he_lr_plan(ctypes.Structure):
     _fields_ = [("level_in", c_int32), ("level_out", c_int32)] + \
         [(n, c_double) for n in ("s1", "s_mask", "s_m", "s_a", "t", "s_z3", "s_b3", "s_c", "s_z1", "s_b1", "s_g")] + \
-        [(n, c_int64) for n in ("k0", "k1", "k3", "kb1", "kw")]
+        [(n, c_int64) for n in ("k0", "k1", "k3", "kb1", "kw")] + [("s_z2", c_double), ("k2", c_int64)]
 
 
 _P = POINTER
@@ -85,10 +85,10 @@ _sig = {
     "he_mul_int": (c_int, [c_void_p, _P(he_ct), c_int64, c_double, _P(he_ct)]),
     "he_mul_plain": (c_int, [c_void_p, _P(he_ct), _P(he_pt), _P(he_ct)]),
     "he_drop_level": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct)]),
-    "he_plan_lr_step": (c_int, [_P(c_uint64), c_int, c_int, c_double, c_double, _P(c_double), c_double,
+    "he_plan_lr_step": (c_int, [_P(c_uint64), c_int, c_int, c_double, c_double, _P(c_double), c_double, c_double,
                                 _P(he_lr_plan)]),
-    "he_lr_grad_step": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), _P(he_pt), _P(c_double), c_double, c_int,
-                                c_int, c_void_p, c_int, _P(he_ct), _P(he_ct)]),
+    "he_lr_grad_step": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), _P(he_pt), _P(c_double), c_double, c_double,
+                                c_int, c_int, c_void_p, c_int, _P(he_ct), _P(he_ct)]),
     "he_ntt": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
 }
 for _n, (_r, _a) in _sig.items():
@@ -124,12 +124,12 @@ def params_primes(log_n, n_q, n_special, alpha, log_delta):
     return [int(v) for v in out]
 
 
-def plan_lr_step(primes, n_q, level, s_z, s_w, coef, eta_over_n):
+def plan_lr_step(primes, n_q, level, s_z, s_w, coef, eta_over_n, w_decay=0.0):
     """Pure host scale schedule (no device)."""
     q = np.ascontiguousarray(primes, dtype=np.uint64)
     cf = np.ascontiguousarray(coef, dtype=np.float64)
     out = he_lr_plan()
-    _chk(_lib.he_plan_lr_step(_u64p(q), n_q, level, s_z, s_w, _f64p(cf), eta_over_n, ctypes.byref(out)),
+    _chk(_lib.he_plan_lr_step(_u64p(q), n_q, level, s_z, s_w, _f64p(cf), eta_over_n, w_decay, ctypes.byref(out)),
          "he_plan_lr_step")
     return {f[0]: getattr(out, f[0]) for f in he_lr_plan._fields_}
 
@@ -342,11 +342,11 @@ class Context:
         _chk(_lib.he_drop_level(self.h, ctypes.byref(a), level, ctypes.byref(o)), "he_drop_level")
         return out.update(o)
 
-    def plan_lr_step(self, level, s_z, s_w, coef, eta_over_n):
-        return plan_lr_step(self.primes, self.n_q, level, s_z, s_w, coef, eta_over_n)
+    def plan_lr_step(self, level, s_z, s_w, coef, eta_over_n, w_decay=0.0):
+        return plan_lr_step(self.primes, self.n_q, level, s_z, s_w, coef, eta_over_n, w_decay)
 
     def lr_grad_step(self, Z, W, mask, coef, eta_over_n, cols, rows, keys, mode=1, W_out=None, G_out=None,
-                     want_g=True):
+                     want_g=True, w_decay=0.0):
         """One encrypted gradient step (he_lr_grad_step).  Z: list of block
         ciphertexts sharing one allocation (ct_block).  Returns (W', g)."""
         zs = (he_ct * len(Z))(*[z.struct() for z in Z])
@@ -359,7 +359,7 @@ class Context:
         go = G_out.struct() if want_g else None
         cf = np.ascontiguousarray(coef, dtype=np.float64)
         _chk(_lib.he_lr_grad_step(self.h, zs, len(Z), ctypes.byref(w), ctypes.byref(m), _f64p(cf), eta_over_n,
-                                  cols, rows, keys.handle, mode, ctypes.byref(wo),
+                                  w_decay, cols, rows, keys.handle, mode, ctypes.byref(wo),
                                   ctypes.byref(go) if go is not None else None), "he_lr_grad_step")
         W_out.update(wo)
         if want_g:

@@ -48,9 +48,9 @@ class ParameterServer:
 class Worker:
     """Evaluates the encrypted gradient step on its shard; Alg. 1."""
 
-    def __init__(self, ctx, keys, Z, coef, eta_over_n, cols, rows, mode=2):
+    def __init__(self, ctx, keys, Z, coef, eta_over_n, cols, rows, mode=2, w_decay=0.0):
         self.ctx, self.keys, self.Z = ctx, keys, Z
-        self.coef, self.eta_over_n = list(coef), eta_over_n
+        self.coef, self.eta_over_n, self.w_decay = list(coef), eta_over_n, w_decay
         self.cols, self.rows, self.mode = cols, rows, mode
         self._masks = {}
         self._bufs = {}
@@ -73,13 +73,13 @@ class Worker:
         """One iteration; the output lives in a buffer owned per output level
         (levels only decrease between refreshes, so it never aliases W)."""
         ctx = self.ctx
-        pl = ctx.plan_lr_step(W.level, self.Z[0].scale, W.scale, self.coef, self.eta_over_n)
+        pl = ctx.plan_lr_step(W.level, self.Z[0].scale, W.scale, self.coef, self.eta_over_n, self.w_decay)
         mask = self._mask(W.level, pl["s_mask"])
         lo = W.level - 4
         W_out = self._out(lo, 0)
         G_out = self._out(lo, 1) if want_g else None
         return ctx.lr_grad_step(self.Z, W, mask, self.coef, self.eta_over_n, self.cols, self.rows, self.keys,
-                                mode=self.mode, W_out=W_out, G_out=G_out, want_g=want_g)
+                                mode=self.mode, W_out=W_out, G_out=G_out, want_g=want_g, w_decay=self.w_decay)
 
 
 def encrypt_shard(ctx, keys, X, y, seed_enc):
@@ -92,14 +92,14 @@ def encrypt_shard(ctx, keys, X, y, seed_enc):
     return Z, cols, rows
 
 
-def train(ctx, keys, X, y, coef, eta, iterations, refresh_every, w0, seed_enc, mode=2, record=None):
+def train(ctx, keys, X, y, coef, eta, iterations, refresh_every, w0, seed_enc, mode=2, record=None, l2=0.0):
     """Alg. 1 + Alg. 2 on one GPU.  Returns the server's final plaintext
     weights (after a last refresh) and, if `record` is a list, appends the
-    decrypted weights after every iteration."""
+    decrypted weights after every iteration.  l2: lambda of R = lambda/2 |w|^2."""
     n, d = X.shape
     Z, cols, rows = encrypt_shard(ctx, keys, X, y, seed_enc)
     ps = ParameterServer(ctx, keys, d, cols, seed_enc)
-    worker = Worker(ctx, keys, Z, coef, eta / n, cols, rows, mode=mode)
+    worker = Worker(ctx, keys, Z, coef, eta / n, cols, rows, mode=mode, w_decay=eta * l2)
     W = ps.encrypt_weights(w0)
     for k in range(1, iterations + 1):
         W, _ = worker.step(W)

@@ -42,23 +42,25 @@ def test_prime_chain_rejects_bad_params():
 
 
 COEF = [0.5, -0.1501204134, 0.0, 0.0015930174]
+HINGE = [0.5875, -0.1005, 0.0008, -0.00039]  # Table 2, hinge row as printed
 
 
 @pytest.mark.parametrize("name", ["small", "image", "large"])
-def test_scale_plan_matches_oracle_bit_for_bit(name):
+@pytest.mark.parametrize("coef,w_decay", [(COEF, 0.0), (HINGE, 0.0), (COEF, 0.01)])
+def test_scale_plan_matches_oracle_bit_for_bit(name, coef, w_decay):
     W = synth.WORKLOADS[name]
     q = O.Params(W["logN"], W["nq"], W["nk"], W["alpha"], W["log_delta"]).q
     delta = float(2 ** W["log_delta"])
     eta_n = 1.0 / W["n"]
     s_w = delta
     for level in range(W["nq"] - 1, 3, -4):
-        a = LR.plan_lr_step(q, level, delta, s_w, COEF, eta_n)
-        b = H.plan_lr_step(q, W["nq"], level, delta, s_w, COEF, eta_n)
-        for k in ("s1", "s_mask", "sM", "sA", "T", "sZ3", "sB3", "sC", "sZ1", "sB1", "s_g"):
+        a = LR.plan_lr_step(q, level, delta, s_w, coef, eta_n, w_decay)
+        b = H.plan_lr_step(q, W["nq"], level, delta, s_w, coef, eta_n, w_decay)
+        for k in ("s1", "s_mask", "sM", "sA", "T", "sZ3", "sB3", "sC", "sZ1", "sB1", "sZ2", "s_g"):
             kk = {"sM": "s_m", "sA": "s_a", "T": "t", "sZ3": "s_z3", "sB3": "s_b3", "sC": "s_c", "sZ1": "s_z1",
-                  "sB1": "s_b1"}.get(k, k)
+                  "sB1": "s_b1", "sZ2": "s_z2"}.get(k, k)
             assert a[k] == b[kk], (level, k)
-        for k in ("k0", "k1", "k3", "kB1", "kW"):
+        for k in ("k0", "k1", "k2", "k3", "kB1", "kW"):
             assert a[k] == b[k.lower()], (level, k)
         s_w = a["s_g"]  # the next step starts from the previous output scale
 
@@ -69,8 +71,11 @@ def test_scale_plan_errors():
         H.plan_lr_step(q, 5, 3, 2.0 ** 30, 2.0 ** 30, COEF, 1 / 2048)
     assert e.value.status == 3  # HE_ELEVEL
     with pytest.raises(H.HEError) as e:
-        H.plan_lr_step(q, 5, 4, 2.0 ** 30, 2.0 ** 30, [0.5, -0.1, 0.01, 0.001], 1 / 2048)
-    assert e.value.status == 4  # HE_ESCALE: x^2 term
+        H.plan_lr_step(q, 5, 4, 2.0 ** 30, 2.0 ** 30, [0.5, 0.0, 0.0, 0.0], 1 / 2048)
+    assert e.value.status == 4  # HE_ESCALE: no a1..a3
+    with pytest.raises(H.HEError) as e:
+        H.plan_lr_step(q, 5, 4, 2.0 ** 30, 2.0 ** 30, COEF, 1 / 2048, 1.0)
+    assert e.value.status == 4  # HE_ESCALE: w_decay outside [0, 1)
     with pytest.raises(H.HEError) as e:
         H.plan_lr_step(q, 5, 4, 2.0 ** 30, 1.0, COEF, 1 / 2048)
     assert e.value.status == 4  # HE_ESCALE: constant out of range

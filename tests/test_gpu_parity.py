@@ -277,3 +277,30 @@ def test_training_with_refresh_small(small):
         w = w + LR.lr_gradient_fp64(X, y, w, coef, 1.0 / X.shape[0])
         assert np.max(np.abs(rec[k] - w)) / np.max(np.abs(w)) < 2.0 ** -16, k
     assert np.max(np.abs(w_final - w)) / np.max(np.abs(w)) < 2.0 ** -16
+
+
+@pytest.mark.parametrize("coef_name,w_decay", [("hinge", 0.0), ("binomial", 0.05)])
+def test_lr_step_other_losses_bit_exact(small, coef_name, w_decay):
+    """Table 2's hinge row (the x^2 product) and a regularised step, batched
+    and graph forms, bit for bit against the oracle."""
+    import os
+    ctx, P = small["ctx"], small["P"]
+    rows = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "table2_gradient_polynomials.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            rows[k] = [float(x) for x in v]
+    coef = rows[coef_name]
+    X, y = synth.small_data(n=600)
+    blocks, c, r = LR.pack_blocks(X, y, P.S)
+    w0 = synth.initial_weights("small", 16, 77)
+    oZ, gZ, oW, gW = _encrypt_small(small, blocks, w0)
+    eta_n = 1.0 / 600
+    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n, w_decay)
+    mm = O.encode(LR.column_mask(P.S, c), pl["s_mask"], P.N)
+    oWn, og = LR.lr_grad_step(P, small["okeys"], oZ, oW, mm, coef, eta_n, c, r, plan=pl)
+    mask = ctx.pt_load(mm, P.L - 1, pl["s_mask"])
+    for mode in (1, 2):
+        Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, small["gkeys"], mode=mode, w_decay=w_decay)
+        assert np.array_equal(ctx.download(Wn), oWn.data)
+        assert np.array_equal(ctx.download(g), og.data)

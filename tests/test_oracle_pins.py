@@ -499,3 +499,34 @@ def test_encrypted_step_matches_fp64_gradient():
         assert np.max(np.abs(gd[row] - gref)) / np.max(np.abs(gref)) < 2.0 ** -20
     wn = O.decrypt(P, keys, Wn).real.reshape(r, c)[0, :16]
     assert np.max(np.abs(wn - (wdec + gref))) / np.max(np.abs(wdec + gref)) < 2.0 ** -20
+
+
+def _table2_row(name):
+    return _table2()[name]
+
+
+@pytest.mark.parametrize("loss,w_decay", [("hinge", 0.0), ("binomial", 0.05)])
+def test_encrypted_step_other_losses_and_regulariser(loss, w_decay):
+    """Table 2's hinge row (nonzero x^2 term) and an L2-regularised binomial
+    step: decrypted g within 2^-20 of FP64, and W' = (1 - eta lambda) W + g."""
+    W = synth.WORKLOADS["small"]
+    P = O.Params(W["logN"], W["nq"], W["nk"], W["alpha"], W["log_delta"])
+    X, y = synth.small_data(n=512)
+    w0 = synth.initial_weights("small", 16, W["seed_w"])
+    blocks, c, r = LR.pack_blocks(X, y, P.S)
+    keys = O.Keys(P, W["seed_keys"], rot_steps=LR.rotation_steps(c, r))
+    coef = _table2_row(loss)
+    eta_n = 1.0 / X.shape[0]
+    Z = [O.encrypt_sk(P, keys, O.encode(blocks[i], P.delta, P.N), P.L, P.delta, 7, i) for i in range(len(blocks))]
+    Wc = O.encrypt_sk(P, keys, O.encode(LR.pack_weights(w0, P.S, c), P.delta, P.N), P.L, P.delta, 7, 999)
+    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n, w_decay)
+    assert (pl["k2"] != 0) == (coef[2] != 0)
+    mask = O.encode(LR.column_mask(P.S, c), pl["s_mask"], P.N)
+    Wn, g = LR.lr_grad_step(P, keys, Z, Wc, mask, coef, eta_n, c, r, plan=pl)
+    wdec = O.decrypt(P, keys, Wc).real[:16]
+    gref = LR.lr_gradient_fp64(X, y, wdec, coef, eta_n)
+    gd = O.decrypt(P, keys, g).real[:16]
+    assert np.max(np.abs(gd - gref)) / np.max(np.abs(gref)) < 2.0 ** -20
+    wn = O.decrypt(P, keys, Wn).real[:16]
+    want = (1.0 - w_decay) * wdec + gref
+    assert np.max(np.abs(wn - want)) / np.max(np.abs(want)) < 2.0 ** -20
