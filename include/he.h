@@ -100,13 +100,24 @@ typedef struct {
     double scale;
 } he_ct3;
 
-/* Scale schedule of one gradient step (pure host; see he_plan_lr_step). */
+/* Block layouts of the gradient step (c = 2^ceil(log2 d) columns, r = N/(2c) rows).
+ * HE_LAYOUT_ROWS: row-major, slot i*c + j holds y_i x_ij (block packing of the
+ * encrypted-LR literature the paper builds on, Sec. 3); W holds w in every row.
+ * HE_LAYOUT_FEATURES: feature-major, slot j*r + i holds y_i x_ij; W holds w_j in
+ * every slot of feature block j.  Same gradient, fewer key switches per block. */
+enum { HE_LAYOUT_ROWS = 0, HE_LAYOUT_FEATURES = 1 };
+
+/* Scale schedule of one gradient step (pure host; see he_plan_lr_step).
+ * s_gsum: scale of the summed gradient before its mask (feature-major; equal to
+ * s_g for row-major). */
 typedef struct {
     int32_t level_in, level_out;
     double s1, s_mask, s_m, s_a, t, s_z3, s_b3, s_c, s_z1, s_b1, s_g;
     int64_t k0, k1, k3, kb1, kw;
     double s_z2;
     int64_t k2;
+    double s_gsum;
+    int32_t layout, reserved;
 } he_lr_plan;
 
 /* ---------------------------------------------------------------- context */
@@ -215,11 +226,13 @@ he_status he_drop_level(he_ctx *ctx, const he_ct *x, int level, he_ct *out);
 
 /* Pure host scale schedule of one gradient step at W's level (no device use).
  * w_decay = eta * lambda of an L2 regulariser R(w) = lambda/2 |w|^2 (eq. (obj);
- * 0 for none), in [0, 1).  HE_ELEVEL when fewer than 4 levels remain,
- * HE_ESCALE when an integer constant leaves |k| < 2^62 or no coefficient
- * a1..a3 is nonzero.  q: the prime chain (he_ctx_primes). */
+ * 0 for none), in [0, 1).  layout: HE_LAYOUT_ROWS or HE_LAYOUT_FEATURES.
+ * HE_ELEVEL when fewer than 4 levels remain, HE_ESCALE when an integer
+ * constant leaves |k| < 2^62 or no coefficient a1..a3 is nonzero, HE_EINVAL
+ * for an unknown layout.  q: the prime chain (he_ctx_primes). */
 he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, double s_w,
-                          const double coef[4], double eta_over_n, double w_decay, he_lr_plan *out);
+                          const double coef[4], double eta_over_n, double w_decay, int layout,
+                          he_lr_plan *out);
 
 /*
  * One encrypted gradient step on one worker's shard: eq. (appr) with a Table 2
@@ -228,11 +241,18 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  *   W' = (1 - w_decay) W + g,   g = (eta/n) sum_i p(y_i w.x_i) y_i x_i
  * (p approximates -L'; w_decay = eta lambda; a nonzero coef[2] adds one
  * product per block).
- * Inputs: Z[0..n_blocks) -- the data blocks, row-major r x c (slot i*c + j holds
- * y_i x_ij; c*r = N/2), all at one level >= W's and one scale; W -- the weights,
- * w replicated in every row; mask -- plaintext of the column-0 indicator at
- * W's level - 1 and the scale he_plan_lr_step gives as s_mask; keys with the
- * relinearisation key and rotations +-2^k (2^k < c) and c*2^k (2^k < r).
+ * Inputs: Z[0..n_blocks) -- the data blocks in `layout` (c*r = N/2), all at one
+ * level >= W's and one scale, one uniform stride apart in memory; W -- the
+ * weights in the same layout; mask -- a plaintext at the scale
+ * he_plan_lr_step gives as s_mask: for HE_LAYOUT_ROWS the column-0 indicator
+ * (slots i*c) at W's level - 1, for HE_LAYOUT_FEATURES the indicator of
+ * slots j*r at W's level - 3; keys with the relinearisation key and the
+ * rotations: rows -- +-2^k (2^k < c) and c*2^k (2^k < r); features -- r*2^k
+ * (2^k < c) and +-2^k (2^k < r).  Row-major: per block, column sum, mask and
+ * replicate, polynomial; row sum once per step.  Feature-major: per block, a
+ * cyclic sum over the feature blocks leaves m_i in every slot of sample i, then
+ * the polynomial; once per step, the sum inside each feature block, the mask
+ * and the replication over the block.
  * Outputs (caller memory, W's level - 4): W_out, and G_out (nullable) = g.
  * mode 0: plain form (one he_* operation per block per step, one kernel
  * sequence each); mode 1: batched form (every block in one launch per
@@ -242,7 +262,7 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  */
 he_status he_lr_grad_step(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct *W,
                           const he_pt *mask, const double coef[4], double eta_over_n,
-                          double w_decay, int c, int r, const he_keys *keys, int mode,
+                          double w_decay, int c, int r, int layout, const he_keys *keys, int mode,
                           he_ct *W_out, he_ct *G_out);
 
 /* ---------------------------------------------------------------- NTT (measurement) */

@@ -18,6 +18,12 @@ Readings where the paper is silent (each listed in the design notes):
     A = M^2, B3 = M * (a3 Z), B1 = M * (a1 Z); C = A * B3; B2 = A * (a2 Z)
     when a2 != 0 (Table 2's hinge row); G_b = C + a1-term + a0 Z (+ B2);
     cross-block sum; row sum by rotations c..(r/2)c.
+  * a second packing, feature-major, puts z_{b*r+i, j} at slot j*r + i and w_j
+    at every slot of feature block j.  A cyclic sum by rotations r..(c/2)r
+    then leaves m_i in every feature block (no per-block mask or replicate);
+    the polynomial runs on that directly, and after the cross-block sum the
+    gradient is summed inside each feature block (rotations 1..r/2), masked to
+    slot j*r and replicated by rotations -1..-r/2, once per step.
   * eta/n enters through the scale bookkeeping (an exact FP64 change of the
     declared scale), and W is brought to the gradient's scale by one integer
     multiplication and rescale, both fixed by plan_lr_step below.
@@ -94,6 +100,28 @@ def column_mask(S, c):
     return m
 
 
+ROWS, FEATURES = 0, 1  # the two block layouts
+
+
+def pack_blocks_features(X, y, S):
+    """Feature-major packing: slot j*r + i of block b = z_{b*r+i, j}."""
+    blocks, c, r = pack_blocks(X, y, S)
+    return np.ascontiguousarray(blocks.reshape(-1, r, c).transpose(0, 2, 1).reshape(-1, S)), c, r
+
+
+def pack_weights_features(w, S, c):
+    v = np.zeros(c)
+    v[: w.shape[0]] = w
+    return np.repeat(v, S // c)
+
+
+def feature_mask(S, r):
+    """1 at the first slot of every feature block (slots j*r)."""
+    m = np.zeros(S)
+    m[::r] = 1.0
+    return m
+
+
 # ---------------------------------------------------------------- scale plan
 class ScaleError(ValueError):
     pass
@@ -116,17 +144,35 @@ def llround(x):
 K_MAX = 2 ** 62
 
 
-def term_scale(coef):
-    """Target scale T of the gradient terms: the power of two with
-    T * min(|a1|, |a2|, |a3|) in [2^22, 2^23) (a nonzero one is required)."""
+def term_scale(coef, q0, eta_over_n, fm_cap=None):
+    """Target scale T of the gradient terms, a power of two.  The output g has
+    scale s_g = T / (eta/n) and must keep 10 bits of headroom below q_0 (the
+    last limb of the chain): T is the largest power of two with
+    T / (eta/n) <= 2^(floor(log2 q_0) - 10), kept between the powers of two
+    with T * min(|a1|, |a2|, |a3|) in [2^22, 2^23) (coefficient resolution)
+    and in [2^30, 2^31).  The rescale noise of the terms is fixed in size,
+    so a larger T makes the terms relatively more precise.
+    fm_cap (feature-major): a further upper bound that keeps the gradient
+    mask's plaintext scale at 2^34 or more; a layout that cannot meet it
+    together with the lower bound is refused."""
     nz = [abs(a) for a in (coef[1], coef[2], coef[3]) if a != 0.0]
     if not nz:
         raise ScaleError("polynomial needs a nonzero a1, a2 or a3")
     _, e = math.frexp(min(nz))
-    return math.ldexp(1.0, 23 - e)
+    lo = math.ldexp(1.0, 23 - e)
+    hi = math.ldexp(1.0, 31 - e)
+    _, ec = math.frexp(math.ldexp(eta_over_n, int(q0).bit_length() - 1 - 10))
+    cap = math.ldexp(1.0, ec - 1)
+    if fm_cap is not None:
+        t = min(hi, cap, fm_cap)
+        if t < lo:
+            raise ScaleError("feature-major step: the gradient mask would fall below scale 2^34 "
+                             "(data scale too small for n/eta); use the row-major layout")
+        return t
+    return max(lo, min(hi, cap))
 
 
-def plan_lr_step(q, level, s_Z, s_W, coef, eta_over_n, w_decay=0.0):
+def plan_lr_step(q, level, s_Z, s_W, coef, eta_over_n, w_decay=0.0, layout=ROWS):
     """FP64 scale schedule of one gradient step at W's level `level`.
     Every expression is evaluated left to right exactly as written.
     w_decay = eta * lambda of an L2 regulariser R = lambda/2 |w|^2 (eq. (obj)):
@@ -135,6 +181,8 @@ def plan_lr_step(q, level, s_Z, s_W, coef, eta_over_n, w_decay=0.0):
         raise LevelError("a gradient step needs 4 levels; W is at level %d" % level)
     if not (0.0 <= w_decay < 1.0):
         raise ScaleError("w_decay must lie in [0, 1)")
+    if layout == FEATURES:
+        return _plan_features(q, level, s_Z, s_W, coef, eta_over_n, w_decay)
     ql = float(q[level])
     ql1 = float(q[level - 1])
     ql2 = float(q[level - 2])
@@ -143,7 +191,7 @@ def plan_lr_step(q, level, s_Z, s_W, coef, eta_over_n, w_decay=0.0):
     s_mask = ql2 * ql1 / s1
     sM = s1 * s_mask / ql1
     sA = sM * sM / ql2
-    T = term_scale(coef)
+    T = term_scale(coef, q[0], eta_over_n)
     sZ3 = T * ql3 / sA * ql2 / sM
     k3 = llround(coef[3] * sZ3 * ql1 / s_Z)
     sB3 = sM * sZ3 / ql2
@@ -162,11 +210,62 @@ def plan_lr_step(q, level, s_Z, s_W, coef, eta_over_n, w_decay=0.0):
             raise ScaleError("%s = %d out of range" % (name, k))
     return dict(level=level, s1=s1, s_mask=s_mask, sM=sM, sA=sA, T=T, sZ3=sZ3, k3=k3, sB3=sB3,
                 sC=sC, sZ1=sZ1, k1=k1, sB1=sB1, kB1=kB1, k0=k0, sZ2=sZ2, k2=k2, s_g=s_g, kW=kW,
-                level_out=level - 4)
+                level_out=level - 4, s_gsum=s_g, layout=ROWS)
 
 
-def rotation_steps(c, r):
-    """Rotation steps used by the step: +-2^k (k < log2 c) and c*2^k (k < log2 r)."""
+def _plan_features(q, level, s_Z, s_W, coef, eta_over_n, w_decay):
+    """Feature-major schedule: M = u at level l-1 (no mask), the polynomial
+    one level higher than in the row-major circuit, the gradient summed at
+    level l-3 and masked down to level l-4.  The mask's plaintext scale
+    returns W' (and g) to the data's scale s_Z, so that M's scale at the next
+    step stays near q and every integer constant keeps its resolution."""
+    ql = float(q[level])
+    ql1 = float(q[level - 1])
+    ql2 = float(q[level - 2])
+    ql3 = float(q[level - 3])
+    _, ef = math.frexp(s_Z * ql3 * eta_over_n)
+    T = term_scale(coef, q[0], eta_over_n, math.ldexp(1.0, ef - 1 - 34))
+    s1 = s_Z * s_W / ql
+    sM = s1
+    sA = sM * sM / ql1
+    sZ3 = T * ql2 / sA * ql1 / sM
+    k3 = llround(coef[3] * sZ3 * ql / s_Z)
+    sB3 = sM * sZ3 / ql1
+    sC = sA * sB3 / ql2
+    sZ1 = sZ3
+    k1 = llround(coef[1] * sZ1 * ql / s_Z)
+    sB1 = sM * sZ1 / ql1
+    kB1 = llround(sC * ql2 / sB1)
+    k0 = llround(coef[0] * sC * ql2 / s_Z)
+    sZ2 = sC * ql2 / sA
+    k2 = llround(coef[2] * sZ2 * ql1 / s_Z)
+    s_gsum = sC / eta_over_n
+    s_mask = s_Z * ql3 / s_gsum
+    s_g = s_gsum * s_mask / ql3
+    kW = llround((1.0 - w_decay) * s_g * ql3 / s_W)
+    for name, k in (("k0", k0), ("k1", k1), ("k2", k2), ("k3", k3), ("kB1", kB1), ("kW", kW)):
+        if abs(k) >= K_MAX:
+            raise ScaleError("%s = %d out of range" % (name, k))
+    return dict(level=level, s1=s1, s_mask=s_mask, sM=sM, sA=sA, T=T, sZ3=sZ3, k3=k3, sB3=sB3,
+                sC=sC, sZ1=sZ1, k1=k1, sB1=sB1, kB1=kB1, k0=k0, sZ2=sZ2, k2=k2, s_g=s_g, kW=kW,
+                level_out=level - 4, s_gsum=s_gsum, layout=FEATURES)
+
+
+def rotation_steps(c, r, layout=ROWS):
+    """Rotation steps used by the step.  Row-major: +-2^k (k < log2 c) and
+    c*2^k (k < log2 r).  Feature-major: r*2^k (k < log2 c) and +-2^k
+    (k < log2 r)."""
+    if layout == FEATURES:
+        st = []
+        t = 1
+        while t < c:
+            st.append(t * r)
+            t *= 2
+        t = 1
+        while t < r:
+            st += [t, -t]
+            t *= 2
+        return st
     st = []
     t = 1
     while t < c:
@@ -180,13 +279,15 @@ def rotation_steps(c, r):
 
 
 # ---------------------------------------------------------------- encrypted step
-def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_decay=0.0):
+def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_decay=0.0, layout=ROWS):
     """One step of eq. (appr) + eq. (update) on ciphertexts (coefficient form).
     Z: list of block ciphertexts (same level >= W.level, same scale);
     W: weight ciphertext; mask_m: integer plaintext of column_mask at scale
     plan['s_mask'].  Returns (W', g); g excludes the regulariser's -eta lambda w."""
     l = W.level
-    pl = plan or plan_lr_step(P.q, l, Z[0].scale, W.scale, coef, eta_over_n, w_decay)
+    pl = plan or plan_lr_step(P.q, l, Z[0].scale, W.scale, coef, eta_over_n, w_decay, layout)
+    if layout == FEATURES:
+        return _step_features(P, keys, Z, W, mask_m, c, r, pl)
     G = None
     for zb in Z:
         zl = O.drop(zb, l)
@@ -220,5 +321,45 @@ def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_dec
         G = O.add(P, G, O.rotate(P, G, t * c, keys))
         t *= 2
     g = O.CT(G.data, G.level, pl["s_g"])
+    Wn = O.rescale(P, O.mul_int(P, O.drop(W, l - 3), pl["kW"]), scale=pl["s_g"])
+    return O.add(P, Wn, g), g
+
+
+def _step_features(P, keys, Z, W, mask_m, c, r, pl):
+    """Feature-major step; mask_m: integer plaintext of feature_mask at scale
+    plan['s_mask'] (used at level l-3)."""
+    l = W.level
+    G = None
+    for zb in Z:
+        u = O.rescale(P, O.mul(P, O.drop(zb, l), W, keys), scale=pl["s1"])
+        t = 1
+        while t < c:  # margins: cyclic sum over the feature blocks
+            u = O.add(P, u, O.rotate(P, u, t * r, keys))
+            t *= 2
+        M = u
+        A = O.rescale(P, O.mul(P, M, M, keys), scale=pl["sA"])
+        Z3 = O.rescale(P, O.mul_int(P, O.drop(zb, l), pl["k3"]), scale=pl["sZ3"])
+        B3 = O.rescale(P, O.mul(P, M, Z3, keys), scale=pl["sB3"])
+        Z1 = O.rescale(P, O.mul_int(P, O.drop(zb, l), pl["k1"]), scale=pl["sZ1"])
+        B1 = O.rescale(P, O.mul(P, M, Z1, keys), scale=pl["sB1"])
+        C = O.rescale(P, O.mul(P, A, B3, keys), scale=pl["sC"])
+        B1p = O.rescale(P, O.mul_int(P, B1, pl["kB1"]), scale=pl["sC"])
+        Z0p = O.rescale(P, O.mul_int(P, O.drop(zb, l - 2), pl["k0"]), scale=pl["sC"])
+        Gb = O.add(P, O.add(P, C, B1p), Z0p)
+        if pl["k2"] != 0:
+            Z2 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 1), pl["k2"]), scale=pl["sZ2"])
+            B2 = O.rescale(P, O.mul(P, A, Z2, keys), scale=pl["sC"])
+            Gb = O.add(P, Gb, B2)
+        G = Gb if G is None else O.add(P, G, Gb)
+    t = 1
+    while t < r:  # sum over the samples inside each feature block
+        G = O.add(P, G, O.rotate(P, G, t, keys))
+        t *= 2
+    G = O.CT(G.data, G.level, pl["s_gsum"])
+    g = O.rescale(P, O.mul_plain(P, G, mask_m, pl["s_mask"]), scale=pl["s_g"])
+    t = 1
+    while t < r:  # replicate g_j over its feature block
+        g = O.add(P, g, O.rotate(P, g, -t, keys))
+        t *= 2
     Wn = O.rescale(P, O.mul_int(P, O.drop(W, l - 3), pl["kW"]), scale=pl["s_g"])
     return O.add(P, Wn, g), g

@@ -341,53 +341,60 @@ he_status make_evk(he_ctx *c, Arena &ar, u64 seed, uint32_t key_id, const u64 *s
 
 // ------------------------------------------------------------------ the gradient step
 struct StepBufs {
-    u64 *T3, *U0, *U, *R, *M, *Y, *Z3, *Z1, *A, *B3, *B1, *C, *B1p, *Z0p, *G, *Rg, *Y1, *Z2, *B2;
+    u64 *T3, *U0, *U, *R, *M, *Y, *Z3, *Z1, *A, *B3, *B1, *C, *B1p, *Z0p, *G, *Rg, *Y1, *Z2, *B2, *Gm;
 };
 
-size_t step_bytes(const he_ctx *c, int l, int nb)
+// Per-block intermediates sit one level higher in the feature-major circuit
+// (no mask level between the margins and the polynomial): e = 1 there.
+size_t step_bytes(const he_ctx *c, int l, int nb, int layout)
 {
     const size_t N = c->N;
+    const int e = layout == HE_LAYOUT_FEATURES ? 1 : 0;
     size_t n = 0;
     n += al((size_t)nb * 3 * (l + 1) * N);                 // T3
     n += al((size_t)nb * 2 * (l + 1) * N);                 // U0
     n += 2 * al((size_t)nb * 2 * l * N);                   // U, R
     n += al((size_t)nb * 2 * (l - 1) * N);                 // M
-    n += al((size_t)nb * 2 * l * N);                       // Y
-    n += 2 * al((size_t)nb * 2 * (l - 1) * N);             // Z3, Z1
-    n += 3 * al((size_t)nb * 2 * (l - 2) * N);             // A, B3, B1
-    n += 3 * al((size_t)nb * 2 * (l - 3) * N);             // C, B1p, Z0p
-    n += al((size_t)nb * 2 * (l - 2) * N);                 // Z2
-    n += al((size_t)nb * 2 * (l - 3) * N);                 // B2
-    n += 2 * al((size_t)2 * (l - 3) * N);                  // G, Rg
+    n += al((size_t)nb * 2 * (l + e) * N);                 // Y
+    n += 2 * al((size_t)nb * 2 * (l - 1 + e) * N);         // Z3, Z1
+    n += 3 * al((size_t)nb * 2 * (l - 2 + e) * N);         // A, B3, B1
+    n += 3 * al((size_t)nb * 2 * (l - 3 + e) * N);         // C, B1p, Z0p
+    n += al((size_t)nb * 2 * (l - 2 + e) * N);             // Z2
+    n += al((size_t)nb * 2 * (l - 3 + e) * N);             // B2
+    n += 2 * al((size_t)2 * (l - 3 + e) * N);              // G, Rg
     n += al((size_t)2 * (l - 2) * N);                      // Y1
+    n += al((size_t)2 * (l - 3) * N);                      // Gm
     size_t scratch = std::max(rotate_scratch(c, l, nb), rescale_scratch(c, l, nb));
-    n += std::max(scratch, rotate_scratch(c, l - 4, 1));
+    n += std::max(scratch, rotate_scratch(c, l - 4 + e, 1));
     return n * 8 + 4096;
 }
 
-he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, StepBufs &s)
+he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, int layout, StepBufs &s)
 {
     const size_t N = c->N;
+    const int e = layout == HE_LAYOUT_FEATURES ? 1 : 0;
     s.T3 = ar.take((size_t)nb * 3 * (l + 1) * N);
     s.U0 = ar.take((size_t)nb * 2 * (l + 1) * N);
     s.U = ar.take((size_t)nb * 2 * l * N);
     s.R = ar.take((size_t)nb * 2 * l * N);
     s.M = ar.take((size_t)nb * 2 * (l - 1) * N);
-    s.Y = ar.take((size_t)nb * 2 * l * N);
-    s.Z3 = ar.take((size_t)nb * 2 * (l - 1) * N);
-    s.Z1 = ar.take((size_t)nb * 2 * (l - 1) * N);
-    s.A = ar.take((size_t)nb * 2 * (l - 2) * N);
-    s.B3 = ar.take((size_t)nb * 2 * (l - 2) * N);
-    s.B1 = ar.take((size_t)nb * 2 * (l - 2) * N);
-    s.C = ar.take((size_t)nb * 2 * (l - 3) * N);
-    s.B1p = ar.take((size_t)nb * 2 * (l - 3) * N);
-    s.Z0p = ar.take((size_t)nb * 2 * (l - 3) * N);
-    s.G = ar.take((size_t)2 * (l - 3) * N);
-    s.Rg = ar.take((size_t)2 * (l - 3) * N);
+    s.Y = ar.take((size_t)nb * 2 * (l + e) * N);
+    s.Z3 = ar.take((size_t)nb * 2 * (l - 1 + e) * N);
+    s.Z1 = ar.take((size_t)nb * 2 * (l - 1 + e) * N);
+    s.A = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
+    s.B3 = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
+    s.B1 = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
+    s.C = ar.take((size_t)nb * 2 * (l - 3 + e) * N);
+    s.B1p = ar.take((size_t)nb * 2 * (l - 3 + e) * N);
+    s.Z0p = ar.take((size_t)nb * 2 * (l - 3 + e) * N);
+    s.G = ar.take((size_t)2 * (l - 3 + e) * N);
+    s.Rg = ar.take((size_t)2 * (l - 3 + e) * N);
     s.Y1 = ar.take((size_t)2 * (l - 2) * N);
-    s.Z2 = ar.take((size_t)nb * 2 * (l - 2) * N);
-    s.B2 = ar.take((size_t)nb * 2 * (l - 3) * N);
-    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Y, s.Z3, s.Z1, s.A, s.B3, s.B1, s.C, s.B1p, s.Z0p, s.G, s.Rg, s.Y1, s.Z2, s.B2};
+    s.Z2 = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
+    s.B2 = ar.take((size_t)nb * 2 * (l - 3 + e) * N);
+    s.Gm = ar.take((size_t)2 * (l - 3) * N);
+    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Y, s.Z3, s.Z1, s.A, s.B3, s.B1, s.C, s.B1p, s.Z0p, s.G, s.Rg, s.Y1,
+                  s.Z2, s.B2, s.Gm};
     for (u64 *p : all)
         if (!p) return HE_ENOMEM;
     return HE_OK;
@@ -471,6 +478,76 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
     return last_error();
 }
 
+// Feature-major per-block part for blocks [b0, b0+nb): margins by a cyclic sum
+// over the feature blocks (every slot of sample i ends with m_i), then the
+// polynomial one level above the row-major circuit; G (+)= sum of the terms
+// at level l-3.
+he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, const he_ct *Z,
+                               long long zbs, int b0, int nb, const he_ct *W, int cols, int rows,
+                               const he_keys *keys, bool accumulate)
+{
+    const long long N = c->N;
+    const int l = W->level;
+    const int lz = Z[b0].level;
+    const u64 *zp = Z[b0].data;
+    const long long zc = (lz + 1) * N;
+    const long long wc = (l + 1) * N;
+    // D1: u = RS(relin(Z (x) W)), level l-1
+    TRY(mul_relin_rescale(c, ar, s, l, nb, zp, zbs, zc, W->data, 0, wc, keys->rlk, s.U));
+    const long long u1 = (long long)l * N;  // component stride at level l-1
+    for (int t = 1; t < cols; t <<= 1) {
+        const u64 gal = galois_of(c, (long long)t * rows);
+        const u64 *key = find_rot_key(keys, gal);
+        if (!key) return HE_EKEY;
+        TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, gal, key, s.R, 2 * u1));
+        hek::ewise(c, 0, l - 1, nb, 2, s.U, 2 * u1, u1, s.R, 2 * u1, u1, s.U, 2 * u1, u1, 0);
+    }
+    // M = u.  A = M^2 ; Z3 = RS(k3 Z), B3 = M Z3 ; Z1 = RS(k1 Z), B1 = M Z1   (level l-2)
+    TRY(mul_relin_rescale(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.U, 2 * u1, u1, keys->rlk, s.A));
+    const long long y1 = (long long)(l + 1) * N;
+    hek::ewise(c, 2, l, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * y1, y1, pl.k3);
+    TRY(rescale_apply(c, ar, l, nb, s.Y, 2 * y1, s.Z3, 2 * u1));
+    TRY(mul_relin_rescale(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.Z3, 2 * u1, u1, keys->rlk, s.B3));
+    hek::ewise(c, 2, l, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * y1, y1, pl.k1);
+    TRY(rescale_apply(c, ar, l, nb, s.Y, 2 * y1, s.Z1, 2 * u1));
+    TRY(mul_relin_rescale(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.Z1, 2 * u1, u1, keys->rlk, s.B1));
+    // C = A B3 (level l-3)
+    const long long a1 = (long long)(l - 1) * N, c1 = (long long)(l - 2) * N;
+    TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.A, 2 * a1, a1, s.B3, 2 * a1, a1, keys->rlk, s.C));
+    // B1' = RS(kB1 B1), Z0' = RS(k0 Z)
+    hek::ewise(c, 2, l - 2, nb, 2, s.B1, 2 * a1, a1, nullptr, 0, 0, s.B1, 2 * a1, a1, pl.kb1);
+    TRY(rescale_apply(c, ar, l - 2, nb, s.B1, 2 * a1, s.B1p, 2 * c1));
+    hek::ewise(c, 2, l - 2, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * a1, a1, pl.k0);
+    TRY(rescale_apply(c, ar, l - 2, nb, s.Y, 2 * a1, s.Z0p, 2 * c1));
+    hek::ewise(c, 0, l - 3, nb, 2, s.C, 2 * c1, c1, s.B1p, 2 * c1, c1, s.C, 2 * c1, c1, 0);
+    hek::ewise(c, 0, l - 3, nb, 2, s.C, 2 * c1, c1, s.Z0p, 2 * c1, c1, s.C, 2 * c1, c1, 0);
+    if (pl.k2 != 0) {
+        // a2 m^2 z: B2 = RS(A (x) RS(k2 Z)) at level l-3
+        hek::ewise(c, 2, l - 1, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * u1, u1, pl.k2);
+        TRY(rescale_apply(c, ar, l - 1, nb, s.Y, 2 * u1, s.Z2, 2 * a1));
+        TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.A, 2 * a1, a1, s.Z2, 2 * a1, a1, keys->rlk, s.B2));
+        hek::ewise(c, 0, l - 3, nb, 2, s.C, 2 * c1, c1, s.B2, 2 * c1, c1, s.C, 2 * c1, c1, 0);
+    }
+    hek::batch_sum(c, l - 3, nb, s.C, 2 * c1, c1, s.G, c1, accumulate);
+    return last_error();
+}
+
+// log2(count) rotate-and-add rounds x += Rot(x, t * unit), t = 1, 2, .., count/2,
+// on one ciphertext at `level` (component stride (level+1) N); tmp: same size
+he_status rotate_sum(he_ctx *c, Arena &ar, int level, u64 *x, u64 *tmp, long long unit, int count,
+                     const he_keys *keys)
+{
+    const long long x1 = (long long)(level + 1) * c->N;
+    for (int t = 1; t < count; t <<= 1) {
+        const u64 gal = galois_of(c, (long long)t * unit);
+        const u64 *key = find_rot_key(keys, gal);
+        if (!key) return HE_EKEY;
+        TRY(rotate_apply(c, ar, level, 1, x, 2 * x1, gal, key, tmp, 2 * x1));
+        hek::ewise(c, 0, level, 1, 2, x, 2 * x1, x1, tmp, 2 * x1, x1, x, 2 * x1, x1, 0);
+    }
+    return HE_OK;
+}
+
 // the whole step; nchunk = 1 (plain: per-block operations) or n_blocks (batched)
 he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_blocks, long long zbs, const he_ct *W,
                     const he_pt *mask, int cols, int rows, const he_keys *keys, int chunk, he_ct *W_out,
@@ -480,28 +557,38 @@ he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_block
     const int l = W->level;
     Arena ar = arena(c);
     StepBufs s;
-    TRY(step_alloc(c, ar, l, chunk, s));
+    const bool fm = pl.layout == HE_LAYOUT_FEATURES;
+    TRY(step_alloc(c, ar, l, chunk, pl.layout, s));
     for (int b0 = 0; b0 < n_blocks; b0 += chunk) {
         int nb = std::min(chunk, n_blocks - b0);
         long long bs = zbs;
         if (chunk == 1) bs = 0;
-        TRY(step_blocks(c, ar, s, pl, Z, bs, b0, nb, W, mask, cols, keys, b0 > 0));
+        if (fm)
+            TRY(step_blocks_features(c, ar, s, pl, Z, bs, b0, nb, W, cols, rows, keys, b0 > 0));
+        else
+            TRY(step_blocks(c, ar, s, pl, Z, bs, b0, nb, W, mask, cols, keys, b0 > 0));
     }
-    // row sum: G += Rot(G, t * cols), t = 1, 2, .., rows/2   (level l-4)
-    const long long g1 = (long long)(l - 3) * N;
-    for (int t = 1; t < rows; t <<= 1) {
-        u64 gal = galois_of(c, (long long)t * cols);
-        const u64 *key = find_rot_key(keys, gal);
-        if (!key) return HE_EKEY;
-        TRY(rotate_apply(c, ar, l - 4, 1, s.G, 2 * g1, gal, key, s.Rg, 2 * g1));
-        hek::ewise(c, 0, l - 4, 1, 2, s.G, 2 * g1, g1, s.Rg, 2 * g1, g1, s.G, 2 * g1, g1, 0);
+    const long long g1 = (long long)(l - 3) * N;  // component stride at level l-4
+    u64 *g = s.G;
+    if (fm) {
+        // sum inside each feature block (level l-3), mask slots j r, rescale to
+        // level l-4, replicate over the block
+        const long long h1 = (long long)(l - 2) * N;
+        TRY(rotate_sum(c, ar, l - 3, s.G, s.Rg, 1, rows, keys));
+        hek::ewise(c, 3, l - 3, 1, 2, s.G, 2 * h1, h1, mask->data, 0, 0, s.G, 2 * h1, h1, 0);
+        TRY(rescale_apply(c, ar, l - 3, 1, s.G, 2 * h1, s.Gm, 2 * g1));
+        TRY(rotate_sum(c, ar, l - 4, s.Gm, s.Rg, -1, rows, keys));
+        g = s.Gm;
+    } else {
+        // row sum: G += Rot(G, t * cols), t = 1, 2, .., rows/2   (level l-4)
+        TRY(rotate_sum(c, ar, l - 4, s.G, s.Rg, cols, rows, keys));
     }
-    if (G_out) hek::ewise(c, 4, l - 4, 1, 2, s.G, 2 * g1, g1, nullptr, 0, 0, G_out->data, 2 * g1, g1, 0);
+    if (G_out) hek::ewise(c, 4, l - 4, 1, 2, g, 2 * g1, g1, nullptr, 0, 0, G_out->data, 2 * g1, g1, 0);
     // W' = RS(kW W) + g
     const long long w2 = (long long)(l - 2) * N;
     hek::ewise(c, 2, l - 3, 1, 2, W->data, 0, (l + 1) * N, nullptr, 0, 0, s.Y1, 2 * w2, w2, pl.kw);
     TRY(rescale_apply(c, ar, l - 3, 1, s.Y1, 2 * w2, W_out->data, 2 * g1));
-    hek::ewise(c, 0, l - 4, 1, 2, W_out->data, 2 * g1, g1, s.G, 2 * g1, g1, W_out->data, 2 * g1, g1, 0);
+    hek::ewise(c, 0, l - 4, 1, 2, W_out->data, 2 * g1, g1, g, 2 * g1, g1, W_out->data, 2 * g1, g1, 0);
     return last_error();
 }
 
@@ -934,25 +1021,27 @@ he_status he_drop_level(he_ctx *c, const he_ct *x, int level, he_ct *out)
 }
 
 he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, double s_w, const double coef[4],
-                          double eta_over_n, double w_decay, he_lr_plan *out)
+                          double eta_over_n, double w_decay, int layout, he_lr_plan *out)
 {
     if (!q || !coef || !out || n_q < 1) return HE_EINVAL;
-    return hehost::plan_lr_step(q, n_q, level, s_z, s_w, coef, eta_over_n, w_decay, out);
+    return hehost::plan_lr_step(q, n_q, level, s_z, s_w, coef, eta_over_n, w_decay, layout, out);
 }
 
 he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, const he_pt *mask,
-                          const double coef[4], double eta_over_n, double w_decay, int cols, int rows,
+                          const double coef[4], double eta_over_n, double w_decay, int cols, int rows, int layout,
                           const he_keys *k, int mode, he_ct *W_out, he_ct *G_out)
 {
     if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !mask || !mask->data || !coef || !k || mode < 0 || mode > 2)
         return HE_EINVAL;
+    if (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES) return HE_EINVAL;
+    const bool fm = layout == HE_LAYOUT_FEATURES;
     if (W->level < 4) return HE_ELEVEL;
     if (!W_out || !W_out->data || (G_out && !G_out->data)) return HE_EINVAL;
     if (cols < 1 || rows < 1 || (cols & (cols - 1)) || (rows & (rows - 1)) || (long long)cols * rows != c->N / 2)
         return HE_EINVAL;
     const int l = W->level;
     if (l < 4) return HE_ELEVEL;
-    if (mask->level != l - 1) return HE_ELEVEL;
+    if (mask->level != (fm ? l - 3 : l - 1)) return HE_ELEVEL;
     const int lz = Z[0].level;
     const double sz = Z[0].scale;
     long long zbs = 0;
@@ -964,15 +1053,18 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
     if (lz < l) return HE_ELEVEL;
     if (mode > 0 && n_blocks > 1 && zbs < 2LL * (lz + 1) * c->N) return HE_EINVAL;
     he_lr_plan pl;
-    TRY(hehost::plan_lr_step(c->q.data(), c->nq, l, sz, W->scale, coef, eta_over_n, w_decay, &pl));
+    TRY(hehost::plan_lr_step(c->q.data(), c->nq, l, sz, W->scale, coef, eta_over_n, w_decay, layout, &pl));
     if (mask->scale != pl.s_mask) return HE_ESCALE;
     // every key the step needs, checked before any launch
-    for (int t = 1; t < cols; t <<= 1)
+    const int pm = fm ? rows : cols;   // the +-2^k rotations
+    const int st = fm ? cols : rows;   // the unit * 2^k rotations
+    const long long unit = fm ? rows : cols;
+    for (int t = 1; t < pm; t <<= 1)
         if (!find_rot_key(k, galois_of(c, t)) || !find_rot_key(k, galois_of(c, -t))) return HE_EKEY;
-    for (int t = 1; t < rows; t <<= 1)
-        if (!find_rot_key(k, galois_of(c, (long long)t * cols))) return HE_EKEY;
+    for (int t = 1; t < st; t <<= 1)
+        if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
     const int chunk = mode == 0 ? 1 : n_blocks;
-    TRY(ensure_ws(c, step_bytes(c, l, chunk)));
+    TRY(ensure_ws(c, step_bytes(c, l, chunk, layout)));
     if (mode == 2) {
         // capture and replay on a private stream ordered after / before the caller's
         if (!c->gstream) {
@@ -985,7 +1077,7 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
             << ':' << l << ':' << (const void *)mask->data << ':' << cols << ':' << (const void *)k << ':'
             << (const void *)W_out->data << ':' << (const void *)(G_out ? G_out->data : nullptr) << ':' << pl.k0
             << ':' << pl.k1 << ':' << pl.k2 << ':' << pl.k3 << ':' << pl.kb1 << ':' << pl.kw << ':'
-            << (const void *)c->ws;
+            << (const void *)c->ws << ':' << layout;
         GraphEntry &ge = c->graphs[key.str()];
         hipStream_t user = c->stream;
         HIPCHK(hipEventRecord(c->ev_in, user));

@@ -79,7 +79,7 @@ void sample_hwt(u64 seed, int logN, int h, i64 *out);
 int encode(int logN, const double *re, const double *im, int n, double scale, i64 *out);
 void decode(int logN, const double *m, double scale, int n, double *re, double *im);
 he_status plan_lr_step(const u64 *q, int n_q, int level, double s_z, double s_w, const double coef[4],
-                       double eta_over_n, double w_decay, he_lr_plan *out);
+                       double eta_over_n, double w_decay, int layout, he_lr_plan *o);
 }  // namespace hehost
 
 enum { ST_SECRET = 1, ST_PK_A = 2, ST_PK_E = 3, ST_EVK_A = 4, ST_EVK_E = 5, ST_ENC_A = 6, ST_ENC_E0 = 7 };

@@ -2,6 +2,7 @@
 // companions, the ChaCha20 stream and the secret sampler (keygen runs it once
 // on the host), FP64 canonical-embedding encode/decode, and the FP64 scale
 // schedule of the gradient step.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -210,9 +211,14 @@ void decode(int logN, const double *m, double scale, int n, double *re, double *
     }
 }
 
-// Target scale of the gradient terms: power of two T with
-// T * min(|a1|, |a2|, |a3|) over the nonzero ones in [2^22, 2^23).
-static bool term_scale(const double coef[4], double *T)
+// Target scale T of the gradient terms, a power of two: the largest with
+// T / (eta/n) <= 2^(floor(log2 q_0) - 10) (10 bits of headroom for the output
+// in the last limb), kept between the powers of two with
+// T * min(|a1|, |a2|, |a3|) over the nonzero ones in [2^22, 2^23) and in
+// [2^30, 2^31).  fm_cap > 0 (feature-major): a further upper bound that keeps
+// the gradient mask's plaintext scale at 2^34 or more; false when it cannot
+// be met together with the lower bound.
+static bool term_scale(const double coef[4], u64 q0, double eta_over_n, double fm_cap, double *T)
 {
     double amin = 0.0;
     for (int k : {1, 2, 3}) {
@@ -220,26 +226,86 @@ static bool term_scale(const double coef[4], double *T)
         if (a != 0.0 && (amin == 0.0 || a < amin)) amin = a;
     }
     if (amin == 0.0) return false;
-    int e;
+    int e, ec;
     std::frexp(amin, &e);
-    *T = std::ldexp(1.0, 23 - e);
+    const double lo = std::ldexp(1.0, 23 - e), hi = std::ldexp(1.0, 31 - e);
+    const int qbits = 63 - __builtin_clzll(q0);
+    std::frexp(std::ldexp(eta_over_n, qbits - 10), &ec);
+    const double cap = std::ldexp(1.0, ec - 1);
+    if (fm_cap > 0.0) {
+        *T = std::min(hi, std::min(cap, fm_cap));
+        return !(*T < lo);
+    }
+    *T = std::max(lo, std::min(hi, cap));
     return true;
+}
+
+static he_status finish_plan(double k0, double k1, double k2, double k3, double kb1, double kw, he_lr_plan *o)
+{
+    const double kmax = 4.611686018427388e18;  // 2^62
+    for (double k : {k0, k1, k2, k3, kb1, kw})
+        if (!(std::fabs(k) < kmax)) return HE_ESCALE;
+    o->k0 = std::llround(k0);
+    o->k2 = std::llround(k2);
+    o->k1 = std::llround(k1);
+    o->k3 = std::llround(k3);
+    o->kb1 = std::llround(kb1);
+    o->kw = std::llround(kw);
+    return HE_OK;
+}
+
+// Feature-major schedule: M = u at level l-1 with no mask, the polynomial one
+// level above the row-major one, the summed gradient at level l-3 masked down
+// to level l-4 by a plaintext whose scale returns W' (and g) to the data's
+// scale s_z, so M's scale at the next step stays near q.
+static he_status plan_features(const u64 *q, int level, double s_z, double s_w, const double coef[4],
+                               double eta_over_n, double w_decay, he_lr_plan *o)
+{
+    const double ql = (double)q[level], ql1 = (double)q[level - 1], ql2 = (double)q[level - 2],
+                 ql3 = (double)q[level - 3];
+    int ef;
+    std::frexp(s_z * ql3 * eta_over_n, &ef);
+    double T;
+    if (!term_scale(coef, q[0], eta_over_n, std::ldexp(1.0, ef - 1 - 34), &T)) return HE_ESCALE;
+    o->s1 = s_z * s_w / ql;
+    o->s_m = o->s1;
+    o->s_a = o->s_m * o->s_m / ql1;
+    o->t = T;
+    o->s_z3 = T * ql2 / o->s_a * ql1 / o->s_m;
+    double k3 = coef[3] * o->s_z3 * ql / s_z;
+    o->s_b3 = o->s_m * o->s_z3 / ql1;
+    o->s_c = o->s_a * o->s_b3 / ql2;
+    o->s_z1 = o->s_z3;
+    double k1 = coef[1] * o->s_z1 * ql / s_z;
+    o->s_b1 = o->s_m * o->s_z1 / ql1;
+    double kb1 = o->s_c * ql2 / o->s_b1;
+    double k0 = coef[0] * o->s_c * ql2 / s_z;
+    o->s_z2 = o->s_c * ql2 / o->s_a;
+    double k2 = coef[2] * o->s_z2 * ql1 / s_z;
+    o->s_gsum = o->s_c / eta_over_n;
+    o->s_mask = s_z * ql3 / o->s_gsum;
+    o->s_g = o->s_gsum * o->s_mask / ql3;
+    double kw = (1.0 - w_decay) * o->s_g * ql3 / s_w;
+    return finish_plan(k0, k1, k2, k3, kb1, kw, o);
 }
 
 // FP64 schedule of one step; each expression is evaluated left to right as
 // written (the library is built with floating-point contraction off).
 he_status plan_lr_step(const u64 *q, int n_q, int level, double s_z, double s_w, const double coef[4],
-                       double eta_over_n, double w_decay, he_lr_plan *o)
+                       double eta_over_n, double w_decay, int layout, he_lr_plan *o)
 {
+    if (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES) return HE_EINVAL;
     if (level < 4 || level >= n_q) return HE_ELEVEL;
     if (!(eta_over_n > 0.0) || !(s_z > 0.0) || !(s_w > 0.0) || !(w_decay >= 0.0 && w_decay < 1.0)) return HE_ESCALE;
-    double T;
-    if (!term_scale(coef, &T)) return HE_ESCALE;
-    const double ql = (double)q[level], ql1 = (double)q[level - 1], ql2 = (double)q[level - 2],
-                 ql3 = (double)q[level - 3];
     std::memset(o, 0, sizeof *o);
     o->level_in = level;
     o->level_out = level - 4;
+    o->layout = layout;
+    if (layout == HE_LAYOUT_FEATURES) return plan_features(q, level, s_z, s_w, coef, eta_over_n, w_decay, o);
+    double T;
+    if (!term_scale(coef, q[0], eta_over_n, 0.0, &T)) return HE_ESCALE;
+    const double ql = (double)q[level], ql1 = (double)q[level - 1], ql2 = (double)q[level - 2],
+                 ql3 = (double)q[level - 3];
     o->s1 = s_z * s_w / ql;
     o->s_mask = ql2 * ql1 / o->s1;
     o->s_m = o->s1 * o->s_mask / ql1;
@@ -257,17 +323,9 @@ he_status plan_lr_step(const u64 *q, int n_q, int level, double s_z, double s_w,
     o->s_z2 = o->s_c * ql3 / o->s_a;
     double k2 = coef[2] * o->s_z2 * ql2 / s_z;
     o->s_g = o->s_c / eta_over_n;
+    o->s_gsum = o->s_g;
     double kw = (1.0 - w_decay) * o->s_g * ql3 / s_w;
-    const double kmax = 4.611686018427388e18;  // 2^62
-    for (double k : {k0, k1, k2, k3, kb1, kw})
-        if (!(std::fabs(k) < kmax)) return HE_ESCALE;
-    o->k0 = std::llround(k0);
-    o->k2 = std::llround(k2);
-    o->k1 = std::llround(k1);
-    o->k3 = std::llround(k3);
-    o->kb1 = std::llround(kb1);
-    o->kw = std::llround(kw);
-    return HE_OK;
+    return finish_plan(k0, k1, k2, k3, kb1, kw, o);
 }
 
 }  // namespace hehost

@@ -50,7 +50,11 @@ he_ct3 = he_ct
 class he_lr_plan(ctypes.Structure):
     _fields_ = [("level_in", c_int32), ("level_out", c_int32)] + \
         [(n, c_double) for n in ("s1", "s_mask", "s_m", "s_a", "t", "s_z3", "s_b3", "s_c", "s_z1", "s_b1", "s_g")] + \
-        [(n, c_int64) for n in ("k0", "k1", "k3", "kb1", "kw")] + [("s_z2", c_double), ("k2", c_int64)]
+        [(n, c_int64) for n in ("k0", "k1", "k3", "kb1", "kw")] + [("s_z2", c_double), ("k2", c_int64)] + \
+        [("s_gsum", c_double), ("layout", c_int32), ("reserved", c_int32)]
+
+
+LAYOUT_ROWS, LAYOUT_FEATURES = 0, 1  # HE_LAYOUT_ROWS / HE_LAYOUT_FEATURES
 
 
 _P = POINTER
@@ -86,9 +90,9 @@ _sig = {
     "he_mul_plain": (c_int, [c_void_p, _P(he_ct), _P(he_pt), _P(he_ct)]),
     "he_drop_level": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct)]),
     "he_plan_lr_step": (c_int, [_P(c_uint64), c_int, c_int, c_double, c_double, _P(c_double), c_double, c_double,
-                                _P(he_lr_plan)]),
+                                c_int, _P(he_lr_plan)]),
     "he_lr_grad_step": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), _P(he_pt), _P(c_double), c_double, c_double,
-                                c_int, c_int, c_void_p, c_int, _P(he_ct), _P(he_ct)]),
+                                c_int, c_int, c_int, c_void_p, c_int, _P(he_ct), _P(he_ct)]),
     "he_ntt": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
 }
 for _n, (_r, _a) in _sig.items():
@@ -124,13 +128,13 @@ def params_primes(log_n, n_q, n_special, alpha, log_delta):
     return [int(v) for v in out]
 
 
-def plan_lr_step(primes, n_q, level, s_z, s_w, coef, eta_over_n, w_decay=0.0):
+def plan_lr_step(primes, n_q, level, s_z, s_w, coef, eta_over_n, w_decay=0.0, layout=LAYOUT_ROWS):
     """Pure host scale schedule (no device)."""
     q = np.ascontiguousarray(primes, dtype=np.uint64)
     cf = np.ascontiguousarray(coef, dtype=np.float64)
     out = he_lr_plan()
-    _chk(_lib.he_plan_lr_step(_u64p(q), n_q, level, s_z, s_w, _f64p(cf), eta_over_n, w_decay, ctypes.byref(out)),
-         "he_plan_lr_step")
+    _chk(_lib.he_plan_lr_step(_u64p(q), n_q, level, s_z, s_w, _f64p(cf), eta_over_n, w_decay, layout,
+                              ctypes.byref(out)), "he_plan_lr_step")
     return {f[0]: getattr(out, f[0]) for f in he_lr_plan._fields_}
 
 
@@ -163,7 +167,7 @@ class Keys:
         self.ctx, self.buf, self.handle, self.rot_steps = ctx, buf, handle, list(rot_steps)
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:  # _lib is None during interpreter teardown
             _lib.he_keys_destroy(self.handle)
             self.handle = None
 
@@ -195,7 +199,7 @@ class Context:
         self.primes = [int(v) for v in q]
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and _lib is not None:
             _lib.he_ctx_destroy(self.h)
             self.h = None
 
@@ -342,13 +346,14 @@ class Context:
         _chk(_lib.he_drop_level(self.h, ctypes.byref(a), level, ctypes.byref(o)), "he_drop_level")
         return out.update(o)
 
-    def plan_lr_step(self, level, s_z, s_w, coef, eta_over_n, w_decay=0.0):
-        return plan_lr_step(self.primes, self.n_q, level, s_z, s_w, coef, eta_over_n, w_decay)
+    def plan_lr_step(self, level, s_z, s_w, coef, eta_over_n, w_decay=0.0, layout=LAYOUT_ROWS):
+        return plan_lr_step(self.primes, self.n_q, level, s_z, s_w, coef, eta_over_n, w_decay, layout)
 
     def lr_grad_step(self, Z, W, mask, coef, eta_over_n, cols, rows, keys, mode=1, W_out=None, G_out=None,
-                     want_g=True, w_decay=0.0):
+                     want_g=True, w_decay=0.0, layout=LAYOUT_ROWS):
         """One encrypted gradient step (he_lr_grad_step).  Z: list of block
-        ciphertexts sharing one allocation (ct_block).  Returns (W', g)."""
+        ciphertexts sharing one allocation (ct_block), packed in `layout`.
+        Returns (W', g)."""
         zs = (he_ct * len(Z))(*[z.struct() for z in Z])
         w, m = W.struct(), mask.struct()
         lo = max(W.level - 4, 0)
@@ -359,7 +364,7 @@ class Context:
         go = G_out.struct() if want_g else None
         cf = np.ascontiguousarray(coef, dtype=np.float64)
         _chk(_lib.he_lr_grad_step(self.h, zs, len(Z), ctypes.byref(w), ctypes.byref(m), _f64p(cf), eta_over_n,
-                                  w_decay, cols, rows, keys.handle, mode, ctypes.byref(wo),
+                                  w_decay, cols, rows, layout, keys.handle, mode, ctypes.byref(wo),
                                   ctypes.byref(go) if go is not None else None), "he_lr_grad_step")
         W_out.update(wo)
         if want_g:
@@ -371,9 +376,10 @@ class Context:
 
 
 # ---------------------------------------------------------------- packing (data layout of the step)
-def pack_blocks(X, y, S):
-    """Row-major blocks of Z = y (.) X: slot i*c + j of block b holds
-    y_{b r + i} x_{b r + i, j}; c = next power of two >= d, r = S / c."""
+def pack_blocks(X, y, S, layout=LAYOUT_ROWS):
+    """Blocks of Z = y (.) X; c = next power of two >= d, r = S / c.
+    Row-major: slot i*c + j of block b holds y_{b r + i} x_{b r + i, j};
+    feature-major: slot j*r + i holds it."""
     n, d = X.shape
     c = 1
     while c < d:
@@ -382,16 +388,57 @@ def pack_blocks(X, y, S):
     nb = -(-n // r)
     Z = np.zeros((nb * r, c))
     Z[:n, :d] = y[:, None] * X
-    return Z.reshape(nb, S), c, r
+    Z = Z.reshape(nb, r, c)
+    if layout == LAYOUT_FEATURES:
+        Z = Z.transpose(0, 2, 1)
+    return np.ascontiguousarray(Z).reshape(nb, S), c, r
 
 
-def pack_weights(w, S, c):
+def pack_weights(w, S, c, layout=LAYOUT_ROWS):
+    """w in every row (row-major) or w_j over feature block j (feature-major)."""
     row = np.zeros(c)
     row[: len(w)] = w
-    return np.tile(row, S // c)
+    return np.repeat(row, S // c) if layout == LAYOUT_FEATURES else np.tile(row, S // c)
+
+
+def unpack_weights(slots, c, d, layout=LAYOUT_ROWS):
+    """w from the first row (row-major) or the first slot of each feature block."""
+    v = np.asarray(slots)
+    if layout == LAYOUT_FEATURES:
+        return v.reshape(c, -1)[:d, 0]
+    return v.reshape(-1, c)[0, :d]
 
 
 def column0_mask(S, c):
     m = np.zeros(S)
     m[::c] = 1.0
     return m
+
+
+def step_mask(S, c, layout=LAYOUT_ROWS):
+    """The step's mask: column 0 of every row (row-major, applied to the
+    margins) or slot 0 of every feature block (feature-major, applied to the
+    gradient)."""
+    m = np.zeros(S)
+    m[:: (S // c) if layout == LAYOUT_FEATURES else c] = 1.0
+    return m
+
+
+def mask_level(level, layout=LAYOUT_ROWS):
+    """Level of the step's mask plaintext for weights at `level`."""
+    return level - 3 if layout == LAYOUT_FEATURES else level - 1
+
+
+def rotation_steps(c, r, layout=LAYOUT_ROWS):
+    """Rotation keys the step needs."""
+    pm, st, unit = (r, c, r) if layout == LAYOUT_FEATURES else (c, r, c)
+    out = []
+    t = 1
+    while t < pm:
+        out += [t, -t]
+        t *= 2
+    t = 1
+    while t < st:
+        out.append(t * unit)
+        t *= 2
+    return out

@@ -16,8 +16,8 @@ from . import he as H
 class ParameterServer:
     """Holds sk (inside `keys`) and the plaintext weights; Alg. 2."""
 
-    def __init__(self, ctx, keys, d, cols, seed_enc, first_index=1 << 24):
-        self.ctx, self.keys, self.d, self.cols = ctx, keys, d, cols
+    def __init__(self, ctx, keys, d, cols, seed_enc, first_index=1 << 24, layout=H.LAYOUT_ROWS):
+        self.ctx, self.keys, self.d, self.cols, self.layout = ctx, keys, d, cols, layout
         self.seed_enc = seed_enc
         self.index = first_index  # ChaCha20 stream index of the next weight encryption
         self.w = None
@@ -29,7 +29,7 @@ class ParameterServer:
         ctx = self.ctx
         L = ctx.n_q - 1
         self.w = np.array(w, dtype=np.float64)
-        m = ctx.encode(H.pack_weights(self.w, ctx.S, self.cols), ctx.delta)
+        m = ctx.encode(H.pack_weights(self.w, ctx.S, self.cols, self.layout), ctx.delta)
         if self._buf is None:
             self._buf = ctx.ct_empty(L)
             self._pt = ctx.pt_empty(L)
@@ -41,17 +41,16 @@ class ParameterServer:
     def refresh(self, W):
         """Decrypt the worker's weights, update the server's copy, re-encrypt."""
         slots = self.ctx.decrypt_decode(W, self.keys).real
-        w = slots.reshape(-1, self.cols)[0, : self.d]
-        return self.encrypt_weights(w)
+        return self.encrypt_weights(H.unpack_weights(slots, self.cols, self.d, self.layout))
 
 
 class Worker:
     """Evaluates the encrypted gradient step on its shard; Alg. 1."""
 
-    def __init__(self, ctx, keys, Z, coef, eta_over_n, cols, rows, mode=2, w_decay=0.0):
+    def __init__(self, ctx, keys, Z, coef, eta_over_n, cols, rows, mode=2, w_decay=0.0, layout=H.LAYOUT_ROWS):
         self.ctx, self.keys, self.Z = ctx, keys, Z
         self.coef, self.eta_over_n, self.w_decay = list(coef), eta_over_n, w_decay
-        self.cols, self.rows, self.mode = cols, rows, mode
+        self.cols, self.rows, self.mode, self.layout = cols, rows, mode, layout
         self._masks = {}
         self._bufs = {}
 
@@ -59,8 +58,8 @@ class Worker:
         key = (level, s_mask)
         if key not in self._masks:
             ctx = self.ctx
-            m = ctx.encode(H.column0_mask(ctx.S, self.cols), s_mask)
-            self._masks[key] = ctx.pt_load(m, level - 1, s_mask)
+            m = ctx.encode(H.step_mask(ctx.S, self.cols, self.layout), s_mask)
+            self._masks[key] = ctx.pt_load(m, H.mask_level(level, self.layout), s_mask)
         return self._masks[key]
 
     def _out(self, level, slot):
@@ -73,18 +72,20 @@ class Worker:
         """One iteration; the output lives in a buffer owned per output level
         (levels only decrease between refreshes, so it never aliases W)."""
         ctx = self.ctx
-        pl = ctx.plan_lr_step(W.level, self.Z[0].scale, W.scale, self.coef, self.eta_over_n, self.w_decay)
+        pl = ctx.plan_lr_step(W.level, self.Z[0].scale, W.scale, self.coef, self.eta_over_n, self.w_decay,
+                              self.layout)
         mask = self._mask(W.level, pl["s_mask"])
         lo = W.level - 4
         W_out = self._out(lo, 0)
         G_out = self._out(lo, 1) if want_g else None
         return ctx.lr_grad_step(self.Z, W, mask, self.coef, self.eta_over_n, self.cols, self.rows, self.keys,
-                                mode=self.mode, W_out=W_out, G_out=G_out, want_g=want_g, w_decay=self.w_decay)
+                                mode=self.mode, W_out=W_out, G_out=G_out, want_g=want_g, w_decay=self.w_decay,
+                                layout=self.layout)
 
 
-def encrypt_shard(ctx, keys, X, y, seed_enc):
+def encrypt_shard(ctx, keys, X, y, seed_enc, layout=H.LAYOUT_ROWS):
     """Alg. 2 initialisation: pack Z = y (.) X into blocks and encrypt each with sk."""
-    blocks, cols, rows = H.pack_blocks(X, y, ctx.S)
+    blocks, cols, rows = H.pack_blocks(X, y, ctx.S, layout)
     L = ctx.n_q - 1
     Z = ctx.ct_block(blocks.shape[0], L)
     for i in range(blocks.shape[0]):
@@ -92,19 +93,20 @@ def encrypt_shard(ctx, keys, X, y, seed_enc):
     return Z, cols, rows
 
 
-def train(ctx, keys, X, y, coef, eta, iterations, refresh_every, w0, seed_enc, mode=2, record=None, l2=0.0):
+def train(ctx, keys, X, y, coef, eta, iterations, refresh_every, w0, seed_enc, mode=2, record=None, l2=0.0,
+          layout=H.LAYOUT_ROWS):
     """Alg. 1 + Alg. 2 on one GPU.  Returns the server's final plaintext
     weights (after a last refresh) and, if `record` is a list, appends the
     decrypted weights after every iteration.  l2: lambda of R = lambda/2 |w|^2."""
     n, d = X.shape
-    Z, cols, rows = encrypt_shard(ctx, keys, X, y, seed_enc)
-    ps = ParameterServer(ctx, keys, d, cols, seed_enc)
-    worker = Worker(ctx, keys, Z, coef, eta / n, cols, rows, mode=mode, w_decay=eta * l2)
+    Z, cols, rows = encrypt_shard(ctx, keys, X, y, seed_enc, layout)
+    ps = ParameterServer(ctx, keys, d, cols, seed_enc, layout=layout)
+    worker = Worker(ctx, keys, Z, coef, eta / n, cols, rows, mode=mode, w_decay=eta * l2, layout=layout)
     W = ps.encrypt_weights(w0)
     for k in range(1, iterations + 1):
         W, _ = worker.step(W)
         if record is not None:
-            record.append(ctx.decrypt_decode(W, keys).real.reshape(-1, cols)[0, :d].copy())
+            record.append(H.unpack_weights(ctx.decrypt_decode(W, keys).real, cols, d, layout).copy())
         if k % refresh_every == 0 or W.level < 4:
             W = ps.refresh(W)
     ps.refresh(W)

@@ -45,24 +45,52 @@ COEF = [0.5, -0.1501204134, 0.0, 0.0015930174]
 HINGE = [0.5875, -0.1005, 0.0008, -0.00039]  # Table 2, hinge row as printed
 
 
-@pytest.mark.parametrize("name", ["small", "image", "large"])
+@pytest.mark.parametrize("name,n", [("small", None), ("image", None), ("large", None), ("image", 128)])
 @pytest.mark.parametrize("coef,w_decay", [(COEF, 0.0), (HINGE, 0.0), (COEF, 0.01)])
-def test_scale_plan_matches_oracle_bit_for_bit(name, coef, w_decay):
+@pytest.mark.parametrize("layout", [LR.ROWS, LR.FEATURES])
+def test_scale_plan_matches_oracle_bit_for_bit(name, n, coef, w_decay, layout):
     W = synth.WORKLOADS[name]
     q = O.Params(W["logN"], W["nq"], W["nk"], W["alpha"], W["log_delta"]).q
     delta = float(2 ** W["log_delta"])
-    eta_n = 1.0 / W["n"]
+    eta_n = 1.0 / (n or W["n"])
     s_w = delta
     for level in range(W["nq"] - 1, 3, -4):
-        a = LR.plan_lr_step(q, level, delta, s_w, coef, eta_n, w_decay)
-        b = H.plan_lr_step(q, W["nq"], level, delta, s_w, coef, eta_n, w_decay)
-        for k in ("s1", "s_mask", "sM", "sA", "T", "sZ3", "sB3", "sC", "sZ1", "sB1", "sZ2", "s_g"):
+        try:
+            a = LR.plan_lr_step(q, level, delta, s_w, coef, eta_n, w_decay, layout)
+        except LR.ScaleError:
+            # refused (feature-major at a data scale too small for n/eta): the library agrees
+            assert layout == LR.FEATURES
+            with pytest.raises(H.HEError) as e:
+                H.plan_lr_step(q, W["nq"], level, delta, s_w, coef, eta_n, w_decay, layout)
+            assert e.value.status == 4
+            return
+        b = H.plan_lr_step(q, W["nq"], level, delta, s_w, coef, eta_n, w_decay, layout)
+        assert b["layout"] == layout
+        for k in ("s1", "s_mask", "sM", "sA", "T", "sZ3", "sB3", "sC", "sZ1", "sB1", "sZ2", "s_g", "s_gsum"):
             kk = {"sM": "s_m", "sA": "s_a", "T": "t", "sZ3": "s_z3", "sB3": "s_b3", "sC": "s_c", "sZ1": "s_z1",
                   "sB1": "s_b1", "sZ2": "s_z2"}.get(k, k)
             assert a[k] == b[kk], (level, k)
         for k in ("k0", "k1", "k2", "k3", "kB1", "kW"):
             assert a[k] == b[k.lower()], (level, k)
         s_w = a["s_g"]  # the next step starts from the previous output scale
+
+
+def test_term_scale_headroom_rule():
+    """T: the largest power of two keeping 10 bits of headroom for the output in
+    q_0, between the two coefficient-resolution bounds."""
+    q = O.Params(16, 20, 4, 4, 40).q
+    assert q[0].bit_length() == 60
+    assert LR.term_scale(COEF, q[0], 1 / 6000) == 2.0 ** 36   # 2^49 / 6000 -> 2^36
+    assert LR.term_scale(COEF, q[0], 1 / 128) == 2.0 ** 40     # capped: T a3 in [2^30, 2^31)
+    assert LR.term_scale(COEF, q[0], 2.0 ** -20) == 2.0 ** 32  # floored: T a3 in [2^22, 2^23)
+    for eta_n in (1 / 6000, 1 / 128, 2.0 ** -20):
+        pl = H.plan_lr_step(q, 20, 19, 2.0 ** 40, 2.0 ** 40, COEF, eta_n)
+        assert pl["t"] == LR.term_scale(COEF, q[0], eta_n)
+    # feature-major: the mask's plaintext scale stays >= 2^34
+    for eta_n, t in ((1 / 6000, 2.0 ** 33), (1 / 128, 2.0 ** 38)):
+        pl = H.plan_lr_step(q, 20, 19, 2.0 ** 40, 2.0 ** 40, COEF, eta_n, 0.0, H.LAYOUT_FEATURES)
+        assert pl["t"] == t and pl["s_mask"] >= 2.0 ** 34
+        assert abs(pl["s_g"] / 2.0 ** 40 - 1) < 1e-12  # W' returns at the data's scale
 
 
 def test_scale_plan_errors():
@@ -79,6 +107,9 @@ def test_scale_plan_errors():
     with pytest.raises(H.HEError) as e:
         H.plan_lr_step(q, 5, 4, 2.0 ** 30, 1.0, COEF, 1 / 2048)
     assert e.value.status == 4  # HE_ESCALE: constant out of range
+    with pytest.raises(H.HEError) as e:
+        H.plan_lr_step(q, 5, 4, 2.0 ** 30, 2.0 ** 30, COEF, 1 / 2048, 0.0, 2)
+    assert e.value.status == 1  # HE_EINVAL: unknown layout
 
 
 def test_packing_matches_oracle_layout():
@@ -90,3 +121,12 @@ def test_packing_matches_oracle_layout():
     w = np.arange(11.0)
     assert np.array_equal(H.pack_weights(w, 4096, 16), LR.pack_weights(w, 4096, 16))
     assert np.array_equal(H.column0_mask(4096, 16), LR.column_mask(4096, 16))
+    a, _, _ = H.pack_blocks(X, y, 4096, H.LAYOUT_FEATURES)
+    b, _, _ = LR.pack_blocks_features(X, y, 4096)
+    assert np.array_equal(a, b)
+    assert np.array_equal(H.pack_weights(w, 4096, 16, H.LAYOUT_FEATURES), LR.pack_weights_features(w, 4096, 16))
+    assert np.array_equal(H.step_mask(4096, 16, H.LAYOUT_FEATURES), LR.feature_mask(4096, 256))
+    assert np.array_equal(H.step_mask(4096, 16), LR.column_mask(4096, 16))
+    for lay in (LR.ROWS, LR.FEATURES):
+        assert sorted(H.rotation_steps(16, 256, lay)) == sorted(LR.rotation_steps(16, 256, lay))
+        assert np.array_equal(H.unpack_weights(H.pack_weights(w, 4096, 16, lay), 16, 11, lay), w)

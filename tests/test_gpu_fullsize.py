@@ -3,10 +3,12 @@ launch configuration the bench times.
 
 * every key-switching operation of the step, bit for bit against the oracle,
   at the levels the step uses;
-* one-block steps (the whole circuit, row sum included) bit for bit against the
-  oracle, in the batched form;
-* the full 47-block shard: the plain, batched and graph-replayed forms agree
-  bit for bit, and the decrypted gradient is within 2^-20 of the FP64 one.
+* one-block steps (the whole circuit, the once-per-step sums included) bit for
+  bit against the oracle, in the batched form, in both block layouts;
+* the full 47-block shard in both layouts: the plain, batched and
+  graph-replayed forms agree bit for bit, and the decrypted gradient is within
+  2^-20 of the FP64 one;
+* 10 training steps with a refresh every 4, both layouts, against FP64.
 """
 import numpy as np
 import pytest
@@ -64,57 +66,78 @@ def test_full_size_keyswitch_ops_bit_exact(env, okeys):
         assert np.array_equal(ctx.download(ctx.rotate(z, t, gk)), O.rotate(P, O.CT(zd, level, 1.0), t, okeys).data)
 
 
-def test_full_size_one_block_step_bit_exact(env, okeys):
-    """One block of the shard through the whole circuit, GPU batched form vs oracle."""
+def _as_grid(H, slots, c, r, layout):
+    """Decoded slots as [sample row, feature column]."""
+    v = np.asarray(slots)
+    return v.reshape(c, r).T if layout == H.LAYOUT_FEATURES else v.reshape(r, c)
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_full_size_one_block_step_bit_exact(env, okeys, layout):
+    """One block of the shard through the whole circuit, GPU batched form vs
+    oracle, in both layouts (the feature-major rotations are a subset of the
+    row-major key set at this shape)."""
     ctx, P, gk = env["ctx"], env["P"], env["gk"]
+    c, r = env["c"], env["r"]
+    assert set(LR.rotation_steps(c, r, layout)) <= set(env["steps"])
     coef = _coef()
     eta_n = 1.0 / 128
-    m = O.encode(env["blocks"][5], P.delta, P.N)
+    blk = (LR.pack_blocks_features if layout else LR.pack_blocks)(env["X"], env["y"], P.S)[0][5]
+    m = O.encode(blk, P.delta, P.N)
     oZ = O.encrypt_sk(P, okeys, m, P.L, P.delta, 9, 5)
     gZ = ctx.ct_block(1, P.L)
     ctx.encrypt(ctx.pt_load(m, P.L, P.delta), gk, 9, 5, out=gZ[0])
     w = np.random.default_rng(5).uniform(-0.05, 0.05, 196)
-    mw = O.encode(LR.pack_weights(w, P.S, env["c"]), P.delta, P.N)
+    pw = LR.pack_weights_features(w, P.S, c) if layout else LR.pack_weights(w, P.S, c)
+    mw = O.encode(pw, P.delta, P.N)
     oW = O.encrypt_sk(P, okeys, mw, P.L, P.delta, 9, 999)
     gW = ctx.encrypt(ctx.pt_load(mw, P.L, P.delta), gk, 9, 999)
-    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n)
-    mm = O.encode(LR.column_mask(P.S, env["c"]), pl["s_mask"], P.N)
-    oWn, og = LR.lr_grad_step(P, okeys, [oZ], oW, mm, coef, eta_n, env["c"], env["r"], plan=pl)
-    mask = ctx.pt_load(mm, P.L - 1, pl["s_mask"])
-    Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, env["c"], env["r"], gk, mode=1)
+    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n, 0.0, layout)
+    mm = O.encode(LR.feature_mask(P.S, r) if layout else LR.column_mask(P.S, c), pl["s_mask"], P.N)
+    oWn, og = LR.lr_grad_step(P, okeys, [oZ], oW, mm, coef, eta_n, c, r, plan=pl, layout=layout)
+    H = env["H"]
+    mask = ctx.pt_load(mm, H.mask_level(P.L, layout), pl["s_mask"])
+    Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, gk, mode=1, layout=layout)
     assert np.array_equal(ctx.download(Wn), oWn.data)
     assert np.array_equal(ctx.download(g), og.data)
 
 
-def test_full_shard_forms_agree_and_gradient_within_tolerance(env):
+@pytest.mark.parametrize("layout", [0, 1])
+def test_full_shard_forms_agree_and_gradient_within_tolerance(env, layout):
     ctx, gk, H = env["ctx"], env["gk"], env["H"]
-    L, S, c, r = ctx.n_q - 1, ctx.S, env["c"], env["r"]
-    blocks, X, y = env["blocks"], env["X"], env["y"]
+    L, S = ctx.n_q - 1, ctx.S
+    X, y = env["X"], env["y"]
+    blocks, c, r = H.pack_blocks(X, y, S, layout)
+    d = X.shape[1]
     Z = ctx.ct_block(blocks.shape[0], L)
     for i in range(blocks.shape[0]):
         ctx.encrypt(ctx.pt_load(ctx.encode(blocks[i], ctx.delta), L, ctx.delta), gk, W["seed_enc"], i, out=Z[i])
-    w0 = np.random.default_rng(8).uniform(-0.02, 0.02, X.shape[1])
-    Wc = ctx.encrypt(ctx.pt_load(ctx.encode(H.pack_weights(w0, S, c), ctx.delta), L, ctx.delta), gk, 3, 77777)
+    w0 = np.random.default_rng(8).uniform(-0.02, 0.02, d)
+    Wc = ctx.encrypt(ctx.pt_load(ctx.encode(H.pack_weights(w0, S, c, layout), ctx.delta), L, ctx.delta), gk, 3,
+                     77777)
     coef, eta_n = _coef(), 1.0 / X.shape[0]
-    pl = ctx.plan_lr_step(L, ctx.delta, ctx.delta, coef, eta_n)
-    mask = ctx.pt_load(ctx.encode(H.column0_mask(S, c), pl["s_mask"]), L - 1, pl["s_mask"])
+    pl = ctx.plan_lr_step(L, ctx.delta, ctx.delta, coef, eta_n, layout=layout)
+    mask = ctx.pt_load(ctx.encode(H.step_mask(S, c, layout), pl["s_mask"]), H.mask_level(L, layout), pl["s_mask"])
     outs = []
     for mode in (0, 1, 2, 2):
-        Wn, g = ctx.lr_grad_step(Z, Wc, mask, coef, eta_n, c, r, gk, mode=mode)
+        Wn, g = ctx.lr_grad_step(Z, Wc, mask, coef, eta_n, c, r, gk, mode=mode, layout=layout)
         outs.append((ctx.download(Wn), ctx.download(g)))
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
-    wdec = ctx.decrypt_decode(Wc, gk).real[: X.shape[1]]
-    gref = LR.lr_gradient_fp64(X, y, wdec, coef, eta_n)
-    gd = ctx.decrypt_decode(g, gk).real.reshape(r, c)
-    for row in (0, r - 1):
-        assert np.max(np.abs(gd[row, : X.shape[1]] - gref)) / np.max(np.abs(gref)) < 2.0 ** -20
-        assert np.max(np.abs(gd[row, X.shape[1]:])) < 2.0 ** -20 * np.max(np.abs(gref))  # padded columns stay 0
-    wn = ctx.decrypt_decode(Wn, gk).real[: X.shape[1]]
-    assert np.max(np.abs(wn - wdec - gref)) / np.max(np.abs(wdec + gref)) < 2.0 ** -20
+    wgrid = _as_grid(H, ctx.decrypt_decode(Wc, gk).real, c, r, layout)
+    gref = LR.lr_gradient_fp64(X, y, wgrid[0, :d], coef, eta_n)
+    gd = _as_grid(H, ctx.decrypt_decode(g, gk).real, c, r, layout)
+    for row in (0, r // 2, r - 1):
+        assert np.max(np.abs(gd[row, :d] - gref)) / np.max(np.abs(gref)) < 2.0 ** -20
+        assert np.max(np.abs(gd[row, d:])) < 2.0 ** -20 * np.max(np.abs(gref))  # padded features stay 0
+    wn = _as_grid(H, ctx.decrypt_decode(Wn, gk).real, c, r, layout)
+    for row in (0, r - 1):  # each slot of W carries its own encryption noise
+        want = wgrid[row, :d] + gref
+        assert np.max(np.abs(wn[row, :d] - want)) / np.max(np.abs(want)) < 2.0 ** -20
 
 
-def test_full_size_training_ten_steps_refresh_every_four(env):
+@pytest.mark.parametrize("layout", [0, 1])
+def test_full_size_training_ten_steps_refresh_every_four(env, layout):
     """The image shard's 10 steps with a refresh every 4 (Alg. 1 / Alg. 2),
     graph-replayed batched form, against FP64 plaintext training."""
     from paper_2006_10091_amd import train as T
@@ -122,7 +145,8 @@ def test_full_size_training_ten_steps_refresh_every_four(env):
     X, y = env["X"], env["y"]
     coef = _coef()
     rec = []
-    w_final = T.train(ctx, gk, X, y, coef, 1.0, 10, 4, np.zeros(X.shape[1]), 3004, mode=2, record=rec)
+    w_final = T.train(ctx, gk, X, y, coef, 1.0, 10, 4, np.zeros(X.shape[1]), 3004, mode=2, record=rec,
+                      layout=layout)
     w = np.zeros(X.shape[1])
     for k in range(10):
         w = w + LR.lr_gradient_fp64(X, y, w, coef, 1.0 / X.shape[0])

@@ -38,7 +38,7 @@ def small():
     ctx = H.Context(*cfg)
     X, y = synth.small_data()
     blocks, c, r = LR.pack_blocks(X, y, P.S)
-    steps = LR.rotation_steps(c, r)
+    steps = sorted(set(LR.rotation_steps(c, r)) | set(LR.rotation_steps(c, r, LR.FEATURES)))
     okeys = O.Keys(P, W["seed_keys"], rot_steps=steps)
     gkeys = ctx.keygen(W["seed_keys"], steps)
     return dict(W=W, P=P, ctx=ctx, X=X, y=y, blocks=blocks, c=c, r=r, okeys=okeys, gkeys=gkeys, H=H)
@@ -304,3 +304,100 @@ def test_lr_step_other_losses_bit_exact(small, coef_name, w_decay):
         Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, small["gkeys"], mode=mode, w_decay=w_decay)
         assert np.array_equal(ctx.download(Wn), oWn.data)
         assert np.array_equal(ctx.download(g), og.data)
+
+
+# ------------------------------------------------------------------ feature-major layout
+def _table2(name):
+    import os
+    rows = {}
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "table2_gradient_polynomials.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            rows[k] = [float(x) for x in v]
+    return rows[name]
+
+
+@pytest.fixture(scope="module")
+def small40():
+    """The small ring at scale 2^40 with keys for both layouts."""
+    W = synth.WORKLOADS["small"]
+    cfg = (13, 5, 2, 2, 40)
+    P = O.Params(*cfg)
+    ctx = _H().Context(*cfg)
+    c, r = 16, P.S // 16
+    steps = sorted(set(LR.rotation_steps(c, r)) | set(LR.rotation_steps(c, r, LR.FEATURES)))
+    return dict(W=W, P=P, ctx=ctx, okeys=O.Keys(P, W["seed_keys"], rot_steps=steps),
+                gkeys=ctx.keygen(W["seed_keys"], steps), H=_H())
+
+
+@pytest.mark.parametrize("loss,w_decay,n", [("ls", 0.0, 2048), ("hinge", 0.0, 700), ("ls", 0.05, 300)])
+def test_lr_step_feature_major_bit_exact(small40, loss, w_decay, n):
+    """Feature-major step, plain, batched and graph-replayed forms, bit for bit
+    against the oracle (full, ragged and single-block shards), and the
+    decrypted g within 2^-20 of FP64."""
+    small = small40
+    ctx, P, W = small["ctx"], small["P"], small["W"]
+    X, y = synth.small_data(n=n)
+    blocks, c, r = LR.pack_blocks_features(X, y, P.S)
+    coef = _coef() if loss == "ls" else _table2(loss)
+    w0 = synth.initial_weights("small", 16, 91)
+    oZ, gZ = [], ctx.ct_block(blocks.shape[0], P.L)
+    for i in range(blocks.shape[0]):
+        m = O.encode(blocks[i], P.delta, P.N)
+        oZ.append(O.encrypt_sk(P, small["okeys"], m, P.L, P.delta, W["seed_enc"], i))
+        ctx.encrypt(ctx.pt_load(m, P.L, P.delta), small["gkeys"], W["seed_enc"], i, out=gZ[i])
+    mw = O.encode(LR.pack_weights_features(w0, P.S, c), P.delta, P.N)
+    oW = O.encrypt_sk(P, small["okeys"], mw, P.L, P.delta, W["seed_enc"], 100001)
+    gW = ctx.encrypt(ctx.pt_load(mw, P.L, P.delta), small["gkeys"], W["seed_enc"], 100001)
+    eta_n = 1.0 / n
+    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n, w_decay, LR.FEATURES)
+    mm = O.encode(LR.feature_mask(P.S, r), pl["s_mask"], P.N)
+    oWn, og = LR.lr_grad_step(P, small["okeys"], oZ, oW, mm, coef, eta_n, c, r, plan=pl, layout=LR.FEATURES)
+    H = small["H"]
+    mask = ctx.pt_load(mm, H.mask_level(P.L, H.LAYOUT_FEATURES), pl["s_mask"])
+    for mode in (0, 1, 2, 2):
+        Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, small["gkeys"], mode=mode, w_decay=w_decay,
+                                 layout=H.LAYOUT_FEATURES)
+        assert Wn.level == P.L - 4 and Wn.scale == pl["s_g"]
+        assert np.array_equal(ctx.download(Wn), oWn.data), mode
+        assert np.array_equal(ctx.download(g), og.data), mode
+    wdec = ctx.decrypt_decode(gW, small["gkeys"]).real.reshape(c, r)[:16, 0]
+    gref = LR.lr_gradient_fp64(X, y, wdec, coef, eta_n)
+    gd = ctx.decrypt_decode(g, small["gkeys"]).real.reshape(c, r)[:16]
+    assert np.max(np.abs(gd - gref[:, None])) / np.max(np.abs(gref)) < TOL
+
+
+def test_lr_step_feature_major_errors(small, small40):
+    """Wrong mask level, missing keys, an unknown layout and a data scale too
+    small for the feature-major mask are refused before any launch."""
+    ctx, P, H = small["ctx"], small["P"], small["H"]
+    X, y = synth.small_data(n=256)
+    blocks, c, r = LR.pack_blocks_features(X, y, P.S)
+    Z = ctx.ct_block(1, P.L)
+    ctx.encrypt(ctx.pt_load(O.encode(blocks[0], P.delta, P.N), P.L, P.delta), small["gkeys"], 5, 0, out=Z[0])
+    Wc = ctx.encrypt(ctx.pt_load(O.encode(np.zeros(P.S), P.delta, P.N), P.L, P.delta), small["gkeys"], 5, 1)
+    mask = ctx.pt_load(O.encode(LR.feature_mask(P.S, r), 2.0 ** 30, P.N), P.L - 3, 2.0 ** 30)
+    with pytest.raises(H.HEError) as e:  # scale 2^30 data: the plan refuses the layout
+        ctx.lr_grad_step(Z, Wc, mask, _coef(), 1 / 256, c, r, small["gkeys"], layout=H.LAYOUT_FEATURES)
+    assert e.value.status == 4
+    ctx, P = small40["ctx"], small40["P"]
+    small = small40
+    blocks, c, r = LR.pack_blocks_features(*synth.small_data(n=256), P.S)
+    Z = ctx.ct_block(1, P.L)
+    ctx.encrypt(ctx.pt_load(O.encode(blocks[0], P.delta, P.N), P.L, P.delta), small["gkeys"], 5, 0, out=Z[0])
+    Wc = ctx.encrypt(ctx.pt_load(O.encode(np.zeros(P.S), P.delta, P.N), P.L, P.delta), small["gkeys"], 5, 1)
+    coef = _coef()
+    pl = ctx.plan_lr_step(P.L, P.delta, P.delta, coef, 1 / 256, layout=H.LAYOUT_FEATURES)
+    mm = O.encode(LR.feature_mask(P.S, r), pl["s_mask"], P.N)
+    bad_level = ctx.pt_load(mm, P.L - 1, pl["s_mask"])
+    with pytest.raises(H.HEError) as e:
+        ctx.lr_grad_step(Z, Wc, bad_level, coef, 1 / 256, c, r, small["gkeys"], layout=H.LAYOUT_FEATURES)
+    assert e.value.status == 3
+    mask = ctx.pt_load(mm, P.L - 3, pl["s_mask"])
+    with pytest.raises(H.HEError) as e:
+        ctx.lr_grad_step(Z, Wc, mask, coef, 1 / 256, c, r, small["gkeys"], layout=2)
+    assert e.value.status == 1
+    rk = ctx.keygen(3, LR.rotation_steps(c, r))  # row-major keys lack -16 .. -128
+    with pytest.raises(H.HEError) as e:
+        ctx.lr_grad_step(Z, Wc, mask, coef, 1 / 256, c, r, rk, layout=H.LAYOUT_FEATURES)
+    assert e.value.status == 5

@@ -530,3 +530,70 @@ def test_encrypted_step_other_losses_and_regulariser(loss, w_decay):
     wn = O.decrypt(P, keys, Wn).real[:16]
     want = (1.0 - w_decay) * wdec + gref
     assert np.max(np.abs(wn - want)) / np.max(np.abs(want)) < 2.0 ** -20
+
+
+def test_feature_major_packing_is_the_transpose():
+    X, y = synth.small_data(n=700)
+    rb, c, r = LR.pack_blocks(X, y, 4096)
+    fb, c2, r2 = LR.pack_blocks_features(X, y, 4096)
+    assert (c, r) == (c2, r2) == (16, 256)
+    for b in (0, 2):
+        for i, j in ((0, 0), (3, 5), (255, 15), (17, 1)):
+            assert fb[b, j * r + i] == rb[b, i * c + j]
+    w = np.arange(1.0, 11.0)
+    pw = LR.pack_weights_features(w, 4096, 16)
+    assert pw[0 * r + 7] == 1.0 and pw[9 * r + 200] == 10.0 and pw[12 * r] == 0.0
+    assert np.flatnonzero(LR.feature_mask(4096, r)).tolist() == [j * r for j in range(16)]
+    st = LR.rotation_steps(c, r, LR.FEATURES)
+    assert st[:4] == [256, 512, 1024, 2048] and sorted(st[4:]) == sorted([t * s for t in (1, 2, 4, 8, 16, 32, 64, 128)
+                                                                          for s in (1, -1)])
+
+
+SMALL40 = (13, 5, 2, 2, 40)  # the small ring at scale 2^40 (feature-major needs a larger data scale)
+
+
+def test_feature_major_refused_where_the_mask_would_lose_precision():
+    W = synth.WORKLOADS["small"]
+    P = O.Params(W["logN"], W["nq"], W["nk"], W["alpha"], W["log_delta"])
+    coef = LR.grad_poly_binomial(8.0)
+    coef[0], coef[2] = 0.5, 0.0
+    with pytest.raises(LR.ScaleError):
+        LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, 1 / 2048, 0.0, LR.FEATURES)
+    LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, 1 / 2048, 0.0, LR.ROWS)
+
+
+@pytest.mark.parametrize("loss,w_decay", [("binomial-ls", 0.0), ("hinge", 0.0), ("binomial-ls", 0.05)])
+def test_encrypted_step_feature_major(loss, w_decay):
+    """Feature-major circuit: the decrypted g, in every slot of each feature
+    block, within 2^-20 of the FP64 gradient; W' = (1 - eta lambda) W + g
+    likewise; 4 levels used."""
+    W = synth.WORKLOADS["small"]
+    P = O.Params(*SMALL40)
+    X, y = synth.small_data(n=700)
+    w0 = synth.initial_weights("small", 16, W["seed_w"])
+    blocks, c, r = LR.pack_blocks_features(X, y, P.S)
+    keys = O.Keys(P, W["seed_keys"], rot_steps=LR.rotation_steps(c, r, LR.FEATURES))
+    if loss == "hinge":
+        coef = _table2_row("hinge")
+    else:
+        coef = LR.grad_poly_binomial(8.0)
+        coef[0], coef[2] = 0.5, 0.0
+    eta_n = 1.0 / X.shape[0]
+    Z = [O.encrypt_sk(P, keys, O.encode(blocks[i], P.delta, P.N), P.L, P.delta, 7, i) for i in range(len(blocks))]
+    Wc = O.encrypt_sk(P, keys, O.encode(LR.pack_weights_features(w0, P.S, c), P.delta, P.N), P.L, P.delta, 7, 999)
+    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n, w_decay, LR.FEATURES)
+    mask = O.encode(LR.feature_mask(P.S, r), pl["s_mask"], P.N)
+    Wn, g = LR.lr_grad_step(P, keys, Z, Wc, mask, coef, eta_n, c, r, plan=pl, layout=LR.FEATURES)
+    assert Wn.level == g.level == P.L - 4
+    wdec = O.decrypt(P, keys, Wc).real.reshape(c, r)[:16, 0]
+    gref = LR.lr_gradient_fp64(X, y, wdec, coef, eta_n)
+    gd = O.decrypt(P, keys, g).real.reshape(c, r)
+    for i in (0, 1, r // 2, r - 1):
+        assert np.max(np.abs(gd[:16, i] - gref)) / np.max(np.abs(gref)) < 2.0 ** -20
+    # W' slot by slot against the same slot of W (each slot carries its own
+    # encryption noise, about 2^-22 absolute at this scale)
+    wfull = O.decrypt(P, keys, Wc).real.reshape(c, r)
+    wn = O.decrypt(P, keys, Wn).real.reshape(c, r)
+    for i in (0, 5, r - 1):
+        want = (1.0 - w_decay) * wfull[:16, i] + gref
+        assert np.max(np.abs(wn[:16, i] - want)) / np.max(np.abs(want)) < 2.0 ** -20
