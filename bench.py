@@ -39,7 +39,7 @@ HBM_PEAK_GBS = 8000.0
 # what the same counter reads for the 1 GiB calibration copy below
 # (profiles/ntt_forward_5640_limbs_pmc.md).  None whenever the NTT kernels have
 # changed since the counters were taken.
-NTT_TRAFFIC_BYTES = {}
+NTT_TRAFFIC_BYTES = {5640: (2 * 1444810 + 2 * 2089074 + 2887680 + 2887680) * 1024}
 COPY_BYTES = 1 << 30
 REFRESH_EVERY = 4
 
@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--layout", choices=("both", "feature-major", "row-major"), default="both",
+                    help="packings to run (value needs feature-major)")
     ap.add_argument("--ntt-counters", action="store_true",
                     help="run only the calibration copy and the NTT batch (a target for rocprofv3 --pmc passes, "
                          "which cannot follow the step's graph launches); prints no bench line")
@@ -233,11 +235,11 @@ def main():
     coef = coef_binomial()
 
     layouts = {}
-    for layout in (H.LAYOUT_FEATURES, H.LAYOUT_ROWS):
-        res = bench_layout(torch, H, T, ctx, keys, X, y, coef, layout, args, Wk)
-        layouts[res["layout"]] = res
-        torch.cuda.empty_cache()
-    best = layouts["feature-major"]
+    for layout, name in ((H.LAYOUT_FEATURES, "feature-major"), (H.LAYOUT_ROWS, "row-major")):
+        if args.layout in ("both", name):
+            layouts[name] = bench_layout(torch, H, T, ctx, keys, X, y, coef, layout, args, Wk)
+            torch.cuda.empty_cache()
+    best = layouts.get("feature-major") or layouts["row-major"]
 
     copy_gbs, ntt = measure_copy_and_ntt(torch, ctx, ev, nb)
     t_fwd, t_inv, nlimb, alg_bytes = ntt["t_fwd"], ntt["t_inv"], ntt["nlimb"], ntt["alg_bytes"]
@@ -258,9 +260,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "image-shard 6000x196, N=2^16, 20+4 primes, dnum 5, scale 2^40, 47 blocks; "
                                "training schedule: steps at levels 19/15/11/7, refresh every 4 steps; "
-                               "feature-major packing; batched form replayed from HIP graphs",
+                               "%s packing; batched form replayed from HIP graphs" % best["layout"],
                    "n": n, "d": int(X.shape[1]), "blocks": nb, "log_n": Wk["logN"], "n_q": Wk["nq"],
-                   "n_special": Wk["nk"], "refresh_every": REFRESH_EVERY, "layout": "feature-major"},
+                   "n_special": Wk["nk"], "refresh_every": REFRESH_EVERY, "layout": best["layout"]},
         "plain_steps_per_s": best["steps_per_s_plain"],
         "batched_nograph_steps_per_s": best["steps_per_s_batched"],
         "batched_over_plain": best["batched_over_plain"],
@@ -281,8 +283,8 @@ def main():
 
 def cpu_baseline(Wk, threads, nb, c, r):
     """The oracle on a bounded sample of the feature-major schedule: one
-    mul+relin+rescale and one rotation at levels 3, 11 and 19, the cost at
-    other levels interpolated linearly in the level, extrapolated by the
+    mul+relin+rescale and one rotation at every level the schedule's key
+    switches run at (the median of two runs each), extrapolated by the
     schedule's key-switch counts (rescales of plain products, additions and
     the refresh are left out, so the CPU rate is an upper bound)."""
     if threads:
@@ -308,39 +310,36 @@ def cpu_baseline(Wk, threads, nb, c, r):
         return O.CT(np.stack([synth.uniform_residues(seed, P.q[: level + 1], P.N),
                               synth.uniform_residues(seed + 1, P.q[: level + 1], P.N)]), level, 1.0)
 
-    def t_mul(level):
-        x, z = ct(level, 1), ct(level, 3)
-        t = time.time()
-        O.rescale(P, O.mul(P, x, z, keys))
-        return time.time() - t
-
-    def t_rot(level):
-        x = ct(level, 5)
-        t = time.time()
-        O.rotate(P, x, 1, keys)
-        return time.time() - t
-
-    pts = (3, 11, 19)
-    sample = {}
-    for lv in pts:
-        sample["mul%d" % lv] = t_mul(lv)
-        sample["rot%d" % lv] = t_rot(lv)
-
-    def cost(kind, lv):
-        return float(np.interp(lv, pts, [sample["%s%d" % (kind, p)] for p in pts]))
+    def timed(fn, *a):
+        ts = []
+        for _ in range(2):
+            t = time.time()
+            fn(*a)
+            ts.append(time.time() - t)
+        return float(np.median(ts))
 
     lc, lr = int(np.log2(c)), int(np.log2(r))
     levels = [P.L - 4 * k for k in range(REFRESH_EVERY)]
+    need_mul = sorted({l - k for l in levels for k in (0, 1, 2)})
+    need_rot = sorted({l - k for l in levels for k in (1, 3, 4)})
+    sample = {}
+    for lv in need_mul:
+        x, z = ct(lv, 1), ct(lv, 3)
+        sample["mul%d" % lv] = timed(lambda: O.rescale(P, O.mul(P, x, z, keys)))
+    for lv in need_rot:
+        x = ct(lv, 5)
+        sample["rot%d" % lv] = timed(lambda: O.rotate(P, x, 1, keys))
     t_sched = 0.0
     for l in levels:  # the feature-major step at level l
-        t_sched += nb * (cost("mul", l) + lc * cost("rot", l - 1) + 3 * cost("mul", l - 1) + cost("mul", l - 2))
-        t_sched += lr * cost("rot", l - 3) + lr * cost("rot", l - 4)
+        t_sched += nb * (sample["mul%d" % l] + lc * sample["rot%d" % (l - 1)] + 3 * sample["mul%d" % (l - 1)] +
+                         sample["mul%d" % (l - 2)])
+        t_sched += lr * sample["rot%d" % (l - 3)] + lr * sample["rot%d" % (l - 4)]
     t_step = t_sched / len(levels)
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": nthreads, "kind": "oracle",
-            "sample": "one oracle mul+relin+rescale and one rotation at levels 3, 11 and 19 (%.1fs; keys %.1fs), "
-                      "interpolated in the level and extrapolated by the feature-major schedule's key-switch counts "
-                      "(steps at levels %s: %d blocks x (1+%d+3+1) + 2x%d per step)" % (
-                          sum(sample.values()), t_keys, "/".join(map(str, levels)), nb, lc, lr),
+            "sample": "one oracle mul+relin+rescale and one rotation at each level the feature-major schedule "
+                      "key-switches at (median of 2 runs; %.1fs of sampled work, keys %.1fs), extrapolated by the "
+                      "schedule's key-switch counts (steps at levels %s: %d blocks x (1+%d+3+1) + 2x%d per step)" % (
+                          2 * sum(sample.values()), t_keys, "/".join(map(str, levels)), nb, lc, lr),
             "extrapolated": True, "sample_seconds": sample}
 
 
