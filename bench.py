@@ -142,6 +142,30 @@ def measure_copy_and_ntt(torch, ctx, ev, nb):
     return copy_gbs, dict(t_fwd=t_fwd, t_inv=t_inv, nlimb=nlimb, alg_bytes=alg_bytes)
 
 
+def ntt_sweep(torch, H, ev):
+    """Forward / inverse NTT over B limbs of a 20 + 4 prime chain (limb i on
+    prime i mod 24), each N and B timed with HIP events; algorithmic GB/s =
+    16 N B / time."""
+    out = []
+    for log_n in (13, 14, 15, 16):
+        ctx = H.Context(log_n, 20, 4, 4, 40)
+        N = ctx.N
+        for B in (1, 24, 48, 768):
+            per = 1 if B == 1 else 24  # limb i uses prime i mod 24 (all 20 + 4 primes)
+            buf = torch.randint(0, 1 << 40, (B * N,), dtype=torch.int64, device="cuda")
+            ctx.ntt(buf, B, 0, per, +1)
+            ctx.ntt(buf, B, 0, per, -1)
+            reps = 20 if B * N <= (1 << 22) else 5
+            t_f = ev.time(lambda: ctx.ntt(buf, B, 0, per, +1), reps)
+            t_i = ev.time(lambda: ctx.ntt(buf, B, 0, per, -1), reps)
+            out.append({"log_n": log_n, "limbs": B, "fwd_us": t_f * 1e6, "inv_us": t_i * 1e6,
+                        "fwd_gbs": 16.0 * N * B / t_f / 1e9, "inv_gbs": 16.0 * N * B / t_i / 1e9})
+            del buf
+        del ctx
+    log("NTT sweep: " + ", ".join("2^%d x %d: %.0f GB/s" % (o["log_n"], o["limbs"], o["fwd_gbs"]) for o in out))
+    return out
+
+
 def bench_layout(torch, H, T, ctx, keys, X, y, coef, layout, args, Wk):
     """Parity of the top-level step (plain == batched == graph, bit for bit;
     decrypted g against FP64), then the top-level step time and the schedule
@@ -244,6 +268,7 @@ def main():
     copy_gbs, ntt = measure_copy_and_ntt(torch, ctx, ev, nb)
     t_fwd, t_inv, nlimb, alg_bytes = ntt["t_fwd"], ntt["t_inv"], ntt["nlimb"], ntt["alg_bytes"]
     ntt_gbs = alg_bytes / t_fwd / 1e9
+    sweep = ntt_sweep(torch, H, ev)
 
     out = {
         "metric": "encrypted LR grad steps/s at N=2^16 (batched vs plain) + NTT HBM GB/s",
@@ -270,6 +295,7 @@ def main():
         "layouts": layouts,
         "ntt_fwd_gbs_algorithmic": ntt_gbs,
         "ntt_inv_gbs_algorithmic": alg_bytes / t_inv / 1e9,
+        "ntt_sweep": sweep,
         "hbm_copy_gbs": copy_gbs,
         "ntt_fwd_frac_of_copy": ntt_gbs / copy_gbs,
         "roofline": {"bound": "hbm", "achieved": ntt_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -265,6 +265,27 @@ he_status he_lr_grad_step(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct
                           double w_decay, int c, int r, int layout, const he_keys *keys, int mode,
                           he_ct *W_out, he_ct *G_out);
 
+/* ---------------------------------------------------------------- batched operations */
+
+/*
+ * Batched multiply -> relinearise -> rescale -> rotate over n independent
+ * ciphertext pairs of one context, at any mix of levels 1..L (the ciphertext
+ * products, key switches and rescalings of Sec. 3 that the step is made of,
+ * as a standalone batch):
+ *   out[i] = Rot(RS(relin(x[i] (x) y[i])), steps[i])   at level(x[i]) - 1,
+ *   out[i].scale = x[i].scale * y[i].scale / q_level.
+ * x[i], y[i]: device ciphertexts of one level each (any addresses); out[i]:
+ * caller memory holding a ciphertext at level(x[i]) - 1, distinct from every
+ * input.  Entries of one level run together, up to 32 per launch, each with
+ * its own rotation key; keys needs the relinearisation key and every step.
+ * mode 0: one entry at a time; 1: grouped by level; 2: grouped, captured
+ * into a HIP graph on first use for these buffers and replayed.  All modes
+ * give bit-identical outputs.  Errors (before any launch): HE_EINVAL,
+ * HE_ELEVEL (level 0 or x/y levels differ), HE_EKEY (a rotation key absent).
+ */
+he_status he_batch_mul_rotate(he_ctx *ctx, const he_ct *x, const he_ct *y, const int *steps, int n,
+                              const he_keys *keys, int mode, he_ct *out);
+
 /* ---------------------------------------------------------------- NTT (measurement) */
 
 /* Forward (dir=+1) or inverse (dir=-1) NTT in place over n_limbs consecutive

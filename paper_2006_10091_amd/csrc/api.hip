@@ -6,6 +6,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <map>
 #include <sstream>
 
 #include "he_internal.h"
@@ -76,7 +77,8 @@ he_status last_error()
 // Key switch of d2 (B entries, NTT, limbs 0..l, batch stride d2s) with key;
 // out = base + KS(d2) on the first nbase components.
 he_status ks_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d2, long long d2s, const u64 *key,
-                   const u64 *base, long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs)
+                   const u64 *base, long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs,
+                   const hek::EntryKeys *keys = nullptr)
 {
     const size_t N = c->N;
     const int nb = l + 1 + c->nk, beta = beta_at(c, l);
@@ -96,7 +98,10 @@ he_status ks_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d2, long long 
         // slower fused), then the forward NTT of the extended digits
         hek::modup_b(c, l, B, y, ys, ext, es, ds);
         hek::ntt_batch(c, ext, es, ds, B, beta, 0, nb, l, +1, nullptr, true);
-        hek::ks_inner_b(c, l, B, d2, d2s, ext, es, ds, key, acc, as);
+        if (keys)
+            hek::ks_inner_multi_b(c, l, B, d2, d2s, ext, es, ds, *keys, acc, as);
+        else
+            hek::ks_inner_b(c, l, B, d2, d2s, ext, es, ds, key, acc, as);
         // special-prime limbs to coefficient form, scaled by N^{-1} [phat_p^{-1}]_p
         hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
         // ModDown conversion inside the first pass, base + (acc - conv) P^{-1} stored by the second
@@ -106,7 +111,10 @@ he_status ks_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d2, long long 
         hek::ntt_batch(c, y, ys, 0, B, 1, 0, l + 1, l, -1, up_post, false);
         hek::modup_b(c, l, B, y, ys, ext, es, ds);
         hek::ntt_batch(c, ext, es, ds, B, beta, 0, nb, l, +1, nullptr, true);
-        hek::ks_inner_b(c, l, B, d2, d2s, ext, es, ds, key, acc, as);
+        if (keys)
+            hek::ks_inner_multi_b(c, l, B, d2, d2s, ext, es, ds, *keys, acc, as);
+        else
+            hek::ks_inner_b(c, l, B, d2, d2s, ext, es, ds, key, acc, as);
         hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
         hek::moddown_conv_b(c, l, B, acc, as, conv, cs);
         hek::ntt_batch(c, conv, cs, (long long)(l + 1) * N, B, 2, 0, l + 1, l, +1, nullptr, false);
@@ -154,6 +162,22 @@ he_status rotate_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long l
     if (!rot) return HE_ENOMEM;
     hek::automorph_b(c, B, l + 1, in, is, lc, rot, 2 * lc, lc, g);
     he_status st = ks_apply(c, ar, l, B, rot + lc, 2 * lc, key, rot, 2 * lc, lc, 1, out, os, lc);
+    ar.off = mark;
+    return st;
+}
+
+// rotate B <= HE_MAXMULTI ciphertexts at level l, entry b by Galois element
+// gals.g[b] with key keys.k[b]
+he_status rotate_multi_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long long is,
+                             const hek::EntryGal &gals, const hek::EntryKeys &keys, u64 *out, long long os)
+{
+    const size_t N = c->N;
+    const size_t mark = ar.off;
+    const long long lc = (long long)(l + 1) * N;
+    u64 *rot = ar.take((size_t)B * 2 * lc);
+    if (!rot) return HE_ENOMEM;
+    hek::automorph_multi_b(c, B, l + 1, in, is, lc, rot, 2 * lc, lc, gals);
+    he_status st = ks_apply(c, ar, l, B, rot + lc, 2 * lc, nullptr, rot, 2 * lc, lc, 1, out, os, lc, &keys);
     ar.off = mark;
     return st;
 }
@@ -546,6 +570,99 @@ he_status rotate_sum(he_ctx *c, Arena &ar, int level, u64 *x, u64 *tmp, long lon
         hek::ewise(c, 0, level, 1, 2, x, 2 * x1, x1, tmp, 2 * x1, x1, x, 2 * x1, x1, 0);
     }
     return HE_OK;
+}
+
+// Run `body` captured into a HIP graph on first use of `key` and replayed
+// after that, on the context's private stream ordered after and before the
+// caller's stream by events.  Buffers must not move between replays (the key
+// names every pointer the body uses, the workspace included).
+template <class F>
+he_status run_graph(he_ctx *c, const std::string &key, F body)
+{
+    if (!c->gstream) {
+        HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    }
+    GraphEntry &ge = c->graphs[key];
+    hipStream_t user = c->stream;
+    HIPCHK(hipEventRecord(c->ev_in, user));
+    HIPCHK(hipStreamWaitEvent(c->gstream, c->ev_in, 0));
+    if (!ge.exec) {
+        c->stream = c->gstream;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess) {
+            c->stream = user;
+            c->graphs.erase(key);
+            return HE_EDEVICE;
+        }
+        c->capturing = true;
+        he_status st = body();
+        c->capturing = false;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(c->stream, &g);
+        c->stream = user;
+        if (st != HE_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            c->graphs.erase(key);
+            return st != HE_OK ? st : HE_EDEVICE;
+        }
+        ge.graph = g;
+        if (hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            c->graphs.erase(key);
+            return HE_EDEVICE;
+        }
+    }
+    HIPCHK(hipGraphLaunch(ge.exec, c->gstream));
+    HIPCHK(hipEventRecord(c->ev_out, c->gstream));
+    HIPCHK(hipStreamWaitEvent(user, c->ev_out, 0));
+    return HE_OK;
+}
+
+// ------------------------------------------------------------------ batched mul -> relin -> rescale -> rotate
+// Entries of one level run together, up to HE_MAXMULTI per launch, each with
+// its own rotation key; inputs are read in place, outputs staged and copied.
+size_t batch_bytes(const he_ctx *c, int l, int B)
+{
+    const size_t N = c->N;
+    size_t n = al((size_t)B * 3 * (l + 1) * N) + al((size_t)B * 2 * (l + 1) * N) + 2 * al((size_t)B * 2 * l * N);
+    n += std::max(ks_scratch(c, l, B), std::max(rescale_scratch(c, l, B), rotate_scratch(c, l - 1, B)));
+    return n * 8 + 4096;
+}
+
+he_status batch_impl(he_ctx *c, const he_ct *x, const he_ct *y, const u64 *gal, const he_keys *k, int chunk,
+                     const std::map<int, std::vector<int>> &groups, he_ct *out)
+{
+    const long long N = c->N;
+    for (const auto &gr : groups) {
+        const int l = gr.first;
+        const std::vector<int> &idx = gr.second;
+        const long long lc = (long long)(l + 1) * N, rc = (long long)l * N;
+        for (size_t s0 = 0; s0 < idx.size(); s0 += chunk) {
+            const int B = (int)std::min<size_t>(chunk, idx.size() - s0);
+            Arena ar = arena(c);
+            u64 *T3 = ar.take((size_t)B * 3 * lc);
+            u64 *U0 = ar.take((size_t)B * 2 * lc);
+            u64 *R = ar.take((size_t)B * 2 * rc);
+            u64 *Ob = ar.take((size_t)B * 2 * rc);
+            if (!T3 || !U0 || !R || !Ob) return HE_ENOMEM;
+            hek::EntryKeys keys;
+            hek::EntryGal gals;
+            for (int b = 0; b < B; ++b) {
+                const int i = idx[s0 + b];
+                hek::tensor_b(c, l, 1, x[i].data, 0, lc, y[i].data, 0, lc, T3 + b * 3 * lc, 3 * lc, lc);
+                keys.k[b] = find_rot_key(k, gal[i]);
+                gals.g[b] = gal[i];
+            }
+            TRY(relin_apply(c, ar, l, B, T3, 3 * lc, k->rlk, U0, 2 * lc));
+            TRY(rescale_apply(c, ar, l, B, U0, 2 * lc, R, 2 * rc));
+            TRY(rotate_multi_apply(c, ar, l - 1, B, R, 2 * rc, gals, keys, Ob, 2 * rc));
+            for (int b = 0; b < B; ++b)
+                hek::ewise(c, 4, l - 1, 1, 2, Ob + b * 2 * rc, 0, rc, nullptr, 0, 0, out[idx[s0 + b]].data, 0, rc, 0);
+        }
+    }
+    return last_error();
 }
 
 // the whole step; nchunk = 1 (plain: per-block operations) or n_blocks (batched)
@@ -1066,51 +1183,14 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
     const int chunk = mode == 0 ? 1 : n_blocks;
     TRY(ensure_ws(c, step_bytes(c, l, chunk, layout)));
     if (mode == 2) {
-        // capture and replay on a private stream ordered after / before the caller's
-        if (!c->gstream) {
-            HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
-        }
         std::ostringstream key;
-        key << (const void *)Z[0].data << ':' << zbs << ':' << n_blocks << ':' << lz << ':' << (const void *)W->data
-            << ':' << l << ':' << (const void *)mask->data << ':' << cols << ':' << (const void *)k << ':'
-            << (const void *)W_out->data << ':' << (const void *)(G_out ? G_out->data : nullptr) << ':' << pl.k0
-            << ':' << pl.k1 << ':' << pl.k2 << ':' << pl.k3 << ':' << pl.kb1 << ':' << pl.kw << ':'
-            << (const void *)c->ws << ':' << layout;
-        GraphEntry &ge = c->graphs[key.str()];
-        hipStream_t user = c->stream;
-        HIPCHK(hipEventRecord(c->ev_in, user));
-        HIPCHK(hipStreamWaitEvent(c->gstream, c->ev_in, 0));
-        if (!ge.exec) {
-            c->stream = c->gstream;
-            hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
-            if (e != hipSuccess) {
-                c->stream = user;
-                c->graphs.erase(key.str());
-                return HE_EDEVICE;
-            }
-            c->capturing = true;
-            he_status st = step_impl(c, pl, Z, n_blocks, zbs, W, mask, cols, rows, k, chunk, W_out, G_out);
-            c->capturing = false;
-            hipGraph_t g = nullptr;
-            e = hipStreamEndCapture(c->stream, &g);
-            c->stream = user;
-            if (st != HE_OK || e != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                c->graphs.erase(key.str());
-                return st != HE_OK ? st : HE_EDEVICE;
-            }
-            ge.graph = g;
-            if (hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0) != hipSuccess) {
-                (void)hipGraphDestroy(g);
-                c->graphs.erase(key.str());
-                return HE_EDEVICE;
-            }
-        }
-        HIPCHK(hipGraphLaunch(ge.exec, c->gstream));
-        HIPCHK(hipEventRecord(c->ev_out, c->gstream));
-        HIPCHK(hipStreamWaitEvent(user, c->ev_out, 0));
+        key << "step:" << (const void *)Z[0].data << ':' << zbs << ':' << n_blocks << ':' << lz << ':'
+            << (const void *)W->data << ':' << l << ':' << (const void *)mask->data << ':' << cols << ':'
+            << (const void *)k << ':' << (const void *)W_out->data << ':'
+            << (const void *)(G_out ? G_out->data : nullptr) << ':' << pl.k0 << ':' << pl.k1 << ':' << pl.k2 << ':'
+            << pl.k3 << ':' << pl.kb1 << ':' << pl.kw << ':' << (const void *)c->ws << ':' << layout;
+        TRY(run_graph(c, key.str(),
+                      [&] { return step_impl(c, pl, Z, n_blocks, zbs, W, mask, cols, rows, k, chunk, W_out, G_out); }));
     } else {
         TRY(step_impl(c, pl, Z, n_blocks, zbs, W, mask, cols, rows, k, chunk, W_out, G_out));
     }
@@ -1119,6 +1199,40 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
     if (G_out) {
         G_out->level = l - 4;
         G_out->scale = pl.s_g;
+    }
+    return last_error();
+}
+
+he_status he_batch_mul_rotate(he_ctx *c, const he_ct *x, const he_ct *y, const int *steps, int n, const he_keys *k,
+                              int mode, he_ct *out)
+{
+    if (!c || !x || !y || !steps || !k || !out || n < 1 || mode < 0 || mode > 2) return HE_EINVAL;
+    std::vector<u64> gal(n);
+    std::map<int, std::vector<int>> groups;
+    for (int i = 0; i < n; ++i) {
+        if (!ct_ok(c, &x[i]) || !ct_ok(c, &y[i]) || !out[i].data) return HE_EINVAL;
+        if (x[i].level != y[i].level || x[i].level < 1) return HE_ELEVEL;
+        gal[i] = galois_of(c, steps[i]);
+        if (!find_rot_key(k, gal[i])) return HE_EKEY;
+        groups[x[i].level].push_back(i);
+    }
+    const int chunk = mode == 0 ? 1 : hek::HE_MAXMULTI;
+    size_t need = 0;
+    for (const auto &g : groups) need = std::max(need, batch_bytes(c, g.first, std::min(chunk, (int)g.second.size())));
+    TRY(ensure_ws(c, need));
+    if (mode == 2) {
+        std::ostringstream key;
+        key << "batch:" << n << ':' << (const void *)k << ':' << (const void *)c->ws;
+        for (int i = 0; i < n; ++i)
+            key << ':' << (const void *)x[i].data << ',' << (const void *)y[i].data << ',' << (const void *)out[i].data
+                << ',' << x[i].level << ',' << gal[i];
+        TRY(run_graph(c, key.str(), [&] { return batch_impl(c, x, y, gal.data(), k, chunk, groups, out); }));
+    } else {
+        TRY(batch_impl(c, x, y, gal.data(), k, chunk, groups, out));
+    }
+    for (int i = 0; i < n; ++i) {
+        out[i].level = x[i].level - 1;
+        out[i].scale = x[i].scale * y[i].scale / (double)c->q[x[i].level];
     }
     return last_error();
 }

@@ -117,6 +117,19 @@ void modup_b(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, 
 // inner product with one key shared by the batch: acc [B][2][l+1+nk][N]
 void ks_inner_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const u64 *ext, long long es,
                 long long ds, const u64 *key, u64 *acc, long long as);
+// per-entry evaluation keys / Galois elements for a batch of up to HE_MAXMULTI
+// entries (passed by value as kernel arguments)
+constexpr int HE_MAXMULTI = 32;
+struct EntryKeys {
+    const u64 *k[HE_MAXMULTI];
+};
+struct EntryGal {
+    u64 g[HE_MAXMULTI];
+};
+void ks_inner_multi_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const u64 *ext, long long es,
+                      long long ds, const EntryKeys &keys, u64 *acc, long long as);
+void automorph_multi_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,
+                       long long oc, const EntryGal &gals);
 // ModDown conversion from the special primes: conv [B][2][l+1][N] (coefficient)
 void moddown_conv_b(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs);
 // out = base + (acc - conv) P^{-1} on the first nbase components (else no base)

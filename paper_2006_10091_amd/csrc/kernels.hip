@@ -815,6 +815,50 @@ __global__ __launch_bounds__(256) void ks_inner_kernel(const u64 *__restrict__ d
     }
 }
 
+// Inner product with a different evaluation key per entry (rotations by
+// different steps in one launch): entry b = blockIdx.z uses keys.k[b]; the key
+// is read once per entry (no reuse across entries to keep in registers).
+__global__ __launch_bounds__(256) void ks_inner_multi_kernel(const u64 *__restrict__ d2, long long d2s,
+                                                             const u64 *__restrict__ ext, long long es, long long ds,
+                                                             hek::EntryKeys keys, u64 *__restrict__ acc, long long as,
+                                                             const PrimeInfo *__restrict__ pinfo, int level,
+                                                             int alpha, int nq, int np, int beta, int logN)
+{
+    typedef __attribute__((ext_vector_type(2))) unsigned long long u64x2;
+    const int t = blockIdx.y;
+    const int b = blockIdx.z;
+    const int tp = prime_of(t, level, nq);
+    const PrimeInfo p = pinfo[tp];
+    const int N = 1 << logN;
+    const int nb = level + 1 + (np - nq);
+    const long long keylimb = (long long)np << logN;
+    const long long lt = (long long)t << logN;
+    const u64 *key = keys.k[b];
+    for (int x = 2 * (blockIdx.x * 256 + threadIdx.x); x < N; x += 2 * gridDim.x * 256) {
+        u64 s0a = 0, s1a = 0, s0b = 0, s1b = 0;
+        for (int j = 0; j < beta; ++j) {
+            const u64 *kj = key + (long long)j * 2 * keylimb + ((long long)tp << logN) + x;
+            const u64x2 kb = *reinterpret_cast<const u64x2 *>(kj);
+            const u64x2 ka = *reinterpret_cast<const u64x2 *>(kj + keylimb);
+            const int d0 = j * alpha, d1 = min(d0 + alpha, level + 1);
+            const u64 *src = (t >= d0 && t < d1) ? d2 + b * d2s + lt + x : ext + b * es + j * ds + lt + x;
+            const u64x2 X = *reinterpret_cast<const u64x2 *>(src);
+            s0a = add_mod(s0a, mul_mod(X.x, kb.x, p), p.q);
+            s1a = add_mod(s1a, mul_mod(X.x, ka.x, p), p.q);
+            s0b = add_mod(s0b, mul_mod(X.y, kb.y, p), p.q);
+            s1b = add_mod(s1b, mul_mod(X.y, ka.y, p), p.q);
+        }
+        u64 *o = acc + b * as + lt + x;
+        u64x2 r0, r1;
+        r0.x = s0a;
+        r0.y = s0b;
+        r1.x = s1a;
+        r1.y = s1b;
+        *reinterpret_cast<u64x2 *>(o) = r0;
+        *reinterpret_cast<u64x2 *>(o + ((long long)nb << logN)) = r1;
+    }
+}
+
 // ModDown conversion: acc[b][comp] positions level+1.. hold scaled iNTT
 // outputs y_p (coefficient); conv[b][comp][i] = sum_p y~_p (phat_p mod q_i).
 // A thread reads the k special residues of one coefficient once.
@@ -937,6 +981,26 @@ __global__ __launch_bounds__(256) void automorph_kernel(const u64 *__restrict__ 
     const int b = blockIdx.z >> 1, c = blockIdx.z & 1;
     const int N = 1 << logN;
     const u64 mask2n = 2 * (u64)N - 1;
+    const u64 *src = in + b * ib + c * ic + ((long long)limb << logN);
+    u64 *dst = out + b * ob + c * oc + ((long long)limb << logN);
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < N; k += gridDim.x * 256) {
+        u64 e = 2 * (u64)brev_n(k, logN) + 1;
+        u64 e2 = (e * g) & mask2n;
+        unsigned k2 = brev_n((unsigned)((e2 - 1) >> 1), logN);
+        dst[k] = src[k2];
+    }
+}
+
+// automorph_kernel with a Galois element per entry b (blockIdx.z = 2 b + c)
+__global__ __launch_bounds__(256) void automorph_multi_kernel(const u64 *__restrict__ in, long long ib, long long ic,
+                                                              u64 *__restrict__ out, long long ob, long long oc,
+                                                              hek::EntryGal gals, int logN)
+{
+    const int limb = blockIdx.y;
+    const int b = blockIdx.z >> 1, c = blockIdx.z & 1;
+    const int N = 1 << logN;
+    const u64 mask2n = 2 * (u64)N - 1;
+    const u64 g = gals.g[b];
     const u64 *src = in + b * ib + c * ic + ((long long)limb << logN);
     u64 *dst = out + b * ob + c * oc + ((long long)limb << logN);
     for (int k = blockIdx.x * 256 + threadIdx.x; k < N; k += gridDim.x * 256) {
@@ -1336,6 +1400,15 @@ void ks_inner_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const
                                               c->nq, c->np, beta, c->logN);
 }
 
+void ks_inner_multi_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const u64 *ext, long long es,
+                      long long ds, const EntryKeys &keys, u64 *acc, long long as)
+{
+    const int beta = (level + 1 + c->alpha - 1) / c->alpha;
+    dim3 g(xblocks(c->N, 2), level + 1 + c->nk, B);
+    ks_inner_multi_kernel<<<g, 256, 0, c->stream>>>(d2, d2s, ext, es, ds, keys, acc, as, c->t.pinfo, level,
+                                                    c->alpha, c->nq, c->np, beta, c->logN);
+}
+
 void moddown_conv_b(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs)
 {
     dim3 g((c->N + 255) / 256, B * 2, 1);
@@ -1371,6 +1444,13 @@ void automorph_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long lon
 {
     dim3 gr(xblocks(c->N), nl, B * 2);
     automorph_kernel<<<gr, 256, 0, c->stream>>>(in, ib, ic, out, ob, oc, g, c->logN);
+}
+
+void automorph_multi_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,
+                       long long oc, const EntryGal &gals)
+{
+    dim3 gr(xblocks(c->N), nl, B * 2);
+    automorph_multi_kernel<<<gr, 256, 0, c->stream>>>(in, ib, ic, out, ob, oc, gals, c->logN);
 }
 
 void batch_sum(he_ctx *c, int level, int B, const u64 *in, long long ib, long long ic, u64 *out, long long oc,

@@ -93,6 +93,8 @@ _sig = {
                                 c_int, _P(he_lr_plan)]),
     "he_lr_grad_step": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), _P(he_pt), _P(c_double), c_double, c_double,
                                 c_int, c_int, c_int, c_void_p, c_int, _P(he_ct), _P(he_ct)]),
+    "he_batch_mul_rotate": (c_int, [c_void_p, _P(he_ct), _P(he_ct), _P(c_int32), c_int, c_void_p, c_int,
+                                    _P(he_ct)]),
     "he_ntt": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
 }
 for _n, (_r, _a) in _sig.items():
@@ -370,6 +372,20 @@ class Context:
         if want_g:
             G_out.update(go)
         return W_out, (G_out if want_g else None)
+
+    def batch_mul_rotate(self, xs, ys, steps, keys, mode=1, outs=None):
+        """he_batch_mul_rotate: out[i] = Rot(RS(relin(x[i] (x) y[i])), steps[i])."""
+        n = len(xs)
+        outs = outs or [self.ct_empty(x.level - 1) for x in xs]
+        xa = (he_ct * n)(*[x.struct() for x in xs])
+        ya = (he_ct * n)(*[y.struct() for y in ys])
+        oa = (he_ct * n)(*[o.struct() for o in outs])
+        st = np.ascontiguousarray(steps, dtype=np.int32)
+        _chk(_lib.he_batch_mul_rotate(self.h, xa, ya, st.ctypes.data_as(POINTER(c_int32)), n, keys.handle, mode, oa),
+             "he_batch_mul_rotate")
+        for o, s_ in zip(outs, oa):
+            o.update(s_)
+        return outs
 
     def ntt(self, tensor, n_limbs, prime_idx0, period, direction):
         _chk(_lib.he_ntt(self.h, c_void_p(tensor.data_ptr()), n_limbs, prime_idx0, period, direction), "he_ntt")

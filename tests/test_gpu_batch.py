@@ -1,0 +1,99 @@
+"""Batched operations of mixed ring degree and level (he_batch_mul_rotate):
+
+* a mixed batch over N = 2^14 and 2^15, levels 1..20, with several entries per
+  level (more than one launch group at some levels): the plain, grouped and
+  graph-replayed forms agree bit for bit, and sampled entries equal the
+  oracle's multiply -> relinearise -> rescale -> rotate bit for bit;
+* the 256-operation mixed workload over N in {2^14, 2^15, 2^16}: all forms
+  agree bit for bit, the graph replays agree with the first run, and one
+  entry per N is checked against the oracle;
+* errors are reported before any launch.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import ckks as O  # noqa: E402
+from paper_2006_10091_amd import batch_ops as BO  # noqa: E402
+from paper_2006_10091_amd import he as H  # noqa: E402
+from paper_2006_10091_amd import synth  # noqa: E402
+
+
+def _oracle_entry(b, i, okeys_cache):
+    """The oracle's result for entry i of Batch b, from the same residues."""
+    log_n, level, step = b.ops[i]
+    P = okeys_cache.setdefault(("P", log_n), O.Params(log_n, BO.CHAIN["n_q"], BO.CHAIN["n_special"],
+                                                      BO.CHAIN["alpha"], BO.CHAIN["log_delta"]))
+    key = ("K", log_n, step)
+    if key not in okeys_cache:
+        okeys_cache[key] = O.Keys(P, 2003 + log_n, rot_steps=[step])
+    ok = okeys_cache[key]
+    j = b.idx[log_n].index(i)
+    ctx = b.ctx[log_n]
+    x = O.CT(ctx.download(b.x[log_n][j]), level, 1.0)
+    y = O.CT(ctx.download(b.y[log_n][j]), level, 1.0)
+    return O.rotate(P, O.rescale(P, O.mul(P, x, y, ok)), step, ok).data
+
+
+def test_mixed_batch_small_rings_forms_and_oracle():
+    g = synth.rng(77)
+    ops = []
+    for level in list(range(1, 21)) + [7] * 40:  # 41 entries at level 7: two launch groups
+        log_n = int(g.choice([14, 15]))
+        ops.append((log_n, level, 1 << int(g.integers(0, log_n - 1))))
+    b = BO.Batch(ops, seed=911)
+    outs = {}
+    for mode in (0, 1, 2, 2):
+        b.run(mode)
+        outs.setdefault(mode, []).append(b.outputs())
+    ref = outs[0][0]
+    for mode in (1, 2):
+        for run in outs[mode]:
+            assert all(np.array_equal(a, r) for a, r in zip(run, ref)), mode
+    for log_n, lst in b.out.items():
+        for i, o in zip(b.idx[log_n], lst):
+            assert o.level == ops[i][1] - 1
+    cache = {}
+    for i in (0, 5, 19, 20, 59):
+        assert np.array_equal(ref[i], _oracle_entry(b, i, cache)), i
+
+
+def test_c3_workload_forms_agree_and_sampled_oracle():
+    ops = BO.draw_ops(256)
+    assert {o[0] for o in ops} == {14, 15, 16} and min(o[1] for o in ops) >= 3 and max(o[1] for o in ops) <= 20
+    b = BO.Batch(ops)
+    b.run(0)
+    ref = b.outputs()
+    for mode in (1, 2, 2):
+        b.run(mode)
+        got = b.outputs()
+        assert all(np.array_equal(a, r) for a, r in zip(got, ref)), mode
+    cache = {}
+    for log_n in (14, 15, 16):
+        i = b.idx[log_n][0]
+        assert np.array_equal(ref[i], _oracle_entry(b, i, cache)), (log_n, i)
+
+
+def test_batch_errors():
+    ctx = H.Context(14, 6, 2, 2, 40)
+    keys = ctx.keygen(5, [1])
+    q = ctx.primes
+    def ct(level, s):
+        d = np.stack([synth.uniform_residues(s, q[: level + 1], ctx.N), synth.uniform_residues(s + 1, q[: level + 1],
+                                                                                             ctx.N)])
+        return ctx.upload(d, level, 1.0)
+    a3, b3, a2, a0, b0 = ct(3, 1), ct(3, 3), ct(2, 5), ct(0, 7), ct(0, 9)
+    with pytest.raises(H.HEError) as e:
+        ctx.batch_mul_rotate([a3], [a2], [1], keys)
+    assert e.value.status == 3  # levels differ
+    with pytest.raises(H.HEError) as e:
+        ctx.batch_mul_rotate([a0], [b0], [1], keys, outs=[ctx.ct_empty(0)])
+    assert e.value.status == 3  # level 0 cannot be rescaled
+    with pytest.raises(H.HEError) as e:
+        ctx.batch_mul_rotate([a3], [b3], [2], keys)
+    assert e.value.status == 5  # no key for step 2
+    with pytest.raises(H.HEError) as e:
+        ctx.batch_mul_rotate([a3], [b3], [1], keys, mode=3)
+    assert e.value.status == 1
