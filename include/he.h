@@ -265,6 +265,27 @@ he_status he_lr_grad_step(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct
                           double w_decay, int c, int r, int layout, const he_keys *keys, int mode,
                           he_ct *W_out, he_ct *G_out);
 
+/*
+ * Encrypted inference on one worker's blocks: the margins m_i = w.x_i of
+ * eq. (appr) (the first half of the step, for scoring data with the current
+ * weights).  Per block: u = RS(relin(Z_b (x) W)), then the margin sum -- row
+ * major: rotations 1, 2, .., c/2 (m_i at slot i*c); feature major: rotations
+ * r, 2r, .., (c/2) r (m_i at every slot j*r + i).  Z, W, c, r, layout as for
+ * he_lr_grad_step (W at any level >= 1, Z at a level >= W's); out[0..n_blocks)
+ * caller memory for ciphertexts at W's level - 1, one uniform stride apart;
+ * scale Z.scale * W.scale / q_level.  mode 0 / 1 / 2 as for he_lr_grad_step
+ * (bit-identical).  Errors before any launch: HE_EINVAL, HE_ELEVEL, HE_EKEY.
+ */
+he_status he_lr_margins(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct *W, int c, int r, int layout,
+                        const he_keys *keys, int mode, he_ct *out);
+
+/* Device workspace (bytes) that he_lr_grad_step / he_lr_margins take for
+ * n_blocks blocks with weights at `level` in `mode` (the context keeps and
+ * grows one workspace; callers doing admission control budget with this).
+ * 0 for invalid arguments. */
+size_t he_lr_step_bytes(const he_ctx *ctx, int level, int n_blocks, int layout, int mode);
+size_t he_lr_margins_bytes(const he_ctx *ctx, int level, int n_blocks, int mode);
+
 /* ---------------------------------------------------------------- batched operations */
 
 /*

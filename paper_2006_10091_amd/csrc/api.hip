@@ -665,6 +665,45 @@ he_status batch_impl(he_ctx *c, const he_ct *x, const he_ct *y, const u64 *gal, 
     return last_error();
 }
 
+// ------------------------------------------------------------------ encrypted inference (margins)
+size_t margins_bytes(const he_ctx *c, int l, int nb)
+{
+    const size_t N = c->N;
+    size_t n = al((size_t)nb * 3 * (l + 1) * N) + al((size_t)nb * 2 * (l + 1) * N) + al((size_t)nb * 2 * l * N);
+    n += std::max(ks_scratch(c, l, nb), std::max(rescale_scratch(c, l, nb), rotate_scratch(c, l - 1, nb)));
+    return n * 8 + 4096;
+}
+
+// u = RS(relin(Z_b (x) W)) written straight into out (uniform batch stride
+// obs), then the margin sum in place: rotations by t * unit, t = 1 .. count/2
+he_status margins_impl(he_ctx *c, const he_ct *Z, int n_blocks, long long zbs, const he_ct *W, long long unit,
+                       int count, const he_keys *keys, int chunk, u64 *out, long long obs)
+{
+    const long long N = c->N;
+    const int l = W->level;
+    const long long zc = (long long)(Z[0].level + 1) * N, wc = (long long)(l + 1) * N, lc = wc, u1 = (long long)l * N;
+    for (int b0 = 0; b0 < n_blocks; b0 += chunk) {
+        const int nb = std::min(chunk, n_blocks - b0);
+        Arena ar = arena(c);
+        u64 *T3 = ar.take((size_t)nb * 3 * lc);
+        u64 *U0 = ar.take((size_t)nb * 2 * lc);
+        u64 *R = ar.take((size_t)nb * 2 * u1);
+        if (!T3 || !U0 || !R) return HE_ENOMEM;
+        u64 *u = out + b0 * obs;
+        hek::tensor_b(c, l, nb, Z[b0].data, chunk == 1 ? 0 : zbs, zc, W->data, 0, wc, T3, 3 * lc, lc);
+        TRY(relin_apply(c, ar, l, nb, T3, 3 * lc, keys->rlk, U0, 2 * lc));
+        TRY(rescale_apply(c, ar, l, nb, U0, 2 * lc, u, obs));
+        for (int t = 1; t < count; t <<= 1) {
+            const u64 gal = galois_of(c, (long long)t * unit);
+            const u64 *key = find_rot_key(keys, gal);
+            if (!key) return HE_EKEY;
+            TRY(rotate_apply(c, ar, l - 1, nb, u, obs, gal, key, R, 2 * u1));
+            hek::ewise(c, 0, l - 1, nb, 2, u, obs, u1, R, 2 * u1, u1, u, obs, u1, 0);
+        }
+    }
+    return last_error();
+}
+
 // the whole step; nchunk = 1 (plain: per-block operations) or n_blocks (batched)
 he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_blocks, long long zbs, const he_ct *W,
                     const he_pt *mask, int cols, int rows, const he_keys *keys, int chunk, he_ct *W_out,
@@ -1233,6 +1272,68 @@ he_status he_batch_mul_rotate(he_ctx *c, const he_ct *x, const he_ct *y, const i
     for (int i = 0; i < n; ++i) {
         out[i].level = x[i].level - 1;
         out[i].scale = x[i].scale * y[i].scale / (double)c->q[x[i].level];
+    }
+    return last_error();
+}
+
+size_t he_lr_step_bytes(const he_ctx *c, int level, int n_blocks, int layout, int mode)
+{
+    if (!c || level < 4 || level >= c->nq || n_blocks < 1 || (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES))
+        return 0;
+    return step_bytes(c, level, mode == 0 ? 1 : n_blocks, layout);
+}
+
+size_t he_lr_margins_bytes(const he_ctx *c, int level, int n_blocks, int mode)
+{
+    if (!c || level < 1 || level >= c->nq || n_blocks < 1) return 0;
+    return margins_bytes(c, level, mode == 0 ? 1 : n_blocks);
+}
+
+he_status he_lr_margins(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, int cols, int rows, int layout,
+                        const he_keys *k, int mode, he_ct *out)
+{
+    if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !k || !out || !out[0].data || mode < 0 || mode > 2)
+        return HE_EINVAL;
+    if (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES) return HE_EINVAL;
+    if (cols < 1 || rows < 1 || (cols & (cols - 1)) || (rows & (rows - 1)) || (long long)cols * rows != c->N / 2)
+        return HE_EINVAL;
+    const int l = W->level;
+    if (l < 1) return HE_ELEVEL;
+    const int lz = Z[0].level;
+    const double sz = Z[0].scale;
+    long long zbs = 0, obs = 0;
+    for (int b = 0; b < n_blocks; ++b) {
+        if (!ct_ok(c, &Z[b]) || Z[b].level != lz || Z[b].scale != sz) return Z[b].level != lz ? HE_ELEVEL : HE_EINVAL;
+        if (!out[b].data) return HE_EINVAL;
+        if (b == 1) {
+            zbs = Z[1].data - Z[0].data;
+            obs = out[1].data - out[0].data;
+        }
+        if (b > 1 && (Z[b].data - Z[b - 1].data != zbs || out[b].data - out[b - 1].data != obs)) return HE_EINVAL;
+    }
+    if (lz < l) return HE_ELEVEL;
+    if (n_blocks > 1 && (zbs < 2LL * (lz + 1) * c->N || obs < 2LL * l * c->N)) return HE_EINVAL;
+    const bool fm = layout == HE_LAYOUT_FEATURES;
+    const long long unit = fm ? rows : 1;
+    const int count = cols;
+    for (int t = 1; t < count; t <<= 1)
+        if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
+    const int chunk = mode == 0 ? 1 : n_blocks;
+    TRY(ensure_ws(c, margins_bytes(c, l, chunk)));
+    if (mode == 2) {
+        std::ostringstream key;
+        key << "margins:" << (const void *)Z[0].data << ':' << zbs << ':' << n_blocks << ':' << lz << ':'
+            << (const void *)W->data << ':' << l << ':' << cols << ':' << layout << ':' << (const void *)k << ':'
+            << (const void *)out[0].data << ':' << obs << ':' << (const void *)c->ws;
+        TRY(run_graph(c, key.str(),
+                      [&] { return margins_impl(c, Z, n_blocks, zbs, W, unit, count, k, chunk, out[0].data, obs); }));
+    } else {
+        TRY(margins_impl(c, Z, n_blocks, zbs, W, unit, count, k, chunk, out[0].data, obs));
+    }
+    const double so = sz * W->scale / (double)c->q[l];
+    for (int b = 0; b < n_blocks; ++b) {
+        out[b].level = l - 1;
+        out[b].scale = so;
     }
     return last_error();
 }

@@ -95,6 +95,10 @@ _sig = {
                                 c_int, c_int, c_int, c_void_p, c_int, _P(he_ct), _P(he_ct)]),
     "he_batch_mul_rotate": (c_int, [c_void_p, _P(he_ct), _P(he_ct), _P(c_int32), c_int, c_void_p, c_int,
                                     _P(he_ct)]),
+    "he_lr_margins": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), c_int, c_int, c_int, c_void_p, c_int,
+                              _P(he_ct)]),
+    "he_lr_step_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int, c_int]),
+    "he_lr_margins_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int]),
     "he_ntt": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
 }
 for _n, (_r, _a) in _sig.items():
@@ -372,6 +376,26 @@ class Context:
         if want_g:
             G_out.update(go)
         return W_out, (G_out if want_g else None)
+
+    def lr_margins(self, Z, W, cols, rows, keys, mode=1, out=None, layout=LAYOUT_ROWS):
+        """he_lr_margins: per block u = RS(relin(Z_b (x) W)) + the margin sum.
+        out: list of len(Z) ciphertexts at W.level - 1 with one stride
+        (ct_block); allocated when None."""
+        out = out or self.ct_block(len(Z), W.level - 1)
+        zs = (he_ct * len(Z))(*[z.struct() for z in Z])
+        os_ = (he_ct * len(out))(*[o.struct() for o in out])
+        w = W.struct()
+        _chk(_lib.he_lr_margins(self.h, zs, len(Z), ctypes.byref(w), cols, rows, layout, keys.handle, mode, os_),
+             "he_lr_margins")
+        for o, s_ in zip(out, os_):
+            o.update(s_)
+        return out
+
+    def step_bytes(self, level, n_blocks, layout=LAYOUT_ROWS, mode=1):
+        return int(_lib.he_lr_step_bytes(self.h, level, n_blocks, layout, mode))
+
+    def margins_bytes(self, level, n_blocks, mode=1):
+        return int(_lib.he_lr_margins_bytes(self.h, level, n_blocks, mode))
 
     def batch_mul_rotate(self, xs, ys, steps, keys, mode=1, outs=None):
         """he_batch_mul_rotate: out[i] = Rot(RS(relin(x[i] (x) y[i])), steps[i])."""

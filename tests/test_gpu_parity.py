@@ -401,3 +401,42 @@ def test_lr_step_feature_major_errors(small, small40):
     with pytest.raises(H.HEError) as e:
         ctx.lr_grad_step(Z, Wc, mask, coef, 1 / 256, c, r, rk, layout=H.LAYOUT_FEATURES)
     assert e.value.status == 5
+
+
+# ------------------------------------------------------------------ encrypted inference (margins)
+@pytest.mark.parametrize("layout", [0, 1])
+def test_margins_bit_exact_and_decrypt_to_inner_products(small, layout):
+    """he_lr_margins in its three forms against the oracle's product, rescale
+    and rotate-and-sum, bit for bit; the decrypted margins are w.z_i."""
+    ctx, P, H = small["ctx"], small["P"], small["H"]
+    X, y = synth.small_data(n=700)
+    blocks, c, r = (LR.pack_blocks_features if layout else LR.pack_blocks)(X, y, P.S)
+    w0 = synth.initial_weights("small", 16, 17)
+    oZ, gZ = [], ctx.ct_block(blocks.shape[0], P.L)
+    for i in range(blocks.shape[0]):
+        m = O.encode(blocks[i], P.delta, P.N)
+        oZ.append(O.encrypt_sk(P, small["okeys"], m, P.L, P.delta, 31, i))
+        ctx.encrypt(ctx.pt_load(m, P.L, P.delta), small["gkeys"], 31, i, out=gZ[i])
+    pw = LR.pack_weights_features(w0, P.S, c) if layout else LR.pack_weights(w0, P.S, c)
+    mw = O.encode(pw, P.delta, P.N)
+    level = P.L - 1
+    oW = O.encrypt_sk(P, small["okeys"], mw, level, P.delta, 31, 500)
+    gW = ctx.encrypt(ctx.pt_load(mw, level, P.delta), small["gkeys"], 31, 500)
+    want = []
+    for zb in oZ:
+        u = O.rescale(P, O.mul(P, O.drop(zb, level), oW, small["okeys"]))
+        t = 1
+        while t < c:
+            u = O.add(P, u, O.rotate(P, u, t * (r if layout else 1), small["okeys"]))
+            t *= 2
+        want.append(u.data)
+    for mode in (0, 1, 2, 2):
+        out = ctx.lr_margins(gZ, gW, c, r, small["gkeys"], mode=mode, layout=layout)
+        assert out[0].level == level - 1
+        for o, wd in zip(out, want):
+            assert np.array_equal(ctx.download(o), wd), mode
+    z = y[:, None] * X
+    m = z @ w0
+    dec = ctx.decrypt_decode(out[1], small["gkeys"]).real
+    grid = dec.reshape(c, r).T if layout else dec.reshape(r, c)
+    assert np.max(np.abs(grid[:, 0] - m[r: 2 * r])) < 1e-5
