@@ -350,6 +350,73 @@ __device__ __forceinline__ void stages_d(double (&v)[LineShape<LM>::E], int tau,
         }
     }
 }
+// ---- signed lazy FP64 forward path for primes below 2^46.  For an integer-
+// valued |a| <= 33q and 0 <= w < q, a*w = hi + lo exactly (FMA), the estimate
+// Q = floor(hi / q) is within one of the true quotient (its FP64 error is below
+// 3 * 2^-53 * 33q < 1), and fma(-Q, q, hi) + lo is exact and lies in (-q, 2q).
+// The forward butterfly x +- t then needs no correction: each stage widens the
+// range by 2q on each side, so the 16 stages of both passes keep every value
+// inside [-32q, 33q], exact in FP64.  The row pass reduces at the end; the
+// intermediate between the passes is stored as a signed integer.
+__device__ __forceinline__ double mulmod_lazy_d(double a, double w, double q, double qinv)
+{
+    double hi = a * w;
+    double lo = __fma_rn(a, w, -hi);
+    double qt = floor(hi * qinv);
+    return __fma_rn(-qt, q, hi) + lo;
+}
+__device__ __forceinline__ double reduce_d(double x, double q, double qinv)
+{
+    double qt = floor(x * qinv);
+    double r = __fma_rn(-qt, q, x);
+    r = r < 0.0 ? r + q : r;
+    return r >= q ? r - q : r;
+}
+template <int LM, bool PASS_B, bool STRIDED>
+__device__ __forceinline__ void fwd_stages_ds(double (&v)[LineShape<LM>::E], int tau, int h, int N1, const double *W,
+                                              double q, double qinv)
+{
+    using S = LineShape<LM>;
+    constexpr int s_lo = STRIDED ? 0 : S::LE, s_hi = STRIDED ? S::LE : LM;
+#pragma unroll
+    for (int s = s_lo; s < s_hi; ++s) {
+        const int hk = STRIDED ? 1 << (S::LE - 1 - s) : 1 << (LM - 1 - s);
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) {
+            if (k & hk) continue;
+            const int x = STRIDED ? tau + S::T * k : S::E * tau + k;
+            const double t = mulmod_lazy_d(v[k + hk], W[tw_index<LM, PASS_B>(s, x, h, N1)], q, qinv);
+            v[k + hk] = v[k] - t;
+            v[k] = v[k] + t;
+        }
+    }
+}
+
+// Inverse (Gentleman-Sande) counterpart for primes below 2^42: x' = x + y and
+// y' = lazy((x - y) w), no corrections.  Sums double the range each stage, so
+// one 8-stage pass from [0, q) stays inside |v| <= 2^8 q <= 2^50 (exact, and the
+// quotient estimate of every product within one); each pass reduces at its end.
+template <int LM, bool PASS_B, bool STRIDED>
+__device__ __forceinline__ void inv_stages_ds(double (&v)[LineShape<LM>::E], int tau, int h, int N1, const double *W,
+                                              double q, double qinv)
+{
+    using S = LineShape<LM>;
+    constexpr int s_lo = STRIDED ? 0 : S::LE, s_hi = STRIDED ? S::LE : LM;
+#pragma unroll
+    for (int si = 0; si < s_hi - s_lo; ++si) {
+        const int s = s_hi - 1 - si;
+        const int hk = STRIDED ? 1 << (S::LE - 1 - s) : 1 << (LM - 1 - s);
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) {
+            if (k & hk) continue;
+            const int x = STRIDED ? tau + S::T * k : S::E * tau + k;
+            const double a = v[k], b = v[k + hk];
+            v[k] = a + b;
+            v[k + hk] = mulmod_lazy_d(a - b, W[tw_index<LM, PASS_B>(s, x, h, N1)], q, qinv);
+        }
+    }
+}
+
 template <int LM>
 __device__ __forceinline__ void exch_d(double (&v)[LineShape<LM>::E], double *line, int tau, bool to_contig)
 {
@@ -515,7 +582,15 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
         const double *Wd = twd + ((long long)pidx << LOGN);
         double *dl = reinterpret_cast<double *>(line);
         double d[S::E];
-        if (!INV) {
+        if (!INV && q < (1ull << 46)) {  // signed lazy: the row pass reads a signed intermediate
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) d[k] = (double)load(tau + S::T * k);
+            fwd_stages_ds<LM, false, true>(d, tau, 0, 0, Wd, qd, qinv);
+            exch_d<LM>(d, dl, tau, true);
+            fwd_stages_ds<LM, false, false>(d, tau, 0, 0, Wd, qd, qinv);
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) limb[(long long)(S::E * tau + k) * N2 + col] = (u64)(long long)d[k];
+        } else if (!INV) {
 #pragma unroll
             for (int k = 0; k < S::E; ++k) d[k] = (double)load(tau + S::T * k);
             stages_d<LM, false, false, true>(d, tau, 0, 0, Wd, qd, qinv);
@@ -523,6 +598,18 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
             stages_d<LM, false, false, false>(d, tau, 0, 0, Wd, qd, qinv);
 #pragma unroll
             for (int k = 0; k < S::E; ++k) limb[(long long)(S::E * tau + k) * N2 + col] = (u64)d[k];
+        } else if (q < (1ull << 42)) {  // lazy inverse: input reduced by the row pass
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) d[k] = (double)limb[(long long)(S::E * tau + k) * N2 + col];
+            inv_stages_ds<LM, false, false>(d, tau, 0, 0, Wd, qd, qinv);
+            exch_d<LM>(d, dl, tau, false);
+            inv_stages_ds<LM, false, true>(d, tau, 0, 0, Wd, qd, qinv);
+            u64 sc = post ? post[2 * blockIdx.y] : p.ninv;
+            const double scd = (double)sc;
+#pragma unroll
+            for (int k = 0; k < S::E; ++k)
+                limb[(long long)(tau + S::T * k) * N2 + col] = (u64)reduce_d(mulmod_lazy_d(d[k], scd, qd, qinv), qd,
+                                                                            qinv);
         } else {
 #pragma unroll
             for (int k = 0; k < S::E; ++k) d[k] = (double)limb[(long long)(S::E * tau + k) * N2 + col];
@@ -603,7 +690,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
             if (c < f.nbase) r = add_mod(r, f.base[b * f.bs + c * f.bcs + roff + e], q);
             f.out[b * f.os + c * f.ocs + roff + e] = r;
         } else {
-            row[e] = x;
+            __builtin_nontemporal_store(x, row + e);
         }
     };
     if (q < (1ull << 49)) {  // exact FP64 path (quotient estimate off by at most one)
@@ -611,8 +698,21 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
         const double *Wd = twd + ((long long)pidx << LOGN);
         double *dl = reinterpret_cast<double *>(line);
         double d[S::E];
+        if (!INV && q < (1ull << 46)) {  // signed lazy: input is the column pass's signed intermediate
 #pragma unroll
-        for (int k = 0; k < S::E; ++k) d[k] = (double)in[tau + S::T * k];
+            for (int k = 0; k < S::E; ++k)
+                d[k] = (double)(long long)__builtin_nontemporal_load(in + tau + S::T * k);
+            fwd_stages_ds<LM, true, true>(d, tau, h, N1, Wd, qd, qinv);
+            exch_d<LM>(d, dl, tau, true);
+            fwd_stages_ds<LM, true, false>(d, tau, h, N1, Wd, qd, qinv);
+            __syncthreads();
+            exch_d<LM>(d, dl, tau, false);
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) store(k, (u64)reduce_d(d[k], qd, qinv));
+            return;
+        }
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) d[k] = (double)__builtin_nontemporal_load(in + tau + S::T * k);
         if (!INV) {
             stages_d<LM, true, false, true>(d, tau, h, N1, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, true);
@@ -625,6 +725,15 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
                 double x = d[k] >= q2d ? d[k] - q2d : d[k];
                 store(k, (u64)(x >= qd ? x - qd : x));
             }
+        } else if (q < (1ull << 42)) {  // lazy inverse, reduced for the column pass
+            exch_d<LM>(d, dl, tau, true);
+            inv_stages_ds<LM, true, false>(d, tau, h, N1, Wd, qd, qinv);
+            __syncthreads();
+            exch_d<LM>(d, dl, tau, false);
+            inv_stages_ds<LM, true, true>(d, tau, h, N1, Wd, qd, qinv);
+#pragma unroll
+            for (int k = 0; k < S::E; ++k)
+                __builtin_nontemporal_store((u64)reduce_d(d[k], qd, qinv), row + tau + S::T * k);
         } else {
             exch_d<LM>(d, dl, tau, true);
             stages_d<LM, true, true, false>(d, tau, h, N1, Wd, qd, qinv);
@@ -632,13 +741,13 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
             exch_d<LM>(d, dl, tau, false);
             stages_d<LM, true, true, true>(d, tau, h, N1, Wd, qd, qinv);
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) row[tau + S::T * k] = (u64)d[k];
+            for (int k = 0; k < S::E; ++k) __builtin_nontemporal_store((u64)d[k], row + tau + S::T * k);
         }
         return;
     }
     u64 v[S::E];
 #pragma unroll
-    for (int k = 0; k < S::E; ++k) v[k] = in[tau + S::T * k];
+    for (int k = 0; k < S::E; ++k) v[k] = __builtin_nontemporal_load(in + tau + S::T * k);
     if (!INV) {
         fwd_strided<LM, true>(v, tau, h, N1, W, Ws, q, q2);
         to_contig<LM>(v, line, tau);
@@ -654,7 +763,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
         to_strided<LM>(v, line, tau);
         inv_strided<LM, true>(v, tau, h, N1, W, Ws, q, q2);
 #pragma unroll
-        for (int k = 0; k < S::E; ++k) row[tau + S::T * k] = v[k];
+        for (int k = 0; k < S::E; ++k) __builtin_nontemporal_store(v[k], row + tau + S::T * k);
     }
 }
 
