@@ -97,11 +97,8 @@ he_status ks_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d2, long long 
         // ModUp conversion (integer-ALU bound: kept out of the NTT passes, measured
         // slower fused), then the forward NTT of the extended digits
         hek::modup_b(c, l, B, y, ys, ext, es, ds);
-        hek::ntt_batch(c, ext, es, ds, B, beta, 0, nb, l, +1, nullptr, true);
-        if (keys)
-            hek::ks_inner_multi_b(c, l, B, d2, d2s, ext, es, ds, *keys, acc, as);
-        else
-            hek::ks_inner_b(c, l, B, d2, d2s, ext, es, ds, key, acc, as);
+        // forward NTT of the extended digits with the key inner product fused into its row pass
+        hek::ks_ntt_inner(c, l, B, d2, d2s, ext, es, ds, key, keys, acc, as);
         // special-prime limbs to coefficient form, scaled by N^{-1} [phat_p^{-1}]_p
         hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
         // ModDown conversion inside the first pass, base + (acc - conv) P^{-1} stored by the second

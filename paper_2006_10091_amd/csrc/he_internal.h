@@ -130,6 +130,11 @@ void ks_inner_multi_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s,
                       long long ds, const EntryKeys &keys, u64 *acc, long long as);
 void automorph_multi_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,
                        long long oc, const EntryGal &gals);
+// forward NTT of the extended digits (column pass into ext) fused with the
+// inner product (row pass accumulating digit x key): acc [B][2][l+1+nk][N];
+// keys: per-entry keys (nullptr: `key` shared by the batch)
+void ks_ntt_inner(he_ctx *c, int level, int B, const u64 *d2, long long d2s, u64 *ext, long long es, long long ds,
+                  const u64 *key, const EntryKeys *keys, u64 *acc, long long as);
 // ModDown conversion from the special primes: conv [B][2][l+1][N] (coefficient)
 void moddown_conv_b(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs);
 // out = base + (acc - conv) P^{-1} on the first nbase components (else no base)

@@ -767,6 +767,129 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
     }
 }
 
+// Row pass of the extended digits' forward NTT fused with the key-switch
+// inner product: for position t of entry b, each digit j's rows go through
+// the last NTT stages (or are read from d2 when t lies inside digit j, already
+// in NTT form), are multiplied by key_j[0] and key_j[1] and accumulated in
+// registers; only acc[b][comp][t] is written.  Entries are the fastest grid
+// index, so consecutive workgroups share key rows in L2.
+struct KsArgs {
+    const u64 *d2;
+    long long d2s;
+    const u64 *ext;  // column-pass intermediates [b][j][pos][N]
+    long long es, ds;
+    const u64 *key;  // [j][2][np][N], shared by the batch unless per_entry
+    hek::EntryKeys ek;
+    int per_entry;
+    u64 *acc;  // [b][2][nb][N]
+    long long as;
+    int alpha, beta, ell, nq, np, nb;
+};
+
+template <int LOGN>
+__global__ __launch_bounds__(LINE_THREADS) void ntt_rows_ks_t(KsArgs a, const PrimeInfo *__restrict__ pinfo,
+                                                              const u64 *__restrict__ tw, const u64 *__restrict__ tws,
+                                                              const double *__restrict__ twd)
+{
+    constexpr int LM = LOGN - (LOGN + 1) / 2, N1 = 1 << ((LOGN + 1) / 2);
+    using S = LineShape<LM>;
+    __shared__ u64 lds[S::LINES * S::PADDED];
+    const int b = blockIdx.x, t = blockIdx.z;
+    const int tau = threadIdx.x % S::T, ln = threadIdx.x / S::T;
+    const int h = blockIdx.y * S::LINES + ln;
+    const int tp = prime_of(t, a.ell, a.nq);
+    const PrimeInfo p = pinfo[tp];
+    const u64 q = p.q;
+    const long long roff = ((long long)t << LOGN) + (long long)h * S::M;
+    const long long keylimb = (long long)a.np << LOGN;
+    const u64 *key = (a.per_entry ? a.ek.k[b] : a.key) + ((long long)tp << LOGN) + (long long)h * S::M;
+    u64 *line = lds + ln * S::PADDED;
+    u64 *o = a.acc + b * a.as + roff;
+    if (q < (1ull << 46)) {  // lazy FP64: products in (-q, 2q), sums of beta <= 12 exact
+        const double qd = (double)q, qinv = 1.0 / qd;
+        const double *Wd = twd + ((long long)tp << LOGN);
+        double *dl = reinterpret_cast<double *>(line);
+        double s0[S::E], s1[S::E];
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) s0[k] = s1[k] = 0.0;
+        for (int j = 0; j < a.beta; ++j) {
+            const int d0 = j * a.alpha, d1 = min(d0 + a.alpha, a.ell + 1);
+            double d[S::E];
+            if (t >= d0 && t < d1) {
+                const u64 *src = a.d2 + b * a.d2s + roff;
+#pragma unroll
+                for (int k = 0; k < S::E; ++k) d[k] = (double)src[tau + S::T * k];
+            } else {
+                const u64 *src = a.ext + b * a.es + j * a.ds + roff;
+#pragma unroll
+                for (int k = 0; k < S::E; ++k)
+                    d[k] = (double)(long long)__builtin_nontemporal_load(src + tau + S::T * k);
+                fwd_stages_ds<LM, true, true>(d, tau, h, N1, Wd, qd, qinv);
+                exch_d<LM>(d, dl, tau, true);
+                fwd_stages_ds<LM, true, false>(d, tau, h, N1, Wd, qd, qinv);
+                __syncthreads();
+                exch_d<LM>(d, dl, tau, false);
+                __syncthreads();  // the next digit's exchange rewrites the line
+            }
+            const u64 *kj = key + (long long)j * 2 * keylimb;
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) {
+                const int e = tau + S::T * k;
+                s0[k] += mulmod_lazy_d(d[k], (double)kj[e], qd, qinv);
+                s1[k] += mulmod_lazy_d(d[k], (double)kj[keylimb + e], qd, qinv);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) {
+            const int e = tau + S::T * k;
+            o[e] = (u64)reduce_d(s0[k], qd, qinv);
+            o[((long long)a.nb << LOGN) + e] = (u64)reduce_d(s1[k], qd, qinv);
+        }
+        return;
+    }
+    // larger primes: Harvey-lazy Shoup stages, canonical values, 128-bit products
+    const u64 *W = tw + ((long long)tp << LOGN);
+    const u64 *Ws = tws + ((long long)tp << LOGN);
+    const u64 q2 = 2 * q;
+    u64 s0[S::E], s1[S::E];
+#pragma unroll
+    for (int k = 0; k < S::E; ++k) s0[k] = s1[k] = 0;
+    for (int j = 0; j < a.beta; ++j) {
+        const int d0 = j * a.alpha, d1 = min(d0 + a.alpha, a.ell + 1);
+        u64 v[S::E];
+        if (t >= d0 && t < d1) {
+            const u64 *src = a.d2 + b * a.d2s + roff;
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) v[k] = src[tau + S::T * k];
+        } else {
+            const u64 *src = a.ext + b * a.es + j * a.ds + roff;
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) v[k] = __builtin_nontemporal_load(src + tau + S::T * k);
+            fwd_strided<LM, true>(v, tau, h, N1, W, Ws, q, q2);
+            to_contig<LM>(v, line, tau);
+            fwd_contig<LM, true>(v, tau, h, N1, W, Ws, q, q2);
+            __syncthreads();
+            to_strided<LM>(v, line, tau);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) v[k] = reduce4q(v[k], q, q2);
+        }
+        const u64 *kj = key + (long long)j * 2 * keylimb;
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) {
+            const int e = tau + S::T * k;
+            s0[k] = add_mod(s0[k], mul_mod(v[k], kj[e], p), q);
+            s1[k] = add_mod(s1[k], mul_mod(v[k], kj[keylimb + e], p), q);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < S::E; ++k) {
+        const int e = tau + S::T * k;
+        o[e] = s0[k];
+        o[((long long)a.nb << LOGN) + e] = s1[k];
+    }
+}
+
 // ------------------------------------------------------------------ elementwise
 struct EwArgs {
     u64 *x, *y, *o;
@@ -1404,6 +1527,51 @@ static NttArgs make_args(he_ctx *c, u64 *base, long long bstride, long long cstr
 }
 
 bool fused_ok(const he_ctx *c) { return c->logN >= 12 && c->alpha <= MAXW && c->nk <= MAXW; }
+
+template <int LOGN>
+static void ks_fused_t(he_ctx *c, NttArgs a, int B, int beta, int nb, const KsArgs &k)
+{
+    constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
+    Fuse f{};
+    a.zoff = 0;
+    dim3 gc((1 << (LOGN - LA)) / LineShape<LA>::LINES, nb, B * beta);
+    ntt_cols_t<LOGN, false, PRO_NONE><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh,
+                                                                          nullptr, c->t.psi_d, f);
+    dim3 gr(B, (1 << LA) / LineShape<LB>::LINES, nb);
+    ntt_rows_ks_t<LOGN><<<gr, LINE_THREADS, 0, c->stream>>>(k, c->t.pinfo, c->t.psi, c->t.psi_sh, c->t.psi_d);
+}
+
+void ks_ntt_inner(he_ctx *c, int level, int B, const u64 *d2, long long d2s, u64 *ext, long long es, long long ds,
+                  const u64 *key, const EntryKeys *keys, u64 *acc, long long as)
+{
+    const int beta = (level + 1 + c->alpha - 1) / c->alpha;
+    const int nb = level + 1 + c->nk;
+    KsArgs k{};
+    k.d2 = d2;
+    k.d2s = d2s;
+    k.ext = ext;
+    k.es = es;
+    k.ds = ds;
+    k.key = key;
+    if (keys) k.ek = *keys;
+    k.per_entry = keys ? 1 : 0;
+    k.acc = acc;
+    k.as = as;
+    k.alpha = c->alpha;
+    k.beta = beta;
+    k.ell = level;
+    k.nq = c->nq;
+    k.np = c->np;
+    k.nb = nb;
+    NttArgs a = make_args(c, ext, es, ds, beta, 0, level, true);
+    switch (c->logN) {
+    case 12: return ks_fused_t<12>(c, a, B, beta, nb, k);
+    case 13: return ks_fused_t<13>(c, a, B, beta, nb, k);
+    case 14: return ks_fused_t<14>(c, a, B, beta, nb, k);
+    case 15: return ks_fused_t<15>(c, a, B, beta, nb, k);
+    default: return ks_fused_t<16>(c, a, B, beta, nb, k);
+    }
+}
 
 void intt_from(he_ctx *c, const u64 *src, long long sbs, u64 *dst, long long dbs, int B, int level, const u64 *post)
 {
