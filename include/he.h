@@ -108,6 +108,10 @@ typedef struct {
 enum { HE_LAYOUT_ROWS = 0, HE_LAYOUT_FEATURES = 1 };
 
 /* Scale schedule of one gradient step (pure host; see he_plan_lr_step).
+ * The polynomial's terms are formed unrescaled at one level with scale
+ * s_c * q (C = A B3, B1 = M Z1 with Z1 at scale s_z1, k0 Z, B2 = A Z2),
+ * summed over the blocks and relinearised and rescaled once: s_b1 is the
+ * scale of M Z1 and kb1 is unused (0).
  * s_gsum: scale of the summed gradient before its mask (feature-major; equal to
  * s_g for row-major). */
 typedef struct {

@@ -24,6 +24,10 @@ Readings where the paper is silent (each listed in the design notes):
     the polynomial runs on that directly, and after the cross-block sum the
     gradient is summed inside each feature block (rotations 1..r/2), masked to
     slot j*r and replicated by rotations -1..-r/2, once per step.
+  * the products C = A B3, B1 = M Z1 and B2 = A Z2 feed only additions, so
+    they are formed at one level with one scale sC q (Z1's scale chosen for
+    it), left unrelinearised and unrescaled, summed with the a0 term and across
+    the blocks, and the sum is relinearised and rescaled once per step.
   * eta/n enters through the scale bookkeeping (an exact FP64 change of the
     declared scale), and W is brought to the gradient's scale by one integer
     multiplication and rescale, both fixed by plan_lr_step below.
@@ -196,10 +200,10 @@ def plan_lr_step(q, level, s_Z, s_W, coef, eta_over_n, w_decay=0.0, layout=ROWS)
     k3 = llround(coef[3] * sZ3 * ql1 / s_Z)
     sB3 = sM * sZ3 / ql2
     sC = sA * sB3 / ql3
-    sZ1 = sZ3
-    k1 = llround(coef[1] * sZ1 * ql1 / s_Z)
-    sB1 = sM * sZ1 / ql2
-    kB1 = llround(sC * ql3 / sB1)
+    sZ1 = sC * ql3 / sM
+    k1 = llround(coef[1] * sZ1 * ql2 / s_Z)
+    sB1 = sM * sZ1
+    kB1 = 0
     k0 = llround(coef[0] * sC * ql3 / s_Z)
     sZ2 = sC * ql3 / sA
     k2 = llround(coef[2] * sZ2 * ql2 / s_Z)
@@ -232,10 +236,10 @@ def _plan_features(q, level, s_Z, s_W, coef, eta_over_n, w_decay):
     k3 = llround(coef[3] * sZ3 * ql / s_Z)
     sB3 = sM * sZ3 / ql1
     sC = sA * sB3 / ql2
-    sZ1 = sZ3
-    k1 = llround(coef[1] * sZ1 * ql / s_Z)
-    sB1 = sM * sZ1 / ql1
-    kB1 = llround(sC * ql2 / sB1)
+    sZ1 = sC * ql2 / sM
+    k1 = llround(coef[1] * sZ1 * ql1 / s_Z)
+    sB1 = sM * sZ1
+    kB1 = 0
     k0 = llround(coef[0] * sC * ql2 / s_Z)
     sZ2 = sC * ql2 / sA
     k2 = llround(coef[2] * sZ2 * ql1 / s_Z)
@@ -278,6 +282,27 @@ def rotation_steps(c, r, layout=ROWS):
     return st
 
 
+# ---------------------------------------------------------------- degree-2 helpers
+# Additions act on each component on its own, so degree-2 ciphertexts
+# (d0, d1, d2) are added pair by pair; relinearisation is linear and is
+# applied once to a sum.
+def _pairs(d3):
+    return O.CT(np.ascontiguousarray(d3[:2]), d3.shape[1] - 1, 1.0), O.CT(np.stack([d3[2], d3[2]]), d3.shape[1] - 1,
+                                                                           1.0)
+
+
+def add3(P, x3, y3):
+    ax, bx = _pairs(x3)
+    ay, by = _pairs(y3)
+    return np.concatenate([O.add(P, ax, ay).data, O.add(P, bx, by).data[:1]])
+
+
+def add3_1(P, x3, y):
+    """Degree-2 plus degree-1 (added to d0, d1)."""
+    ax, _ = _pairs(x3)
+    return np.concatenate([O.add(P, ax, y).data, x3[2:3]])
+
+
 # ---------------------------------------------------------------- encrypted step
 def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_decay=0.0, layout=ROWS):
     """One step of eq. (appr) + eq. (update) on ciphertexts (coefficient form).
@@ -304,18 +329,14 @@ def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_dec
         A = O.rescale(P, O.mul(P, M, M, keys), scale=pl["sA"])
         Z3 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 1), pl["k3"]), scale=pl["sZ3"])
         B3 = O.rescale(P, O.mul(P, M, Z3, keys), scale=pl["sB3"])
-        Z1 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 1), pl["k1"]), scale=pl["sZ1"])
-        B1 = O.rescale(P, O.mul(P, M, Z1, keys), scale=pl["sB1"])
-        C = O.rescale(P, O.mul(P, A, B3, keys), scale=pl["sC"])
-        B1p = O.rescale(P, O.mul_int(P, B1, pl["kB1"]), scale=pl["sC"])
-        Z0p = O.rescale(P, O.mul_int(P, O.drop(zb, l - 3), pl["k0"]), scale=pl["sC"])
-        Gb = O.add(P, O.add(P, C, B1p), Z0p)
+        Z1 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 2), pl["k1"]), scale=pl["sZ1"])
+        Z2 = None
         if pl["k2"] != 0:
-            # a2 m^2 z: A (level l-3) times a2 Z brought to level l-3
             Z2 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 2), pl["k2"]), scale=pl["sZ2"])
-            B2 = O.rescale(P, O.mul(P, A, Z2, keys), scale=pl["sC"])
-            Gb = O.add(P, Gb, B2)
-        G = Gb if G is None else O.add(P, G, Gb)
+        Gb = _terms_prescale(P, zb, A, B3, M, Z1, Z2, l - 3, pl)
+        G = Gb if G is None else add3(P, G, Gb)
+    # one relinearisation and one rescale of the summed terms
+    G = O.rescale(P, O.relin(P, G, pl["sC"] * float(P.q[l - 3]), l - 3, keys), scale=pl["sC"])
     t = 1
     while t < r:
         G = O.add(P, G, O.rotate(P, G, t * c, keys))
@@ -323,6 +344,17 @@ def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_dec
     g = O.CT(G.data, G.level, pl["s_g"])
     Wn = O.rescale(P, O.mul_int(P, O.drop(W, l - 3), pl["kW"]), scale=pl["s_g"])
     return O.add(P, Wn, g), g
+
+
+def _terms_prescale(P, zb, A, B3, M, Z1, Z2, lp, pl):
+    """The block's gradient terms, unrescaled, as one degree-2 ciphertext at
+    level lp with scale sC q_lp: C = A (x) B3, B1 = M (x) Z1 (M dropped to lp;
+    Z1 carries sC q_lp / sM), k0 Z, and for a2 != 0 B2 = A (x) Z2."""
+    G = add3(P, O.tensor(P, A, B3)[0], O.tensor(P, O.drop(M, lp), Z1)[0])
+    G = add3_1(P, G, O.mul_int(P, O.drop(zb, lp), pl["k0"]))
+    if pl["k2"] != 0:
+        G = add3(P, G, O.tensor(P, A, Z2)[0])
+    return G
 
 
 def _step_features(P, keys, Z, W, mask_m, c, r, pl):
@@ -340,17 +372,14 @@ def _step_features(P, keys, Z, W, mask_m, c, r, pl):
         A = O.rescale(P, O.mul(P, M, M, keys), scale=pl["sA"])
         Z3 = O.rescale(P, O.mul_int(P, O.drop(zb, l), pl["k3"]), scale=pl["sZ3"])
         B3 = O.rescale(P, O.mul(P, M, Z3, keys), scale=pl["sB3"])
-        Z1 = O.rescale(P, O.mul_int(P, O.drop(zb, l), pl["k1"]), scale=pl["sZ1"])
-        B1 = O.rescale(P, O.mul(P, M, Z1, keys), scale=pl["sB1"])
-        C = O.rescale(P, O.mul(P, A, B3, keys), scale=pl["sC"])
-        B1p = O.rescale(P, O.mul_int(P, B1, pl["kB1"]), scale=pl["sC"])
-        Z0p = O.rescale(P, O.mul_int(P, O.drop(zb, l - 2), pl["k0"]), scale=pl["sC"])
-        Gb = O.add(P, O.add(P, C, B1p), Z0p)
+        Z1 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 1), pl["k1"]), scale=pl["sZ1"])
+        Z2 = None
         if pl["k2"] != 0:
             Z2 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 1), pl["k2"]), scale=pl["sZ2"])
-            B2 = O.rescale(P, O.mul(P, A, Z2, keys), scale=pl["sC"])
-            Gb = O.add(P, Gb, B2)
-        G = Gb if G is None else O.add(P, G, Gb)
+        Gb = _terms_prescale(P, zb, A, B3, M, Z1, Z2, l - 2, pl)
+        G = Gb if G is None else add3(P, G, Gb)
+    # one relinearisation and one rescale of the summed terms
+    G = O.rescale(P, O.relin(P, G, pl["sC"] * float(P.q[l - 2]), l - 2, keys), scale=pl["sC"])
     t = 1
     while t < r:  # sum over the samples inside each feature block
         G = O.add(P, G, O.rotate(P, G, t, keys))

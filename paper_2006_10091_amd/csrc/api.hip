@@ -65,7 +65,10 @@ size_t ks_scratch(const he_ctx *c, int l, int B)
     return al(B * (l + 1) * N) + al((size_t)B * beta_at(c, l) * nb * N) + al((size_t)B * 2 * nb * N) +
            al((size_t)B * 2 * (l + 1) * N);
 }
-size_t rescale_scratch(const he_ctx *c, int l, int B) { return al((size_t)B * 2 * c->N) + al((size_t)B * 2 * l * c->N); }
+size_t rescale_scratch(const he_ctx *c, int l, int B, int ncomp = 2)
+{
+    return al((size_t)B * ncomp * c->N) + al((size_t)B * ncomp * l * c->N);
+}
 size_t rotate_scratch(const he_ctx *c, int l, int B) { return al((size_t)B * 2 * (l + 1) * c->N) + ks_scratch(c, l, B); }
 
 he_status last_error()
@@ -129,21 +132,25 @@ he_status relin_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d3, long lo
     return ks_apply(c, ar, l, B, d3 + 2 * lc, d3s, rlk, d3, d3s, lc, 2, out, os, lc);
 }
 
-// rescale B ciphertexts at level l -> level l-1 (out may equal in only for B == 1)
-he_status rescale_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long long is, u64 *out, long long os)
+// rescale B ciphertexts of ncomp components at level l -> level l-1 (each
+// component on its own; out may equal in only for B == 1)
+he_status rescale_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long long is, u64 *out, long long os,
+                        int ncomp = 2)
 {
     const size_t N = c->N;
     const size_t mark = ar.off;
-    u64 *lastc = ar.take((size_t)B * 2 * N);
-    u64 *tmp = ar.take((size_t)B * 2 * l * N);
+    u64 *lastc = ar.take((size_t)B * ncomp * N);
+    u64 *tmp = ar.take((size_t)B * ncomp * l * N);
     if (!lastc || !tmp) return HE_ENOMEM;
     const long long lc = (long long)(l + 1) * N;
-    hek::ewise(c, 4, 0, B, 2, in + (long long)l * N, is, lc, nullptr, 0, 0, lastc, 2LL * N, (long long)N, 0);
+    hek::ewise(c, 4, 0, B, ncomp, in + (long long)l * N, is, lc, nullptr, 0, 0, lastc, (long long)ncomp * N,
+               (long long)N, 0);
     // the limbs use prime q_l: address them as position l of a shifted base
-    hek::ntt_batch(c, lastc - (long long)l * N, 2LL * N, (long long)N, B, 2, l, 1, l, -1, nullptr, false);
-    hek::rescale_bcast_b(c, l, B, lastc, tmp);
-    hek::ntt_batch(c, tmp, 2LL * l * N, (long long)l * N, B, 2, 0, l, l - 1, +1, nullptr, false);
-    hek::rescale_finish_b(c, l, B, in, is, tmp, out, os);
+    hek::ntt_batch(c, lastc - (long long)l * N, (long long)ncomp * N, (long long)N, B, ncomp, l, 1, l, -1, nullptr,
+                   false);
+    hek::rescale_bcast_b(c, l, B, lastc, tmp, ncomp);
+    hek::ntt_batch(c, tmp, (long long)ncomp * l * N, (long long)l * N, B, ncomp, 0, l, l - 1, +1, nullptr, false);
+    hek::rescale_finish_b(c, l, B, in, is, tmp, out, os, ncomp);
     ar.off = mark;
     return last_error();
 }
@@ -362,11 +369,14 @@ he_status make_evk(he_ctx *c, Arena &ar, u64 seed, uint32_t key_id, const u64 *s
 
 // ------------------------------------------------------------------ the gradient step
 struct StepBufs {
-    u64 *T3, *U0, *U, *R, *M, *Y, *Z3, *Z1, *A, *B3, *B1, *C, *B1p, *Z0p, *G, *Rg, *Y1, *Z2, *B2, *Gm;
+    u64 *T3, *U0, *U, *R, *M, *Y, *Z3, *Z1, *A, *B3, *C, *G, *Rg, *Y1, *Z2, *Gm, *G3;
 };
 
 // Per-block intermediates sit one level higher in the feature-major circuit
-// (no mask level between the margins and the polynomial): e = 1 there.
+// (no mask level between the margins and the polynomial): e = 1 there.  The
+// block's gradient terms C (and B1, B2, k0 Z) are summed unrescaled and
+// unrelinearised (three components) at level l-3+e, across the blocks too,
+// and the sum is relinearised and rescaled once per step.
 size_t step_bytes(const he_ctx *c, int l, int nb, int layout)
 {
     const size_t N = c->N;
@@ -378,15 +388,15 @@ size_t step_bytes(const he_ctx *c, int l, int nb, int layout)
     n += al((size_t)nb * 2 * (l - 1) * N);                 // M
     n += al((size_t)nb * 2 * (l + e) * N);                 // Y
     n += 2 * al((size_t)nb * 2 * (l - 1 + e) * N);         // Z3, Z1
-    n += 3 * al((size_t)nb * 2 * (l - 2 + e) * N);         // A, B3, B1
-    n += 3 * al((size_t)nb * 2 * (l - 3 + e) * N);         // C, B1p, Z0p
+    n += 2 * al((size_t)nb * 2 * (l - 2 + e) * N);         // A, B3
+    n += al((size_t)nb * 3 * (l - 2 + e) * N);             // C (degree-2 terms)
     n += al((size_t)nb * 2 * (l - 2 + e) * N);             // Z2
-    n += al((size_t)nb * 2 * (l - 3 + e) * N);             // B2
+    n += al((size_t)3 * (l - 2 + e) * N);                  // G3
     n += 2 * al((size_t)2 * (l - 3 + e) * N);              // G, Rg
     n += al((size_t)2 * (l - 2) * N);                      // Y1
     n += al((size_t)2 * (l - 3) * N);                      // Gm
     size_t scratch = std::max(rotate_scratch(c, l, nb), rescale_scratch(c, l, nb));
-    n += std::max(scratch, rotate_scratch(c, l - 4 + e, 1));
+    n += std::max(scratch, rotate_scratch(c, l - 3 + e, 1));
     return n * 8 + 4096;
 }
 
@@ -404,18 +414,14 @@ he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, int layout, StepBufs &
     s.Z1 = ar.take((size_t)nb * 2 * (l - 1 + e) * N);
     s.A = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
     s.B3 = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
-    s.B1 = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
-    s.C = ar.take((size_t)nb * 2 * (l - 3 + e) * N);
-    s.B1p = ar.take((size_t)nb * 2 * (l - 3 + e) * N);
-    s.Z0p = ar.take((size_t)nb * 2 * (l - 3 + e) * N);
+    s.C = ar.take((size_t)nb * 3 * (l - 2 + e) * N);
+    s.Z2 = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
+    s.G3 = ar.take((size_t)3 * (l - 2 + e) * N);
     s.G = ar.take((size_t)2 * (l - 3 + e) * N);
     s.Rg = ar.take((size_t)2 * (l - 3 + e) * N);
     s.Y1 = ar.take((size_t)2 * (l - 2) * N);
-    s.Z2 = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
-    s.B2 = ar.take((size_t)nb * 2 * (l - 3 + e) * N);
     s.Gm = ar.take((size_t)2 * (l - 3) * N);
-    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Y, s.Z3, s.Z1, s.A, s.B3, s.B1, s.C, s.B1p, s.Z0p, s.G, s.Rg, s.Y1,
-                  s.Z2, s.B2, s.Gm};
+    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Y, s.Z3, s.Z1, s.A, s.B3, s.C, s.Z2, s.G3, s.G, s.Rg, s.Y1, s.Gm};
     for (u64 *p : all)
         if (!p) return HE_ENOMEM;
     return HE_OK;
@@ -436,6 +442,27 @@ he_status mul_relin_rescale(he_ctx *c, Arena &ar, StepBufs &s, int l, int nb, co
     hek::tensor_b(c, l, nb, x, xb, xc, y, yb, yc, s.T3, 3 * lc, lc);
     TRY(relin_apply(c, ar, l, nb, s.T3, 3 * lc, rlk, s.U0, 2 * lc));
     return rescale_apply(c, ar, l, nb, s.U0, 2 * lc, out, 2LL * l * N);
+}
+
+// The block's gradient terms, unrescaled and unrelinearised, as one degree-2
+// sum at level lp (into s.C, scale sC q_lp): C = A (x) B3, B1 = M (x) Z1 (M,
+// component stride mc, read on its first lp+1 limbs), k0 Z and, for k2 != 0,
+// B2 = A (x) Z2.  A, B3, Z1, Z2 at level lp.
+he_status terms_prescale(he_ctx *c, StepBufs &s, const he_lr_plan &pl, int lp, int nb, const u64 *zp,
+                         long long zbs, long long zc, const u64 *M, long long mc)
+{
+    const long long N = c->N;
+    const long long p1 = (long long)(lp + 1) * N;
+    hek::tensor_b(c, lp, nb, s.A, 2 * p1, p1, s.B3, 2 * p1, p1, s.C, 3 * p1, p1);
+    hek::tensor_b(c, lp, nb, M, 2 * mc, mc, s.Z1, 2 * p1, p1, s.T3, 3 * p1, p1);
+    hek::ewise(c, 0, lp, nb, 3, s.C, 3 * p1, p1, s.T3, 3 * p1, p1, s.C, 3 * p1, p1, 0);
+    hek::ewise(c, 2, lp, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * p1, p1, pl.k0);
+    hek::ewise(c, 0, lp, nb, 2, s.C, 3 * p1, p1, s.Y, 2 * p1, p1, s.C, 3 * p1, p1, 0);
+    if (pl.k2 != 0) {
+        hek::tensor_b(c, lp, nb, s.A, 2 * p1, p1, s.Z2, 2 * p1, p1, s.T3, 3 * p1, p1);
+        hek::ewise(c, 0, lp, nb, 3, s.C, 3 * p1, p1, s.T3, 3 * p1, p1, s.C, 3 * p1, p1, 0);
+    }
+    return last_error();
 }
 
 // per-block part of the step for blocks [b0, b0+nb); G (+)= sum of their terms
@@ -474,28 +501,17 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
     hek::ewise(c, 2, l - 1, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * y1, y1, pl.k3);
     TRY(rescale_apply(c, ar, l - 1, nb, s.Y, 2 * y1, s.Z3, 2 * m1));
     TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.Z3, 2 * m1, m1, keys->rlk, s.B3));
-    hek::ewise(c, 2, l - 1, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * y1, y1, pl.k1);
-    TRY(rescale_apply(c, ar, l - 1, nb, s.Y, 2 * y1, s.Z1, 2 * m1));
-    TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.Z1, 2 * m1, m1, keys->rlk, s.B1));
-    // C = A B3 (level l-4)
-    const long long a1 = (long long)(l - 2) * N, c1 = (long long)(l - 3) * N;
-    TRY(mul_relin_rescale(c, ar, s, l - 3, nb, s.A, 2 * a1, a1, s.B3, 2 * a1, a1, keys->rlk, s.C));
-    // B1' = RS(kB1 B1), Z0' = RS(k0 Z)
-    hek::ewise(c, 2, l - 3, nb, 2, s.B1, 2 * a1, a1, nullptr, 0, 0, s.B1, 2 * a1, a1, pl.kb1);
-    TRY(rescale_apply(c, ar, l - 3, nb, s.B1, 2 * a1, s.B1p, 2 * c1));
-    hek::ewise(c, 2, l - 3, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * a1, a1, pl.k0);
-    TRY(rescale_apply(c, ar, l - 3, nb, s.Y, 2 * a1, s.Z0p, 2 * c1));
-    // G_b = C + B1' + Z0'; G (+)= sum_b G_b
-    hek::ewise(c, 0, l - 4, nb, 2, s.C, 2 * c1, c1, s.B1p, 2 * c1, c1, s.C, 2 * c1, c1, 0);
-    hek::ewise(c, 0, l - 4, nb, 2, s.C, 2 * c1, c1, s.Z0p, 2 * c1, c1, s.C, 2 * c1, c1, 0);
+    // Z1 = RS(k1 Z) and, for a2 != 0, Z2 = RS(k2 Z), both at level l-3
+    const long long a1 = (long long)(l - 2) * N;
+    hek::ewise(c, 2, l - 2, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * m1, m1, pl.k1);
+    TRY(rescale_apply(c, ar, l - 2, nb, s.Y, 2 * m1, s.Z1, 2 * a1));
     if (pl.k2 != 0) {
-        // a2 m^2 z (Table 2's hinge row): B2 = RS(A (x) RS(k2 Z)) at level l-4
         hek::ewise(c, 2, l - 2, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * m1, m1, pl.k2);
         TRY(rescale_apply(c, ar, l - 2, nb, s.Y, 2 * m1, s.Z2, 2 * a1));
-        TRY(mul_relin_rescale(c, ar, s, l - 3, nb, s.A, 2 * a1, a1, s.Z2, 2 * a1, a1, keys->rlk, s.B2));
-        hek::ewise(c, 0, l - 4, nb, 2, s.C, 2 * c1, c1, s.B2, 2 * c1, c1, s.C, 2 * c1, c1, 0);
     }
-    hek::batch_sum(c, l - 4, nb, s.C, 2 * c1, c1, s.G, c1, accumulate);
+    // the block's terms at level l-3 (unrescaled); G3 (+)= their sum
+    TRY(terms_prescale(c, s, pl, l - 3, nb, zp, zbs, zc, s.M, m1));
+    hek::batch_sum(c, l - 3, nb, s.C, 3 * a1, a1, s.G3, a1, accumulate, 3);
     return last_error();
 }
 
@@ -529,27 +545,17 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
     hek::ewise(c, 2, l, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * y1, y1, pl.k3);
     TRY(rescale_apply(c, ar, l, nb, s.Y, 2 * y1, s.Z3, 2 * u1));
     TRY(mul_relin_rescale(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.Z3, 2 * u1, u1, keys->rlk, s.B3));
-    hek::ewise(c, 2, l, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * y1, y1, pl.k1);
-    TRY(rescale_apply(c, ar, l, nb, s.Y, 2 * y1, s.Z1, 2 * u1));
-    TRY(mul_relin_rescale(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.Z1, 2 * u1, u1, keys->rlk, s.B1));
-    // C = A B3 (level l-3)
-    const long long a1 = (long long)(l - 1) * N, c1 = (long long)(l - 2) * N;
-    TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.A, 2 * a1, a1, s.B3, 2 * a1, a1, keys->rlk, s.C));
-    // B1' = RS(kB1 B1), Z0' = RS(k0 Z)
-    hek::ewise(c, 2, l - 2, nb, 2, s.B1, 2 * a1, a1, nullptr, 0, 0, s.B1, 2 * a1, a1, pl.kb1);
-    TRY(rescale_apply(c, ar, l - 2, nb, s.B1, 2 * a1, s.B1p, 2 * c1));
-    hek::ewise(c, 2, l - 2, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * a1, a1, pl.k0);
-    TRY(rescale_apply(c, ar, l - 2, nb, s.Y, 2 * a1, s.Z0p, 2 * c1));
-    hek::ewise(c, 0, l - 3, nb, 2, s.C, 2 * c1, c1, s.B1p, 2 * c1, c1, s.C, 2 * c1, c1, 0);
-    hek::ewise(c, 0, l - 3, nb, 2, s.C, 2 * c1, c1, s.Z0p, 2 * c1, c1, s.C, 2 * c1, c1, 0);
+    // Z1 = RS(k1 Z) and, for a2 != 0, Z2 = RS(k2 Z), both at level l-2
+    const long long a1 = (long long)(l - 1) * N;
+    hek::ewise(c, 2, l - 1, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * u1, u1, pl.k1);
+    TRY(rescale_apply(c, ar, l - 1, nb, s.Y, 2 * u1, s.Z1, 2 * a1));
     if (pl.k2 != 0) {
-        // a2 m^2 z: B2 = RS(A (x) RS(k2 Z)) at level l-3
         hek::ewise(c, 2, l - 1, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * u1, u1, pl.k2);
         TRY(rescale_apply(c, ar, l - 1, nb, s.Y, 2 * u1, s.Z2, 2 * a1));
-        TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.A, 2 * a1, a1, s.Z2, 2 * a1, a1, keys->rlk, s.B2));
-        hek::ewise(c, 0, l - 3, nb, 2, s.C, 2 * c1, c1, s.B2, 2 * c1, c1, s.C, 2 * c1, c1, 0);
     }
-    hek::batch_sum(c, l - 3, nb, s.C, 2 * c1, c1, s.G, c1, accumulate);
+    // the block's terms at level l-2 (unrescaled); G3 (+)= their sum
+    TRY(terms_prescale(c, s, pl, l - 2, nb, zp, zbs, zc, s.U, u1));
+    hek::batch_sum(c, l - 2, nb, s.C, 3 * a1, a1, s.G3, a1, accumulate, 3);
     return last_error();
 }
 
@@ -722,6 +728,13 @@ he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_block
             TRY(step_blocks(c, ar, s, pl, Z, bs, b0, nb, W, mask, cols, keys, b0 > 0));
     }
     const long long g1 = (long long)(l - 3) * N;  // component stride at level l-4
+    {
+        // one relinearisation and one rescale of the summed terms
+        const int lg = fm ? l - 2 : l - 3;
+        const long long x1 = (long long)(lg + 1) * N;
+        TRY(relin_apply(c, ar, lg, 1, s.G3, 3 * x1, keys->rlk, s.U0, 2 * x1));
+        TRY(rescale_apply(c, ar, lg, 1, s.U0, 2 * x1, s.G, 2LL * lg * N));
+    }
     u64 *g = s.G;
     if (fm) {
         // sum inside each feature block (level l-3), mask slots j r, rescale to

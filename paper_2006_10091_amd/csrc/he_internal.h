@@ -142,15 +142,15 @@ void moddown_finish_b(he_ctx *c, int level, int B, const u64 *acc, long long as,
                       const u64 *base, long long bs, long long bcs, int nbase, u64 *out, long long os,
                       long long ocs);
 // rescale pieces: lastc [B][2][N] (coefficient) -> tmp [B][2][l][N]; finish
-void rescale_bcast_b(he_ctx *c, int level, int B, const u64 *lastc, u64 *tmp);
+void rescale_bcast_b(he_ctx *c, int level, int B, const u64 *lastc, u64 *tmp, int ncomp = 2);
 void rescale_finish_b(he_ctx *c, int level, int B, const u64 *in, long long is, const u64 *tmp, u64 *out,
-                      long long os);
+                      long long os, int ncomp = 2);
 // NTT-order automorphism X -> X^g of B two-component entries of nl limbs
 void automorph_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,
                  long long oc, u64 g);
 // out[c] (+)= sum over B entries of in[b][c], positions 0..level, both components
 void batch_sum(he_ctx *c, int level, int B, const u64 *in, long long ib, long long ic, u64 *out, long long oc,
-               bool accumulate);
+               bool accumulate, int ncomp = 2);
 // PRNG and samplers (coefficient form), positions -> primes given on the host
 void sample_uniform(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp_base, int n_pos,
                     const int *prime_of_pos, u64 *out);

@@ -275,10 +275,10 @@ static he_status plan_features(const u64 *q, int level, double s_z, double s_w, 
     double k3 = coef[3] * o->s_z3 * ql / s_z;
     o->s_b3 = o->s_m * o->s_z3 / ql1;
     o->s_c = o->s_a * o->s_b3 / ql2;
-    o->s_z1 = o->s_z3;
-    double k1 = coef[1] * o->s_z1 * ql / s_z;
-    o->s_b1 = o->s_m * o->s_z1 / ql1;
-    double kb1 = o->s_c * ql2 / o->s_b1;
+    o->s_z1 = o->s_c * ql2 / o->s_m;
+    double k1 = coef[1] * o->s_z1 * ql1 / s_z;
+    o->s_b1 = o->s_m * o->s_z1;
+    double kb1 = 0.0;
     double k0 = coef[0] * o->s_c * ql2 / s_z;
     o->s_z2 = o->s_c * ql2 / o->s_a;
     double k2 = coef[2] * o->s_z2 * ql1 / s_z;
@@ -315,10 +315,10 @@ he_status plan_lr_step(const u64 *q, int n_q, int level, double s_z, double s_w,
     double k3 = coef[3] * o->s_z3 * ql1 / s_z;
     o->s_b3 = o->s_m * o->s_z3 / ql2;
     o->s_c = o->s_a * o->s_b3 / ql3;
-    o->s_z1 = o->s_z3;
-    double k1 = coef[1] * o->s_z1 * ql1 / s_z;
-    o->s_b1 = o->s_m * o->s_z1 / ql2;
-    double kb1 = o->s_c * ql3 / o->s_b1;
+    o->s_z1 = o->s_c * ql3 / o->s_m;
+    double k1 = coef[1] * o->s_z1 * ql2 / s_z;
+    o->s_b1 = o->s_m * o->s_z1;
+    double kb1 = 0.0;
     double k0 = coef[0] * o->s_c * ql3 / s_z;
     o->s_z2 = o->s_c * ql3 / o->s_a;
     double k2 = coef[2] * o->s_z2 * ql2 / s_z;

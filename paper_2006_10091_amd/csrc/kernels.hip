@@ -1183,15 +1183,15 @@ __global__ __launch_bounds__(256) void rescale_finish_kernel(const u64 *in, long
                                                              u64 *out, long long os,
                                                              const PrimeInfo *__restrict__ pinfo,
                                                              const u64 *__restrict__ rs_qinv, int level, int nq,
-                                                             int logN)
+                                                             int logN, int ncomp)
 {
     const int b = blockIdx.y;
     const int N = 1 << logN;
     const u64 *qi_tab = rs_qinv + (long long)level * nq * 2;
     for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < ncomp; ++c) {
             const u64 *src = in + b * is + ((long long)c * (level + 1) << logN);
-            const u64 *tp = tmp + ((long long)(b * 2 + c) * level << logN);
+            const u64 *tp = tmp + ((long long)(b * ncomp + c) * level << logN);
             u64 *dst = out + b * os + ((long long)c * level << logN);
             for (int i = 0; i < level; ++i) {
                 const u64 q = pinfo[i].q;
@@ -1702,18 +1702,18 @@ void moddown_finish_b(he_ctx *c, int level, int B, const u64 *acc, long long as,
                                                     c->t.pinfo, c->t.dn_pinv, level, c->nk, c->logN);
 }
 
-void rescale_bcast_b(he_ctx *c, int level, int B, const u64 *lastc, u64 *tmp)
+void rescale_bcast_b(he_ctx *c, int level, int B, const u64 *lastc, u64 *tmp, int ncomp)
 {
-    dim3 g(xblocks(c->N), level, B * 2);
+    dim3 g(xblocks(c->N), level, B * ncomp);
     rescale_bcast_kernel<<<g, 256, 0, c->stream>>>(lastc, tmp, c->t.pinfo, c->t.rs_ql, level, c->nq, c->logN);
 }
 
 void rescale_finish_b(he_ctx *c, int level, int B, const u64 *in, long long is, const u64 *tmp, u64 *out,
-                      long long os)
+                      long long os, int ncomp)
 {
     dim3 g(xblocks(c->N, 1), B, 1);
     rescale_finish_kernel<<<g, 256, 0, c->stream>>>(in, is, tmp, out, os, c->t.pinfo, c->t.rs_qinv, level, c->nq,
-                                                    c->logN);
+                                                    c->logN, ncomp);
 }
 
 void automorph_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,
@@ -1731,9 +1731,9 @@ void automorph_multi_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, lo
 }
 
 void batch_sum(he_ctx *c, int level, int B, const u64 *in, long long ib, long long ic, u64 *out, long long oc,
-               bool accumulate)
+               bool accumulate, int ncomp)
 {
-    dim3 g(xblocks(c->N), level + 1, 2);
+    dim3 g(xblocks(c->N), level + 1, ncomp);
     batch_sum_kernel<<<g, 256, 0, c->stream>>>(in, ib, ic, B, out, oc, accumulate ? 1 : 0, c->t.pinfo, c->logN);
 }
 

@@ -464,11 +464,15 @@ def test_plan_consistency():
     coef = [0.5, -0.15012041, 0.0, 0.00159302]
     for sW in (P.delta, 2.0 ** 44.55):
         pl = LR.plan_lr_step(P.q, 19, P.delta, sW, coef, 1 / 6000)
-        for k in ("k0", "k1", "k3", "kB1", "kW"):
+        for k in ("k0", "k1", "k3", "kW"):
             assert 2 ** 20 <= abs(pl[k]) < 2 ** 62
-        # every term lands on the same declared scale
-        assert abs(pl["sB1"] * pl["kB1"] / P.q[16] / pl["sC"] - 1) < 2 ** -20
-        assert abs(P.delta * pl["k0"] / P.q[16] / pl["sC"] / coef[0] - 1) < 2 ** -20
+        assert pl["kB1"] == 0
+        # every unrescaled term lands on the same scale sC q_{l-3}: C = A B3,
+        # B1 = M Z1 (Z1's actual scale from its integer k1), k0 Z
+        ql3, ql2 = float(P.q[16]), float(P.q[17])
+        assert abs(pl["sA"] * pl["sB3"] / ql3 / pl["sC"] - 1) < 2 ** -40
+        assert abs(pl["sM"] * (P.delta * pl["k1"] / ql2) / ql3 / pl["sC"] / coef[1] - 1) < 2 ** -20
+        assert abs(P.delta * pl["k0"] / ql3 / pl["sC"] / coef[0] - 1) < 2 ** -20
     with pytest.raises(LR.LevelError):
         LR.plan_lr_step(P.q, 3, P.delta, P.delta, coef, 1 / 6000)
 
