@@ -311,8 +311,11 @@ def cpu_baseline(Wk, threads, nb, c, r):
     """The oracle on a bounded sample of the feature-major schedule: one
     mul+relin+rescale and one rotation at every level the schedule's key
     switches run at (the median of two runs each), extrapolated by the
-    schedule's key-switch counts (rescales of plain products, additions and
-    the refresh are left out, so the CPU rate is an upper bound)."""
+    schedule's key-switch counts: per block the margin product, the margin
+    rotations and the two products A and B3; per step the one
+    relinearisation of the summed terms and the sample-sum and replicate
+    rotations.  Tensor products, plaintext products, additions and the
+    refresh are left out, so the CPU rate is an upper bound."""
     if threads:
         os.environ["OMP_NUM_THREADS"] = str(threads)
     nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -357,14 +360,14 @@ def cpu_baseline(Wk, threads, nb, c, r):
         sample["rot%d" % lv] = timed(lambda: O.rotate(P, x, 1, keys))
     t_sched = 0.0
     for l in levels:  # the feature-major step at level l
-        t_sched += nb * (sample["mul%d" % l] + lc * sample["rot%d" % (l - 1)] + 3 * sample["mul%d" % (l - 1)] +
-                         sample["mul%d" % (l - 2)])
-        t_sched += lr * sample["rot%d" % (l - 3)] + lr * sample["rot%d" % (l - 4)]
+        t_sched += nb * (sample["mul%d" % l] + lc * sample["rot%d" % (l - 1)] + 2 * sample["mul%d" % (l - 1)])
+        t_sched += sample["mul%d" % (l - 2)] + lr * sample["rot%d" % (l - 3)] + lr * sample["rot%d" % (l - 4)]
     t_step = t_sched / len(levels)
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": nthreads, "kind": "oracle",
             "sample": "one oracle mul+relin+rescale and one rotation at each level the feature-major schedule "
                       "key-switches at (median of 2 runs; %.1fs of sampled work, keys %.1fs), extrapolated by the "
-                      "schedule's key-switch counts (steps at levels %s: %d blocks x (1+%d+3+1) + 2x%d per step)" % (
+                      "schedule's key-switch counts (steps at levels %s: %d blocks x (1+%d+2) + 1+2x%d per step; the "
+                      "degree-2 term products, which need no key switch, are left out)" % (
                           2 * sum(sample.values()), t_keys, "/".join(map(str, levels)), nb, lc, lr),
             "extrapolated": True, "sample_seconds": sample}
 
