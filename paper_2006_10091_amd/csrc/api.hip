@@ -97,8 +97,8 @@ he_status ks_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d2, long long 
     if (hek::fused_ok(c)) {
         // digits to coefficient form, scaled by N^{-1} [qhat_i^{-1}]_{q_i} (read from d2)
         hek::intt_from(c, d2, d2s, y, ys, B, l, up_post);
-        // ModUp conversion (integer-ALU bound: kept out of the NTT passes, measured
-        // slower fused), then the forward NTT of the extended digits
+        // ModUp conversion (its own kernel: fused into the first forward pass it
+        // measured no faster), then the forward NTT of the extended digits
         hek::modup_b(c, l, B, y, ys, ext, es, ds);
         // forward NTT of the extended digits with the key inner product fused into its row pass
         hek::ks_ntt_inner(c, l, B, d2, d2s, ext, es, ds, key, keys, acc, as);
@@ -306,6 +306,39 @@ he_status build_tables(he_ctx *c)
         dn_pinv[2 * i] = Pi;
         dn_pinv[2 * i + 1] = shoup(Pi, qi);
     }
+    // FP64 forms of the conversion constants (used for targets below 2^46)
+    auto bits = [](u64 x) { return 64 - __builtin_clzll(x); };
+    auto pow2mod = [&](int e, u64 m) {
+        u64 r = 1 % m;
+        for (int k = 0; k < e; ++k) r = mulmod(r, 2, m);
+        return r;
+    };
+    std::vector<double> up_convd(up_conv.size(), 0.0), up_qdd((size_t)nq * HE_MAXDIG * np, 0.0),
+        dn_convd(dn_conv.size(), 0.0), dn_pd(nq, 0.0), qinv_d(np, 0.0);
+    for (int t = 0; t < np; ++t) qinv_d[t] = 1.0 / (double)c->q[t];
+    for (int l = 0; l < nq; ++l)
+        for (int j = 0; j < beta_at(c, l); ++j) {
+            int d0 = j * A, d1 = std::min(d0 + A, l + 1);
+            for (int i = d0; i < d1; ++i) {
+                const int S = conv_split_bits(bits(c->q[i]));
+                for (int t = 0; t < np; ++t) {
+                    size_t o = ((((size_t)l * HE_MAXDIG + j) * A + (i - d0)) * np + t) * 2;
+                    up_convd[o] = (double)up_conv[o];
+                    up_convd[o + 1] = (double)mulmod(up_conv[o], pow2mod(S, c->q[t]), c->q[t]);
+                }
+            }
+            for (int t = 0; t < np; ++t)
+                up_qdd[((size_t)l * HE_MAXDIG + j) * np + t] = (double)up_qd[(((size_t)l * HE_MAXDIG + j) * np + t) * 2];
+        }
+    for (int k = 0; k < nk; ++k) {
+        const int S = conv_split_bits(bits(c->q[nq + k]));
+        for (int i = 0; i < nq; ++i) {
+            size_t o = ((size_t)k * nq + i) * 2;
+            dn_convd[o] = (double)dn_conv[o];
+            dn_convd[o + 1] = (double)mulmod(dn_conv[o], pow2mod(S, c->q[i]), c->q[i]);
+        }
+    }
+    for (int i = 0; i < nq; ++i) dn_pd[i] = (double)dn_p[2 * i];
     std::vector<u64> rs_qinv((size_t)nq * nq * 2, 0), rs_ql((size_t)nq * nq, 0);
     for (int l = 1; l < nq; ++l)
         for (int i = 0; i < l; ++i) {
@@ -330,10 +363,16 @@ he_status build_tables(he_ctx *c)
     t.dn_conv = dev_upload(c, dn_conv);
     t.dn_p = dev_upload(c, dn_p);
     t.dn_pinv = dev_upload(c, dn_pinv);
+    t.up_convd = dev_upload(c, up_convd);
+    t.up_qdd = dev_upload(c, up_qdd);
+    t.qinv_d = dev_upload(c, qinv_d);
+    t.dn_convd = dev_upload(c, dn_convd);
+    t.dn_pd = dev_upload(c, dn_pd);
     t.rs_qinv = dev_upload(c, rs_qinv);
     t.rs_ql = dev_upload(c, rs_ql);
     if (!t.pinfo || !t.psi || !t.psi_sh || !t.ipsi || !t.ipsi_sh || !t.psi_d || !t.ipsi_d || !t.up_scale || !t.up_conv || !t.up_qd ||
-        !t.dn_scale || !t.dn_conv || !t.dn_p || !t.dn_pinv || !t.rs_qinv || !t.rs_ql)
+        !t.dn_scale || !t.dn_conv || !t.dn_p || !t.dn_pinv || !t.rs_qinv || !t.rs_ql || !t.up_convd || !t.up_qdd ||
+        !t.qinv_d || !t.dn_convd || !t.dn_pd)
         return HE_ENOMEM;
     return HE_OK;
 }

@@ -29,11 +29,19 @@ struct DeviceTables {
     u64 *up_scale;           // [nq][nq][2]
     u64 *up_conv;            // [nq][HE_MAXDIG][alpha][np][2]
     u64 *up_qd;              // [nq][HE_MAXDIG][np][2]
+    // FP64 forms for targets below 2^46 (S_i = conv_split_bits(bit length of q_i)):
+    //   up_convd[l][j][ii][t]    = (qhat_i mod t, qhat_i 2^S_i mod t)
+    //   up_qdd[l][j][t]          = Q_D mod t
+    double *up_convd;        // [nq][HE_MAXDIG][alpha][np][2]
+    double *up_qdd;          // [nq][HE_MAXDIG][np]
+    double *qinv_d;          // [np] 1 / q_t
     // ModDown (independent of the level):
     u64 *dn_scale;           // [nk][2]  N^{-1} [phat_p^{-1}]_p
     u64 *dn_conv;            // [nk][nq][2] phat_p mod q_i
     u64 *dn_p;               // [nq][2]  P mod q_i
     u64 *dn_pinv;            // [nq][2]  P^{-1} mod q_i
+    double *dn_convd;        // [nk][nq][2] (phat_p mod q_i, phat_p 2^S_p mod q_i)
+    double *dn_pd;           // [nq] P mod q_i
     // Rescale: rs_qinv[l][i] = q_l^{-1} mod q_i, rs_ql[l][i] = q_l mod q_i  (i < l)
     u64 *rs_qinv;            // [nq][nq][2]
     u64 *rs_ql;              // [nq][nq]
@@ -101,7 +109,6 @@ void ntt_batch(he_ctx *c, u64 *base, long long bstride, long long cstride, int n
 // base + (acc - conv) P^{-1} into out.
 bool fused_ok(const he_ctx *c);
 void intt_from(he_ctx *c, const u64 *src, long long sbs, u64 *dst, long long dbs, int B, int level, const u64 *post);
-void ntt_modup(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, long long es, long long ds);
 void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs, const u64 *base,
                  long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs);
 // op 0 add, 1 sub, 2 multiply by integer k, 3 multiply by plaintext y ([pos][N]), 4 copy;

@@ -457,18 +457,19 @@ __device__ __forceinline__ u64 reduce4q(u64 v, u64 q, u64 q2)
 }
 
 // Fusion around the two passes (all optional, chosen per launch):
-//   pass A prologue  PRO_MODUP   : input = ModUp conversion of the scaled digit residues (y)
-//                    PRO_MODDOWN : input = ModDown conversion of the special-prime residues (acc)
+//   pass A prologue  PRO_MODDOWN : input = ModDown conversion of the special-prime residues (acc)
 //   pass B (inverse) PRO_SRC     : read the limb from another buffer (out-of-place)
 //   pass B epilogue  EPI_FINISH  : store base + (acc - x) P^{-1} instead of x
-enum { PRO_NONE = 0, PRO_MODUP = 1, PRO_MODDOWN = 2, PRO_SRC = 3 };
+enum { PRO_NONE = 0, PRO_MODDOWN = 2, PRO_SRC = 3 };
 enum { EPI_NONE = 0, EPI_FINISH = 1 };
 
 struct Fuse {
-    const u64 *src;      // y (ModUp) / acc (ModDown) / source limbs (PRO_SRC)
+    const u64 *src;      // acc (ModDown) / source limbs (PRO_SRC)
     long long sbs, scs;  // batch / component strides of src
-    const u64 *cvt;      // ModUp: up_conv of the level; ModDown: dn_conv
-    const u64 *cnt;      // ModUp: up_qd of the level; ModDown: dn_p
+    const u64 *cvt;      // ModDown: dn_conv
+    const u64 *cnt;      // ModDown: dn_p
+    const double *cvtd;  // FP64 forms: dn_convd
+    const double *cntd;  // dn_pd
     int alpha, np, nk;
     const u64 *acc;      // finish: acc [b][comp][pos], strides as / acs
     long long as, acs;
@@ -480,7 +481,7 @@ struct Fuse {
     const u64 *pinv;     // finish: P^{-1} mod q_pos (+ Shoup)
 };
 
-constexpr int MAXW = 8;  // digit width / special primes a fused prologue can read
+constexpr int MAXW = 8;  // special primes the ModDown prologue reads (and the fused path's digit-width bound)
 
 // per-workgroup constants of a conversion prologue
 struct ConvConst {
@@ -488,46 +489,55 @@ struct ConvConst {
     u64 k, ks;
     int n;
     const u64 *src;
+    // FP64 path (target below 2^46): per source the constant, its 2^S multiple
+    // and split point (S = 0: the source enters whole), and Q mod p
+    bool fp;
+    double cd[MAXW], ch[MAXW], kd;
+    int sh[MAXW];
 };
 
-template <int PRO>
+// FP64 constants of a conversion to a target of bit length kp, sources
+// s0 .. s0 + cc.n - 1 (their constant pairs e[i * es], e[i * es + 1])
+__device__ __forceinline__ void conv_setup_fp(ConvConst &cc, const PrimeInfo *pinfo, int s0, const double *e,
+                                              long long es, double kd, int kp)
+{
+    int kmax = 0;
+#pragma unroll
+    for (int i = 0; i < MAXW; ++i) {
+        if (i < cc.n) {
+            const int ki = (int)pinfo[s0 + i].k;
+            kmax = max(kmax, ki);
+            cc.cd[i] = e[i * es];
+            cc.ch[i] = e[i * es + 1];
+            cc.sh[i] = conv_whole(ki, kp) ? 0 : conv_split_bits(ki);
+        }
+    }
+    cc.kd = kd;
+    cc.fp = conv_fp_ok(kmax, kp);
+}
+
+// ModDown prologue constants: sources are the special primes, the target is
+// q_pos of this workgroup
 __device__ __forceinline__ void conv_setup(const NttArgs &a, const Fuse &f, const PrimeInfo *pinfo, int tp,
                                            ConvConst &cc)
 {
     const int z = (int)blockIdx.z + a.zoff;
     const int b = z / a.ncomp, c = z % a.ncomp;
-    if (PRO == PRO_MODUP) {
-        const int d0 = c * f.alpha;
-        cc.n = min(f.alpha, a.ell + 1 - d0);
-        cc.src = f.src + b * f.sbs + ((long long)d0 << a.logN);
+    const int pos = a.pos0 + (int)blockIdx.y;  // target q_pos
+    cc.n = f.nk;
+    cc.src = f.src + b * f.sbs + c * f.scs + ((long long)(a.ell + 1) << a.logN);
 #pragma unroll
-        for (int i = 0; i < MAXW; ++i) {
-            if (i < cc.n) {
-                const u64 *e = f.cvt + (((long long)c * f.alpha + i) * f.np + tp) * 2;
-                cc.c[i] = e[0];
-                cc.cs[i] = e[1];
-                cc.half[i] = pinfo[d0 + i].q >> 1;
-            }
+    for (int i = 0; i < MAXW; ++i) {
+        if (i < cc.n) {
+            const u64 *e = f.cvt + ((long long)i * a.nq + pos) * 2;
+            cc.c[i] = e[0];
+            cc.cs[i] = e[1];
+            cc.half[i] = pinfo[a.nq + i].q >> 1;
         }
-        const u64 *e = f.cnt + ((long long)c * f.np + tp) * 2;
-        cc.k = e[0];
-        cc.ks = e[1];
-    } else {
-        const int pos = a.pos0 + (int)blockIdx.y;  // target q_pos
-        cc.n = f.nk;
-        cc.src = f.src + b * f.sbs + c * f.scs + ((long long)(a.ell + 1) << a.logN);
-#pragma unroll
-        for (int i = 0; i < MAXW; ++i) {
-            if (i < cc.n) {
-                const u64 *e = f.cvt + ((long long)i * a.nq + pos) * 2;
-                cc.c[i] = e[0];
-                cc.cs[i] = e[1];
-                cc.half[i] = pinfo[a.nq + i].q >> 1;
-            }
-        }
-        cc.k = f.cnt[2 * pos];
-        cc.ks = f.cnt[2 * pos + 1];
     }
+    cc.k = f.cnt[2 * pos];
+    cc.ks = f.cnt[2 * pos + 1];
+    conv_setup_fp(cc, pinfo, a.nq, f.cvtd + (long long)pos * 2, 2LL * a.nq, f.cntd[pos], (int)pinfo[tp].k);
 }
 
 // centred fast basis conversion of one coefficient (offset off in the limb) to
@@ -548,6 +558,51 @@ __device__ __forceinline__ u64 conv_value(const ConvConst &cc, long long off, co
     }
     const u64 acc = reduce128(hi, lo, p);
     return sub_mod(acc, mul_shoup(cnt, cc.k, cc.ks, p.q), p.q);
+}
+
+// The conversion in FP64 (cc.fp: target p below 2^46) for the E elements of
+// one column-pass thread (offsets
+// off0 + k * step), source by source: the E loads of one source limb are
+// issued together before their products, so a thread keeps E loads in flight
+template <int E>
+__device__ __forceinline__ void conv_column_d(const ConvConst &cc, long long off0, long long step, double (&d)[E],
+                                              double pd, double pinv, int logN)
+{
+    u32 cnt[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        d[k] = 0.0;
+        cnt[k] = 0;
+    }
+#pragma unroll
+    for (int i = 0; i < MAXW; ++i) {
+        if (i < cc.n) {
+            const u64 *src = cc.src + ((long long)i << logN) + off0;
+            u64 v[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) v[k] = src[k * step];
+            const int sh = cc.sh[i];
+            const double c0 = cc.cd[i], c1 = cc.ch[i];
+            const u64 half = cc.half[i];
+            if (sh == 0) {
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    cnt[k] += v[k] > half;
+                    d[k] += mulmod_lazy_d((double)v[k], c0, pd, pinv);
+                }
+            } else {
+                const u64 m = (1ull << sh) - 1;
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    cnt[k] += v[k] > half;
+                    d[k] += mulmod_lazy_d((double)(v[k] >> sh), c1, pd, pinv) +
+                            mulmod_lazy_d((double)(v[k] & m), c0, pd, pinv);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) d[k] = reduce_d(__fma_rn(-(double)cnt[k], cc.kd, d[k]), pd, pinv);
 }
 
 // pass A: columns.  Thread (tau, cc) with cc fastest; LINES consecutive columns per workgroup.
@@ -571,10 +626,10 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
     const u64 *Ws = tws + ((long long)pidx << LOGN);
     u64 *line = lds + cc * S::PADDED;
     ConvConst cv;
-    if (PRO == PRO_MODUP || PRO == PRO_MODDOWN) conv_setup<PRO>(a, f, pinfo, pidx, cv);
+    if (PRO == PRO_MODDOWN) conv_setup(a, f, pinfo, pidx, cv);
     auto load = [&](int row) -> u64 {
         const long long off = (long long)row * N2 + col;
-        if (PRO == PRO_MODUP || PRO == PRO_MODDOWN) return conv_value(cv, off, p, LOGN);
+        if (PRO == PRO_MODDOWN) return conv_value(cv, off, p, LOGN);
         return limb[off];
     };
     if (q < (1ull << 49)) {  // exact FP64 path (quotient estimate off by at most one)
@@ -583,8 +638,12 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
         double *dl = reinterpret_cast<double *>(line);
         double d[S::E];
         if (!INV && q < (1ull << 46)) {  // signed lazy: the row pass reads a signed intermediate
+            if (PRO == PRO_MODDOWN && cv.fp) {
+                conv_column_d<S::E>(cv, (long long)tau * N2 + col, (long long)S::T * N2, d, qd, qinv, LOGN);
+            } else {
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) d[k] = (double)load(tau + S::T * k);
+                for (int k = 0; k < S::E; ++k) d[k] = (double)load(tau + S::T * k);
+            }
             fwd_stages_ds<LM, false, true>(d, tau, 0, 0, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, true);
             fwd_stages_ds<LM, false, false>(d, tau, 0, 0, Wd, qd, qinv);
@@ -956,47 +1015,103 @@ __global__ __launch_bounds__(256) void tensor_kernel(const u64 *__restrict__ x, 
 
 // ModUp conversion: ext[b][j][t] for positions t outside digit j.
 // y[b][i] holds [d_i qhat_i^{-1}]_{q_i} (coefficient form).  A thread reads
-// the digit's alpha residues of one coefficient once and writes every target.
+// the digit's residues of two neighbouring coefficients once (16-byte loads)
+// and writes every target.  Targets below 2^46 take the FP64 path (exact lazy
+// products, one reduction); wider ones an exact 128-bit sum and one Barrett
+// reduction.  Both give the canonical residue of the same integer.  A bounds
+// the digit width at compile time (registers); nd <= A is the digit's width.
 constexpr int MAX_ALPHA = 12;
+template <int A>
 __global__ __launch_bounds__(256) void modup_kernel(const u64 *__restrict__ y, long long ys, u64 *__restrict__ ext,
                                                     long long es, long long ds, const PrimeInfo *__restrict__ pinfo,
                                                     const u64 *__restrict__ conv, const u64 *__restrict__ qd,
-                                                    int level, int alpha, int nq, int np, int nk, int beta, int logN)
+                                                    const double *__restrict__ convd, const double *__restrict__ qdd,
+                                                    const double *__restrict__ qinv_d, int level, int alpha, int nq,
+                                                    int np, int nk, int beta, int logN)
 {
+    typedef __attribute__((ext_vector_type(2))) unsigned long long u64x2;
     const int z = blockIdx.y;
     const int b = z / beta, j = z % beta;
     const int d0 = j * alpha, d1 = min(d0 + alpha, level + 1);
     const int nd = d1 - d0;
     const int N = 1 << logN;
-    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int x = 2 * (blockIdx.x * 256 + threadIdx.x);
     if (x >= N) return;
     const u64 *yb = y + b * ys;
-    u64 v[MAX_ALPHA];
-    u64 cnt = 0;
-    for (int i = 0; i < nd; ++i) {
-        v[i] = yb[((long long)(d0 + i) << logN) + x];
-        cnt += v[i] > (pinfo[d0 + i].q >> 1);
+    u64 v[A][2];
+    u64 cnt[2] = {0, 0};
+    int kmax = 0;
+#pragma unroll
+    for (int i = 0; i < A; ++i) {
+        if (i < nd) {
+            const PrimeInfo pi = pinfo[d0 + i];
+            const u64x2 w = *reinterpret_cast<const u64x2 *>(yb + ((long long)(d0 + i) << logN) + x);
+            v[i][0] = w.x;
+            v[i][1] = w.y;
+            cnt[0] += w.x > (pi.q >> 1);
+            cnt[1] += w.y > (pi.q >> 1);
+            kmax = max(kmax, (int)pi.k);
+        }
     }
     // conv layout: [level][HE_MAXDIG][alpha][np][2]; qd: [level][HE_MAXDIG][np][2]
-    const u64 *cv = conv + ((((long long)level * HE_MAXDIG + j) * alpha) * np) * 2;
+    const long long cbase = (((long long)level * HE_MAXDIG + j) * alpha) * np;
+    const u64 *cv = conv + cbase * 2;
+    const double *cvd = convd + cbase * 2;
     const u64 *qq = qd + (((long long)level * HE_MAXDIG + j) * np) * 2;
+    const double *qqd = qdd + ((long long)level * HE_MAXDIG + j) * np;
     u64 *o = ext + b * es + j * ds + x;
     const int nb = level + 1 + nk;
     for (int t = 0; t < nb; ++t) {
         if (t >= d0 && t < d1) continue;
         const int tp = prime_of(t, level, nq);
         const PrimeInfo pt = pinfo[tp];
-        // exact 128-bit sum of the alpha products (each < 2^120), one reduction
-        u64 lo = 0, hi = 0;
-        for (int i = 0; i < nd; ++i) {
-            const u64 ci = cv[((long long)i * np + tp) * 2];
-            const u64 pl = v[i] * ci, ph = __umul64hi(v[i], ci);
-            lo += pl;
-            hi += ph + (lo < pl);
+        const int kp = (int)pt.k;
+        u64x2 r;
+        if (conv_fp_ok(kmax, kp)) {
+            const double pd = (double)pt.q, pinv = qinv_d[tp];
+            const double kd = qqd[tp];
+            double s0 = -(double)cnt[0] * kd, s1 = -(double)cnt[1] * kd;
+#pragma unroll
+            for (int i = 0; i < A; ++i) {
+                if (i < nd) {
+                    const double *e = cvd + ((long long)i * np + tp) * 2;
+                    const int ki = (int)pinfo[d0 + i].k;
+                    if (conv_whole(ki, kp)) {
+                        s0 += mulmod_lazy_d((double)v[i][0], e[0], pd, pinv);
+                        s1 += mulmod_lazy_d((double)v[i][1], e[0], pd, pinv);
+                    } else {
+                        const int S = conv_split_bits(ki);
+                        const u64 m = (1ull << S) - 1;
+                        s0 += mulmod_lazy_d((double)(v[i][0] >> S), e[1], pd, pinv) +
+                              mulmod_lazy_d((double)(v[i][0] & m), e[0], pd, pinv);
+                        s1 += mulmod_lazy_d((double)(v[i][1] >> S), e[1], pd, pinv) +
+                              mulmod_lazy_d((double)(v[i][1] & m), e[0], pd, pinv);
+                    }
+                }
+            }
+            r.x = (u64)reduce_d(s0, pd, pinv);
+            r.y = (u64)reduce_d(s1, pd, pinv);
+        } else {
+            // exact 128-bit sum of the products (each < 2^120), one reduction
+            u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+#pragma unroll
+            for (int i = 0; i < A; ++i) {
+                if (i < nd) {
+                    const u64 ci = cv[((long long)i * np + tp) * 2];
+                    u64 pl = v[i][0] * ci, ph = __umul64hi(v[i][0], ci);
+                    lo0 += pl;
+                    hi0 += ph + (lo0 < pl);
+                    pl = v[i][1] * ci;
+                    ph = __umul64hi(v[i][1], ci);
+                    lo1 += pl;
+                    hi1 += ph + (lo1 < pl);
+                }
+            }
+            const u64 kq = qq[2 * tp], kqs = qq[2 * tp + 1];
+            r.x = sub_mod(reduce128(hi0, lo0, pt), mul_shoup(cnt[0], kq, kqs, pt.q), pt.q);
+            r.y = sub_mod(reduce128(hi1, lo1, pt), mul_shoup(cnt[1], kq, kqs, pt.q), pt.q);
         }
-        u64 acc = reduce128(hi, lo, pt);
-        acc = sub_mod(acc, mul_shoup(cnt, qq[2 * tp], qq[2 * tp + 1], pt.q), pt.q);
-        o[(long long)t << logN] = acc;
+        *reinterpret_cast<u64x2 *>(o + ((long long)t << logN)) = r;
     }
 }
 
@@ -1433,10 +1548,7 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
         dim3 gr((1 << LA) / LineShape<LB>::LINES, npos, nzc);
         hipStream_t st = c->stream;
         if (dir > 0) {
-            if (pro == PRO_MODUP)
-                ntt_cols_t<LOGN, false, PRO_MODUP><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh, nullptr,
-                                                                               c->t.psi_d, f);
-            else if (pro == PRO_MODDOWN)
+            if (pro == PRO_MODDOWN)
                 ntt_cols_t<LOGN, false, PRO_MODDOWN><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh,
                                                                                  nullptr, c->t.psi_d, f);
             else
@@ -1583,21 +1695,6 @@ void intt_from(he_ctx *c, const u64 *src, long long sbs, u64 *dst, long long dbs
     ntt_launch(c, a, B, level + 1, -1, post, PRO_SRC, EPI_NONE, &f);
 }
 
-void ntt_modup(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, long long es, long long ds)
-{
-    const int beta = (level + 1 + c->alpha - 1) / c->alpha;
-    Fuse f{};
-    f.src = y;
-    f.sbs = ys;
-    f.cvt = c->t.up_conv + ((long long)level * HE_MAXDIG * c->alpha * c->np) * 2;
-    f.cnt = c->t.up_qd + ((long long)level * HE_MAXDIG * c->np) * 2;
-    f.alpha = c->alpha;
-    f.np = c->np;
-    f.nk = c->nk;
-    NttArgs a = make_args(c, ext, es, ds, beta, 0, level, true);
-    ntt_launch(c, a, B, level + 1 + c->nk, +1, nullptr, PRO_MODUP, EPI_NONE, &f);
-}
-
 void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs, const u64 *base,
                  long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs)
 {
@@ -1608,6 +1705,8 @@ void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 
     f.scs = nb * N;
     f.cvt = c->t.dn_conv;
     f.cnt = c->t.dn_p;
+    f.cvtd = c->t.dn_convd;
+    f.cntd = c->t.dn_pd;
     f.nk = c->nk;
     f.np = c->np;
     f.acc = acc;
@@ -1663,9 +1762,24 @@ void tensor_b(he_ctx *c, int level, int B, const u64 *x, long long xb, long long
 void modup_b(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, long long es, long long ds)
 {
     const int beta = (level + 1 + c->alpha - 1) / c->alpha;
-    dim3 g((c->N + 255) / 256, B * beta, 1);
-    modup_kernel<<<g, 256, 0, c->stream>>>(y, ys, ext, es, ds, c->t.pinfo, c->t.up_conv, c->t.up_qd, level, c->alpha,
-                                           c->nq, c->np, c->nk, beta, c->logN);
+    dim3 g((c->N / 2 + 255) / 256, B * beta, 1);
+#define HE_MODUP(A)                                                                                                     \
+    modup_kernel<A><<<g, 256, 0, c->stream>>>(y, ys, ext, es, ds, c->t.pinfo, c->t.up_conv, c->t.up_qd, c->t.up_convd, \
+                                              c->t.up_qdd, c->t.qinv_d, level, c->alpha, c->nq, c->np, c->nk, beta,     \
+                                              c->logN)
+    if (c->alpha <= 1)
+        HE_MODUP(1);
+    else if (c->alpha <= 2)
+        HE_MODUP(2);
+    else if (c->alpha <= 4)
+        HE_MODUP(4);
+    else if (c->alpha <= 6)
+        HE_MODUP(6);
+    else if (c->alpha <= 8)
+        HE_MODUP(8);
+    else
+        HE_MODUP(MAX_ALPHA);
+#undef HE_MODUP
 }
 
 void ks_inner_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const u64 *ext, long long es,

@@ -14,6 +14,19 @@
 typedef uint64_t u64;
 typedef uint32_t u32;
 
+// FP64 fast basis conversion (the centred conversion of the key switch, every
+// target prime p below 2^46).  Each source residue v < q_i enters one exact
+// lazy FP64 product with a constant below p, which needs |v| <= 33p: a source
+// of at most kp + 4 bits (kp = bit length of p) enters whole, a wider one as
+// two halves v = vh 2^S + vl with S = ceil(ki / 2), each half of at most
+// kp + 4 bits.
+__host__ __device__ constexpr int conv_split_bits(int ki) { return (ki + 1) / 2; }
+__host__ __device__ constexpr bool conv_whole(int ki, int kp) { return ki <= kp + 4; }
+__host__ __device__ constexpr bool conv_fp_ok(int ki_max, int kp)
+{
+    return kp <= 46 && conv_split_bits(ki_max) <= kp + 4;
+}
+
 // Per-prime constants (device table, one entry per prime of the chain).
 struct PrimeInfo {
     u64 q;
