@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--ntt-counters", action="store_true",
                     help="run only the calibration copy and the NTT batch (a target for rocprofv3 --pmc passes, "
                          "which cannot follow the step's graph launches); prints no bench line")
+    ap.add_argument("--ks-counters", action="store_true",
+                    help="run only the calibration copy and 3 batched multiply-relinearise-rescale-rotate launches "
+                         "over 32 ciphertexts at level 18 (key-switch kernels at the step's top-level shape, "
+                         "without graphs); prints no bench line")
     return ap.parse_args()
 
 
@@ -140,6 +144,28 @@ def measure_copy_and_ntt(torch, ctx, ev, nb):
         nlimb, t_fwd * 1e3, alg_bytes / t_fwd / 1e9, t_inv * 1e3))
     del buf
     return copy_gbs, dict(t_fwd=t_fwd, t_inv=t_inv, nlimb=nlimb, alg_bytes=alg_bytes)
+
+
+def measure_copy_and_ks(torch, H, synth, ctx, ev, n_ct=32, level=18):
+    """The calibration copy, then he_batch_mul_rotate (two key switches per
+    entry: relinearisation at `level`, rotation by 1 at level - 1) over n_ct
+    ciphertexts of uniform residues, batched form, 3 timed launches."""
+    N = ctx.N
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    del src, dst
+    keys = ctx.keygen(11, [1])
+    q = ctx.primes[: level + 1]
+    xs, ys = [], []
+    for i in range(n_ct):
+        for dst_, s_ in ((xs, 100 + 4 * i), (ys, 102 + 4 * i)):
+            d = np.stack([synth.uniform_residues(s_, q, N), synth.uniform_residues(s_ + 1, q, N)])
+            dst_.append(ctx.upload(d, level, 1.0))
+    outs = [ctx.ct_empty(level - 1) for _ in range(n_ct)]
+    ctx.batch_mul_rotate(xs, ys, [1] * n_ct, keys, mode=1, outs=outs)
+    t = ev.time(lambda: ctx.batch_mul_rotate(xs, ys, [1] * n_ct, keys, mode=1, outs=outs), 3)
+    log("batched mul+relin+rescale+rotate, %d entries at level %d: %.3f ms" % (n_ct, level, t * 1e3))
 
 
 def ntt_sweep(torch, H, ev):
@@ -250,6 +276,9 @@ def main():
     ev = Events(torch, torch.cuda.current_stream())
     if args.ntt_counters:
         measure_copy_and_ntt(torch, ctx, ev, nb)
+        return
+    if args.ks_counters:
+        measure_copy_and_ks(torch, H, synth, ctx, ev)
         return
     steps = sorted(set(H.rotation_steps(c, r, H.LAYOUT_ROWS)) | set(H.rotation_steps(c, r, H.LAYOUT_FEATURES)))
     t0 = time.time()

@@ -143,14 +143,28 @@ he_status rescale_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long 
     u64 *tmp = ar.take((size_t)B * ncomp * l * N);
     if (!lastc || !tmp) return HE_ENOMEM;
     const long long lc = (long long)(l + 1) * N;
-    hek::ewise(c, 4, 0, B, ncomp, in + (long long)l * N, is, lc, nullptr, 0, 0, lastc, (long long)ncomp * N,
-               (long long)N, 0);
-    // the limbs use prime q_l: address them as position l of a shifted base
-    hek::ntt_batch(c, lastc - (long long)l * N, (long long)ncomp * N, (long long)N, B, ncomp, l, 1, l, -1, nullptr,
-                   false);
-    hek::rescale_bcast_b(c, l, B, lastc, tmp, ncomp);
-    hek::ntt_batch(c, tmp, (long long)ncomp * l * N, (long long)l * N, B, ncomp, 0, l, l - 1, +1, nullptr, false);
-    hek::rescale_finish_b(c, l, B, in, is, tmp, out, os, ncomp);
+    // the fused form reads limb i of the input and writes limb i of the output
+    // from different workgroups: it needs them apart (he_rescale allows out == in)
+    const u64 *in_end = in + (long long)(B - 1) * is + ncomp * lc;
+    const u64 *out_end = out + (long long)(B - 1) * os + (long long)ncomp * l * N;
+    const bool apart = out >= in_end || in >= out_end;
+    if (hek::fused_ok(c) && apart) {
+        // a one-prime ModDown: the last limbs to coefficient form, then the
+        // centred conversion to q_0..q_{l-1} inside the first forward pass and
+        // (c_i - x) q_l^{-1} stored by the second
+        hek::intt_last(c, l, B, ncomp, in, is, lastc);
+        hek::ntt_rescale(c, l, B, ncomp, lastc, in, is, tmp, out, os);
+    } else {
+        hek::ewise(c, 4, 0, B, ncomp, in + (long long)l * N, is, lc, nullptr, 0, 0, lastc, (long long)ncomp * N,
+                   (long long)N, 0);
+        // the limbs use prime q_l: address them as position l of a shifted base
+        hek::ntt_batch(c, lastc - (long long)l * N, (long long)ncomp * N, (long long)N, B, ncomp, l, 1, l, -1,
+                       nullptr, false);
+        hek::rescale_bcast_b(c, l, B, lastc, tmp, ncomp);
+        hek::ntt_batch(c, tmp, (long long)ncomp * l * N, (long long)l * N, B, ncomp, 0, l, l - 1, +1, nullptr,
+                       false);
+        hek::rescale_finish_b(c, l, B, in, is, tmp, out, os, ncomp);
+    }
     ar.off = mark;
     return last_error();
 }
@@ -340,13 +354,26 @@ he_status build_tables(he_ctx *c)
     }
     for (int i = 0; i < nq; ++i) dn_pd[i] = (double)dn_p[2 * i];
     std::vector<u64> rs_qinv((size_t)nq * nq * 2, 0), rs_ql((size_t)nq * nq, 0);
-    for (int l = 1; l < nq; ++l)
+    std::vector<u64> rs_one((size_t)nq * 2), rs_ql2((size_t)nq * nq * 2, 0);
+    std::vector<double> rs_oned((size_t)nq * nq * 2, 0.0), rs_qld((size_t)nq * nq, 0.0);
+    for (int i = 0; i < nq; ++i) {
+        rs_one[2 * i] = 1;
+        rs_one[2 * i + 1] = shoup(1, c->q[i]);
+    }
+    for (int l = 1; l < nq; ++l) {
+        const int S = conv_split_bits(bits(c->q[l]));
         for (int i = 0; i < l; ++i) {
             u64 qi = c->q[i], v = invmod(c->q[l] % qi, qi);
             rs_qinv[((size_t)l * nq + i) * 2] = v;
             rs_qinv[((size_t)l * nq + i) * 2 + 1] = shoup(v, qi);
             rs_ql[(size_t)l * nq + i] = c->q[l] % qi;
+            rs_ql2[((size_t)l * nq + i) * 2] = c->q[l] % qi;
+            rs_ql2[((size_t)l * nq + i) * 2 + 1] = shoup(c->q[l] % qi, qi);
+            rs_oned[((size_t)l * nq + i) * 2] = 1.0;
+            rs_oned[((size_t)l * nq + i) * 2 + 1] = (double)pow2mod(S, qi);
+            rs_qld[(size_t)l * nq + i] = (double)(c->q[l] % qi);
         }
+    }
     DeviceTables &t = c->t;
     t.pinfo = dev_upload(c, pi);
     t.psi = dev_upload(c, psi);
@@ -368,11 +395,15 @@ he_status build_tables(he_ctx *c)
     t.qinv_d = dev_upload(c, qinv_d);
     t.dn_convd = dev_upload(c, dn_convd);
     t.dn_pd = dev_upload(c, dn_pd);
+    t.rs_one = dev_upload(c, rs_one);
+    t.rs_ql2 = dev_upload(c, rs_ql2);
+    t.rs_oned = dev_upload(c, rs_oned);
+    t.rs_qld = dev_upload(c, rs_qld);
     t.rs_qinv = dev_upload(c, rs_qinv);
     t.rs_ql = dev_upload(c, rs_ql);
     if (!t.pinfo || !t.psi || !t.psi_sh || !t.ipsi || !t.ipsi_sh || !t.psi_d || !t.ipsi_d || !t.up_scale || !t.up_conv || !t.up_qd ||
         !t.dn_scale || !t.dn_conv || !t.dn_p || !t.dn_pinv || !t.rs_qinv || !t.rs_ql || !t.up_convd || !t.up_qdd ||
-        !t.qinv_d || !t.dn_convd || !t.dn_pd)
+        !t.qinv_d || !t.dn_convd || !t.dn_pd || !t.rs_one || !t.rs_ql2 || !t.rs_oned || !t.rs_qld)
         return HE_ENOMEM;
     return HE_OK;
 }

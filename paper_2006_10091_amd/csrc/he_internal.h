@@ -45,6 +45,11 @@ struct DeviceTables {
     // Rescale: rs_qinv[l][i] = q_l^{-1} mod q_i, rs_ql[l][i] = q_l mod q_i  (i < l)
     u64 *rs_qinv;            // [nq][nq][2]
     u64 *rs_ql;              // [nq][nq]
+    // Rescale as a one-prime ModDown (source q_l, targets q_i, i < l):
+    u64 *rs_one;             // [nq][2]  (1, Shoup of 1) mod q_i: the conversion constant
+    u64 *rs_ql2;             // [nq][nq][2] q_l mod q_i (+ Shoup): the centring term
+    double *rs_oned;         // [nq][nq][2] (1, 2^S_l mod q_i), S_l = conv_split_bits(bit length of q_l)
+    double *rs_qld;          // [nq][nq] q_l mod q_i
 };
 
 struct GraphEntry {
@@ -111,6 +116,9 @@ bool fused_ok(const he_ctx *c);
 void intt_from(he_ctx *c, const u64 *src, long long sbs, u64 *dst, long long dbs, int B, int level, const u64 *post);
 void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs, const u64 *base,
                  long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs);
+void ntt_rescale(he_ctx *c, int level, int B, int ncomp, const u64 *last, const u64 *in, long long is, u64 *tmp,
+                 u64 *out, long long os);
+void intt_last(he_ctx *c, int level, int B, int ncomp, const u64 *in, long long is, u64 *last);
 // op 0 add, 1 sub, 2 multiply by integer k, 3 multiply by plaintext y ([pos][N]), 4 copy;
 // positions 0..level of nbatch x ncomp polys.
 void ewise(he_ctx *c, int op, int level, int nbatch, int ncomp, const u64 *x, long long xb, long long xc,

@@ -365,6 +365,26 @@ __device__ __forceinline__ double mulmod_lazy_d(double a, double w, double q, do
     double qt = floor(hi * qinv);
     return __fma_rn(-qt, q, hi) + lo;
 }
+// Exact conversions between FP64 and integers through the exponent bits (two
+// operations each): an unsigned value below 2^52 is the mantissa of
+// 2^52 + v; a signed one of magnitude below 2^51 (two's complement bits) that
+// of 1.5 * 2^52 + v.  Every lazy path keeps its values inside these ranges.
+__device__ __forceinline__ double d_from_u52(u64 v)
+{
+    return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - 4503599627370496.0;
+}
+__device__ __forceinline__ double d_from_s51(u64 v)
+{
+    return __longlong_as_double((long long)(v + 0x4338000000000000ull)) - 6755399441055744.0;
+}
+__device__ __forceinline__ u64 u52_from_d(double x)
+{
+    return (u64)__double_as_longlong(x + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull;
+}
+__device__ __forceinline__ u64 s51_from_d(double x)
+{
+    return (u64)__double_as_longlong(x + 6755399441055744.0) - 0x4338000000000000ull;
+}
 __device__ __forceinline__ double reduce_d(double x, double q, double qinv)
 {
     double qt = floor(x * qinv);
@@ -457,19 +477,22 @@ __device__ __forceinline__ u64 reduce4q(u64 v, u64 q, u64 q2)
 }
 
 // Fusion around the two passes (all optional, chosen per launch):
-//   pass A prologue  PRO_MODDOWN : input = ModDown conversion of the special-prime residues (acc)
+//   pass A prologue  PRO_MODDOWN : input = centred conversion of the source residues to the
+//                                  limb's prime (ModDown: the special primes; rescale: q_l)
 //   pass B (inverse) PRO_SRC     : read the limb from another buffer (out-of-place)
 //   pass B epilogue  EPI_FINISH  : store base + (acc - x) P^{-1} instead of x
 enum { PRO_NONE = 0, PRO_MODDOWN = 2, PRO_SRC = 3 };
 enum { EPI_NONE = 0, EPI_FINISH = 1 };
 
 struct Fuse {
-    const u64 *src;      // acc (ModDown) / source limbs (PRO_SRC)
+    const u64 *src;      // conversion sources (acc / last limbs) or source limbs (PRO_SRC)
     long long sbs, scs;  // batch / component strides of src
-    const u64 *cvt;      // ModDown: dn_conv
-    const u64 *cnt;      // ModDown: dn_p
-    const double *cvtd;  // FP64 forms: dn_convd
-    const double *cntd;  // dn_pd
+    long long soff;      // conversion: limb offset of the first source in src[b][c]
+    int nsrc, sp0;       // conversion: number of sources, prime index of the first
+    const u64 *cvt;      // conversion constants [source][target][2]: dn_conv / rs_one
+    const u64 *cnt;      // centring term [target][2]: dn_p / rs_ql2 of the level
+    const double *cvtd;  // FP64 forms: dn_convd / rs_oned of the level
+    const double *cntd;  // dn_pd / rs_qld of the level
     int alpha, np, nk;
     const u64 *acc;      // finish: acc [b][comp][pos], strides as / acs
     long long as, acs;
@@ -516,28 +539,29 @@ __device__ __forceinline__ void conv_setup_fp(ConvConst &cc, const PrimeInfo *pi
     cc.fp = conv_fp_ok(kmax, kp);
 }
 
-// ModDown prologue constants: sources are the special primes, the target is
-// q_pos of this workgroup
+// conversion prologue constants: sources are primes sp0 .. sp0 + nsrc - 1
+// (ModDown: the special primes; rescale: q_l), the target is q_pos of this
+// workgroup
 __device__ __forceinline__ void conv_setup(const NttArgs &a, const Fuse &f, const PrimeInfo *pinfo, int tp,
                                            ConvConst &cc)
 {
     const int z = (int)blockIdx.z + a.zoff;
     const int b = z / a.ncomp, c = z % a.ncomp;
     const int pos = a.pos0 + (int)blockIdx.y;  // target q_pos
-    cc.n = f.nk;
-    cc.src = f.src + b * f.sbs + c * f.scs + ((long long)(a.ell + 1) << a.logN);
+    cc.n = f.nsrc;
+    cc.src = f.src + b * f.sbs + c * f.scs + (f.soff << a.logN);
 #pragma unroll
     for (int i = 0; i < MAXW; ++i) {
         if (i < cc.n) {
             const u64 *e = f.cvt + ((long long)i * a.nq + pos) * 2;
             cc.c[i] = e[0];
             cc.cs[i] = e[1];
-            cc.half[i] = pinfo[a.nq + i].q >> 1;
+            cc.half[i] = pinfo[f.sp0 + i].q >> 1;
         }
     }
     cc.k = f.cnt[2 * pos];
     cc.ks = f.cnt[2 * pos + 1];
-    conv_setup_fp(cc, pinfo, a.nq, f.cvtd + (long long)pos * 2, 2LL * a.nq, f.cntd[pos], (int)pinfo[tp].k);
+    conv_setup_fp(cc, pinfo, f.sp0, f.cvtd + (long long)pos * 2, 2LL * a.nq, f.cntd[pos], (int)pinfo[tp].k);
 }
 
 // centred fast basis conversion of one coefficient (offset off in the limb) to
@@ -588,15 +612,15 @@ __device__ __forceinline__ void conv_column_d(const ConvConst &cc, long long off
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
                     cnt[k] += v[k] > half;
-                    d[k] += mulmod_lazy_d((double)v[k], c0, pd, pinv);
+                    d[k] += mulmod_lazy_d(d_from_u52(v[k]), c0, pd, pinv);
                 }
             } else {
                 const u64 m = (1ull << sh) - 1;
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
                     cnt[k] += v[k] > half;
-                    d[k] += mulmod_lazy_d((double)(v[k] >> sh), c1, pd, pinv) +
-                            mulmod_lazy_d((double)(v[k] & m), c0, pd, pinv);
+                    d[k] += mulmod_lazy_d((double)(u32)(v[k] >> sh), c1, pd, pinv) +
+                            mulmod_lazy_d((double)(u32)(v[k] & m), c0, pd, pinv);
                 }
             }
         }
@@ -642,13 +666,13 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
                 conv_column_d<S::E>(cv, (long long)tau * N2 + col, (long long)S::T * N2, d, qd, qinv, LOGN);
             } else {
 #pragma unroll
-                for (int k = 0; k < S::E; ++k) d[k] = (double)load(tau + S::T * k);
+                for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(load(tau + S::T * k));
             }
             fwd_stages_ds<LM, false, true>(d, tau, 0, 0, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, true);
             fwd_stages_ds<LM, false, false>(d, tau, 0, 0, Wd, qd, qinv);
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) limb[(long long)(S::E * tau + k) * N2 + col] = (u64)(long long)d[k];
+            for (int k = 0; k < S::E; ++k) limb[(long long)(S::E * tau + k) * N2 + col] = s51_from_d(d[k]);
         } else if (!INV) {
 #pragma unroll
             for (int k = 0; k < S::E; ++k) d[k] = (double)load(tau + S::T * k);
@@ -659,7 +683,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
             for (int k = 0; k < S::E; ++k) limb[(long long)(S::E * tau + k) * N2 + col] = (u64)d[k];
         } else if (q < (1ull << 42)) {  // lazy inverse: input reduced by the row pass
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) d[k] = (double)limb[(long long)(S::E * tau + k) * N2 + col];
+            for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(limb[(long long)(S::E * tau + k) * N2 + col]);
             inv_stages_ds<LM, false, false>(d, tau, 0, 0, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, false);
             inv_stages_ds<LM, false, true>(d, tau, 0, 0, Wd, qd, qinv);
@@ -667,8 +691,8 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
             const double scd = (double)sc;
 #pragma unroll
             for (int k = 0; k < S::E; ++k)
-                limb[(long long)(tau + S::T * k) * N2 + col] = (u64)reduce_d(mulmod_lazy_d(d[k], scd, qd, qinv), qd,
-                                                                            qinv);
+                limb[(long long)(tau + S::T * k) * N2 + col] = u52_from_d(reduce_d(mulmod_lazy_d(d[k], scd, qd, qinv),
+                                                                                  qd, qinv));
         } else {
 #pragma unroll
             for (int k = 0; k < S::E; ++k) d[k] = (double)limb[(long long)(S::E * tau + k) * N2 + col];
@@ -760,18 +784,41 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
         if (!INV && q < (1ull << 46)) {  // signed lazy: input is the column pass's signed intermediate
 #pragma unroll
             for (int k = 0; k < S::E; ++k)
-                d[k] = (double)(long long)__builtin_nontemporal_load(in + tau + S::T * k);
+                d[k] = d_from_s51(__builtin_nontemporal_load(in + tau + S::T * k));
+            // finish operands are loaded before the stages, so their latency overlaps them
+            u64 fa[FIN ? S::E : 1], fb[FIN ? S::E : 1];
+            if (FIN) {
+                const u64 *ap = f.acc + b * f.as + c * f.acs + roff + tau;
+                const u64 *bp = f.base + b * f.bs + c * f.bcs + roff + tau;
+#pragma unroll
+                for (int k = 0; k < S::E; ++k) {
+                    fa[k] = ap[S::T * k];
+                    fb[k] = c < f.nbase ? bp[S::T * k] : 0;
+                }
+            }
             fwd_stages_ds<LM, true, true>(d, tau, h, N1, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, true);
             fwd_stages_ds<LM, true, false>(d, tau, h, N1, Wd, qd, qinv);
             __syncthreads();
             exch_d<LM>(d, dl, tau, false);
+            if (FIN) {
+                // base + (acc - x) P^{-1}: the lazy product is in (-q, 2q), the sum in (-q, 3q)
+                const double pinv = d_from_u52(f.pinv[2 * pos]);
+                u64 *op = f.out + b * f.os + c * f.ocs + roff + tau;
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) store(k, (u64)reduce_d(d[k], qd, qinv));
+                for (int k = 0; k < S::E; ++k) {
+                    const double x = reduce_d(d[k], qd, qinv);
+                    const double r = mulmod_lazy_d(d_from_u52(fa[k]) - x, pinv, qd, qinv) + d_from_u52(fb[k]);
+                    op[S::T * k] = u52_from_d(reduce_d(r, qd, qinv));
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < S::E; ++k) store(k, u52_from_d(reduce_d(d[k], qd, qinv)));
+            }
             return;
         }
 #pragma unroll
-        for (int k = 0; k < S::E; ++k) d[k] = (double)__builtin_nontemporal_load(in + tau + S::T * k);
+        for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(__builtin_nontemporal_load(in + tau + S::T * k));
         if (!INV) {
             stages_d<LM, true, false, true>(d, tau, h, N1, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, true);
@@ -792,7 +839,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
             inv_stages_ds<LM, true, true>(d, tau, h, N1, Wd, qd, qinv);
 #pragma unroll
             for (int k = 0; k < S::E; ++k)
-                __builtin_nontemporal_store((u64)reduce_d(d[k], qd, qinv), row + tau + S::T * k);
+                __builtin_nontemporal_store(u52_from_d(reduce_d(d[k], qd, qinv)), row + tau + S::T * k);
         } else {
             exch_d<LM>(d, dl, tau, true);
             stages_d<LM, true, true, false>(d, tau, h, N1, Wd, qd, qinv);
@@ -877,12 +924,12 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_ks_t(KsArgs a, const Pr
             if (t >= d0 && t < d1) {
                 const u64 *src = a.d2 + b * a.d2s + roff;
 #pragma unroll
-                for (int k = 0; k < S::E; ++k) d[k] = (double)src[tau + S::T * k];
+                for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(src[tau + S::T * k]);
             } else {
                 const u64 *src = a.ext + b * a.es + j * a.ds + roff;
 #pragma unroll
                 for (int k = 0; k < S::E; ++k)
-                    d[k] = (double)(long long)__builtin_nontemporal_load(src + tau + S::T * k);
+                    d[k] = d_from_s51(__builtin_nontemporal_load(src + tau + S::T * k));
                 fwd_stages_ds<LM, true, true>(d, tau, h, N1, Wd, qd, qinv);
                 exch_d<LM>(d, dl, tau, true);
                 fwd_stages_ds<LM, true, false>(d, tau, h, N1, Wd, qd, qinv);
@@ -894,15 +941,15 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_ks_t(KsArgs a, const Pr
 #pragma unroll
             for (int k = 0; k < S::E; ++k) {
                 const int e = tau + S::T * k;
-                s0[k] += mulmod_lazy_d(d[k], (double)kj[e], qd, qinv);
-                s1[k] += mulmod_lazy_d(d[k], (double)kj[keylimb + e], qd, qinv);
+                s0[k] += mulmod_lazy_d(d[k], d_from_u52(kj[e]), qd, qinv);
+                s1[k] += mulmod_lazy_d(d[k], d_from_u52(kj[keylimb + e]), qd, qinv);
             }
         }
 #pragma unroll
         for (int k = 0; k < S::E; ++k) {
             const int e = tau + S::T * k;
-            o[e] = (u64)reduce_d(s0[k], qd, qinv);
-            o[((long long)a.nb << LOGN) + e] = (u64)reduce_d(s1[k], qd, qinv);
+            o[e] = u52_from_d(reduce_d(s0[k], qd, qinv));
+            o[((long long)a.nb << LOGN) + e] = u52_from_d(reduce_d(s1[k], qd, qinv));
         }
         return;
     }
@@ -1077,20 +1124,20 @@ __global__ __launch_bounds__(256) void modup_kernel(const u64 *__restrict__ y, l
                     const double *e = cvd + ((long long)i * np + tp) * 2;
                     const int ki = (int)pinfo[d0 + i].k;
                     if (conv_whole(ki, kp)) {
-                        s0 += mulmod_lazy_d((double)v[i][0], e[0], pd, pinv);
-                        s1 += mulmod_lazy_d((double)v[i][1], e[0], pd, pinv);
+                        s0 += mulmod_lazy_d(d_from_u52(v[i][0]), e[0], pd, pinv);
+                        s1 += mulmod_lazy_d(d_from_u52(v[i][1]), e[0], pd, pinv);
                     } else {
                         const int S = conv_split_bits(ki);
                         const u64 m = (1ull << S) - 1;
-                        s0 += mulmod_lazy_d((double)(v[i][0] >> S), e[1], pd, pinv) +
-                              mulmod_lazy_d((double)(v[i][0] & m), e[0], pd, pinv);
-                        s1 += mulmod_lazy_d((double)(v[i][1] >> S), e[1], pd, pinv) +
-                              mulmod_lazy_d((double)(v[i][1] & m), e[0], pd, pinv);
+                        s0 += mulmod_lazy_d((double)(u32)(v[i][0] >> S), e[1], pd, pinv) +
+                              mulmod_lazy_d((double)(u32)(v[i][0] & m), e[0], pd, pinv);
+                        s1 += mulmod_lazy_d((double)(u32)(v[i][1] >> S), e[1], pd, pinv) +
+                              mulmod_lazy_d((double)(u32)(v[i][1] & m), e[0], pd, pinv);
                     }
                 }
             }
-            r.x = (u64)reduce_d(s0, pd, pinv);
-            r.y = (u64)reduce_d(s1, pd, pinv);
+            r.x = u52_from_d(reduce_d(s0, pd, pinv));
+            r.y = u52_from_d(reduce_d(s1, pd, pinv));
         } else {
             // exact 128-bit sum of the products (each < 2^120), one reduction
             u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
@@ -1703,6 +1750,9 @@ void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 
     f.src = acc;
     f.sbs = as;
     f.scs = nb * N;
+    f.soff = level + 1;
+    f.nsrc = c->nk;
+    f.sp0 = c->nq;
     f.cvt = c->t.dn_conv;
     f.cnt = c->t.dn_p;
     f.cvtd = c->t.dn_convd;
@@ -1722,6 +1772,51 @@ void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 
     f.pinv = c->t.dn_pinv;
     NttArgs a = make_args(c, conv, cs, (level + 1) * N, 2, 0, level, false);
     ntt_launch(c, a, B, level + 1, +1, nullptr, PRO_MODDOWN, EPI_FINISH, &f);
+}
+
+// Rescale of B ciphertexts of ncomp components at level l as a one-prime
+// ModDown: the last limbs, already in coefficient form in last [b][comp][N],
+// are converted (centred) to q_0 .. q_{l-1} inside the first forward pass, and
+// the second pass stores (in - x) q_l^{-1} into out.  tmp [b][comp][l][N]
+// holds the intermediate between the passes.
+void ntt_rescale(he_ctx *c, int level, int B, int ncomp, const u64 *last, const u64 *in, long long is, u64 *tmp,
+                 u64 *out, long long os)
+{
+    const long long N = c->N, lc_in = (level + 1) * N, lc_out = (long long)level * N;
+    Fuse f{};
+    f.src = last;
+    f.sbs = ncomp * N;
+    f.scs = N;
+    f.soff = 0;
+    f.nsrc = 1;
+    f.sp0 = level;
+    f.cvt = c->t.rs_one;
+    f.cnt = c->t.rs_ql2 + (long long)level * c->nq * 2;
+    f.cvtd = c->t.rs_oned + (long long)level * c->nq * 2;
+    f.cntd = c->t.rs_qld + (long long)level * c->nq;
+    f.acc = in;
+    f.as = is;
+    f.acs = lc_in;
+    f.nbase = 0;
+    f.out = out;
+    f.os = os;
+    f.ocs = lc_out;
+    f.pinv = c->t.rs_qinv + (long long)level * c->nq * 2;
+    NttArgs a = make_args(c, tmp, ncomp * lc_out, lc_out, ncomp, 0, level - 1, false);
+    ntt_launch(c, a, B, level, +1, nullptr, PRO_MODDOWN, EPI_FINISH, &f);
+}
+
+// inverse NTT of the last limb (position l) of B ciphertexts of ncomp
+// components, read in place from in, written to last [b][comp][N]
+void intt_last(he_ctx *c, int level, int B, int ncomp, const u64 *in, long long is, u64 *last)
+{
+    const long long N = c->N;
+    Fuse f{};
+    f.src = in;
+    f.sbs = is;
+    f.scs = (level + 1) * N;
+    NttArgs a = make_args(c, last - (long long)level * N, ncomp * N, N, ncomp, level, level, false);
+    ntt_launch(c, a, B, 1, -1, nullptr, PRO_SRC, EPI_NONE, &f);
 }
 
 static void ew(he_ctx *c, int op, const EwArgs &a, int npos, int nbatch, i64 k)
