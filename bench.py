@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--layout", choices=("both", "feature-major", "row-major"), default="both",
                     help="packings to run (value needs feature-major)")
+    ap.add_argument("--baby", type=int, default=16,
+                    help="baby steps of the feature-major margin sum (1 = rotations only)")
     ap.add_argument("--ntt-counters", action="store_true",
                     help="run only the calibration copy and the NTT batch (a target for rocprofv3 --pmc passes, "
                          "which cannot follow the step's graph launches); prints no bench line")
@@ -208,7 +210,21 @@ def bench_layout(torch, H, T, ctx, keys, X, y, coef, layout, args, Wk):
     wt = np.random.default_rng(Wk["seed_w"]).uniform(-0.05, 0.05, d)
     Wt = ctx.encrypt(ctx.pt_load(ctx.encode(H.pack_weights(wt, ctx.S, c, layout), ctx.delta), L, ctx.delta), keys,
                      Wk["seed_enc"], 1 << 22)
-    workers = {mode: T.Worker(ctx, keys, Z, coef, eta_n, c, r, mode=mode, layout=layout) for mode in (0, 1, 2)}
+    n_baby = args.baby if layout == H.LAYOUT_FEATURES else 1
+    res["n_baby"] = n_baby
+    Zrot = None
+    if n_baby > 1:
+        # the worker's baby-step copies of its data: computed once per shard
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Zrot = ctx.rotate_data(Z, r, n_baby, keys)
+        torch.cuda.synchronize()
+        res["baby_step_data_s"] = time.perf_counter() - t0
+        res["baby_step_data_gib"] = len(Zrot) * 2 * (L + 1) * ctx.N * 8 / 2 ** 30
+        log("%s: baby-step data copies (%d per block, %.1f GiB) in %.2f s" % (
+            name, n_baby - 1, res["baby_step_data_gib"], res["baby_step_data_s"]))
+    workers = {mode: T.Worker(ctx, keys, Z, coef, eta_n, c, r, mode=mode, layout=layout, n_baby=n_baby, Zrot=Zrot)
+               for mode in (0, 1, 2)}
     outs = {}
     for mode in (0, 1, 2):
         Wn, g = workers[mode].step(Wt, want_g=True)
@@ -247,7 +263,7 @@ def bench_layout(torch, H, T, ctx, keys, X, y, coef, layout, args, Wk):
         log("%s, %s: schedule %.2f ms/step (%d steps); top-level step %.2f ms" % (
             name, key, dt / steps * 1e3, steps, res["top_level_step_ms_" + key]))
     res["batched_over_plain"] = res["steps_per_s_graph"] / res["steps_per_s_plain"]
-    del Z, workers
+    del Z, workers, Zrot
     return res
 
 
@@ -280,7 +296,8 @@ def main():
     if args.ks_counters:
         measure_copy_and_ks(torch, H, synth, ctx, ev)
         return
-    steps = sorted(set(H.rotation_steps(c, r, H.LAYOUT_ROWS)) | set(H.rotation_steps(c, r, H.LAYOUT_FEATURES)))
+    steps = sorted(set(H.rotation_steps(c, r, H.LAYOUT_ROWS)) |
+                   set(H.rotation_steps(c, r, H.LAYOUT_FEATURES, max(args.baby, 1))))
     t0 = time.time()
     keys = ctx.keygen(Wk["seed_keys"], steps)
     torch.cuda.synchronize()
@@ -314,9 +331,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "image-shard 6000x196, N=2^16, 20+4 primes, dnum 5, scale 2^40, 47 blocks; "
                                "training schedule: steps at levels 19/15/11/7, refresh every 4 steps; "
-                               "%s packing; batched form replayed from HIP graphs" % best["layout"],
+                               "%s packing%s; batched form replayed from HIP graphs" % (
+                                   best["layout"], ", %d baby steps" % best["n_baby"] if best["n_baby"] > 1 else ""),
                    "n": n, "d": int(X.shape[1]), "blocks": nb, "log_n": Wk["logN"], "n_q": Wk["nq"],
-                   "n_special": Wk["nk"], "refresh_every": REFRESH_EVERY, "layout": best["layout"]},
+                   "n_special": Wk["nk"], "refresh_every": REFRESH_EVERY, "layout": best["layout"],
+                   "n_baby": best["n_baby"]},
         "plain_steps_per_s": best["steps_per_s_plain"],
         "batched_nograph_steps_per_s": best["steps_per_s_batched"],
         "batched_over_plain": best["batched_over_plain"],

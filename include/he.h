@@ -107,6 +107,9 @@ typedef struct {
  * every slot of feature block j.  Same gradient, fewer key switches per block. */
 enum { HE_LAYOUT_ROWS = 0, HE_LAYOUT_FEATURES = 1 };
 
+/* Most baby steps a feature-major margin sum may take (he_lr_grad_step). */
+#define HE_MAXBABY 16
+
 /* Scale schedule of one gradient step (pure host; see he_plan_lr_step).
  * The polynomial's terms are formed unrescaled at one level with scale
  * s_c * q (C = A B3, B1 = M Z1 with Z1 at scale s_z1, k0 Z, B2 = A Z2),
@@ -257,6 +260,15 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  * cyclic sum over the feature blocks leaves m_i in every slot of sample i, then
  * the polynomial; once per step, the sum inside each feature block, the mask
  * and the replication over the block.
+ * Baby steps (feature-major only; n_baby a power of two, 1 <= n_baby <=
+ * min(c, HE_MAXBABY); 1 = none): the margin sum over the c feature blocks is
+ * split as sum_{g} Rot(sum_{j < n_baby} Rot(Z, j r) (x) Rot(W, j r), g n_baby r).
+ * The caller keeps Zrot[b * (n_baby - 1) + j - 1] = Rot(Z[b], j r) for
+ * j = 1 .. n_baby - 1 (he_rotate_many; one level >= W's, Z's scale, uniform
+ * strides in that order; NULL when n_baby = 1); the step rotates W by j r once
+ * for all blocks, sums the n_baby products per block without relinearising,
+ * and relinearises and rescales once: per block log2(c / n_baby) rotations
+ * instead of log2 c.  keys then also hold the rotations j r (j < n_baby).
  * Outputs (caller memory, W's level - 4): W_out, and G_out (nullable) = g.
  * mode 0: plain form (one he_* operation per block per step, one kernel
  * sequence each); mode 1: batched form (every block in one launch per
@@ -266,8 +278,8 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  */
 he_status he_lr_grad_step(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct *W,
                           const he_pt *mask, const double coef[4], double eta_over_n,
-                          double w_decay, int c, int r, int layout, const he_keys *keys, int mode,
-                          he_ct *W_out, he_ct *G_out);
+                          double w_decay, int c, int r, int layout, const he_ct *Zrot, int n_baby,
+                          const he_keys *keys, int mode, he_ct *W_out, he_ct *G_out);
 
 /*
  * Encrypted inference on one worker's blocks: the margins m_i = w.x_i of
@@ -284,10 +296,10 @@ he_status he_lr_margins(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct *
                         const he_keys *keys, int mode, he_ct *out);
 
 /* Device workspace (bytes) that he_lr_grad_step / he_lr_margins take for
- * n_blocks blocks with weights at `level` in `mode` (the context keeps and
- * grows one workspace; callers doing admission control budget with this).
- * 0 for invalid arguments. */
-size_t he_lr_step_bytes(const he_ctx *ctx, int level, int n_blocks, int layout, int mode);
+ * n_blocks blocks with weights at `level` in `mode` (with n_baby baby steps for
+ * the step; the context keeps and grows one workspace; callers doing
+ * admission control budget with this).  0 for invalid arguments. */
+size_t he_lr_step_bytes(const he_ctx *ctx, int level, int n_blocks, int layout, int n_baby, int mode);
 size_t he_lr_margins_bytes(const he_ctx *ctx, int level, int n_blocks, int mode);
 
 /* ---------------------------------------------------------------- batched operations */
@@ -310,6 +322,19 @@ size_t he_lr_margins_bytes(const he_ctx *ctx, int level, int n_blocks, int mode)
  */
 he_status he_batch_mul_rotate(he_ctx *ctx, const he_ct *x, const he_ct *y, const int *steps, int n,
                               const he_keys *keys, int mode, he_ct *out);
+
+/*
+ * Rotations of n ciphertexts by each of n_steps steps (Sec. 3 rotations; the
+ * baby-step copies of a shard's data for he_lr_grad_step):
+ *   out[i * n_steps + s] = Rot(x[i], steps[s]).
+ * x[0..n): one level and scale, one uniform stride apart; out: caller memory
+ * for n * n_steps ciphertexts at that level, one allocation with a uniform
+ * stride in that order, distinct from x.  Each step runs as one batched
+ * rotation of all n ciphertexts.  Errors before any launch: HE_EINVAL,
+ * HE_ELEVEL, HE_EKEY (a rotation key absent).
+ */
+he_status he_rotate_many(he_ctx *ctx, const he_ct *x, int n, const int *steps, int n_steps, const he_keys *keys,
+                         he_ct *out);
 
 /* ---------------------------------------------------------------- NTT (measurement) */
 

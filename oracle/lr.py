@@ -24,6 +24,13 @@ Readings where the paper is silent (each listed in the design notes):
     the polynomial runs on that directly, and after the cross-block sum the
     gradient is summed inside each feature block (rotations 1..r/2), masked to
     slot j*r and replicated by rotations -1..-r/2, once per step.
+  * the feature-major margin sum may take baby and giant steps: with n_b
+    baby steps, the worker keeps Rot(Z, b r) (b < n_b) of its own data and
+    rotates W by the same b r once per step, sums the n_b products
+    Rot(Z, b r) (x) Rot(W, b r) as one degree-2 ciphertext (a rotation is a
+    ring automorphism, so that is the sum of Rot(Z (x) W, b r)), relinearises
+    and rescales it once, and finishes with the giant-step rotations
+    n_b r .. (c/2) r.
   * the products C = A B3, B1 = M Z1 and B2 = A Z2 feed only additions, so
     they are formed at one level with one scale sC q (Z1's scale chosen for
     it), left unrelinearised and unrescaled, summed with the a0 term and across
@@ -255,12 +262,12 @@ def _plan_features(q, level, s_Z, s_W, coef, eta_over_n, w_decay):
                 level_out=level - 4, s_gsum=s_gsum, layout=FEATURES)
 
 
-def rotation_steps(c, r, layout=ROWS):
+def rotation_steps(c, r, layout=ROWS, n_baby=1):
     """Rotation steps used by the step.  Row-major: +-2^k (k < log2 c) and
     c*2^k (k < log2 r).  Feature-major: r*2^k (k < log2 c) and +-2^k
-    (k < log2 r)."""
+    (k < log2 r); with n_baby > 1 baby steps also b*r for b < n_baby."""
     if layout == FEATURES:
-        st = []
+        st = [b * r for b in range(3, n_baby) if b & (b - 1)]
         t = 1
         while t < c:
             st.append(t * r)
@@ -304,15 +311,18 @@ def add3_1(P, x3, y):
 
 
 # ---------------------------------------------------------------- encrypted step
-def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_decay=0.0, layout=ROWS):
+def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_decay=0.0, layout=ROWS, Zrot=None,
+                 n_baby=1):
     """One step of eq. (appr) + eq. (update) on ciphertexts (coefficient form).
     Z: list of block ciphertexts (same level >= W.level, same scale);
     W: weight ciphertext; mask_m: integer plaintext of column_mask at scale
-    plan['s_mask'].  Returns (W', g); g excludes the regulariser's -eta lambda w."""
+    plan['s_mask'].  Feature-major only: n_baby > 1 takes the margins by baby
+    and giant steps, with Zrot = rotate_data(P, keys, Z, r, n_baby).
+    Returns (W', g); g excludes the regulariser's -eta lambda w."""
     l = W.level
     pl = plan or plan_lr_step(P.q, l, Z[0].scale, W.scale, coef, eta_over_n, w_decay, layout)
     if layout == FEATURES:
-        return _step_features(P, keys, Z, W, mask_m, c, r, pl)
+        return _step_features(P, keys, Z, W, mask_m, c, r, pl, Zrot, n_baby)
     G = None
     for zb in Z:
         zl = O.drop(zb, l)
@@ -357,14 +367,36 @@ def _terms_prescale(P, zb, A, B3, M, Z1, Z2, lp, pl):
     return G
 
 
-def _step_features(P, keys, Z, W, mask_m, c, r, pl):
+def rotate_data(P, keys, Z, r, n_baby):
+    """The worker's baby-step copies of its data: Rot(z_b, b r) for
+    b = 1 .. n_baby - 1, per block."""
+    return [[O.rotate(P, zb, b * r, keys) for b in range(1, n_baby)] for zb in Z]
+
+
+def _margin_products(P, keys, zs, Ws, l, s1):
+    """RS(relin(sum_b zs[b] (x) Ws[b])) at scale s1: the baby-step sum of the
+    products, one degree-2 ciphertext relinearised and rescaled once."""
+    D = None
+    for zr, wr in zip(zs, Ws):
+        t3 = O.tensor(P, O.drop(zr, l), wr)[0]
+        D = t3 if D is None else add3(P, D, t3)
+    return O.rescale(P, O.relin(P, D, s1 * float(P.q[l]), l, keys), scale=s1)
+
+
+def _step_features(P, keys, Z, W, mask_m, c, r, pl, Zrot=None, n_baby=1):
     """Feature-major step; mask_m: integer plaintext of feature_mask at scale
     plan['s_mask'] (used at level l-3)."""
     l = W.level
     G = None
-    for zb in Z:
-        u = O.rescale(P, O.mul(P, O.drop(zb, l), W, keys), scale=pl["s1"])
-        t = 1
+    if n_baby > 1:
+        Ws = [W] + [O.rotate(P, W, b * r, keys) for b in range(1, n_baby)]
+    for k, zb in enumerate(Z):
+        if n_baby > 1:
+            u = _margin_products(P, keys, [zb] + list(Zrot[k]), Ws, l, pl["s1"])
+            t = n_baby
+        else:
+            u = O.rescale(P, O.mul(P, O.drop(zb, l), W, keys), scale=pl["s1"])
+            t = 1
         while t < c:  # margins: cyclic sum over the feature blocks
             u = O.add(P, u, O.rotate(P, u, t * r, keys))
             t *= 2

@@ -440,6 +440,7 @@ he_status make_evk(he_ctx *c, Arena &ar, u64 seed, uint32_t key_id, const u64 *s
 // ------------------------------------------------------------------ the gradient step
 struct StepBufs {
     u64 *T3, *U0, *U, *R, *M, *Y, *Z3, *Z1, *A, *B3, *C, *G, *Rg, *Y1, *Z2, *Gm, *G3;
+    u64 *Wr;  // feature-major baby steps: Rot(W, b r), b = 1 .. n_baby - 1
 };
 
 // Per-block intermediates sit one level higher in the feature-major circuit
@@ -447,7 +448,7 @@ struct StepBufs {
 // block's gradient terms C (and B1, B2, k0 Z) are summed unrescaled and
 // unrelinearised (three components) at level l-3+e, across the blocks too,
 // and the sum is relinearised and rescaled once per step.
-size_t step_bytes(const he_ctx *c, int l, int nb, int layout)
+size_t step_bytes(const he_ctx *c, int l, int nb, int layout, int n_baby = 1)
 {
     const size_t N = c->N;
     const int e = layout == HE_LAYOUT_FEATURES ? 1 : 0;
@@ -466,11 +467,15 @@ size_t step_bytes(const he_ctx *c, int l, int nb, int layout)
     n += al((size_t)2 * (l - 2) * N);                      // Y1
     n += al((size_t)2 * (l - 3) * N);                      // Gm
     size_t scratch = std::max(rotate_scratch(c, l, nb), rescale_scratch(c, l, nb));
+    if (n_baby > 1) {
+        n += al((size_t)(n_baby - 1) * 2 * (l + 1) * N);  // Wr
+        scratch = std::max(scratch, rotate_scratch(c, l, n_baby - 1));
+    }
     n += std::max(scratch, rotate_scratch(c, l - 3 + e, 1));
     return n * 8 + 4096;
 }
 
-he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, int layout, StepBufs &s)
+he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, int layout, int n_baby, StepBufs &s)
 {
     const size_t N = c->N;
     const int e = layout == HE_LAYOUT_FEATURES ? 1 : 0;
@@ -491,9 +496,11 @@ he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, int layout, StepBufs &
     s.Rg = ar.take((size_t)2 * (l - 3 + e) * N);
     s.Y1 = ar.take((size_t)2 * (l - 2) * N);
     s.Gm = ar.take((size_t)2 * (l - 3) * N);
+    s.Wr = n_baby > 1 ? ar.take((size_t)(n_baby - 1) * 2 * (l + 1) * N) : nullptr;
     u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Y, s.Z3, s.Z1, s.A, s.B3, s.C, s.Z2, s.G3, s.G, s.Rg, s.Y1, s.Gm};
     for (u64 *p : all)
         if (!p) return HE_ENOMEM;
+    if (n_baby > 1 && !s.Wr) return HE_ENOMEM;
     return HE_OK;
 }
 
@@ -589,9 +596,18 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
 // over the feature blocks (every slot of sample i ends with m_i), then the
 // polynomial one level above the row-major circuit; G (+)= sum of the terms
 // at level l-3.
+// Baby-step copies of the data for the feature-major margins: block b's copy
+// for baby step j (1 <= j < n_baby) at zr + b * zrb + (j - 1) * zrs, component
+// stride zrc.
+struct BabyData {
+    const u64 *zr = nullptr;
+    long long zrb = 0, zrs = 0, zrc = 0;
+    int n_baby = 1;
+};
+
 he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, const he_ct *Z,
                                long long zbs, int b0, int nb, const he_ct *W, int cols, int rows,
-                               const he_keys *keys, bool accumulate)
+                               const he_keys *keys, bool accumulate, const BabyData &bd)
 {
     const long long N = c->N;
     const int l = W->level;
@@ -599,10 +615,21 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
     const u64 *zp = Z[b0].data;
     const long long zc = (lz + 1) * N;
     const long long wc = (l + 1) * N;
-    // D1: u = RS(relin(Z (x) W)), level l-1
-    TRY(mul_relin_rescale(c, ar, s, l, nb, zp, zbs, zc, W->data, 0, wc, keys->rlk, s.U));
     const long long u1 = (long long)l * N;  // component stride at level l-1
-    for (int t = 1; t < cols; t <<= 1) {
+    int t0 = 1;
+    if (bd.n_baby > 1) {
+        // D1 by baby steps: u = RS(relin(sum_j Rot(Z, j r) (x) Rot(W, j r))), level l-1
+        const long long lc = (l + 1) * N;
+        hek::baby_sum_b(c, l, nb, bd.n_baby, zp, zbs, zc, bd.zr + b0 * bd.zrb, bd.zrb, bd.zrs, bd.zrc, W->data, wc,
+                        s.Wr, 2 * lc, lc, s.T3, 3 * lc, lc);
+        TRY(relin_apply(c, ar, l, nb, s.T3, 3 * lc, keys->rlk, s.U0, 2 * lc));
+        TRY(rescale_apply(c, ar, l, nb, s.U0, 2 * lc, s.U, 2 * u1));
+        t0 = bd.n_baby;
+    } else {
+        // D1: u = RS(relin(Z (x) W)), level l-1
+        TRY(mul_relin_rescale(c, ar, s, l, nb, zp, zbs, zc, W->data, 0, wc, keys->rlk, s.U));
+    }
+    for (int t = t0; t < cols; t <<= 1) {
         const u64 gal = galois_of(c, (long long)t * rows);
         const u64 *key = find_rot_key(keys, gal);
         if (!key) return HE_EKEY;
@@ -778,22 +805,33 @@ he_status margins_impl(he_ctx *c, const he_ct *Z, int n_blocks, long long zbs, c
 }
 
 // the whole step; nchunk = 1 (plain: per-block operations) or n_blocks (batched)
-he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_blocks, long long zbs, const he_ct *W,
-                    const he_pt *mask, int cols, int rows, const he_keys *keys, int chunk, he_ct *W_out,
-                    he_ct *G_out)
+he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_blocks, long long zbs, const BabyData &bd,
+                    const he_ct *W, const he_pt *mask, int cols, int rows, const he_keys *keys, int chunk,
+                    he_ct *W_out, he_ct *G_out)
 {
     const long long N = c->N;
     const int l = W->level;
     Arena ar = arena(c);
     StepBufs s;
     const bool fm = pl.layout == HE_LAYOUT_FEATURES;
-    TRY(step_alloc(c, ar, l, chunk, pl.layout, s));
+    TRY(step_alloc(c, ar, l, chunk, pl.layout, bd.n_baby, s));
+    if (fm && bd.n_baby > 1) {
+        // the baby steps of W, once per step for every block: Rot(W, j r), j = 1 .. n_baby - 1
+        const long long lc = (l + 1) * N;
+        hek::EntryKeys ek;
+        hek::EntryGal eg;
+        for (int j = 1; j < bd.n_baby; ++j) {
+            eg.g[j - 1] = galois_of(c, (long long)j * rows);
+            ek.k[j - 1] = find_rot_key(keys, eg.g[j - 1]);
+        }
+        TRY(rotate_multi_apply(c, ar, l, bd.n_baby - 1, W->data, 0, eg, ek, s.Wr, 2 * lc));
+    }
     for (int b0 = 0; b0 < n_blocks; b0 += chunk) {
         int nb = std::min(chunk, n_blocks - b0);
         long long bs = zbs;
         if (chunk == 1) bs = 0;
         if (fm)
-            TRY(step_blocks_features(c, ar, s, pl, Z, bs, b0, nb, W, cols, rows, keys, b0 > 0));
+            TRY(step_blocks_features(c, ar, s, pl, Z, bs, b0, nb, W, cols, rows, keys, b0 > 0, bd));
         else
             TRY(step_blocks(c, ar, s, pl, Z, bs, b0, nb, W, mask, cols, keys, b0 > 0));
     }
@@ -1265,12 +1303,14 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
 
 he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, const he_pt *mask,
                           const double coef[4], double eta_over_n, double w_decay, int cols, int rows, int layout,
-                          const he_keys *k, int mode, he_ct *W_out, he_ct *G_out)
+                          const he_ct *Zrot, int n_baby, const he_keys *k, int mode, he_ct *W_out, he_ct *G_out)
 {
     if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !mask || !mask->data || !coef || !k || mode < 0 || mode > 2)
         return HE_EINVAL;
     if (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES) return HE_EINVAL;
     const bool fm = layout == HE_LAYOUT_FEATURES;
+    if (n_baby < 1 || n_baby > HE_MAXBABY || (n_baby & (n_baby - 1)) || (n_baby > 1 && (!fm || n_baby > cols || !Zrot)))
+        return HE_EINVAL;
     if (W->level < 4) return HE_ELEVEL;
     if (!W_out || !W_out->data || (G_out && !G_out->data)) return HE_EINVAL;
     if (cols < 1 || rows < 1 || (cols & (cols - 1)) || (rows & (rows - 1)) || (long long)cols * rows != c->N / 2)
@@ -1288,6 +1328,25 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
     }
     if (lz < l) return HE_ELEVEL;
     if (mode > 0 && n_blocks > 1 && zbs < 2LL * (lz + 1) * c->N) return HE_EINVAL;
+    // baby-step copies: Zrot[b * (n_baby - 1) + j - 1] = Rot(Z[b], j rows), one level, one scale, uniform strides
+    BabyData bd;
+    bd.n_baby = n_baby;
+    if (n_baby > 1) {
+        const int m = n_baby - 1, lr = Zrot[0].level;
+        if (lr < l) return HE_ELEVEL;
+        bd.zr = Zrot[0].data;
+        bd.zrc = (long long)(lr + 1) * c->N;
+        bd.zrs = m > 1 ? Zrot[1].data - Zrot[0].data : 0;
+        bd.zrb = n_blocks > 1 ? Zrot[m].data - Zrot[0].data : 0;
+        for (int b = 0; b < n_blocks; ++b)
+            for (int j = 0; j < m; ++j) {
+                const he_ct &z = Zrot[b * m + j];
+                if (!ct_ok(c, &z) || z.level != lr || z.scale != sz) return z.level != lr ? HE_ELEVEL : HE_EINVAL;
+                if (z.data != bd.zr + b * bd.zrb + j * bd.zrs) return HE_EINVAL;  // uniform strides
+            }
+        if (m > 1 && bd.zrs < 2 * bd.zrc) return HE_EINVAL;
+        if (n_blocks > 1 && bd.zrb < (long long)m * 2 * bd.zrc) return HE_EINVAL;
+    }
     he_lr_plan pl;
     TRY(hehost::plan_lr_step(c->q.data(), c->nq, l, sz, W->scale, coef, eta_over_n, w_decay, layout, &pl));
     if (mask->scale != pl.s_mask) return HE_ESCALE;
@@ -1297,27 +1356,75 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
     const long long unit = fm ? rows : cols;
     for (int t = 1; t < pm; t <<= 1)
         if (!find_rot_key(k, galois_of(c, t)) || !find_rot_key(k, galois_of(c, -t))) return HE_EKEY;
-    for (int t = 1; t < st; t <<= 1)
+    for (int t = n_baby; t < st; t <<= 1)
         if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
+    for (int j = 1; j < n_baby; ++j)
+        if (!find_rot_key(k, galois_of(c, (long long)j * unit))) return HE_EKEY;
     const int chunk = mode == 0 ? 1 : n_blocks;
-    TRY(ensure_ws(c, step_bytes(c, l, chunk, layout)));
+    TRY(ensure_ws(c, step_bytes(c, l, chunk, layout, n_baby)));
     if (mode == 2) {
         std::ostringstream key;
         key << "step:" << (const void *)Z[0].data << ':' << zbs << ':' << n_blocks << ':' << lz << ':'
             << (const void *)W->data << ':' << l << ':' << (const void *)mask->data << ':' << cols << ':'
             << (const void *)k << ':' << (const void *)W_out->data << ':'
             << (const void *)(G_out ? G_out->data : nullptr) << ':' << pl.k0 << ':' << pl.k1 << ':' << pl.k2 << ':'
-            << pl.k3 << ':' << pl.kb1 << ':' << pl.kw << ':' << (const void *)c->ws << ':' << layout;
-        TRY(run_graph(c, key.str(),
-                      [&] { return step_impl(c, pl, Z, n_blocks, zbs, W, mask, cols, rows, k, chunk, W_out, G_out); }));
+            << pl.k3 << ':' << pl.kb1 << ':' << pl.kw << ':' << (const void *)c->ws << ':' << layout << ':' << n_baby
+            << ':' << (const void *)bd.zr << ':' << bd.zrb << ':' << bd.zrs << ':' << bd.zrc;
+        TRY(run_graph(c, key.str(), [&] {
+            return step_impl(c, pl, Z, n_blocks, zbs, bd, W, mask, cols, rows, k, chunk, W_out, G_out);
+        }));
     } else {
-        TRY(step_impl(c, pl, Z, n_blocks, zbs, W, mask, cols, rows, k, chunk, W_out, G_out));
+        TRY(step_impl(c, pl, Z, n_blocks, zbs, bd, W, mask, cols, rows, k, chunk, W_out, G_out));
     }
     W_out->level = l - 4;
     W_out->scale = pl.s_g;
     if (G_out) {
         G_out->level = l - 4;
         G_out->scale = pl.s_g;
+    }
+    return last_error();
+}
+
+he_status he_rotate_many(he_ctx *c, const he_ct *x, int n, const int *steps, int n_steps, const he_keys *k,
+                         he_ct *out)
+{
+    if (!c || !x || n < 1 || !steps || n_steps < 1 || !k || !out) return HE_EINVAL;
+    const int l = x[0].level;
+    const long long N = c->N, lc = (long long)(l + 1) * N;
+    long long xs = 0, os = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!ct_ok(c, &x[i]) || x[i].scale != x[0].scale) return HE_EINVAL;
+        if (x[i].level != l) return HE_ELEVEL;
+        if (i == 1) xs = x[1].data - x[0].data;
+        if (i > 1 && x[i].data - x[i - 1].data != xs) return HE_EINVAL;
+    }
+    if (n > 1 && xs < 2 * lc) return HE_EINVAL;
+    const int m = n * n_steps;
+    for (int i = 0; i < m; ++i) {
+        if (!out[i].data) return HE_EINVAL;
+        if (i == 1) os = out[1].data - out[0].data;
+        if (i > 1 && out[i].data - out[i - 1].data != os) return HE_EINVAL;
+    }
+    if (m > 1 && os < 2 * lc) return HE_EINVAL;
+    // outputs apart from the inputs
+    const u64 *x_end = x[0].data + (long long)(n - 1) * xs + 2 * lc;
+    const u64 *o_end = out[0].data + (long long)(m - 1) * os + 2 * lc;
+    if (!(o_end <= x[0].data || out[0].data >= x_end)) return HE_EINVAL;
+    std::vector<u64> gal(n_steps);
+    std::vector<const u64 *> key(n_steps);
+    for (int s = 0; s < n_steps; ++s) {
+        gal[s] = galois_of(c, steps[s]);
+        key[s] = find_rot_key(k, gal[s]);
+        if (!key[s]) return HE_EKEY;
+    }
+    TRY(ensure_ws(c, rotate_scratch(c, l, n) * 8 + 4096));
+    for (int s = 0; s < n_steps; ++s) {
+        Arena ar = arena(c);
+        TRY(rotate_apply(c, ar, l, n, x[0].data, xs, gal[s], key[s], out[s].data, (long long)n_steps * os));
+    }
+    for (int i = 0; i < m; ++i) {
+        out[i].level = l;
+        out[i].scale = x[0].scale;
     }
     return last_error();
 }
@@ -1356,11 +1463,13 @@ he_status he_batch_mul_rotate(he_ctx *c, const he_ct *x, const he_ct *y, const i
     return last_error();
 }
 
-size_t he_lr_step_bytes(const he_ctx *c, int level, int n_blocks, int layout, int mode)
+size_t he_lr_step_bytes(const he_ctx *c, int level, int n_blocks, int layout, int n_baby, int mode)
 {
     if (!c || level < 4 || level >= c->nq || n_blocks < 1 || (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES))
         return 0;
-    return step_bytes(c, level, mode == 0 ? 1 : n_blocks, layout);
+    if (n_baby < 1 || n_baby > HE_MAXBABY || (n_baby & (n_baby - 1)) || (n_baby > 1 && layout != HE_LAYOUT_FEATURES))
+        return 0;
+    return step_bytes(c, level, mode == 0 ? 1 : n_blocks, layout, n_baby);
 }
 
 size_t he_lr_margins_bytes(const he_ctx *c, int level, int n_blocks, int mode)

@@ -128,6 +128,10 @@ void tensor_b(he_ctx *c, int level, int B, const u64 *x, long long xb, long long
               long long yc, u64 *o, long long ob, long long oc);
 // ModUp basis conversion of every digit: y [B][l+1][N] scaled iNTT output,
 // ext [B][beta][l+1+nk][N] (positions outside each digit written)
+// baby-step margin products (MAX_BABY = 16 at most): o[blk] = sum_b Zb[blk] (x) Wb[b]
+void baby_sum_b(he_ctx *c, int level, int nblk, int nbaby, const u64 *z, long long zb, long long zc, const u64 *zr,
+                long long zrb, long long zrs, long long zrc, const u64 *w, long long wc, const u64 *wr, long long wrs,
+                long long wrc, u64 *o, long long ob, long long oc);
 void modup_b(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, long long es, long long ds);
 // inner product with one key shared by the batch: acc [B][2][l+1+nk][N]
 void ks_inner_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const u64 *ext, long long es,

@@ -890,6 +890,7 @@ struct KsArgs {
     u64 *acc;  // [b][2][nb][N]
     long long as;
     int alpha, beta, ell, nq, np, nb;
+    int nent;  // entries B
 };
 
 template <int LOGN>
@@ -900,9 +901,24 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_ks_t(KsArgs a, const Pr
     constexpr int LM = LOGN - (LOGN + 1) / 2, N1 = 1 << ((LOGN + 1) / 2);
     using S = LineShape<LM>;
     __shared__ u64 lds[S::LINES * S::PADDED];
-    const int b = blockIdx.x, t = blockIdx.z;
+    // one-dimensional grid over (entry, row block, position).  Workgroups are
+    // dealt to the 8 XCDs in turn; when the (row block, position) pairs split
+    // evenly, every entry of one pair lands on the same XCD, so that pair's
+    // key rows are fetched into one L2 once instead of once per XCD.
+    constexpr int NRB = N1 / S::LINES;
+    const int w = blockIdx.x, npair = NRB * a.nb;
+    int b, pr;
+    if ((npair & 7) == 0) {
+        const int sidx = w >> 3;
+        b = sidx % a.nent;
+        pr = (sidx / a.nent) * 8 + (w & 7);
+    } else {
+        b = w % a.nent;
+        pr = w / a.nent;
+    }
+    const int t = pr / NRB;
     const int tau = threadIdx.x % S::T, ln = threadIdx.x / S::T;
-    const int h = blockIdx.y * S::LINES + ln;
+    const int h = (pr % NRB) * S::LINES + ln;
     const int tp = prime_of(t, a.ell, a.nq);
     const PrimeInfo p = pinfo[tp];
     const u64 q = p.q;
@@ -1057,6 +1073,92 @@ __global__ __launch_bounds__(256) void tensor_kernel(const u64 *__restrict__ x, 
         o0[t] = mul_mod(a0, b0, p);
         o1[t] = add_mod(mul_mod(a0, b1, p), mul_mod(a1, b0, p), p.q);
         o2[t] = mul_mod(a1, b1, p);
+    }
+}
+
+// Baby-step margin products: o[blk] = sum_{b < nbaby} Zb[blk] (x) Wb[b], one
+// degree-2 ciphertext per block (NTT domain, limbs 0..l).  Zb[blk] is the block
+// itself for b = 0 and its rotated copy zr[blk][b-1] otherwise; Wb[0] = w and
+// Wb[b] = wr[b-1].  A thread keeps the W values of its coefficient in
+// registers and streams every block's data once.  Primes below 2^46: exact
+// lazy FP64 products, each in (-q, 2q), at most 2 * MAX_BABY = 32 of them per
+// sum, so every sum stays inside (-32q, 64q) and one reduction ends it; wider
+// primes: Barrett products and modular sums.
+constexpr int MAX_BABY = 16;
+struct BabyArgs {
+    const u64 *z;
+    long long zb, zc;  // blocks: block stride, component stride
+    const u64 *zr;
+    long long zrb, zrs, zrc;  // rotated data: block stride, baby-step stride, component stride
+    const u64 *w;
+    long long wc;  // W: component stride
+    const u64 *wr;
+    long long wrs, wrc;  // rotated W: baby-step stride, component stride
+    u64 *o;
+    long long ob, oc;  // output: block stride, component stride
+    int nbaby, nblk, logN;
+};
+
+__global__ __launch_bounds__(256) void baby_sum_kernel(BabyArgs a, const PrimeInfo *__restrict__ pinfo)
+{
+    const int i = blockIdx.y;
+    const PrimeInfo p = pinfo[i];
+    const long long off = ((long long)i << a.logN) + blockIdx.x * 256 + threadIdx.x;
+    if (p.q < (1ull << 46)) {
+        const double qd = (double)p.q, qinv = 1.0 / qd;
+        double w0[MAX_BABY], w1[MAX_BABY];
+#pragma unroll
+        for (int b = 0; b < MAX_BABY; ++b) {
+            if (b < a.nbaby) {
+                const u64 *wp = b == 0 ? a.w + off : a.wr + (b - 1) * a.wrs + off;
+                w0[b] = d_from_u52(wp[0]);
+                w1[b] = d_from_u52(wp[b == 0 ? a.wc : a.wrc]);
+            }
+        }
+        for (int blk = 0; blk < a.nblk; ++blk) {
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll
+            for (int b = 0; b < MAX_BABY; ++b) {
+                if (b < a.nbaby) {
+                    const u64 *zp = b == 0 ? a.z + blk * a.zb + off : a.zr + blk * a.zrb + (b - 1) * a.zrs + off;
+                    const double z0 = d_from_u52(zp[0]), z1 = d_from_u52(zp[b == 0 ? a.zc : a.zrc]);
+                    d0 += mulmod_lazy_d(z0, w0[b], qd, qinv);
+                    d1 += mulmod_lazy_d(z0, w1[b], qd, qinv) + mulmod_lazy_d(z1, w0[b], qd, qinv);
+                    d2 += mulmod_lazy_d(z1, w1[b], qd, qinv);
+                }
+            }
+            u64 *o = a.o + blk * a.ob + off;
+            o[0] = u52_from_d(reduce_d(d0, qd, qinv));
+            o[a.oc] = u52_from_d(reduce_d(d1, qd, qinv));
+            o[2 * a.oc] = u52_from_d(reduce_d(d2, qd, qinv));
+        }
+        return;
+    }
+    u64 w0[MAX_BABY], w1[MAX_BABY];
+#pragma unroll
+    for (int b = 0; b < MAX_BABY; ++b) {
+        if (b < a.nbaby) {
+            const u64 *wp = b == 0 ? a.w + off : a.wr + (b - 1) * a.wrs + off;
+            w0[b] = wp[0];
+            w1[b] = wp[b == 0 ? a.wc : a.wrc];
+        }
+    }
+    for (int blk = 0; blk < a.nblk; ++blk) {
+        u64 d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+        for (int b = 0; b < MAX_BABY; ++b) {
+            if (b < a.nbaby) {
+                const u64 *zp = b == 0 ? a.z + blk * a.zb + off : a.zr + blk * a.zrb + (b - 1) * a.zrs + off;
+                const u64 z0 = zp[0], z1 = zp[b == 0 ? a.zc : a.zrc];
+                d0 = add_mod(d0, mul_mod(z0, w0[b], p), p.q);
+                d1 = add_mod(d1, add_mod(mul_mod(z0, w1[b], p), mul_mod(z1, w0[b], p), p.q), p.q);
+                d2 = add_mod(d2, mul_mod(z1, w1[b], p), p.q);
+            }
+        }
+        u64 *o = a.o + blk * a.ob + off;
+        o[0] = d0;
+        o[a.oc] = d1;
+        o[2 * a.oc] = d2;
     }
 }
 
@@ -1696,8 +1798,10 @@ static void ks_fused_t(he_ctx *c, NttArgs a, int B, int beta, int nb, const KsAr
     dim3 gc((1 << (LOGN - LA)) / LineShape<LA>::LINES, nb, B * beta);
     ntt_cols_t<LOGN, false, PRO_NONE><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh,
                                                                           nullptr, c->t.psi_d, f);
-    dim3 gr(B, (1 << LA) / LineShape<LB>::LINES, nb);
-    ntt_rows_ks_t<LOGN><<<gr, LINE_THREADS, 0, c->stream>>>(k, c->t.pinfo, c->t.psi, c->t.psi_sh, c->t.psi_d);
+    KsArgs kk = k;
+    kk.nent = B;
+    dim3 gr(B * ((1 << LA) / LineShape<LB>::LINES) * nb, 1, 1);
+    ntt_rows_ks_t<LOGN><<<gr, LINE_THREADS, 0, c->stream>>>(kk, c->t.pinfo, c->t.psi, c->t.psi_sh, c->t.psi_d);
 }
 
 void ks_ntt_inner(he_ctx *c, int level, int B, const u64 *d2, long long d2s, u64 *ext, long long es, long long ds,
@@ -1852,6 +1956,15 @@ void tensor_b(he_ctx *c, int level, int B, const u64 *x, long long xb, long long
 {
     dim3 g(xblocks(c->N), level + 1, B);
     tensor_kernel<<<g, 256, 0, c->stream>>>(x, xb, xc, y, yb, yc, o, ob, oc, c->t.pinfo, c->logN);
+}
+
+void baby_sum_b(he_ctx *c, int level, int nblk, int nbaby, const u64 *z, long long zb, long long zc, const u64 *zr,
+                long long zrb, long long zrs, long long zrc, const u64 *w, long long wc, const u64 *wr, long long wrs,
+                long long wrc, u64 *o, long long ob, long long oc)
+{
+    BabyArgs a{z, zb, zc, zr, zrb, zrs, zrc, w, wc, wr, wrs, wrc, o, ob, oc, nbaby, nblk, c->logN};
+    dim3 g(c->N / 256, level + 1, 1);
+    baby_sum_kernel<<<g, 256, 0, c->stream>>>(a, c->t.pinfo);
 }
 
 void modup_b(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, long long es, long long ds)

@@ -92,12 +92,13 @@ _sig = {
     "he_plan_lr_step": (c_int, [_P(c_uint64), c_int, c_int, c_double, c_double, _P(c_double), c_double, c_double,
                                 c_int, _P(he_lr_plan)]),
     "he_lr_grad_step": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), _P(he_pt), _P(c_double), c_double, c_double,
-                                c_int, c_int, c_int, c_void_p, c_int, _P(he_ct), _P(he_ct)]),
+                                c_int, c_int, c_int, _P(he_ct), c_int, c_void_p, c_int, _P(he_ct), _P(he_ct)]),
+    "he_rotate_many": (c_int, [c_void_p, _P(he_ct), c_int, _P(c_int32), c_int, c_void_p, _P(he_ct)]),
     "he_batch_mul_rotate": (c_int, [c_void_p, _P(he_ct), _P(he_ct), _P(c_int32), c_int, c_void_p, c_int,
                                     _P(he_ct)]),
     "he_lr_margins": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), c_int, c_int, c_int, c_void_p, c_int,
                               _P(he_ct)]),
-    "he_lr_step_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int, c_int]),
+    "he_lr_step_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int, c_int, c_int]),
     "he_lr_margins_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int]),
     "he_ntt": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
 }
@@ -356,11 +357,13 @@ class Context:
         return plan_lr_step(self.primes, self.n_q, level, s_z, s_w, coef, eta_over_n, w_decay, layout)
 
     def lr_grad_step(self, Z, W, mask, coef, eta_over_n, cols, rows, keys, mode=1, W_out=None, G_out=None,
-                     want_g=True, w_decay=0.0, layout=LAYOUT_ROWS):
+                     want_g=True, w_decay=0.0, layout=LAYOUT_ROWS, Zrot=None, n_baby=1):
         """One encrypted gradient step (he_lr_grad_step).  Z: list of block
-        ciphertexts sharing one allocation (ct_block), packed in `layout`.
+        ciphertexts sharing one allocation (ct_block), packed in `layout`;
+        feature-major with n_baby > 1: Zrot = rotate_data(Z, rows, n_baby).
         Returns (W', g)."""
         zs = (he_ct * len(Z))(*[z.struct() for z in Z])
+        zr = (he_ct * len(Zrot))(*[z.struct() for z in Zrot]) if Zrot else None
         w, m = W.struct(), mask.struct()
         lo = max(W.level - 4, 0)
         W_out = W_out or self.ct_empty(lo)
@@ -370,7 +373,7 @@ class Context:
         go = G_out.struct() if want_g else None
         cf = np.ascontiguousarray(coef, dtype=np.float64)
         _chk(_lib.he_lr_grad_step(self.h, zs, len(Z), ctypes.byref(w), ctypes.byref(m), _f64p(cf), eta_over_n,
-                                  w_decay, cols, rows, layout, keys.handle, mode, ctypes.byref(wo),
+                                  w_decay, cols, rows, layout, zr, n_baby, keys.handle, mode, ctypes.byref(wo),
                                   ctypes.byref(go) if go is not None else None), "he_lr_grad_step")
         W_out.update(wo)
         if want_g:
@@ -391,8 +394,29 @@ class Context:
             o.update(s_)
         return out
 
-    def step_bytes(self, level, n_blocks, layout=LAYOUT_ROWS, mode=1):
-        return int(_lib.he_lr_step_bytes(self.h, level, n_blocks, layout, mode))
+    def step_bytes(self, level, n_blocks, layout=LAYOUT_ROWS, mode=1, n_baby=1):
+        return int(_lib.he_lr_step_bytes(self.h, level, n_blocks, layout, n_baby, mode))
+
+    def rotate_many(self, xs, steps, keys, outs=None):
+        """he_rotate_many: outs[i * len(steps) + s] = Rot(xs[i], steps[s]);
+        outs allocated as one block when None."""
+        m = len(xs) * len(steps)
+        outs = outs or self.ct_block(m, xs[0].level)
+        xa = (he_ct * len(xs))(*[x.struct() for x in xs])
+        oa = (he_ct * m)(*[o.struct() for o in outs])
+        st = np.ascontiguousarray(steps, dtype=np.int32)
+        _chk(_lib.he_rotate_many(self.h, xa, len(xs), st.ctypes.data_as(POINTER(c_int32)), len(steps), keys.handle,
+                                 oa), "he_rotate_many")
+        for o, s_ in zip(outs, oa):
+            o.update(s_)
+        return outs
+
+    def rotate_data(self, Z, rows, n_baby, keys):
+        """The baby-step copies of a feature-major shard for lr_grad_step:
+        Rot(Z[b], j rows) for j = 1 .. n_baby - 1, block by block."""
+        if n_baby <= 1:
+            return None
+        return self.rotate_many(Z, [j * rows for j in range(1, n_baby)], keys)
 
     def margins_bytes(self, level, n_blocks, mode=1):
         return int(_lib.he_lr_margins_bytes(self.h, level, n_blocks, mode))
@@ -469,10 +493,10 @@ def mask_level(level, layout=LAYOUT_ROWS):
     return level - 3 if layout == LAYOUT_FEATURES else level - 1
 
 
-def rotation_steps(c, r, layout=LAYOUT_ROWS):
-    """Rotation keys the step needs."""
+def rotation_steps(c, r, layout=LAYOUT_ROWS, n_baby=1):
+    """Rotation keys the step needs (with n_baby baby steps: also j r, j < n_baby)."""
     pm, st, unit = (r, c, r) if layout == LAYOUT_FEATURES else (c, r, c)
-    out = []
+    out = [j * unit for j in range(3, n_baby) if j & (j - 1)]
     t = 1
     while t < pm:
         out += [t, -t]

@@ -47,10 +47,18 @@ class ParameterServer:
 class Worker:
     """Evaluates the encrypted gradient step on its shard; Alg. 1."""
 
-    def __init__(self, ctx, keys, Z, coef, eta_over_n, cols, rows, mode=2, w_decay=0.0, layout=H.LAYOUT_ROWS):
+    def __init__(self, ctx, keys, Z, coef, eta_over_n, cols, rows, mode=2, w_decay=0.0, layout=H.LAYOUT_ROWS,
+                 n_baby=1, Zrot=None):
+        """n_baby > 1 (feature-major): the worker keeps the baby-step rotations
+        of its data (n_baby - 1 copies of the shard), computed here unless
+        given as Zrot (ctx.rotate_data)."""
         self.ctx, self.keys, self.Z = ctx, keys, Z
         self.coef, self.eta_over_n, self.w_decay = list(coef), eta_over_n, w_decay
         self.cols, self.rows, self.mode, self.layout = cols, rows, mode, layout
+        self.n_baby = n_baby
+        if n_baby > 1 and Zrot is None:
+            Zrot = ctx.rotate_data(Z, rows, n_baby, keys)
+        self.Zrot = Zrot if n_baby > 1 else None
         self._masks = {}
         self._bufs = {}
 
@@ -80,7 +88,7 @@ class Worker:
         G_out = self._out(lo, 1) if want_g else None
         return ctx.lr_grad_step(self.Z, W, mask, self.coef, self.eta_over_n, self.cols, self.rows, self.keys,
                                 mode=self.mode, W_out=W_out, G_out=G_out, want_g=want_g, w_decay=self.w_decay,
-                                layout=self.layout)
+                                layout=self.layout, Zrot=self.Zrot, n_baby=self.n_baby)
 
 
 def encrypt_shard(ctx, keys, X, y, seed_enc, layout=H.LAYOUT_ROWS):
@@ -94,14 +102,15 @@ def encrypt_shard(ctx, keys, X, y, seed_enc, layout=H.LAYOUT_ROWS):
 
 
 def train(ctx, keys, X, y, coef, eta, iterations, refresh_every, w0, seed_enc, mode=2, record=None, l2=0.0,
-          layout=H.LAYOUT_ROWS):
+          layout=H.LAYOUT_ROWS, n_baby=1):
     """Alg. 1 + Alg. 2 on one GPU.  Returns the server's final plaintext
     weights (after a last refresh) and, if `record` is a list, appends the
     decrypted weights after every iteration.  l2: lambda of R = lambda/2 |w|^2."""
     n, d = X.shape
     Z, cols, rows = encrypt_shard(ctx, keys, X, y, seed_enc, layout)
     ps = ParameterServer(ctx, keys, d, cols, seed_enc, layout=layout)
-    worker = Worker(ctx, keys, Z, coef, eta / n, cols, rows, mode=mode, w_decay=eta * l2, layout=layout)
+    worker = Worker(ctx, keys, Z, coef, eta / n, cols, rows, mode=mode, w_decay=eta * l2, layout=layout,
+                    n_baby=n_baby)
     W = ps.encrypt_weights(w0)
     for k in range(1, iterations + 1):
         W, _ = worker.step(W)

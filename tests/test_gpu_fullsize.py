@@ -4,10 +4,11 @@ launch configuration the bench times.
 * every key-switching operation of the step, bit for bit against the oracle,
   at the levels the step uses;
 * one-block steps (the whole circuit, the once-per-step sums included) bit for
-  bit against the oracle, in the batched form, in both block layouts;
-* the full 47-block shard in both layouts: the plain, batched and
-  graph-replayed forms agree bit for bit, and the decrypted gradient is within
-  2^-20 of the FP64 one;
+  bit against the oracle, in the batched form, in both block layouts, and
+  feature-major with 16 baby steps;
+* the full 47-block shard in both layouts (feature-major also with 16 baby
+  steps): the plain, batched and graph-replayed forms agree bit for bit, and
+  the decrypted gradient is within 2^-20 of the FP64 one;
 * 10 training steps with a refresh every 4, both layouts, against FP64.
 """
 import numpy as np
@@ -36,7 +37,7 @@ def env():
     ctx = H.Context(*CFG)
     X, y = synth.image_data(W["seed_data"], W["n"])
     blocks, c, r = H.pack_blocks(X, y, ctx.S)
-    steps = LR.rotation_steps(c, r)
+    steps = sorted(set(LR.rotation_steps(c, r)) | set(LR.rotation_steps(c, r, LR.FEATURES, 16)))
     gk = ctx.keygen(W["seed_keys"], steps)
     return dict(H=H, P=P, ctx=ctx, X=X, y=y, blocks=blocks, c=c, r=r, steps=steps, gk=gk)
 
@@ -72,14 +73,13 @@ def _as_grid(H, slots, c, r, layout):
     return v.reshape(c, r).T if layout == H.LAYOUT_FEATURES else v.reshape(r, c)
 
 
-@pytest.mark.parametrize("layout", [0, 1])
-def test_full_size_one_block_step_bit_exact(env, okeys, layout):
+@pytest.mark.parametrize("layout,n_baby", [(0, 1), (1, 1), (1, 16)])
+def test_full_size_one_block_step_bit_exact(env, okeys, layout, n_baby):
     """One block of the shard through the whole circuit, GPU batched form vs
-    oracle, in both layouts (the feature-major rotations are a subset of the
-    row-major key set at this shape)."""
+    oracle, in both layouts, and feature-major with baby steps."""
     ctx, P, gk = env["ctx"], env["P"], env["gk"]
     c, r = env["c"], env["r"]
-    assert set(LR.rotation_steps(c, r, layout)) <= set(env["steps"])
+    assert set(LR.rotation_steps(c, r, layout, n_baby)) <= set(env["steps"])
     coef = _coef()
     eta_n = 1.0 / 128
     blk = (LR.pack_blocks_features if layout else LR.pack_blocks)(env["X"], env["y"], P.S)[0][5]
@@ -94,16 +94,19 @@ def test_full_size_one_block_step_bit_exact(env, okeys, layout):
     gW = ctx.encrypt(ctx.pt_load(mw, P.L, P.delta), gk, 9, 999)
     pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n, 0.0, layout)
     mm = O.encode(LR.feature_mask(P.S, r) if layout else LR.column_mask(P.S, c), pl["s_mask"], P.N)
-    oWn, og = LR.lr_grad_step(P, okeys, [oZ], oW, mm, coef, eta_n, c, r, plan=pl, layout=layout)
+    oZr = LR.rotate_data(P, okeys, [oZ], r, n_baby) if n_baby > 1 else None
+    oWn, og = LR.lr_grad_step(P, okeys, [oZ], oW, mm, coef, eta_n, c, r, plan=pl, layout=layout, Zrot=oZr,
+                              n_baby=n_baby)
     H = env["H"]
     mask = ctx.pt_load(mm, H.mask_level(P.L, layout), pl["s_mask"])
-    Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, gk, mode=1, layout=layout)
+    gZr = ctx.rotate_data(gZ, r, n_baby, gk)
+    Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, gk, mode=1, layout=layout, Zrot=gZr, n_baby=n_baby)
     assert np.array_equal(ctx.download(Wn), oWn.data)
     assert np.array_equal(ctx.download(g), og.data)
 
 
-@pytest.mark.parametrize("layout", [0, 1])
-def test_full_shard_forms_agree_and_gradient_within_tolerance(env, layout):
+@pytest.mark.parametrize("layout,n_baby", [(0, 1), (1, 1), (1, 16)])
+def test_full_shard_forms_agree_and_gradient_within_tolerance(env, layout, n_baby):
     ctx, gk, H = env["ctx"], env["gk"], env["H"]
     L, S = ctx.n_q - 1, ctx.S
     X, y = env["X"], env["y"]
@@ -118,9 +121,11 @@ def test_full_shard_forms_agree_and_gradient_within_tolerance(env, layout):
     coef, eta_n = _coef(), 1.0 / X.shape[0]
     pl = ctx.plan_lr_step(L, ctx.delta, ctx.delta, coef, eta_n, layout=layout)
     mask = ctx.pt_load(ctx.encode(H.step_mask(S, c, layout), pl["s_mask"]), H.mask_level(L, layout), pl["s_mask"])
+    Zr = ctx.rotate_data(Z, r, n_baby, gk)
     outs = []
     for mode in (0, 1, 2, 2):
-        Wn, g = ctx.lr_grad_step(Z, Wc, mask, coef, eta_n, c, r, gk, mode=mode, layout=layout)
+        Wn, g = ctx.lr_grad_step(Z, Wc, mask, coef, eta_n, c, r, gk, mode=mode, layout=layout, Zrot=Zr,
+                                 n_baby=n_baby)
         outs.append((ctx.download(Wn), ctx.download(g)))
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
@@ -136,8 +141,8 @@ def test_full_shard_forms_agree_and_gradient_within_tolerance(env, layout):
         assert np.max(np.abs(wn[row, :d] - want)) / np.max(np.abs(want)) < 2.0 ** -20
 
 
-@pytest.mark.parametrize("layout", [0, 1])
-def test_full_size_training_ten_steps_refresh_every_four(env, layout):
+@pytest.mark.parametrize("layout,n_baby", [(0, 1), (1, 1), (1, 16)])
+def test_full_size_training_ten_steps_refresh_every_four(env, layout, n_baby):
     """The image shard's 10 steps with a refresh every 4 (Alg. 1 / Alg. 2),
     graph-replayed batched form, against FP64 plaintext training."""
     from paper_2006_10091_amd import train as T
@@ -146,7 +151,7 @@ def test_full_size_training_ten_steps_refresh_every_four(env, layout):
     coef = _coef()
     rec = []
     w_final = T.train(ctx, gk, X, y, coef, 1.0, 10, 4, np.zeros(X.shape[1]), 3004, mode=2, record=rec,
-                      layout=layout)
+                      layout=layout, n_baby=n_baby)
     w = np.zeros(X.shape[1])
     for k in range(10):
         w = w + LR.lr_gradient_fp64(X, y, w, coef, 1.0 / X.shape[0])

@@ -325,7 +325,7 @@ def small40():
     P = O.Params(*cfg)
     ctx = _H().Context(*cfg)
     c, r = 16, P.S // 16
-    steps = sorted(set(LR.rotation_steps(c, r)) | set(LR.rotation_steps(c, r, LR.FEATURES)))
+    steps = sorted(set(LR.rotation_steps(c, r)) | set(LR.rotation_steps(c, r, LR.FEATURES, 16)))
     return dict(W=W, P=P, ctx=ctx, okeys=O.Keys(P, W["seed_keys"], rot_steps=steps),
                 gkeys=ctx.keygen(W["seed_keys"], steps), H=_H())
 
@@ -365,6 +365,79 @@ def test_lr_step_feature_major_bit_exact(small40, loss, w_decay, n):
     gref = LR.lr_gradient_fp64(X, y, wdec, coef, eta_n)
     gd = ctx.decrypt_decode(g, small["gkeys"]).real.reshape(c, r)[:16]
     assert np.max(np.abs(gd - gref[:, None])) / np.max(np.abs(gref)) < TOL
+
+
+@pytest.mark.parametrize("n_baby,n", [(4, 700), (16, 700), (2, 256)])
+def test_lr_step_feature_major_baby_steps_bit_exact(small40, n_baby, n):
+    """Baby-step margins: he_rotate_many's copies of the data and the step in
+    its three forms, bit for bit against the oracle (n_baby = 16 = c: no giant
+    step), and the decrypted g within 2^-20 of FP64."""
+    small = small40
+    ctx, P, W, H = small["ctx"], small["P"], small["W"], small["H"]
+    X, y = synth.small_data(n=n)
+    blocks, c, r = LR.pack_blocks_features(X, y, P.S)
+    coef = _coef()
+    w0 = synth.initial_weights("small", 16, 93)
+    oZ, gZ = [], ctx.ct_block(blocks.shape[0], P.L)
+    for i in range(blocks.shape[0]):
+        m = O.encode(blocks[i], P.delta, P.N)
+        oZ.append(O.encrypt_sk(P, small["okeys"], m, P.L, P.delta, W["seed_enc"], i))
+        ctx.encrypt(ctx.pt_load(m, P.L, P.delta), small["gkeys"], W["seed_enc"], i, out=gZ[i])
+    oZr = LR.rotate_data(P, small["okeys"], oZ, r, n_baby)
+    gZr = ctx.rotate_data(gZ, r, n_baby, small["gkeys"])
+    assert len(gZr) == len(gZ) * (n_baby - 1)
+    for b in range(len(oZ)):
+        for j in range(n_baby - 1):
+            assert np.array_equal(ctx.download(gZr[b * (n_baby - 1) + j]), oZr[b][j].data), (b, j)
+    mw = O.encode(LR.pack_weights_features(w0, P.S, c), P.delta, P.N)
+    oW = O.encrypt_sk(P, small["okeys"], mw, P.L, P.delta, W["seed_enc"], 100003)
+    gW = ctx.encrypt(ctx.pt_load(mw, P.L, P.delta), small["gkeys"], W["seed_enc"], 100003)
+    eta_n = 1.0 / n
+    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n, 0.0, LR.FEATURES)
+    mm = O.encode(LR.feature_mask(P.S, r), pl["s_mask"], P.N)
+    oWn, og = LR.lr_grad_step(P, small["okeys"], oZ, oW, mm, coef, eta_n, c, r, plan=pl, layout=LR.FEATURES,
+                              Zrot=oZr, n_baby=n_baby)
+    mask = ctx.pt_load(mm, H.mask_level(P.L, H.LAYOUT_FEATURES), pl["s_mask"])
+    for mode in (0, 1, 2, 2):
+        Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, small["gkeys"], mode=mode,
+                                 layout=H.LAYOUT_FEATURES, Zrot=gZr, n_baby=n_baby)
+        assert np.array_equal(ctx.download(Wn), oWn.data), mode
+        assert np.array_equal(ctx.download(g), og.data), mode
+    wdec = ctx.decrypt_decode(gW, small["gkeys"]).real.reshape(c, r)[:16, 0]
+    gref = LR.lr_gradient_fp64(X, y, wdec, coef, eta_n)
+    gd = ctx.decrypt_decode(g, small["gkeys"]).real.reshape(c, r)[:16]
+    assert np.max(np.abs(gd - gref[:, None])) / np.max(np.abs(gref)) < TOL
+
+
+def test_lr_step_baby_step_errors(small40):
+    """Baby-step arguments are checked before any launch: a count that is not a
+    power of two or exceeds c, row-major, missing copies or keys."""
+    small = small40
+    ctx, P, H = small["ctx"], small["P"], small["H"]
+    blocks, c, r = LR.pack_blocks_features(*synth.small_data(n=256), P.S)
+    Z = ctx.ct_block(1, P.L)
+    ctx.encrypt(ctx.pt_load(O.encode(blocks[0], P.delta, P.N), P.L, P.delta), small["gkeys"], 5, 0, out=Z[0])
+    Wc = ctx.encrypt(ctx.pt_load(O.encode(np.zeros(P.S), P.delta, P.N), P.L, P.delta), small["gkeys"], 5, 1)
+    coef = _coef()
+    pl = ctx.plan_lr_step(P.L, P.delta, P.delta, coef, 1 / 256, layout=H.LAYOUT_FEATURES)
+    mask = ctx.pt_load(O.encode(LR.feature_mask(P.S, r), pl["s_mask"], P.N), P.L - 3, pl["s_mask"])
+    Zr4 = ctx.rotate_data(Z, r, 4, small["gkeys"])
+    for kw in (dict(n_baby=3, Zrot=Zr4), dict(n_baby=32, Zrot=Zr4), dict(n_baby=4, Zrot=None)):
+        with pytest.raises(H.HEError) as e:
+            ctx.lr_grad_step(Z, Wc, mask, coef, 1 / 256, c, r, small["gkeys"], layout=H.LAYOUT_FEATURES, **kw)
+        assert e.value.status == 1, kw
+    with pytest.raises(H.HEError) as e:  # copies at a level below W's
+        low = [ctx.drop_level(z, P.L - 1) for z in Zr4]
+        ctx.lr_grad_step(Z, Wc, mask, coef, 1 / 256, c, r, small["gkeys"], layout=H.LAYOUT_FEATURES, Zrot=low,
+                         n_baby=4)
+    assert e.value.status in (1, 3)
+    rk = ctx.keygen(3, LR.rotation_steps(c, r, LR.FEATURES))  # no key for the baby step 3 r
+    with pytest.raises(H.HEError) as e:
+        ctx.lr_grad_step(Z, Wc, mask, coef, 1 / 256, c, r, rk, layout=H.LAYOUT_FEATURES, Zrot=Zr4, n_baby=4)
+    assert e.value.status == 5
+    with pytest.raises(H.HEError) as e:
+        ctx.rotate_many(Z, [3 * r], rk)
+    assert e.value.status == 5
 
 
 def test_lr_step_feature_major_errors(small, small40):

@@ -551,6 +551,29 @@ def test_feature_major_packing_is_the_transpose():
     st = LR.rotation_steps(c, r, LR.FEATURES)
     assert st[:4] == [256, 512, 1024, 2048] and sorted(st[4:]) == sorted([t * s for t in (1, 2, 4, 8, 16, 32, 64, 128)
                                                                           for s in (1, -1)])
+    # baby steps b r for every b < n_baby, giant steps n_baby r .. (c/2) r
+    st8 = LR.rotation_steps(c, r, LR.FEATURES, 8)
+    assert {b * r for b in range(1, 8)} <= set(st8) and 8 * r in st8 and len(st8) == len(set(st8)) == 7 + 1 + 16
+
+
+def test_baby_giant_margins_equal_the_rotation_sum():
+    """Sum_b Rot(Z, b r) (x) Rot(W, b r), relinearised and rescaled, decrypts to
+    the sum of Rot(Z (x) W, b r) (a rotation is a ring automorphism): checked
+    slot by slot against the plain sum of the rolled products."""
+    P = O.Params(*SMALL40)
+    r, n_baby = 256, 4
+    keys = O.Keys(P, 5, rot_steps=[b * r for b in range(1, n_baby)])
+    g = np.random.default_rng(3)
+    z, w = g.uniform(-1, 1, P.S), g.uniform(-1, 1, P.S)
+    Zc = O.encrypt_sk(P, keys, O.encode(z, P.delta, P.N), P.L, P.delta, 1, 1)
+    Wc = O.encrypt_sk(P, keys, O.encode(w, P.delta, P.N), P.L, P.delta, 1, 2)
+    Zr = LR.rotate_data(P, keys, [Zc], r, n_baby)[0]
+    Wr = [Wc] + [O.rotate(P, Wc, b * r, keys) for b in range(1, n_baby)]
+    s1 = P.delta * P.delta / P.q[P.L]
+    u = LR._margin_products(P, keys, [Zc] + Zr, Wr, P.L, s1)
+    want = sum(np.roll(z * w, -b * r) for b in range(n_baby))
+    got = O.decrypt(P, keys, u).real
+    assert u.level == P.L - 1 and np.max(np.abs(got - want)) < 2.0 ** -18
 
 
 SMALL40 = (13, 5, 2, 2, 40)  # the small ring at scale 2^40 (feature-major needs a larger data scale)
@@ -566,17 +589,19 @@ def test_feature_major_refused_where_the_mask_would_lose_precision():
     LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, 1 / 2048, 0.0, LR.ROWS)
 
 
-@pytest.mark.parametrize("loss,w_decay", [("binomial-ls", 0.0), ("hinge", 0.0), ("binomial-ls", 0.05)])
-def test_encrypted_step_feature_major(loss, w_decay):
+@pytest.mark.parametrize("loss,w_decay,n_baby", [("binomial-ls", 0.0, 1), ("hinge", 0.0, 1), ("binomial-ls", 0.05, 1),
+                                                 ("binomial-ls", 0.0, 4), ("hinge", 0.0, 8)])
+def test_encrypted_step_feature_major(loss, w_decay, n_baby):
     """Feature-major circuit: the decrypted g, in every slot of each feature
     block, within 2^-20 of the FP64 gradient; W' = (1 - eta lambda) W + g
-    likewise; 4 levels used."""
+    likewise; 4 levels used.  n_baby > 1: margins by baby and giant steps from
+    the rotated data."""
     W = synth.WORKLOADS["small"]
     P = O.Params(*SMALL40)
     X, y = synth.small_data(n=700)
     w0 = synth.initial_weights("small", 16, W["seed_w"])
     blocks, c, r = LR.pack_blocks_features(X, y, P.S)
-    keys = O.Keys(P, W["seed_keys"], rot_steps=LR.rotation_steps(c, r, LR.FEATURES))
+    keys = O.Keys(P, W["seed_keys"], rot_steps=LR.rotation_steps(c, r, LR.FEATURES, n_baby))
     if loss == "hinge":
         coef = _table2_row("hinge")
     else:
@@ -587,7 +612,9 @@ def test_encrypted_step_feature_major(loss, w_decay):
     Wc = O.encrypt_sk(P, keys, O.encode(LR.pack_weights_features(w0, P.S, c), P.delta, P.N), P.L, P.delta, 7, 999)
     pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n, w_decay, LR.FEATURES)
     mask = O.encode(LR.feature_mask(P.S, r), pl["s_mask"], P.N)
-    Wn, g = LR.lr_grad_step(P, keys, Z, Wc, mask, coef, eta_n, c, r, plan=pl, layout=LR.FEATURES)
+    Zrot = LR.rotate_data(P, keys, Z, r, n_baby) if n_baby > 1 else None
+    Wn, g = LR.lr_grad_step(P, keys, Z, Wc, mask, coef, eta_n, c, r, plan=pl, layout=LR.FEATURES, Zrot=Zrot,
+                            n_baby=n_baby)
     assert Wn.level == g.level == P.L - 4
     wdec = O.decrypt(P, keys, Wc).real.reshape(c, r)[:16, 0]
     gref = LR.lr_gradient_fp64(X, y, wdec, coef, eta_n)
