@@ -78,10 +78,12 @@ he_status last_error()
 
 // ------------------------------------------------------------------ core batched operations
 // Key switch of d2 (B entries, NTT, limbs 0..l, batch stride d2s) with key;
-// out = base + KS(d2) on the first nbase components.
+// out = base + KS(d2) on the first nbase components, plus add (optional, every
+// component; may be out itself).
 he_status ks_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d2, long long d2s, const u64 *key,
                    const u64 *base, long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs,
-                   const hek::EntryKeys *keys = nullptr)
+                   const hek::EntryKeys *keys = nullptr, const u64 *add = nullptr, long long ads = 0,
+                   long long adcs = 0)
 {
     const size_t N = c->N;
     const int nb = l + 1 + c->nk, beta = beta_at(c, l);
@@ -105,7 +107,7 @@ he_status ks_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d2, long long 
         // special-prime limbs to coefficient form, scaled by N^{-1} [phat_p^{-1}]_p
         hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
         // ModDown conversion inside the first pass, base + (acc - conv) P^{-1} stored by the second
-        hek::ntt_moddown(c, l, B, acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs);
+        hek::ntt_moddown(c, l, B, acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs, add, ads, adcs);
     } else {
         hek::ewise(c, 4, l, B, 1, d2, d2s, 0, nullptr, 0, 0, y, ys, 0, 0);
         hek::ntt_batch(c, y, ys, 0, B, 1, 0, l + 1, l, -1, up_post, false);
@@ -118,7 +120,7 @@ he_status ks_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d2, long long 
         hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
         hek::moddown_conv_b(c, l, B, acc, as, conv, cs);
         hek::ntt_batch(c, conv, cs, (long long)(l + 1) * N, B, 2, 0, l + 1, l, +1, nullptr, false);
-        hek::moddown_finish_b(c, l, B, acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs);
+        hek::moddown_finish_b(c, l, B, acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs, add, ads, adcs);
     }
     ar.off = mark;
     return last_error();
@@ -170,8 +172,9 @@ he_status rescale_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long 
 }
 
 // rotate B ciphertexts at level l by the Galois element g
+// out = Rot_g(in) (+ add, component stride (l+1) N, batch stride os; may be out)
 he_status rotate_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long long is, u64 g, const u64 *key,
-                       u64 *out, long long os)
+                       u64 *out, long long os, const u64 *add = nullptr)
 {
     const size_t N = c->N;
     const size_t mark = ar.off;
@@ -179,7 +182,7 @@ he_status rotate_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long l
     u64 *rot = ar.take((size_t)B * 2 * lc);
     if (!rot) return HE_ENOMEM;
     hek::automorph_b(c, B, l + 1, in, is, lc, rot, 2 * lc, lc, g);
-    he_status st = ks_apply(c, ar, l, B, rot + lc, 2 * lc, key, rot, 2 * lc, lc, 1, out, os, lc);
+    he_status st = ks_apply(c, ar, l, B, rot + lc, 2 * lc, key, rot, 2 * lc, lc, 1, out, os, lc, nullptr, add, os, lc);
     ar.off = mark;
     return st;
 }
@@ -559,8 +562,7 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
     for (int t = 1; t < cols; t <<= 1) {
         const u64 *key = find_rot_key(keys, galois_of(c, t));
         if (!key) return HE_EKEY;
-        TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, galois_of(c, t), key, s.R, 2 * u1));
-        hek::ewise(c, 0, l - 1, nb, 2, s.U, 2 * u1, u1, s.R, 2 * u1, u1, s.U, 2 * u1, u1, 0);
+        TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, galois_of(c, t), key, s.U, 2 * u1, s.U));  // U += Rot(U)
     }
     // mask column 0, rescale: M at level l-2
     hek::ewise(c, 3, l - 1, nb, 2, s.U, 2 * u1, u1, mask->data, 0, 0, s.U, 2 * u1, u1, 0);
@@ -569,8 +571,7 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
     for (int t = 1; t < cols; t <<= 1) {
         const u64 *key = find_rot_key(keys, galois_of(c, -t));
         if (!key) return HE_EKEY;
-        TRY(rotate_apply(c, ar, l - 2, nb, s.M, 2 * m1, galois_of(c, -t), key, s.R, 2 * m1));
-        hek::ewise(c, 0, l - 2, nb, 2, s.M, 2 * m1, m1, s.R, 2 * m1, m1, s.M, 2 * m1, m1, 0);
+        TRY(rotate_apply(c, ar, l - 2, nb, s.M, 2 * m1, galois_of(c, -t), key, s.M, 2 * m1, s.M));  // M += Rot(M)
     }
     // A = M^2 ; Z3 = RS(k3 Z), B3 = M Z3 ; Z1 = RS(k1 Z), B1 = M Z1   (level l-3)
     TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.M, 2 * m1, m1, keys->rlk, s.A));
@@ -633,8 +634,7 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
         const u64 gal = galois_of(c, (long long)t * rows);
         const u64 *key = find_rot_key(keys, gal);
         if (!key) return HE_EKEY;
-        TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, gal, key, s.R, 2 * u1));
-        hek::ewise(c, 0, l - 1, nb, 2, s.U, 2 * u1, u1, s.R, 2 * u1, u1, s.U, 2 * u1, u1, 0);
+        TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, gal, key, s.U, 2 * u1, s.U));  // U += Rot(U)
     }
     // M = u.  A = M^2 ; Z3 = RS(k3 Z), B3 = M Z3 ; Z1 = RS(k1 Z), B1 = M Z1   (level l-2)
     TRY(mul_relin_rescale(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.U, 2 * u1, u1, keys->rlk, s.A));
@@ -666,8 +666,7 @@ he_status rotate_sum(he_ctx *c, Arena &ar, int level, u64 *x, u64 *tmp, long lon
         const u64 gal = galois_of(c, (long long)t * unit);
         const u64 *key = find_rot_key(keys, gal);
         if (!key) return HE_EKEY;
-        TRY(rotate_apply(c, ar, level, 1, x, 2 * x1, gal, key, tmp, 2 * x1));
-        hek::ewise(c, 0, level, 1, 2, x, 2 * x1, x1, tmp, 2 * x1, x1, x, 2 * x1, x1, 0);
+        TRY(rotate_apply(c, ar, level, 1, x, 2 * x1, gal, key, x, 2 * x1, x));  // x += Rot(x)
     }
     return HE_OK;
 }
@@ -797,8 +796,7 @@ he_status margins_impl(he_ctx *c, const he_ct *Z, int n_blocks, long long zbs, c
             const u64 gal = galois_of(c, (long long)t * unit);
             const u64 *key = find_rot_key(keys, gal);
             if (!key) return HE_EKEY;
-            TRY(rotate_apply(c, ar, l - 1, nb, u, obs, gal, key, R, 2 * u1));
-            hek::ewise(c, 0, l - 1, nb, 2, u, obs, u1, R, 2 * u1, u1, u, obs, u1, 0);
+            TRY(rotate_apply(c, ar, l - 1, nb, u, obs, gal, key, u, obs, u));  // u += Rot(u)
         }
     }
     return last_error();

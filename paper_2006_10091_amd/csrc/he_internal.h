@@ -115,7 +115,8 @@ void ntt_batch(he_ctx *c, u64 *base, long long bstride, long long cstride, int n
 bool fused_ok(const he_ctx *c);
 void intt_from(he_ctx *c, const u64 *src, long long sbs, u64 *dst, long long dbs, int B, int level, const u64 *post);
 void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs, const u64 *base,
-                 long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs);
+                 long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs,
+                 const u64 *add = nullptr, long long ads = 0, long long adcs = 0);
 void ntt_rescale(he_ctx *c, int level, int B, int ncomp, const u64 *last, const u64 *in, long long is, u64 *tmp,
                  u64 *out, long long os);
 void intt_last(he_ctx *c, int level, int B, int ncomp, const u64 *in, long long is, u64 *last);
@@ -159,7 +160,7 @@ void moddown_conv_b(he_ctx *c, int level, int B, const u64 *acc, long long as, u
 // out = base + (acc - conv) P^{-1} on the first nbase components (else no base)
 void moddown_finish_b(he_ctx *c, int level, int B, const u64 *acc, long long as, const u64 *conv, long long cs,
                       const u64 *base, long long bs, long long bcs, int nbase, u64 *out, long long os,
-                      long long ocs);
+                      long long ocs, const u64 *add = nullptr, long long ads = 0, long long adcs = 0);
 // rescale pieces: lastc [B][2][N] (coefficient) -> tmp [B][2][l][N]; finish
 void rescale_bcast_b(he_ctx *c, int level, int B, const u64 *lastc, u64 *tmp, int ncomp = 2);
 void rescale_finish_b(he_ctx *c, int level, int B, const u64 *in, long long is, const u64 *tmp, u64 *out,

@@ -502,6 +502,8 @@ struct Fuse {
     u64 *out;            // finish: out [b][comp][pos]
     long long os, ocs;
     const u64 *pinv;     // finish: P^{-1} mod q_pos (+ Shoup)
+    const u64 *add;      // finish: optional addend [b][comp][pos] on every component (may be out)
+    long long ads, adcs;
 };
 
 constexpr int MAXW = 8;  // special primes the ModDown prologue reads (and the fused path's digit-width bound)
@@ -771,6 +773,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
             const u64 av = f.acc[b * f.as + c * f.acs + roff + e];
             u64 r = mul_shoup(sub_mod(av, x, q), f.pinv[2 * pos], f.pinv[2 * pos + 1], q);
             if (c < f.nbase) r = add_mod(r, f.base[b * f.bs + c * f.bcs + roff + e], q);
+            if (f.add) r = add_mod(r, f.add[b * f.ads + c * f.adcs + roff + e], q);
             f.out[b * f.os + c * f.ocs + roff + e] = r;
         } else {
             __builtin_nontemporal_store(x, row + e);
@@ -788,12 +791,14 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
             // finish operands are loaded before the stages, so their latency overlaps them
             u64 fa[FIN ? S::E : 1], fb[FIN ? S::E : 1];
             if (FIN) {
+                // fb = base + addend (each below q, so the sum is below 2q)
                 const u64 *ap = f.acc + b * f.as + c * f.acs + roff + tau;
                 const u64 *bp = f.base + b * f.bs + c * f.bcs + roff + tau;
+                const u64 *dp = f.add + b * f.ads + c * f.adcs + roff + tau;
 #pragma unroll
                 for (int k = 0; k < S::E; ++k) {
                     fa[k] = ap[S::T * k];
-                    fb[k] = c < f.nbase ? bp[S::T * k] : 0;
+                    fb[k] = (c < f.nbase ? bp[S::T * k] : 0) + (f.add ? dp[S::T * k] : 0);
                 }
             }
             fwd_stages_ds<LM, true, true>(d, tau, h, N1, Wd, qd, qinv);
@@ -802,7 +807,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
             __syncthreads();
             exch_d<LM>(d, dl, tau, false);
             if (FIN) {
-                // base + (acc - x) P^{-1}: the lazy product is in (-q, 2q), the sum in (-q, 3q)
+                // base (+ addend) + (acc - x) P^{-1}: the lazy product is in (-q, 2q), the sum in (-q, 4q)
                 const double pinv = d_from_u52(f.pinv[2 * pos]);
                 u64 *op = f.out + b * f.os + c * f.ocs + roff + tau;
 #pragma unroll
@@ -1099,33 +1104,40 @@ struct BabyArgs {
     int nbaby, nblk, logN;
 };
 
+// NB (compile time) baby steps, so the 2 NB loads of a block are issued
+// together; blockIdx.z selects a chunk of BABY_CHUNK blocks.
+constexpr int BABY_CHUNK = 8;
+template <int NB>
 __global__ __launch_bounds__(256) void baby_sum_kernel(BabyArgs a, const PrimeInfo *__restrict__ pinfo)
 {
     const int i = blockIdx.y;
     const PrimeInfo p = pinfo[i];
     const long long off = ((long long)i << a.logN) + blockIdx.x * 256 + threadIdx.x;
+    const int blk0 = blockIdx.z * BABY_CHUNK, blk1 = min(blk0 + BABY_CHUNK, a.nblk);
     if (p.q < (1ull << 46)) {
         const double qd = (double)p.q, qinv = 1.0 / qd;
-        double w0[MAX_BABY], w1[MAX_BABY];
+        double w0[NB], w1[NB];
 #pragma unroll
-        for (int b = 0; b < MAX_BABY; ++b) {
-            if (b < a.nbaby) {
-                const u64 *wp = b == 0 ? a.w + off : a.wr + (b - 1) * a.wrs + off;
-                w0[b] = d_from_u52(wp[0]);
-                w1[b] = d_from_u52(wp[b == 0 ? a.wc : a.wrc]);
-            }
+        for (int b = 0; b < NB; ++b) {
+            const u64 *wp = b == 0 ? a.w + off : a.wr + (b - 1) * a.wrs + off;
+            w0[b] = d_from_u52(wp[0]);
+            w1[b] = d_from_u52(wp[b == 0 ? a.wc : a.wrc]);
         }
-        for (int blk = 0; blk < a.nblk; ++blk) {
+        for (int blk = blk0; blk < blk1; ++blk) {
+            u64 z0[NB], z1[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const u64 *zp = b == 0 ? a.z + blk * a.zb + off : a.zr + blk * a.zrb + (b - 1) * a.zrs + off;
+                z0[b] = zp[0];
+                z1[b] = zp[b == 0 ? a.zc : a.zrc];
+            }
             double d0 = 0.0, d1 = 0.0, d2 = 0.0;
 #pragma unroll
-            for (int b = 0; b < MAX_BABY; ++b) {
-                if (b < a.nbaby) {
-                    const u64 *zp = b == 0 ? a.z + blk * a.zb + off : a.zr + blk * a.zrb + (b - 1) * a.zrs + off;
-                    const double z0 = d_from_u52(zp[0]), z1 = d_from_u52(zp[b == 0 ? a.zc : a.zrc]);
-                    d0 += mulmod_lazy_d(z0, w0[b], qd, qinv);
-                    d1 += mulmod_lazy_d(z0, w1[b], qd, qinv) + mulmod_lazy_d(z1, w0[b], qd, qinv);
-                    d2 += mulmod_lazy_d(z1, w1[b], qd, qinv);
-                }
+            for (int b = 0; b < NB; ++b) {
+                const double x0 = d_from_u52(z0[b]), x1 = d_from_u52(z1[b]);
+                d0 += mulmod_lazy_d(x0, w0[b], qd, qinv);
+                d1 += mulmod_lazy_d(x0, w1[b], qd, qinv) + mulmod_lazy_d(x1, w0[b], qd, qinv);
+                d2 += mulmod_lazy_d(x1, w1[b], qd, qinv);
             }
             u64 *o = a.o + blk * a.ob + off;
             o[0] = u52_from_d(reduce_d(d0, qd, qinv));
@@ -1134,26 +1146,22 @@ __global__ __launch_bounds__(256) void baby_sum_kernel(BabyArgs a, const PrimeIn
         }
         return;
     }
-    u64 w0[MAX_BABY], w1[MAX_BABY];
+    u64 w0[NB], w1[NB];
 #pragma unroll
-    for (int b = 0; b < MAX_BABY; ++b) {
-        if (b < a.nbaby) {
-            const u64 *wp = b == 0 ? a.w + off : a.wr + (b - 1) * a.wrs + off;
-            w0[b] = wp[0];
-            w1[b] = wp[b == 0 ? a.wc : a.wrc];
-        }
+    for (int b = 0; b < NB; ++b) {
+        const u64 *wp = b == 0 ? a.w + off : a.wr + (b - 1) * a.wrs + off;
+        w0[b] = wp[0];
+        w1[b] = wp[b == 0 ? a.wc : a.wrc];
     }
-    for (int blk = 0; blk < a.nblk; ++blk) {
+    for (int blk = blk0; blk < blk1; ++blk) {
         u64 d0 = 0, d1 = 0, d2 = 0;
 #pragma unroll
-        for (int b = 0; b < MAX_BABY; ++b) {
-            if (b < a.nbaby) {
-                const u64 *zp = b == 0 ? a.z + blk * a.zb + off : a.zr + blk * a.zrb + (b - 1) * a.zrs + off;
-                const u64 z0 = zp[0], z1 = zp[b == 0 ? a.zc : a.zrc];
-                d0 = add_mod(d0, mul_mod(z0, w0[b], p), p.q);
-                d1 = add_mod(d1, add_mod(mul_mod(z0, w1[b], p), mul_mod(z1, w0[b], p), p.q), p.q);
-                d2 = add_mod(d2, mul_mod(z1, w1[b], p), p.q);
-            }
+        for (int b = 0; b < NB; ++b) {
+            const u64 *zp = b == 0 ? a.z + blk * a.zb + off : a.zr + blk * a.zrb + (b - 1) * a.zrs + off;
+            const u64 x0 = zp[0], x1 = zp[b == 0 ? a.zc : a.zrc];
+            d0 = add_mod(d0, mul_mod(x0, w0[b], p), p.q);
+            d1 = add_mod(d1, add_mod(mul_mod(x0, w1[b], p), mul_mod(x1, w0[b], p), p.q), p.q);
+            d2 = add_mod(d2, mul_mod(x1, w1[b], p), p.q);
         }
         u64 *o = a.o + blk * a.ob + off;
         o[0] = d0;
@@ -1394,9 +1402,9 @@ __global__ __launch_bounds__(256) void moddown_conv_kernel(const u64 *__restrict
 __global__ __launch_bounds__(256) void moddown_finish_kernel(const u64 *__restrict__ acc, long long as,
                                                              const u64 *__restrict__ conv, long long cs,
                                                              const u64 *__restrict__ base, long long bs,
-                                                             long long bcs, int nbase, u64 *__restrict__ out,
-                                                             long long os, long long ocs,
-                                                             const PrimeInfo *__restrict__ pinfo,
+                                                             long long bcs, int nbase, u64 *out, long long os,
+                                                             long long ocs, const u64 *add, long long ads,
+                                                             long long adcs, const PrimeInfo *__restrict__ pinfo,
                                                              const u64 *__restrict__ pinv, int level, int nk,
                                                              int logN)
 {
@@ -1412,9 +1420,11 @@ __global__ __launch_bounds__(256) void moddown_finish_kernel(const u64 *__restri
     const u64 *c = conv + b * cs + ((long long)comp * (level + 1) << logN) + li;
     const u64 *bb = (comp < nbase) ? base + b * bs + comp * bcs + li : nullptr;
     u64 *o = out + b * os + comp * ocs + li;
+    const u64 *ad = add ? add + b * ads + comp * adcs + li : nullptr;  // may be o itself: read before the write
     for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
         u64 v = mul_shoup(sub_mod(a[x], c[x], q), w, ws, q);
         if (bb) v = add_mod(v, bb[x], q);
+        if (ad) v = add_mod(v, ad[x], q);
         o[x] = v;
     }
 }
@@ -1847,7 +1857,8 @@ void intt_from(he_ctx *c, const u64 *src, long long sbs, u64 *dst, long long dbs
 }
 
 void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs, const u64 *base,
-                 long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs)
+                 long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs, const u64 *add,
+                 long long ads, long long adcs)
 {
     const long long N = c->N, nb = level + 1 + c->nk;
     Fuse f{};
@@ -1873,6 +1884,9 @@ void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 
     f.out = out;
     f.os = os;
     f.ocs = ocs;
+    f.add = add;
+    f.ads = ads;
+    f.adcs = adcs;
     f.pinv = c->t.dn_pinv;
     NttArgs a = make_args(c, conv, cs, (level + 1) * N, 2, 0, level, false);
     ntt_launch(c, a, B, level + 1, +1, nullptr, PRO_MODDOWN, EPI_FINISH, &f);
@@ -1963,8 +1977,13 @@ void baby_sum_b(he_ctx *c, int level, int nblk, int nbaby, const u64 *z, long lo
                 long long wrc, u64 *o, long long ob, long long oc)
 {
     BabyArgs a{z, zb, zc, zr, zrb, zrs, zrc, w, wc, wr, wrs, wrc, o, ob, oc, nbaby, nblk, c->logN};
-    dim3 g(c->N / 256, level + 1, 1);
-    baby_sum_kernel<<<g, 256, 0, c->stream>>>(a, c->t.pinfo);
+    dim3 g(c->N / 256, level + 1, (nblk + BABY_CHUNK - 1) / BABY_CHUNK);
+    switch (nbaby) {
+    case 2: baby_sum_kernel<2><<<g, 256, 0, c->stream>>>(a, c->t.pinfo); break;
+    case 4: baby_sum_kernel<4><<<g, 256, 0, c->stream>>>(a, c->t.pinfo); break;
+    case 8: baby_sum_kernel<8><<<g, 256, 0, c->stream>>>(a, c->t.pinfo); break;
+    default: baby_sum_kernel<MAX_BABY><<<g, 256, 0, c->stream>>>(a, c->t.pinfo); break;
+    }
 }
 
 void modup_b(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, long long es, long long ds)
@@ -2017,11 +2036,11 @@ void moddown_conv_b(he_ctx *c, int level, int B, const u64 *acc, long long as, u
 
 void moddown_finish_b(he_ctx *c, int level, int B, const u64 *acc, long long as, const u64 *conv, long long cs,
                       const u64 *base, long long bs, long long bcs, int nbase, u64 *out, long long os,
-                      long long ocs)
+                      long long ocs, const u64 *add, long long ads, long long adcs)
 {
     dim3 g(xblocks(c->N), level + 1, B * 2);
-    moddown_finish_kernel<<<g, 256, 0, c->stream>>>(acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs,
-                                                    c->t.pinfo, c->t.dn_pinv, level, c->nk, c->logN);
+    moddown_finish_kernel<<<g, 256, 0, c->stream>>>(acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs, add, ads,
+                                                    adcs, c->t.pinfo, c->t.dn_pinv, level, c->nk, c->logN);
 }
 
 void rescale_bcast_b(he_ctx *c, int level, int B, const u64 *lastc, u64 *tmp, int ncomp)

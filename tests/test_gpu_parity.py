@@ -476,6 +476,48 @@ def test_lr_step_feature_major_errors(small, small40):
     assert e.value.status == 5
 
 
+# ------------------------------------------------------------------ rings below 2^12 (unfused kernels)
+def test_small_ring_unfused_path_bit_exact():
+    """N = 2^11 runs the stage-per-barrier NTT and the unfused key switch,
+    rescale and rotate-and-add: products, rotations and the margins (in place
+    rotate-and-sum) bit for bit against the oracle."""
+    H = _H()
+    cfg = (11, 4, 1, 1, 30)
+    P = O.Params(*cfg)
+    ctx = H.Context(*cfg)
+    c, r = 16, P.S // 16
+    steps = LR.rotation_steps(c, r)
+    okeys, gkeys = O.Keys(P, 41, rot_steps=steps), ctx.keygen(41, steps)
+    q = P.q
+    def rct(level, seed):
+        d = np.stack([synth.uniform_residues(seed, q[: level + 1], P.N), synth.uniform_residues(seed + 1, q[: level + 1],
+                                                                                             P.N)])
+        return d, ctx.upload(d, level, 1.0)
+    xd, x = rct(P.L, 11)
+    yd, y = rct(P.L, 13)
+    want = O.rotate(P, O.rescale(P, O.mul(P, O.CT(xd, P.L, 1.0), O.CT(yd, P.L, 1.0), okeys)), 2, okeys)
+    got = ctx.batch_mul_rotate([x], [y], [2], gkeys, mode=1)[0]
+    assert np.array_equal(ctx.download(got), want.data)
+    X, yl = synth.small_data(n=r)
+    blocks, c2, r2 = LR.pack_blocks(X, yl, P.S)
+    assert (c2, r2) == (c, r)
+    m = O.encode(blocks[0], P.delta, P.N)
+    oZ = O.encrypt_sk(P, okeys, m, P.L, P.delta, 3, 0)
+    gZ = ctx.ct_block(1, P.L)
+    ctx.encrypt(ctx.pt_load(m, P.L, P.delta), gkeys, 3, 0, out=gZ[0])
+    mw = O.encode(LR.pack_weights(synth.initial_weights("small", 16, 5), P.S, c), P.delta, P.N)
+    oW = O.encrypt_sk(P, okeys, mw, P.L, P.delta, 3, 9)
+    gW = ctx.encrypt(ctx.pt_load(mw, P.L, P.delta), gkeys, 3, 9)
+    u = O.rescale(P, O.mul(P, oZ, oW, okeys))
+    t = 1
+    while t < c:
+        u = O.add(P, u, O.rotate(P, u, t, okeys))
+        t *= 2
+    for mode in (0, 1):
+        out = ctx.lr_margins(gZ, gW, c, r, gkeys, mode=mode)
+        assert np.array_equal(ctx.download(out[0]), u.data), mode
+
+
 # ------------------------------------------------------------------ encrypted inference (margins)
 @pytest.mark.parametrize("layout", [0, 1])
 def test_margins_bit_exact_and_decrypt_to_inner_products(small, layout):
