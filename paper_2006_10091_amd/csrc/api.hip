@@ -442,7 +442,7 @@ he_status make_evk(he_ctx *c, Arena &ar, u64 seed, uint32_t key_id, const u64 *s
 
 // ------------------------------------------------------------------ the gradient step
 struct StepBufs {
-    u64 *T3, *U0, *U, *R, *M, *Y, *Z3, *Z1, *A, *B3, *C, *G, *Rg, *Y1, *Z2, *Gm, *G3;
+    u64 *T3, *U0, *U, *R, *M, *Y, *Z3, *Z1, *A, *B3, *G, *Rg, *Y1, *Z2, *Gm, *G3;
     u64 *Wr;  // feature-major baby steps: Rot(W, b r), b = 1 .. n_baby - 1
 };
 
@@ -463,7 +463,6 @@ size_t step_bytes(const he_ctx *c, int l, int nb, int layout, int n_baby = 1)
     n += al((size_t)nb * 2 * (l + e) * N);                 // Y
     n += 2 * al((size_t)nb * 2 * (l - 1 + e) * N);         // Z3, Z1
     n += 2 * al((size_t)nb * 2 * (l - 2 + e) * N);         // A, B3
-    n += al((size_t)nb * 3 * (l - 2 + e) * N);             // C (degree-2 terms)
     n += al((size_t)nb * 2 * (l - 2 + e) * N);             // Z2
     n += al((size_t)3 * (l - 2 + e) * N);                  // G3
     n += 2 * al((size_t)2 * (l - 3 + e) * N);              // G, Rg
@@ -492,7 +491,6 @@ he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, int layout, int n_baby
     s.Z1 = ar.take((size_t)nb * 2 * (l - 1 + e) * N);
     s.A = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
     s.B3 = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
-    s.C = ar.take((size_t)nb * 3 * (l - 2 + e) * N);
     s.Z2 = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
     s.G3 = ar.take((size_t)3 * (l - 2 + e) * N);
     s.G = ar.take((size_t)2 * (l - 3 + e) * N);
@@ -500,7 +498,7 @@ he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, int layout, int n_baby
     s.Y1 = ar.take((size_t)2 * (l - 2) * N);
     s.Gm = ar.take((size_t)2 * (l - 3) * N);
     s.Wr = n_baby > 1 ? ar.take((size_t)(n_baby - 1) * 2 * (l + 1) * N) : nullptr;
-    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Y, s.Z3, s.Z1, s.A, s.B3, s.C, s.Z2, s.G3, s.G, s.Rg, s.Y1, s.Gm};
+    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Y, s.Z3, s.Z1, s.A, s.B3, s.Z2, s.G3, s.G, s.Rg, s.Y1, s.Gm};
     for (u64 *p : all)
         if (!p) return HE_ENOMEM;
     if (n_baby > 1 && !s.Wr) return HE_ENOMEM;
@@ -522,27 +520,6 @@ he_status mul_relin_rescale(he_ctx *c, Arena &ar, StepBufs &s, int l, int nb, co
     hek::tensor_b(c, l, nb, x, xb, xc, y, yb, yc, s.T3, 3 * lc, lc);
     TRY(relin_apply(c, ar, l, nb, s.T3, 3 * lc, rlk, s.U0, 2 * lc));
     return rescale_apply(c, ar, l, nb, s.U0, 2 * lc, out, 2LL * l * N);
-}
-
-// The block's gradient terms, unrescaled and unrelinearised, as one degree-2
-// sum at level lp (into s.C, scale sC q_lp): C = A (x) B3, B1 = M (x) Z1 (M,
-// component stride mc, read on its first lp+1 limbs), k0 Z and, for k2 != 0,
-// B2 = A (x) Z2.  A, B3, Z1, Z2 at level lp.
-he_status terms_prescale(he_ctx *c, StepBufs &s, const he_lr_plan &pl, int lp, int nb, const u64 *zp,
-                         long long zbs, long long zc, const u64 *M, long long mc)
-{
-    const long long N = c->N;
-    const long long p1 = (long long)(lp + 1) * N;
-    hek::tensor_b(c, lp, nb, s.A, 2 * p1, p1, s.B3, 2 * p1, p1, s.C, 3 * p1, p1);
-    hek::tensor_b(c, lp, nb, M, 2 * mc, mc, s.Z1, 2 * p1, p1, s.T3, 3 * p1, p1);
-    hek::ewise(c, 0, lp, nb, 3, s.C, 3 * p1, p1, s.T3, 3 * p1, p1, s.C, 3 * p1, p1, 0);
-    hek::ewise(c, 2, lp, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * p1, p1, pl.k0);
-    hek::ewise(c, 0, lp, nb, 2, s.C, 3 * p1, p1, s.Y, 2 * p1, p1, s.C, 3 * p1, p1, 0);
-    if (pl.k2 != 0) {
-        hek::tensor_b(c, lp, nb, s.A, 2 * p1, p1, s.Z2, 2 * p1, p1, s.T3, 3 * p1, p1);
-        hek::ewise(c, 0, lp, nb, 3, s.C, 3 * p1, p1, s.T3, 3 * p1, p1, s.C, 3 * p1, p1, 0);
-    }
-    return last_error();
 }
 
 // per-block part of the step for blocks [b0, b0+nb); G (+)= sum of their terms
@@ -587,9 +564,9 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
         hek::ewise(c, 2, l - 2, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * m1, m1, pl.k2);
         TRY(rescale_apply(c, ar, l - 2, nb, s.Y, 2 * m1, s.Z2, 2 * a1));
     }
-    // the block's terms at level l-3 (unrescaled); G3 (+)= their sum
-    TRY(terms_prescale(c, s, pl, l - 3, nb, zp, zbs, zc, s.M, m1));
-    hek::batch_sum(c, l - 3, nb, s.C, 3 * a1, a1, s.G3, a1, accumulate, 3);
+    // the blocks' terms at level l-3 (unrescaled), summed straight into G3
+    hek::terms_sum_b(c, l - 3, nb, s.A, s.B3, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, s.M, 2 * m1, m1, zp, zbs,
+                     zc, pl.k0, s.G3, accumulate);
     return last_error();
 }
 
@@ -651,8 +628,8 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
         TRY(rescale_apply(c, ar, l - 1, nb, s.Y, 2 * u1, s.Z2, 2 * a1));
     }
     // the block's terms at level l-2 (unrescaled); G3 (+)= their sum
-    TRY(terms_prescale(c, s, pl, l - 2, nb, zp, zbs, zc, s.U, u1));
-    hek::batch_sum(c, l - 2, nb, s.C, 3 * a1, a1, s.G3, a1, accumulate, 3);
+    hek::terms_sum_b(c, l - 2, nb, s.A, s.B3, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, s.U, 2 * u1, u1, zp, zbs,
+                     zc, pl.k0, s.G3, accumulate);
     return last_error();
 }
 
