@@ -67,7 +67,9 @@ size_t ks_scratch(const he_ctx *c, int l, int B)
 }
 size_t rescale_scratch(const he_ctx *c, int l, int B, int ncomp = 2)
 {
-    return al((size_t)B * ncomp * c->N) + al((size_t)B * ncomp * l * c->N);
+    // the unfused form copies a scaled or strided input to a plain one first
+    const size_t y = hek::fused_ok(c) ? 0 : al((size_t)B * ncomp * (l + 1) * c->N);
+    return al((size_t)B * ncomp * c->N) + al((size_t)B * ncomp * l * c->N) + y;
 }
 size_t rotate_scratch(const he_ctx *c, int l, int B) { return al((size_t)B * 2 * (l + 1) * c->N) + ks_scratch(c, l, B); }
 
@@ -137,26 +139,38 @@ he_status relin_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d3, long lo
 // rescale B ciphertexts of ncomp components at level l -> level l-1 (each
 // component on its own; out may equal in only for B == 1)
 he_status rescale_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long long is, u64 *out, long long os,
-                        int ncomp = 2)
+                        int ncomp = 2, const i64 *kmul = nullptr, long long ics = 0)
 {
+    // out = RS(k in) with k = *kmul when given; in's component stride is ics
+    // (default (l+1) N: a ciphertext at level l, or a higher-level one read on
+    // its first l+1 limbs)
     const size_t N = c->N;
     const size_t mark = ar.off;
+    const long long lc = (long long)(l + 1) * N;
+    if (ics == 0) ics = lc;
     u64 *lastc = ar.take((size_t)B * ncomp * N);
     u64 *tmp = ar.take((size_t)B * ncomp * l * N);
     if (!lastc || !tmp) return HE_ENOMEM;
-    const long long lc = (long long)(l + 1) * N;
     // the fused form reads limb i of the input and writes limb i of the output
     // from different workgroups: it needs them apart (he_rescale allows out == in)
-    const u64 *in_end = in + (long long)(B - 1) * is + ncomp * lc;
+    const u64 *in_end = in + (long long)(B - 1) * is + (ncomp - 1) * ics + lc;
     const u64 *out_end = out + (long long)(B - 1) * os + (long long)ncomp * l * N;
     const bool apart = out >= in_end || in >= out_end;
     if (hek::fused_ok(c) && apart) {
         // a one-prime ModDown: the last limbs to coefficient form, then the
         // centred conversion to q_0..q_{l-1} inside the first forward pass and
         // (c_i - x) q_l^{-1} stored by the second
-        hek::intt_last(c, l, B, ncomp, in, is, lastc);
-        hek::ntt_rescale(c, l, B, ncomp, lastc, in, is, tmp, out, os);
+        hek::intt_last(c, l, B, ncomp, in, is, ics, lastc, kmul);
+        hek::ntt_rescale(c, l, B, ncomp, lastc, in, is, ics, tmp, out, os, kmul);
     } else {
+        if (kmul || ics != lc) {
+            // the unfused kernels take a plain level-l input: k in, or a copy
+            u64 *y = ar.take((size_t)B * ncomp * lc);
+            if (!y) return HE_ENOMEM;
+            hek::ewise(c, kmul ? 2 : 4, l, B, ncomp, in, is, ics, nullptr, 0, 0, y, ncomp * lc, lc, kmul ? *kmul : 0);
+            in = y;
+            is = ncomp * lc;
+        }
         hek::ewise(c, 4, 0, B, ncomp, in + (long long)l * N, is, lc, nullptr, 0, 0, lastc, (long long)ncomp * N,
                    (long long)N, 0);
         // the limbs use prime q_l: address them as position l of a shifted base
@@ -442,7 +456,7 @@ he_status make_evk(he_ctx *c, Arena &ar, u64 seed, uint32_t key_id, const u64 *s
 
 // ------------------------------------------------------------------ the gradient step
 struct StepBufs {
-    u64 *T3, *U0, *U, *R, *M, *Y, *Z3, *Z1, *A, *B3, *G, *Rg, *Y1, *Z2, *Gm, *G3;
+    u64 *T3, *U0, *U, *R, *M, *Z3, *Z1, *A, *B3, *G, *Rg, *Z2, *Gm, *G3;
     u64 *Wr;  // feature-major baby steps: Rot(W, b r), b = 1 .. n_baby - 1
 };
 
@@ -460,13 +474,11 @@ size_t step_bytes(const he_ctx *c, int l, int nb, int layout, int n_baby = 1)
     n += al((size_t)nb * 2 * (l + 1) * N);                 // U0
     n += 2 * al((size_t)nb * 2 * l * N);                   // U, R
     n += al((size_t)nb * 2 * (l - 1) * N);                 // M
-    n += al((size_t)nb * 2 * (l + e) * N);                 // Y
     n += 2 * al((size_t)nb * 2 * (l - 1 + e) * N);         // Z3, Z1
     n += 2 * al((size_t)nb * 2 * (l - 2 + e) * N);         // A, B3
     n += al((size_t)nb * 2 * (l - 2 + e) * N);             // Z2
     n += al((size_t)3 * (l - 2 + e) * N);                  // G3
     n += 2 * al((size_t)2 * (l - 3 + e) * N);              // G, Rg
-    n += al((size_t)2 * (l - 2) * N);                      // Y1
     n += al((size_t)2 * (l - 3) * N);                      // Gm
     size_t scratch = std::max(rotate_scratch(c, l, nb), rescale_scratch(c, l, nb));
     if (n_baby > 1) {
@@ -486,7 +498,6 @@ he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, int layout, int n_baby
     s.U = ar.take((size_t)nb * 2 * l * N);
     s.R = ar.take((size_t)nb * 2 * l * N);
     s.M = ar.take((size_t)nb * 2 * (l - 1) * N);
-    s.Y = ar.take((size_t)nb * 2 * (l + e) * N);
     s.Z3 = ar.take((size_t)nb * 2 * (l - 1 + e) * N);
     s.Z1 = ar.take((size_t)nb * 2 * (l - 1 + e) * N);
     s.A = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
@@ -495,10 +506,9 @@ he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, int layout, int n_baby
     s.G3 = ar.take((size_t)3 * (l - 2 + e) * N);
     s.G = ar.take((size_t)2 * (l - 3 + e) * N);
     s.Rg = ar.take((size_t)2 * (l - 3 + e) * N);
-    s.Y1 = ar.take((size_t)2 * (l - 2) * N);
     s.Gm = ar.take((size_t)2 * (l - 3) * N);
     s.Wr = n_baby > 1 ? ar.take((size_t)(n_baby - 1) * 2 * (l + 1) * N) : nullptr;
-    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Y, s.Z3, s.Z1, s.A, s.B3, s.Z2, s.G3, s.G, s.Rg, s.Y1, s.Gm};
+    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Z3, s.Z1, s.A, s.B3, s.Z2, s.G3, s.G, s.Rg, s.Gm};
     for (u64 *p : all)
         if (!p) return HE_ENOMEM;
     if (n_baby > 1 && !s.Wr) return HE_ENOMEM;
@@ -552,18 +562,12 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
     }
     // A = M^2 ; Z3 = RS(k3 Z), B3 = M Z3 ; Z1 = RS(k1 Z), B1 = M Z1   (level l-3)
     TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.M, 2 * m1, m1, keys->rlk, s.A));
-    const long long y1 = (long long)l * N;
-    hek::ewise(c, 2, l - 1, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * y1, y1, pl.k3);
-    TRY(rescale_apply(c, ar, l - 1, nb, s.Y, 2 * y1, s.Z3, 2 * m1));
+    TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z3, 2 * m1, 2, &pl.k3, zc));
     TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.Z3, 2 * m1, m1, keys->rlk, s.B3));
     // Z1 = RS(k1 Z) and, for a2 != 0, Z2 = RS(k2 Z), both at level l-3
     const long long a1 = (long long)(l - 2) * N;
-    hek::ewise(c, 2, l - 2, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * m1, m1, pl.k1);
-    TRY(rescale_apply(c, ar, l - 2, nb, s.Y, 2 * m1, s.Z1, 2 * a1));
-    if (pl.k2 != 0) {
-        hek::ewise(c, 2, l - 2, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * m1, m1, pl.k2);
-        TRY(rescale_apply(c, ar, l - 2, nb, s.Y, 2 * m1, s.Z2, 2 * a1));
-    }
+    TRY(rescale_apply(c, ar, l - 2, nb, zp, zbs, s.Z1, 2 * a1, 2, &pl.k1, zc));
+    if (pl.k2 != 0) TRY(rescale_apply(c, ar, l - 2, nb, zp, zbs, s.Z2, 2 * a1, 2, &pl.k2, zc));
     // the blocks' terms at level l-3 (unrescaled), summed straight into G3
     hek::terms_sum_b(c, l - 3, nb, s.A, s.B3, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, s.M, 2 * m1, m1, zp, zbs,
                      zc, pl.k0, s.G3, accumulate);
@@ -615,18 +619,12 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
     }
     // M = u.  A = M^2 ; Z3 = RS(k3 Z), B3 = M Z3 ; Z1 = RS(k1 Z), B1 = M Z1   (level l-2)
     TRY(mul_relin_rescale(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.U, 2 * u1, u1, keys->rlk, s.A));
-    const long long y1 = (long long)(l + 1) * N;
-    hek::ewise(c, 2, l, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * y1, y1, pl.k3);
-    TRY(rescale_apply(c, ar, l, nb, s.Y, 2 * y1, s.Z3, 2 * u1));
+    TRY(rescale_apply(c, ar, l, nb, zp, zbs, s.Z3, 2 * u1, 2, &pl.k3, zc));
     TRY(mul_relin_rescale(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.Z3, 2 * u1, u1, keys->rlk, s.B3));
     // Z1 = RS(k1 Z) and, for a2 != 0, Z2 = RS(k2 Z), both at level l-2
     const long long a1 = (long long)(l - 1) * N;
-    hek::ewise(c, 2, l - 1, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * u1, u1, pl.k1);
-    TRY(rescale_apply(c, ar, l - 1, nb, s.Y, 2 * u1, s.Z1, 2 * a1));
-    if (pl.k2 != 0) {
-        hek::ewise(c, 2, l - 1, nb, 2, zp, zbs, zc, nullptr, 0, 0, s.Y, 2 * u1, u1, pl.k2);
-        TRY(rescale_apply(c, ar, l - 1, nb, s.Y, 2 * u1, s.Z2, 2 * a1));
-    }
+    TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z1, 2 * a1, 2, &pl.k1, zc));
+    if (pl.k2 != 0) TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z2, 2 * a1, 2, &pl.k2, zc));
     // the block's terms at level l-2 (unrescaled); G3 (+)= their sum
     hek::terms_sum_b(c, l - 2, nb, s.A, s.B3, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, s.U, 2 * u1, u1, zp, zbs,
                      zc, pl.k0, s.G3, accumulate);
@@ -834,9 +832,7 @@ he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_block
     }
     if (G_out) hek::ewise(c, 4, l - 4, 1, 2, g, 2 * g1, g1, nullptr, 0, 0, G_out->data, 2 * g1, g1, 0);
     // W' = RS(kW W) + g
-    const long long w2 = (long long)(l - 2) * N;
-    hek::ewise(c, 2, l - 3, 1, 2, W->data, 0, (l + 1) * N, nullptr, 0, 0, s.Y1, 2 * w2, w2, pl.kw);
-    TRY(rescale_apply(c, ar, l - 3, 1, s.Y1, 2 * w2, W_out->data, 2 * g1));
+    TRY(rescale_apply(c, ar, l - 3, 1, W->data, 0, W_out->data, 2 * g1, 2, &pl.kw, (l + 1) * N));
     hek::ewise(c, 0, l - 4, 1, 2, W_out->data, 2 * g1, g1, g, 2 * g1, g1, W_out->data, 2 * g1, g1, 0);
     return last_error();
 }

@@ -117,9 +117,10 @@ void intt_from(he_ctx *c, const u64 *src, long long sbs, u64 *dst, long long dbs
 void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs, const u64 *base,
                  long long bs, long long bcs, int nbase, u64 *out, long long os, long long ocs,
                  const u64 *add = nullptr, long long ads = 0, long long adcs = 0);
-void ntt_rescale(he_ctx *c, int level, int B, int ncomp, const u64 *last, const u64 *in, long long is, u64 *tmp,
-                 u64 *out, long long os);
-void intt_last(he_ctx *c, int level, int B, int ncomp, const u64 *in, long long is, u64 *last);
+void ntt_rescale(he_ctx *c, int level, int B, int ncomp, const u64 *last, const u64 *in, long long is, long long ics,
+                 u64 *tmp, u64 *out, long long os, const i64 *kmul);
+void intt_last(he_ctx *c, int level, int B, int ncomp, const u64 *in, long long is, long long ics, u64 *last,
+               const i64 *kmul);
 // op 0 add, 1 sub, 2 multiply by integer k, 3 multiply by plaintext y ([pos][N]), 4 copy;
 // positions 0..level of nbatch x ncomp polys.
 void ewise(he_ctx *c, int op, int level, int nbatch, int ncomp, const u64 *x, long long xb, long long xc,

@@ -504,7 +504,19 @@ struct Fuse {
     const u64 *pinv;     // finish: P^{-1} mod q_pos (+ Shoup)
     const u64 *add;      // finish: optional addend [b][comp][pos] on every component (may be out)
     long long ads, adcs;
+    int has_kmul;        // PRO_SRC: multiply the source by kmul (mod each prime) as it is read
+    i64 kmul;
+    int has_kacc;        // finish: multiply acc by kacc (mod each prime) as it is read
+    i64 kacc;
 };
+
+// k mod p for a signed 64-bit integer k
+__device__ __forceinline__ u64 int_mod(i64 k, const PrimeInfo &p)
+{
+    const u64 mag = k < 0 ? (u64)(-(k + 1)) + 1 : (u64)k;
+    const u64 r = reduce64(mag, p);
+    return k < 0 ? neg_mod(r, p.q) : r;
+}
 
 constexpr int MAXW = 8;  // special primes the ModDown prologue reads (and the fused path's digit-width bound)
 
@@ -770,7 +782,8 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
     auto store = [&](int k, u64 x) {
         const int e = tau + S::T * k;
         if (FIN) {
-            const u64 av = f.acc[b * f.as + c * f.acs + roff + e];
+            u64 av = f.acc[b * f.as + c * f.acs + roff + e];
+            if (f.has_kacc) av = mul_mod(av, int_mod(f.kacc, p), p);
             u64 r = mul_shoup(sub_mod(av, x, q), f.pinv[2 * pos], f.pinv[2 * pos + 1], q);
             if (c < f.nbase) r = add_mod(r, f.base[b * f.bs + c * f.bcs + roff + e], q);
             if (f.add) r = add_mod(r, f.add[b * f.ads + c * f.adcs + roff + e], q);
@@ -810,10 +823,13 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
                 // base (+ addend) + (acc - x) P^{-1}: the lazy product is in (-q, 2q), the sum in (-q, 4q)
                 const double pinv = d_from_u52(f.pinv[2 * pos]);
                 u64 *op = f.out + b * f.os + c * f.ocs + roff + tau;
+                const double ka = f.has_kacc ? d_from_u52(int_mod(f.kacc, p)) : 0.0;
 #pragma unroll
                 for (int k = 0; k < S::E; ++k) {
                     const double x = reduce_d(d[k], qd, qinv);
-                    const double r = mulmod_lazy_d(d_from_u52(fa[k]) - x, pinv, qd, qinv) + d_from_u52(fb[k]);
+                    // kacc acc is a lazy product in (-q, 2q); minus x it stays within (-2q, 2q)
+                    const double av = f.has_kacc ? mulmod_lazy_d(d_from_u52(fa[k]), ka, qd, qinv) : d_from_u52(fa[k]);
+                    const double r = mulmod_lazy_d(av - x, pinv, qd, qinv) + d_from_u52(fb[k]);
                     op[S::T * k] = u52_from_d(reduce_d(r, qd, qinv));
                 }
             } else {
@@ -824,6 +840,11 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
         }
 #pragma unroll
         for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(__builtin_nontemporal_load(in + tau + S::T * k));
+        if (SRC && f.has_kmul) {  // the source times kmul, reduced to [0, q)
+            const double kd = d_from_u52(int_mod(f.kmul, p));
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) d[k] = mulmod_d(d[k], kd, qd, qinv);
+        }
         if (!INV) {
             stages_d<LM, true, false, true>(d, tau, h, N1, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, true);
@@ -859,6 +880,11 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
     u64 v[S::E];
 #pragma unroll
     for (int k = 0; k < S::E; ++k) v[k] = __builtin_nontemporal_load(in + tau + S::T * k);
+    if (SRC && f.has_kmul) {
+        const u64 kq = int_mod(f.kmul, p);
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) v[k] = mul_mod(v[k], kq, p);
+    }
     if (!INV) {
         fwd_strided<LM, true>(v, tau, h, N1, W, Ws, q, q2);
         to_contig<LM>(v, line, tau);
@@ -1984,12 +2010,13 @@ void ntt_moddown(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 
 // Rescale of B ciphertexts of ncomp components at level l as a one-prime
 // ModDown: the last limbs, already in coefficient form in last [b][comp][N],
 // are converted (centred) to q_0 .. q_{l-1} inside the first forward pass, and
-// the second pass stores (in - x) q_l^{-1} into out.  tmp [b][comp][l][N]
-// holds the intermediate between the passes.
-void ntt_rescale(he_ctx *c, int level, int B, int ncomp, const u64 *last, const u64 *in, long long is, u64 *tmp,
-                 u64 *out, long long os)
+// the second pass stores (in - x) q_l^{-1} into out (in read with component
+// stride ics, times *kmul when kmul is given).  tmp [b][comp][l][N] holds the
+// intermediate between the passes.
+void ntt_rescale(he_ctx *c, int level, int B, int ncomp, const u64 *last, const u64 *in, long long is, long long ics,
+                 u64 *tmp, u64 *out, long long os, const i64 *kmul)
 {
-    const long long N = c->N, lc_in = (level + 1) * N, lc_out = (long long)level * N;
+    const long long N = c->N, lc_in = ics, lc_out = (long long)level * N;
     Fuse f{};
     f.src = last;
     f.sbs = ncomp * N;
@@ -2009,19 +2036,29 @@ void ntt_rescale(he_ctx *c, int level, int B, int ncomp, const u64 *last, const 
     f.os = os;
     f.ocs = lc_out;
     f.pinv = c->t.rs_qinv + (long long)level * c->nq * 2;
+    if (kmul) {
+        f.has_kacc = 1;
+        f.kacc = *kmul;
+    }
     NttArgs a = make_args(c, tmp, ncomp * lc_out, lc_out, ncomp, 0, level - 1, false);
     ntt_launch(c, a, B, level, +1, nullptr, PRO_MODDOWN, EPI_FINISH, &f);
 }
 
 // inverse NTT of the last limb (position l) of B ciphertexts of ncomp
-// components, read in place from in, written to last [b][comp][N]
-void intt_last(he_ctx *c, int level, int B, int ncomp, const u64 *in, long long is, u64 *last)
+// components (component stride ics), read in place from in (times *kmul when
+// given), written to last [b][comp][N]
+void intt_last(he_ctx *c, int level, int B, int ncomp, const u64 *in, long long is, long long ics, u64 *last,
+               const i64 *kmul)
 {
     const long long N = c->N;
     Fuse f{};
     f.src = in;
     f.sbs = is;
-    f.scs = (level + 1) * N;
+    f.scs = ics;
+    if (kmul) {
+        f.has_kmul = 1;
+        f.kmul = *kmul;
+    }
     NttArgs a = make_args(c, last - (long long)level * N, ncomp * N, N, ncomp, level, level, false);
     ntt_launch(c, a, B, 1, -1, nullptr, PRO_SRC, EPI_NONE, &f);
 }

@@ -479,10 +479,11 @@ def test_lr_step_feature_major_errors(small, small40):
 # ------------------------------------------------------------------ rings below 2^12 (unfused kernels)
 def test_small_ring_unfused_path_bit_exact():
     """N = 2^11 runs the stage-per-barrier NTT and the unfused key switch,
-    rescale and rotate-and-add: products, rotations and the margins (in place
-    rotate-and-sum) bit for bit against the oracle."""
+    rescale and rotate-and-add: products, rotations, the margins (in place
+    rotate-and-sum) and a whole row-major step (rescales of k Z read from the
+    higher-level data) bit for bit against the oracle."""
     H = _H()
-    cfg = (11, 4, 1, 1, 30)
+    cfg = (11, 5, 1, 1, 30)
     P = O.Params(*cfg)
     ctx = H.Context(*cfg)
     c, r = 16, P.S // 16
@@ -516,6 +517,15 @@ def test_small_ring_unfused_path_bit_exact():
     for mode in (0, 1):
         out = ctx.lr_margins(gZ, gW, c, r, gkeys, mode=mode)
         assert np.array_equal(ctx.download(out[0]), u.data), mode
+    coef = _coef()
+    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, 1.0 / r, 0.0)
+    mm = O.encode(LR.column_mask(P.S, c), pl["s_mask"], P.N)
+    oWn, og = LR.lr_grad_step(P, okeys, [oZ], oW, mm, coef, 1.0 / r, c, r, plan=pl)
+    mask = ctx.pt_load(mm, P.L - 1, pl["s_mask"])
+    for mode in (0, 1, 2):
+        Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, 1.0 / r, c, r, gkeys, mode=mode)
+        assert np.array_equal(ctx.download(Wn), oWn.data), mode
+        assert np.array_equal(ctx.download(g), og.data), mode
 
 
 # ------------------------------------------------------------------ encrypted inference (margins)
