@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <map>
+#include <mutex>
 #include <cstring>
 #include <vector>
 
@@ -151,6 +153,25 @@ void sample_hwt(u64 seed, int logN, int h, i64 *out)
     }
 }
 
+// Twiddles of every stage of a size-M FFT, stage len at offset len/2 - 1:
+// w[len/2 - 1 + k] = exp(sign 2 pi i k / len), k < len/2.  Computed once per
+// (M, sign) and kept for the process (the values are those each call used to
+// compute, so results do not change).
+static const std::vector<std::complex<double>> &fft_twiddles(size_t M, int sign)
+{
+    static std::mutex mu;
+    static std::map<std::pair<size_t, int>, std::vector<std::complex<double>>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto &w = cache[{M, sign}];
+    if (w.empty()) {
+        w.resize(M - 1);
+        for (size_t len = 2; len <= M; len <<= 1)
+            for (size_t k = 0; k < len / 2; ++k)
+                w[len / 2 - 1 + k] = std::polar(1.0, sign * 2.0 * M_PI * (double)k / (double)len);
+    }
+    return w;
+}
+
 // In-place radix-2 complex FFT of size M (power of two):
 // A[k] = sum_n a[n] exp(sign * 2 pi i k n / M).
 static void fft(std::vector<std::complex<double>> &a, int sign)
@@ -162,35 +183,63 @@ static void fft(std::vector<std::complex<double>> &a, int sign)
         j ^= bit;
         if (i < j) std::swap(a[i], a[j]);
     }
+    const std::vector<std::complex<double>> &tw = fft_twiddles(M, sign);
+    // the complex product written out (the library is built without
+    // contraction, so it rounds as std::complex's operator* does for finite
+    // operands)
+    double *d = reinterpret_cast<double *>(a.data());
+    const double *wd = reinterpret_cast<const double *>(tw.data());
     for (size_t len = 2; len <= M; len <<= 1) {
         const size_t half = len / 2;
-        std::vector<std::complex<double>> w(half);
-        for (size_t k = 0; k < half; ++k) w[k] = std::polar(1.0, sign * 2.0 * M_PI * (double)k / (double)len);
+        const double *w = wd + 2 * (half - 1);
         for (size_t s = 0; s < M; s += len)
             for (size_t k = 0; k < half; ++k) {
-                std::complex<double> u = a[s + k], v = a[s + k + half] * w[k];
-                a[s + k] = u + v;
-                a[s + k + half] = u - v;
+                double *x = d + 2 * (s + k), *y = d + 2 * (s + k + half);
+                const double wr = w[2 * k], wi = w[2 * k + 1];
+                const double vr = y[0] * wr - y[1] * wi, vi = y[0] * wi + y[1] * wr;
+                const double ur = x[0], ui = x[1];
+                x[0] = ur + vr;
+                x[1] = ui + vi;
+                y[0] = ur - vr;
+                y[1] = ui - vi;
             }
     }
 }
 
-// slot j <-> root zeta^(5^j), zeta = exp(i pi / N).  m_i = (1/N) sum over the
-// 2N-th roots of unity of the slot values at odd exponents, conjugates at -5^j.
+// Powers zeta^i, i < N, of zeta = exp(sign i pi / N), kept per (N, sign).
+static const std::vector<std::complex<double>> &twist(size_t N, int sign)
+{
+    static std::mutex mu;
+    static std::map<std::pair<size_t, int>, std::vector<std::complex<double>>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto &w = cache[{N, sign}];
+    if (w.empty()) {
+        w.resize(N);
+        for (size_t i = 0; i < N; ++i) w[i] = std::polar(1.0, sign * M_PI * (double)i / (double)N);
+    }
+    return w;
+}
+
+// slot j <-> root zeta^(5^j), zeta = exp(i pi / N); the conjugate slot sits at
+// zeta^(-5^j).  Only odd powers of zeta occur, so both directions are N-point
+// FFTs over omega = zeta^2 with a twist by zeta^i:
+//   encode: m_i = (1/N) Re(zeta^-i sum_k V_k omega^-(k i)), V_k the value at zeta^(2k+1);
+//   decode: value at zeta^(2k+1) = sum_i (m_i zeta^i) omega^(k i).
 int encode(int logN, const double *re, const double *im, int n, double scale, i64 *out)
 {
     const size_t N = (size_t)1 << logN, M = 2 * N;
-    std::vector<std::complex<double>> V(M, 0.0);
+    std::vector<std::complex<double>> V(N, 0.0);
     size_t e = 1;
     for (int j = 0; j < n; ++j) {
         std::complex<double> z(re[j], im ? im[j] : 0.0);
-        V[e] = z * scale;
-        V[M - e] = std::conj(z) * scale;
+        V[(e - 1) / 2] = z * scale;
+        V[(M - e - 1) / 2] = std::conj(z) * scale;
         e = (e * 5) % M;
     }
     fft(V, -1);
+    const std::vector<std::complex<double>> &tw = twist(N, -1);
     for (size_t i = 0; i < N; ++i) {
-        double v = V[i].real() / (double)N;
+        const double v = (V[i].real() * tw[i].real() - V[i].imag() * tw[i].imag()) / (double)N;
         if (!(std::fabs(v) < 4.611686018427388e18)) return -1;  // 2^62
         out[i] = (i64)std::llround(v);
     }
@@ -200,13 +249,15 @@ int encode(int logN, const double *re, const double *im, int n, double scale, i6
 void decode(int logN, const double *m, double scale, int n, double *re, double *im)
 {
     const size_t N = (size_t)1 << logN, M = 2 * N;
-    std::vector<std::complex<double>> A(M, 0.0);
-    for (size_t i = 0; i < N; ++i) A[i] = m[i];
+    const std::vector<std::complex<double>> &tw = twist(N, +1);
+    std::vector<std::complex<double>> A(N);
+    for (size_t i = 0; i < N; ++i) A[i] = m[i] * tw[i];
     fft(A, +1);
     size_t e = 1;
     for (int j = 0; j < n; ++j) {
-        re[j] = A[e].real() / scale;
-        if (im) im[j] = A[e].imag() / scale;
+        const size_t k = (e - 1) / 2;
+        re[j] = A[k].real() / scale;
+        if (im) im[j] = A[k].imag() / scale;
         e = (e * 5) % M;
     }
 }

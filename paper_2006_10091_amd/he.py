@@ -361,9 +361,10 @@ class Context:
         """One encrypted gradient step (he_lr_grad_step).  Z: list of block
         ciphertexts sharing one allocation (ct_block), packed in `layout`;
         feature-major with n_baby > 1: Zrot = rotate_data(Z, rows, n_baby).
-        Returns (W', g)."""
-        zs = (he_ct * len(Z))(*[z.struct() for z in Z])
-        zr = (he_ct * len(Zrot))(*[z.struct() for z in Zrot]) if Zrot else None
+        Z and Zrot may also be ct_array()s built once (callers stepping many
+        times skip rebuilding the argument arrays).  Returns (W', g)."""
+        zs = ct_array(Z)
+        zr = ct_array(Zrot) if Zrot else None
         w, m = W.struct(), mask.struct()
         lo = max(W.level - 4, 0)
         W_out = W_out or self.ct_empty(lo)
@@ -491,6 +492,14 @@ def step_mask(S, c, layout=LAYOUT_ROWS):
 def mask_level(level, layout=LAYOUT_ROWS):
     """Level of the step's mask plaintext for weights at `level`."""
     return level - 3 if layout == LAYOUT_FEATURES else level - 1
+
+
+def ct_array(cts):
+    """he_ct array argument for a list of ciphertexts (returned unchanged when
+    it already is one)."""
+    if isinstance(cts, ctypes.Array):
+        return cts
+    return (he_ct * len(cts))(*[c.struct() for c in cts])
 
 
 def rotation_steps(c, r, layout=LAYOUT_ROWS, n_baby=1):

@@ -59,6 +59,9 @@ class Worker:
         if n_baby > 1 and Zrot is None:
             Zrot = ctx.rotate_data(Z, rows, n_baby, keys)
         self.Zrot = Zrot if n_baby > 1 else None
+        # argument arrays built once: the blocks and their copies do not move
+        self._za = H.ct_array(Z)
+        self._zra = H.ct_array(self.Zrot) if self.Zrot else None
         self._masks = {}
         self._bufs = {}
 
@@ -86,9 +89,9 @@ class Worker:
         lo = W.level - 4
         W_out = self._out(lo, 0)
         G_out = self._out(lo, 1) if want_g else None
-        return ctx.lr_grad_step(self.Z, W, mask, self.coef, self.eta_over_n, self.cols, self.rows, self.keys,
+        return ctx.lr_grad_step(self._za, W, mask, self.coef, self.eta_over_n, self.cols, self.rows, self.keys,
                                 mode=self.mode, W_out=W_out, G_out=G_out, want_g=want_g, w_decay=self.w_decay,
-                                layout=self.layout, Zrot=self.Zrot, n_baby=self.n_baby)
+                                layout=self.layout, Zrot=self._zra, n_baby=self.n_baby)
 
 
 def encrypt_shard(ctx, keys, X, y, seed_enc, layout=H.LAYOUT_ROWS):
