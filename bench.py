@@ -351,19 +351,20 @@ def main():
                      "kernel": "ntt (forward, two passes) over %d limbs of N=2^16" % nlimb},
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(Wk, args.cpu_threads, nb, c, r)
+        out["cpu_baseline"] = cpu_baseline(Wk, args.cpu_threads, nb, c, r, best["n_baby"])
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(Wk, threads, nb, c, r):
+def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
     """The oracle on a bounded sample of the feature-major schedule: one
     mul+relin+rescale and one rotation at every level the schedule's key
     switches run at (the median of two runs each), extrapolated by the
-    schedule's key-switch counts: per block the margin product, the margin
-    rotations and the two products A and B3; per step the one
-    relinearisation of the summed terms and the sample-sum and replicate
-    rotations.  Tensor products, plaintext products, additions and the
-    refresh are left out, so the CPU rate is an upper bound."""
+    schedule's key-switch counts: per block the margin relinearisation, the
+    log2(c / n_baby) margin rotations and the two products A and B3; per step
+    W's n_baby - 1 baby-step rotations, the one relinearisation of the summed
+    terms and the sample-sum and replicate rotations.  Tensor products,
+    plaintext products, additions, the data's baby-step copies (built once per
+    shard) and the refresh are left out, so the CPU rate is an upper bound."""
     if threads:
         os.environ["OMP_NUM_THREADS"] = str(threads)
     nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -395,10 +396,10 @@ def cpu_baseline(Wk, threads, nb, c, r):
             ts.append(time.time() - t)
         return float(np.median(ts))
 
-    lc, lr = int(np.log2(c)), int(np.log2(r))
+    lc, lr = int(np.log2(c // n_baby)), int(np.log2(r))
     levels = [P.L - 4 * k for k in range(REFRESH_EVERY)]
     need_mul = sorted({l - k for l in levels for k in (0, 1, 2)})
-    need_rot = sorted({l - k for l in levels for k in (1, 3, 4)})
+    need_rot = sorted({l - k for l in levels for k in ((0, 1, 3, 4) if n_baby > 1 else (1, 3, 4))})
     sample = {}
     for lv in need_mul:
         x, z = ct(lv, 1), ct(lv, 3)
@@ -410,13 +411,16 @@ def cpu_baseline(Wk, threads, nb, c, r):
     for l in levels:  # the feature-major step at level l
         t_sched += nb * (sample["mul%d" % l] + lc * sample["rot%d" % (l - 1)] + 2 * sample["mul%d" % (l - 1)])
         t_sched += sample["mul%d" % (l - 2)] + lr * sample["rot%d" % (l - 3)] + lr * sample["rot%d" % (l - 4)]
+        if n_baby > 1:
+            t_sched += (n_baby - 1) * sample["rot%d" % l]
     t_step = t_sched / len(levels)
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": nthreads, "kind": "oracle",
             "sample": "one oracle mul+relin+rescale and one rotation at each level the feature-major schedule "
                       "key-switches at (median of 2 runs; %.1fs of sampled work, keys %.1fs), extrapolated by the "
-                      "schedule's key-switch counts (steps at levels %s: %d blocks x (1+%d+2) + 1+2x%d per step; the "
-                      "degree-2 term products, which need no key switch, are left out)" % (
-                          2 * sum(sample.values()), t_keys, "/".join(map(str, levels)), nb, lc, lr),
+                      "schedule's key-switch counts (steps at levels %s, %d baby steps: %d blocks x (1+%d+2) + %d+1+2x%d "
+                      "per step; tensor products, which need no key switch, are left out)" % (
+                          2 * sum(sample.values()), t_keys, "/".join(map(str, levels)), n_baby, nb, lc,
+                          n_baby - 1, lr),
             "extrapolated": True, "sample_seconds": sample}
 
 
