@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--layout", choices=("both", "feature-major", "row-major"), default="both",
                     help="packings to run (value needs feature-major)")
     ap.add_argument("--baby", type=int, default=16,
-                    help="baby steps of the feature-major margin sum (1 = rotations only)")
+                    help="baby steps of the margin sum, both packings (1 = rotations only)")
     ap.add_argument("--ntt-counters", action="store_true",
                     help="run only the calibration copy and the NTT batch (a target for rocprofv3 --pmc passes, "
                          "which cannot follow the step's graph launches); prints no bench line")
@@ -210,14 +210,14 @@ def bench_layout(torch, H, T, ctx, keys, X, y, coef, layout, args, Wk):
     wt = np.random.default_rng(Wk["seed_w"]).uniform(-0.05, 0.05, d)
     Wt = ctx.encrypt(ctx.pt_load(ctx.encode(H.pack_weights(wt, ctx.S, c, layout), ctx.delta), L, ctx.delta), keys,
                      Wk["seed_enc"], 1 << 22)
-    n_baby = args.baby if layout == H.LAYOUT_FEATURES else 1
+    n_baby = args.baby
     res["n_baby"] = n_baby
     Zrot = None
     if n_baby > 1:
         # the worker's baby-step copies of its data: computed once per shard
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Zrot = ctx.rotate_data(Z, r, n_baby, keys)
+        Zrot = ctx.rotate_data(Z, H.baby_unit(layout, r), n_baby, keys)
         torch.cuda.synchronize()
         res["baby_step_data_s"] = time.perf_counter() - t0
         res["baby_step_data_gib"] = len(Zrot) * 2 * (L + 1) * ctx.N * 8 / 2 ** 30
@@ -296,7 +296,7 @@ def main():
     if args.ks_counters:
         measure_copy_and_ks(torch, H, synth, ctx, ev)
         return
-    steps = sorted(set(H.rotation_steps(c, r, H.LAYOUT_ROWS)) |
+    steps = sorted(set(H.rotation_steps(c, r, H.LAYOUT_ROWS, max(args.baby, 1))) |
                    set(H.rotation_steps(c, r, H.LAYOUT_FEATURES, max(args.baby, 1))))
     t0 = time.time()
     keys = ctx.keygen(Wk["seed_keys"], steps)

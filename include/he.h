@@ -260,15 +260,16 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  * cyclic sum over the feature blocks leaves m_i in every slot of sample i, then
  * the polynomial; once per step, the sum inside each feature block, the mask
  * and the replication over the block.
- * Baby steps (feature-major only; n_baby a power of two, 1 <= n_baby <=
- * min(c, HE_MAXBABY); 1 = none): the margin sum over the c feature blocks is
- * split as sum_{g} Rot(sum_{j < n_baby} Rot(Z, j r) (x) Rot(W, j r), g n_baby r).
- * The caller keeps Zrot[b * (n_baby - 1) + j - 1] = Rot(Z[b], j r) for
+ * Baby steps (n_baby a power of two, 1 <= n_baby <= min(c, HE_MAXBABY);
+ * 1 = none): the margin sum, a cyclic sum of c rotations by multiples of a
+ * unit u (u = r feature-major, 1 row-major), is split as
+ * sum_{g} Rot(sum_{j < n_baby} Rot(Z, j u) (x) Rot(W, j u), g n_baby u).
+ * The caller keeps Zrot[b * (n_baby - 1) + j - 1] = Rot(Z[b], j u) for
  * j = 1 .. n_baby - 1 (he_rotate_many; one level >= W's, Z's scale, uniform
- * strides in that order; NULL when n_baby = 1); the step rotates W by j r once
+ * strides in that order; NULL when n_baby = 1); the step rotates W by j u once
  * for all blocks, sums the n_baby products per block without relinearising,
  * and relinearises and rescales once: per block log2(c / n_baby) rotations
- * instead of log2 c.  keys then also hold the rotations j r (j < n_baby).
+ * instead of log2 c.  keys then also hold the rotations j u (j < n_baby).
  * Outputs (caller memory, W's level - 4): W_out, and G_out (nullable) = g.
  * mode 0: plain form (one he_* operation per block per step, one kernel
  * sequence each); mode 1: batched form (every block in one launch per

@@ -24,13 +24,13 @@ Readings where the paper is silent (each listed in the design notes):
     the polynomial runs on that directly, and after the cross-block sum the
     gradient is summed inside each feature block (rotations 1..r/2), masked to
     slot j*r and replicated by rotations -1..-r/2, once per step.
-  * the feature-major margin sum may take baby and giant steps: with n_b
-    baby steps, the worker keeps Rot(Z, b r) (b < n_b) of its own data and
-    rotates W by the same b r once per step, sums the n_b products
-    Rot(Z, b r) (x) Rot(W, b r) as one degree-2 ciphertext (a rotation is a
-    ring automorphism, so that is the sum of Rot(Z (x) W, b r)), relinearises
-    and rescales it once, and finishes with the giant-step rotations
-    n_b r .. (c/2) r.
+  * the margin sum may take baby and giant steps: with n_b baby steps, the
+    worker keeps Rot(Z, b u) (b < n_b; u = r feature-major, 1 row-major) of
+    its own data and rotates W by the same b u once per step, sums the n_b
+    products Rot(Z, b u) (x) Rot(W, b u) as one degree-2 ciphertext (a
+    rotation is a ring automorphism, so that is the sum of Rot(Z (x) W, b u)),
+    relinearises and rescales it once, and finishes with the giant-step
+    rotations n_b u .. (c/2) u.
   * the products C = A B3, B1 = M Z1 and B2 = A Z2 feed only additions, so
     they are formed at one level with one scale sC q (Z1's scale chosen for
     it), left unrelinearised and unrescaled, summed with the a0 term and across
@@ -265,7 +265,8 @@ def _plan_features(q, level, s_Z, s_W, coef, eta_over_n, w_decay):
 def rotation_steps(c, r, layout=ROWS, n_baby=1):
     """Rotation steps used by the step.  Row-major: +-2^k (k < log2 c) and
     c*2^k (k < log2 r).  Feature-major: r*2^k (k < log2 c) and +-2^k
-    (k < log2 r); with n_baby > 1 baby steps also b*r for b < n_baby."""
+    (k < log2 r).  With n_baby > 1 baby steps also b*u for b < n_baby (u = r
+    feature-major, 1 row-major)."""
     if layout == FEATURES:
         st = [b * r for b in range(3, n_baby) if b & (b - 1)]
         t = 1
@@ -277,7 +278,7 @@ def rotation_steps(c, r, layout=ROWS, n_baby=1):
             st += [t, -t]
             t *= 2
         return st
-    st = []
+    st = [b for b in range(3, n_baby) if b & (b - 1)]
     t = 1
     while t < c:
         st += [t, -t]
@@ -316,18 +317,24 @@ def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_dec
     """One step of eq. (appr) + eq. (update) on ciphertexts (coefficient form).
     Z: list of block ciphertexts (same level >= W.level, same scale);
     W: weight ciphertext; mask_m: integer plaintext of column_mask at scale
-    plan['s_mask'].  Feature-major only: n_baby > 1 takes the margins by baby
-    and giant steps, with Zrot = rotate_data(P, keys, Z, r, n_baby).
+    plan['s_mask'].  n_baby > 1 takes the margins by baby and giant steps,
+    with Zrot = rotate_data(P, keys, Z, u, n_baby) (u = r feature-major, 1
+    row-major).
     Returns (W', g); g excludes the regulariser's -eta lambda w."""
     l = W.level
     pl = plan or plan_lr_step(P.q, l, Z[0].scale, W.scale, coef, eta_over_n, w_decay, layout)
     if layout == FEATURES:
         return _step_features(P, keys, Z, W, mask_m, c, r, pl, Zrot, n_baby)
     G = None
-    for zb in Z:
-        zl = O.drop(zb, l)
-        u = O.rescale(P, O.mul(P, zl, W, keys), scale=pl["s1"])
-        t = 1
+    if n_baby > 1:
+        Ws = [W] + [O.rotate(P, W, b, keys) for b in range(1, n_baby)]
+    for k, zb in enumerate(Z):
+        if n_baby > 1:
+            u = _margin_products(P, keys, [zb] + list(Zrot[k]), Ws, l, pl["s1"])
+            t = n_baby
+        else:
+            u = O.rescale(P, O.mul(P, O.drop(zb, l), W, keys), scale=pl["s1"])
+            t = 1
         while t < c:
             u = O.add(P, u, O.rotate(P, u, t, keys))
             t *= 2
@@ -367,10 +374,10 @@ def _terms_prescale(P, zb, A, B3, M, Z1, Z2, lp, pl):
     return G
 
 
-def rotate_data(P, keys, Z, r, n_baby):
-    """The worker's baby-step copies of its data: Rot(z_b, b r) for
-    b = 1 .. n_baby - 1, per block."""
-    return [[O.rotate(P, zb, b * r, keys) for b in range(1, n_baby)] for zb in Z]
+def rotate_data(P, keys, Z, unit, n_baby):
+    """The worker's baby-step copies of its data: Rot(z_b, b unit) for
+    b = 1 .. n_baby - 1, per block (unit = r feature-major, 1 row-major)."""
+    return [[O.rotate(P, zb, b * unit, keys) for b in range(1, n_baby)] for zb in Z]
 
 
 def _margin_products(P, keys, zs, Ws, l, s1):

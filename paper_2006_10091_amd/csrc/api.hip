@@ -533,8 +533,17 @@ he_status mul_relin_rescale(he_ctx *c, Arena &ar, StepBufs &s, int l, int nb, co
 }
 
 // per-block part of the step for blocks [b0, b0+nb); G (+)= sum of their terms
+// Baby-step copies of the data for the margins: block b's copy for baby step
+// j (1 <= j < n_baby) at zr + b * zrb + (j - 1) * zrs, component stride zrc.
+struct BabyData {
+    const u64 *zr = nullptr;
+    long long zrb = 0, zrs = 0, zrc = 0;
+    int n_baby = 1;
+};
+
 he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, const he_ct *Z, long long zbs, int b0,
-                      int nb, const he_ct *W, const he_pt *mask, int cols, const he_keys *keys, bool accumulate)
+                      int nb, const he_ct *W, const he_pt *mask, int cols, const he_keys *keys, bool accumulate,
+                      const BabyData &bd)
 {
     const long long N = c->N;
     const int l = W->level;
@@ -542,11 +551,22 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
     const u64 *zp = Z[b0].data;
     const long long zc = (lz + 1) * N;
     const long long wc = (l + 1) * N;
-    // D1: u = RS(relin(Z (x) W)), level l-1
-    TRY(mul_relin_rescale(c, ar, s, l, nb, zp, zbs, zc, W->data, 0, wc, keys->rlk, s.U));
     const long long u1 = (long long)l * N;  // component stride at level l-1
-    // column sum: u += Rot(u, t), t = 1, 2, .., cols/2
-    for (int t = 1; t < cols; t <<= 1) {
+    int t0 = 1;
+    if (bd.n_baby > 1) {
+        // D1 by baby steps: u = RS(relin(sum_j Rot(Z, j) (x) Rot(W, j))), level l-1
+        const long long lc = (l + 1) * N;
+        hek::baby_sum_b(c, l, nb, bd.n_baby, zp, zbs, zc, bd.zr + b0 * bd.zrb, bd.zrb, bd.zrs, bd.zrc, W->data, wc,
+                        s.Wr, 2 * lc, lc, s.T3, 3 * lc, lc);
+        TRY(relin_apply(c, ar, l, nb, s.T3, 3 * lc, keys->rlk, s.U0, 2 * lc));
+        TRY(rescale_apply(c, ar, l, nb, s.U0, 2 * lc, s.U, 2 * u1));
+        t0 = bd.n_baby;
+    } else {
+        // D1: u = RS(relin(Z (x) W)), level l-1
+        TRY(mul_relin_rescale(c, ar, s, l, nb, zp, zbs, zc, W->data, 0, wc, keys->rlk, s.U));
+    }
+    // column sum: u += Rot(u, t), t = t0, 2 t0, .., cols/2
+    for (int t = t0; t < cols; t <<= 1) {
         const u64 *key = find_rot_key(keys, galois_of(c, t));
         if (!key) return HE_EKEY;
         TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, galois_of(c, t), key, s.U, 2 * u1, s.U));  // U += Rot(U)
@@ -578,15 +598,6 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
 // over the feature blocks (every slot of sample i ends with m_i), then the
 // polynomial one level above the row-major circuit; G (+)= sum of the terms
 // at level l-3.
-// Baby-step copies of the data for the feature-major margins: block b's copy
-// for baby step j (1 <= j < n_baby) at zr + b * zrb + (j - 1) * zrs, component
-// stride zrc.
-struct BabyData {
-    const u64 *zr = nullptr;
-    long long zrb = 0, zrs = 0, zrc = 0;
-    int n_baby = 1;
-};
-
 he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, const he_ct *Z,
                                long long zbs, int b0, int nb, const he_ct *W, int cols, int rows,
                                const he_keys *keys, bool accumulate, const BabyData &bd)
@@ -788,13 +799,15 @@ he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_block
     StepBufs s;
     const bool fm = pl.layout == HE_LAYOUT_FEATURES;
     TRY(step_alloc(c, ar, l, chunk, pl.layout, bd.n_baby, s));
-    if (fm && bd.n_baby > 1) {
-        // the baby steps of W, once per step for every block: Rot(W, j r), j = 1 .. n_baby - 1
+    if (bd.n_baby > 1) {
+        // the baby steps of W, once per step for every block: Rot(W, j u), j = 1 .. n_baby - 1
+        // (u = rows feature-major, 1 row-major)
         const long long lc = (l + 1) * N;
+        const long long unit = fm ? rows : 1;
         hek::EntryKeys ek;
         hek::EntryGal eg;
         for (int j = 1; j < bd.n_baby; ++j) {
-            eg.g[j - 1] = galois_of(c, (long long)j * rows);
+            eg.g[j - 1] = galois_of(c, (long long)j * unit);
             ek.k[j - 1] = find_rot_key(keys, eg.g[j - 1]);
         }
         TRY(rotate_multi_apply(c, ar, l, bd.n_baby - 1, W->data, 0, eg, ek, s.Wr, 2 * lc));
@@ -806,7 +819,7 @@ he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_block
         if (fm)
             TRY(step_blocks_features(c, ar, s, pl, Z, bs, b0, nb, W, cols, rows, keys, b0 > 0, bd));
         else
-            TRY(step_blocks(c, ar, s, pl, Z, bs, b0, nb, W, mask, cols, keys, b0 > 0));
+            TRY(step_blocks(c, ar, s, pl, Z, bs, b0, nb, W, mask, cols, keys, b0 > 0, bd));
     }
     const long long g1 = (long long)(l - 3) * N;  // component stride at level l-4
     {
@@ -1280,7 +1293,7 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
         return HE_EINVAL;
     if (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES) return HE_EINVAL;
     const bool fm = layout == HE_LAYOUT_FEATURES;
-    if (n_baby < 1 || n_baby > HE_MAXBABY || (n_baby & (n_baby - 1)) || (n_baby > 1 && (!fm || n_baby > cols || !Zrot)))
+    if (n_baby < 1 || n_baby > HE_MAXBABY || (n_baby & (n_baby - 1)) || (n_baby > 1 && (n_baby > cols || !Zrot)))
         return HE_EINVAL;
     if (W->level < 4) return HE_ELEVEL;
     if (!W_out || !W_out->data || (G_out && !G_out->data)) return HE_EINVAL;
@@ -1327,10 +1340,14 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
     const long long unit = fm ? rows : cols;
     for (int t = 1; t < pm; t <<= 1)
         if (!find_rot_key(k, galois_of(c, t)) || !find_rot_key(k, galois_of(c, -t))) return HE_EKEY;
-    for (int t = n_baby; t < st; t <<= 1)
-        if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
+    // the margin sum: baby steps j u (j < n_baby; u = rows feature-major, 1 row-major), giant steps
+    const long long mu = fm ? rows : 1;
     for (int j = 1; j < n_baby; ++j)
-        if (!find_rot_key(k, galois_of(c, (long long)j * unit))) return HE_EKEY;
+        if (!find_rot_key(k, galois_of(c, (long long)j * mu))) return HE_EKEY;
+    for (int t = n_baby; t < cols; t <<= 1)
+        if (!find_rot_key(k, galois_of(c, (long long)t * mu))) return HE_EKEY;
+    for (int t = 1; t < st; t <<= 1)
+        if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
     const int chunk = mode == 0 ? 1 : n_blocks;
     TRY(ensure_ws(c, step_bytes(c, l, chunk, layout, n_baby)));
     if (mode == 2) {
@@ -1438,8 +1455,7 @@ size_t he_lr_step_bytes(const he_ctx *c, int level, int n_blocks, int layout, in
 {
     if (!c || level < 4 || level >= c->nq || n_blocks < 1 || (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES))
         return 0;
-    if (n_baby < 1 || n_baby > HE_MAXBABY || (n_baby & (n_baby - 1)) || (n_baby > 1 && layout != HE_LAYOUT_FEATURES))
-        return 0;
+    if (n_baby < 1 || n_baby > HE_MAXBABY || (n_baby & (n_baby - 1))) return 0;
     return step_bytes(c, level, mode == 0 ? 1 : n_blocks, layout, n_baby);
 }
 

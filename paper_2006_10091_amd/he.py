@@ -360,7 +360,7 @@ class Context:
                      want_g=True, w_decay=0.0, layout=LAYOUT_ROWS, Zrot=None, n_baby=1):
         """One encrypted gradient step (he_lr_grad_step).  Z: list of block
         ciphertexts sharing one allocation (ct_block), packed in `layout`;
-        feature-major with n_baby > 1: Zrot = rotate_data(Z, rows, n_baby).
+        with n_baby > 1: Zrot = rotate_data(Z, baby_unit(layout, rows), n_baby).
         Z and Zrot may also be ct_array()s built once (callers stepping many
         times skip rebuilding the argument arrays).  Returns (W', g)."""
         zs = ct_array(Z)
@@ -412,12 +412,13 @@ class Context:
             o.update(s_)
         return outs
 
-    def rotate_data(self, Z, rows, n_baby, keys):
-        """The baby-step copies of a feature-major shard for lr_grad_step:
-        Rot(Z[b], j rows) for j = 1 .. n_baby - 1, block by block."""
+    def rotate_data(self, Z, unit, n_baby, keys):
+        """The baby-step copies of a shard for lr_grad_step: Rot(Z[b], j unit)
+        for j = 1 .. n_baby - 1, block by block (unit = baby_unit(layout,
+        rows))."""
         if n_baby <= 1:
             return None
-        return self.rotate_many(Z, [j * rows for j in range(1, n_baby)], keys)
+        return self.rotate_many(Z, [j * unit for j in range(1, n_baby)], keys)
 
     def margins_bytes(self, level, n_blocks, mode=1):
         return int(_lib.he_lr_margins_bytes(self.h, level, n_blocks, mode))
@@ -494,6 +495,12 @@ def mask_level(level, layout=LAYOUT_ROWS):
     return level - 3 if layout == LAYOUT_FEATURES else level - 1
 
 
+def baby_unit(layout, rows):
+    """Rotation unit of the margin sum's baby steps: a feature block (rows
+    slots) feature-major, one slot row-major."""
+    return rows if layout == LAYOUT_FEATURES else 1
+
+
 def ct_array(cts):
     """he_ct array argument for a list of ciphertexts (returned unchanged when
     it already is one)."""
@@ -503,9 +510,11 @@ def ct_array(cts):
 
 
 def rotation_steps(c, r, layout=LAYOUT_ROWS, n_baby=1):
-    """Rotation keys the step needs (with n_baby baby steps: also j r, j < n_baby)."""
+    """Rotation keys the step needs (with n_baby baby steps also j u, j < n_baby,
+    u = baby_unit(layout, r))."""
     pm, st, unit = (r, c, r) if layout == LAYOUT_FEATURES else (c, r, c)
-    out = [j * unit for j in range(3, n_baby) if j & (j - 1)]
+    mu = baby_unit(layout, r)
+    out = [j * mu for j in range(3, n_baby) if j & (j - 1)]
     t = 1
     while t < pm:
         out += [t, -t]

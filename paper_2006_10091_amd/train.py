@@ -49,7 +49,7 @@ class Worker:
 
     def __init__(self, ctx, keys, Z, coef, eta_over_n, cols, rows, mode=2, w_decay=0.0, layout=H.LAYOUT_ROWS,
                  n_baby=1, Zrot=None):
-        """n_baby > 1 (feature-major): the worker keeps the baby-step rotations
+        """n_baby > 1: the worker keeps the baby-step rotations
         of its data (n_baby - 1 copies of the shard), computed here unless
         given as Zrot (ctx.rotate_data)."""
         self.ctx, self.keys, self.Z = ctx, keys, Z
@@ -57,7 +57,7 @@ class Worker:
         self.cols, self.rows, self.mode, self.layout = cols, rows, mode, layout
         self.n_baby = n_baby
         if n_baby > 1 and Zrot is None:
-            Zrot = ctx.rotate_data(Z, rows, n_baby, keys)
+            Zrot = ctx.rotate_data(Z, H.baby_unit(layout, rows), n_baby, keys)
         self.Zrot = Zrot if n_baby > 1 else None
         # argument arrays built once: the blocks and their copies do not move
         self._za = H.ct_array(Z)

@@ -4,11 +4,11 @@ launch configuration the bench times.
 * every key-switching operation of the step, bit for bit against the oracle,
   at the levels the step uses;
 * one-block steps (the whole circuit, the once-per-step sums included) bit for
-  bit against the oracle, in the batched form, in both block layouts, and
-  feature-major with 16 baby steps;
-* the full 47-block shard in both layouts (feature-major also with 16 baby
-  steps): the plain, batched and graph-replayed forms agree bit for bit, and
-  the decrypted gradient is within 2^-20 of the FP64 one;
+  bit against the oracle, in the batched form, in both block layouts, with
+  and without 16 baby steps;
+* the full 47-block shard in both layouts, with and without 16 baby steps:
+  the plain, batched and graph-replayed forms agree bit for bit, and the
+  decrypted gradient is within 2^-20 of the FP64 one;
 * 10 training steps with a refresh every 4, both layouts, against FP64.
 """
 import numpy as np
@@ -37,7 +37,7 @@ def env():
     ctx = H.Context(*CFG)
     X, y = synth.image_data(W["seed_data"], W["n"])
     blocks, c, r = H.pack_blocks(X, y, ctx.S)
-    steps = sorted(set(LR.rotation_steps(c, r)) | set(LR.rotation_steps(c, r, LR.FEATURES, 16)))
+    steps = sorted(set(LR.rotation_steps(c, r, LR.ROWS, 16)) | set(LR.rotation_steps(c, r, LR.FEATURES, 16)))
     gk = ctx.keygen(W["seed_keys"], steps)
     return dict(H=H, P=P, ctx=ctx, X=X, y=y, blocks=blocks, c=c, r=r, steps=steps, gk=gk)
 
@@ -73,7 +73,7 @@ def _as_grid(H, slots, c, r, layout):
     return v.reshape(c, r).T if layout == H.LAYOUT_FEATURES else v.reshape(r, c)
 
 
-@pytest.mark.parametrize("layout,n_baby", [(0, 1), (1, 1), (1, 16)])
+@pytest.mark.parametrize("layout,n_baby", [(0, 1), (1, 1), (1, 16), (0, 16)])
 def test_full_size_one_block_step_bit_exact(env, okeys, layout, n_baby):
     """One block of the shard through the whole circuit, GPU batched form vs
     oracle, in both layouts, and feature-major with baby steps."""
@@ -94,18 +94,19 @@ def test_full_size_one_block_step_bit_exact(env, okeys, layout, n_baby):
     gW = ctx.encrypt(ctx.pt_load(mw, P.L, P.delta), gk, 9, 999)
     pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n, 0.0, layout)
     mm = O.encode(LR.feature_mask(P.S, r) if layout else LR.column_mask(P.S, c), pl["s_mask"], P.N)
-    oZr = LR.rotate_data(P, okeys, [oZ], r, n_baby) if n_baby > 1 else None
+    unit = r if layout else 1
+    oZr = LR.rotate_data(P, okeys, [oZ], unit, n_baby) if n_baby > 1 else None
     oWn, og = LR.lr_grad_step(P, okeys, [oZ], oW, mm, coef, eta_n, c, r, plan=pl, layout=layout, Zrot=oZr,
                               n_baby=n_baby)
     H = env["H"]
     mask = ctx.pt_load(mm, H.mask_level(P.L, layout), pl["s_mask"])
-    gZr = ctx.rotate_data(gZ, r, n_baby, gk)
+    gZr = ctx.rotate_data(gZ, unit, n_baby, gk)
     Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, gk, mode=1, layout=layout, Zrot=gZr, n_baby=n_baby)
     assert np.array_equal(ctx.download(Wn), oWn.data)
     assert np.array_equal(ctx.download(g), og.data)
 
 
-@pytest.mark.parametrize("layout,n_baby", [(0, 1), (1, 1), (1, 16)])
+@pytest.mark.parametrize("layout,n_baby", [(0, 1), (1, 1), (1, 16), (0, 16)])
 def test_full_shard_forms_agree_and_gradient_within_tolerance(env, layout, n_baby):
     ctx, gk, H = env["ctx"], env["gk"], env["H"]
     L, S = ctx.n_q - 1, ctx.S
@@ -121,7 +122,7 @@ def test_full_shard_forms_agree_and_gradient_within_tolerance(env, layout, n_bab
     coef, eta_n = _coef(), 1.0 / X.shape[0]
     pl = ctx.plan_lr_step(L, ctx.delta, ctx.delta, coef, eta_n, layout=layout)
     mask = ctx.pt_load(ctx.encode(H.step_mask(S, c, layout), pl["s_mask"]), H.mask_level(L, layout), pl["s_mask"])
-    Zr = ctx.rotate_data(Z, r, n_baby, gk)
+    Zr = ctx.rotate_data(Z, H.baby_unit(layout, r), n_baby, gk)
     outs = []
     for mode in (0, 1, 2, 2):
         Wn, g = ctx.lr_grad_step(Z, Wc, mask, coef, eta_n, c, r, gk, mode=mode, layout=layout, Zrot=Zr,
@@ -141,7 +142,7 @@ def test_full_shard_forms_agree_and_gradient_within_tolerance(env, layout, n_bab
         assert np.max(np.abs(wn[row, :d] - want)) / np.max(np.abs(want)) < 2.0 ** -20
 
 
-@pytest.mark.parametrize("layout,n_baby", [(0, 1), (1, 1), (1, 16)])
+@pytest.mark.parametrize("layout,n_baby", [(0, 1), (1, 1), (1, 16), (0, 16)])
 def test_full_size_training_ten_steps_refresh_every_four(env, layout, n_baby):
     """The image shard's 10 steps with a refresh every 4 (Alg. 1 / Alg. 2),
     graph-replayed batched form, against FP64 plaintext training."""

@@ -38,7 +38,7 @@ def small():
     ctx = H.Context(*cfg)
     X, y = synth.small_data()
     blocks, c, r = LR.pack_blocks(X, y, P.S)
-    steps = sorted(set(LR.rotation_steps(c, r)) | set(LR.rotation_steps(c, r, LR.FEATURES)))
+    steps = sorted(set(LR.rotation_steps(c, r, LR.ROWS, 16)) | set(LR.rotation_steps(c, r, LR.FEATURES)))
     okeys = O.Keys(P, W["seed_keys"], rot_steps=steps)
     gkeys = ctx.keygen(W["seed_keys"], steps)
     return dict(W=W, P=P, ctx=ctx, X=X, y=y, blocks=blocks, c=c, r=r, okeys=okeys, gkeys=gkeys, H=H)
@@ -150,7 +150,7 @@ def test_error_paths(small):
         ctx.add(a, b)
     assert e.value.status == 4
     with pytest.raises(H.HEError) as e:
-        ctx.rotate(a, 3, gk)  # no key for step 3
+        ctx.rotate(a, 17, gk)  # no key for step 17
     assert e.value.status == 5
 
 
@@ -328,6 +328,45 @@ def small40():
     steps = sorted(set(LR.rotation_steps(c, r)) | set(LR.rotation_steps(c, r, LR.FEATURES, 16)))
     return dict(W=W, P=P, ctx=ctx, okeys=O.Keys(P, W["seed_keys"], rot_steps=steps),
                 gkeys=ctx.keygen(W["seed_keys"], steps), H=_H())
+
+
+@pytest.mark.parametrize("n_baby,n", [(4, 2048), (16, 700), (8, 256)])
+def test_lr_step_row_major_baby_steps_bit_exact(small, n_baby, n):
+    """Row-major column sums by baby steps over the rotated data (unit 1):
+    the data copies and the step in its three forms, bit for bit against the
+    oracle (16 = c: no giant step), and the decrypted g within 2^-20."""
+    ctx, P, W, H = small["ctx"], small["P"], small["W"], small["H"]
+    X, y = synth.small_data(n=n)
+    blocks, c, r = LR.pack_blocks(X, y, P.S)
+    coef = _coef()
+    w0 = synth.initial_weights("small", 16, 97)
+    oZ, gZ = [], ctx.ct_block(blocks.shape[0], P.L)
+    for i in range(blocks.shape[0]):
+        m = O.encode(blocks[i], P.delta, P.N)
+        oZ.append(O.encrypt_sk(P, small["okeys"], m, P.L, P.delta, W["seed_enc"], i))
+        ctx.encrypt(ctx.pt_load(m, P.L, P.delta), small["gkeys"], W["seed_enc"], i, out=gZ[i])
+    oZr = LR.rotate_data(P, small["okeys"], oZ, 1, n_baby)
+    gZr = ctx.rotate_data(gZ, H.baby_unit(H.LAYOUT_ROWS, r), n_baby, small["gkeys"])
+    for b in range(len(oZ)):
+        for j in range(n_baby - 1):
+            assert np.array_equal(ctx.download(gZr[b * (n_baby - 1) + j]), oZr[b][j].data), (b, j)
+    mw = O.encode(LR.pack_weights(w0, P.S, c), P.delta, P.N)
+    oW = O.encrypt_sk(P, small["okeys"], mw, P.L, P.delta, W["seed_enc"], 100005)
+    gW = ctx.encrypt(ctx.pt_load(mw, P.L, P.delta), small["gkeys"], W["seed_enc"], 100005)
+    eta_n = 1.0 / n
+    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n)
+    mm = O.encode(LR.column_mask(P.S, c), pl["s_mask"], P.N)
+    oWn, og = LR.lr_grad_step(P, small["okeys"], oZ, oW, mm, coef, eta_n, c, r, plan=pl, Zrot=oZr, n_baby=n_baby)
+    mask = ctx.pt_load(mm, P.L - 1, pl["s_mask"])
+    for mode in (0, 1, 2, 2):
+        Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, small["gkeys"], mode=mode, Zrot=gZr,
+                                 n_baby=n_baby)
+        assert np.array_equal(ctx.download(Wn), oWn.data), mode
+        assert np.array_equal(ctx.download(g), og.data), mode
+    wdec = ctx.decrypt_decode(gW, small["gkeys"]).real[:16]
+    gref = LR.lr_gradient_fp64(X, y, wdec, coef, eta_n)
+    gd = ctx.decrypt_decode(g, small["gkeys"]).real.reshape(r, c)[:, :16]
+    assert np.max(np.abs(gd - gref)) / np.max(np.abs(gref)) < TOL
 
 
 @pytest.mark.parametrize("loss,w_decay,n", [("ls", 0.0, 2048), ("hinge", 0.0, 700), ("ls", 0.05, 300)])

@@ -477,15 +477,18 @@ def test_plan_consistency():
         LR.plan_lr_step(P.q, 3, P.delta, P.delta, coef, 1 / 6000)
 
 
-def test_encrypted_step_matches_fp64_gradient():
+@pytest.mark.parametrize("n_baby", [1, 4, 16])
+def test_encrypted_step_matches_fp64_gradient(n_baby):
     """Whole circuit on the small workload: decrypted g within 2^-20 of the FP64
-    gradient with the same polynomial at the decrypted input weights."""
+    gradient with the same polynomial at the decrypted input weights; with
+    n_baby > 1 the column sum takes baby steps over the rotated data (16 = c:
+    no giant step)."""
     W = synth.WORKLOADS["small"]
     P = O.Params(W["logN"], W["nq"], W["nk"], W["alpha"], W["log_delta"])
     X, y = synth.small_data()
     w0 = synth.initial_weights("small", 16, W["seed_w"])
     blocks, c, r = LR.pack_blocks(X, y, P.S)
-    keys = O.Keys(P, W["seed_keys"], rot_steps=LR.rotation_steps(c, r))
+    keys = O.Keys(P, W["seed_keys"], rot_steps=LR.rotation_steps(c, r, LR.ROWS, n_baby))
     coef = LR.grad_poly_binomial(8.0)
     coef[0], coef[2] = 0.5, 0.0
     eta_n = 1.0 / X.shape[0]
@@ -495,7 +498,8 @@ def test_encrypted_step_matches_fp64_gradient():
                       W["seed_enc"], 100000)
     pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n)
     mask = O.encode(LR.column_mask(P.S, c), pl["s_mask"], P.N)
-    Wn, g = LR.lr_grad_step(P, keys, Z, Wc, mask, coef, eta_n, c, r, plan=pl)
+    Zrot = LR.rotate_data(P, keys, Z, 1, n_baby) if n_baby > 1 else None
+    Wn, g = LR.lr_grad_step(P, keys, Z, Wc, mask, coef, eta_n, c, r, plan=pl, Zrot=Zrot, n_baby=n_baby)
     wdec = O.decrypt(P, keys, Wc).real[:16]
     gref = LR.lr_gradient_fp64(X, y, wdec, coef, eta_n)
     gd = O.decrypt(P, keys, g).real.reshape(r, c)[:, :16]
