@@ -359,10 +359,11 @@ def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
     """The oracle on a bounded sample of the feature-major schedule: one
     mul+relin+rescale and one rotation at every level the schedule's key
     switches run at (the median of two runs each), extrapolated by the
-    schedule's key-switch counts: per block the margin relinearisation, the
-    log2(c / n_baby) margin rotations and the two products A and B3; per step
-    W's n_baby - 1 baby-step rotations, the one relinearisation of the summed
-    terms and the sample-sum and replicate rotations.  Tensor products,
+    schedule's key-switch counts: per block the margin relinearisation and the
+    log2(c / n_baby) margin rotations; per step W's n_baby - 1 baby-step
+    rotations, the one relinearisation of the summed degree-4 terms (three key
+    switches, each timed as a mul+relin+rescale) and the sample-sum and
+    replicate rotations.  The degree-2 products A and B3 (tensor and rescale),
     plaintext products, additions, the data's baby-step copies (built once per
     shard) and the refresh are left out, so the CPU rate is an upper bound."""
     if threads:
@@ -398,7 +399,7 @@ def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
 
     lc, lr = int(np.log2(c // n_baby)), int(np.log2(r))
     levels = [P.L - 4 * k for k in range(REFRESH_EVERY)]
-    need_mul = sorted({l - k for l in levels for k in (0, 1, 2)})
+    need_mul = sorted({l - k for l in levels for k in (0, 2)})
     need_rot = sorted({l - k for l in levels for k in ((0, 1, 3, 4) if n_baby > 1 else (1, 3, 4))})
     sample = {}
     for lv in need_mul:
@@ -409,16 +410,16 @@ def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
         sample["rot%d" % lv] = timed(lambda: O.rotate(P, x, 1, keys))
     t_sched = 0.0
     for l in levels:  # the feature-major step at level l
-        t_sched += nb * (sample["mul%d" % l] + lc * sample["rot%d" % (l - 1)] + 2 * sample["mul%d" % (l - 1)])
-        t_sched += sample["mul%d" % (l - 2)] + lr * sample["rot%d" % (l - 3)] + lr * sample["rot%d" % (l - 4)]
+        t_sched += nb * (sample["mul%d" % l] + lc * sample["rot%d" % (l - 1)])
+        t_sched += 3 * sample["mul%d" % (l - 2)] + lr * sample["rot%d" % (l - 3)] + lr * sample["rot%d" % (l - 4)]
         if n_baby > 1:
             t_sched += (n_baby - 1) * sample["rot%d" % l]
     t_step = t_sched / len(levels)
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": nthreads, "kind": "oracle",
             "sample": "one oracle mul+relin+rescale and one rotation at each level the feature-major schedule "
                       "key-switches at (median of 2 runs; %.1fs of sampled work, keys %.1fs), extrapolated by the "
-                      "schedule's key-switch counts (steps at levels %s, %d baby steps: %d blocks x (1+%d+2) + %d+1+2x%d "
-                      "per step; tensor products, which need no key switch, are left out)" % (
+                      "schedule's key-switch counts (steps at levels %s, %d baby steps: %d blocks x (1+%d) + %d+3+2x%d "
+                      "per step; tensor products and rescales of A and B3, which need no key switch, are left out)" % (
                           2 * sum(sample.values()), t_keys, "/".join(map(str, levels)), n_baby, nb, lc,
                           n_baby - 1, lr),
             "extrapolated": True, "sample_seconds": sample}

@@ -151,13 +151,15 @@ size_t he_ct3_bytes(const he_ctx *ctx, int level);
 
 /* ---------------------------------------------------------------- keys */
 
-/* Bytes of the key buffer for n_rot rotation keys (secret key, relinearisation
- * key and the rotation keys, each evaluation key [dnum][2][n_q+n_special][N]). */
+/* Bytes of the key buffer for n_rot rotation keys (secret key, the keys for
+ * s^2, s^3 and s^4 and the rotation keys, each evaluation key
+ * [dnum][2][n_q+n_special][N]). */
 size_t he_keys_bytes(const he_ctx *ctx, int n_rot);
 
 /* Key generation (Alg. 2, initialisation: the server generates the keys).
  * The secret is ternary with 64 nonzero coefficients; the relinearisation key
- * is for s^2 and one rotation key is made per entry of rot_steps (a left
+ * is for s^2, two more switch s^3 and s^4 to s (the gradient step relinearises
+ * a degree-4 sum), and one rotation key is made per entry of rot_steps (a left
  * rotation of the slot vector by that many slots, Galois element 5^t mod 2N).
  * Randomness: ChaCha20 keyed by seed.  key_buf: caller device memory of at
  * least he_keys_bytes(ctx, n_rot) bytes; *out is a host handle referencing it
@@ -166,8 +168,9 @@ he_status he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *rot_steps, int n_
                     void *key_buf, size_t key_buf_bytes, he_keys **out);
 he_status he_keys_destroy(he_keys *keys);
 /* Download a key for inspection, coefficient order: which = -2 secret
- * ([n_q+n_special][N]), -1 relinearisation key, else the Galois element of a
- * rotation key ([dnum][2][n_q+n_special][N]).  host must hold the size. */
+ * ([n_q+n_special][N]), -1 relinearisation key (s^2), -3 / -4 the keys for s^3
+ * / s^4, else the Galois element of a rotation key ([dnum][2][n_q+n_special][N]).
+ * host must hold the size. */
 he_status he_keys_download(he_ctx *ctx, const he_keys *keys, int64_t which, uint64_t *host);
 
 /* ---------------------------------------------------------------- encoding (host FP64) */
@@ -259,7 +262,10 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  * replicate, polynomial; row sum once per step.  Feature-major: per block, a
  * cyclic sum over the feature blocks leaves m_i in every slot of sample i, then
  * the polynomial; once per step, the sum inside each feature block, the mask
- * and the replication over the block.
+ * and the replication over the block.  In the polynomial, A = M^2 and
+ * B3 = M (a3 Z) are rescaled but not relinearised; the terms (degree 4 in the
+ * secret) are summed over the blocks and relinearised once per step with the
+ * keys for s^2, s^3 and s^4, then rescaled.
  * Baby steps (n_baby a power of two, 1 <= n_baby <= min(c, HE_MAXBABY);
  * 1 = none): the margin sum, a cyclic sum of c rotations by multiples of a
  * unit u (u = r feature-major, 1 row-major), is split as

@@ -59,6 +59,8 @@ def lib():
         "orc_ndigits": (c_int, [P, c_int]),
         "orc_keyswitch": (None, [P, c_int, u64p, u64p, u64p]),
         "orc_rescale": (None, [P, c_int, u64p, u64p]),
+        "orc_rescale_n": (None, [P, c_int, c_int, u64p, u64p]),
+        "orc_tensor_n": (None, [P, c_int, c_int, u64p, c_int, u64p, u64p]),
         "orc_automorph": (None, [P, c_int, POINTER(c_int), c_uint64, u64p, u64p]),
         "orc_add": (None, [P, c_int, u64p, u64p, u64p]),
         "orc_mul_int": (None, [P, c_int, u64p, c_int64, u64p]),
@@ -234,6 +236,17 @@ class Keys:
         sp = np.zeros((nfull, N), dtype=np.uint64)
         L.orc_secret_square(P.cp, _i(self.s), _u(sp))
         self.rlk = self._evk(sp, 0)
+        # keys for s^3 and s^4 (relinearising degree-3 and degree-4
+        # ciphertexts), key ids 2 and 4: even, so apart from every Galois
+        # element; s^3 = s^2 s and s^4 = s^2 s^2, negacyclic, per prime
+        sp3 = np.zeros_like(sp)
+        sp4 = np.zeros_like(sp)
+        for i in range(nfull):
+            q = P.q[i]
+            si = np.ascontiguousarray(np.where(self.s < 0, self.s + q, self.s).astype(np.uint64))
+            L.orc_polymul(_u(sp[i]), _u(si), _u(sp3[i]), P.logN, q, P.psi[i])
+            L.orc_polymul(_u(sp[i]), _u(sp[i]), _u(sp4[i]), P.logN, q, P.psi[i])
+        self.rlk_pow = {2: self.rlk, 3: self._evk(sp3, 2), 4: self._evk(sp4, 4)}
         self.rot = {}
         for t in rot_steps:
             self.add_rotation(t)
@@ -363,6 +376,53 @@ def relin(P, d, scale, level, keys):
     lib().orc_add(P.cp, n, _u(np.ascontiguousarray(d[1])), _u(ks[1]), _u(o1))
     out[0], out[1] = o0, o1
     return CT(out, level, scale)
+
+
+def tensor_n(P, level, x, y):
+    """Tensor of two ciphertexts of any degree at level l, each an array
+    [deg+1][l+1][N] (a polynomial in the secret): d_k = sum_{i+j=k} x_i y_j."""
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    y = np.ascontiguousarray(y, dtype=np.uint64)
+    assert x.shape[1:] == (level + 1, P.N) and y.shape[1:] == (level + 1, P.N)
+    d = np.zeros((x.shape[0] + y.shape[0] - 1, level + 1, P.N), dtype=np.uint64)
+    lib().orc_tensor_n(P.cp, level, x.shape[0], _u(x), y.shape[0], _u(y), _u(d))
+    return d
+
+
+def rescale_n(P, level, d):
+    """Rescale of every component of an array [n][l+1][N] -> [n][l][N]."""
+    d = np.ascontiguousarray(d, dtype=np.uint64)
+    out = np.zeros((d.shape[0], level, P.N), dtype=np.uint64)
+    lib().orc_rescale_n(P.cp, level, d.shape[0], _u(d), _u(out))
+    return out
+
+
+def add_n(P, level, x, y):
+    """Sum of two ciphertext arrays of any degrees (the shorter one padded)."""
+    n = level + 1
+    if x.shape[0] < y.shape[0]:
+        x, y = y, x
+    out = np.array(x, dtype=np.uint64, copy=True)
+    for k in range(y.shape[0]):
+        o = np.zeros((n, P.N), dtype=np.uint64)
+        lib().orc_add(P.cp, n, _u(np.ascontiguousarray(x[k])), _u(np.ascontiguousarray(y[k])), _u(o))
+        out[k] = o
+    return out
+
+
+def relin_n(P, d, scale, level, keys):
+    """Relinearisation of a degree-k ciphertext (k <= 4): (d_0, d_1) plus the
+    key switch of each d_j (j >= 2) from s^j to s, each on its own."""
+    assert 2 <= d.shape[0] - 1 <= 4
+    n = level + 1
+    o = [np.ascontiguousarray(d[0]), np.ascontiguousarray(d[1])]
+    for j in range(2, d.shape[0]):
+        ks = keyswitch(P, level, d[j], keys.rlk_pow[j])
+        for c in range(2):
+            t = np.zeros((n, P.N), dtype=np.uint64)
+            lib().orc_add(P.cp, n, _u(o[c]), _u(ks[c]), _u(t))
+            o[c] = t
+    return CT(np.stack(o), level, scale)
 
 
 def mul(P, x, y, keys):

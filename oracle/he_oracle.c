@@ -368,6 +368,28 @@ void orc_tensor(const orc_params *P, int level, const u64 *x, const u64 *y, u64 
     free(t);
 }
 
+/*
+ * tensor of a degree-(nx-1) and a degree-(ny-1) ciphertext at level l (the
+ * ciphertext as a polynomial in the secret): d_k = sum_{i+j=k} x_i y_j,
+ * k = 0 .. nx+ny-2.  x: [nx][l+1][N], y: [ny][l+1][N], d: [nx+ny-1][l+1][N].
+ */
+void orc_tensor_n(const orc_params *P, int level, int nx, const u64 *x, int ny, const u64 *y, u64 *d)
+{
+    u64 N = (u64)1 << P->logN;
+    int n = level + 1;
+    size_t pl = (size_t)n * N;
+    u64 *t = (u64 *)malloc(pl * 8);
+    memset(d, 0, (size_t)(nx + ny - 1) * pl * 8);
+    for (int i = 0; i < nx; i++)
+        for (int j = 0; j < ny; j++) {
+            u64 *dk = d + (size_t)(i + j) * pl;
+            rns_polymul(P, x + (size_t)i * pl, y + (size_t)j * pl, t, n);
+            for (int r = 0; r < n; r++)
+                for (u64 k = 0; k < N; k++) LIMB(dk, r)[k] = addmod(LIMB(dk, r)[k], LIMB(t, r)[k], P->q[r]);
+        }
+    free(t);
+}
+
 /* prime of basis position pos at level l: pos <= l -> q_pos, else special pos-l-1 */
 static u64 basis_prime(const orc_params *P, int level, int pos, u64 *psi)
 {
@@ -492,12 +514,13 @@ void orc_keyswitch(const orc_params *P, int level, const u64 *d, const u64 *evk,
     free(acc);
 }
 
-/* rescale: [2][l+1][N] -> [2][l][N]; c_i <- (c_i - [c_l]_centered) * q_l^{-1} mod q_i */
-void orc_rescale(const orc_params *P, int level, const u64 *ct, u64 *out)
+/* rescale of ncomp components: [ncomp][l+1][N] -> [ncomp][l][N];
+ * c_i <- (c_i - [c_l]_centered) * q_l^{-1} mod q_i, each component on its own */
+void orc_rescale_n(const orc_params *P, int level, int ncomp, const u64 *ct, u64 *out)
 {
     u64 N = (u64)1 << P->logN;
     u64 ql = P->q[level];
-    for (int c = 0; c < 2; c++) {
+    for (int c = 0; c < ncomp; c++) {
         const u64 *in = ct + (size_t)c * (level + 1) * N;
         u64 *o = out + (size_t)c * level * N;
         for (int i = 0; i < level; i++) {
@@ -511,6 +534,8 @@ void orc_rescale(const orc_params *P, int level, const u64 *ct, u64 *out)
         }
     }
 }
+
+void orc_rescale(const orc_params *P, int level, const u64 *ct, u64 *out) { orc_rescale_n(P, level, 2, ct, out); }
 
 /* automorphism X -> X^g (g odd) on n limbs, coefficient form */
 void orc_automorph(const orc_params *P, int n, const int *prime_idx, u64 g, const u64 *in, u64 *out)

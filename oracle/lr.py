@@ -35,6 +35,12 @@ Readings where the paper is silent (each listed in the design notes):
     they are formed at one level with one scale sC q (Z1's scale chosen for
     it), left unrelinearised and unrescaled, summed with the a0 term and across
     the blocks, and the sum is relinearised and rescaled once per step.
+  * A = M^2 and B3 = M Z3 feed only those products, so they are rescaled but
+    not relinearised (three components each): C is then of degree 4 in the
+    secret (B2 of degree 3), and the step's one relinearisation switches d_2,
+    d_3 and d_4 from s^2, s^3 and s^4 to s with three keys (rescaling a
+    degree-2 ciphertext is the same per-component rounding; its error grows
+    with s^2, a few bits below the scale here).
   * eta/n enters through the scale bookkeeping (an exact FP64 change of the
     declared scale), and W is brought to the gradient's scale by one integer
     multiplication and rescale, both fixed by plan_lr_step below.
@@ -290,27 +296,6 @@ def rotation_steps(c, r, layout=ROWS, n_baby=1):
     return st
 
 
-# ---------------------------------------------------------------- degree-2 helpers
-# Additions act on each component on its own, so degree-2 ciphertexts
-# (d0, d1, d2) are added pair by pair; relinearisation is linear and is
-# applied once to a sum.
-def _pairs(d3):
-    return O.CT(np.ascontiguousarray(d3[:2]), d3.shape[1] - 1, 1.0), O.CT(np.stack([d3[2], d3[2]]), d3.shape[1] - 1,
-                                                                           1.0)
-
-
-def add3(P, x3, y3):
-    ax, bx = _pairs(x3)
-    ay, by = _pairs(y3)
-    return np.concatenate([O.add(P, ax, ay).data, O.add(P, bx, by).data[:1]])
-
-
-def add3_1(P, x3, y):
-    """Degree-2 plus degree-1 (added to d0, d1)."""
-    ax, _ = _pairs(x3)
-    return np.concatenate([O.add(P, ax, y).data, x3[2:3]])
-
-
 # ---------------------------------------------------------------- encrypted step
 def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_decay=0.0, layout=ROWS, Zrot=None,
                  n_baby=1):
@@ -343,17 +328,17 @@ def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_dec
         while t < c:
             M = O.add(P, M, O.rotate(P, M, -t, keys))
             t *= 2
-        A = O.rescale(P, O.mul(P, M, M, keys), scale=pl["sA"])
+        A = _rs_product(P, M, M)
         Z3 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 1), pl["k3"]), scale=pl["sZ3"])
-        B3 = O.rescale(P, O.mul(P, M, Z3, keys), scale=pl["sB3"])
+        B3 = _rs_product(P, M, Z3)
         Z1 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 2), pl["k1"]), scale=pl["sZ1"])
         Z2 = None
         if pl["k2"] != 0:
             Z2 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 2), pl["k2"]), scale=pl["sZ2"])
         Gb = _terms_prescale(P, zb, A, B3, M, Z1, Z2, l - 3, pl)
-        G = Gb if G is None else add3(P, G, Gb)
+        G = Gb if G is None else O.add_n(P, l - 3, G, Gb)
     # one relinearisation and one rescale of the summed terms
-    G = O.rescale(P, O.relin(P, G, pl["sC"] * float(P.q[l - 3]), l - 3, keys), scale=pl["sC"])
+    G = O.rescale(P, O.relin_n(P, G, pl["sC"] * float(P.q[l - 3]), l - 3, keys), scale=pl["sC"])
     t = 1
     while t < r:
         G = O.add(P, G, O.rotate(P, G, t * c, keys))
@@ -363,14 +348,22 @@ def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_dec
     return O.add(P, Wn, g), g
 
 
+def _rs_product(P, x, y):
+    """RS(x (x) y), not relinearised: a degree-2 array [3][l][N] one level
+    below x and y (which share their level)."""
+    l = x.level
+    return O.rescale_n(P, l, O.tensor_n(P, l, x.data, y.data))
+
+
 def _terms_prescale(P, zb, A, B3, M, Z1, Z2, lp, pl):
-    """The block's gradient terms, unrescaled, as one degree-2 ciphertext at
-    level lp with scale sC q_lp: C = A (x) B3, B1 = M (x) Z1 (M dropped to lp;
-    Z1 carries sC q_lp / sM), k0 Z, and for a2 != 0 B2 = A (x) Z2."""
-    G = add3(P, O.tensor(P, A, B3)[0], O.tensor(P, O.drop(M, lp), Z1)[0])
-    G = add3_1(P, G, O.mul_int(P, O.drop(zb, lp), pl["k0"]))
+    """The block's gradient terms, unrescaled, as one degree-4 array at level lp
+    with scale sC q_lp: C = A (x) B3 (A, B3 of degree 2), B1 = M (x) Z1 (M
+    dropped to lp; Z1 carries sC q_lp / sM), k0 Z, and for a2 != 0
+    B2 = A (x) Z2."""
+    G = O.add_n(P, lp, O.tensor_n(P, lp, A, B3), O.tensor_n(P, lp, O.drop(M, lp).data, Z1.data))
+    G = O.add_n(P, lp, G, O.mul_int(P, O.drop(zb, lp), pl["k0"]).data)
     if pl["k2"] != 0:
-        G = add3(P, G, O.tensor(P, A, Z2)[0])
+        G = O.add_n(P, lp, G, O.tensor_n(P, lp, A, Z2.data))
     return G
 
 
@@ -386,7 +379,7 @@ def _margin_products(P, keys, zs, Ws, l, s1):
     D = None
     for zr, wr in zip(zs, Ws):
         t3 = O.tensor(P, O.drop(zr, l), wr)[0]
-        D = t3 if D is None else add3(P, D, t3)
+        D = t3 if D is None else O.add_n(P, l, D, t3)
     return O.rescale(P, O.relin(P, D, s1 * float(P.q[l]), l, keys), scale=s1)
 
 
@@ -408,17 +401,17 @@ def _step_features(P, keys, Z, W, mask_m, c, r, pl, Zrot=None, n_baby=1):
             u = O.add(P, u, O.rotate(P, u, t * r, keys))
             t *= 2
         M = u
-        A = O.rescale(P, O.mul(P, M, M, keys), scale=pl["sA"])
+        A = _rs_product(P, M, M)
         Z3 = O.rescale(P, O.mul_int(P, O.drop(zb, l), pl["k3"]), scale=pl["sZ3"])
-        B3 = O.rescale(P, O.mul(P, M, Z3, keys), scale=pl["sB3"])
+        B3 = _rs_product(P, M, Z3)
         Z1 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 1), pl["k1"]), scale=pl["sZ1"])
         Z2 = None
         if pl["k2"] != 0:
             Z2 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 1), pl["k2"]), scale=pl["sZ2"])
         Gb = _terms_prescale(P, zb, A, B3, M, Z1, Z2, l - 2, pl)
-        G = Gb if G is None else add3(P, G, Gb)
+        G = Gb if G is None else O.add_n(P, l - 2, G, Gb)
     # one relinearisation and one rescale of the summed terms
-    G = O.rescale(P, O.relin(P, G, pl["sC"] * float(P.q[l - 2]), l - 2, keys), scale=pl["sC"])
+    G = O.rescale(P, O.relin_n(P, G, pl["sC"] * float(P.q[l - 2]), l - 2, keys), scale=pl["sC"])
     t = 1
     while t < r:  # sum over the samples inside each feature block
         G = O.add(P, G, O.rotate(P, G, t, keys))

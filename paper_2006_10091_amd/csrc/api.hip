@@ -456,15 +456,16 @@ he_status make_evk(he_ctx *c, Arena &ar, u64 seed, uint32_t key_id, const u64 *s
 
 // ------------------------------------------------------------------ the gradient step
 struct StepBufs {
-    u64 *T3, *U0, *U, *R, *M, *Z3, *Z1, *A, *B3, *G, *Rg, *Z2, *Gm, *G3;
+    u64 *T3, *U0, *U, *R, *M, *Z3, *Z1, *A, *B3, *G, *Rg, *Z2, *Gm, *G5;
     u64 *Wr;  // feature-major baby steps: Rot(W, b r), b = 1 .. n_baby - 1
 };
 
 // Per-block intermediates sit one level higher in the feature-major circuit
-// (no mask level between the margins and the polynomial): e = 1 there.  The
-// block's gradient terms C (and B1, B2, k0 Z) are summed unrescaled and
-// unrelinearised (three components) at level l-3+e, across the blocks too,
-// and the sum is relinearised and rescaled once per step.
+// (no mask level between the margins and the polynomial): e = 1 there.  A and
+// B3 are rescaled but not relinearised (three components); the block's
+// gradient terms C = A B3 (and B1, B2, k0 Z) are summed unrescaled and
+// unrelinearised (degree 4, five components) at level l-3+e, across the
+// blocks too, and the sum is relinearised and rescaled once per step.
 size_t step_bytes(const he_ctx *c, int l, int nb, int layout, int n_baby = 1)
 {
     const size_t N = c->N;
@@ -475,12 +476,13 @@ size_t step_bytes(const he_ctx *c, int l, int nb, int layout, int n_baby = 1)
     n += 2 * al((size_t)nb * 2 * l * N);                   // U, R
     n += al((size_t)nb * 2 * (l - 1) * N);                 // M
     n += 2 * al((size_t)nb * 2 * (l - 1 + e) * N);         // Z3, Z1
-    n += 2 * al((size_t)nb * 2 * (l - 2 + e) * N);         // A, B3
+    n += 2 * al((size_t)nb * 3 * (l - 2 + e) * N);         // A, B3
     n += al((size_t)nb * 2 * (l - 2 + e) * N);             // Z2
-    n += al((size_t)3 * (l - 2 + e) * N);                  // G3
+    n += al((size_t)5 * (l - 2 + e) * N);                  // G5
     n += 2 * al((size_t)2 * (l - 3 + e) * N);              // G, Rg
     n += al((size_t)2 * (l - 3) * N);                      // Gm
     size_t scratch = std::max(rotate_scratch(c, l, nb), rescale_scratch(c, l, nb));
+    scratch = std::max(scratch, rescale_scratch(c, l - 1, nb, 3));  // A, B3: degree 2
     if (n_baby > 1) {
         n += al((size_t)(n_baby - 1) * 2 * (l + 1) * N);  // Wr
         scratch = std::max(scratch, rotate_scratch(c, l, n_baby - 1));
@@ -500,15 +502,15 @@ he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, int layout, int n_baby
     s.M = ar.take((size_t)nb * 2 * (l - 1) * N);
     s.Z3 = ar.take((size_t)nb * 2 * (l - 1 + e) * N);
     s.Z1 = ar.take((size_t)nb * 2 * (l - 1 + e) * N);
-    s.A = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
-    s.B3 = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
+    s.A = ar.take((size_t)nb * 3 * (l - 2 + e) * N);
+    s.B3 = ar.take((size_t)nb * 3 * (l - 2 + e) * N);
     s.Z2 = ar.take((size_t)nb * 2 * (l - 2 + e) * N);
-    s.G3 = ar.take((size_t)3 * (l - 2 + e) * N);
+    s.G5 = ar.take((size_t)5 * (l - 2 + e) * N);
     s.G = ar.take((size_t)2 * (l - 3 + e) * N);
     s.Rg = ar.take((size_t)2 * (l - 3 + e) * N);
     s.Gm = ar.take((size_t)2 * (l - 3) * N);
     s.Wr = n_baby > 1 ? ar.take((size_t)(n_baby - 1) * 2 * (l + 1) * N) : nullptr;
-    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Z3, s.Z1, s.A, s.B3, s.Z2, s.G3, s.G, s.Rg, s.Gm};
+    u64 *all[] = {s.T3, s.U0, s.U, s.R, s.M, s.Z3, s.Z1, s.A, s.B3, s.Z2, s.G5, s.G, s.Rg, s.Gm};
     for (u64 *p : all)
         if (!p) return HE_ENOMEM;
     if (n_baby > 1 && !s.Wr) return HE_ENOMEM;
@@ -530,6 +532,16 @@ he_status mul_relin_rescale(he_ctx *c, Arena &ar, StepBufs &s, int l, int nb, co
     hek::tensor_b(c, l, nb, x, xb, xc, y, yb, yc, s.T3, 3 * lc, lc);
     TRY(relin_apply(c, ar, l, nb, s.T3, 3 * lc, rlk, s.U0, 2 * lc));
     return rescale_apply(c, ar, l, nb, s.U0, 2 * lc, out, 2LL * l * N);
+}
+
+// ct x ct -> rescale, not relinearised, for nb entries at level l: output
+// [nb][3][l][N] (degree 2)
+he_status mul_rescale3(he_ctx *c, Arena &ar, StepBufs &s, int l, int nb, const u64 *x, long long xb, long long xc,
+                       const u64 *y, long long yb, long long yc, u64 *out)
+{
+    const long long N = c->N, lc = (l + 1) * N;
+    hek::tensor_b(c, l, nb, x, xb, xc, y, yb, yc, s.T3, 3 * lc, lc);
+    return rescale_apply(c, ar, l, nb, s.T3, 3 * lc, out, 3LL * l * N, 3);
 }
 
 // per-block part of the step for blocks [b0, b0+nb); G (+)= sum of their terms
@@ -580,17 +592,17 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
         if (!key) return HE_EKEY;
         TRY(rotate_apply(c, ar, l - 2, nb, s.M, 2 * m1, galois_of(c, -t), key, s.M, 2 * m1, s.M));  // M += Rot(M)
     }
-    // A = M^2 ; Z3 = RS(k3 Z), B3 = M Z3 ; Z1 = RS(k1 Z), B1 = M Z1   (level l-3)
-    TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.M, 2 * m1, m1, keys->rlk, s.A));
+    // A = RS(M^2) ; Z3 = RS(k3 Z), B3 = RS(M Z3), degree 2 ; Z1 = RS(k1 Z)   (level l-3)
+    TRY(mul_rescale3(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.M, 2 * m1, m1, s.A));
     TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z3, 2 * m1, 2, &pl.k3, zc));
-    TRY(mul_relin_rescale(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.Z3, 2 * m1, m1, keys->rlk, s.B3));
+    TRY(mul_rescale3(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.Z3, 2 * m1, m1, s.B3));
     // Z1 = RS(k1 Z) and, for a2 != 0, Z2 = RS(k2 Z), both at level l-3
     const long long a1 = (long long)(l - 2) * N;
     TRY(rescale_apply(c, ar, l - 2, nb, zp, zbs, s.Z1, 2 * a1, 2, &pl.k1, zc));
     if (pl.k2 != 0) TRY(rescale_apply(c, ar, l - 2, nb, zp, zbs, s.Z2, 2 * a1, 2, &pl.k2, zc));
-    // the blocks' terms at level l-3 (unrescaled), summed straight into G3
-    hek::terms_sum_b(c, l - 3, nb, s.A, s.B3, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, s.M, 2 * m1, m1, zp, zbs,
-                     zc, pl.k0, s.G3, accumulate);
+    // the blocks' terms at level l-3 (unrescaled, degree 4), summed straight into G5
+    hek::terms_sum_b(c, l - 3, nb, s.A, s.B3, 3 * a1, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, s.M, 2 * m1, m1,
+                     zp, zbs, zc, pl.k0, s.G5, accumulate);
     return last_error();
 }
 
@@ -628,17 +640,17 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
         if (!key) return HE_EKEY;
         TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, gal, key, s.U, 2 * u1, s.U));  // U += Rot(U)
     }
-    // M = u.  A = M^2 ; Z3 = RS(k3 Z), B3 = M Z3 ; Z1 = RS(k1 Z), B1 = M Z1   (level l-2)
-    TRY(mul_relin_rescale(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.U, 2 * u1, u1, keys->rlk, s.A));
+    // M = u.  A = RS(M^2) ; Z3 = RS(k3 Z), B3 = RS(M Z3), degree 2 ; Z1 = RS(k1 Z)   (level l-2)
+    TRY(mul_rescale3(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.U, 2 * u1, u1, s.A));
     TRY(rescale_apply(c, ar, l, nb, zp, zbs, s.Z3, 2 * u1, 2, &pl.k3, zc));
-    TRY(mul_relin_rescale(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.Z3, 2 * u1, u1, keys->rlk, s.B3));
+    TRY(mul_rescale3(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.Z3, 2 * u1, u1, s.B3));
     // Z1 = RS(k1 Z) and, for a2 != 0, Z2 = RS(k2 Z), both at level l-2
     const long long a1 = (long long)(l - 1) * N;
     TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z1, 2 * a1, 2, &pl.k1, zc));
     if (pl.k2 != 0) TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z2, 2 * a1, 2, &pl.k2, zc));
-    // the block's terms at level l-2 (unrescaled); G3 (+)= their sum
-    hek::terms_sum_b(c, l - 2, nb, s.A, s.B3, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, s.U, 2 * u1, u1, zp, zbs,
-                     zc, pl.k0, s.G3, accumulate);
+    // the block's terms at level l-2 (unrescaled, degree 4); G5 (+)= their sum
+    hek::terms_sum_b(c, l - 2, nb, s.A, s.B3, 3 * a1, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, s.U, 2 * u1, u1,
+                     zp, zbs, zc, pl.k0, s.G5, accumulate);
     return last_error();
 }
 
@@ -823,10 +835,13 @@ he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_block
     }
     const long long g1 = (long long)(l - 3) * N;  // component stride at level l-4
     {
-        // one relinearisation and one rescale of the summed terms
+        // one relinearisation of the summed degree-4 terms: (g0, g1) plus the
+        // key switches of g2, g3, g4 from s^2, s^3, s^4; then one rescale
         const int lg = fm ? l - 2 : l - 3;
         const long long x1 = (long long)(lg + 1) * N;
-        TRY(relin_apply(c, ar, lg, 1, s.G3, 3 * x1, keys->rlk, s.U0, 2 * x1));
+        TRY(ks_apply(c, ar, lg, 1, s.G5 + 2 * x1, 0, keys->rlk, s.G5, 0, x1, 2, s.U0, 0, x1));
+        TRY(ks_apply(c, ar, lg, 1, s.G5 + 3 * x1, 0, keys->rlk3, s.U0, 0, x1, 2, s.U0, 0, x1));
+        TRY(ks_apply(c, ar, lg, 1, s.G5 + 4 * x1, 0, keys->rlk4, s.U0, 0, x1, 2, s.U0, 0, x1));
         TRY(rescale_apply(c, ar, lg, 1, s.U0, 2 * x1, s.G, 2LL * lg * N));
     }
     u64 *g = s.G;
@@ -960,7 +975,7 @@ size_t he_keys_bytes(const he_ctx *c, int n_rot)
 {
     if (!c || n_rot < 0) return 0;
     const size_t evk = (size_t)c->dnum * 2 * c->np * c->N * 8;
-    return (size_t)c->np * c->N * 8 + evk * (1 + (size_t)n_rot);
+    return (size_t)c->np * c->N * 8 + evk * (3 + (size_t)n_rot);
 }
 
 he_status he_keygen(he_ctx *c, uint64_t seed, const int32_t *rot_steps, int n_rot, void *key_buf,
@@ -972,19 +987,22 @@ he_status he_keygen(he_ctx *c, uint64_t seed, const int32_t *rot_steps, int n_ro
     const size_t N = c->N;
     const int np = c->np;
     const size_t evk_n = (size_t)c->dnum * 2 * np * N;
-    TRY(ensure_ws(c, (al((size_t)np * N) * 3) * 8 + 4096));
+    TRY(ensure_ws(c, (al((size_t)np * N) * 4) * 8 + 4096));
     std::unique_ptr<he_keys> k(new (std::nothrow) he_keys());
     if (!k) return HE_ENOMEM;
     k->ctx = c;
     k->sk = (u64 *)key_buf;
     k->rlk = k->sk + (size_t)np * N;
+    k->rlk3 = k->rlk + evk_n;
+    k->rlk4 = k->rlk3 + evk_n;
     // secret: ternary, 64 nonzero coefficients (host ChaCha20), residues, NTT
     std::vector<i64> s(N);
     hehost::sample_hwt(seed, c->logN, std::min(64, (int)N), s.data());
     Arena ar = arena(c);
     u64 *sd = ar.take(N);
     u64 *sp = ar.take((size_t)np * N);
-    if (!sd || !sp) return HE_ENOMEM;
+    u64 *sq = ar.take((size_t)np * N);
+    if (!sd || !sp || !sq) return HE_ENOMEM;
     HIPCHK(hipMemcpyAsync(sd, s.data(), N * 8, hipMemcpyHostToDevice, c->stream));
     std::vector<int> ids = identity_positions(np);
     hek::int_to_rns(c, (const i64 *)sd, np, ids.data(), k->sk);
@@ -992,7 +1010,13 @@ he_status he_keygen(he_ctx *c, uint64_t seed, const int32_t *rot_steps, int n_ro
     // relinearisation key: s' = s^2
     hek::ewise(c, 3, np - 1, 1, 1, k->sk, 0, 0, k->sk, 0, 0, sp, 0, 0, 0);
     TRY(make_evk(c, ar, seed, 0, k->sk, sp, k->rlk));
-    u64 *next = k->rlk + evk_n;
+    // keys for s^3 = s^2 s and s^4 = s^2 s^2 (key ids 2 and 4: even, so apart
+    // from every Galois element)
+    hek::ewise(c, 3, np - 1, 1, 1, sp, 0, 0, k->sk, 0, 0, sq, 0, 0, 0);
+    TRY(make_evk(c, ar, seed, 2, k->sk, sq, k->rlk3));
+    hek::ewise(c, 3, np - 1, 1, 1, sp, 0, 0, sp, 0, 0, sq, 0, 0, 0);
+    TRY(make_evk(c, ar, seed, 4, k->sk, sq, k->rlk4));
+    u64 *next = k->rlk4 + evk_n;
     for (int r = 0; r < n_rot; ++r) {
         u64 g = galois_of(c, rot_steps[r]);
         if (g == 1 || k->rot.count(g)) continue;
@@ -1025,7 +1049,7 @@ he_status he_keys_download(he_ctx *c, const he_keys *k, int64_t which, uint64_t 
         src = k->sk;
         npoly = 1;
     } else {
-        src = which == -1 ? k->rlk : find_rot_key(k, (u64)which);
+        src = which == -1 ? k->rlk : which == -3 ? k->rlk3 : which == -4 ? k->rlk4 : find_rot_key(k, (u64)which);
         if (!src) return HE_EKEY;
         npoly = c->dnum * 2;
     }

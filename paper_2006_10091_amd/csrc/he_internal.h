@@ -75,7 +75,8 @@ struct he_ctx {
 struct he_keys {
     he_ctx *ctx;
     u64 *sk;                        // [np][N] NTT
-    u64 *rlk;                       // [dnum][2][np][N] NTT
+    u64 *rlk;                       // [dnum][2][np][N] NTT: s^2 -> s
+    u64 *rlk3, *rlk4;               // the same for s^3 and s^4 (degree-4 relinearisation)
     std::map<uint64_t, u64 *> rot;  // Galois element -> key
 };
 
@@ -130,11 +131,12 @@ void tensor_b(he_ctx *c, int level, int B, const u64 *x, long long xb, long long
               long long yc, u64 *o, long long ob, long long oc);
 // ModUp basis conversion of every digit: y [B][l+1][N] scaled iNTT output,
 // ext [B][beta][l+1+nk][N] (positions outside each digit written)
-// the gradient terms of nb blocks summed (or accumulated) into G [3][lp+1][N]:
-// sum_b A (x) B3 + M (x) Z1 + k0 Z (+ A (x) Z2 when Z2)
-void terms_sum_b(he_ctx *c, int lp, int nb, const u64 *A, const u64 *B3, const u64 *Z1, const u64 *Z2, long long ps,
-                 long long pc, const u64 *M, long long ms, long long mc, const u64 *Z, long long zs, long long zc,
-                 i64 k0, u64 *G, bool accumulate);
+// the gradient terms of nb blocks summed (or accumulated) into the degree-4
+// G [5][lp+1][N]: sum_b A (x) B3 + M (x) Z1 + k0 Z (+ A (x) Z2 when Z2), with
+// A, B3 of degree 2 ([b][3][lp+1][N], batch stride as)
+void terms_sum_b(he_ctx *c, int lp, int nb, const u64 *A, const u64 *B3, long long as, const u64 *Z1, const u64 *Z2,
+                 long long ps, long long pc, const u64 *M, long long ms, long long mc, const u64 *Z, long long zs,
+                 long long zc, i64 k0, u64 *G, bool accumulate);
 // baby-step margin products (MAX_BABY = 16 at most): o[blk] = sum_b Zb[blk] (x) Wb[b]
 void baby_sum_b(he_ctx *c, int level, int nblk, int nbaby, const u64 *z, long long zb, long long zc, const u64 *zr,
                 long long zrb, long long zrs, long long zrc, const u64 *w, long long wc, const u64 *wr, long long wrs,

@@ -678,15 +678,20 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
         if (!INV && q < (1ull << 46)) {  // signed lazy: the row pass reads a signed intermediate
             if (PRO == PRO_MODDOWN && cv.fp) {
                 conv_column_d<S::E>(cv, (long long)tau * N2 + col, (long long)S::T * N2, d, qd, qinv, LOGN);
-            } else {
+            } else if (PRO == PRO_MODDOWN) {
 #pragma unroll
                 for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(load(tau + S::T * k));
+            } else {
+#pragma unroll
+                for (int k = 0; k < S::E; ++k)
+                    d[k] = d_from_u52(__builtin_nontemporal_load(limb + (long long)(tau + S::T * k) * N2 + col));
             }
             fwd_stages_ds<LM, false, true>(d, tau, 0, 0, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, true);
             fwd_stages_ds<LM, false, false>(d, tau, 0, 0, Wd, qd, qinv);
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) limb[(long long)(S::E * tau + k) * N2 + col] = s51_from_d(d[k]);
+            for (int k = 0; k < S::E; ++k)
+                __builtin_nontemporal_store(s51_from_d(d[k]), limb + (long long)(S::E * tau + k) * N2 + col);
         } else if (!INV) {
 #pragma unroll
             for (int k = 0; k < S::E; ++k) d[k] = (double)load(tau + S::T * k);
@@ -697,7 +702,8 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
             for (int k = 0; k < S::E; ++k) limb[(long long)(S::E * tau + k) * N2 + col] = (u64)d[k];
         } else if (q < (1ull << 42)) {  // lazy inverse: input reduced by the row pass
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(limb[(long long)(S::E * tau + k) * N2 + col]);
+            for (int k = 0; k < S::E; ++k)
+                d[k] = d_from_u52(__builtin_nontemporal_load(limb + (long long)(S::E * tau + k) * N2 + col));
             inv_stages_ds<LM, false, false>(d, tau, 0, 0, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, false);
             inv_stages_ds<LM, false, true>(d, tau, 0, 0, Wd, qd, qinv);
@@ -705,8 +711,8 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
             const double scd = (double)sc;
 #pragma unroll
             for (int k = 0; k < S::E; ++k)
-                limb[(long long)(tau + S::T * k) * N2 + col] = u52_from_d(reduce_d(mulmod_lazy_d(d[k], scd, qd, qinv),
-                                                                                  qd, qinv));
+                __builtin_nontemporal_store(u52_from_d(reduce_d(mulmod_lazy_d(d[k], scd, qd, qinv), qd, qinv)),
+                                            limb + (long long)(tau + S::T * k) * N2 + col);
         } else {
 #pragma unroll
             for (int k = 0; k < S::E; ++k) d[k] = (double)limb[(long long)(S::E * tau + k) * N2 + col];
@@ -1107,21 +1113,25 @@ __global__ __launch_bounds__(256) void tensor_kernel(const u64 *__restrict__ x, 
     }
 }
 
-// The gradient terms of nb blocks summed into one degree-2 ciphertext at level
+// The gradient terms of nb blocks summed into one degree-4 ciphertext at level
 // lp (limbs 0..lp), straight into g (accumulated onto g when acc):
 //   g += sum_b A_b (x) B3_b + M_b (x) Z1_b + k0 Z_b  (+ A_b (x) Z2_b when z2)
-// where (x) is the tensor product (d0, d1, d2) and k0 Z adds to d0, d1.  No
-// block's terms are stored.  Primes below 2^46: lazy FP64 products (at most 7
-// in (-q, 2q) per component and block), one reduction per block; wider
-// primes: Barrett products and modular sums.
+// where (x) is the tensor product of polynomials in the secret: A and B3 are
+// of degree 2 (three components, not relinearised), M, Z1, Z2 and Z of
+// degree 1, and d_k of a product sums the component products of degrees
+// i + j = k.  No block's terms are stored.  Primes below 2^46: lazy FP64
+// products (at most 6 in (-q, 2q) per component and block), one reduction per
+// block; wider primes: Barrett products and modular sums.
 struct TermArgs {
-    const u64 *a, *b3, *z1, *z2;  // level lp, [b][2][lp+1][N]: batch stride ps, component stride pc
+    const u64 *a, *b3;  // level lp, [b][3][lp+1][N]: batch stride as, component stride pc
+    long long as;
+    const u64 *z1, *z2;  // level lp, [b][2][lp+1][N]: batch stride ps, component stride pc
     long long ps, pc;
     const u64 *m;  // M: batch stride ms, component stride mc (first lp+1 limbs read)
     long long ms, mc;
     const u64 *z;  // data: batch stride zs, component stride zc
     long long zs, zc;
-    u64 *g;  // [3][lp+1][N], component stride pc
+    u64 *g;  // [5][lp+1][N], component stride pc
     i64 k0;
     int nb, acc, logN;
 };
@@ -1131,69 +1141,81 @@ __global__ __launch_bounds__(256) void terms_sum_kernel(TermArgs a, const PrimeI
     const int i = blockIdx.y;
     const PrimeInfo p = pinfo[i];
     const long long off = ((long long)i << a.logN) + blockIdx.x * 256 + threadIdx.x;
+    const long long pc = a.pc;
     const u64 mag = a.k0 < 0 ? (u64)(-(a.k0 + 1)) + 1 : (u64)a.k0;
     u64 kq = reduce64(mag, p);
     if (a.k0 < 0) kq = neg_mod(kq, p.q);
     u64 *g = a.g + off;
     if (p.q < (1ull << 46)) {
         const double qd = (double)p.q, qinv = 1.0 / qd, kd = d_from_u52(kq);
-        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-        if (a.acc) {
-            g0 = d_from_u52(g[0]);
-            g1 = d_from_u52(g[a.pc]);
-            g2 = d_from_u52(g[2 * a.pc]);
-        }
+        double gk[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) gk[k] = a.acc ? d_from_u52(g[k * pc]) : 0.0;
+        auto mm = [&](double x, double y) { return mulmod_lazy_d(x, y, qd, qinv); };
         for (int b = 0; b < a.nb; ++b) {
-            const long long pb = b * a.ps + off;
-            const u64 ra0 = a.a[pb], ra1 = a.a[pb + a.pc], rb0 = a.b3[pb], rb1 = a.b3[pb + a.pc];
-            const u64 rz10 = a.z1[pb], rz11 = a.z1[pb + a.pc];
-            const u64 rm0 = a.m[b * a.ms + off], rm1 = a.m[b * a.ms + a.mc + off];
-            const u64 rz0 = a.z[b * a.zs + off], rz1 = a.z[b * a.zs + a.zc + off];
-            const double a0 = d_from_u52(ra0), a1 = d_from_u52(ra1), m0 = d_from_u52(rm0), m1 = d_from_u52(rm1);
-            const double b0 = d_from_u52(rb0), b1 = d_from_u52(rb1), y0 = d_from_u52(rz10), y1 = d_from_u52(rz11);
-            double t0 = mulmod_lazy_d(a0, b0, qd, qinv) + mulmod_lazy_d(m0, y0, qd, qinv) +
-                        mulmod_lazy_d(d_from_u52(rz0), kd, qd, qinv);
-            double t1 = mulmod_lazy_d(a0, b1, qd, qinv) + mulmod_lazy_d(a1, b0, qd, qinv) +
-                        mulmod_lazy_d(m0, y1, qd, qinv) + mulmod_lazy_d(m1, y0, qd, qinv) +
-                        mulmod_lazy_d(d_from_u52(rz1), kd, qd, qinv);
-            double t2 = mulmod_lazy_d(a1, b1, qd, qinv) + mulmod_lazy_d(m1, y1, qd, qinv);
-            if (a.z2) {
-                const double w0 = d_from_u52(a.z2[pb]), w1 = d_from_u52(a.z2[pb + a.pc]);
-                t0 += mulmod_lazy_d(a0, w0, qd, qinv);
-                t1 += mulmod_lazy_d(a0, w1, qd, qinv) + mulmod_lazy_d(a1, w0, qd, qinv);
-                t2 += mulmod_lazy_d(a1, w1, qd, qinv);
+            const long long ab = b * a.as + off, pb = b * a.ps + off;
+            double x[3], y[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                x[k] = d_from_u52(a.a[ab + k * pc]);
+                y[k] = d_from_u52(a.b3[ab + k * pc]);
             }
-            g0 = reduce_d(g0 + t0, qd, qinv);
-            g1 = reduce_d(g1 + t1, qd, qinv);
-            g2 = reduce_d(g2 + t2, qd, qinv);
+            const double m0 = d_from_u52(a.m[b * a.ms + off]), m1 = d_from_u52(a.m[b * a.ms + a.mc + off]);
+            const double u0 = d_from_u52(a.z1[pb]), u1 = d_from_u52(a.z1[pb + pc]);
+            const double z0 = d_from_u52(a.z[b * a.zs + off]), z1 = d_from_u52(a.z[b * a.zs + a.zc + off]);
+            double t0 = mm(x[0], y[0]) + mm(m0, u0) + mm(z0, kd);
+            double t1 = mm(x[0], y[1]) + mm(x[1], y[0]) + mm(m0, u1) + mm(m1, u0) + mm(z1, kd);
+            double t2 = mm(x[0], y[2]) + mm(x[1], y[1]) + mm(x[2], y[0]) + mm(m1, u1);
+            double t3 = mm(x[1], y[2]) + mm(x[2], y[1]);
+            double t4 = mm(x[2], y[2]);
+            if (a.z2) {
+                const double w0 = d_from_u52(a.z2[pb]), w1 = d_from_u52(a.z2[pb + pc]);
+                t0 += mm(x[0], w0);
+                t1 += mm(x[0], w1) + mm(x[1], w0);
+                t2 += mm(x[1], w1) + mm(x[2], w0);
+                t3 += mm(x[2], w1);
+            }
+            gk[0] = reduce_d(gk[0] + t0, qd, qinv);
+            gk[1] = reduce_d(gk[1] + t1, qd, qinv);
+            gk[2] = reduce_d(gk[2] + t2, qd, qinv);
+            gk[3] = reduce_d(gk[3] + t3, qd, qinv);
+            gk[4] = reduce_d(gk[4] + t4, qd, qinv);
         }
-        g[0] = u52_from_d(g0);
-        g[a.pc] = u52_from_d(g1);
-        g[2 * a.pc] = u52_from_d(g2);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) g[k * pc] = u52_from_d(gk[k]);
         return;
     }
-    u64 g0 = a.acc ? g[0] : 0, g1 = a.acc ? g[a.pc] : 0, g2 = a.acc ? g[2 * a.pc] : 0;
+    u64 gk[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) gk[k] = a.acc ? g[k * pc] : 0;
+    auto mm = [&](u64 x, u64 y) { return mul_mod(x, y, p); };
+    auto ad = [&](u64 x, u64 y) { return add_mod(x, y, p.q); };
     for (int b = 0; b < a.nb; ++b) {
-        const long long pb = b * a.ps + off;
-        const u64 a0 = a.a[pb], a1 = a.a[pb + a.pc], b0 = a.b3[pb], b1 = a.b3[pb + a.pc];
-        const u64 y0 = a.z1[pb], y1 = a.z1[pb + a.pc];
+        const long long ab = b * a.as + off, pb = b * a.ps + off;
+        u64 x[3], y[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            x[k] = a.a[ab + k * pc];
+            y[k] = a.b3[ab + k * pc];
+        }
         const u64 m0 = a.m[b * a.ms + off], m1 = a.m[b * a.ms + a.mc + off];
+        const u64 u0 = a.z1[pb], u1 = a.z1[pb + pc];
         const u64 z0 = a.z[b * a.zs + off], z1 = a.z[b * a.zs + a.zc + off];
-        g0 = add_mod(g0, add_mod(add_mod(mul_mod(a0, b0, p), mul_mod(m0, y0, p), p.q), mul_mod(z0, kq, p), p.q), p.q);
-        u64 t1 = add_mod(add_mod(mul_mod(a0, b1, p), mul_mod(a1, b0, p), p.q),
-                         add_mod(mul_mod(m0, y1, p), mul_mod(m1, y0, p), p.q), p.q);
-        g1 = add_mod(g1, add_mod(t1, mul_mod(z1, kq, p), p.q), p.q);
-        g2 = add_mod(g2, add_mod(mul_mod(a1, b1, p), mul_mod(m1, y1, p), p.q), p.q);
+        gk[0] = ad(gk[0], ad(ad(mm(x[0], y[0]), mm(m0, u0)), mm(z0, kq)));
+        gk[1] = ad(gk[1], ad(ad(ad(mm(x[0], y[1]), mm(x[1], y[0])), ad(mm(m0, u1), mm(m1, u0))), mm(z1, kq)));
+        gk[2] = ad(gk[2], ad(ad(mm(x[0], y[2]), mm(x[1], y[1])), ad(mm(x[2], y[0]), mm(m1, u1))));
+        gk[3] = ad(gk[3], ad(mm(x[1], y[2]), mm(x[2], y[1])));
+        gk[4] = ad(gk[4], mm(x[2], y[2]));
         if (a.z2) {
-            const u64 w0 = a.z2[pb], w1 = a.z2[pb + a.pc];
-            g0 = add_mod(g0, mul_mod(a0, w0, p), p.q);
-            g1 = add_mod(g1, add_mod(mul_mod(a0, w1, p), mul_mod(a1, w0, p), p.q), p.q);
-            g2 = add_mod(g2, mul_mod(a1, w1, p), p.q);
+            const u64 w0 = a.z2[pb], w1 = a.z2[pb + pc];
+            gk[0] = ad(gk[0], mm(x[0], w0));
+            gk[1] = ad(gk[1], ad(mm(x[0], w1), mm(x[1], w0)));
+            gk[2] = ad(gk[2], ad(mm(x[1], w1), mm(x[2], w0)));
+            gk[3] = ad(gk[3], mm(x[2], w1));
         }
     }
-    g[0] = g0;
-    g[a.pc] = g1;
-    g[2 * a.pc] = g2;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) g[k * pc] = gk[k];
 }
 
 // Baby-step margin products: o[blk] = sum_{b < nbaby} Zb[blk] (x) Wb[b], one
@@ -2098,11 +2120,11 @@ void tensor_b(he_ctx *c, int level, int B, const u64 *x, long long xb, long long
     tensor_kernel<<<g, 256, 0, c->stream>>>(x, xb, xc, y, yb, yc, o, ob, oc, c->t.pinfo, c->logN);
 }
 
-void terms_sum_b(he_ctx *c, int lp, int nb, const u64 *A, const u64 *B3, const u64 *Z1, const u64 *Z2, long long ps,
-                 long long pc, const u64 *M, long long ms, long long mc, const u64 *Z, long long zs, long long zc,
-                 i64 k0, u64 *G, bool accumulate)
+void terms_sum_b(he_ctx *c, int lp, int nb, const u64 *A, const u64 *B3, long long as, const u64 *Z1, const u64 *Z2,
+                 long long ps, long long pc, const u64 *M, long long ms, long long mc, const u64 *Z, long long zs,
+                 long long zc, i64 k0, u64 *G, bool accumulate)
 {
-    TermArgs a{A, B3, Z1, Z2, ps, pc, M, ms, mc, Z, zs, zc, G, k0, nb, accumulate ? 1 : 0, c->logN};
+    TermArgs a{A, B3, as, Z1, Z2, ps, pc, M, ms, mc, Z, zs, zc, G, k0, nb, accumulate ? 1 : 0, c->logN};
     dim3 g(c->N / 256, lp + 1, 1);
     terms_sum_kernel<<<g, 256, 0, c->stream>>>(a, c->t.pinfo);
 }

@@ -84,6 +84,8 @@ def test_keys_bit_exact(small):
     srns = np.array([[int(v) % q for v in okeys.s] for q in P.q], dtype=np.uint64)
     assert np.array_equal(s, srns)
     assert np.array_equal(gkeys.download(-1).reshape(okeys.rlk.shape), okeys.rlk)
+    for j in (3, 4):  # keys for s^3 and s^4
+        assert np.array_equal(gkeys.download(-j).reshape(okeys.rlk_pow[j].shape), okeys.rlk_pow[j])
     for t in (1, -1, small["c"]):
         g = O.galois(P, t)
         assert np.array_equal(gkeys.download(g).reshape(okeys.rot[g].shape), okeys.rot[g])

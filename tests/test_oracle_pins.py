@@ -357,6 +357,69 @@ def test_keyswitch_decrypts_to_d_times_sprime():
         assert abs(diff) < 2 ** 12
 
 
+def _poly_in_secret(comps, s, Q):
+    """sum_k comps[k] s^k in Z_Q[X]/(X^N + 1), by schoolbook products."""
+    N = len(s)
+    acc, sk = [0] * N, [1] + [0] * (N - 1)
+    for k, ck in enumerate(comps):
+        if k:
+            sk = schoolbook_negacyclic(sk, s, Q)
+        acc = [(a + b) % Q for a, b in zip(acc, schoolbook_negacyclic(ck, sk, Q))]
+    return acc
+
+
+def test_tensor_of_degree_two_ciphertexts_decrypts_to_the_product():
+    # a ciphertext of degree k is a polynomial in s: the tensor must be the
+    # product of the two polynomials, so its value at s is the product of values
+    P = tiny_params(logN=3, nq=3, nk=1, alpha=1, bits=24)
+    N, level = P.N, 2
+    Q = math.prod(P.q[:3])
+    rnd = random.Random(31)
+    s = [rnd.choice((-1, 0, 1)) for _ in range(N)]
+    for nx, ny in ((3, 3), (3, 2), (2, 2)):
+        xs = [[rnd.randrange(Q) for _ in range(N)] for _ in range(nx)]
+        ys = [[rnd.randrange(Q) for _ in range(N)] for _ in range(ny)]
+        d = O.tensor_n(P, level, np.stack([limbs_of_int(x, P.q[:3]) for x in xs]),
+                       np.stack([limbs_of_int(y, P.q[:3]) for y in ys]))
+        assert d.shape[0] == nx + ny - 1
+        got = _poly_in_secret([[crt_py(d[k][:, i], P.q[:3]) % Q for i in range(N)] for k in range(d.shape[0])], s, Q)
+        vx, vy = _poly_in_secret(xs, s, Q), _poly_in_secret(ys, s, Q)
+        assert got == schoolbook_negacyclic(vx, vy, Q)
+
+
+def test_rescale_of_three_components_is_rounded_division():
+    P = tiny_params(logN=4, nq=4, nk=1, alpha=1)
+    N, level = P.N, 3
+    rnd = random.Random(32)
+    Q = math.prod(P.q[:4])
+    xs = [[rnd.randrange(-(Q // 2), Q // 2) for _ in range(N)] for _ in range(3)]
+    out = O.rescale_n(P, level, np.stack([limbs_of_int(x, P.q[:4]) for x in xs]))
+    ql = P.q[level]
+    for c in range(3):
+        for k in range(N):
+            assert crt_py(out[c][:, k], P.q[:3]) == (2 * xs[c][k] + ql) // (2 * ql)
+
+
+def test_relinearisation_of_degree_four_decrypts_to_its_value_at_s():
+    # (d0..d4) -> (d0', d1') with d0' + d1' s = sum_k d_k s^k + small: pins
+    # the keys for s^2, s^3 and s^4 (a wrong power leaves an error of size Q)
+    P = tiny_params(logN=5, nq=4, nk=2, alpha=2, bits=28)
+    keys = O.Keys(P, 22, h=8)
+    N, level = P.N, 3
+    Q = math.prod(P.q[:4])
+    rnd = random.Random(33)
+    s = [int(v) for v in keys.s]
+    for deg in (2, 3, 4):
+        ds = [[rnd.randrange(Q) for _ in range(N)] for _ in range(deg + 1)]
+        ct = O.relin_n(P, np.stack([limbs_of_int(x, P.q[:4]) for x in ds]), 1.0, level, keys)
+        got = O.crt_centered(O.decrypt_residues(P, keys, ct), P.q[:4])
+        want = _poly_in_secret(ds, s, Q)
+        for k in range(N):
+            diff = (got[k] - want[k]) % Q
+            diff = diff - Q if diff > Q // 2 else diff
+            assert abs(diff) < (deg - 1) * 2 ** 12
+
+
 # ------------------------------------------------------------ encode / decode
 def test_encode_constant_is_exact():
     N = 1 << 13
