@@ -102,7 +102,10 @@ he_status ks_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d2, long long 
         // digits to coefficient form, scaled by N^{-1} [qhat_i^{-1}]_{q_i} (read from d2)
         hek::intt_from(c, d2, d2s, y, ys, B, l, up_post);
         // ModUp conversion (its own kernel: fused into the first forward pass it
-        // measured no faster), then the forward NTT of the extended digits
+        // measured no faster, also with each digit's targets grouped on one XCD
+        // so that the sources are read from L2 -- that pass then waits on the
+        // conversion's loads and arithmetic), then the forward NTT of the
+        // extended digits
         hek::modup_b(c, l, B, y, ys, ext, es, ds);
         // forward NTT of the extended digits with the key inner product fused into its row pass
         hek::ks_ntt_inner(c, l, B, d2, d2s, ext, es, ds, key, keys, acc, as);
