@@ -276,6 +276,11 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  * for all blocks, sums the n_baby products per block without relinearising,
  * and relinearises and rescales once: per block log2(c / n_baby) rotations
  * instead of log2 c.  keys then also hold the rotations j u (j < n_baby).
+ * Feature-major with 1 < n_baby < c and c / n_baby <= 16, the giant steps
+ * g n_baby r (0 < g < c / n_baby; they form a group of rotations, c r = N/2)
+ * are taken as one hoisted sum, x + sum_g Rot(x, g n_baby r): one ModUp of
+ * x's a-part, every rotation's inner product summed in Q u P, one ModDown;
+ * keys then hold every g n_baby r instead of the powers of two from n_baby r.
  * Outputs (caller memory, W's level - 4): W_out, and G_out (nullable) = g.
  * mode 0: plain form (one he_* operation per block per step, one kernel
  * sequence each); mode 1: batched form (every block in one launch per

@@ -58,6 +58,7 @@ def lib():
         "orc_moddown": (None, [P, c_int, u64p, u64p]),
         "orc_ndigits": (c_int, [P, c_int]),
         "orc_keyswitch": (None, [P, c_int, u64p, u64p, u64p]),
+        "orc_keyswitch_sum": (None, [P, c_int, c_int, u64p, u64p, u64p]),
         "orc_rescale": (None, [P, c_int, u64p, u64p]),
         "orc_rescale_n": (None, [P, c_int, c_int, u64p, u64p]),
         "orc_tensor_n": (None, [P, c_int, c_int, u64p, c_int, u64p, u64p]),
@@ -366,6 +367,16 @@ def keyswitch(P, level, d, evk):
     return out
 
 
+def keyswitch_sum(P, level, ds, evks):
+    """sum_m KS(d_m, evk_m) with the inner products summed before one ModDown."""
+    assert len(ds) == len(evks) >= 1
+    d = np.ascontiguousarray(np.stack(ds), dtype=np.uint64)
+    k = np.ascontiguousarray(np.stack(evks), dtype=np.uint64)
+    out = np.zeros((2, level + 1, P.N), dtype=np.uint64)
+    lib().orc_keyswitch_sum(P.cp, level, len(ds), _u(d), _u(k), _u(out))
+    return out
+
+
 def relin(P, d, scale, level, keys):
     ks = keyswitch(P, level, d[2], keys.rlk)
     out = np.zeros((2, level + 1, P.N), dtype=np.uint64)
@@ -435,6 +446,32 @@ def rescale(P, x, scale=None):
     out = np.zeros((2, l, P.N), dtype=np.uint64)
     lib().orc_rescale(P.cp, l, _u(np.ascontiguousarray(x.data)), _u(out))
     return CT(out, l - 1, x.scale / float(P.q[l]) if scale is None else scale)
+
+
+def rotate_sum_hoisted(P, x, steps, keys):
+    """x + sum_{t in steps} Rot(x, t) as one key switch: each rotation's
+    automorphed a-part is switched back to s by its own key, the inner
+    products are summed in Q_l u P and divided by P once; the b-parts are
+    automorphed and added directly."""
+    n = x.level + 1
+    idx = list(range(n))
+    b = np.ascontiguousarray(x.data[0])
+    a_parts, evks = [], []
+    for t in steps:
+        g = galois(P, t)
+        if g not in keys.rot:
+            raise KeyError("no rotation key for step %d" % t)
+        o = np.zeros((n, P.N), dtype=np.uint64)
+        lib().orc_add(P.cp, n, _u(b), _u(automorph_limbs(P, x.data[0], idx, g)), _u(o))
+        b = o
+        a_parts.append(automorph_limbs(P, x.data[1], idx, g))
+        evks.append(keys.rot[g])
+    ks = keyswitch_sum(P, x.level, a_parts, evks)
+    o0 = np.zeros((n, P.N), dtype=np.uint64)
+    o1 = np.zeros((n, P.N), dtype=np.uint64)
+    lib().orc_add(P.cp, n, _u(b), _u(ks[0]), _u(o0))
+    lib().orc_add(P.cp, n, _u(np.ascontiguousarray(x.data[1])), _u(ks[1]), _u(o1))
+    return CT(np.stack([o0, o1]), x.level, x.scale)
 
 
 def rotate(P, x, t, keys):

@@ -514,6 +514,49 @@ void orc_keyswitch(const orc_params *P, int level, const u64 *d, const u64 *evk,
     free(acc);
 }
 
+/*
+ * Sum of n key switches with one ModDown: the inner products of the ModUp of
+ * each d_m with its key evk_m are summed in Q_l u P, then the sum is divided
+ * by P once.  d: n x [l+1][N] (coefficient form); evk: n x [beta][2][nq+nk][N].
+ * For n = 1 this is orc_keyswitch.
+ */
+void orc_keyswitch_sum(const orc_params *P, int level, int n, const u64 *d, const u64 *evk, u64 *out)
+{
+    u64 N = (u64)1 << P->logN;
+    int nb = level + 1 + P->nk;
+    int nfull = P->nq + P->nk;
+    int beta = orc_ndigits(P, level);
+    size_t ext_sz = (size_t)nb * N;
+    size_t key_sz = (size_t)orc_ndigits(P, P->nq - 1) * 2 * nfull * N;
+    u64 *ext = (u64 *)malloc(ext_sz * 8);
+    u64 *acc = (u64 *)calloc(2 * ext_sz, 8);
+    for (int m = 0; m < n; m++) {
+        const u64 *dm = d + (size_t)m * (level + 1) * N;
+        const u64 *km = evk + (size_t)m * key_sz;
+        for (int j = 0; j < beta; j++) {
+            orc_modup(P, level, j, dm, ext);
+            for (int comp = 0; comp < 2; comp++) {
+                const u64 *key = km + ((size_t)j * 2 + comp) * nfull * N;
+                u64 *a = acc + comp * ext_sz;
+#pragma omp parallel for schedule(dynamic)
+                for (int t = 0; t < nb; t++) {
+                    u64 psi;
+                    u64 qt = basis_prime(P, level, t, &psi);
+                    int kpos = t <= level ? t : P->nq + (t - level - 1);
+                    u64 *prod = (u64 *)malloc(N * 8);
+                    orc_polymul(LIMB(ext, t), LIMB(key, kpos), prod, P->logN, qt, psi);
+                    for (u64 x = 0; x < N; x++) LIMB(a, t)[x] = addmod(LIMB(a, t)[x], prod[x], qt);
+                    free(prod);
+                }
+            }
+        }
+    }
+    orc_moddown(P, level, acc, out);
+    orc_moddown(P, level, acc + ext_sz, out + (size_t)(level + 1) * N);
+    free(ext);
+    free(acc);
+}
+
 /* rescale of ncomp components: [ncomp][l+1][N] -> [ncomp][l][N];
  * c_i <- (c_i - [c_l]_centered) * q_l^{-1} mod q_i, each component on its own */
 void orc_rescale_n(const orc_params *P, int level, int ncomp, const u64 *ct, u64 *out)

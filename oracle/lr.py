@@ -30,7 +30,10 @@ Readings where the paper is silent (each listed in the design notes):
     products Rot(Z, b u) (x) Rot(W, b u) as one degree-2 ciphertext (a
     rotation is a ring automorphism, so that is the sum of Rot(Z (x) W, b u)),
     relinearises and rescales it once, and finishes with the giant-step
-    rotations n_b u .. (c/2) u.
+    rotations n_b u .. (c/2) u.  Feature-major, the c/n_b giant steps g n_b r
+    form a group of rotations (c r = N/2): for c/n_b <= 16 their sum
+    x + sum_g Rot(x, g n_b r) is taken as one key switch, the rotations'
+    inner products summed in Q u P before one ModDown (rotate_sum_hoisted).
   * the products C = A B3, B1 = M Z1 and B2 = A Z2 feed only additions, so
     they are formed at one level with one scale sC q (Z1's scale chosen for
     it), left unrelinearised and unrescaled, summed with the a0 term and across
@@ -268,13 +271,27 @@ def _plan_features(q, level, s_Z, s_W, coef, eta_over_n, w_decay):
                 level_out=level - 4, s_gsum=s_gsum, layout=FEATURES)
 
 
+GIANT_MAX = 16  # most giant steps (c / n_baby) a hoisted feature-major giant sum takes
+
+
+def giant_hoisted(c, layout, n_baby):
+    """Feature-major margins with baby steps take their giant steps as one
+    hoisted sum: the rotations by g n_baby r (g < c / n_baby) are a group
+    (c r = N/2), so their sum is x + sum_g Rot(x, g n_baby r), one key switch
+    with every rotation's inner product summed before one ModDown."""
+    return layout == FEATURES and 1 < n_baby < c and c // n_baby <= GIANT_MAX
+
+
 def rotation_steps(c, r, layout=ROWS, n_baby=1):
     """Rotation steps used by the step.  Row-major: +-2^k (k < log2 c) and
     c*2^k (k < log2 r).  Feature-major: r*2^k (k < log2 c) and +-2^k
     (k < log2 r).  With n_baby > 1 baby steps also b*u for b < n_baby (u = r
-    feature-major, 1 row-major)."""
+    feature-major, 1 row-major), and for a hoisted giant sum the steps
+    g n_baby r, g < c / n_baby."""
     if layout == FEATURES:
         st = [b * r for b in range(3, n_baby) if b & (b - 1)]
+        if giant_hoisted(c, layout, n_baby):
+            st += [g * n_baby * r for g in range(3, c // n_baby) if g & (g - 1)]
         t = 1
         while t < c:
             st.append(t * r)
@@ -397,6 +414,9 @@ def _step_features(P, keys, Z, W, mask_m, c, r, pl, Zrot=None, n_baby=1):
         else:
             u = O.rescale(P, O.mul(P, O.drop(zb, l), W, keys), scale=pl["s1"])
             t = 1
+        if giant_hoisted(c, FEATURES, n_baby):  # margins: the giant steps as one key switch
+            u = O.rotate_sum_hoisted(P, u, [g * n_baby * r for g in range(1, c // n_baby)], keys)
+            t = c
         while t < c:  # margins: cyclic sum over the feature blocks
             u = O.add(P, u, O.rotate(P, u, t * r, keys))
             t *= 2

@@ -220,6 +220,55 @@ he_status rotate_multi_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, 
     return st;
 }
 
+// x + sum_g Rot(x, g) for B ciphertexts at level l (in, batch stride is) as
+// one key switch: the a-part's ModUp once, every rotation's inner product
+// (automorphism applied to the extended digits, which commutes with ModUp)
+// summed in Q_l u P, one ModDown; the b-parts are automorphed and added
+// directly.  out [B][2][l+1][N] (batch stride os) must not overlap in.
+he_status rotate_sum_hoisted_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long long is,
+                                   const hek::EntryGal &gals, const hek::EntryKeys &keys, int ng, u64 *out,
+                                   long long os)
+{
+    const size_t N = c->N;
+    const int nb = l + 1 + c->nk, beta = beta_at(c, l);
+    const size_t mark = ar.off;
+    u64 *y = ar.take((size_t)B * (l + 1) * N);
+    u64 *ext = ar.take((size_t)B * beta * nb * N);
+    u64 *acc = ar.take((size_t)B * 2 * nb * N);
+    u64 *conv = ar.take((size_t)B * 2 * (l + 1) * N);
+    if (!y || !ext || !acc || !conv) return HE_ENOMEM;
+    const long long lc = (long long)(l + 1) * N, ds = (long long)nb * N, es = (long long)beta * ds;
+    const long long as = 2LL * nb * N, cs = 2LL * (l + 1) * N;
+    const u64 *up_post = c->t.up_scale + (size_t)l * c->nq * 2;
+    if (hek::fused_ok(c)) {
+        hek::intt_from(c, in + lc, is, y, lc, B, l, up_post);
+    } else {
+        hek::ewise(c, 4, l, B, 1, in + lc, is, 0, nullptr, 0, 0, y, lc, 0, 0);
+        hek::ntt_batch(c, y, lc, 0, B, 1, 0, l + 1, l, -1, up_post, false);
+    }
+    hek::modup_b(c, l, B, y, lc, ext, es, ds);
+    hek::ntt_batch(c, ext, es, ds, B, beta, 0, nb, l, +1, nullptr, true);
+    hek::giant_sum_b(c, l, B, ext, es, ds, in, is, lc, gals, keys, ng, acc, as, out, os);
+    hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
+    if (hek::fused_ok(c)) {
+        hek::ntt_moddown(c, l, B, acc, as, conv, cs, out, os, lc, 2, out, os, lc);
+    } else {
+        hek::moddown_conv_b(c, l, B, acc, as, conv, cs);
+        hek::ntt_batch(c, conv, cs, lc, B, 2, 0, l + 1, l, +1, nullptr, false);
+        hek::moddown_finish_b(c, l, B, acc, as, conv, cs, out, os, lc, 2, out, os, lc);
+    }
+    ar.off = mark;
+    return last_error();
+}
+
+// feature-major giant steps taken as one hoisted sum (the rotations by
+// g n_baby rows, g < cols / n_baby, form a group: cols rows = N/2)
+constexpr int HE_GIANT_MAX = 16;
+bool giant_hoisted(int layout, int cols, int n_baby)
+{
+    return layout == HE_LAYOUT_FEATURES && n_baby > 1 && n_baby < cols && cols / n_baby <= HE_GIANT_MAX;
+}
+
 u64 galois_of(const he_ctx *c, long long steps)
 {
     const long long S = c->N / 2;
@@ -637,22 +686,37 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
         // D1: u = RS(relin(Z (x) W)), level l-1
         TRY(mul_relin_rescale(c, ar, s, l, nb, zp, zbs, zc, W->data, 0, wc, keys->rlk, s.U));
     }
-    for (int t = t0; t < cols; t <<= 1) {
-        const u64 gal = galois_of(c, (long long)t * rows);
-        const u64 *key = find_rot_key(keys, gal);
-        if (!key) return HE_EKEY;
-        TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, gal, key, s.U, 2 * u1, s.U));  // U += Rot(U)
+    u64 *M = s.U;
+    if (giant_hoisted(HE_LAYOUT_FEATURES, cols, bd.n_baby)) {
+        // the giant steps g n_baby rows (0 < g < cols / n_baby) as one key switch: M = U + sum_g Rot(U)
+        hek::EntryGal eg;
+        hek::EntryKeys ek;
+        const int ng = cols / bd.n_baby - 1;
+        for (int g = 1; g <= ng; ++g) {
+            eg.g[g - 1] = galois_of(c, (long long)g * bd.n_baby * rows);
+            ek.k[g - 1] = find_rot_key(keys, eg.g[g - 1]);
+            if (!ek.k[g - 1]) return HE_EKEY;
+        }
+        TRY(rotate_sum_hoisted_apply(c, ar, l - 1, nb, s.U, 2 * u1, eg, ek, ng, s.R, 2 * u1));
+        M = s.R;
+    } else {
+        for (int t = t0; t < cols; t <<= 1) {
+            const u64 gal = galois_of(c, (long long)t * rows);
+            const u64 *key = find_rot_key(keys, gal);
+            if (!key) return HE_EKEY;
+            TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, gal, key, s.U, 2 * u1, s.U));  // U += Rot(U)
+        }
     }
-    // M = u.  A = RS(M^2) ; Z3 = RS(k3 Z), B3 = RS(M Z3), degree 2 ; Z1 = RS(k1 Z)   (level l-2)
-    TRY(mul_rescale3(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.U, 2 * u1, u1, s.A));
+    // A = RS(M^2) ; Z3 = RS(k3 Z), B3 = RS(M Z3), degree 2 ; Z1 = RS(k1 Z)   (level l-2)
+    TRY(mul_rescale3(c, ar, s, l - 1, nb, M, 2 * u1, u1, M, 2 * u1, u1, s.A));
     TRY(rescale_apply(c, ar, l, nb, zp, zbs, s.Z3, 2 * u1, 2, &pl.k3, zc));
-    TRY(mul_rescale3(c, ar, s, l - 1, nb, s.U, 2 * u1, u1, s.Z3, 2 * u1, u1, s.B3));
+    TRY(mul_rescale3(c, ar, s, l - 1, nb, M, 2 * u1, u1, s.Z3, 2 * u1, u1, s.B3));
     // Z1 = RS(k1 Z) and, for a2 != 0, Z2 = RS(k2 Z), both at level l-2
     const long long a1 = (long long)(l - 1) * N;
     TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z1, 2 * a1, 2, &pl.k1, zc));
     if (pl.k2 != 0) TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z2, 2 * a1, 2, &pl.k2, zc));
     // the block's terms at level l-2 (unrescaled, degree 4); G5 (+)= their sum
-    hek::terms_sum_b(c, l - 2, nb, s.A, s.B3, 3 * a1, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, s.U, 2 * u1, u1,
+    hek::terms_sum_b(c, l - 2, nb, s.A, s.B3, 3 * a1, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, M, 2 * u1, u1,
                      zp, zbs, zc, pl.k0, s.G5, accumulate);
     return last_error();
 }
@@ -1371,8 +1435,13 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
     const long long mu = fm ? rows : 1;
     for (int j = 1; j < n_baby; ++j)
         if (!find_rot_key(k, galois_of(c, (long long)j * mu))) return HE_EKEY;
-    for (int t = n_baby; t < cols; t <<= 1)
-        if (!find_rot_key(k, galois_of(c, (long long)t * mu))) return HE_EKEY;
+    if (giant_hoisted(layout, cols, n_baby)) {
+        for (int g = 1; g < cols / n_baby; ++g)
+            if (!find_rot_key(k, galois_of(c, (long long)g * n_baby * mu))) return HE_EKEY;
+    } else {
+        for (int t = n_baby; t < cols; t <<= 1)
+            if (!find_rot_key(k, galois_of(c, (long long)t * mu))) return HE_EKEY;
+    }
     for (int t = 1; t < st; t <<= 1)
         if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
     const int chunk = mode == 0 ? 1 : n_blocks;

@@ -154,6 +154,14 @@ struct EntryKeys {
 struct EntryGal {
     u64 g[HE_MAXMULTI];
 };
+// hoisted rotation sum, inner products: acc [B][2][l+1+nk][N] = sum_g sum_j
+// sigma_g(D_j) key_g[j] from ext [B][beta][l+1+nk][N] (NTT form; digit
+// positions from x's a-part), and the ModDown base out [B][2][l+1][N] =
+// (x0 + sum_g sigma_g(x0), x1); x, out: batch strides xs / os, component
+// stride xc.  ng <= HE_MAXMULTI Galois elements and keys.
+void giant_sum_b(he_ctx *c, int level, int B, const u64 *ext, long long es, long long ds, const u64 *x, long long xs,
+                 long long xc, const EntryGal &gals, const EntryKeys &keys, int ng, u64 *acc, long long as, u64 *out,
+                 long long os);
 void ks_inner_multi_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const u64 *ext, long long es,
                       long long ds, const EntryKeys &keys, u64 *acc, long long as);
 void automorph_multi_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,

@@ -1634,6 +1634,150 @@ __global__ __launch_bounds__(256) void automorph_kernel(const u64 *__restrict__ 
     }
 }
 
+// Hoisted sum of rotations, the inner-product step: for every entry b,
+// position t of Q_l u P and coefficient k (NTT order),
+//   acc[b][comp][t][k] = sum_{g < ng} sum_{j < beta} D_j[t][s_g(k)] key_g[j][comp][t][k]
+// where D_j is digit j's ModUp in NTT form (ext, or the input's own a-part on
+// the digit's positions) and s_g the index map of the automorphism X -> X^g
+// (sigma_g(a) at k = a at s_g(k); the automorphism commutes with ModUp).  For
+// t <= l it also writes out[b][0][t][k] = x0[k] + sum_g x0[s_g(k)] and
+// out[b][1][t][k] = x1[k], the base of the one ModDown that follows.  When the
+// Galois elements form a group of order ng + 1 <= 16 whose elements are 1 mod
+// 2^m, s_g(k) stays inside k's aligned run of 2N / 2^m coefficients: the
+// gathers stay within a few cache lines.  Each thread serves up to GIANT_EPT
+// entries, so each key value is loaded once for all of them; the entry groups
+// of one (t, k-tile) are dealt to one XCD, so the keys are fetched into one L2.
+constexpr int GIANT_EPT = 4;
+struct GiantArgs {
+    const u64 *ext;  // [b][beta][nb][N]
+    long long es, ds;
+    const u64 *x;  // input [b][2][l+1][N]: batch stride xs, component stride xc
+    long long xs, xc;
+    hek::EntryKeys keys;  // key_g [beta][2][np][N]
+    hek::EntryGal gals;
+    int ng;
+    u64 *acc;  // [b][2][nb][N]
+    long long as;
+    u64 *out;  // [b][2][l+1][N]: batch stride os, component stride xc
+    long long os;
+    int alpha, beta, ell, nq, np, nb, nent, ngroups, logN;
+};
+
+__global__ __launch_bounds__(256) void giant_sum_kernel(GiantArgs a, const PrimeInfo *__restrict__ pinfo)
+{
+    const int ntile = (1 << a.logN) / 256;
+    const int npair = ntile * a.nb;
+    const int w = blockIdx.x;
+    int grp, pr;
+    if ((npair & 7) == 0) {
+        const int sidx = w >> 3;
+        grp = sidx % a.ngroups;
+        pr = (sidx / a.ngroups) * 8 + (w & 7);
+    } else {
+        grp = w % a.ngroups;
+        pr = w / a.ngroups;
+    }
+    const int t = pr / ntile;
+    const int k = (pr % ntile) * 256 + threadIdx.x;
+    const int b0 = grp * GIANT_EPT;
+    const int ne = min(GIANT_EPT, a.nent - b0);
+    const int tp = prime_of(t, a.ell, a.nq);
+    const PrimeInfo p = pinfo[tp];
+    const long long N = 1ll << a.logN;
+    const u64 mask2n = 2 * (u64)N - 1;
+    const u64 e = 2 * (u64)brev_n((unsigned)k, a.logN) + 1;
+    const long long keylimb = ((long long)tp << a.logN) + k;
+    const long long np_n = (long long)a.np << a.logN;
+    const long long toff = (long long)t << a.logN;
+    // the digit holding position t (inside Q_l), whose D_j[t] is the input's a-part
+    const int jt = t <= a.ell ? t / a.alpha : -1;
+    if (p.q < (1ull << 46)) {
+        const double qd = (double)p.q, qinv = 1.0 / qd;
+        double s0[GIANT_EPT], s1[GIANT_EPT];
+#pragma unroll
+        for (int i = 0; i < GIANT_EPT; ++i) s0[i] = s1[i] = 0.0;
+        for (int g = 0; g < a.ng; ++g) {
+            const u64 e2 = (e * a.gals.g[g]) & mask2n;
+            const long long k2 = brev_n((unsigned)((e2 - 1) >> 1), a.logN);
+            const u64 *key = a.keys.k[g] + keylimb;
+            double p0[GIANT_EPT], p1[GIANT_EPT];
+#pragma unroll
+            for (int i = 0; i < GIANT_EPT; ++i) p0[i] = p1[i] = 0.0;
+            for (int j = 0; j < a.beta; ++j) {
+                const double k0 = d_from_u52(key[(2 * j) * np_n]), k1 = d_from_u52(key[(2 * j + 1) * np_n]);
+#pragma unroll
+                for (int i = 0; i < GIANT_EPT; ++i) {
+                    if (i < ne) {
+                        const int b = b0 + i;
+                        const u64 v = j == jt ? a.x[b * a.xs + a.xc + toff + k2]
+                                              : a.ext[b * a.es + j * a.ds + toff + k2];
+                        const double dv = d_from_u52(v);
+                        p0[i] += mulmod_lazy_d(dv, k0, qd, qinv);
+                        p1[i] += mulmod_lazy_d(dv, k1, qd, qinv);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < GIANT_EPT; ++i) {
+                s0[i] = reduce_d(s0[i] + p0[i], qd, qinv);
+                s1[i] = reduce_d(s1[i] + p1[i], qd, qinv);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < GIANT_EPT; ++i) {
+            if (i < ne) {
+                u64 *o = a.acc + (b0 + i) * a.as + toff + k;
+                o[0] = u52_from_d(s0[i]);
+                o[(long long)a.nb << a.logN] = u52_from_d(s1[i]);
+            }
+        }
+    } else {
+        u64 s0[GIANT_EPT], s1[GIANT_EPT];
+#pragma unroll
+        for (int i = 0; i < GIANT_EPT; ++i) s0[i] = s1[i] = 0;
+        for (int g = 0; g < a.ng; ++g) {
+            const u64 e2 = (e * a.gals.g[g]) & mask2n;
+            const long long k2 = brev_n((unsigned)((e2 - 1) >> 1), a.logN);
+            const u64 *key = a.keys.k[g] + keylimb;
+            for (int j = 0; j < a.beta; ++j) {
+                const u64 k0 = key[(2 * j) * np_n], k1 = key[(2 * j + 1) * np_n];
+#pragma unroll
+                for (int i = 0; i < GIANT_EPT; ++i) {
+                    if (i < ne) {
+                        const int b = b0 + i;
+                        const u64 v = j == jt ? a.x[b * a.xs + a.xc + toff + k2]
+                                              : a.ext[b * a.es + j * a.ds + toff + k2];
+                        s0[i] = add_mod(s0[i], mul_mod(v, k0, p), p.q);
+                        s1[i] = add_mod(s1[i], mul_mod(v, k1, p), p.q);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < GIANT_EPT; ++i) {
+            if (i < ne) {
+                u64 *o = a.acc + (b0 + i) * a.as + toff + k;
+                o[0] = s0[i];
+                o[(long long)a.nb << a.logN] = s1[i];
+            }
+        }
+    }
+    if (t > a.ell) return;
+    // the base: b-parts automorphed and summed, the a-part copied
+    for (int i = 0; i < ne; ++i) {
+        const int b = b0 + i;
+        const u64 *x0 = a.x + b * a.xs + toff;
+        u64 v = x0[k];
+        for (int g = 0; g < a.ng; ++g) {
+            const u64 e2 = (e * a.gals.g[g]) & mask2n;
+            v = add_mod(v, x0[brev_n((unsigned)((e2 - 1) >> 1), a.logN)], p.q);
+        }
+        u64 *o = a.out + b * a.os + toff + k;
+        o[0] = v;
+        o[a.xc] = x0[a.xc + k];
+    }
+}
+
 // automorph_kernel with a Galois element per entry b (blockIdx.z = 2 b + c)
 __global__ __launch_bounds__(256) void automorph_multi_kernel(const u64 *__restrict__ in, long long ib, long long ic,
                                                               u64 *__restrict__ out, long long ob, long long oc,
@@ -2219,6 +2363,37 @@ void automorph_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long lon
 {
     dim3 gr(xblocks(c->N), nl, B * 2);
     automorph_kernel<<<gr, 256, 0, c->stream>>>(in, ib, ic, out, ob, oc, g, c->logN);
+}
+
+void giant_sum_b(he_ctx *c, int level, int B, const u64 *ext, long long es, long long ds, const u64 *x, long long xs,
+                 long long xc, const EntryGal &gals, const EntryKeys &keys, int ng, u64 *acc, long long as, u64 *out,
+                 long long os)
+{
+    GiantArgs a{};
+    a.ext = ext;
+    a.es = es;
+    a.ds = ds;
+    a.x = x;
+    a.xs = xs;
+    a.xc = xc;
+    a.keys = keys;
+    a.gals = gals;
+    a.ng = ng;
+    a.acc = acc;
+    a.as = as;
+    a.out = out;
+    a.os = os;
+    a.alpha = c->alpha;
+    a.beta = (level + 1 + c->alpha - 1) / c->alpha;
+    a.ell = level;
+    a.nq = c->nq;
+    a.np = c->np;
+    a.nb = level + 1 + c->nk;
+    a.nent = B;
+    a.ngroups = (B + GIANT_EPT - 1) / GIANT_EPT;
+    a.logN = c->logN;
+    const long long nwg = (long long)a.ngroups * (c->N / 256) * a.nb;
+    giant_sum_kernel<<<dim3((unsigned)nwg, 1, 1), 256, 0, c->stream>>>(a, c->t.pinfo);
 }
 
 void automorph_multi_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,

@@ -509,12 +509,24 @@ def ct_array(cts):
     return (he_ct * len(cts))(*[c.struct() for c in cts])
 
 
+GIANT_MAX = 16  # most giant steps a hoisted feature-major giant sum takes
+
+
+def giant_hoisted(layout, c, n_baby):
+    """Feature-major margins with 1 < n_baby < c and c / n_baby <= GIANT_MAX
+    take their giant steps g n_baby r as one hoisted sum."""
+    return layout == LAYOUT_FEATURES and 1 < n_baby < c and c // n_baby <= GIANT_MAX
+
+
 def rotation_steps(c, r, layout=LAYOUT_ROWS, n_baby=1):
     """Rotation keys the step needs (with n_baby baby steps also j u, j < n_baby,
-    u = baby_unit(layout, r))."""
+    u = baby_unit(layout, r); with a hoisted giant sum also g n_baby r,
+    g < c / n_baby)."""
     pm, st, unit = (r, c, r) if layout == LAYOUT_FEATURES else (c, r, c)
     mu = baby_unit(layout, r)
     out = [j * mu for j in range(3, n_baby) if j & (j - 1)]
+    if giant_hoisted(layout, c, n_baby):
+        out += [g * n_baby * r for g in range(3, c // n_baby) if g & (g - 1)]
     t = 1
     while t < pm:
         out += [t, -t]

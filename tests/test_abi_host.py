@@ -128,5 +128,7 @@ def test_packing_matches_oracle_layout():
     assert np.array_equal(H.step_mask(4096, 16, H.LAYOUT_FEATURES), LR.feature_mask(4096, 256))
     assert np.array_equal(H.step_mask(4096, 16), LR.column_mask(4096, 16))
     for lay in (LR.ROWS, LR.FEATURES):
-        assert sorted(H.rotation_steps(16, 256, lay)) == sorted(LR.rotation_steps(16, 256, lay))
+        for nb in (1, 2, 4, 8, 16):
+            assert sorted(H.rotation_steps(16, 256, lay, nb)) == sorted(LR.rotation_steps(16, 256, lay, nb))
+            assert sorted(H.rotation_steps(256, 128, lay, nb)) == sorted(LR.rotation_steps(256, 128, lay, nb))
         assert np.array_equal(H.unpack_weights(H.pack_weights(w, 4096, 16, lay), 16, 11, lay), w)

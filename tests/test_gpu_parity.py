@@ -327,7 +327,10 @@ def small40():
     P = O.Params(*cfg)
     ctx = _H().Context(*cfg)
     c, r = 16, P.S // 16
-    steps = sorted(set(LR.rotation_steps(c, r)) | set(LR.rotation_steps(c, r, LR.FEATURES, 16)))
+    steps = set(LR.rotation_steps(c, r))
+    for nb in (2, 4, 16):  # the baby-step counts the tests take (2 and 4: hoisted giant sums)
+        steps |= set(LR.rotation_steps(c, r, LR.FEATURES, nb))
+    steps = sorted(steps)
     return dict(W=W, P=P, ctx=ctx, okeys=O.Keys(P, W["seed_keys"], rot_steps=steps),
                 gkeys=ctx.keygen(W["seed_keys"], steps), H=_H())
 

@@ -420,6 +420,56 @@ def test_relinearisation_of_degree_four_decrypts_to_its_value_at_s():
             assert abs(diff) < (deg - 1) * 2 ** 12
 
 
+def test_keyswitch_sum_decrypts_to_the_sum_of_products():
+    # sum_m KS(d_m, evk_m) with one ModDown: decrypts to sum_m d_m s'_m + small
+    P = tiny_params(logN=5, nq=4, nk=2, alpha=2, bits=28)
+    keys = O.Keys(P, 23, rot_steps=[1, 3], h=8)
+    N, level = P.N, 3
+    Q = math.prod(P.q[:4])
+    rnd = random.Random(34)
+    s = [int(v) for v in keys.s]
+    ds = [[rnd.randrange(Q) for _ in range(N)] for _ in range(3)]
+    evks = [keys.rlk, keys.rot[O.galois(P, 1)], keys.rot[O.galois(P, 3)]]
+    ks = O.keyswitch_sum(P, level, [limbs_of_int(x, P.q[:4]) for x in ds], evks)
+    got = O.crt_centered(O.decrypt_residues(P, keys, O.CT(ks, level, 1.0)), P.q[:4])
+    s2 = schoolbook_negacyclic(s, s, Q)
+    want = [0] * N
+    for dm, sp in zip(ds, [s2, _subst(s, O.galois(P, 1), Q), _subst(s, O.galois(P, 3), Q)]):
+        want = [(a + b) % Q for a, b in zip(want, schoolbook_negacyclic(dm, sp, Q))]
+    for k in range(N):
+        diff = (got[k] - want[k]) % Q
+        diff = diff - Q if diff > Q // 2 else diff
+        assert abs(diff) < 2 ** 12
+
+
+def _subst(a, g, Q):
+    """a(X^g) mod X^N + 1 (brute force)."""
+    N = len(a)
+    out = [0] * N
+    for i, v in enumerate(a):
+        e = (i * g) % (2 * N)
+        if e < N:
+            out[e] = (out[e] + v) % Q
+        else:
+            out[e - N] = (out[e - N] - v) % Q
+    return out
+
+
+def test_hoisted_rotation_sum():
+    P = O.Params(13, 5, 1, 1, 30)
+    steps = [512, 1024, 1536]  # three of the rotations by multiples of S / 8
+    keys = O.Keys(P, 2001, rot_steps=steps)
+    a = np.random.default_rng(5).uniform(-1, 1, P.S)
+    ct = O.encrypt_sk(P, keys, O.encode(a, P.delta, P.N), P.L, P.delta, 3001, 0)
+    # one step: exactly the rotate-and-add (one key switch, one ModDown)
+    one = O.rotate_sum_hoisted(P, ct, [512], keys)
+    assert np.array_equal(one.data, O.add(P, ct, O.rotate(P, ct, 512, keys)).data)
+    # several: the slot sum of the rotations
+    got = O.decrypt(P, keys, O.rotate_sum_hoisted(P, ct, steps, keys)).real
+    want = a + sum(np.roll(a, -t) for t in steps)
+    assert np.max(np.abs(got - want)) < 2.0 ** -14
+
+
 # ------------------------------------------------------------ encode / decode
 def test_encode_constant_is_exact():
     N = 1 << 13
@@ -618,9 +668,14 @@ def test_feature_major_packing_is_the_transpose():
     st = LR.rotation_steps(c, r, LR.FEATURES)
     assert st[:4] == [256, 512, 1024, 2048] and sorted(st[4:]) == sorted([t * s for t in (1, 2, 4, 8, 16, 32, 64, 128)
                                                                           for s in (1, -1)])
-    # baby steps b r for every b < n_baby, giant steps n_baby r .. (c/2) r
+    # baby steps b r for every b < n_baby, giant steps g n_baby r for every g < c / n_baby (hoisted)
     st8 = LR.rotation_steps(c, r, LR.FEATURES, 8)
     assert {b * r for b in range(1, 8)} <= set(st8) and 8 * r in st8 and len(st8) == len(set(st8)) == 7 + 1 + 16
+    st4 = LR.rotation_steps(c, r, LR.FEATURES, 4)
+    assert {b * r for b in range(1, 4)} | {g * 4 * r for g in range(1, 4)} <= set(st4)
+    assert len(st4) == len(set(st4)) == 3 + 3 + 16
+    assert LR.giant_hoisted(c, LR.FEATURES, 4) and not LR.giant_hoisted(c, LR.FEATURES, 16)
+    assert not LR.giant_hoisted(c, LR.ROWS, 4) and not LR.giant_hoisted(256, LR.FEATURES, 8)
 
 
 def test_baby_giant_margins_equal_the_rotation_sum():
