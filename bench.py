@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--ntt-counters", action="store_true",
                     help="run only the calibration copy and the NTT batch (a target for rocprofv3 --pmc passes, "
                          "which cannot follow the step's graph launches); prints no bench line")
+    ap.add_argument("--giant-counters", action="store_true",
+                    help="run only the calibration copy and the hoisted giant-step sum over the shard's blocks "
+                         "(for rocprofv3 --pmc)")
     ap.add_argument("--ks-counters", action="store_true",
                     help="run only the calibration copy and 3 batched multiply-relinearise-rescale-rotate launches "
                          "over 32 ciphertexts at level 18 (key-switch kernels at the step's top-level shape, "
@@ -168,6 +171,27 @@ def measure_copy_and_ks(torch, H, synth, ctx, ev, n_ct=32, level=18):
     ctx.batch_mul_rotate(xs, ys, [1] * n_ct, keys, mode=1, outs=outs)
     t = ev.time(lambda: ctx.batch_mul_rotate(xs, ys, [1] * n_ct, keys, mode=1, outs=outs), 3)
     log("batched mul+relin+rescale+rotate, %d entries at level %d: %.3f ms" % (n_ct, level, t * 1e3))
+
+
+def measure_copy_and_giant(torch, H, synth, ctx, ev, n_ct, steps, level=18):
+    """The calibration copy, then he_rotate_sum (the feature-major giant steps
+    as one hoisted key switch) over n_ct ciphertexts of uniform residues at
+    `level`, 3 timed launches."""
+    N = ctx.N
+    src = torch.ones(COPY_BYTES // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    del src, dst
+    keys = ctx.keygen(11, steps)
+    q = ctx.primes[: level + 1]
+    xs = ctx.ct_block(n_ct, level)
+    for i in range(n_ct):
+        d = np.stack([synth.uniform_residues(300 + 2 * i, q, N), synth.uniform_residues(301 + 2 * i, q, N)])
+        ctx.upload(d, level, 1.0, out=xs[i])
+    outs = ctx.ct_block(n_ct, level)
+    ctx.rotate_sum(xs, steps, keys, outs=outs)
+    t = ev.time(lambda: ctx.rotate_sum(xs, steps, keys, outs=outs), 3)
+    log("hoisted sum of %d rotations, %d entries at level %d: %.3f ms" % (len(steps), n_ct, level, t * 1e3))
 
 
 def ntt_sweep(torch, H, ev):
@@ -296,12 +320,15 @@ def main():
     if args.ks_counters:
         measure_copy_and_ks(torch, H, synth, ctx, ev)
         return
+    if args.giant_counters:
+        measure_copy_and_giant(torch, H, synth, ctx, ev, nb, [g * args.baby * r for g in range(1, c // args.baby)])
+        return
     steps = sorted(set(H.rotation_steps(c, r, H.LAYOUT_ROWS, max(args.baby, 1))) |
                    set(H.rotation_steps(c, r, H.LAYOUT_FEATURES, max(args.baby, 1))))
     t0 = time.time()
     keys = ctx.keygen(Wk["seed_keys"], steps)
     torch.cuda.synchronize()
-    log("keygen: relin + %d rotation keys (%.1fs)" % (len(steps), time.time() - t0))
+    log("keygen: 3 relinearisation + %d rotation keys (%.1fs)" % (len(steps), time.time() - t0))
     coef = coef_binomial()
 
     layouts = {}
@@ -358,12 +385,14 @@ def main():
 def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
     """The oracle on a bounded sample of the feature-major schedule: one
     mul+relin+rescale and one rotation at every level the schedule's key
-    switches run at (the median of two runs each), extrapolated by the
-    schedule's key-switch counts: per block the margin relinearisation and the
-    log2(c / n_baby) margin rotations; per step W's n_baby - 1 baby-step
-    rotations, the one relinearisation of the summed degree-4 terms (three key
-    switches, each timed as a mul+relin+rescale) and the sample-sum and
-    replicate rotations.  The degree-2 products A and B3 (tensor and rescale),
+    switches run at, and one hoisted giant-step sum at the top step level
+    (scaled to the other levels by the rotation times; one run each),
+    extrapolated by the schedule's counts: per block the margin
+    relinearisation and the giant steps (one hoisted sum, or log2(c / n_baby)
+    rotations); per step W's n_baby - 1 baby-step rotations, the one
+    relinearisation of the summed degree-4 terms (three key switches, each
+    timed as a mul+relin+rescale) and the sample-sum and replicate rotations.
+    The degree-2 products A and B3 (tensor and rescale),
     plaintext products, additions, the data's baby-step copies (built once per
     shard) and the refresh are left out, so the CPU rate is an upper bound."""
     if threads:
@@ -383,6 +412,12 @@ def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
     keys.rlk = keys._evk(sp, 0)
     keys.rot = {}
     keys.add_rotation(1)
+    from oracle import lr as LR
+    hoisted = LR.giant_hoisted(c, LR.FEATURES, n_baby)
+    giant = [g * n_baby * r for g in range(1, c // n_baby)]
+    if hoisted:  # the giant-step keys g n_baby r
+        for t in giant:
+            keys.add_rotation(t)
     t_keys = time.time() - t0
 
     def ct(level, seed):
@@ -390,12 +425,9 @@ def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
                               synth.uniform_residues(seed + 1, P.q[: level + 1], P.N)]), level, 1.0)
 
     def timed(fn, *a):
-        ts = []
-        for _ in range(2):
-            t = time.time()
-            fn(*a)
-            ts.append(time.time() - t)
-        return float(np.median(ts))
+        t = time.time()
+        fn(*a)
+        return time.time() - t
 
     lc, lr = int(np.log2(c // n_baby)), int(np.log2(r))
     levels = [P.L - 4 * k for k in range(REFRESH_EVERY)]
@@ -408,20 +440,30 @@ def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
     for lv in need_rot:
         x = ct(lv, 5)
         sample["rot%d" % lv] = timed(lambda: O.rotate(P, x, 1, keys))
+    if hoisted:  # timed at the top step level, scaled to the others by the rotation times
+        lt = levels[0] - 1
+        x = ct(lt, 7)
+        sample["giant%d" % lt] = timed(lambda: O.rotate_sum_hoisted(P, x, giant, keys))
     t_sched = 0.0
     for l in levels:  # the feature-major step at level l
-        t_sched += nb * (sample["mul%d" % l] + lc * sample["rot%d" % (l - 1)])
+        if hoisted:
+            t_giant = sample["giant%d" % lt] * sample["rot%d" % (l - 1)] / sample["rot%d" % lt]
+        else:
+            t_giant = lc * sample["rot%d" % (l - 1)]
+        t_sched += nb * (sample["mul%d" % l] + t_giant)
         t_sched += 3 * sample["mul%d" % (l - 2)] + lr * sample["rot%d" % (l - 3)] + lr * sample["rot%d" % (l - 4)]
         if n_baby > 1:
             t_sched += (n_baby - 1) * sample["rot%d" % l]
     t_step = t_sched / len(levels)
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": nthreads, "kind": "oracle",
             "sample": "one oracle mul+relin+rescale and one rotation at each level the feature-major schedule "
-                      "key-switches at (median of 2 runs; %.1fs of sampled work, keys %.1fs), extrapolated by the "
-                      "schedule's key-switch counts (steps at levels %s, %d baby steps: %d blocks x (1+%d) + %d+3+2x%d "
-                      "per step; tensor products and rescales of A and B3, which need no key switch, are left out)" % (
-                          2 * sum(sample.values()), t_keys, "/".join(map(str, levels)), n_baby, nb, lc,
-                          n_baby - 1, lr),
+                      "key-switches at, and one hoisted sum of the %d giant steps at the top step level, scaled to "
+                      "the others by the rotation times (one run each; "
+                      "%.1fs of sampled work, keys %.1fs), extrapolated by the schedule's counts (steps at levels %s, "
+                      "%d baby steps: %d blocks x (1 mul + %s) + %d+3+2x%d rotations per step; tensor products and "
+                      "rescales of A and B3, which need no key switch, are left out)" % (
+                          len(giant) if hoisted else 0, sum(sample.values()), t_keys, "/".join(map(str, levels)),
+                          n_baby, nb, "1 hoisted sum" if hoisted else "%d rotations" % lc, n_baby - 1, lr),
             "extrapolated": True, "sample_seconds": sample}
 
 

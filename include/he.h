@@ -336,6 +336,21 @@ he_status he_batch_mul_rotate(he_ctx *ctx, const he_ct *x, const he_ct *y, const
                               const he_keys *keys, int mode, he_ct *out);
 
 /*
+ * Hoisted sum of rotations (Sec. 3 rotations; the feature-major giant steps of
+ * he_lr_grad_step): out[i] = x[i] + sum_s Rot(x[i], steps[s]) for n
+ * ciphertexts, as one key switch each: x's a-part is raised to Q_l u P once,
+ * every rotation's inner product with its key is summed there, and the sum is
+ * divided by P once (so the rounding differs from a chain of rotate-and-adds;
+ * the slots agree).  1 <= n_steps <= 32.  The gathers are local when the
+ * steps' Galois elements form a small group (as the giant steps do); any steps
+ * are accepted.  x[0..n): one level and scale, uniform stride; out: caller
+ * memory for n ciphertexts at that level, uniform stride, not overlapping x.
+ * Errors before any launch: HE_EINVAL, HE_ELEVEL, HE_EKEY.
+ */
+he_status he_rotate_sum(he_ctx *ctx, const he_ct *x, int n, const int *steps, int n_steps, const he_keys *keys,
+                        he_ct *out);
+
+/*
  * Rotations of n ciphertexts by each of n_steps steps (Sec. 3 rotations; the
  * baby-step copies of a shard's data for he_lr_grad_step):
  *   out[i * n_steps + s] = Rot(x[i], steps[s]).

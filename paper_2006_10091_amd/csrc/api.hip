@@ -1513,6 +1513,43 @@ he_status he_rotate_many(he_ctx *c, const he_ct *x, int n, const int *steps, int
     return last_error();
 }
 
+he_status he_rotate_sum(he_ctx *c, const he_ct *x, int n, const int *steps, int n_steps, const he_keys *k,
+                        he_ct *out)
+{
+    if (!c || !x || n < 1 || !steps || n_steps < 1 || n_steps > hek::HE_MAXMULTI || !k || !out) return HE_EINVAL;
+    const int l = x[0].level;
+    const long long N = c->N, lc = (long long)(l + 1) * N;
+    long long xs = 0, os = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!ct_ok(c, &x[i]) || x[i].scale != x[0].scale || !out[i].data) return HE_EINVAL;
+        if (x[i].level != l) return HE_ELEVEL;
+        if (i == 1) {
+            xs = x[1].data - x[0].data;
+            os = out[1].data - out[0].data;
+        }
+        if (i > 1 && (x[i].data - x[i - 1].data != xs || out[i].data - out[i - 1].data != os)) return HE_EINVAL;
+    }
+    if (n > 1 && (xs < 2 * lc || os < 2 * lc)) return HE_EINVAL;
+    const u64 *x_end = x[0].data + (long long)(n - 1) * xs + 2 * lc;
+    const u64 *o_end = out[0].data + (long long)(n - 1) * os + 2 * lc;
+    if (!(o_end <= x[0].data || out[0].data >= x_end)) return HE_EINVAL;
+    hek::EntryGal eg;
+    hek::EntryKeys ek;
+    for (int s = 0; s < n_steps; ++s) {
+        eg.g[s] = galois_of(c, steps[s]);
+        ek.k[s] = find_rot_key(k, eg.g[s]);
+        if (!ek.k[s]) return HE_EKEY;
+    }
+    TRY(ensure_ws(c, ks_scratch(c, l, n) * 8 + 4096));
+    Arena ar = arena(c);
+    TRY(rotate_sum_hoisted_apply(c, ar, l, n, x[0].data, xs, eg, ek, n_steps, out[0].data, os));
+    for (int i = 0; i < n; ++i) {
+        out[i].level = l;
+        out[i].scale = x[0].scale;
+    }
+    return last_error();
+}
+
 he_status he_batch_mul_rotate(he_ctx *c, const he_ct *x, const he_ct *y, const int *steps, int n, const he_keys *k,
                               int mode, he_ct *out)
 {

@@ -1655,7 +1655,7 @@ struct GiantArgs {
     long long xs, xc;
     hek::EntryKeys keys;  // key_g [beta][2][np][N]
     hek::EntryGal gals;
-    int ng;
+    int ng, gc;  // rotations; rotations per staged key chunk (tile kernel)
     u64 *acc;  // [b][2][nb][N]
     long long as;
     u64 *out;  // [b][2][l+1][N]: batch stride os, component stride xc
@@ -1663,7 +1663,13 @@ struct GiantArgs {
     int alpha, beta, ell, nq, np, nb, nent, ngroups, logN;
 };
 
-__global__ __launch_bounds__(256) void giant_sum_kernel(GiantArgs a, const PrimeInfo *__restrict__ pinfo)
+__device__ __forceinline__ long long giant_index(u64 e, u64 g, u64 mask2n, int logN)
+{
+    const u64 e2 = (e * g) & mask2n;
+    return brev_n((unsigned)((e2 - 1) >> 1), logN);
+}
+
+__global__ __launch_bounds__(256) void giant_gather_kernel(GiantArgs a, const PrimeInfo *__restrict__ pinfo)
 {
     const int ntile = (1 << a.logN) / 256;
     const int npair = ntile * a.nb;
@@ -1772,6 +1778,126 @@ __global__ __launch_bounds__(256) void giant_sum_kernel(GiantArgs a, const Prime
             const u64 e2 = (e * a.gals.g[g]) & mask2n;
             v = add_mod(v, x0[brev_n((unsigned)((e2 - 1) >> 1), a.logN)], p.q);
         }
+        u64 *o = a.out + b * a.os + toff + k;
+        o[0] = v;
+        o[a.xc] = x0[a.xc + k];
+    }
+}
+
+// The same sum when every s_g keeps k inside its aligned tile of 64
+// coefficients (g = 1 mod 2^(logN - 5)): the 64 lanes of a wave hold one tile,
+// each lane loads its own coefficient of every digit once (coalesced) and takes
+// D_j[s_g(k)] from the lane holding it (ds_bpermute, two 32-bit halves).  A
+// workgroup takes one position t and one tile for up to 4 * EPT entries (wave
+// w serves entries w, w + 4, ..); the tile's keys are staged in LDS a chunk of
+// rotations at a time and read there by every entry.  FP: positions whose prime
+// is below 2^46, lazy FP64 products reduced once per rotation; otherwise exact
+// 128-bit sums reduced once per chunk (at most 40 products below 2^120 each).
+constexpr int GP_TK = 64, GP_LANES = 4, GP_MAXB = 8;
+constexpr int GP_LDS = 40 * 1024;  // bytes of staged keys per workgroup
+
+__device__ __forceinline__ u64 lane_take(u64 v, int src)
+{
+    const int addr = src << 2;
+    const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(v >> 32));
+    return ((u64)hi << 32) | lo;
+}
+
+template <bool FP, int BETA>
+__global__ __launch_bounds__(GP_TK *GP_LANES) void giant_perm_kernel(GiantArgs a, const PrimeInfo *__restrict__ pinfo)
+{
+    extern __shared__ u64 keys_lds[];
+    const int ntile = (1 << a.logN) / GP_TK;
+    const int t = blockIdx.x / ntile;
+    const int L = threadIdx.x % GP_TK, lane = threadIdx.x / GP_TK;
+    const int k = (blockIdx.x % ntile) * GP_TK + L;
+    const int tp = prime_of(t, a.ell, a.nq);
+    const PrimeInfo p = pinfo[tp];
+    if ((p.q < (1ull << 46)) != FP) return;  // the other instantiation's position (uniform per workgroup)
+    const long long N = 1ll << a.logN;
+    const u64 mask2n = 2 * (u64)N - 1;
+    const u64 e = 2 * (u64)brev_n((unsigned)k, a.logN) + 1;
+    const long long toff = (long long)t << a.logN;
+    const long long np_n = (long long)a.np << a.logN;
+    const long long comp1 = (long long)a.nb << a.logN;
+    const int jt = t <= a.ell ? t / a.alpha : -1;
+    const double qd = (double)p.q, qinv = 1.0 / qd;
+    constexpr int per = BETA * 2 * GP_TK;  // staged values per rotation
+    for (int g0 = 0; g0 < a.ng; g0 += a.gc) {
+        const int gn = min(a.gc, a.ng - g0);
+        __syncthreads();
+        for (int v = threadIdx.x; v < gn * per; v += blockDim.x) {
+            const int gi = v / per, r = v % per, jc = r / GP_TK, kk = r % GP_TK;
+            const u64 kv = a.keys.k[g0 + gi][jc * np_n + ((long long)tp << a.logN) + (k - L) + kk];
+            keys_lds[v] = FP ? (u64)__double_as_longlong(d_from_u52(kv)) : kv;
+        }
+        __syncthreads();
+        for (int b = lane; b < a.nent; b += GP_LANES) {  // uniform per wave
+            u64 d[BETA];
+#pragma unroll
+            for (int j = 0; j < BETA; ++j)
+                d[j] = j == jt ? a.x[b * a.xs + a.xc + toff + k] : a.ext[b * a.es + j * a.ds + toff + k];
+            if (FP) {
+#pragma unroll
+                for (int j = 0; j < BETA; ++j) d[j] = (u64)__double_as_longlong(d_from_u52(d[j]));
+            }
+            u64 *o = a.acc + b * a.as + toff + k;
+            double s0 = 0.0, s1 = 0.0;
+            u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+            if (g0 > 0) {  // the running sums of the earlier chunks
+                if (FP) {
+                    s0 = d_from_u52(o[0]);
+                    s1 = d_from_u52(o[comp1]);
+                } else {
+                    lo0 = o[0];
+                    lo1 = o[comp1];
+                }
+            }
+            for (int gi = 0; gi < gn; ++gi) {
+                const int src = (int)(giant_index(e, a.gals.g[g0 + gi], mask2n, a.logN) & (GP_TK - 1));
+                const u64 *kl = keys_lds + gi * per + L;
+                u64 v[BETA], k0[BETA], k1[BETA];
+#pragma unroll
+                for (int j = 0; j < BETA; ++j) {
+                    v[j] = lane_take(d[j], src);
+                    k0[j] = kl[(2 * j) * GP_TK];
+                    k1[j] = kl[(2 * j + 1) * GP_TK];
+                }
+#pragma unroll
+                for (int j = 0; j < BETA; ++j) {
+                    if (FP) {
+                        const double dv = __longlong_as_double((long long)v[j]);
+                        s0 += mulmod_lazy_d(dv, __longlong_as_double((long long)k0[j]), qd, qinv);
+                        s1 += mulmod_lazy_d(dv, __longlong_as_double((long long)k1[j]), qd, qinv);
+                    } else {
+                        u64 pl = v[j] * k0[j], ph = __umul64hi(v[j], k0[j]);
+                        lo0 += pl;
+                        hi0 += ph + (lo0 < pl);
+                        pl = v[j] * k1[j];
+                        ph = __umul64hi(v[j], k1[j]);
+                        lo1 += pl;
+                        hi1 += ph + (lo1 < pl);
+                    }
+                }
+                if (FP) {  // back into (-q, 2q): the sum holds at most 8 more lazy products per rotation
+                    s0 = __fma_rn(-floor(s0 * qinv), qd, s0);
+                    s1 = __fma_rn(-floor(s1 * qinv), qd, s1);
+                }
+            }
+            // FP: one full reduction; 128-bit sums of at most 40 products below 2^120 per chunk: reduced once
+            o[0] = FP ? u52_from_d(reduce_d(s0, qd, qinv)) : reduce128(hi0, lo0, p);
+            o[comp1] = FP ? u52_from_d(reduce_d(s1, qd, qinv)) : reduce128(hi1, lo1, p);
+        }
+    }
+    if (t > a.ell) return;
+    // the base: b-parts automorphed and summed, the a-part copied
+    for (int b = lane; b < a.nent; b += GP_LANES) {
+        const u64 *x0 = a.x + b * a.xs + toff;
+        const u64 own = x0[k];
+        u64 v = own;
+        for (int g = 0; g < a.ng; ++g)
+            v = add_mod(v, lane_take(own, (int)(giant_index(e, a.gals.g[g], mask2n, a.logN) & (GP_TK - 1))), p.q);
         u64 *o = a.out + b * a.os + toff + k;
         o[0] = v;
         o[a.xc] = x0[a.xc + k];
@@ -2365,9 +2491,9 @@ void automorph_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long lon
     automorph_kernel<<<gr, 256, 0, c->stream>>>(in, ib, ic, out, ob, oc, g, c->logN);
 }
 
-void giant_sum_b(he_ctx *c, int level, int B, const u64 *ext, long long es, long long ds, const u64 *x, long long xs,
-                 long long xc, const EntryGal &gals, const EntryKeys &keys, int ng, u64 *acc, long long as, u64 *out,
-                 long long os)
+static void giant_gather_b(he_ctx *c, int level, int B, const u64 *ext, long long es, long long ds, const u64 *x,
+                           long long xs, long long xc, const EntryGal &gals, const EntryKeys &keys, int ng, u64 *acc,
+                           long long as, u64 *out, long long os)
 {
     GiantArgs a{};
     a.ext = ext;
@@ -2393,7 +2519,65 @@ void giant_sum_b(he_ctx *c, int level, int B, const u64 *ext, long long es, long
     a.ngroups = (B + GIANT_EPT - 1) / GIANT_EPT;
     a.logN = c->logN;
     const long long nwg = (long long)a.ngroups * (c->N / 256) * a.nb;
-    giant_sum_kernel<<<dim3((unsigned)nwg, 1, 1), 256, 0, c->stream>>>(a, c->t.pinfo);
+    giant_gather_kernel<<<dim3((unsigned)nwg, 1, 1), 256, 0, c->stream>>>(a, c->t.pinfo);
+}
+
+void giant_sum_b(he_ctx *c, int level, int B, const u64 *ext, long long es, long long ds, const u64 *x, long long xs,
+                 long long xc, const EntryGal &gals, const EntryKeys &keys, int ng, u64 *acc, long long as, u64 *out,
+                 long long os)
+{
+    const int beta = (level + 1 + c->alpha - 1) / c->alpha;
+    // tile-local permutations: every Galois element 1 mod 2^(logN - 5)
+    bool local = c->logN >= 6 && beta <= GP_MAXB;
+    for (int g = 0; g < ng; ++g) local = local && ((gals.g[g] - 1) & ((2ull << (c->logN - 6)) - 1)) == 0;
+    if (!local) {
+        giant_gather_b(c, level, B, ext, es, ds, x, xs, xc, gals, keys, ng, acc, as, out, os);
+        return;
+    }
+    GiantArgs a{};
+    a.es = es;
+    a.ds = ds;
+    a.xs = xs;
+    a.xc = xc;
+    a.keys = keys;
+    a.gals = gals;
+    a.ng = ng;
+    a.as = as;
+    a.os = os;
+    a.alpha = c->alpha;
+    a.beta = beta;
+    a.ell = level;
+    a.nq = c->nq;
+    a.np = c->np;
+    a.nb = level + 1 + c->nk;
+    a.logN = c->logN;
+    const int per = beta * 2 * GP_TK * 8;  // staged key bytes per rotation
+    // rotations per staged chunk: balanced chunks of at most GP_LDS bytes
+    const int nchunk = (ng * per + GP_LDS - 1) / GP_LDS;
+    a.gc = (ng + nchunk - 1) / nchunk;
+    const size_t lds = (size_t)a.gc * per;
+    const unsigned nwg = (unsigned)((c->N / GP_TK) * a.nb);
+    a.ext = ext;
+    a.x = x;
+    a.acc = acc;
+    a.out = out;
+    a.nent = B;
+    switch (beta) {
+#define HE_GIANT(BT)                                                                                  \
+    case BT:                                                                                          \
+        giant_perm_kernel<true, BT><<<nwg, GP_TK * GP_LANES, lds, c->stream>>>(a, c->t.pinfo);  \
+        giant_perm_kernel<false, BT><<<nwg, GP_TK * GP_LANES, lds, c->stream>>>(a, c->t.pinfo); \
+        break
+        HE_GIANT(1);
+        HE_GIANT(2);
+        HE_GIANT(3);
+        HE_GIANT(4);
+        HE_GIANT(5);
+        HE_GIANT(6);
+        HE_GIANT(7);
+        HE_GIANT(8);
+#undef HE_GIANT
+    }
 }
 
 void automorph_multi_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,

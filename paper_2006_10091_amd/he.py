@@ -94,6 +94,7 @@ _sig = {
     "he_lr_grad_step": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), _P(he_pt), _P(c_double), c_double, c_double,
                                 c_int, c_int, c_int, _P(he_ct), c_int, c_void_p, c_int, _P(he_ct), _P(he_ct)]),
     "he_rotate_many": (c_int, [c_void_p, _P(he_ct), c_int, _P(c_int32), c_int, c_void_p, _P(he_ct)]),
+    "he_rotate_sum": (c_int, [c_void_p, _P(he_ct), c_int, _P(c_int32), c_int, c_void_p, _P(he_ct)]),
     "he_batch_mul_rotate": (c_int, [c_void_p, _P(he_ct), _P(he_ct), _P(c_int32), c_int, c_void_p, c_int,
                                     _P(he_ct)]),
     "he_lr_margins": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), c_int, c_int, c_int, c_void_p, c_int,
@@ -408,6 +409,19 @@ class Context:
         st = np.ascontiguousarray(steps, dtype=np.int32)
         _chk(_lib.he_rotate_many(self.h, xa, len(xs), st.ctypes.data_as(POINTER(c_int32)), len(steps), keys.handle,
                                  oa), "he_rotate_many")
+        for o, s_ in zip(outs, oa):
+            o.update(s_)
+        return outs
+
+    def rotate_sum(self, xs, steps, keys, outs=None):
+        """he_rotate_sum: outs[i] = xs[i] + sum_s Rot(xs[i], steps[s]), one
+        hoisted key switch each; outs allocated as one block when None."""
+        outs = outs or self.ct_block(len(xs), xs[0].level)
+        xa = (he_ct * len(xs))(*[x.struct() for x in xs])
+        oa = (he_ct * len(xs))(*[o.struct() for o in outs])
+        st = np.ascontiguousarray(steps, dtype=np.int32)
+        _chk(_lib.he_rotate_sum(self.h, xa, len(xs), st.ctypes.data_as(POINTER(c_int32)), len(steps), keys.handle,
+                                oa), "he_rotate_sum")
         for o, s_ in zip(outs, oa):
             o.update(s_)
         return outs
