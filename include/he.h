@@ -281,6 +281,10 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  * are taken as one hoisted sum, x + sum_g Rot(x, g n_baby r): one ModUp of
  * x's a-part, every rotation's inner product summed in Q u P, one ModDown;
  * keys then hold every g n_baby r instead of the powers of two from n_baby r.
+ * Zk (nullable): the step's data terms precomputed by he_lr_data_terms for
+ * the same Z, W level and scale, coef, eta_over_n, w_decay and layout
+ * (checked: levels, scales and uniform strides; HE_ESCALE when a scale differs);
+ * the step then skips their rescales.  NULL: computed in the step.
  * Outputs (caller memory, W's level - 4): W_out, and G_out (nullable) = g.
  * mode 0: plain form (one he_* operation per block per step, one kernel
  * sequence each); mode 1: batched form (every block in one launch per
@@ -291,7 +295,24 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
 he_status he_lr_grad_step(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct *W,
                           const he_pt *mask, const double coef[4], double eta_over_n,
                           double w_decay, int c, int r, int layout, const he_ct *Zrot, int n_baby,
-                          const he_keys *keys, int mode, he_ct *W_out, he_ct *G_out);
+                          const he_ct *Zk, const he_keys *keys, int mode, he_ct *W_out, he_ct *G_out);
+
+/*
+ * The data terms of a gradient step (eq. (appr): the a3 and a1 (and a2)
+ * coefficients times the data, each an integer multiple of Z rescaled once),
+ * which depend on the weights only through their level and scale: a worker
+ * whose weights return to the same level and scale every refresh period
+ * computes them once per level and passes them to he_lr_grad_step as Zk.
+ *   out[b]                = RS(k3 Z[b])   at level l - 1 (features) / l - 2 (rows)
+ *   out[n_blocks + b]     = RS(k1 Z[b])   at level l - 2 / l - 3
+ *   out[2 n_blocks + b]   = RS(k2 Z[b])   same level, only when coef[2] != 0
+ * with k1, k2, k3 from the step's plan (he_plan_lr_step(q, l, Z's scale,
+ * w_scale, ...)); l = w_level.  Z as for he_lr_grad_step; out: caller memory,
+ * each group of n_blocks at one uniform stride (the k2 group at the k1
+ * group's stride).  Errors before any launch: HE_EINVAL, HE_ELEVEL, HE_ESCALE.
+ */
+he_status he_lr_data_terms(he_ctx *ctx, const he_ct *Z, int n_blocks, int w_level, double w_scale,
+                           const double coef[4], double eta_over_n, double w_decay, int layout, he_ct *out);
 
 /*
  * Encrypted inference on one worker's blocks: the margins m_i = w.x_i of

@@ -539,7 +539,10 @@ size_t step_bytes(const he_ctx *c, int l, int nb, int layout, int n_baby = 1)
         n += al((size_t)(n_baby - 1) * 2 * (l + 1) * N);  // Wr
         scratch = std::max(scratch, rotate_scratch(c, l, n_baby - 1));
     }
-    n += std::max(scratch, rotate_scratch(c, l - 3 + e, 1));
+    // per step: the rotations at level l-3+e, or the degree-4 relinearisation's
+    // three-entry key switch and its three outputs
+    n += std::max(scratch, std::max(rotate_scratch(c, l - 3 + e, 1),
+                                    al((size_t)6 * (l - 2 + e) * N) + ks_scratch(c, l - 3 + e, 3)));
     return n * 8 + 4096;
 }
 
@@ -605,9 +608,17 @@ struct BabyData {
     int n_baby = 1;
 };
 
+// The step's data terms precomputed by he_lr_data_terms: Z3 = RS(k3 Z) and
+// Z1 = RS(k1 Z) (and Z2 = RS(k2 Z) for k2 != 0, with Z1's batch stride),
+// block b at z3 + b z3s etc.; nullptr: the step computes them.
+struct TermData {
+    const u64 *z3 = nullptr, *z1 = nullptr, *z2 = nullptr;
+    long long z3s = 0, z1s = 0;
+};
+
 he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, const he_ct *Z, long long zbs, int b0,
                       int nb, const he_ct *W, const he_pt *mask, int cols, const he_keys *keys, bool accumulate,
-                      const BabyData &bd)
+                      const BabyData &bd, const TermData &td)
 {
     const long long N = c->N;
     const int l = W->level;
@@ -646,15 +657,30 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
     }
     // A = RS(M^2) ; Z3 = RS(k3 Z), B3 = RS(M Z3), degree 2 ; Z1 = RS(k1 Z)   (level l-3)
     TRY(mul_rescale3(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.M, 2 * m1, m1, s.A));
-    TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z3, 2 * m1, 2, &pl.k3, zc));
-    TRY(mul_rescale3(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.Z3, 2 * m1, m1, s.B3));
+    const u64 *z3p = s.Z3;
+    long long z3s = 2 * m1;
+    if (td.z3) {
+        z3p = td.z3 + (long long)b0 * td.z3s;
+        z3s = td.z3s;
+    } else {
+        TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z3, 2 * m1, 2, &pl.k3, zc));
+    }
+    TRY(mul_rescale3(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, z3p, z3s, m1, s.B3));
     // Z1 = RS(k1 Z) and, for a2 != 0, Z2 = RS(k2 Z), both at level l-3
     const long long a1 = (long long)(l - 2) * N;
-    TRY(rescale_apply(c, ar, l - 2, nb, zp, zbs, s.Z1, 2 * a1, 2, &pl.k1, zc));
-    if (pl.k2 != 0) TRY(rescale_apply(c, ar, l - 2, nb, zp, zbs, s.Z2, 2 * a1, 2, &pl.k2, zc));
+    const u64 *z1p = s.Z1, *z2p = pl.k2 != 0 ? s.Z2 : nullptr;
+    long long z1s = 2 * a1;
+    if (td.z1) {
+        z1p = td.z1 + (long long)b0 * td.z1s;
+        z2p = pl.k2 != 0 ? td.z2 + (long long)b0 * td.z1s : nullptr;
+        z1s = td.z1s;
+    } else {
+        TRY(rescale_apply(c, ar, l - 2, nb, zp, zbs, s.Z1, 2 * a1, 2, &pl.k1, zc));
+        if (pl.k2 != 0) TRY(rescale_apply(c, ar, l - 2, nb, zp, zbs, s.Z2, 2 * a1, 2, &pl.k2, zc));
+    }
     // the blocks' terms at level l-3 (unrescaled, degree 4), summed straight into G5
-    hek::terms_sum_b(c, l - 3, nb, s.A, s.B3, 3 * a1, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, s.M, 2 * m1, m1,
-                     zp, zbs, zc, pl.k0, s.G5, accumulate);
+    hek::terms_sum_b(c, l - 3, nb, s.A, s.B3, 3 * a1, z1p, z2p, z1s, a1, s.M, 2 * m1, m1, zp, zbs, zc, pl.k0, s.G5,
+                     accumulate);
     return last_error();
 }
 
@@ -664,7 +690,7 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
 // at level l-3.
 he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, const he_ct *Z,
                                long long zbs, int b0, int nb, const he_ct *W, int cols, int rows,
-                               const he_keys *keys, bool accumulate, const BabyData &bd)
+                               const he_keys *keys, bool accumulate, const BabyData &bd, const TermData &td)
 {
     const long long N = c->N;
     const int l = W->level;
@@ -709,15 +735,30 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
     }
     // A = RS(M^2) ; Z3 = RS(k3 Z), B3 = RS(M Z3), degree 2 ; Z1 = RS(k1 Z)   (level l-2)
     TRY(mul_rescale3(c, ar, s, l - 1, nb, M, 2 * u1, u1, M, 2 * u1, u1, s.A));
-    TRY(rescale_apply(c, ar, l, nb, zp, zbs, s.Z3, 2 * u1, 2, &pl.k3, zc));
-    TRY(mul_rescale3(c, ar, s, l - 1, nb, M, 2 * u1, u1, s.Z3, 2 * u1, u1, s.B3));
+    const u64 *z3p = s.Z3;
+    long long z3s = 2 * u1;
+    if (td.z3) {
+        z3p = td.z3 + (long long)b0 * td.z3s;
+        z3s = td.z3s;
+    } else {
+        TRY(rescale_apply(c, ar, l, nb, zp, zbs, s.Z3, 2 * u1, 2, &pl.k3, zc));
+    }
+    TRY(mul_rescale3(c, ar, s, l - 1, nb, M, 2 * u1, u1, z3p, z3s, u1, s.B3));
     // Z1 = RS(k1 Z) and, for a2 != 0, Z2 = RS(k2 Z), both at level l-2
     const long long a1 = (long long)(l - 1) * N;
-    TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z1, 2 * a1, 2, &pl.k1, zc));
-    if (pl.k2 != 0) TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z2, 2 * a1, 2, &pl.k2, zc));
+    const u64 *z1p = s.Z1, *z2p = pl.k2 != 0 ? s.Z2 : nullptr;
+    long long z1s = 2 * a1;
+    if (td.z1) {
+        z1p = td.z1 + (long long)b0 * td.z1s;
+        z2p = pl.k2 != 0 ? td.z2 + (long long)b0 * td.z1s : nullptr;
+        z1s = td.z1s;
+    } else {
+        TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z1, 2 * a1, 2, &pl.k1, zc));
+        if (pl.k2 != 0) TRY(rescale_apply(c, ar, l - 1, nb, zp, zbs, s.Z2, 2 * a1, 2, &pl.k2, zc));
+    }
     // the block's terms at level l-2 (unrescaled, degree 4); G5 (+)= their sum
-    hek::terms_sum_b(c, l - 2, nb, s.A, s.B3, 3 * a1, s.Z1, pl.k2 != 0 ? s.Z2 : nullptr, 2 * a1, a1, M, 2 * u1, u1,
-                     zp, zbs, zc, pl.k0, s.G5, accumulate);
+    hek::terms_sum_b(c, l - 2, nb, s.A, s.B3, 3 * a1, z1p, z2p, z1s, a1, M, 2 * u1, u1, zp, zbs, zc, pl.k0, s.G5,
+                     accumulate);
     return last_error();
 }
 
@@ -869,8 +910,8 @@ he_status margins_impl(he_ctx *c, const he_ct *Z, int n_blocks, long long zbs, c
 
 // the whole step; nchunk = 1 (plain: per-block operations) or n_blocks (batched)
 he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_blocks, long long zbs, const BabyData &bd,
-                    const he_ct *W, const he_pt *mask, int cols, int rows, const he_keys *keys, int chunk,
-                    he_ct *W_out, he_ct *G_out)
+                    const TermData &td, const he_ct *W, const he_pt *mask, int cols, int rows, const he_keys *keys,
+                    int chunk, he_ct *W_out, he_ct *G_out)
 {
     const long long N = c->N;
     const int l = W->level;
@@ -896,9 +937,9 @@ he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_block
         long long bs = zbs;
         if (chunk == 1) bs = 0;
         if (fm)
-            TRY(step_blocks_features(c, ar, s, pl, Z, bs, b0, nb, W, cols, rows, keys, b0 > 0, bd));
+            TRY(step_blocks_features(c, ar, s, pl, Z, bs, b0, nb, W, cols, rows, keys, b0 > 0, bd, td));
         else
-            TRY(step_blocks(c, ar, s, pl, Z, bs, b0, nb, W, mask, cols, keys, b0 > 0, bd));
+            TRY(step_blocks(c, ar, s, pl, Z, bs, b0, nb, W, mask, cols, keys, b0 > 0, bd, td));
     }
     const long long g1 = (long long)(l - 3) * N;  // component stride at level l-4
     {
@@ -906,9 +947,20 @@ he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_block
         // key switches of g2, g3, g4 from s^2, s^3, s^4; then one rescale
         const int lg = fm ? l - 2 : l - 3;
         const long long x1 = (long long)(lg + 1) * N;
-        TRY(ks_apply(c, ar, lg, 1, s.G5 + 2 * x1, 0, keys->rlk, s.G5, 0, x1, 2, s.U0, 0, x1));
-        TRY(ks_apply(c, ar, lg, 1, s.G5 + 3 * x1, 0, keys->rlk3, s.U0, 0, x1, 2, s.U0, 0, x1));
-        TRY(ks_apply(c, ar, lg, 1, s.G5 + 4 * x1, 0, keys->rlk4, s.U0, 0, x1, 2, s.U0, 0, x1));
+        // the three key switches as one batch of three entries (per-entry keys),
+        // then (g0, g1) plus their sum
+        hek::EntryKeys ek;
+        ek.k[0] = keys->rlk;
+        ek.k[1] = keys->rlk3;
+        ek.k[2] = keys->rlk4;
+        const size_t mark = ar.off;
+        u64 *ksx = ar.take((size_t)6 * x1);
+        if (!ksx) return HE_ENOMEM;
+        TRY(ks_apply(c, ar, lg, 3, s.G5 + 2 * x1, x1, nullptr, nullptr, 0, 0, 0, ksx, 2 * x1, x1, &ek));
+        hek::ewise(c, 0, lg, 1, 2, s.G5, 0, x1, ksx, 0, x1, s.U0, 0, x1, 0);
+        for (int e = 1; e < 3; ++e)
+            hek::ewise(c, 0, lg, 1, 2, s.U0, 0, x1, ksx + 2 * e * x1, 0, x1, s.U0, 0, x1, 0);
+        ar.off = mark;
         TRY(rescale_apply(c, ar, lg, 1, s.U0, 2 * x1, s.G, 2LL * lg * N));
     }
     u64 *g = s.G;
@@ -1376,9 +1428,29 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
     return hehost::plan_lr_step(q, n_q, level, s_z, s_w, coef, eta_over_n, w_decay, layout, out);
 }
 
+// levels of the step's data terms Z3 and Z1 / Z2 for weights at level l
+inline int z3_level(int l, bool fm) { return fm ? l - 1 : l - 2; }
+inline int z1_level(int l, bool fm) { return fm ? l - 2 : l - 3; }
+
+// n ciphertexts x[0..n) at one level and scale with one uniform stride (0 for n = 1)
+he_status uniform_group(const he_ctx *c, const he_ct *x, int n, int level, double scale, long long &stride)
+{
+    stride = 0;
+    for (int b = 0; b < n; ++b) {
+        if (!ct_ok(c, &x[b])) return HE_EINVAL;
+        if (x[b].level != level) return HE_ELEVEL;
+        if (x[b].scale != scale) return HE_ESCALE;
+        if (b == 1) stride = x[1].data - x[0].data;
+        if (b > 1 && x[b].data - x[b - 1].data != stride) return HE_EINVAL;
+    }
+    if (n > 1 && stride < 2LL * (level + 1) * c->N) return HE_EINVAL;
+    return HE_OK;
+}
+
 he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, const he_pt *mask,
                           const double coef[4], double eta_over_n, double w_decay, int cols, int rows, int layout,
-                          const he_ct *Zrot, int n_baby, const he_keys *k, int mode, he_ct *W_out, he_ct *G_out)
+                          const he_ct *Zrot, int n_baby, const he_ct *Zk, const he_keys *k, int mode, he_ct *W_out,
+                          he_ct *G_out)
 {
     if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !mask || !mask->data || !coef || !k || mode < 0 || mode > 2)
         return HE_EINVAL;
@@ -1425,6 +1497,22 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
     he_lr_plan pl;
     TRY(hehost::plan_lr_step(c->q.data(), c->nq, l, sz, W->scale, coef, eta_over_n, w_decay, layout, &pl));
     if (mask->scale != pl.s_mask) return HE_ESCALE;
+    // precomputed data terms (he_lr_data_terms for this plan): Z3 group, Z1 group, Z2 group when k2 != 0
+    TermData td;
+    if (Zk) {
+        long long s3, s1, s2;
+        TRY(uniform_group(c, Zk, n_blocks, z3_level(l, fm), pl.s_z3, s3));
+        TRY(uniform_group(c, Zk + n_blocks, n_blocks, z1_level(l, fm), pl.s_z1, s1));
+        td.z3 = Zk[0].data;
+        td.z3s = s3;
+        td.z1 = Zk[n_blocks].data;
+        td.z1s = s1;
+        if (pl.k2 != 0) {
+            TRY(uniform_group(c, Zk + 2 * n_blocks, n_blocks, z1_level(l, fm), pl.s_z2, s2));
+            if (s2 != s1) return HE_EINVAL;
+            td.z2 = Zk[2 * n_blocks].data;
+        }
+    }
     // every key the step needs, checked before any launch
     const int pm = fm ? rows : cols;   // the +-2^k rotations
     const int st = fm ? cols : rows;   // the unit * 2^k rotations
@@ -1453,18 +1541,65 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
             << (const void *)k << ':' << (const void *)W_out->data << ':'
             << (const void *)(G_out ? G_out->data : nullptr) << ':' << pl.k0 << ':' << pl.k1 << ':' << pl.k2 << ':'
             << pl.k3 << ':' << pl.kb1 << ':' << pl.kw << ':' << (const void *)c->ws << ':' << layout << ':' << n_baby
-            << ':' << (const void *)bd.zr << ':' << bd.zrb << ':' << bd.zrs << ':' << bd.zrc;
+            << ':' << (const void *)bd.zr << ':' << bd.zrb << ':' << bd.zrs << ':' << bd.zrc << ':'
+            << (const void *)td.z3 << ':' << td.z3s << ':' << (const void *)td.z1 << ':' << td.z1s << ':'
+            << (const void *)td.z2;
         TRY(run_graph(c, key.str(), [&] {
-            return step_impl(c, pl, Z, n_blocks, zbs, bd, W, mask, cols, rows, k, chunk, W_out, G_out);
+            return step_impl(c, pl, Z, n_blocks, zbs, bd, td, W, mask, cols, rows, k, chunk, W_out, G_out);
         }));
     } else {
-        TRY(step_impl(c, pl, Z, n_blocks, zbs, bd, W, mask, cols, rows, k, chunk, W_out, G_out));
+        TRY(step_impl(c, pl, Z, n_blocks, zbs, bd, td, W, mask, cols, rows, k, chunk, W_out, G_out));
     }
     W_out->level = l - 4;
     W_out->scale = pl.s_g;
     if (G_out) {
         G_out->level = l - 4;
         G_out->scale = pl.s_g;
+    }
+    return last_error();
+}
+
+he_status he_lr_data_terms(he_ctx *c, const he_ct *Z, int n_blocks, int w_level, double w_scale, const double coef[4],
+                           double eta_over_n, double w_decay, int layout, he_ct *out)
+{
+    if (!c || !Z || n_blocks < 1 || !coef || !out) return HE_EINVAL;
+    if (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES) return HE_EINVAL;
+    const bool fm = layout == HE_LAYOUT_FEATURES;
+    const int l = w_level;
+    if (l < 4) return HE_ELEVEL;
+    const int lz = Z[0].level;
+    const double sz = Z[0].scale;
+    long long zbs;
+    TRY(uniform_group(c, Z, n_blocks, lz, sz, zbs));
+    if (lz < l) return HE_ELEVEL;
+    he_lr_plan pl;
+    TRY(hehost::plan_lr_step(c->q.data(), c->nq, l, sz, w_scale, coef, eta_over_n, w_decay, layout, &pl));
+    const int ng = pl.k2 != 0 ? 3 : 2;
+    const int lev[3] = {z3_level(l, fm), z1_level(l, fm), z1_level(l, fm)};
+    const i64 kk[3] = {pl.k3, pl.k1, pl.k2};
+    const double sc[3] = {pl.s_z3, pl.s_z1, pl.s_z2};
+    long long os[3];
+    for (int g = 0; g < ng; ++g) {
+        const long long lc = (long long)(lev[g] + 1) * c->N;
+        os[g] = 0;
+        for (int b = 0; b < n_blocks; ++b) {
+            const he_ct &o = out[g * n_blocks + b];
+            if (!o.data) return HE_EINVAL;
+            if (b == 1) os[g] = o.data - out[g * n_blocks].data;
+            if (b > 1 && o.data - out[g * n_blocks + b - 1].data != os[g]) return HE_EINVAL;
+        }
+        if (n_blocks > 1 && os[g] < 2 * lc) return HE_EINVAL;
+    }
+    if (ng == 3 && os[2] != os[1]) return HE_EINVAL;
+    TRY(ensure_ws(c, rescale_scratch(c, l, n_blocks) * 8 + 4096));
+    const long long zc = (long long)(lz + 1) * c->N;
+    for (int g = 0; g < ng; ++g) {
+        Arena ar = arena(c);
+        TRY(rescale_apply(c, ar, lev[g] + 1, n_blocks, Z[0].data, zbs, out[g * n_blocks].data, os[g], 2, &kk[g], zc));
+        for (int b = 0; b < n_blocks; ++b) {
+            out[g * n_blocks + b].level = lev[g];
+            out[g * n_blocks + b].scale = sc[g];
+        }
     }
     return last_error();
 }

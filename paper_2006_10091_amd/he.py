@@ -92,7 +92,10 @@ _sig = {
     "he_plan_lr_step": (c_int, [_P(c_uint64), c_int, c_int, c_double, c_double, _P(c_double), c_double, c_double,
                                 c_int, _P(he_lr_plan)]),
     "he_lr_grad_step": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), _P(he_pt), _P(c_double), c_double, c_double,
-                                c_int, c_int, c_int, _P(he_ct), c_int, c_void_p, c_int, _P(he_ct), _P(he_ct)]),
+                                c_int, c_int, c_int, _P(he_ct), c_int, _P(he_ct), c_void_p, c_int, _P(he_ct),
+                                _P(he_ct)]),
+    "he_lr_data_terms": (c_int, [c_void_p, _P(he_ct), c_int, c_int, c_double, _P(c_double), c_double, c_double, c_int,
+                                 _P(he_ct)]),
     "he_rotate_many": (c_int, [c_void_p, _P(he_ct), c_int, _P(c_int32), c_int, c_void_p, _P(he_ct)]),
     "he_rotate_sum": (c_int, [c_void_p, _P(he_ct), c_int, _P(c_int32), c_int, c_void_p, _P(he_ct)]),
     "he_batch_mul_rotate": (c_int, [c_void_p, _P(he_ct), _P(he_ct), _P(c_int32), c_int, c_void_p, c_int,
@@ -358,14 +361,16 @@ class Context:
         return plan_lr_step(self.primes, self.n_q, level, s_z, s_w, coef, eta_over_n, w_decay, layout)
 
     def lr_grad_step(self, Z, W, mask, coef, eta_over_n, cols, rows, keys, mode=1, W_out=None, G_out=None,
-                     want_g=True, w_decay=0.0, layout=LAYOUT_ROWS, Zrot=None, n_baby=1):
+                     want_g=True, w_decay=0.0, layout=LAYOUT_ROWS, Zrot=None, n_baby=1, Zk=None):
         """One encrypted gradient step (he_lr_grad_step).  Z: list of block
         ciphertexts sharing one allocation (ct_block), packed in `layout`;
-        with n_baby > 1: Zrot = rotate_data(Z, baby_unit(layout, rows), n_baby).
-        Z and Zrot may also be ct_array()s built once (callers stepping many
-        times skip rebuilding the argument arrays).  Returns (W', g)."""
+        with n_baby > 1: Zrot = rotate_data(Z, baby_unit(layout, rows), n_baby);
+        Zk: lr_data_terms for this W's level and scale, or None.  Z, Zrot and Zk
+        may also be ct_array()s built once (callers stepping many times skip
+        rebuilding the argument arrays).  Returns (W', g)."""
         zs = ct_array(Z)
         zr = ct_array(Zrot) if Zrot else None
+        zk = ct_array(Zk) if Zk else None
         w, m = W.struct(), mask.struct()
         lo = max(W.level - 4, 0)
         W_out = W_out or self.ct_empty(lo)
@@ -375,12 +380,30 @@ class Context:
         go = G_out.struct() if want_g else None
         cf = np.ascontiguousarray(coef, dtype=np.float64)
         _chk(_lib.he_lr_grad_step(self.h, zs, len(Z), ctypes.byref(w), ctypes.byref(m), _f64p(cf), eta_over_n,
-                                  w_decay, cols, rows, layout, zr, n_baby, keys.handle, mode, ctypes.byref(wo),
+                                  w_decay, cols, rows, layout, zr, n_baby, zk, keys.handle, mode, ctypes.byref(wo),
                                   ctypes.byref(go) if go is not None else None), "he_lr_grad_step")
         W_out.update(wo)
         if want_g:
             G_out.update(go)
         return W_out, (G_out if want_g else None)
+
+    def lr_data_terms(self, Z, w_level, w_scale, coef, eta_over_n, w_decay=0.0, layout=LAYOUT_ROWS):
+        """he_lr_data_terms: RS(k3 Z), RS(k1 Z) (and RS(k2 Z) when coef[2] != 0)
+        for weights at w_level with scale w_scale, one ct_block per group;
+        returns the list in the order he_lr_grad_step's Zk takes."""
+        fm = layout == LAYOUT_FEATURES
+        l3, l1 = (w_level - 1, w_level - 2) if fm else (w_level - 2, w_level - 3)
+        groups = [self.ct_block(len(Z), l3), self.ct_block(len(Z), l1)]
+        if coef[2] != 0:
+            groups.append(self.ct_block(len(Z), l1))
+        out = [o for g in groups for o in g]
+        oa = (he_ct * len(out))(*[o.struct() for o in out])
+        cf = np.ascontiguousarray(coef, dtype=np.float64)
+        _chk(_lib.he_lr_data_terms(self.h, ct_array(Z), len(Z), w_level, w_scale, _f64p(cf), eta_over_n, w_decay,
+                                   layout, oa), "he_lr_data_terms")
+        for o, s_ in zip(out, oa):
+            o.update(s_)
+        return out
 
     def lr_margins(self, Z, W, cols, rows, keys, mode=1, out=None, layout=LAYOUT_ROWS):
         """he_lr_margins: per block u = RS(relin(Z_b (x) W)) + the margin sum.

@@ -47,11 +47,16 @@ class ParameterServer:
 class Worker:
     """Evaluates the encrypted gradient step on its shard; Alg. 1."""
 
+    TERMS_KEPT = 8  # (level, scale) pairs whose data terms the worker keeps
+
     def __init__(self, ctx, keys, Z, coef, eta_over_n, cols, rows, mode=2, w_decay=0.0, layout=H.LAYOUT_ROWS,
-                 n_baby=1, Zrot=None):
+                 n_baby=1, Zrot=None, terms=True):
         """n_baby > 1: the worker keeps the baby-step rotations
         of its data (n_baby - 1 copies of the shard), computed here unless
-        given as Zrot (ctx.rotate_data)."""
+        given as Zrot (ctx.rotate_data).  terms: the worker keeps the step's
+        data terms (ctx.lr_data_terms) per weight level and scale, computed
+        on first use; the weights return to the same levels and scales every
+        refresh period."""
         self.ctx, self.keys, self.Z = ctx, keys, Z
         self.coef, self.eta_over_n, self.w_decay = list(coef), eta_over_n, w_decay
         self.cols, self.rows, self.mode, self.layout = cols, rows, mode, layout
@@ -64,6 +69,8 @@ class Worker:
         self._zra = H.ct_array(self.Zrot) if self.Zrot else None
         self._masks = {}
         self._bufs = {}
+        self.terms = terms
+        self._terms = {}
 
     def _mask(self, level, s_mask):
         key = (level, s_mask)
@@ -86,12 +93,22 @@ class Worker:
         pl = ctx.plan_lr_step(W.level, self.Z[0].scale, W.scale, self.coef, self.eta_over_n, self.w_decay,
                               self.layout)
         mask = self._mask(W.level, pl["s_mask"])
+        zk = None
+        if self.terms:
+            key = (W.level, W.scale)
+            if key not in self._terms:
+                if len(self._terms) >= self.TERMS_KEPT:
+                    self._terms.pop(next(iter(self._terms)))
+                cts = ctx.lr_data_terms(self.Z, W.level, W.scale, self.coef, self.eta_over_n, self.w_decay,
+                                        self.layout)
+                self._terms[key] = (cts, H.ct_array(cts))
+            zk = self._terms[key][1]
         lo = W.level - 4
         W_out = self._out(lo, 0)
         G_out = self._out(lo, 1) if want_g else None
         return ctx.lr_grad_step(self._za, W, mask, self.coef, self.eta_over_n, self.cols, self.rows, self.keys,
                                 mode=self.mode, W_out=W_out, G_out=G_out, want_g=want_g, w_decay=self.w_decay,
-                                layout=self.layout, Zrot=self._zra, n_baby=self.n_baby)
+                                layout=self.layout, Zrot=self._zra, n_baby=self.n_baby, Zk=zk)
 
 
 def encrypt_shard(ctx, keys, X, y, seed_enc, layout=H.LAYOUT_ROWS):

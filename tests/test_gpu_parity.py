@@ -286,6 +286,18 @@ def test_lr_step_error_paths(small, small_step):
     with pytest.raises(H.HEError) as e:
         ctx.lr_grad_step(s["gZ"], s["gW"], mask, s["coef"], s["eta_n"], c, r, few)
     assert e.value.status == 5  # HE_EKEY: rotations missing
+    # data terms of another plan (here another eta / n: another Z3 scale) are refused
+    eta2 = s["eta_n"] * 64
+    assert LR.plan_lr_step(P.q, P.L, P.delta, P.delta, s["coef"], eta2)["sZ3"] != s["pl"]["sZ3"]
+    other = ctx.lr_data_terms(s["gZ"], s["gW"].level, s["gW"].scale, s["coef"], eta2)
+    with pytest.raises(H.HEError) as e:
+        ctx.lr_grad_step(s["gZ"], s["gW"], mask, s["coef"], s["eta_n"], c, r, gk, Zk=other)
+    assert e.value.status == 4  # HE_ESCALE
+    good = ctx.lr_data_terms(s["gZ"], s["gW"].level, s["gW"].scale, s["coef"], s["eta_n"])
+    n = len(s["gZ"])
+    with pytest.raises(H.HEError) as e:  # the Z3 group where the Z1 group belongs
+        ctx.lr_grad_step(s["gZ"], s["gW"], mask, s["coef"], s["eta_n"], c, r, gk, Zk=good[:n] + good[:n])
+    assert e.value.status == 3  # HE_ELEVEL
 
 
 def test_training_with_refresh_small(small):
@@ -326,10 +338,13 @@ def test_lr_step_other_losses_bit_exact(small, coef_name, w_decay):
     mm = O.encode(LR.column_mask(P.S, c), pl["s_mask"], P.N)
     oWn, og = LR.lr_grad_step(P, small["okeys"], oZ, oW, mm, coef, eta_n, c, r, plan=pl)
     mask = ctx.pt_load(mm, P.L - 1, pl["s_mask"])
-    for mode in (1, 2):
-        Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, small["gkeys"], mode=mode, w_decay=w_decay)
-        assert np.array_equal(ctx.download(Wn), oWn.data)
-        assert np.array_equal(ctx.download(g), og.data)
+    zk = ctx.lr_data_terms(gZ, gW.level, gW.scale, coef, eta_n, w_decay)  # with Z2 for the hinge row
+    assert len(zk) == (3 if coef[2] != 0 else 2) * len(gZ)
+    for mode, terms in ((1, None), (2, None), (0, zk), (1, zk), (2, zk)):
+        Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, small["gkeys"], mode=mode, w_decay=w_decay,
+                                 Zk=terms)
+        assert np.array_equal(ctx.download(Wn), oWn.data), (mode, terms is not None)
+        assert np.array_equal(ctx.download(g), og.data), (mode, terms is not None)
 
 
 # ------------------------------------------------------------------ feature-major layout
@@ -423,12 +438,14 @@ def test_lr_step_feature_major_bit_exact(small40, loss, w_decay, n):
     oWn, og = LR.lr_grad_step(P, small["okeys"], oZ, oW, mm, coef, eta_n, c, r, plan=pl, layout=LR.FEATURES)
     H = small["H"]
     mask = ctx.pt_load(mm, H.mask_level(P.L, H.LAYOUT_FEATURES), pl["s_mask"])
-    for mode in (0, 1, 2, 2):
+    zk = ctx.lr_data_terms(gZ, gW.level, gW.scale, coef, eta_n, w_decay, H.LAYOUT_FEATURES)
+    assert len(zk) == (3 if coef[2] != 0 else 2) * len(gZ)
+    for mode, terms in ((0, None), (1, None), (2, None), (2, None), (0, zk), (1, zk), (2, zk)):
         Wn, g = ctx.lr_grad_step(gZ, gW, mask, coef, eta_n, c, r, small["gkeys"], mode=mode, w_decay=w_decay,
-                                 layout=H.LAYOUT_FEATURES)
+                                 layout=H.LAYOUT_FEATURES, Zk=terms)
         assert Wn.level == P.L - 4 and Wn.scale == pl["s_g"]
-        assert np.array_equal(ctx.download(Wn), oWn.data), mode
-        assert np.array_equal(ctx.download(g), og.data), mode
+        assert np.array_equal(ctx.download(Wn), oWn.data), (mode, terms is not None)
+        assert np.array_equal(ctx.download(g), og.data), (mode, terms is not None)
     wdec = ctx.decrypt_decode(gW, small["gkeys"]).real.reshape(c, r)[:16, 0]
     gref = LR.lr_gradient_fp64(X, y, wdec, coef, eta_n)
     gd = ctx.decrypt_decode(g, small["gkeys"]).real.reshape(c, r)[:16]
