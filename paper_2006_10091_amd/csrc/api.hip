@@ -215,9 +215,30 @@ he_status rotate_multi_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, 
     u64 *rot = ar.take((size_t)B * 2 * lc);
     if (!rot) return HE_ENOMEM;
     hek::automorph_multi_b(c, B, l + 1, in, is, lc, rot, 2 * lc, lc, gals);
-    he_status st = ks_apply(c, ar, l, B, rot + lc, 2 * lc, nullptr, rot, 2 * lc, lc, 1, out, os, lc, &keys);
+    if (is != 0 || B < 2 || !hek::fused_ok(c)) {
+        he_status st = ks_apply(c, ar, l, B, rot + lc, 2 * lc, nullptr, rot, 2 * lc, lc, 1, out, os, lc, &keys);
+        ar.off = mark;
+        return st;
+    }
+    // one input rotated B ways: its a-part raised to Q_l u P and transformed
+    // once, each rotation's inner product taken from the automorphed digits
+    // (the automorphism commutes with the scaling, ModUp and the NTT, so the
+    // result is the same as B separate key switches), one ModDown per rotation
+    const int nb = l + 1 + c->nk, beta = beta_at(c, l);
+    u64 *y = ar.take((size_t)(l + 1) * N);
+    u64 *ext = ar.take((size_t)beta * nb * N);
+    u64 *acc = ar.take((size_t)B * 2 * nb * N);
+    u64 *conv = ar.take((size_t)B * 2 * (l + 1) * N);
+    if (!y || !ext || !acc || !conv) return HE_ENOMEM;
+    const long long ds = (long long)nb * N, es = (long long)beta * ds, as = 2LL * nb * N, cs = 2LL * (l + 1) * N;
+    hek::intt_from(c, in + lc, 0, y, lc, 1, l, c->t.up_scale + (size_t)l * c->nq * 2);
+    hek::modup_b(c, l, 1, y, lc, ext, es, ds);
+    hek::ntt_batch(c, ext, es, ds, 1, beta, 0, nb, l, +1, nullptr, true);
+    hek::rot_inner_b(c, l, B, ext, ds, in, lc, gals, keys, acc, as);
+    hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
+    hek::ntt_moddown(c, l, B, acc, as, conv, cs, rot, 2 * lc, lc, 1, out, os, lc);
     ar.off = mark;
-    return st;
+    return last_error();
 }
 
 // x + sum_g Rot(x, g) for B ciphertexts at level l (in, batch stride is) as

@@ -162,6 +162,12 @@ struct EntryGal {
 void giant_sum_b(he_ctx *c, int level, int B, const u64 *ext, long long es, long long ds, const u64 *x, long long xs,
                  long long xc, const EntryGal &gals, const EntryKeys &keys, int ng, u64 *acc, long long as, u64 *out,
                  long long os);
+// rotations of one ciphertext sharing its ModUp, inner products: acc
+// [n][2][l+1+nk][N] (stride as) = sum_j sigma_g(D_j) key_g[j] from ext
+// [beta][l+1+nk][N] (NTT form; digit positions from x's a-part, x component
+// stride xc); n <= HE_MAXMULTI
+void rot_inner_b(he_ctx *c, int level, int n, const u64 *ext, long long ds, const u64 *x, long long xc,
+                 const EntryGal &gals, const EntryKeys &keys, u64 *acc, long long as);
 void ks_inner_multi_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const u64 *ext, long long es,
                       long long ds, const EntryKeys &keys, u64 *acc, long long as);
 void automorph_multi_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,

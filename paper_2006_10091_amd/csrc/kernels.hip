@@ -1904,6 +1904,60 @@ __global__ __launch_bounds__(GP_TK *GP_LANES) void giant_perm_kernel(GiantArgs a
     }
 }
 
+// Rotations of one ciphertext sharing its ModUp, the inner-product step: for
+// rotation g < n, position t of Q_l u P and coefficient k (NTT order),
+//   acc[g][comp][t][k] = sum_{j < beta} D_j[t][s_g(k)] key_g[j][comp][t][k]
+// with D_j and s_g as in the hoisted sum above (the digits of the one input
+// raised once; the automorphism commutes with ModUp), each rotation kept
+// apart for its own ModDown.  One thread per (g, t, k); the gathers are
+// global (the steps need not form a group).
+__global__ __launch_bounds__(256) void rot_inner_kernel(GiantArgs a, const PrimeInfo *__restrict__ pinfo)
+{
+    const int ntile = (1 << a.logN) / 256;
+    const int w = blockIdx.x;
+    const int g = w / (ntile * a.nb), r = w % (ntile * a.nb);
+    const int t = r / ntile;
+    const int k = (r % ntile) * 256 + threadIdx.x;
+    const int tp = prime_of(t, a.ell, a.nq);
+    const PrimeInfo p = pinfo[tp];
+    const long long N = 1ll << a.logN;
+    const u64 mask2n = 2 * (u64)N - 1;
+    const u64 e = 2 * (u64)brev_n((unsigned)k, a.logN) + 1;
+    const long long k2 = giant_index(e, a.gals.g[g], mask2n, a.logN);
+    const long long toff = (long long)t << a.logN;
+    const long long np_n = (long long)a.np << a.logN;
+    const int jt = t <= a.ell ? t / a.alpha : -1;
+    const u64 *key = a.keys.k[g] + ((long long)tp << a.logN) + k;
+    u64 *o = a.acc + g * a.as + toff + k;
+    if (p.q < (1ull << 46)) {
+        const double qd = (double)p.q, qinv = 1.0 / qd;
+        double s0 = 0.0, s1 = 0.0;
+        for (int j = 0; j < a.beta; ++j) {
+            const u64 v = j == jt ? a.x[a.xc + toff + k2] : a.ext[j * a.ds + toff + k2];
+            const double dv = d_from_u52(v);
+            s0 += mulmod_lazy_d(dv, d_from_u52(key[(2 * j) * np_n]), qd, qinv);
+            s1 += mulmod_lazy_d(dv, d_from_u52(key[(2 * j + 1) * np_n]), qd, qinv);
+        }
+        o[0] = u52_from_d(reduce_d(s0, qd, qinv));
+        o[(long long)a.nb << a.logN] = u52_from_d(reduce_d(s1, qd, qinv));
+    } else {
+        u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+        for (int j = 0; j < a.beta; ++j) {
+            const u64 v = j == jt ? a.x[a.xc + toff + k2] : a.ext[j * a.ds + toff + k2];
+            const u64 k0 = key[(2 * j) * np_n], k1 = key[(2 * j + 1) * np_n];
+            u64 pl = v * k0, ph = __umul64hi(v, k0);
+            lo0 += pl;
+            hi0 += ph + (lo0 < pl);
+            pl = v * k1;
+            ph = __umul64hi(v, k1);
+            lo1 += pl;
+            hi1 += ph + (lo1 < pl);
+        }
+        o[0] = reduce128(hi0, lo0, p);
+        o[(long long)a.nb << a.logN] = reduce128(hi1, lo1, p);
+    }
+}
+
 // automorph_kernel with a Galois element per entry b (blockIdx.z = 2 b + c)
 __global__ __launch_bounds__(256) void automorph_multi_kernel(const u64 *__restrict__ in, long long ib, long long ic,
                                                               u64 *__restrict__ out, long long ob, long long oc,
@@ -2578,6 +2632,30 @@ void giant_sum_b(he_ctx *c, int level, int B, const u64 *ext, long long es, long
         HE_GIANT(8);
 #undef HE_GIANT
     }
+}
+
+void rot_inner_b(he_ctx *c, int level, int n, const u64 *ext, long long ds, const u64 *x, long long xc,
+                 const EntryGal &gals, const EntryKeys &keys, u64 *acc, long long as)
+{
+    GiantArgs a{};
+    a.ext = ext;
+    a.ds = ds;
+    a.x = x;
+    a.xc = xc;
+    a.keys = keys;
+    a.gals = gals;
+    a.ng = n;
+    a.acc = acc;
+    a.as = as;
+    a.alpha = c->alpha;
+    a.beta = (level + 1 + c->alpha - 1) / c->alpha;
+    a.ell = level;
+    a.nq = c->nq;
+    a.np = c->np;
+    a.nb = level + 1 + c->nk;
+    a.logN = c->logN;
+    const long long nwg = (long long)n * a.nb * (c->N / 256);
+    rot_inner_kernel<<<dim3((unsigned)nwg, 1, 1), 256, 0, c->stream>>>(a, c->t.pinfo);
 }
 
 void automorph_multi_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,
