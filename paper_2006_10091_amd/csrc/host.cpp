@@ -7,6 +7,7 @@
 #include <complex>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <cstring>
 #include <vector>
 
@@ -172,27 +173,17 @@ static const std::vector<std::complex<double>> &fft_twiddles(size_t M, int sign)
     return w;
 }
 
-// In-place radix-2 complex FFT of size M (power of two):
-// A[k] = sum_n a[n] exp(sign * 2 pi i k n / M).
-static void fft(std::vector<std::complex<double>> &a, int sign)
+// Butterflies of the radix-2 stages len = len0 .. len1 (powers of two) on the
+// elements [lo, hi) of d (interleaved re, im), a whole number of len1 blocks.
+static void fft_stages(double *d, const double *wd, size_t lo, size_t hi, size_t len0, size_t len1)
 {
-    const size_t M = a.size();
-    for (size_t i = 1, j = 0; i < M; ++i) {
-        size_t bit = M >> 1;
-        for (; j & bit; bit >>= 1) j ^= bit;
-        j ^= bit;
-        if (i < j) std::swap(a[i], a[j]);
-    }
-    const std::vector<std::complex<double>> &tw = fft_twiddles(M, sign);
     // the complex product written out (the library is built without
     // contraction, so it rounds as std::complex's operator* does for finite
     // operands)
-    double *d = reinterpret_cast<double *>(a.data());
-    const double *wd = reinterpret_cast<const double *>(tw.data());
-    for (size_t len = 2; len <= M; len <<= 1) {
+    for (size_t len = len0; len <= len1; len <<= 1) {
         const size_t half = len / 2;
         const double *w = wd + 2 * (half - 1);
-        for (size_t s = 0; s < M; s += len)
+        for (size_t s = lo; s < hi; s += len)
             for (size_t k = 0; k < half; ++k) {
                 double *x = d + 2 * (s + k), *y = d + 2 * (s + k + half);
                 const double wr = w[2 * k], wi = w[2 * k + 1];
@@ -204,6 +195,37 @@ static void fft(std::vector<std::complex<double>> &a, int sign)
                 y[1] = ui - vi;
             }
     }
+}
+
+// In-place radix-2 complex FFT of size M (power of two):
+// A[k] = sum_n a[n] exp(sign * 2 pi i k n / M).  After the bit reversal the
+// stages up to length M / T act on T contiguous blocks of their own, one per
+// thread; the last log2 T stages run on the calling thread.  Every butterfly
+// is computed as in a one-thread run, so the result does not depend on T.
+static void fft(std::vector<std::complex<double>> &a, int sign, bool reversed = false)
+{
+    const size_t M = a.size();
+    if (!reversed)  // callers that write their input to bit-reversed positions skip this pass
+        for (size_t i = 1, j = 0; i < M; ++i) {
+            size_t bit = M >> 1;
+            for (; j & bit; bit >>= 1) j ^= bit;
+            j ^= bit;
+            if (i < j) std::swap(a[i], a[j]);
+        }
+    const std::vector<std::complex<double>> &tw = fft_twiddles(M, sign);
+    double *d = reinterpret_cast<double *>(a.data());
+    const double *wd = reinterpret_cast<const double *>(tw.data());
+    const size_t T = M >= ((size_t)1 << 14) ? 4 : 1;
+    if (T == 1) {
+        fft_stages(d, wd, 0, M, 2, M);
+        return;
+    }
+    const size_t blk = M / T;
+    std::vector<std::thread> th;
+    for (size_t t = 1; t < T; ++t) th.emplace_back(fft_stages, d, wd, t * blk, (t + 1) * blk, (size_t)2, blk);
+    fft_stages(d, wd, 0, blk, 2, blk);
+    for (auto &x : th) x.join();
+    fft_stages(d, wd, 0, M, 2 * blk, M);
 }
 
 // Powers zeta^i, i < N, of zeta = exp(sign i pi / N), kept per (N, sign).
@@ -225,23 +247,40 @@ static const std::vector<std::complex<double>> &twist(size_t N, int sign)
 // FFTs over omega = zeta^2 with a twist by zeta^i:
 //   encode: m_i = (1/N) Re(zeta^-i sum_k V_k omega^-(k i)), V_k the value at zeta^(2k+1);
 //   decode: value at zeta^(2k+1) = sum_i (m_i zeta^i) omega^(k i).
+// index i of an N-point transform at its bit-reversed position (N = 2^logN)
+static inline size_t brev_idx(size_t i, int logN)
+{
+    return (size_t)(__builtin_bitreverse32((uint32_t)i) >> (32 - logN));
+}
+
+// the working vector of one thread, kept between calls (no fresh page faults)
+static std::vector<std::complex<double>> &fft_buffer(size_t N)
+{
+    thread_local std::vector<std::complex<double>> buf;
+    buf.assign(N, 0.0);
+    return buf;
+}
+
 int encode(int logN, const double *re, const double *im, int n, double scale, i64 *out)
 {
     const size_t N = (size_t)1 << logN, M = 2 * N;
-    std::vector<std::complex<double>> V(N, 0.0);
+    std::vector<std::complex<double>> &V = fft_buffer(N);
     size_t e = 1;
     for (int j = 0; j < n; ++j) {
         std::complex<double> z(re[j], im ? im[j] : 0.0);
-        V[(e - 1) / 2] = z * scale;
-        V[(M - e - 1) / 2] = std::conj(z) * scale;
+        V[brev_idx((e - 1) / 2, logN)] = z * scale;
+        V[brev_idx((M - e - 1) / 2, logN)] = std::conj(z) * scale;
         e = (e * 5) % M;
     }
-    fft(V, -1);
+    fft(V, -1, true);
     const std::vector<std::complex<double>> &tw = twist(N, -1);
     for (size_t i = 0; i < N; ++i) {
         const double v = (V[i].real() * tw[i].real() - V[i].imag() * tw[i].imag()) / (double)N;
-        if (!(std::fabs(v) < 4.611686018427388e18)) return -1;  // 2^62
-        out[i] = (i64)std::llround(v);
+        const double a = std::fabs(v);
+        if (!(a < 4.611686018427388e18)) return -1;  // 2^62
+        // half away from zero: floor(|v| + 0.5) is exact below 2^52; above, v is an integer
+        const double r = a < 4503599627370496.0 ? std::floor(a + 0.5) : a;
+        out[i] = (i64)(v < 0 ? -r : r);
     }
     return 0;
 }
@@ -250,9 +289,9 @@ void decode(int logN, const double *m, double scale, int n, double *re, double *
 {
     const size_t N = (size_t)1 << logN, M = 2 * N;
     const std::vector<std::complex<double>> &tw = twist(N, +1);
-    std::vector<std::complex<double>> A(N);
-    for (size_t i = 0; i < N; ++i) A[i] = m[i] * tw[i];
-    fft(A, +1);
+    std::vector<std::complex<double>> &A = fft_buffer(N);
+    for (size_t i = 0; i < N; ++i) A[brev_idx(i, logN)] = m[i] * tw[i];
+    fft(A, +1, true);
     size_t e = 1;
     for (int j = 0; j < n; ++j) {
         const size_t k = (e - 1) / 2;
