@@ -1657,10 +1657,30 @@ he_status he_rotate_many(he_ctx *c, const he_ct *x, int n, const int *steps, int
         key[s] = find_rot_key(k, gal[s]);
         if (!key[s]) return HE_EKEY;
     }
-    TRY(ensure_ws(c, rotate_scratch(c, l, n) * 8 + 4096));
-    for (int s = 0; s < n_steps; ++s) {
-        Arena ar = arena(c);
-        TRY(rotate_apply(c, ar, l, n, x[0].data, xs, gal[s], key[s], out[s].data, (long long)n_steps * os));
+    if (n_steps >= 2 && hek::fused_ok(c)) {
+        // each input rotated every way at once, sharing its ModUp (bit-identical
+        // to one rotation per step), in groups of at most HE_MAXMULTI steps
+        const int G = std::min(n_steps, hek::HE_MAXMULTI);
+        TRY(ensure_ws(c, rotate_scratch(c, l, G) * 8 + 4096));
+        for (int i = 0; i < n; ++i)
+            for (int s0 = 0; s0 < n_steps; s0 += G) {
+                const int g = std::min(G, n_steps - s0);
+                hek::EntryGal eg;
+                hek::EntryKeys ek;
+                for (int s = 0; s < g; ++s) {
+                    eg.g[s] = gal[s0 + s];
+                    ek.k[s] = key[s0 + s];
+                }
+                Arena ar = arena(c);
+                TRY(rotate_multi_apply(c, ar, l, g, x[0].data + (long long)i * xs, 0, eg, ek,
+                                       out[(long long)i * n_steps + s0].data, os));
+            }
+    } else {
+        TRY(ensure_ws(c, rotate_scratch(c, l, n) * 8 + 4096));
+        for (int s = 0; s < n_steps; ++s) {
+            Arena ar = arena(c);
+            TRY(rotate_apply(c, ar, l, n, x[0].data, xs, gal[s], key[s], out[s].data, (long long)n_steps * os));
+        }
     }
     for (int i = 0; i < m; ++i) {
         out[i].level = l;
