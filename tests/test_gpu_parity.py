@@ -584,6 +584,14 @@ def test_small_ring_unfused_path_bit_exact():
     want = O.rotate(P, O.rescale(P, O.mul(P, O.CT(xd, P.L, 1.0), O.CT(yd, P.L, 1.0), okeys)), 2, okeys)
     got = ctx.batch_mul_rotate([x], [y], [2], gkeys, mode=1)[0]
     assert np.array_equal(ctx.download(got), want.data)
+    # the hoisted rotation sum and the multi-step rotations on the unfused key switch
+    hs = [1, 2, 4]
+    xs = ctx.ct_block(1, P.L)
+    ctx.upload(xd, P.L, 1.0, out=xs[0])
+    got = ctx.rotate_sum(xs, hs, gkeys)[0]
+    assert np.array_equal(ctx.download(got), O.rotate_sum_hoisted(P, O.CT(xd, P.L, 1.0), hs, okeys).data)
+    for s_, o in zip(hs, ctx.rotate_many(xs, hs, gkeys)):
+        assert np.array_equal(ctx.download(o), O.rotate(P, O.CT(xd, P.L, 1.0), s_, okeys).data), s_
     X, yl = synth.small_data(n=r)
     blocks, c2, r2 = LR.pack_blocks(X, yl, P.S)
     assert (c2, r2) == (c, r)
