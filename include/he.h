@@ -377,9 +377,12 @@ he_status he_rotate_sum(he_ctx *ctx, const he_ct *x, int n, const int *steps, in
  *   out[i * n_steps + s] = Rot(x[i], steps[s]).
  * x[0..n): one level and scale, one uniform stride apart; out: caller memory
  * for n * n_steps ciphertexts at that level, one allocation with a uniform
- * stride in that order, distinct from x.  Each step runs as one batched
- * rotation of all n ciphertexts.  Errors before any launch: HE_EINVAL,
- * HE_ELEVEL, HE_EKEY (a rotation key absent).
+ * stride in that order, distinct from x.  With two or more steps each input
+ * is raised to Q u P once and rotated every way from there (its digits
+ * automorphed per step, one ModDown per output; the same ciphertexts as one
+ * key switch per rotation); with one step all n ciphertexts rotate as one
+ * batch.  Errors before any launch: HE_EINVAL, HE_ELEVEL, HE_EKEY (a rotation
+ * key absent).
  */
 he_status he_rotate_many(he_ctx *ctx, const he_ct *x, int n, const int *steps, int n_steps, const he_keys *keys,
                          he_ct *out);

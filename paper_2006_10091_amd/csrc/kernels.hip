@@ -1265,8 +1265,8 @@ __global__ __launch_bounds__(256) void baby_sum_kernel(BabyArgs a, const PrimeIn
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const u64 *zp = b == 0 ? a.z + blk * a.zb + off : a.zr + blk * a.zrb + (b - 1) * a.zrs + off;
-                z0[b] = zp[0];
-                z1[b] = zp[b == 0 ? a.zc : a.zrc];
+                z0[b] = __builtin_nontemporal_load(zp);  // streamed once per step: keep W's rows in cache
+                z1[b] = __builtin_nontemporal_load(zp + (b == 0 ? a.zc : a.zrc));
             }
             double d0 = 0.0, d1 = 0.0, d2 = 0.0;
 #pragma unroll

@@ -155,6 +155,32 @@ def test_rotate_sum_hoisted_bit_exact(small, steps):
         ctx.rotate_sum(xs, steps, gkeys, outs=xs)
 
 
+def test_rotate_sum_and_data_terms_errors(small, small_step):
+    """Errors before any launch: he_rotate_sum with more than 32 steps, a
+    step without a key, and no steps; he_lr_data_terms with an unknown layout
+    or weights too low to plan."""
+    ctx, P, gk, H, s = small["ctx"], small["P"], small["gkeys"], small["H"], small_step
+    xs = ctx.ct_block(2, 3)
+    for i in range(2):
+        d = np.stack([synth.uniform_residues(71 + 2 * i, P.q[:4], P.N), synth.uniform_residues(72 + 2 * i, P.q[:4], P.N)])
+        ctx.upload(d, 3, 1.0, out=xs[i])
+    with pytest.raises(H.HEError) as e:
+        ctx.rotate_sum(xs, [1] * 33, gk)
+    assert e.value.status == 1  # HE_EINVAL
+    with pytest.raises(H.HEError) as e:
+        ctx.rotate_sum(xs, [1, 17], gk)
+    assert e.value.status == 5  # HE_EKEY
+    with pytest.raises(H.HEError) as e:
+        ctx.rotate_sum(xs, [], gk)
+    assert e.value.status == 1
+    with pytest.raises(H.HEError) as e:
+        ctx.lr_data_terms(s["gZ"], s["gW"].level, s["gW"].scale, s["coef"], s["eta_n"], layout=7)
+    assert e.value.status == 1
+    with pytest.raises(H.HEError) as e:
+        ctx.lr_data_terms(s["gZ"], 3, s["gW"].scale, s["coef"], s["eta_n"])
+    assert e.value.status == 3  # HE_ELEVEL: fewer than 4 levels
+
+
 def test_rescale_in_place(small):
     ctx, P = small["ctx"], small["P"]
     xd, x = random_ct(ctx, P, P.L, 41)
