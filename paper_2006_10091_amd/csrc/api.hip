@@ -139,10 +139,52 @@ he_status relin_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d3, long lo
     return ks_apply(c, ar, l, B, d3 + 2 * lc, d3s, rlk, d3, d3s, lc, 2, out, os, lc);
 }
 
+// relinearise and rescale B degree-2 ciphertexts d3 [B][3][l+1][N] (batch
+// stride d3s) -> out [B][2][l][N] (batch stride os): the key switch's ModDown
+// and the rescale by q_l share one forward transform (the same integers as
+// relin_apply then rescale_apply); unfused contexts take those two
+he_status rescale_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long long is, u64 *out, long long os,
+                        int ncomp = 2, const i64 *kmul = nullptr, long long ics = 0);
+he_status relin_rescale_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *d3, long long d3s, const u64 *rlk,
+                              u64 *out, long long os)
+{
+    const size_t N = c->N;
+    const long long lc = (long long)(l + 1) * N;
+    const size_t mark = ar.off;
+    if (!hek::fused_ok(c)) {
+        u64 *u0 = ar.take((size_t)B * 2 * lc);
+        if (!u0) return HE_ENOMEM;
+        he_status st = relin_apply(c, ar, l, B, d3, d3s, rlk, u0, 2 * lc);
+        if (st == HE_OK) st = rescale_apply(c, ar, l, B, u0, 2 * lc, out, os, 2, nullptr, 0);
+        ar.off = mark;
+        return st;
+    }
+    const int nb = l + 1 + c->nk, beta = beta_at(c, l);
+    u64 *y = ar.take((size_t)B * (l + 1) * N);
+    u64 *ext = ar.take((size_t)B * beta * nb * N);
+    u64 *acc = ar.take((size_t)B * 2 * nb * N);
+    u64 *tmp = ar.take((size_t)B * 2 * (l + 1) * N);
+    u64 *tb = ar.take((size_t)B * 2 * N), *ta = ar.take((size_t)B * 2 * N), *last = ar.take((size_t)B * 2 * N);
+    if (!y || !ext || !acc || !tmp || !tb || !ta || !last) return HE_ENOMEM;
+    const long long ys = lc, ds = (long long)nb * N, es = (long long)beta * ds, as = 2LL * nb * N;
+    const u64 *d2 = d3 + 2 * lc;
+    hek::intt_from(c, d2, d3s, y, ys, B, l, c->t.up_scale + (size_t)l * c->nq * 2);
+    hek::modup_b(c, l, B, y, ys, ext, es, ds);
+    hek::ks_ntt_inner(c, l, B, d2, d3s, ext, es, ds, rlk, nullptr, acc, as);
+    hek::ntt_batch(c, acc, as, ds, B, 2, l + 1, c->nk, l, -1, c->t.dn_scale, false);
+    // limb l of base and acc in coefficient form, then the ModDown output's limb l
+    hek::intt_last(c, l, B, 2, d3, d3s, lc, tb, nullptr);
+    hek::intt_last(c, l, B, 2, acc, as, ds, ta, nullptr);
+    hek::md_last_b(c, l, B, tb, ta, acc, as, ds, last);
+    hek::ntt_moddown_rescale(c, l, B, acc, as, last, d3, d3s, lc, tmp, out, os);
+    ar.off = mark;
+    return last_error();
+}
+
 // rescale B ciphertexts of ncomp components at level l -> level l-1 (each
 // component on its own; out may equal in only for B == 1)
 he_status rescale_apply(he_ctx *c, Arena &ar, int l, int B, const u64 *in, long long is, u64 *out, long long os,
-                        int ncomp = 2, const i64 *kmul = nullptr, long long ics = 0)
+                        int ncomp, const i64 *kmul, long long ics)
 {
     // out = RS(k in) with k = *kmul when given; in's component stride is ics
     // (default (l+1) N: a ciphertext at level l, or a higher-level one read on
@@ -606,8 +648,7 @@ he_status mul_relin_rescale(he_ctx *c, Arena &ar, StepBufs &s, int l, int nb, co
 {
     const long long N = c->N, lc = (l + 1) * N;
     hek::tensor_b(c, l, nb, x, xb, xc, y, yb, yc, s.T3, 3 * lc, lc);
-    TRY(relin_apply(c, ar, l, nb, s.T3, 3 * lc, rlk, s.U0, 2 * lc));
-    return rescale_apply(c, ar, l, nb, s.U0, 2 * lc, out, 2LL * l * N);
+    return relin_rescale_apply(c, ar, l, nb, s.T3, 3 * lc, rlk, out, 2LL * l * N);
 }
 
 // ct x ct -> rescale, not relinearised, for nb entries at level l: output
@@ -654,8 +695,7 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
         const long long lc = (l + 1) * N;
         hek::baby_sum_b(c, l, nb, bd.n_baby, zp, zbs, zc, bd.zr + b0 * bd.zrb, bd.zrb, bd.zrs, bd.zrc, W->data, wc,
                         s.Wr, 2 * lc, lc, s.T3, 3 * lc, lc);
-        TRY(relin_apply(c, ar, l, nb, s.T3, 3 * lc, keys->rlk, s.U0, 2 * lc));
-        TRY(rescale_apply(c, ar, l, nb, s.U0, 2 * lc, s.U, 2 * u1));
+        TRY(relin_rescale_apply(c, ar, l, nb, s.T3, 3 * lc, keys->rlk, s.U, 2 * u1));
         t0 = bd.n_baby;
     } else {
         // D1: u = RS(relin(Z (x) W)), level l-1
@@ -726,8 +766,7 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
         const long long lc = (l + 1) * N;
         hek::baby_sum_b(c, l, nb, bd.n_baby, zp, zbs, zc, bd.zr + b0 * bd.zrb, bd.zrb, bd.zrs, bd.zrc, W->data, wc,
                         s.Wr, 2 * lc, lc, s.T3, 3 * lc, lc);
-        TRY(relin_apply(c, ar, l, nb, s.T3, 3 * lc, keys->rlk, s.U0, 2 * lc));
-        TRY(rescale_apply(c, ar, l, nb, s.U0, 2 * lc, s.U, 2 * u1));
+        TRY(relin_rescale_apply(c, ar, l, nb, s.T3, 3 * lc, keys->rlk, s.U, 2 * u1));
         t0 = bd.n_baby;
     } else {
         // D1: u = RS(relin(Z (x) W)), level l-1

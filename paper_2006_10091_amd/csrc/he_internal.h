@@ -162,6 +162,14 @@ struct EntryGal {
 void giant_sum_b(he_ctx *c, int level, int B, const u64 *ext, long long es, long long ds, const u64 *x, long long xs,
                  long long xc, const EntryGal &gals, const EntryKeys &keys, int ng, u64 *acc, long long as, u64 *out,
                  long long os);
+// the limb at q_l of a ModDown's output in coefficient form (from base's and
+// acc's limbs l in coefficient form, [b][comp][N], and acc's special limbs)
+void md_last_b(he_ctx *c, int level, int B, const u64 *bl, const u64 *al, const u64 *acc, long long as,
+               long long acs, u64 *last);
+// ModDown and the rescale by q_l after it in one forward transform:
+// out [B][2][l][N] = RS(base + ModDown(acc)), last from md_last_b
+void ntt_moddown_rescale(he_ctx *c, int level, int B, const u64 *acc, long long as, const u64 *last,
+                         const u64 *base, long long bs, long long bcs, u64 *tmp, u64 *out, long long os);
 // rotations of one ciphertext sharing its ModUp, inner products: acc
 // [n][2][l+1+nk][N] (stride as) = sum_j sigma_g(D_j) key_g[j] from ext
 // [beta][l+1+nk][N] (NTT form; digit positions from x's a-part, x component

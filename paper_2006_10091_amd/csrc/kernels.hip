@@ -481,7 +481,7 @@ __device__ __forceinline__ u64 reduce4q(u64 v, u64 q, u64 q2)
 //                                  limb's prime (ModDown: the special primes; rescale: q_l)
 //   pass B (inverse) PRO_SRC     : read the limb from another buffer (out-of-place)
 //   pass B epilogue  EPI_FINISH  : store base + (acc - x) P^{-1} instead of x
-enum { PRO_NONE = 0, PRO_MODDOWN = 2, PRO_SRC = 3 };
+enum { PRO_NONE = 0, PRO_MODDOWN = 2, PRO_SRC = 3, PRO_MDRS = 5 };
 enum { EPI_NONE = 0, EPI_FINISH = 1 };
 
 struct Fuse {
@@ -508,6 +508,9 @@ struct Fuse {
     i64 kmul;
     int has_kacc;        // finish: multiply acc by kacc (mod each prime) as it is read
     i64 kacc;
+    const u64 *post;     // finish: final multiplier per target position (+ Shoup), or null
+    const u64 *last;     // PRO_MDRS: the ModDown output's limb at q_l in coefficient form, [b][comp][N]
+    int lpos;            // PRO_MDRS: l, the position of q_l
 };
 
 // k mod p for a signed 64-bit integer k
@@ -664,9 +667,30 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
     const u64 *Ws = tws + ((long long)pidx << LOGN);
     u64 *line = lds + cc * S::PADDED;
     ConvConst cv;
-    if (PRO == PRO_MODDOWN) conv_setup(a, f, pinfo, pidx, cv);
+    constexpr bool CONV = PRO == PRO_MODDOWN || PRO == PRO_MDRS;
+    if (CONV) conv_setup(a, f, pinfo, pidx, cv);
+    // PRO_MDRS (a ModDown and the rescale by q_l after it, in one transform):
+    // the input is the ModDown conversion plus [P] times the rescale's centred
+    // conversion of the ModDown output's last limb, conv + P x; both are
+    // linear before the forward transform.  cv.k / cv.kd hold [P] here.
+    const u64 *lastp = nullptr;
+    u64 lq = 0;
+    if (PRO == PRO_MDRS) {
+        lastp = f.last + ((long long)((int)blockIdx.z + a.zoff) << LOGN);
+        lq = pinfo[f.lpos].q;
+    }
+    auto mdrs_d = [&](double conv, long long off, double qd, double qinv) -> double {
+        const u64 v = lastp[off];
+        const double x = (double)v - (v > (lq >> 1) ? (double)lq : 0.0);  // centred, |x| < q_l / 2
+        return reduce_d(conv + mulmod_lazy_d(x, cv.kd, qd, qinv), qd, qinv);
+    };
     auto load = [&](int row) -> u64 {
         const long long off = (long long)row * N2 + col;
+        if (PRO == PRO_MDRS) {
+            const u64 v = lastp[off];
+            const u64 xm = v > (lq >> 1) ? sub_mod(reduce64(v, p), reduce64(lq, p), q) : reduce64(v, p);
+            return add_mod(conv_value(cv, off, p, LOGN), mul_shoup(xm, cv.k, cv.ks, q), q);
+        }
         if (PRO == PRO_MODDOWN) return conv_value(cv, off, p, LOGN);
         return limb[off];
     };
@@ -676,9 +700,13 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
         double *dl = reinterpret_cast<double *>(line);
         double d[S::E];
         if (!INV && q < (1ull << 46)) {  // signed lazy: the row pass reads a signed intermediate
-            if (PRO == PRO_MODDOWN && cv.fp) {
+            if (CONV && cv.fp) {
                 conv_column_d<S::E>(cv, (long long)tau * N2 + col, (long long)S::T * N2, d, qd, qinv, LOGN);
-            } else if (PRO == PRO_MODDOWN) {
+                if (PRO == PRO_MDRS) {
+#pragma unroll
+                    for (int k = 0; k < S::E; ++k) d[k] = mdrs_d(d[k], (long long)(tau + S::T * k) * N2 + col, qd, qinv);
+                }
+            } else if (CONV) {
 #pragma unroll
                 for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(load(tau + S::T * k));
             } else {
@@ -793,6 +821,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
             u64 r = mul_shoup(sub_mod(av, x, q), f.pinv[2 * pos], f.pinv[2 * pos + 1], q);
             if (c < f.nbase) r = add_mod(r, f.base[b * f.bs + c * f.bcs + roff + e], q);
             if (f.add) r = add_mod(r, f.add[b * f.ads + c * f.adcs + roff + e], q);
+            if (f.post) r = mul_shoup(r, f.post[2 * pos], f.post[2 * pos + 1], q);
             f.out[b * f.os + c * f.ocs + roff + e] = r;
         } else {
             __builtin_nontemporal_store(x, row + e);
@@ -828,6 +857,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
             if (FIN) {
                 // base (+ addend) + (acc - x) P^{-1}: the lazy product is in (-q, 2q), the sum in (-q, 4q)
                 const double pinv = d_from_u52(f.pinv[2 * pos]);
+                const double postd = f.post ? d_from_u52(f.post[2 * pos]) : 0.0;
                 u64 *op = f.out + b * f.os + c * f.ocs + roff + tau;
                 const double ka = f.has_kacc ? d_from_u52(int_mod(f.kacc, p)) : 0.0;
 #pragma unroll
@@ -836,7 +866,10 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
                     // kacc acc is a lazy product in (-q, 2q); minus x it stays within (-2q, 2q)
                     const double av = f.has_kacc ? mulmod_lazy_d(d_from_u52(fa[k]), ka, qd, qinv) : d_from_u52(fa[k]);
                     const double r = mulmod_lazy_d(av - x, pinv, qd, qinv) + d_from_u52(fb[k]);
-                    op[S::T * k] = u52_from_d(reduce_d(r, qd, qinv));
+                    if (f.post)
+                        op[S::T * k] = u52_from_d(reduce_d(mulmod_lazy_d(r, postd, qd, qinv), qd, qinv));
+                    else
+                        op[S::T * k] = u52_from_d(reduce_d(r, qd, qinv));
                 }
             } else {
 #pragma unroll
@@ -1958,6 +1991,39 @@ __global__ __launch_bounds__(256) void rot_inner_kernel(GiantArgs a, const Prime
     }
 }
 
+// The limb at q_l of a ModDown's output, in coefficient form, for the rescale
+// by q_l that follows: last = base + (acc - conv) P^{-1} mod q_l from the
+// coefficient forms of base's and acc's limbs l (bl, al: [b][comp][N]) and the
+// special limbs of acc (coefficient form, scaled as the ModDown reads them),
+// conv their centred conversion to q_l -- the same integers as the inverse
+// transform of the ModDown output's limb l.
+__global__ __launch_bounds__(256) void md_last_kernel(const u64 *__restrict__ bl, const u64 *__restrict__ al,
+                                                      const u64 *__restrict__ acc, long long as, long long acs,
+                                                      u64 *__restrict__ last, const PrimeInfo *__restrict__ pinfo,
+                                                      const u64 *__restrict__ dn_conv, const u64 *__restrict__ dn_p,
+                                                      const u64 *__restrict__ dn_pinv, int level, int nq, int nk,
+                                                      int logN)
+{
+    const int bc = blockIdx.y;
+    const int b = bc >> 1, c = bc & 1;
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    const PrimeInfo p = pinfo[level];
+    const u64 *src = acc + b * as + c * acs + ((long long)(level + 1) << logN) + k;
+    u64 lo = 0, hi = 0, cnt = 0;
+    for (int i = 0; i < nk; ++i) {
+        const u64 v = src[(long long)i << logN];
+        cnt += v > (pinfo[nq + i].q >> 1);
+        const u64 ci = dn_conv[((long long)i * nq + level) * 2];
+        const u64 pl = v * ci, ph = __umul64hi(v, ci);
+        lo += pl;
+        hi += ph + (lo < pl);
+    }
+    const u64 conv = sub_mod(reduce128(hi, lo, p), mul_shoup(cnt, dn_p[2 * level], dn_p[2 * level + 1], p.q), p.q);
+    const long long o = ((long long)bc << logN) + k;
+    last[o] = add_mod(bl[o], mul_shoup(sub_mod(al[o], conv, p.q), dn_pinv[2 * level], dn_pinv[2 * level + 1], p.q),
+                      p.q);
+}
+
 // automorph_kernel with a Galois element per entry b (blockIdx.z = 2 b + c)
 __global__ __launch_bounds__(256) void automorph_multi_kernel(const u64 *__restrict__ in, long long ib, long long ic,
                                                               u64 *__restrict__ out, long long ob, long long oc,
@@ -2171,6 +2237,9 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
             if (pro == PRO_MODDOWN)
                 ntt_cols_t<LOGN, false, PRO_MODDOWN><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh,
                                                                                  nullptr, c->t.psi_d, f);
+            else if (pro == PRO_MDRS)
+                ntt_cols_t<LOGN, false, PRO_MDRS><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh,
+                                                                              nullptr, c->t.psi_d, f);
             else
                 ntt_cols_t<LOGN, false, PRO_NONE><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh, nullptr,
                                                                               c->t.psi_d, f);
@@ -2656,6 +2725,53 @@ void rot_inner_b(he_ctx *c, int level, int n, const u64 *ext, long long ds, cons
     a.logN = c->logN;
     const long long nwg = (long long)n * a.nb * (c->N / 256);
     rot_inner_kernel<<<dim3((unsigned)nwg, 1, 1), 256, 0, c->stream>>>(a, c->t.pinfo);
+}
+
+void md_last_b(he_ctx *c, int level, int B, const u64 *bl, const u64 *al, const u64 *acc, long long as,
+               long long acs, u64 *last)
+{
+    dim3 g(c->N / 256, B * 2, 1);
+    md_last_kernel<<<g, 256, 0, c->stream>>>(bl, al, acc, as, acs, last, c->t.pinfo, c->t.dn_conv, c->t.dn_p,
+                                            c->t.dn_pinv, level, c->nq, c->nk, c->logN);
+}
+
+// ModDown of acc by P and the rescale by q_l after it as one forward
+// transform: out = (base + (acc - Y) P^{-1}) q_l^{-1} on positions 0..l-1,
+// Y the transform of conv_P(acc) + [P] conv_{q_l}(last) (PRO_MDRS); tmp
+// [B][2][l][N] holds the transform's intermediate.
+void ntt_moddown_rescale(he_ctx *c, int level, int B, const u64 *acc, long long as, const u64 *last,
+                         const u64 *base, long long bs, long long bcs, u64 *tmp, u64 *out, long long os)
+{
+    const long long N = c->N, nb = level + 1 + c->nk;
+    Fuse f{};
+    f.src = acc;
+    f.sbs = as;
+    f.scs = nb * N;
+    f.soff = level + 1;
+    f.nsrc = c->nk;
+    f.sp0 = c->nq;
+    f.cvt = c->t.dn_conv;
+    f.cnt = c->t.dn_p;
+    f.cvtd = c->t.dn_convd;
+    f.cntd = c->t.dn_pd;
+    f.nk = c->nk;
+    f.np = c->np;
+    f.acc = acc;
+    f.as = as;
+    f.acs = nb * N;
+    f.base = base;
+    f.bs = bs;
+    f.bcs = bcs;
+    f.nbase = 2;
+    f.out = out;
+    f.os = os;
+    f.ocs = (long long)level * N;
+    f.pinv = c->t.dn_pinv;
+    f.post = c->t.rs_qinv + (long long)level * c->nq * 2;
+    f.last = last;
+    f.lpos = level;
+    NttArgs a = make_args(c, tmp, 2LL * level * N, (long long)level * N, 2, 0, level - 1, false);
+    ntt_launch(c, a, B, level, +1, nullptr, PRO_MDRS, EPI_FINISH, &f);
 }
 
 void automorph_multi_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long long ic, u64 *out, long long ob,
