@@ -1819,13 +1819,15 @@ __global__ __launch_bounds__(256) void giant_gather_kernel(GiantArgs a, const Pr
 
 // The same sum when every s_g keeps k inside its aligned tile of 64
 // coefficients (g = 1 mod 2^(logN - 5)): the 64 lanes of a wave hold one tile,
-// each lane loads its own coefficient of every digit once (coalesced) and takes
-// D_j[s_g(k)] from the lane holding it (ds_bpermute, two 32-bit halves).  A
-// workgroup takes one position t and one tile for up to 4 * EPT entries (wave
-// w serves entries w, w + 4, ..); the tile's keys are staged in LDS a chunk of
-// rotations at a time and read there by every entry.  FP: positions whose prime
-// is below 2^46, lazy FP64 products reduced once per rotation; otherwise exact
-// 128-bit sums reduced once per chunk (at most 40 products below 2^120 each).
+// each lane loads its own coefficient of every digit once (coalesced).  A
+// workgroup takes one position t and one tile for the entries (wave w serves
+// entries w, w + 4, ..); the tile's keys are staged in LDS a chunk of rotations
+// at a time and read there by every entry.  FP (positions whose prime is below
+// 2^46): key_g[j][k] is staged at lane m = s_g(k), so lane m forms
+// sum_j D_j[m] key_g[j][k] from its own digits and lane k pulls that partial
+// sum (ds_bpermute, two 32-bit halves); lazy FP64 products, reduced once per
+// rotation.  Otherwise lane k pulls every D_j[s_g(k)] and keeps exact 128-bit
+// sums reduced once per chunk (at most 40 products below 2^120 each).
 constexpr int GP_TK = 64, GP_LANES = 4, GP_MAXB = 8;
 constexpr int GP_LDS = 40 * 1024;  // bytes of staged keys per workgroup
 
@@ -1863,7 +1865,13 @@ __global__ __launch_bounds__(GP_TK *GP_LANES) void giant_perm_kernel(GiantArgs a
         for (int v = threadIdx.x; v < gn * per; v += blockDim.x) {
             const int gi = v / per, r = v % per, jc = r / GP_TK, kk = r % GP_TK;
             const u64 kv = a.keys.k[g0 + gi][jc * np_n + ((long long)tp << a.logN) + (k - L) + kk];
-            keys_lds[v] = FP ? (u64)__double_as_longlong(d_from_u52(kv)) : kv;
+            if (FP) {  // stored at the lane whose digits coefficient kk takes
+                const u64 ek = 2 * (u64)brev_n((unsigned)((k - L) + kk), a.logN) + 1;
+                const int m = (int)(giant_index(ek, a.gals.g[g0 + gi], mask2n, a.logN) & (GP_TK - 1));
+                keys_lds[v - kk + m] = (u64)__double_as_longlong(d_from_u52(kv));
+            } else {
+                keys_lds[v] = kv;
+            }
         }
         __syncthreads();
         for (int b = lane; b < a.nent; b += GP_LANES) {  // uniform per wave
@@ -1890,20 +1898,33 @@ __global__ __launch_bounds__(GP_TK *GP_LANES) void giant_perm_kernel(GiantArgs a
             for (int gi = 0; gi < gn; ++gi) {
                 const int src = (int)(giant_index(e, a.gals.g[g0 + gi], mask2n, a.logN) & (GP_TK - 1));
                 const u64 *kl = keys_lds + gi * per + L;
-                u64 v[BETA], k0[BETA], k1[BETA];
+                if constexpr (FP) {
+                    // this lane's own digits times the keys staged at it: the
+                    // rotation's partial sum for the lane that takes these
+                    // digits, which pulls it (2 pulls per component instead of
+                    // 2 per digit); every sum is an exact integer below 2^52
+                    double p0 = 0.0, p1 = 0.0;
 #pragma unroll
-                for (int j = 0; j < BETA; ++j) {
-                    v[j] = lane_take(d[j], src);
-                    k0[j] = kl[(2 * j) * GP_TK];
-                    k1[j] = kl[(2 * j + 1) * GP_TK];
-                }
+                    for (int j = 0; j < BETA; ++j) {
+                        const double dv = __longlong_as_double((long long)d[j]);
+                        p0 += mulmod_lazy_d(dv, __longlong_as_double((long long)kl[(2 * j) * GP_TK]), qd, qinv);
+                        p1 += mulmod_lazy_d(dv, __longlong_as_double((long long)kl[(2 * j + 1) * GP_TK]), qd, qinv);
+                    }
+                    s0 += __longlong_as_double((long long)lane_take((u64)__double_as_longlong(p0), src));
+                    s1 += __longlong_as_double((long long)lane_take((u64)__double_as_longlong(p1), src));
+                    // back into (-q, 2q): the sum holds at most 8 more lazy products per rotation
+                    s0 = __fma_rn(-floor(s0 * qinv), qd, s0);
+                    s1 = __fma_rn(-floor(s1 * qinv), qd, s1);
+                } else {
+                    u64 v[BETA], k0[BETA], k1[BETA];
 #pragma unroll
-                for (int j = 0; j < BETA; ++j) {
-                    if (FP) {
-                        const double dv = __longlong_as_double((long long)v[j]);
-                        s0 += mulmod_lazy_d(dv, __longlong_as_double((long long)k0[j]), qd, qinv);
-                        s1 += mulmod_lazy_d(dv, __longlong_as_double((long long)k1[j]), qd, qinv);
-                    } else {
+                    for (int j = 0; j < BETA; ++j) {
+                        v[j] = lane_take(d[j], src);
+                        k0[j] = kl[(2 * j) * GP_TK];
+                        k1[j] = kl[(2 * j + 1) * GP_TK];
+                    }
+#pragma unroll
+                    for (int j = 0; j < BETA; ++j) {
                         u64 pl = v[j] * k0[j], ph = __umul64hi(v[j], k0[j]);
                         lo0 += pl;
                         hi0 += ph + (lo0 < pl);
@@ -1912,10 +1933,6 @@ __global__ __launch_bounds__(GP_TK *GP_LANES) void giant_perm_kernel(GiantArgs a
                         lo1 += pl;
                         hi1 += ph + (lo1 < pl);
                     }
-                }
-                if (FP) {  // back into (-q, 2q): the sum holds at most 8 more lazy products per rotation
-                    s0 = __fma_rn(-floor(s0 * qinv), qd, s0);
-                    s1 = __fma_rn(-floor(s1 * qinv), qd, s1);
                 }
             }
             // FP: one full reduction; 128-bit sums of at most 40 products below 2^120 per chunk: reduced once
