@@ -1825,9 +1825,10 @@ __global__ __launch_bounds__(256) void giant_gather_kernel(GiantArgs a, const Pr
 // at a time and read there by every entry.  FP (positions whose prime is below
 // 2^46): key_g[j][k] is staged at lane m = s_g(k), so lane m forms
 // sum_j D_j[m] key_g[j][k] from its own digits and lane k pulls that partial
-// sum (ds_bpermute, two 32-bit halves); lazy FP64 products, reduced once per
-// rotation.  Otherwise lane k pulls every D_j[s_g(k)] and keeps exact 128-bit
-// sums reduced once per chunk (at most 40 products below 2^120 each).
+// sum (ds_bpermute, two 32-bit halves); lazy FP64 products, the running sum
+// reduced every 48 / beta rotations.  Otherwise lane k pulls every
+// D_j[s_g(k)] and keeps exact 128-bit sums reduced once per chunk (at most 40
+// products below 2^120 each), for two entries per pass.
 constexpr int GP_TK = 64, GP_LANES = 4, GP_MAXB = 8;
 constexpr int GP_LDS = 40 * 1024;  // bytes of staged keys per workgroup
 
@@ -1874,27 +1875,42 @@ __global__ __launch_bounds__(GP_TK *GP_LANES) void giant_perm_kernel(GiantArgs a
             }
         }
         __syncthreads();
-        for (int b = lane; b < a.nent; b += GP_LANES) {  // uniform per wave
-            u64 d[BETA];
+        // 60-bit positions: two entries per pass (b and b + GP_LANES, uniform
+        // per wave), sharing the staged keys' reads and the source lane (the
+        // FP64 positions measured slower that way)
+        constexpr int GP_EP = FP ? 1 : 2;
+        for (int b = lane; b < a.nent; b += GP_EP * GP_LANES) {
+            const int ne = GP_EP == 2 && b + GP_LANES < a.nent ? 2 : 1;
+            u64 d[GP_EP][BETA];
 #pragma unroll
-            for (int j = 0; j < BETA; ++j)
-                d[j] = j == jt ? a.x[b * a.xs + a.xc + toff + k] : a.ext[b * a.es + j * a.ds + toff + k];
-            if (FP) {
+            for (int i = 0; i < GP_EP; ++i) {
+                const int bi = b + i * GP_LANES;
 #pragma unroll
-                for (int j = 0; j < BETA; ++j) d[j] = (u64)__double_as_longlong(d_from_u52(d[j]));
-            }
-            u64 *o = a.acc + b * a.as + toff + k;
-            double s0 = 0.0, s1 = 0.0;
-            u64 lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
-            if (g0 > 0) {  // the running sums of the earlier chunks
-                if (FP) {
-                    s0 = d_from_u52(o[0]);
-                    s1 = d_from_u52(o[comp1]);
-                } else {
-                    lo0 = o[0];
-                    lo1 = o[comp1];
+                for (int j = 0; j < BETA; ++j) {
+                    u64 x = 0;
+                    if (i < ne) x = j == jt ? a.x[bi * a.xs + a.xc + toff + k] : a.ext[bi * a.es + j * a.ds + toff + k];
+                    d[i][j] = FP ? (u64)__double_as_longlong(d_from_u52(x)) : x;
                 }
             }
+            double s0[GP_EP], s1[GP_EP];
+            u64 lo0[GP_EP], hi0[GP_EP], lo1[GP_EP], hi1[GP_EP];
+#pragma unroll
+            for (int i = 0; i < GP_EP; ++i) {
+                s0[i] = s1[i] = 0.0;
+                lo0[i] = hi0[i] = lo1[i] = hi1[i] = 0;
+                if (g0 > 0 && i < ne) {  // the running sums of the earlier chunks
+                    const u64 *o = a.acc + (b + i * GP_LANES) * a.as + toff + k;
+                    if (FP) {
+                        s0[i] = d_from_u52(o[0]);
+                        s1[i] = d_from_u52(o[comp1]);
+                    } else {
+                        lo0[i] = o[0];
+                        lo1[i] = o[comp1];
+                    }
+                }
+            }
+            constexpr int GP_RED = 48 / BETA;
+            int nred = 0;
             for (int gi = 0; gi < gn; ++gi) {
                 const int src = (int)(giant_index(e, a.gals.g[g0 + gi], mask2n, a.logN) & (GP_TK - 1));
                 const u64 *kl = keys_lds + gi * per + L;
@@ -1903,41 +1919,63 @@ __global__ __launch_bounds__(GP_TK *GP_LANES) void giant_perm_kernel(GiantArgs a
                     // rotation's partial sum for the lane that takes these
                     // digits, which pulls it (2 pulls per component instead of
                     // 2 per digit); every sum is an exact integer below 2^52
-                    double p0 = 0.0, p1 = 0.0;
+                    double p0[GP_EP], p1[GP_EP];
+#pragma unroll
+                    for (int i = 0; i < GP_EP; ++i) p0[i] = p1[i] = 0.0;
 #pragma unroll
                     for (int j = 0; j < BETA; ++j) {
-                        const double dv = __longlong_as_double((long long)d[j]);
-                        p0 += mulmod_lazy_d(dv, __longlong_as_double((long long)kl[(2 * j) * GP_TK]), qd, qinv);
-                        p1 += mulmod_lazy_d(dv, __longlong_as_double((long long)kl[(2 * j + 1) * GP_TK]), qd, qinv);
+                        const double k0 = __longlong_as_double((long long)kl[(2 * j) * GP_TK]);
+                        const double k1 = __longlong_as_double((long long)kl[(2 * j + 1) * GP_TK]);
+#pragma unroll
+                        for (int i = 0; i < GP_EP; ++i) {
+                            const double dv = __longlong_as_double((long long)d[i][j]);
+                            p0[i] += mulmod_lazy_d(dv, k0, qd, qinv);
+                            p1[i] += mulmod_lazy_d(dv, k1, qd, qinv);
+                        }
                     }
-                    s0 += __longlong_as_double((long long)lane_take((u64)__double_as_longlong(p0), src));
-                    s1 += __longlong_as_double((long long)lane_take((u64)__double_as_longlong(p1), src));
-                    // back into (-q, 2q): the sum holds at most 8 more lazy products per rotation
-                    s0 = __fma_rn(-floor(s0 * qinv), qd, s0);
-                    s1 = __fma_rn(-floor(s1 * qinv), qd, s1);
+#pragma unroll
+                    for (int i = 0; i < GP_EP; ++i) {
+                        s0[i] += __longlong_as_double((long long)lane_take((u64)__double_as_longlong(p0[i]), src));
+                        s1[i] += __longlong_as_double((long long)lane_take((u64)__double_as_longlong(p1[i]), src));
+                    }
+                    // back into (-q, 2q) every GP_RED rotations: from there the
+                    // sum takes at most 48 lazy products of magnitude below
+                    // 2q + 2^29 < 2^47.1 and stays an exact integer below 2^52.6
+                    if (++nred == GP_RED) {
+                        nred = 0;
+#pragma unroll
+                        for (int i = 0; i < GP_EP; ++i) {
+                            s0[i] = __fma_rn(-floor(s0[i] * qinv), qd, s0[i]);
+                            s1[i] = __fma_rn(-floor(s1[i] * qinv), qd, s1[i]);
+                        }
+                    }
                 } else {
-                    u64 v[BETA], k0[BETA], k1[BETA];
 #pragma unroll
                     for (int j = 0; j < BETA; ++j) {
-                        v[j] = lane_take(d[j], src);
-                        k0[j] = kl[(2 * j) * GP_TK];
-                        k1[j] = kl[(2 * j + 1) * GP_TK];
-                    }
+                        const u64 k0 = kl[(2 * j) * GP_TK], k1 = kl[(2 * j + 1) * GP_TK];
 #pragma unroll
-                    for (int j = 0; j < BETA; ++j) {
-                        u64 pl = v[j] * k0[j], ph = __umul64hi(v[j], k0[j]);
-                        lo0 += pl;
-                        hi0 += ph + (lo0 < pl);
-                        pl = v[j] * k1[j];
-                        ph = __umul64hi(v[j], k1[j]);
-                        lo1 += pl;
-                        hi1 += ph + (lo1 < pl);
+                        for (int i = 0; i < GP_EP; ++i) {
+                            const u64 v = lane_take(d[i][j], src);
+                            u64 pl = v * k0, ph = __umul64hi(v, k0);
+                            lo0[i] += pl;
+                            hi0[i] += ph + (lo0[i] < pl);
+                            pl = v * k1;
+                            ph = __umul64hi(v, k1);
+                            lo1[i] += pl;
+                            hi1[i] += ph + (lo1[i] < pl);
+                        }
                     }
                 }
             }
             // FP: one full reduction; 128-bit sums of at most 40 products below 2^120 per chunk: reduced once
-            o[0] = FP ? u52_from_d(reduce_d(s0, qd, qinv)) : reduce128(hi0, lo0, p);
-            o[comp1] = FP ? u52_from_d(reduce_d(s1, qd, qinv)) : reduce128(hi1, lo1, p);
+#pragma unroll
+            for (int i = 0; i < GP_EP; ++i) {
+                if (i < ne) {
+                    u64 *o = a.acc + (b + i * GP_LANES) * a.as + toff + k;
+                    o[0] = FP ? u52_from_d(reduce_d(s0[i], qd, qinv)) : reduce128(hi0[i], lo0[i], p);
+                    o[comp1] = FP ? u52_from_d(reduce_d(s1[i], qd, qinv)) : reduce128(hi1[i], lo1[i], p);
+                }
+            }
         }
     }
     if (t > a.ell) return;
