@@ -1698,8 +1698,9 @@ struct GiantArgs {
 
 __device__ __forceinline__ long long giant_index(u64 e, u64 g, u64 mask2n, int logN)
 {
-    const u64 e2 = (e * g) & mask2n;
-    return brev_n((unsigned)((e2 - 1) >> 1), logN);
+    // only the low logN + 1 bits of e g are used: a 32-bit product suffices
+    const unsigned e2 = ((unsigned)e * (unsigned)g) & (unsigned)mask2n;
+    return brev_n((e2 - 1) >> 1, logN);
 }
 
 __global__ __launch_bounds__(256) void giant_gather_kernel(GiantArgs a, const PrimeInfo *__restrict__ pinfo)
