@@ -1276,7 +1276,7 @@ struct BabyArgs {
 
 // NB (compile time) baby steps, so the 2 NB loads of a block are issued
 // together; blockIdx.z selects a chunk of BABY_CHUNK blocks.
-constexpr int BABY_CHUNK = 16;
+constexpr int BABY_CHUNK = 24;
 template <int NB>
 __global__ __launch_bounds__(256) void baby_sum_kernel(BabyArgs a, const PrimeInfo *__restrict__ pinfo)
 {
