@@ -132,24 +132,26 @@ def test_ops_bit_exact_small(small):
 
 
 @pytest.mark.parametrize("steps", [[512 * g for g in range(1, 8)], [1, 3, -100, 2048]])
-def test_rotate_sum_hoisted_bit_exact(small, steps):
-    """x + sum_s Rot(x, s) as one hoisted key switch, three ciphertexts at a
+@pytest.mark.parametrize("n_ct", [3, 9])
+def test_rotate_sum_hoisted_bit_exact(small, steps, n_ct):
+    """x + sum_s Rot(x, s) as one hoisted key switch, n_ct ciphertexts at a
     middle level, against the oracle bit for bit: the rotations by multiples
     of S/8 (a group: the gathers stay inside 16-coefficient runs) and an
-    arbitrary set."""
+    arbitrary set.  With 9 ciphertexts the 4 waves of a workgroup take two of
+    them per pass on the wide primes, and one wave a last single one."""
     ctx, P, W = small["ctx"], small["P"], small["W"]
     okeys = O.Keys(P, W["seed_keys"] + 7, rot_steps=steps)
     gkeys = ctx.keygen(W["seed_keys"] + 7, steps)
     level = 3
-    xs = ctx.ct_block(3, level)
+    xs = ctx.ct_block(n_ct, level)
     want = []
-    for i in range(3):
+    for i in range(n_ct):
         data = np.stack([synth.uniform_residues(61 + 2 * i, P.q[: level + 1], P.N),
                          synth.uniform_residues(62 + 2 * i, P.q[: level + 1], P.N)])
         ctx.upload(data, level, 1.0, out=xs[i])
         want.append(O.rotate_sum_hoisted(P, O.CT(data, level, 1.0), steps, okeys).data)
     got = ctx.rotate_sum(xs, steps, gkeys)
-    for i in range(3):
+    for i in range(n_ct):
         assert np.array_equal(ctx.download(got[i]), want[i]), i
     with pytest.raises(small["H"].HEError):  # an output overlapping the input
         ctx.rotate_sum(xs, steps, gkeys, outs=xs)
