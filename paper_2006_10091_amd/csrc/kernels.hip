@@ -1940,8 +1940,10 @@ __global__ __launch_bounds__(GP_TK *GP_LANES) void giant_perm_kernel(GiantArgs a
                         s1[i] += __longlong_as_double((long long)lane_take((u64)__double_as_longlong(p1[i]), src));
                     }
                     // back into (-q, 2q) every GP_RED rotations: from there the
-                    // sum takes at most 48 lazy products of magnitude below
-                    // 2q + 2^29 < 2^47.1 and stays an exact integer below 2^52.6
+                    // sum takes at most 48 lazy products, each below 2q + 2^39
+                    // < 2^47.1 in magnitude (q < 2^46: the product's low part is
+                    // at most half an ulp of a value below 2^92), and stays an
+                    // exact integer below 2^52.6
                     if (++nred == GP_RED) {
                         nred = 0;
 #pragma unroll
