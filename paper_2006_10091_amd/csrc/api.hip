@@ -72,6 +72,13 @@ size_t rescale_scratch(const he_ctx *c, int l, int B, int ncomp = 2)
     return al((size_t)B * ncomp * c->N) + al((size_t)B * ncomp * l * c->N) + y;
 }
 size_t rotate_scratch(const he_ctx *c, int l, int B) { return al((size_t)B * 2 * (l + 1) * c->N) + ks_scratch(c, l, B); }
+// relin_rescale_apply: the key switch's buffers and three limbs per component
+// (fused); else the relinearised intermediate and the larger of the two steps
+size_t relin_rescale_scratch(const he_ctx *c, int l, int B)
+{
+    if (hek::fused_ok(c)) return ks_scratch(c, l, B) + 3 * al((size_t)B * 2 * c->N);
+    return al((size_t)B * 2 * (l + 1) * c->N) + std::max(ks_scratch(c, l, B), rescale_scratch(c, l, B));
+}
 
 he_status last_error()
 {
@@ -598,6 +605,7 @@ size_t step_bytes(const he_ctx *c, int l, int nb, int layout, int n_baby = 1)
     n += al((size_t)2 * (l - 3) * N);                      // Gm
     size_t scratch = std::max(rotate_scratch(c, l, nb), rescale_scratch(c, l, nb));
     scratch = std::max(scratch, rescale_scratch(c, l - 1, nb, 3));  // A, B3: degree 2
+    scratch = std::max(scratch, relin_rescale_scratch(c, l, nb));     // the margins' products
     if (n_baby > 1) {
         n += al((size_t)(n_baby - 1) * 2 * (l + 1) * N);  // Wr
         scratch = std::max(scratch, rotate_scratch(c, l, n_baby - 1));
@@ -891,8 +899,8 @@ he_status run_graph(he_ctx *c, const std::string &key, F body)
 size_t batch_bytes(const he_ctx *c, int l, int B)
 {
     const size_t N = c->N;
-    size_t n = al((size_t)B * 3 * (l + 1) * N) + al((size_t)B * 2 * (l + 1) * N) + 2 * al((size_t)B * 2 * l * N);
-    n += std::max(ks_scratch(c, l, B), std::max(rescale_scratch(c, l, B), rotate_scratch(c, l - 1, B)));
+    size_t n = al((size_t)B * 3 * (l + 1) * N) + 2 * al((size_t)B * 2 * l * N);
+    n += std::max(relin_rescale_scratch(c, l, B), rotate_scratch(c, l - 1, B));
     return n * 8 + 4096;
 }
 
@@ -908,10 +916,9 @@ he_status batch_impl(he_ctx *c, const he_ct *x, const he_ct *y, const u64 *gal, 
             const int B = (int)std::min<size_t>(chunk, idx.size() - s0);
             Arena ar = arena(c);
             u64 *T3 = ar.take((size_t)B * 3 * lc);
-            u64 *U0 = ar.take((size_t)B * 2 * lc);
             u64 *R = ar.take((size_t)B * 2 * rc);
             u64 *Ob = ar.take((size_t)B * 2 * rc);
-            if (!T3 || !U0 || !R || !Ob) return HE_ENOMEM;
+            if (!T3 || !R || !Ob) return HE_ENOMEM;
             hek::EntryKeys keys;
             hek::EntryGal gals;
             for (int b = 0; b < B; ++b) {
@@ -920,8 +927,7 @@ he_status batch_impl(he_ctx *c, const he_ct *x, const he_ct *y, const u64 *gal, 
                 keys.k[b] = find_rot_key(k, gal[i]);
                 gals.g[b] = gal[i];
             }
-            TRY(relin_apply(c, ar, l, B, T3, 3 * lc, k->rlk, U0, 2 * lc));
-            TRY(rescale_apply(c, ar, l, B, U0, 2 * lc, R, 2 * rc));
+            TRY(relin_rescale_apply(c, ar, l, B, T3, 3 * lc, k->rlk, R, 2 * rc));
             TRY(rotate_multi_apply(c, ar, l - 1, B, R, 2 * rc, gals, keys, Ob, 2 * rc));
             for (int b = 0; b < B; ++b)
                 hek::ewise(c, 4, l - 1, 1, 2, Ob + b * 2 * rc, 0, rc, nullptr, 0, 0, out[idx[s0 + b]].data, 0, rc, 0);
