@@ -940,8 +940,8 @@ he_status batch_impl(he_ctx *c, const he_ct *x, const he_ct *y, const u64 *gal, 
 size_t margins_bytes(const he_ctx *c, int l, int nb)
 {
     const size_t N = c->N;
-    size_t n = al((size_t)nb * 3 * (l + 1) * N) + al((size_t)nb * 2 * (l + 1) * N) + al((size_t)nb * 2 * l * N);
-    n += std::max(ks_scratch(c, l, nb), std::max(rescale_scratch(c, l, nb), rotate_scratch(c, l - 1, nb)));
+    size_t n = al((size_t)nb * 3 * (l + 1) * N) + al((size_t)nb * 2 * l * N);
+    n += std::max(relin_rescale_scratch(c, l, nb), rotate_scratch(c, l - 1, nb));
     return n * 8 + 4096;
 }
 
@@ -957,13 +957,11 @@ he_status margins_impl(he_ctx *c, const he_ct *Z, int n_blocks, long long zbs, c
         const int nb = std::min(chunk, n_blocks - b0);
         Arena ar = arena(c);
         u64 *T3 = ar.take((size_t)nb * 3 * lc);
-        u64 *U0 = ar.take((size_t)nb * 2 * lc);
         u64 *R = ar.take((size_t)nb * 2 * u1);
-        if (!T3 || !U0 || !R) return HE_ENOMEM;
+        if (!T3 || !R) return HE_ENOMEM;
         u64 *u = out + b0 * obs;
         hek::tensor_b(c, l, nb, Z[b0].data, chunk == 1 ? 0 : zbs, zc, W->data, 0, wc, T3, 3 * lc, lc);
-        TRY(relin_apply(c, ar, l, nb, T3, 3 * lc, keys->rlk, U0, 2 * lc));
-        TRY(rescale_apply(c, ar, l, nb, U0, 2 * lc, u, obs));
+        TRY(relin_rescale_apply(c, ar, l, nb, T3, 3 * lc, keys->rlk, u, obs));
         for (int t = 1; t < count; t <<= 1) {
             const u64 gal = galois_of(c, (long long)t * unit);
             const u64 *key = find_rot_key(keys, gal);
