@@ -73,6 +73,7 @@ def lib():
         "orc_encrypt_pk": (None, [P, c_int, i64p, u64p, c_uint64, c_uint32, u64p]),
         "orc_decrypt": (None, [P, c_int, u64p, i64p, u64p]),
         "orc_secret_square": (None, [P, i64p, u64p]),
+        "orc_set_conv_centring": (None, [c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -390,6 +390,16 @@ void orc_tensor_n(const orc_params *P, int level, int nx, const u64 *x, int ny, 
     free(t);
 }
 
+/*
+ * Centring of the fast basis conversion (ModUp and ModDown).  On (the
+ * reading used everywhere): each digit y = [x qhat^{-1}]_q enters as its
+ * centred representative in (-q/2, q/2).  Off: as its residue in [0, q).  The
+ * switch exists only so that a test can plant the uncentred conversion in the
+ * oracle and check that the exact pins reject it.
+ */
+static int conv_centred = 1;
+void orc_set_conv_centring(int on) { conv_centred = on != 0; }
+
 /* prime of basis position pos at level l: pos <= l -> q_pos, else special pos-l-1 */
 static u64 basis_prime(const orc_params *P, int level, int pos, u64 *psi)
 {
@@ -429,7 +439,7 @@ void orc_modup(const orc_params *P, int level, int j, const u64 *d, u64 *ext)
             for (int i = lo; i < hi; i++) {
                 u64 qi = P->q[i];
                 u64 y = mulmod(LIMB(d, i)[x], yinv[i], qi);
-                i64 yc = y > qi / 2 ? -(i64)(qi - y) : (i64)y; /* centered representative */
+                i64 yc = conv_centred && y > qi / 2 ? -(i64)(qi - y) : (i64)y; /* centered representative */
                 acc = addmod(acc, mulmod(smod(yc, qt), qh_t[i], qt), qt);
             }
             LIMB(ext, t)[x] = acc;
@@ -466,7 +476,7 @@ void orc_moddown(const orc_params *P, int level, const u64 *c, u64 *out)
             for (int p = 0; p < nk; p++) {
                 u64 pp = P->q[P->nq + p];
                 u64 y = mulmod(LIMB(c, level + 1 + p)[x], yinv[p], pp);
-                i64 yc = y > pp / 2 ? -(i64)(pp - y) : (i64)y; /* centered representative */
+                i64 yc = conv_centred && y > pp / 2 ? -(i64)(pp - y) : (i64)y; /* centered representative */
                 conv = addmod(conv, mulmod(smod(yc, qi), ph_i[p], qi), qi);
             }
             LIMB(out, i)[x] = mulmod(submod(LIMB(c, i)[x], conv, qi), Pinv, qi);

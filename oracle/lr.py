@@ -444,3 +444,70 @@ def _step_features(P, keys, Z, W, mask_m, c, r, pl, Zrot=None, n_baby=1):
         t *= 2
     Wn = O.rescale(P, O.mul_int(P, O.drop(W, l - 3), pl["kW"]), scale=pl["s_g"])
     return O.add(P, Wn, g), g
+
+
+# ---------------------------------------------------------------- paper-order circuit
+def lr_grad_step_plain(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_decay=0.0, layout=ROWS):
+    """The same step in the order Sec. 3 and Sec. 4 state it, with no schedule
+    of this build's: every ciphertext product is relinearised and rescaled
+    before it is used (Sec. 3, multiplication then scaling), every slot sum is
+    a sequence of rotate-and-adds, each block's gradient terms C, B1, k0 Z
+    (and B2) are rescaled on their own before the cross-block sum of
+    eq. (appr), and W is updated by eq. (update).  No baby steps, no hoisted
+    key switch, no degree-3 or degree-4 ciphertext, no unrescaled sum.
+
+    It takes the same scale plan (plan_lr_step) as lr_grad_step: every term
+    still lands on the plan's scale sC, so the two circuits compute the same
+    slots and differ only by where they round (rescale and key-switch noise).
+    It is the reference lr_grad_step is pinned against.  Returns (W', g)."""
+    l = W.level
+    pl = plan or plan_lr_step(P.q, l, Z[0].scale, W.scale, coef, eta_over_n, w_decay, layout)
+    feat = layout == FEATURES
+    lt = l - 2 if feat else l - 3  # level of the products C, B1 (and B2) before their rescale
+    G = None
+    for zb in Z:
+        u = O.rescale(P, O.mul(P, O.drop(zb, l), W, keys), scale=pl["s1"])
+        t = 1
+        while t < c:  # margins: rotate-and-add over the columns (row-major) or feature blocks
+            u = O.add(P, u, O.rotate(P, u, t * r if feat else t, keys))
+            t *= 2
+        if feat:
+            M = u
+        else:
+            M = O.rescale(P, O.mul_plain(P, u, mask_m, pl["s_mask"]), scale=pl["sM"])
+            t = 1
+            while t < c:  # replicate m_i over row i
+                M = O.add(P, M, O.rotate(P, M, -t, keys))
+                t *= 2
+        lm = M.level  # l-1 feature-major, l-2 row-major
+        A = O.rescale(P, O.mul(P, M, M, keys), scale=pl["sA"])
+        Z3 = O.rescale(P, O.mul_int(P, O.drop(zb, lm + 1), pl["k3"]), scale=pl["sZ3"])
+        B3 = O.rescale(P, O.mul(P, M, Z3, keys), scale=pl["sB3"])
+        C = O.rescale(P, O.mul(P, A, B3, keys), scale=pl["sC"])
+        Z1 = O.rescale(P, O.mul_int(P, O.drop(zb, lt + 1), pl["k1"]), scale=pl["sZ1"])
+        B1 = O.rescale(P, O.mul(P, O.drop(M, lt), Z1, keys), scale=pl["sC"])
+        Z0 = O.rescale(P, O.mul_int(P, O.drop(zb, lt), pl["k0"]), scale=pl["sC"])
+        Gb = O.add(P, O.add(P, C, B1), Z0)
+        if pl["k2"] != 0:
+            Z2 = O.rescale(P, O.mul_int(P, O.drop(zb, lt + 1), pl["k2"]), scale=pl["sZ2"])
+            Gb = O.add(P, Gb, O.rescale(P, O.mul(P, A, Z2, keys), scale=pl["sC"]))
+        G = Gb if G is None else O.add(P, G, Gb)
+    if feat:
+        t = 1
+        while t < r:  # sum over the samples inside each feature block
+            G = O.add(P, G, O.rotate(P, G, t, keys))
+            t *= 2
+        G = O.CT(G.data, G.level, pl["s_gsum"])
+        g = O.rescale(P, O.mul_plain(P, G, mask_m, pl["s_mask"]), scale=pl["s_g"])
+        t = 1
+        while t < r:  # replicate g_j over its feature block
+            g = O.add(P, g, O.rotate(P, g, -t, keys))
+            t *= 2
+    else:
+        t = 1
+        while t < r:  # sum over the rows, replicated in every row
+            G = O.add(P, G, O.rotate(P, G, t * c, keys))
+            t *= 2
+        g = O.CT(G.data, G.level, pl["s_g"])
+    Wn = O.rescale(P, O.mul_int(P, O.drop(W, l - 3), pl["kW"]), scale=pl["s_g"])
+    return O.add(P, Wn, g), g
