@@ -16,8 +16,9 @@
  *   Memory.   Ciphertexts, plaintexts and key buffers are device memory OWNED
  *             BY THE CALLER (allocated, for example, with torch); the library
  *             never frees them.  The context owns only its precomputed tables
- *             and a scratch workspace (hipMalloc, grown on demand outside any
- *             graph capture, freed by he_ctx_destroy).
+ *             and a scratch workspace, and takes both from the allocator the
+ *             caller gives he_ctx_create (grown on demand outside any graph
+ *             capture, given back by he_ctx_trim / he_ctx_destroy).
  *   Layout.   A ciphertext at level l is uint64 [2][l+1][N], limb-major (limb i
  *             of component c at element offset (c*(l+1)+i)*N), values in
  *             [0, q_i), in the library's private NTT order.  A plaintext at
@@ -127,12 +128,37 @@ typedef struct {
     int32_t layout, reserved;
 } he_lr_plan;
 
+/* Scale schedule of an encrypted inference with the polynomial (pure host;
+ * he_plan_lr_infer).  The margins u (scale s_u) go through
+ * U2 = RS(relin(u u)) (scale s_u2), H = RS(k3 u) + k2c (declared s_h) and
+ * p(u) = RS(relin(H U2)) + RS(k1 u) + k0c at scale s_p; k3 and k1 multiply,
+ * k2c and k0c are added as constants. */
+typedef struct {
+    int32_t level_in, level_out;
+    double s_u, s_u2, s_h, s_p;
+    int64_t k3, k2c, k1, k0c;
+} he_infer_plan;
+
 /* ---------------------------------------------------------------- context */
 
+/* Device memory provider of a context.  alloc(user, bytes) returns `bytes` of
+ * device memory on the context's device, 256-byte aligned, or NULL when none
+ * is left (the call that needed it then returns HE_ENOMEM); release(user, p)
+ * gives back a pointer alloc returned.  The library calls them only from
+ * inside its own calls, on the calling thread, and never while a HIP graph is
+ * being captured.  The Python binding backs them with torch.empty, so all of
+ * the library's device memory is torch's. */
+typedef void *(*he_alloc_fn)(void *user, size_t bytes);
+typedef void (*he_free_fn)(void *user, void *ptr);
+
 /* Create a context: prime chain, roots, twiddle and basis-conversion tables
- * (device).  hip_stream: a hipStream_t (NULL = default stream).  Errors:
- * HE_EINVAL on parameters out of range, HE_EDEVICE/HE_ENOMEM from HIP. */
-he_status he_ctx_create(const he_params *prm, void *hip_stream, he_ctx **out);
+ * (device memory from `alloc`; alloc = NULL: hipMalloc / hipFree, release
+ * then ignored).  alloc_user is passed back to both callbacks unchanged.
+ * hip_stream: a hipStream_t (NULL = default stream).  Errors: HE_EINVAL on
+ * parameters out of range, HE_ENOMEM when the allocator fails, HE_EDEVICE
+ * from HIP.  On error nothing stays allocated. */
+he_status he_ctx_create(const he_params *prm, he_alloc_fn alloc, he_free_fn release, void *alloc_user,
+                        void *hip_stream, he_ctx **out);
 he_status he_ctx_destroy(he_ctx *ctx);
 he_status he_ctx_set_stream(he_ctx *ctx, void *hip_stream);
 /* Copy the prime chain (q_0..q_{n_q-1}, then the specials) to host memory;
@@ -141,7 +167,8 @@ he_status he_ctx_primes(const he_ctx *ctx, uint64_t *out, int n);
 /* Pure host (no device): the prime chain the parameters select, as above;
  * n must be >= n_q + n_special.  HE_EINVAL on parameters out of range. */
 he_status he_params_primes(const he_params *prm, uint64_t *out, int n);
-/* Release the context's scratch workspace (it is re-grown on demand). */
+/* Give the context's scratch workspace back to its allocator (it is re-grown
+ * on demand); graphs captured over it are dropped. */
 he_status he_ctx_trim(he_ctx *ctx);
 
 /* Bytes of a ciphertext / plaintext / degree-2 ciphertext at a level. */
@@ -152,8 +179,8 @@ size_t he_ct3_bytes(const he_ctx *ctx, int level);
 /* ---------------------------------------------------------------- keys */
 
 /* Bytes of the key buffer for n_rot rotation keys (secret key, the keys for
- * s^2, s^3 and s^4 and the rotation keys, each evaluation key
- * [dnum][2][n_q+n_special][N]). */
+ * s^2, s^3 and s^4, the public key [2][n_q][N] and the rotation keys, each
+ * evaluation key [dnum][2][n_q+n_special][N]). */
 size_t he_keys_bytes(const he_ctx *ctx, int n_rot);
 
 /* Key generation (Alg. 2, initialisation: the server generates the keys).
@@ -161,16 +188,19 @@ size_t he_keys_bytes(const he_ctx *ctx, int n_rot);
  * is for s^2, two more switch s^3 and s^4 to s (the gradient step relinearises
  * a degree-4 sum), and one rotation key is made per entry of rot_steps (a left
  * rotation of the slot vector by that many slots, Galois element 5^t mod 2N).
- * Randomness: ChaCha20 keyed by seed.  key_buf: caller device memory of at
- * least he_keys_bytes(ctx, n_rot) bytes; *out is a host handle referencing it
+ * The public key (-a*s + e, a) over q_0..q_{n_q-1} is made too (Alg. 1: the
+ * worker's pk).  Randomness: ChaCha20 keyed by seed.  key_buf: caller device
+ * memory of at least he_keys_bytes(ctx, n_rot) bytes; *out is a host handle referencing it
  * (free with he_keys_destroy; the buffer stays the caller's). */
 he_status he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *rot_steps, int n_rot,
                     void *key_buf, size_t key_buf_bytes, he_keys **out);
+/* Release a key handle; graphs captured with it are dropped (the buffer stays
+ * the caller's). */
 he_status he_keys_destroy(he_keys *keys);
 /* Download a key for inspection, coefficient order: which = -2 secret
- * ([n_q+n_special][N]), -1 relinearisation key (s^2), -3 / -4 the keys for s^3
- * / s^4, else the Galois element of a rotation key ([dnum][2][n_q+n_special][N]).
- * host must hold the size. */
+ * ([n_q+n_special][N]), -5 the public key ([2][n_q][N]), -1 relinearisation
+ * key (s^2), -3 / -4 the keys for s^3 / s^4, else the Galois element of a
+ * rotation key ([dnum][2][n_q+n_special][N]).  host must hold the size. */
 he_status he_keys_download(he_ctx *ctx, const he_keys *keys, int64_t which, uint64_t *host);
 
 /* ---------------------------------------------------------------- encoding (host FP64) */
@@ -191,10 +221,17 @@ he_status he_pt_load(he_ctx *ctx, const int64_t *coeffs, int level, double scale
 
 /* ---------------------------------------------------------------- encryption */
 
-/* Secret-key encryption (Alg. 2: the server encrypts data and weights with sk):
- * (-a*s + e + m, a), a uniform, e centered binomial (21 pairs); stream index
- * `index` separates ciphertexts made with one seed.  Output level = pt level. */
-he_status he_encrypt(he_ctx *ctx, const he_pt *pt, const he_keys *keys, uint64_t seed,
+/* Encryption of a plaintext at its level (output level = pt level).
+ *   use_sk != 0: secret-key encryption (Alg. 2: the server encrypts data and
+ *     weights with sk): (-a*s + e + m, a), a uniform, e centred binomial (21
+ *     pairs).
+ *   use_sk == 0: public-key encryption (Alg. 1: a worker holds pk):
+ *     (v*pk_b + e0 + m, v*pk_a + e1), v ternary (P(0) = 1/2), e0 and e1
+ *     centred binomial; pk = (-a*s + e, a) is made by he_keygen.
+ * Randomness: ChaCha20 keyed by seed; stream index `index` separates
+ * ciphertexts made with one seed.  out: caller memory for a ciphertext at
+ * pt's level.  Errors: HE_EINVAL. */
+he_status he_encrypt(he_ctx *ctx, const he_pt *pt, const he_keys *keys, int use_sk, uint64_t seed,
                      uint32_t index, he_ct *out);
 /* Decrypt (Alg. 2: the server decrypts the worker's weights): residues of
  * b + a*s at every limb, coefficient order, to host [level+1][N]. */
@@ -327,6 +364,31 @@ he_status he_lr_data_terms(he_ctx *ctx, const he_ct *Z, int n_blocks, int w_leve
  */
 he_status he_lr_margins(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct *W, int c, int r, int layout,
                         const he_keys *keys, int mode, he_ct *out);
+
+/* Pure host schedule of he_lr_infer with a polynomial (no device use): W at
+ * `level` (>= 3), data scale s_z, weight scale s_w, coef = a0..a3.  HE_ELEVEL
+ * below level 3, HE_ESCALE when a constant leaves |k| < 2^62.  q: the prime
+ * chain (he_ctx_primes). */
+he_status he_plan_lr_infer(const uint64_t *q, int n_q, int level, double s_z, double s_w, const double coef[4],
+                           he_infer_plan *out);
+
+/*
+ * Encrypted inference (the serving call; Alg. 1's worker scores its data with
+ * the current encrypted weights): the margins m_i = w.x_i of eq. (appr), as
+ * he_lr_margins computes them, and, when coef is given, the Table 2
+ * polynomial applied slot by slot, p(m) = coef[0] + coef[1] m + coef[2] m^2 +
+ * coef[3] m^3 (with p approximating -L', p(m) scores each sample; for the
+ * binomial deviance it approximates sigma(-m)).
+ *   coef == NULL: out[b] = the margins, exactly he_lr_margins (level W - 1).
+ *   coef != NULL: out[b] = p(margins) at W's level - 3 with scale s_p of
+ *     he_plan_lr_infer (W at level >= 3).
+ * Row-major blocks hold m_i (and p(m_i)) at slot i*c, feature-major ones at
+ * every slot j*r + i.  Z, W, c, r, layout, keys, mode as for he_lr_margins;
+ * out[0..n_blocks): caller memory at the output level, one uniform stride
+ * apart.  Errors before any launch: HE_EINVAL, HE_ELEVEL, HE_ESCALE, HE_EKEY.
+ */
+he_status he_lr_infer(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct *W, int c, int r, int layout,
+                      const double *coef, const he_keys *keys, int mode, he_ct *out);
 
 /* Device workspace (bytes) that he_lr_grad_step / he_lr_margins take for
  * n_blocks blocks with weights at `level` in `mode` (with n_baby baby steps for

@@ -491,3 +491,13 @@ def rotate(P, x, t, keys):
     o0 = np.zeros((n, P.N), dtype=np.uint64)
     lib().orc_add(P.cp, n, _u(b), _u(ks[0]), _u(o0))
     return CT(np.stack([o0, ks[1]]), x.level, x.scale)
+
+
+def add_const(P, x, k):
+    """x + k for an integer k: the constant polynomial k added to the b-part
+    (coefficient 0), which adds k to every slot at x's scale."""
+    out = x.data.copy()
+    for i in range(x.level + 1):
+        q = P.q[i]
+        out[0, i, 0] = np.uint64((int(out[0, i, 0]) + int(k)) % q)
+    return CT(out, x.level, x.scale)

@@ -511,3 +511,62 @@ def lr_grad_step_plain(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None,
         g = O.CT(G.data, G.level, pl["s_g"])
     Wn = O.rescale(P, O.mul_int(P, O.drop(W, l - 3), pl["kW"]), scale=pl["s_g"])
     return O.add(P, Wn, g), g
+
+
+# ---------------------------------------------------------------- encrypted inference
+def lr_margins(P, keys, Z, W, c, r, layout=ROWS):
+    """The margins m_i = w.z_i per block (eq. (appr)'s inner products):
+    u = RS(relin(Z (x) W)), then rotate-and-add by t u, t = 1 .. c/2 (u = r
+    feature-major, 1 row-major)."""
+    l = W.level
+    unit = r if layout == FEATURES else 1
+    out = []
+    for zb in Z:
+        u = O.rescale(P, O.mul(P, O.drop(zb, l), W, keys))
+        t = 1
+        while t < c:
+            u = O.add(P, u, O.rotate(P, u, t * unit, keys))
+            t *= 2
+        out.append(u)
+    return out
+
+
+def plan_lr_infer(q, level, s_Z, s_W, coef):
+    """FP64 schedule of p(u) on the margins u (level l-1, scale s_u):
+    U2 = RS(relin(u u)), H = RS(k3 u) + k2c, p = RS(relin(H U2)) + RS(k1 u) +
+    k0c at level l-3 and scale s_p = s_u.  Expressions evaluated left to right
+    exactly as written."""
+    if level < 3:
+        raise LevelError("inference with the polynomial needs 3 levels; W is at level %d" % level)
+    ql, q1, q2 = float(q[level]), float(q[level - 1]), float(q[level - 2])
+    s_u = s_Z * s_W / ql
+    s_u2 = s_u * s_u / q1
+    s_p = s_u
+    s_h = s_p * q2 / s_u2
+    k3 = coef[3] * s_h * q1 / s_u
+    k2c = coef[2] * s_h
+    k1 = coef[1] * s_p * q2 / s_u
+    k0c = coef[0] * s_p
+    for name, k in (("k3", k3), ("k2c", k2c), ("k1", k1), ("k0c", k0c)):
+        if not abs(k) < K_MAX:
+            raise ScaleError("%s out of range" % name)
+    return dict(level=level, level_out=level - 3, s_u=s_u, s_u2=s_u2, s_h=s_h, s_p=s_p, k3=llround(k3),
+                k2c=llround(k2c), k1=llround(k1), k0c=llround(k0c))
+
+
+def lr_infer(P, keys, Z, W, c, r, layout=ROWS, coef=None):
+    """Encrypted scoring: the margins, and with coef the polynomial
+    p(m) = a0 + a1 m + a2 m^2 + a3 m^3 slot by slot (Table 2's p approximates
+    -L'; for the binomial deviance p(m) ~ sigma(-m))."""
+    us = lr_margins(P, keys, Z, W, c, r, layout)
+    if coef is None:
+        return us
+    pl = plan_lr_infer(P.q, W.level, Z[0].scale, W.scale, coef)
+    out = []
+    for u in us:
+        U2 = O.rescale(P, O.mul(P, u, u, keys))
+        H = O.add_const(P, O.rescale(P, O.mul_int(P, u, pl["k3"]), scale=pl["s_h"]), pl["k2c"])
+        T = O.rescale(P, O.mul(P, H, U2, keys), scale=pl["s_p"])
+        L = O.rescale(P, O.mul_int(P, O.drop(u, u.level - 1), pl["k1"]), scale=pl["s_p"])
+        out.append(O.add_const(P, O.add(P, T, L), pl["k0c"]))
+    return out

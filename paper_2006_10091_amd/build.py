@@ -1,17 +1,21 @@
-"""Build libhe.so (the HIP library behind include/he.h) in-tree for gfx950."""
+"""Build libhe.so (the HIP library behind include/he.h) in-tree for gfx950.
+
+Each source is compiled to an object in parallel, then linked."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhe.so")
+OBJ = os.path.join(HERE, "_build")
 SOURCES = ["host.cpp", "kernels.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions stay off on this path (no v_pk_* f32 ops emitted)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # host FP64 scale planning must round exactly as written: no contraction
@@ -20,11 +24,26 @@ FLAGS = [
 ]
 
 
+def _compile(src):
+    obj = os.path.join(OBJ, src + ".o")
+    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", "-o", obj,
+                             os.path.join(CSRC, src)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    # hipcc's host pass does not know the packed-FP32 feature: drop that warning only
+    err = "\n".join(x for x in r.stderr.splitlines() if "packed-fp32-ops" not in x)
+    if err.strip():
+        sys.stderr.write(err + "\n")
+    if r.returncode != 0:
+        raise subprocess.CalledProcessError(r.returncode, cmd)
+    return obj
+
+
 def build() -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    with ThreadPoolExecutor(len(SOURCES)) as ex:
+        objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp] + \
-        [os.path.join(CSRC, s) for s in SOURCES]
-    subprocess.run(cmd, check=True)
+    subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs, check=True)
     os.replace(tmp, LIB)
     return LIB
 

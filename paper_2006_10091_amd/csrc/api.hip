@@ -1,6 +1,7 @@
 // api.hip -- the C ABI of libhe (include/he.h): context and tables, keys,
 // encryption, the homomorphic operations and the encrypted gradient step.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -10,6 +11,12 @@
 #include <sstream>
 
 #include "he_internal.h"
+
+#define TRY(x)                          \
+    do {                                \
+        he_status st_ = (x);            \
+        if (st_ != HE_OK) return st_;   \
+    } while (0)
 
 namespace {
 
@@ -29,20 +36,59 @@ struct Arena {
 
 inline size_t al(size_t n_u64) { return ((n_u64 * 8 + 255) & ~(size_t)255) / 8; }
 
+// Device memory comes from the caller's allocator when one was given (the
+// Python binding backs it with torch), else from hipMalloc.
+void *dev_alloc(he_ctx *c, size_t bytes)
+{
+    if (c->alloc_fn) return c->alloc_fn(c->alloc_user, bytes);
+    void *p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+void dev_free(he_ctx *c, void *p)
+{
+    if (!p) return;
+    if (c->alloc_fn) {
+        if (c->free_fn) c->free_fn(c->alloc_user, p);
+        return;
+    }
+    (void)hipFree(p);
+}
+
+// Drop the captured graphs that read key set `keys_gen` (0: every graph).
+// Called when that key set is destroyed and whenever the workspace moves: a
+// graph holds the device addresses it was captured with.
+he_status drop_graphs(he_ctx *c, uint64_t keys_gen)
+{
+    bool any = false;
+    for (auto &kv : c->graphs) any |= keys_gen == 0 || kv.second.keys_gen == keys_gen;
+    if (!any) return HE_OK;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->gstream) HIPCHK(hipStreamSynchronize(c->gstream));
+    for (auto it = c->graphs.begin(); it != c->graphs.end();) {
+        if (keys_gen == 0 || it->second.keys_gen == keys_gen) {
+            if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+            if (it->second.graph) (void)hipGraphDestroy(it->second.graph);
+            it = c->graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    return HE_OK;
+}
+
 he_status ensure_ws(he_ctx *c, size_t bytes)
 {
     if (c->ws_bytes >= bytes) return HE_OK;
     if (c->capturing) return HE_ENOMEM;
     if (c->ws) {
+        TRY(drop_graphs(c, 0));
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(hipFree(c->ws));
+        dev_free(c, c->ws);
         c->ws = nullptr;
         c->ws_bytes = 0;
     }
-    if (hipMalloc(&c->ws, bytes) != hipSuccess) {
-        c->ws = nullptr;
-        return HE_ENOMEM;
-    }
+    c->ws = dev_alloc(c, bytes);
+    if (!c->ws) return HE_ENOMEM;
     c->ws_bytes = bytes;
     return HE_OK;
 }
@@ -358,10 +404,10 @@ bool ct_ok(const he_ctx *c, const he_ct *x) { return x && x->data && x->level >=
 template <class T>
 T *dev_upload(he_ctx *c, const std::vector<T> &h)
 {
-    void *p = nullptr;
-    if (hipMalloc(&p, h.size() * sizeof(T)) != hipSuccess) return nullptr;
-    if (hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    void *p = dev_alloc(c, h.size() * sizeof(T));
+    if (!p) return nullptr;
     c->owned.push_back(p);
+    if (hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
     return (T *)p;
 }
 
@@ -643,12 +689,6 @@ he_status step_alloc(he_ctx *c, Arena &ar, int l, int nb, int layout, int n_baby
     return HE_OK;
 }
 
-#define TRY(x)                          \
-    do {                                \
-        he_status st_ = (x);            \
-        if (st_ != HE_OK) return st_;   \
-    } while (0)
-
 // ct x ct -> relin -> rescale for nb entries at level l (inputs [nb][2][*] with
 // batch/component strides), output [nb][2][l][N]
 he_status mul_relin_rescale(he_ctx *c, Arena &ar, StepBufs &s, int l, int nb, const u64 *x, long long xb,
@@ -850,7 +890,7 @@ he_status rotate_sum(he_ctx *c, Arena &ar, int level, u64 *x, u64 *tmp, long lon
 // caller's stream by events.  Buffers must not move between replays (the key
 // names every pointer the body uses, the workspace included).
 template <class F>
-he_status run_graph(he_ctx *c, const std::string &key, F body)
+he_status run_graph(he_ctx *c, const std::string &key, uint64_t keys_gen, F body)
 {
     if (!c->gstream) {
         HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
@@ -881,6 +921,7 @@ he_status run_graph(he_ctx *c, const std::string &key, F body)
             return st != HE_OK ? st : HE_EDEVICE;
         }
         ge.graph = g;
+        ge.keys_gen = keys_gen;
         if (hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0) != hipSuccess) {
             (void)hipGraphDestroy(g);
             c->graphs.erase(key);
@@ -948,7 +989,7 @@ size_t margins_bytes(const he_ctx *c, int l, int nb)
 // u = RS(relin(Z_b (x) W)) written straight into out (uniform batch stride
 // obs), then the margin sum in place: rotations by t * unit, t = 1 .. count/2
 he_status margins_impl(he_ctx *c, const he_ct *Z, int n_blocks, long long zbs, const he_ct *W, long long unit,
-                       int count, const he_keys *keys, int chunk, u64 *out, long long obs)
+                       int count, const he_keys *keys, int chunk, u64 *out, long long obs, size_t ws_off = 0)
 {
     const long long N = c->N;
     const int l = W->level;
@@ -956,6 +997,7 @@ he_status margins_impl(he_ctx *c, const he_ct *Z, int n_blocks, long long zbs, c
     for (int b0 = 0; b0 < n_blocks; b0 += chunk) {
         const int nb = std::min(chunk, n_blocks - b0);
         Arena ar = arena(c);
+        ar.off = ws_off;  // the workspace below ws_off belongs to the caller
         u64 *T3 = ar.take((size_t)nb * 3 * lc);
         u64 *R = ar.take((size_t)nb * 2 * u1);
         if (!T3 || !R) return HE_ENOMEM;
@@ -1067,7 +1109,8 @@ const char *he_strerror(he_status s)
     return "unknown status";
 }
 
-he_status he_ctx_create(const he_params *prm, void *hip_stream, he_ctx **out)
+he_status he_ctx_create(const he_params *prm, he_alloc_fn alloc, he_free_fn release, void *alloc_user,
+                        void *hip_stream, he_ctx **out)
 {
     if (!prm || !out) return HE_EINVAL;
     *out = nullptr;
@@ -1088,6 +1131,9 @@ he_status he_ctx_create(const he_params *prm, void *hip_stream, he_ctx **out)
     c->alpha = prm->alpha;
     c->dnum = dnum;
     c->stream = (hipStream_t)hip_stream;
+    c->alloc_fn = alloc;
+    c->free_fn = release;
+    c->alloc_user = alloc_user;
     c->q.assign(c->np, 0);
     if (hehost::gen_primes(c->nq, c->nk, prm->log_delta, c->q.data()) != 0) return HE_EINVAL;
     c->psi.resize(c->np);
@@ -1115,8 +1161,8 @@ he_status he_ctx_destroy(he_ctx *c)
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
     }
-    for (void *p : c->owned) (void)hipFree(p);
-    if (c->ws) (void)hipFree(c->ws);
+    for (void *p : c->owned) dev_free(c, p);
+    dev_free(c, c->ws);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     if (c->gstream) (void)hipStreamDestroy(c->gstream);
@@ -1141,9 +1187,10 @@ he_status he_ctx_primes(const he_ctx *c, uint64_t *out, int n)
 he_status he_ctx_trim(he_ctx *c)
 {
     if (!c) return HE_EINVAL;
+    TRY(drop_graphs(c, 0));
     if (c->ws) {
         HIPCHK(hipStreamSynchronize(c->stream));
-        HIPCHK(hipFree(c->ws));
+        dev_free(c, c->ws);
     }
     c->ws = nullptr;
     c->ws_bytes = 0;
@@ -1158,7 +1205,8 @@ size_t he_keys_bytes(const he_ctx *c, int n_rot)
 {
     if (!c || n_rot < 0) return 0;
     const size_t evk = (size_t)c->dnum * 2 * c->np * c->N * 8;
-    return (size_t)c->np * c->N * 8 + evk * (3 + (size_t)n_rot);
+    const size_t pk = (size_t)2 * c->nq * c->N * 8;
+    return (size_t)c->np * c->N * 8 + evk * (3 + (size_t)n_rot) + pk;
 }
 
 he_status he_keygen(he_ctx *c, uint64_t seed, const int32_t *rot_steps, int n_rot, void *key_buf,
@@ -1173,7 +1221,9 @@ he_status he_keygen(he_ctx *c, uint64_t seed, const int32_t *rot_steps, int n_ro
     TRY(ensure_ws(c, (al((size_t)np * N) * 4) * 8 + 4096));
     std::unique_ptr<he_keys> k(new (std::nothrow) he_keys());
     if (!k) return HE_ENOMEM;
+    static std::atomic<uint64_t> next_gen{1};
     k->ctx = c;
+    k->gen = next_gen++;
     k->sk = (u64 *)key_buf;
     k->rlk = k->sk + (size_t)np * N;
     k->rlk3 = k->rlk + evk_n;
@@ -1199,7 +1249,18 @@ he_status he_keygen(he_ctx *c, uint64_t seed, const int32_t *rot_steps, int n_ro
     TRY(make_evk(c, ar, seed, 2, k->sk, sq, k->rlk3));
     hek::ewise(c, 3, np - 1, 1, 1, sp, 0, 0, sp, 0, 0, sq, 0, 0, 0);
     TRY(make_evk(c, ar, seed, 4, k->sk, sq, k->rlk4));
-    u64 *next = k->rlk4 + evk_n;
+    // public key (-a s + e, a) over q_0 .. q_{nq-1} (Alg. 1's worker key)
+    k->pk = k->rlk4 + evk_n;
+    {
+        u64 *pb = k->pk, *pa = k->pk + (size_t)c->nq * N;
+        std::vector<int> qi = identity_positions(c->nq);
+        hek::sample_uniform(c, seed, ST_PK_A, 0, 0, c->nq, qi.data(), pa);
+        hek::ntt_batch(c, pa, 0, 0, 1, 1, 0, c->nq, c->nq - 1, +1, nullptr, false);
+        hek::sample_cbd(c, seed, ST_PK_E, 0, 0, c->nq, qi.data(), sq);
+        hek::ntt_batch(c, sq, 0, 0, 1, 1, 0, c->nq, c->nq - 1, +1, nullptr, false);
+        hek::enc_combine(c, c->nq - 1, pa, k->sk, sq, nullptr, pb);
+    }
+    u64 *next = k->pk + (size_t)2 * c->nq * N;
     for (int r = 0; r < n_rot; ++r) {
         u64 g = galois_of(c, rot_steps[r]);
         if (g == 1 || k->rot.count(g)) continue;
@@ -1217,7 +1278,11 @@ he_status he_keygen(he_ctx *c, uint64_t seed, const int32_t *rot_steps, int n_ro
 he_status he_keys_destroy(he_keys *k)
 {
     if (!k) return HE_EINVAL;
+    // graphs captured with these keys hold their device addresses: a later key
+    // set may be given the same host handle or buffer
+    const he_status st = k->ctx ? drop_graphs(k->ctx, k->gen) : HE_OK;
     delete k;
+    if (st != HE_OK) return st;
     return HE_OK;
 }
 
@@ -1228,20 +1293,25 @@ he_status he_keys_download(he_ctx *c, const he_keys *k, int64_t which, uint64_t 
     const int np = c->np;
     const u64 *src;
     int npoly;
+    int nlimb = np;
     if (which == -2) {
         src = k->sk;
         npoly = 1;
+    } else if (which == -5) {
+        src = k->pk;
+        npoly = 2;
+        nlimb = c->nq;
     } else {
         src = which == -1 ? k->rlk : which == -3 ? k->rlk3 : which == -4 ? k->rlk4 : find_rot_key(k, (u64)which);
         if (!src) return HE_EKEY;
         npoly = c->dnum * 2;
     }
-    const size_t n = (size_t)npoly * np * N;
+    const size_t n = (size_t)npoly * nlimb * N;
     TRY(ensure_ws(c, al(n) * 8 + 4096));
     Arena ar = arena(c);
     u64 *t = ar.take(n);
     HIPCHK(hipMemcpyAsync(t, src, n * 8, hipMemcpyDeviceToDevice, c->stream));
-    hek::ntt_batch(c, t, (long long)np * N, 0, npoly, 1, 0, np, c->nq - 1, -1, nullptr, false);
+    hek::ntt_batch(c, t, (long long)nlimb * N, 0, npoly, 1, 0, nlimb, c->nq - 1, -1, nullptr, false);
     HIPCHK(hipMemcpyAsync(host, t, n * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return last_error();
@@ -1277,16 +1347,35 @@ he_status he_pt_load(he_ctx *c, const int64_t *coeffs, int level, double scale, 
     return last_error();
 }
 
-he_status he_encrypt(he_ctx *c, const he_pt *pt, const he_keys *k, uint64_t seed, uint32_t index, he_ct *out)
+he_status he_encrypt(he_ctx *c, const he_pt *pt, const he_keys *k, int use_sk, uint64_t seed, uint32_t index,
+                     he_ct *out)
 {
     if (!c || !pt || !k || !out || !pt->data || !out->data || pt->level < 0 || pt->level >= c->nq) return HE_EINVAL;
     const int l = pt->level;
     const size_t N = c->N;
-    TRY(ensure_ws(c, al((size_t)(l + 1) * N) * 8 + 4096));
-    Arena ar = arena(c);
-    u64 *e = ar.take((size_t)(l + 1) * N);
-    u64 *b = out->data, *a = out->data + (size_t)(l + 1) * N;
+    const size_t n = (size_t)(l + 1) * N;
+    u64 *b = out->data, *a = out->data + n;
     std::vector<int> ids = identity_positions(l + 1);
+    if (!use_sk) {
+        // (v pk_b + e0 + m, v pk_a + e1), v ternary, e0 and e1 centred binomial
+        TRY(ensure_ws(c, 3 * al(n) * 8 + 4096));
+        Arena ar = arena(c);
+        u64 *v = ar.take(n), *e0 = ar.take(n), *e1 = ar.take(n);
+        if (!v || !e0 || !e1) return HE_ENOMEM;
+        hek::sample_ternary(c, seed, ST_ENC_V, index, 0, l + 1, ids.data(), v);
+        hek::sample_cbd(c, seed, ST_ENC_E0, index, 0, l + 1, ids.data(), e0);
+        hek::sample_cbd(c, seed, ST_ENC_E1, index, 0, l + 1, ids.data(), e1);
+        hek::ntt_batch(c, v, 0, 0, 1, 1, 0, l + 1, l, +1, nullptr, false);
+        hek::ntt_batch(c, e0, 0, 0, 1, 1, 0, l + 1, l, +1, nullptr, false);
+        hek::ntt_batch(c, e1, 0, 0, 1, 1, 0, l + 1, l, +1, nullptr, false);
+        hek::encpk_combine(c, l, v, k->pk, e0, e1, pt->data, b, a);
+        out->level = l;
+        out->scale = pt->scale;
+        return last_error();
+    }
+    TRY(ensure_ws(c, al(n) * 8 + 4096));
+    Arena ar = arena(c);
+    u64 *e = ar.take(n);
     hek::sample_uniform(c, seed, ST_ENC_A, index, 0, l + 1, ids.data(), a);
     hek::ntt_batch(c, a, 0, 0, 1, 1, 0, l + 1, l, +1, nullptr, false);
     hek::sample_cbd(c, seed, ST_ENC_E0, index, 0, l + 1, ids.data(), e);
@@ -1602,13 +1691,13 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
         std::ostringstream key;
         key << "step:" << (const void *)Z[0].data << ':' << zbs << ':' << n_blocks << ':' << lz << ':'
             << (const void *)W->data << ':' << l << ':' << (const void *)mask->data << ':' << cols << ':'
-            << (const void *)k << ':' << (const void *)W_out->data << ':'
+            << k->gen << ':' << (const void *)k->sk << ':' << (const void *)W_out->data << ':'
             << (const void *)(G_out ? G_out->data : nullptr) << ':' << pl.k0 << ':' << pl.k1 << ':' << pl.k2 << ':'
             << pl.k3 << ':' << pl.kb1 << ':' << pl.kw << ':' << (const void *)c->ws << ':' << layout << ':' << n_baby
             << ':' << (const void *)bd.zr << ':' << bd.zrb << ':' << bd.zrs << ':' << bd.zrc << ':'
             << (const void *)td.z3 << ':' << td.z3s << ':' << (const void *)td.z1 << ':' << td.z1s << ':'
             << (const void *)td.z2;
-        TRY(run_graph(c, key.str(), [&] {
+        TRY(run_graph(c, key.str(), k->gen, [&] {
             return step_impl(c, pl, Z, n_blocks, zbs, bd, td, W, mask, cols, rows, k, chunk, W_out, G_out);
         }));
     } else {
@@ -1788,11 +1877,11 @@ he_status he_batch_mul_rotate(he_ctx *c, const he_ct *x, const he_ct *y, const i
     TRY(ensure_ws(c, need));
     if (mode == 2) {
         std::ostringstream key;
-        key << "batch:" << n << ':' << (const void *)k << ':' << (const void *)c->ws;
+        key << "batch:" << n << ':' << k->gen << ':' << (const void *)k->sk << ':' << (const void *)c->ws;
         for (int i = 0; i < n; ++i)
             key << ':' << (const void *)x[i].data << ',' << (const void *)y[i].data << ',' << (const void *)out[i].data
                 << ',' << x[i].level << ',' << gal[i];
-        TRY(run_graph(c, key.str(), [&] { return batch_impl(c, x, y, gal.data(), k, chunk, groups, out); }));
+        TRY(run_graph(c, key.str(), k->gen, [&] { return batch_impl(c, x, y, gal.data(), k, chunk, groups, out); }));
     } else {
         TRY(batch_impl(c, x, y, gal.data(), k, chunk, groups, out));
     }
@@ -1817,8 +1906,11 @@ size_t he_lr_margins_bytes(const he_ctx *c, int level, int n_blocks, int mode)
     return margins_bytes(c, level, mode == 0 ? 1 : n_blocks);
 }
 
-he_status he_lr_margins(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, int cols, int rows, int layout,
-                        const he_keys *k, int mode, he_ct *out)
+// Argument checks shared by he_lr_margins and he_lr_infer (before any launch):
+// Z and out uniform strides (out at level out_level), levels, the margin keys.
+he_status margins_args(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, int cols, int rows, int layout,
+                       const he_keys *k, int mode, const he_ct *out, int min_level, int out_level, long long &zbs,
+                       long long &obs)
 {
     if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !k || !out || !out[0].data || mode < 0 || mode > 2)
         return HE_EINVAL;
@@ -1826,10 +1918,11 @@ he_status he_lr_margins(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W,
     if (cols < 1 || rows < 1 || (cols & (cols - 1)) || (rows & (rows - 1)) || (long long)cols * rows != c->N / 2)
         return HE_EINVAL;
     const int l = W->level;
-    if (l < 1) return HE_ELEVEL;
+    if (l < min_level) return HE_ELEVEL;
     const int lz = Z[0].level;
     const double sz = Z[0].scale;
-    long long zbs = 0, obs = 0;
+    zbs = 0;
+    obs = 0;
     for (int b = 0; b < n_blocks; ++b) {
         if (!ct_ok(c, &Z[b]) || Z[b].level != lz || Z[b].scale != sz) return Z[b].level != lz ? HE_ELEVEL : HE_EINVAL;
         if (!out[b].data) return HE_EINVAL;
@@ -1840,20 +1933,88 @@ he_status he_lr_margins(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W,
         if (b > 1 && (Z[b].data - Z[b - 1].data != zbs || out[b].data - out[b - 1].data != obs)) return HE_EINVAL;
     }
     if (lz < l) return HE_ELEVEL;
-    if (n_blocks > 1 && (zbs < 2LL * (lz + 1) * c->N || obs < 2LL * l * c->N)) return HE_EINVAL;
+    if (n_blocks > 1 && (zbs < 2LL * (lz + 1) * c->N || obs < 2LL * (out_level + 1) * c->N)) return HE_EINVAL;
+    const long long unit = layout == HE_LAYOUT_FEATURES ? rows : 1;
+    for (int t = 1; t < cols; t <<= 1)
+        if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
+    return HE_OK;
+}
+
+// p(u) of he_lr_infer for nb blocks: u [nb][2][l][N] (level l-1, batch stride
+// us) -> out [nb][2][l-2][N] (level l-3, batch stride os); see he_plan_lr_infer
+he_status infer_poly(he_ctx *c, Arena &ar, const he_infer_plan &pl, int nb, const u64 *u, long long us, u64 *out,
+                     long long os, const u64 *rlk)
+{
+    const long long N = c->N;
+    const int l1 = pl.level_in - 1, l2 = l1 - 1;  // u's level, then U2's and H's
+    const long long c1 = (long long)(l1 + 1) * N, c2 = (long long)(l2 + 1) * N, c3 = (long long)l2 * N;
+    const size_t mark = ar.off;
+    u64 *T3 = ar.take((size_t)nb * 3 * c1);
+    u64 *U2 = ar.take((size_t)nb * 2 * c2);
+    u64 *Hb = ar.take((size_t)nb * 2 * c2);
+    u64 *Lb = ar.take((size_t)nb * 2 * c3);
+    if (!T3 || !U2 || !Hb || !Lb) return HE_ENOMEM;
+    // U2 = RS(relin(u u))
+    hek::tensor_b(c, l1, nb, u, us, c1, u, us, c1, T3, 3 * c1, c1);
+    TRY(relin_rescale_apply(c, ar, l1, nb, T3, 3 * c1, rlk, U2, 2 * c2));
+    // H = RS(k3 u) + k2c
+    TRY(rescale_apply(c, ar, l1, nb, u, us, Hb, 2 * c2, 2, &pl.k3));
+    if (pl.k2c != 0) hek::ewise(c, 5, l2, nb, 1, Hb, 2 * c2, 0, nullptr, 0, 0, Hb, 2 * c2, 0, pl.k2c);
+    // out = RS(relin(H U2)) + RS(k1 u) + k0c
+    hek::tensor_b(c, l2, nb, Hb, 2 * c2, c2, U2, 2 * c2, c2, T3, 3 * c2, c2);
+    TRY(relin_rescale_apply(c, ar, l2, nb, T3, 3 * c2, rlk, out, os));
+    TRY(rescale_apply(c, ar, l2, nb, u, us, Lb, 2 * c3, 2, &pl.k1, c1));
+    hek::ewise(c, 0, l2 - 1, nb, 2, out, os, c3, Lb, 2 * c3, c3, out, os, c3, 0);
+    if (pl.k0c != 0) hek::ewise(c, 5, l2 - 1, nb, 1, out, os, 0, nullptr, 0, 0, out, os, 0, pl.k0c);
+    ar.off = mark;
+    return last_error();
+}
+
+size_t infer_bytes(const he_ctx *c, int l, int nb)
+{
+    const size_t N = c->N;
+    size_t n = al((size_t)nb * 2 * l * N);  // the margins
+    const size_t poly = al((size_t)nb * 3 * l * N) + 2 * al((size_t)nb * 2 * (l - 1) * N) +
+                        al((size_t)nb * 2 * (l - 2) * N) +
+                        std::max(relin_rescale_scratch(c, l - 1, nb), rescale_scratch(c, l - 1, nb));
+    return n * 8 + std::max(margins_bytes(c, l, nb), poly * 8 + 4096);
+}
+
+he_status infer_impl(he_ctx *c, const he_infer_plan &pl, const he_ct *Z, int n_blocks, long long zbs, const he_ct *W,
+                     long long unit, int count, const he_keys *keys, int chunk, u64 *out, long long obs)
+{
+    const long long N = c->N;
+    const int l = W->level;
+    for (int b0 = 0; b0 < n_blocks; b0 += chunk) {
+        const int nb = std::min(chunk, n_blocks - b0);
+        Arena ar = arena(c);
+        u64 *U = ar.take((size_t)nb * 2 * l * N);
+        if (!U) return HE_ENOMEM;
+        TRY(margins_impl(c, Z + b0, nb, zbs, W, unit, count, keys, nb, U, 2LL * l * N, ar.off));
+        TRY(infer_poly(c, ar, pl, nb, U, 2LL * l * N, out + b0 * obs, obs, keys->rlk));
+    }
+    return last_error();
+}
+
+he_status he_lr_margins(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, int cols, int rows, int layout,
+                        const he_keys *k, int mode, he_ct *out)
+{
+    long long zbs = 0, obs = 0;
+    TRY(margins_args(c, Z, n_blocks, W, cols, rows, layout, k, mode, out, 1, W ? W->level - 1 : 0, zbs, obs));
+    const int l = W->level;
+    const int lz = Z[0].level;
+    const double sz = Z[0].scale;
     const bool fm = layout == HE_LAYOUT_FEATURES;
     const long long unit = fm ? rows : 1;
     const int count = cols;
-    for (int t = 1; t < count; t <<= 1)
-        if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
     const int chunk = mode == 0 ? 1 : n_blocks;
     TRY(ensure_ws(c, margins_bytes(c, l, chunk)));
     if (mode == 2) {
         std::ostringstream key;
         key << "margins:" << (const void *)Z[0].data << ':' << zbs << ':' << n_blocks << ':' << lz << ':'
-            << (const void *)W->data << ':' << l << ':' << cols << ':' << layout << ':' << (const void *)k << ':'
-            << (const void *)out[0].data << ':' << obs << ':' << (const void *)c->ws;
-        TRY(run_graph(c, key.str(),
+            << (const void *)W->data << ':' << l << ':' << cols << ':' << layout << ':' << k->gen << ':'
+            << (const void *)k->sk << ':' << (const void *)out[0].data << ':' << obs << ':' << (const void *)c->ws;
+        TRY(run_graph(c, key.str(), k->gen,
                       [&] { return margins_impl(c, Z, n_blocks, zbs, W, unit, count, k, chunk, out[0].data, obs); }));
     } else {
         TRY(margins_impl(c, Z, n_blocks, zbs, W, unit, count, k, chunk, out[0].data, obs));
@@ -1862,6 +2023,44 @@ he_status he_lr_margins(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W,
     for (int b = 0; b < n_blocks; ++b) {
         out[b].level = l - 1;
         out[b].scale = so;
+    }
+    return last_error();
+}
+
+he_status he_plan_lr_infer(const uint64_t *q, int n_q, int level, double s_z, double s_w, const double coef[4],
+                           he_infer_plan *out)
+{
+    if (!q || !coef || !out || n_q < 1) return HE_EINVAL;
+    return hehost::plan_lr_infer(q, n_q, level, s_z, s_w, coef, out);
+}
+
+he_status he_lr_infer(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, int cols, int rows, int layout,
+                      const double *coef, const he_keys *k, int mode, he_ct *out)
+{
+    if (!coef) return he_lr_margins(c, Z, n_blocks, W, cols, rows, layout, k, mode, out);
+    long long zbs = 0, obs = 0;
+    TRY(margins_args(c, Z, n_blocks, W, cols, rows, layout, k, mode, out, 3, W ? W->level - 3 : 0, zbs, obs));
+    const int l = W->level;
+    he_infer_plan pl;
+    TRY(hehost::plan_lr_infer(c->q.data(), c->nq, l, Z[0].scale, W->scale, coef, &pl));
+    const long long unit = layout == HE_LAYOUT_FEATURES ? rows : 1;
+    const int chunk = mode == 0 ? 1 : n_blocks;
+    TRY(ensure_ws(c, infer_bytes(c, l, chunk)));
+    if (mode == 2) {
+        std::ostringstream key;
+        key << "infer:" << (const void *)Z[0].data << ':' << zbs << ':' << n_blocks << ':' << Z[0].level << ':'
+            << (const void *)W->data << ':' << l << ':' << cols << ':' << layout << ':' << k->gen << ':'
+            << (const void *)k->sk << ':' << (const void *)out[0].data << ':' << obs << ':' << (const void *)c->ws
+            << ':' << pl.k3 << ':' << pl.k2c << ':' << pl.k1 << ':' << pl.k0c;
+        TRY(run_graph(c, key.str(), k->gen, [&] {
+            return infer_impl(c, pl, Z, n_blocks, zbs, W, unit, cols, k, chunk, out[0].data, obs);
+        }));
+    } else {
+        TRY(infer_impl(c, pl, Z, n_blocks, zbs, W, unit, cols, k, chunk, out[0].data, obs));
+    }
+    for (int b = 0; b < n_blocks; ++b) {
+        out[b].level = l - 3;
+        out[b].scale = pl.s_p;
     }
     return last_error();
 }

@@ -55,6 +55,7 @@ struct DeviceTables {
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    uint64_t keys_gen = 0;  // generation of the key set the captured launches read
 };
 
 struct he_ctx {
@@ -62,8 +63,11 @@ struct he_ctx {
     int N, logN, nq, nk, np, alpha, dnum;
     std::vector<u64> q, psi;
     hipStream_t stream;
+    he_alloc_fn alloc_fn = nullptr;  // caller's device allocator (null: hipMalloc / hipFree)
+    he_free_fn free_fn = nullptr;
+    void *alloc_user = nullptr;
     DeviceTables t;
-    std::vector<void *> owned;  // device allocations of the tables
+    std::vector<void *> owned;  // device allocations of the tables (through the allocator)
     void *ws = nullptr;         // scratch workspace
     size_t ws_bytes = 0;
     std::map<std::string, GraphEntry> graphs;
@@ -74,9 +78,11 @@ struct he_ctx {
 
 struct he_keys {
     he_ctx *ctx;
+    uint64_t gen;                   // unique per key set (graph-cache key; never reused)
     u64 *sk;                        // [np][N] NTT
     u64 *rlk;                       // [dnum][2][np][N] NTT: s^2 -> s
     u64 *rlk3, *rlk4;               // the same for s^3 and s^4 (degree-4 relinearisation)
+    u64 *pk;                        // [2][nq][N] NTT: the public key (-a s + e, a)
     std::map<uint64_t, u64 *> rot;  // Galois element -> key
 };
 
@@ -94,9 +100,12 @@ int encode(int logN, const double *re, const double *im, int n, double scale, i6
 void decode(int logN, const double *m, double scale, int n, double *re, double *im);
 he_status plan_lr_step(const u64 *q, int n_q, int level, double s_z, double s_w, const double coef[4],
                        double eta_over_n, double w_decay, int layout, he_lr_plan *o);
+he_status plan_lr_infer(const u64 *q, int n_q, int level, double s_z, double s_w, const double coef[4],
+                        he_infer_plan *o);
 }  // namespace hehost
 
-enum { ST_SECRET = 1, ST_PK_A = 2, ST_PK_E = 3, ST_EVK_A = 4, ST_EVK_E = 5, ST_ENC_A = 6, ST_ENC_E0 = 7 };
+enum { ST_SECRET = 1, ST_PK_A = 2, ST_PK_E = 3, ST_EVK_A = 4, ST_EVK_E = 5, ST_ENC_A = 6, ST_ENC_E0 = 7,
+       ST_ENC_V = 8, ST_ENC_E1 = 9 };
 
 // ------------------------------------------------------------------ launchers (kernels.hip)
 // Batched operands are addressed as base + b * (batch stride) + c * (component
@@ -122,7 +131,8 @@ void ntt_rescale(he_ctx *c, int level, int B, int ncomp, const u64 *last, const 
                  u64 *tmp, u64 *out, long long os, const i64 *kmul);
 void intt_last(he_ctx *c, int level, int B, int ncomp, const u64 *in, long long is, long long ics, u64 *last,
                const i64 *kmul);
-// op 0 add, 1 sub, 2 multiply by integer k, 3 multiply by plaintext y ([pos][N]), 4 copy;
+// op 0 add, 1 sub, 2 multiply by integer k, 3 multiply by plaintext y ([pos][N]), 4 copy,
+// 5 add the integer k to every coefficient (a constant polynomial, NTT form);
 // positions 0..level of nbatch x ncomp polys.
 void ewise(he_ctx *c, int op, int level, int nbatch, int ncomp, const u64 *x, long long xb, long long xc,
            const u64 *y, long long yb, long long yc, u64 *o, long long ob, long long oc, i64 k);
@@ -207,8 +217,15 @@ void sample_uniform(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t
 void sample_cbd(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp, int n_pos,
                 const int *prime_of_pos, u64 *out);
 void int_to_rns(he_ctx *c, const i64 *m, int n_pos, const int *prime_of_pos, u64 *out);
+// ternary v: word x of the stream, bit 0 clear -> 0, else bit 1 ? -1 : +1
+void sample_ternary(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp, int n_pos,
+                    const int *prime_of_pos, u64 *out);
+// public-key encryption combine (NTT): b = v pk_b + e0 + m, a = v pk_a + e1 on limbs 0..level
+void encpk_combine(he_ctx *c, int level, const u64 *v, const u64 *pk, const u64 *e0, const u64 *e1, const u64 *m,
+                   u64 *b, u64 *a);
 // key generation / encryption / decryption combines (NTT domain)
 void evk_combine(he_ctx *c, const u64 *a, const u64 *s, const u64 *e, const u64 *sp, int digit, u64 *b);
+// b = -a s + e + m (m nullable: the public key's b)
 void enc_combine(he_ctx *c, int level, const u64 *a, const u64 *s, const u64 *e, const u64 *m, u64 *b);
 void dec_combine(he_ctx *c, int level, const u64 *ct, const u64 *s, u64 *out);
 }  // namespace hek

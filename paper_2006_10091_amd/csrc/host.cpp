@@ -418,4 +418,38 @@ he_status plan_lr_step(const u64 *q, int n_q, int level, double s_z, double s_w,
     return finish_plan(k0, k1, k2, k3, kb1, kw, o);
 }
 
+// Encrypted inference with the polynomial: the margins u (level l-1, scale
+// s_u = s_z s_w / q_l) go through p(u) = a0 + a1 u + a2 u^2 + a3 u^3 as
+//   U2 = RS(relin(u u))                 level l-2, scale s_u2
+//   H  = RS(k3 u) + k2c                 level l-2, declared s_h
+//   P  = RS(relin(H U2)) + RS(k1 u) + k0c   level l-3, declared s_p = s_u
+// with the integers chosen so that every term carries s_p.  Each expression is
+// evaluated left to right as written.
+he_status plan_lr_infer(const u64 *q, int n_q, int level, double s_z, double s_w, const double coef[4],
+                        he_infer_plan *o)
+{
+    if (level < 3 || level >= n_q) return HE_ELEVEL;
+    if (!(s_z > 0.0) || !(s_w > 0.0)) return HE_ESCALE;
+    std::memset(o, 0, sizeof *o);
+    o->level_in = level;
+    o->level_out = level - 3;
+    const double ql = (double)q[level], q1 = (double)q[level - 1], q2 = (double)q[level - 2];
+    o->s_u = s_z * s_w / ql;
+    o->s_u2 = o->s_u * o->s_u / q1;
+    o->s_p = o->s_u;
+    o->s_h = o->s_p * q2 / o->s_u2;
+    const double k3 = coef[3] * o->s_h * q1 / o->s_u;
+    const double k2c = coef[2] * o->s_h;
+    const double k1 = coef[1] * o->s_p * q2 / o->s_u;
+    const double k0c = coef[0] * o->s_p;
+    const double kmax = 4.611686018427388e18;  // 2^62
+    for (double k : {k3, k2c, k1, k0c})
+        if (!(std::fabs(k) < kmax)) return HE_ESCALE;
+    o->k3 = std::llround(k3);
+    o->k2c = std::llround(k2c);
+    o->k1 = std::llround(k1);
+    o->k0c = std::llround(k0c);
+    return HE_OK;
+}
+
 }  // namespace hehost

@@ -1094,7 +1094,8 @@ __device__ __forceinline__ long long ew_off(long long bs, long long cs, int b, i
     return (long long)b * bs + (long long)c * cs + ((long long)pos << logN);
 }
 
-// op: 0 add, 1 sub, 2 mul by integer, 3 mul by plaintext (y: [pos][N], no batch/comp), 4 copy
+// op: 0 add, 1 sub, 2 mul by integer, 3 mul by plaintext (y: [pos][N], no batch/comp), 4 copy,
+// 5 add the integer k to every coefficient (NTT form: a constant polynomial)
 template <int OP>
 __global__ __launch_bounds__(256) void ew_kernel(EwArgs a, const PrimeInfo *__restrict__ pinfo, i64 k)
 {
@@ -1109,7 +1110,7 @@ __global__ __launch_bounds__(256) void ew_kernel(EwArgs a, const PrimeInfo *__re
     if (OP == 0 || OP == 1) y = a.y + ew_off(a.yb, a.yc, b, c, pos, a.logN);
     if (OP == 3) y = a.y + ((long long)pos << a.logN);
     u64 kq = 0;
-    if (OP == 2) {
+    if (OP == 2 || OP == 5) {
         u64 mag = k < 0 ? (u64)(-(k + 1)) + 1 : (u64)k;
         kq = reduce64(mag, p);
         if (k < 0) kq = neg_mod(kq, p.q);
@@ -1120,6 +1121,7 @@ __global__ __launch_bounds__(256) void ew_kernel(EwArgs a, const PrimeInfo *__re
         else if (OP == 1) v = sub_mod(x[i], y[i], p.q);
         else if (OP == 2) v = mul_mod(x[i], kq, p);
         else if (OP == 3) v = mul_mod(x[i], y[i], p);
+        else if (OP == 5) v = add_mod(x[i], kq, p.q);
         else v = x[i];
         o[i] = v;
     }
@@ -2194,6 +2196,27 @@ __global__ __launch_bounds__(256) void cbd_kernel(u64 seed, uint32_t type, uint3
     }
 }
 
+// ternary with P(0) = 1/2, P(+-1) = 1/4 from word x: bit 0 clear -> 0, else bit 1 ? -1 : +1
+__global__ __launch_bounds__(256) void ternary_kernel(u64 seed, uint32_t type, uint32_t index, uint32_t comp,
+                                                      PosPrimes pp, const PrimeInfo *__restrict__ pinfo,
+                                                      u64 *__restrict__ out, int logN)
+{
+    const int N = 1 << logN;
+    const int nblk = N / 8;
+    for (int blk = blockIdx.x * 256 + threadIdx.x; blk < nblk; blk += gridDim.x * 256) {
+        uint32_t w[16];
+        chacha_block((uint32_t)seed, (uint32_t)(seed >> 32), (uint32_t)blk, type, index, comp, w);
+        for (int c = 0; c < 8; ++c) {
+            const uint32_t lo = w[2 * c];
+            const int t = (lo & 1) ? ((lo & 2) ? -1 : 1) : 0;
+            for (int pos = 0; pos < pp.n; ++pos) {
+                const u64 q = pinfo[pp.prime[pos]].q;
+                out[((long long)pos << logN) + 8 * blk + c] = t >= 0 ? (u64)t : q - 1;
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void int_to_rns_kernel(const i64 *__restrict__ m, PosPrimes pp,
                                                          const PrimeInfo *__restrict__ pinfo, u64 *__restrict__ out,
                                                          int logN)
@@ -2237,7 +2260,25 @@ __global__ __launch_bounds__(256) void enc_kernel(const u64 *__restrict__ a, con
     const PrimeInfo p = pinfo[i];
     const long long off = (long long)i << logN;
     for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256)
-        b[off + x] = add_mod(sub_mod(e[off + x], mul_mod(a[off + x], s[off + x], p), p.q), m[off + x], p.q);
+        b[off + x] = add_mod(sub_mod(e[off + x], mul_mod(a[off + x], s[off + x], p), p.q), m ? m[off + x] : 0, p.q);
+}
+
+// public-key encryption: b = v pk_b + e0 + m, a = v pk_a + e1 (pk component stride pkc)
+__global__ __launch_bounds__(256) void encpk_kernel(const u64 *__restrict__ v, const u64 *__restrict__ pk,
+                                                    long long pkc, const u64 *__restrict__ e0,
+                                                    const u64 *__restrict__ e1, const u64 *__restrict__ m,
+                                                    const PrimeInfo *__restrict__ pinfo, u64 *__restrict__ b,
+                                                    u64 *__restrict__ a, int logN)
+{
+    const int i = blockIdx.y;
+    const int N = 1 << logN;
+    const PrimeInfo p = pinfo[i];
+    const long long off = (long long)i << logN;
+    for (int x = blockIdx.x * 256 + threadIdx.x; x < N; x += gridDim.x * 256) {
+        const u64 vx = v[off + x];
+        b[off + x] = add_mod(add_mod(mul_mod(vx, pk[off + x], p), e0[off + x], p.q), m[off + x], p.q);
+        a[off + x] = add_mod(mul_mod(vx, pk[pkc + off + x], p), e1[off + x], p.q);
+    }
 }
 
 __global__ __launch_bounds__(256) void dec_kernel(const u64 *__restrict__ ct, const u64 *__restrict__ s,
@@ -2544,6 +2585,7 @@ static void ew(he_ctx *c, int op, const EwArgs &a, int npos, int nbatch, i64 k)
     case 1: ew_kernel<1><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
     case 2: ew_kernel<2><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
     case 3: ew_kernel<3><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
+    case 5: ew_kernel<5><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
     default: ew_kernel<4><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
     }
 }
@@ -2873,6 +2915,21 @@ void evk_combine(he_ctx *c, const u64 *a, const u64 *s, const u64 *e, const u64 
     int d0 = digit * c->alpha, d1 = std::min(d0 + c->alpha, c->nq);
     dim3 g(xblocks(c->N), c->np, 1);
     evk_kernel<<<g, 256, 0, c->stream>>>(a, s, e, sp, c->t.dn_p, c->t.pinfo, d0, d1, b, c->logN);
+}
+
+void sample_ternary(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp, int n_pos,
+                    const int *prime_of_pos, u64 *out)
+{
+    dim3 g(std::max(1, c->N / 8 / 256), 1, 1);
+    ternary_kernel<<<g, 256, 0, c->stream>>>(seed, type, index, comp, make_pp(n_pos, prime_of_pos), c->t.pinfo, out,
+                                             c->logN);
+}
+
+void encpk_combine(he_ctx *c, int level, const u64 *v, const u64 *pk, const u64 *e0, const u64 *e1, const u64 *m,
+                   u64 *b, u64 *a)
+{
+    dim3 g(xblocks(c->N), level + 1, 1);
+    encpk_kernel<<<g, 256, 0, c->stream>>>(v, pk, (long long)c->nq * c->N, e0, e1, m, c->t.pinfo, b, a, c->logN);
 }
 
 void enc_combine(he_ctx *c, int level, const u64 *a, const u64 *s, const u64 *e, const u64 *m, u64 *b)

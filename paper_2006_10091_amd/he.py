@@ -54,13 +54,18 @@ class he_lr_plan(ctypes.Structure):
         [("s_gsum", c_double), ("layout", c_int32), ("reserved", c_int32)]
 
 
+class he_infer_plan(ctypes.Structure):
+    _fields_ = [("level_in", c_int32), ("level_out", c_int32)] + \
+        [(n, c_double) for n in ("s_u", "s_u2", "s_h", "s_p")] + [(n, c_int64) for n in ("k3", "k2c", "k1", "k0c")]
+
+
 LAYOUT_ROWS, LAYOUT_FEATURES = 0, 1  # HE_LAYOUT_ROWS / HE_LAYOUT_FEATURES
 
 
 _P = POINTER
 _sig = {
     "he_strerror": (ctypes.c_char_p, [c_int]),
-    "he_ctx_create": (c_int, [_P(he_params), c_void_p, _P(c_void_p)]),
+    "he_ctx_create": (c_int, [_P(he_params), c_void_p, c_void_p, c_void_p, c_void_p, _P(c_void_p)]),
     "he_ctx_destroy": (c_int, [c_void_p]),
     "he_ctx_set_stream": (c_int, [c_void_p, c_void_p]),
     "he_ctx_primes": (c_int, [c_void_p, _P(c_uint64), c_int]),
@@ -76,7 +81,7 @@ _sig = {
     "he_encode": (c_int, [c_void_p, _P(c_double), _P(c_double), c_int, c_double, _P(c_int64)]),
     "he_decode": (c_int, [c_void_p, _P(c_double), c_double, c_int, _P(c_double), _P(c_double)]),
     "he_pt_load": (c_int, [c_void_p, _P(c_int64), c_int, c_double, _P(he_pt)]),
-    "he_encrypt": (c_int, [c_void_p, _P(he_pt), c_void_p, c_uint64, c_uint32, _P(he_ct)]),
+    "he_encrypt": (c_int, [c_void_p, _P(he_pt), c_void_p, c_int, c_uint64, c_uint32, _P(he_ct)]),
     "he_decrypt": (c_int, [c_void_p, _P(he_ct), c_void_p, _P(c_uint64)]),
     "he_decrypt_decode": (c_int, [c_void_p, _P(he_ct), c_void_p, c_int, _P(c_double), _P(c_double)]),
     "he_ct_download": (c_int, [c_void_p, _P(he_ct), _P(c_uint64)]),
@@ -102,6 +107,10 @@ _sig = {
                                     _P(he_ct)]),
     "he_lr_margins": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), c_int, c_int, c_int, c_void_p, c_int,
                               _P(he_ct)]),
+    "he_lr_infer": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), c_int, c_int, c_int, _P(c_double), c_void_p,
+                            c_int, _P(he_ct)]),
+    "he_plan_lr_infer": (c_int, [_P(c_uint64), c_int, c_int, c_double, c_double, _P(c_double),
+                                 _P(he_infer_plan)]),
     "he_lr_step_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int, c_int, c_int]),
     "he_lr_margins_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int]),
     "he_ntt": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
@@ -149,6 +158,15 @@ def plan_lr_step(primes, n_q, level, s_z, s_w, coef, eta_over_n, w_decay=0.0, la
     return {f[0]: getattr(out, f[0]) for f in he_lr_plan._fields_}
 
 
+def plan_lr_infer(primes, n_q, level, s_z, s_w, coef):
+    """Pure host schedule of he_lr_infer with the polynomial."""
+    q = np.ascontiguousarray(primes, dtype=np.uint64)
+    cf = np.ascontiguousarray(coef, dtype=np.float64)
+    out = he_infer_plan()
+    _chk(_lib.he_plan_lr_infer(_u64p(q), n_q, level, s_z, s_w, _f64p(cf), ctypes.byref(out)), "he_plan_lr_infer")
+    return {f[0]: getattr(out, f[0]) for f in he_infer_plan._fields_}
+
+
 class Ciphertext:
     """Device ciphertext (torch storage) + level and scale metadata."""
 
@@ -173,6 +191,40 @@ class Ciphertext:
 Plaintext = Ciphertext
 
 
+# he_alloc_fn / he_free_fn: the library's device memory comes from torch
+_ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_void_p, c_size_t)
+_FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
+class TorchMemory:
+    """Device memory provider of a context: every table and workspace the
+    library holds is a torch uint8 tensor kept alive here until released."""
+
+    def __init__(self, device):
+        self.device = device
+        self.live = {}
+        self.alloc_fn = _ALLOC_FN(self._alloc)
+        self.free_fn = _FREE_FN(self._free)
+
+    def _alloc(self, user, nbytes):
+        try:
+            t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=self.device)
+        except Exception:  # out of memory: the library returns HE_ENOMEM
+            return None
+        p = t.data_ptr()
+        self.live[p] = t
+        return p
+
+    def _free(self, user, ptr):
+        if self.live is not None:
+            self.live.pop(ptr, None)
+
+    @property
+    def bytes(self):
+        """Device bytes the context holds now (tables and workspace)."""
+        return sum(t.numel() for t in self.live.values())
+
+
 class Keys:
     def __init__(self, ctx, buf, handle, rot_steps):
         self.ctx, self.buf, self.handle, self.rot_steps = ctx, buf, handle, list(rot_steps)
@@ -184,7 +236,7 @@ class Keys:
 
     def download(self, which):
         c = self.ctx
-        n = c.np * c.N if which == -2 else c.dnum * 2 * c.np * c.N
+        n = c.np * c.N if which == -2 else 2 * c.n_q * c.N if which == -5 else c.dnum * 2 * c.np * c.N
         out = np.zeros(n, dtype=np.uint64)
         _chk(_lib.he_keys_download(c.h, self.handle, which, _u64p(out)), "he_keys_download")
         return out
@@ -198,7 +250,10 @@ class Context:
         p = he_params(log_n, n_q, n_special, alpha, log_delta)
         h = c_void_p()
         s = torch.cuda.current_stream().cuda_stream if stream is None else stream
-        _chk(_lib.he_ctx_create(ctypes.byref(p), c_void_p(s), ctypes.byref(h)), "he_ctx_create")
+        self.mem = TorchMemory(self.device)
+        _chk(_lib.he_ctx_create(ctypes.byref(p), ctypes.cast(self.mem.alloc_fn, c_void_p),
+                                ctypes.cast(self.mem.free_fn, c_void_p), None, c_void_p(s), ctypes.byref(h)),
+             "he_ctx_create")
         self.h = h
         self.log_n, self.n_q, self.n_special, self.alpha, self.log_delta = log_n, n_q, n_special, alpha, log_delta
         self.N = 1 << log_n
@@ -274,10 +329,12 @@ class Context:
         return out.update(s)
 
     # ------------------------------------------------------------ encryption
-    def encrypt(self, pt, keys, seed, index, out=None):
+    def encrypt(self, pt, keys, seed, index, out=None, use_sk=True):
+        """Secret-key (use_sk, Alg. 2's server) or public-key (Alg. 1's worker) encryption."""
         out = out or self.ct_empty(pt.level)
         p, s = pt.struct(), out.struct()
-        _chk(_lib.he_encrypt(self.h, ctypes.byref(p), keys.handle, seed, index, ctypes.byref(s)), "he_encrypt")
+        _chk(_lib.he_encrypt(self.h, ctypes.byref(p), keys.handle, 1 if use_sk else 0, seed, index, ctypes.byref(s)),
+             "he_encrypt")
         return out.update(s)
 
     def decrypt(self, ct, keys):
@@ -415,6 +472,22 @@ class Context:
         w = W.struct()
         _chk(_lib.he_lr_margins(self.h, zs, len(Z), ctypes.byref(w), cols, rows, layout, keys.handle, mode, os_),
              "he_lr_margins")
+        for o, s_ in zip(out, os_):
+            o.update(s_)
+        return out
+
+    def lr_infer(self, Z, W, cols, rows, keys, coef=None, mode=1, out=None, layout=LAYOUT_ROWS):
+        """he_lr_infer: the margins (coef None) or p(margins) slot by slot, per
+        block; out: list of len(Z) ciphertexts with one stride (ct_block) at
+        W.level - 1 (margins) or W.level - 3 (polynomial); allocated when None."""
+        lo = W.level - 1 if coef is None else W.level - 3
+        out = out or self.ct_block(len(Z), lo)
+        zs = ct_array(Z)
+        os_ = (he_ct * len(out))(*[o.struct() for o in out])
+        w = W.struct()
+        cf = np.ascontiguousarray(coef, dtype=np.float64) if coef is not None else None
+        _chk(_lib.he_lr_infer(self.h, zs, len(Z), ctypes.byref(w), cols, rows, layout,
+                              _f64p(cf) if cf is not None else None, keys.handle, mode, os_), "he_lr_infer")
         for o, s_ in zip(out, os_):
             o.update(s_)
         return out

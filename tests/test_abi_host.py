@@ -132,3 +132,23 @@ def test_packing_matches_oracle_layout():
             assert sorted(H.rotation_steps(16, 256, lay, nb)) == sorted(LR.rotation_steps(16, 256, lay, nb))
             assert sorted(H.rotation_steps(256, 128, lay, nb)) == sorted(LR.rotation_steps(256, 128, lay, nb))
         assert np.array_equal(H.unpack_weights(H.pack_weights(w, 4096, 16, lay), 16, 11, lay), w)
+
+
+@pytest.mark.parametrize("name", ["small", "image", "large"])
+@pytest.mark.parametrize("coef", [COEF, HINGE, [0.1, 0.2, 0.3, 0.0]])
+def test_inference_plan_matches_oracle_bit_for_bit(name, coef):
+    W = synth.WORKLOADS[name]
+    q = O.Params(W["logN"], W["nq"], W["nk"], W["alpha"], W["log_delta"]).q
+    delta = float(2 ** W["log_delta"])
+    for level in range(W["nq"] - 1, 2, -3):
+        for s_w in (delta, delta * 1.37):
+            a = LR.plan_lr_infer(q, level, delta, s_w, coef)
+            b = H.plan_lr_infer(q, W["nq"], level, delta, s_w, coef)
+            assert (b["level_in"], b["level_out"]) == (level, level - 3)
+            for k in ("s_u", "s_u2", "s_h", "s_p", "k3", "k2c", "k1", "k0c"):
+                assert a[k] == b[k], (level, k)
+    with pytest.raises(H.HEError) as e:
+        H.plan_lr_infer(q, W["nq"], 2, delta, delta, coef)
+    assert e.value.status == 3
+    with pytest.raises(LR.LevelError):
+        LR.plan_lr_infer(q, 2, delta, delta, coef)

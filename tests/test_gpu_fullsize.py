@@ -67,6 +67,38 @@ def test_full_size_keyswitch_ops_bit_exact(env, okeys):
         assert np.array_equal(ctx.download(ctx.rotate(z, t, gk)), O.rotate(P, O.CT(zd, level, 1.0), t, okeys).data)
 
 
+def _edge_ct(env, level, seed):
+    """Residues drawn only from {0, 1, (q-1)/2, (q+1)/2, q-1}: the centring
+    boundaries of the rescale and basis conversions and the extremes of the
+    lazy ranges."""
+    P = env["P"]
+    g = np.random.default_rng(seed)
+    d = np.zeros((2, level + 1, P.N), dtype=np.uint64)
+    for i, q in enumerate(P.q[: level + 1]):
+        edges = np.array([0, 1, (q - 1) // 2, (q + 1) // 2, q - 1], dtype=np.uint64)
+        d[:, i, :] = edges[g.integers(0, 5, size=(2, P.N))]
+    return d, env["ctx"].upload(d, level, 1.0)
+
+
+def test_full_size_edge_residues_bit_exact(env, okeys):
+    """mul -> relin -> rescale, a rotation and a hoisted rotation sum at N = 2^16
+    with 20 + 4 primes on edge-valued residues, bit for bit against the oracle."""
+    ctx, P, gk = env["ctx"], env["P"], env["gk"]
+    L = P.L
+    xd, x = _edge_ct(env, L, 1)
+    yd, y = _edge_ct(env, L, 2)
+    got = ctx.rescale(ctx.relin(ctx.mul(x, y), gk))
+    want = O.rescale(P, O.mul(P, O.CT(xd, L, 1.0), O.CT(yd, L, 1.0), okeys))
+    assert np.array_equal(ctx.download(got), want.data)
+    zd, z = _edge_ct(env, L - 1, 3)
+    t = env["c"] // 2
+    assert np.array_equal(ctx.download(ctx.rotate(z, t, gk)), O.rotate(P, O.CT(zd, L - 1, 1.0), t, okeys).data)
+    steps = [16 * env["r"] * g for g in (1, 2, 3)]  # giant steps of the feature-major margin sum
+    out = ctx.rotate_sum([z], steps, gk)
+    want = O.rotate_sum_hoisted(P, O.CT(zd, L - 1, 1.0), steps, okeys)
+    assert np.array_equal(ctx.download(out[0]), want.data)
+
+
 def _as_grid(H, slots, c, r, layout):
     """Decoded slots as [sample row, feature column]."""
     v = np.asarray(slots)

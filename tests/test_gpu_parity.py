@@ -649,6 +649,28 @@ def test_small_ring_unfused_path_bit_exact():
         assert np.array_equal(ctx.download(g), og.data), mode
 
 
+# ------------------------------------------------------------------ encoding
+@pytest.mark.parametrize("log_n,log_delta", [(13, 30), (16, 40)])
+def test_encode_matches_oracle_encode(small, log_n, log_delta):
+    """The library's host FP64 encode against the oracle's (a different FFT):
+    every coefficient within 1, and a constant exactly (round(c Delta), 0, ...)."""
+    H = small["H"]
+    ctx = small["ctx"] if log_n == 13 else H.Context(16, 3, 1, 1, 40)
+    N, S = 1 << log_n, 1 << (log_n - 1)
+    delta = float(2 ** log_delta)
+    g = np.random.default_rng(log_n)
+    for z in (g.uniform(-1, 1, S), g.uniform(-1, 1, S) + 1j * g.uniform(-1, 1, S), g.uniform(0, 1, S // 3)):
+        a = ctx.encode(z, delta)
+        b = O.encode(z, delta, N)
+        d = np.abs(a.astype(np.int64) - b.astype(np.int64))
+        assert d.max() <= 1 and np.count_nonzero(d) < N // 100
+    for cst in (0.75, -1.3125):
+        want = np.zeros(N, dtype=np.int64)
+        want[0] = int(round(cst * delta))
+        assert np.array_equal(ctx.encode(np.full(S, cst), delta), want)
+        assert np.array_equal(O.encode(np.full(S, cst), delta, N), want)
+
+
 # ------------------------------------------------------------------ encrypted inference (margins)
 @pytest.mark.parametrize("layout", [0, 1])
 def test_margins_bit_exact_and_decrypt_to_inner_products(small, layout):

@@ -94,3 +94,46 @@ def test_serving_results_identical_alone_and_in_the_mix():
         assert len(alone) == len(mix[q.rid])
         for a, b in zip(alone, mix[q.rid]):
             assert np.array_equal(a, b), q
+
+
+@pytest.mark.gpu
+def test_serving_chain_step_and_margins_bit_exact():
+    """The serving parameters (8 + 2 primes, two-prime digits, N = 2^15): one
+    gradient step and one margins call, as a serving lane runs them, bit for
+    bit against the oracle."""
+    import numpy as np
+    from oracle import ckks as O
+    from oracle import lr as LR
+    from paper_2006_10091_amd import he as H
+    from paper_2006_10091_amd import serve as SV
+    from paper_2006_10091_amd import synth
+    cfg = (15, SV.CHAIN["n_q"], SV.CHAIN["n_special"], SV.CHAIN["alpha"], SV.CHAIN["log_delta"])
+    P = O.Params(*cfg)
+    ctx = H.Context(*cfg)
+    n, d = 1500, 24
+    g = synth.rng(12)
+    X = g.uniform(0.0, 1.0, size=(n, d))
+    y = np.where(g.uniform(size=n) < 0.5, 1.0, -1.0)
+    blocks, c, r = LR.pack_blocks(X, y, P.S)
+    steps = LR.rotation_steps(c, r)
+    okeys, gk = O.Keys(P, 2019, rot_steps=steps), ctx.keygen(2019, steps)
+    L = P.L
+    oZ, gZ = [], ctx.ct_block(len(blocks), L)
+    for i in range(len(blocks)):
+        m = O.encode(blocks[i], P.delta, P.N)
+        oZ.append(O.encrypt_sk(P, okeys, m, L, P.delta, 8, i))
+        ctx.encrypt(ctx.pt_load(m, L, P.delta), gk, 8, i, out=gZ[i])
+    w = g.uniform(-0.05, 0.05, size=d)
+    mw = O.encode(LR.pack_weights(w, P.S, c), P.delta, P.N)
+    oW = O.encrypt_sk(P, okeys, mw, L, P.delta, 8, 999)
+    gW = ctx.encrypt(ctx.pt_load(mw, L, P.delta), gk, 8, 999)
+    coef = [0.5, -0.1501204134, 0.0, 0.0015930174]
+    pl = LR.plan_lr_step(P.q, L, P.delta, P.delta, coef, 1.0 / n)
+    mm = O.encode(LR.column_mask(P.S, c), pl["s_mask"], P.N)
+    oWn, og = LR.lr_grad_step(P, okeys, oZ, oW, mm, coef, 1.0 / n, c, r, plan=pl)
+    Wn, gg = ctx.lr_grad_step(gZ, gW, ctx.pt_load(mm, L - 1, pl["s_mask"]), coef, 1.0 / n, c, r, gk, mode=1)
+    assert np.array_equal(ctx.download(Wn), oWn.data) and np.array_equal(ctx.download(gg), og.data)
+    want = LR.lr_margins(P, okeys, oZ, oW, c, r)
+    got = ctx.lr_margins(gZ, gW, c, r, gk, mode=1)
+    for a, b in zip(got, want):
+        assert np.array_equal(ctx.download(a), b.data)
