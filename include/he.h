@@ -259,6 +259,23 @@ he_status he_rescale(he_ctx *ctx, const he_ct *in, he_ct *out);
 /* Left rotation of the slots by `steps` (automorphism X -> X^(5^steps) and a key
  * switch back to s).  HE_EKEY if that rotation key was not generated. */
 he_status he_rotate(he_ctx *ctx, const he_ct *in, int steps, const he_keys *keys, he_ct *out);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): he_rotate
+ * with its scratch taken from a fixed array of HE_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each device until the process ends, so the call
+ * allocates nothing (no hipMalloc, no allocator callback).  Arguments,
+ * layout and results as he_rotate (bit-identical), out distinct from in.
+ * HE_ENOMEM when the rotation needs more scratch than the array holds
+ * (he_rotate_noalloc_bytes(ctx, level) > HE_NOALLOC_SCRATCH_BYTES; at
+ * N = 2^16 with 4 special primes in 4-prime digits, levels up to 9).  No
+ * buffer of the array needs to start at zero.  Every call on one device
+ * shares that device's array: calls that overlap on one device (other
+ * streams, other threads, other contexts) race and give wrong results;
+ * serialise them. */
+#define HE_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+he_status he_rotate_noalloc(he_ctx *ctx, const he_ct *in, int steps, const he_keys *keys, he_ct *out);
+size_t he_rotate_noalloc_bytes(const he_ctx *ctx, int level);
+
 /* out = x + y (same level; HE_ESCALE unless the scales are equal). */
 he_status he_add(he_ctx *ctx, const he_ct *x, const he_ct *y, he_ct *out);
 /* out = k * x for an integer k, |k| < 2^62; out->scale = out_scale (the caller

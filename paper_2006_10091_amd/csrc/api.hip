@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <map>
 #include <sstream>
@@ -35,6 +36,28 @@ struct Arena {
 };
 
 inline size_t al(size_t n_u64) { return ((n_u64 * 8 + 255) & ~(size_t)255) / 8; }
+
+// Fixed device scratch of he_rotate_noalloc: one array per device, held until
+// the process ends.  Host code never names it: it uses the device address
+// hipGetSymbolAddress returned on that device (noalloc_ptr).
+static __device__ __align__(256) u64 noalloc_scratch[HE_NOALLOC_SCRATCH_BYTES / 8];
+constexpr int HE_MAXDEV = 64;
+std::mutex noalloc_mu;
+u64 *noalloc_ptr[HE_MAXDEV] = {};
+
+// the scratch array's address on device `dev` (current), looked up once per device
+he_status noalloc_setup(int dev, u64 **out)
+{
+    if (dev < 0 || dev >= HE_MAXDEV) return HE_EDEVICE;
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    if (!noalloc_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !p) return HE_EDEVICE;
+        noalloc_ptr[dev] = (u64 *)p;
+    }
+    *out = noalloc_ptr[dev];
+    return HE_OK;
+}
 
 // Device memory comes from the caller's allocator when one was given (the
 // Python binding backs it with torch), else from hipMalloc.
@@ -1131,6 +1154,8 @@ he_status he_ctx_create(const he_params *prm, he_alloc_fn alloc, he_free_fn rele
     c->alpha = prm->alpha;
     c->dnum = dnum;
     c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) return HE_EDEVICE;
+    TRY(noalloc_setup(c->device, &c->noalloc));
     c->alloc_fn = alloc;
     c->free_fn = release;
     c->alloc_user = alloc_user;
@@ -1512,6 +1537,37 @@ he_status he_rotate(he_ctx *c, const he_ct *in, int steps, const he_keys *k, he_
     out->level = l;
     out->scale = sc;
     return last_error();
+}
+
+he_status he_rotate_noalloc(he_ctx *c, const he_ct *in, int steps, const he_keys *k, he_ct *out)
+{
+    if (!c || !ct_ok(c, in) || !k || !out || !out->data || out->data == in->data) return HE_EINVAL;
+    if (!c->noalloc) return HE_EDEVICE;
+    const int l = in->level;
+    const u64 g = galois_of(c, steps);
+    const double sc = in->scale;
+    if (g == 1) {
+        const long long lc = (long long)(l + 1) * c->N;
+        hek::ewise(c, 4, l, 1, 2, in->data, 0, lc, nullptr, 0, 0, out->data, 0, lc, 0);
+    } else {
+        const u64 *key = find_rot_key(k, g);
+        if (!key) return HE_EKEY;
+        // the same kernels as he_rotate, their buffers carved from the fixed array
+        if (rotate_scratch(c, l, 1) * 8 > HE_NOALLOC_SCRATCH_BYTES) return HE_ENOMEM;
+        Arena ar;
+        ar.base = (char *)c->noalloc;
+        ar.cap = HE_NOALLOC_SCRATCH_BYTES;
+        TRY(rotate_apply(c, ar, l, 1, in->data, 0, g, key, out->data, 0));
+    }
+    out->level = l;
+    out->scale = sc;
+    return last_error();
+}
+
+size_t he_rotate_noalloc_bytes(const he_ctx *c, int level)
+{
+    if (!c || level < 0 || level >= c->nq) return 0;
+    return rotate_scratch(c, level, 1) * 8;
 }
 
 he_status he_add(he_ctx *c, const he_ct *x, const he_ct *y, he_ct *out)

@@ -63,6 +63,8 @@ struct he_ctx {
     int N, logN, nq, nk, np, alpha, dnum;
     std::vector<u64> q, psi;
     hipStream_t stream;
+    int device = 0;                  // the HIP device current at creation
+    u64 *noalloc = nullptr;          // this device's fixed scratch array (he_rotate_noalloc)
     he_alloc_fn alloc_fn = nullptr;  // caller's device allocator (null: hipMalloc / hipFree)
     he_free_fn free_fn = nullptr;
     void *alloc_user = nullptr;

@@ -60,6 +60,7 @@ class he_infer_plan(ctypes.Structure):
 
 
 LAYOUT_ROWS, LAYOUT_FEATURES = 0, 1  # HE_LAYOUT_ROWS / HE_LAYOUT_FEATURES
+NOALLOC_SCRATCH_BYTES = 64 << 20  # HE_NOALLOC_SCRATCH_BYTES
 
 
 _P = POINTER
@@ -90,6 +91,8 @@ _sig = {
     "he_relin": (c_int, [c_void_p, _P(he_ct3), c_void_p, _P(he_ct)]),
     "he_rescale": (c_int, [c_void_p, _P(he_ct), _P(he_ct)]),
     "he_rotate": (c_int, [c_void_p, _P(he_ct), c_int, c_void_p, _P(he_ct)]),
+    "he_rotate_noalloc": (c_int, [c_void_p, _P(he_ct), c_int, c_void_p, _P(he_ct)]),
+    "he_rotate_noalloc_bytes": (c_size_t, [c_void_p, c_int]),
     "he_add": (c_int, [c_void_p, _P(he_ct), _P(he_ct), _P(he_ct)]),
     "he_mul_int": (c_int, [c_void_p, _P(he_ct), c_int64, c_double, _P(he_ct)]),
     "he_mul_plain": (c_int, [c_void_p, _P(he_ct), _P(he_pt), _P(he_ct)]),
@@ -388,6 +391,16 @@ class Context:
         out = out or self.ct_empty(x.level)
         a, o = x.struct(), out.struct()
         _chk(_lib.he_rotate(self.h, ctypes.byref(a), steps, keys.handle, ctypes.byref(o)), "he_rotate")
+        return out.update(o)
+
+    def _noalloc_bytes(self, level):
+        return int(_lib.he_rotate_noalloc_bytes(self.h, level))
+
+    def rotate_noalloc(self, x, steps, keys, out):
+        """he_rotate_noalloc: he_rotate with no device allocation; out is the
+        caller's (a ciphertext at x's level)."""
+        a, o = x.struct(), out.struct()
+        _chk(_lib.he_rotate_noalloc(self.h, ctypes.byref(a), steps, keys.handle, ctypes.byref(o)), "he_rotate_noalloc")
         return out.update(o)
 
     def add(self, x, y, out=None):

@@ -152,3 +152,10 @@ def test_inference_plan_matches_oracle_bit_for_bit(name, coef):
     assert e.value.status == 3
     with pytest.raises(LR.LevelError):
         LR.plan_lr_infer(q, 2, delta, delta, coef)
+
+
+def test_noalloc_scratch_size_matches_header():
+    import re
+    src = open(os.path.join(ROOT, "include", "he.h")).read()
+    m = re.search(r"#define HE_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == H.NOALLOC_SCRATCH_BYTES
