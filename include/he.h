@@ -167,6 +167,18 @@ he_status he_ctx_primes(const he_ctx *ctx, uint64_t *out, int n);
 /* Pure host (no device): the prime chain the parameters select, as above;
  * n must be >= n_q + n_special.  HE_EINVAL on parameters out of range. */
 he_status he_params_primes(const he_params *prm, uint64_t *out, int n);
+/* Launch shape of the context's plain forward and inverse NTTs (a tuning
+ * knob; results are bit-identical for every setting).  persistent = 1: both
+ * passes in one persistent launch of 8 * wg_per_xcd workgroups, each XCD
+ * transforming its own limbs with the intermediate kept in its L2 and `lag`
+ * first passes issued ahead of the second ones (1 <= lag <= 3), for
+ * transforms of at least min_limbs limbs (smaller ones take the two-launch
+ * form); 0: one launch per pass (the intermediate goes through HBM).  Drops
+ * the captured graphs.  HE_EINVAL for values out of range, during capture,
+ * or persistent on a ring below 2^12.  Default: the two-launch form
+ * (paper_2006_10091_amd/autotune.py measures the choices and writes the
+ * table the binding applies). */
+he_status he_ctx_set_ntt(he_ctx *ctx, int persistent, int wg_per_xcd, int lag, int min_limbs);
 /* Give the context's scratch workspace back to its allocator (it is re-grown
  * on demand); graphs captured over it are dropped. */
 he_status he_ctx_trim(he_ctx *ctx);

@@ -613,6 +613,17 @@ he_status build_tables(he_ctx *c)
         !t.dn_scale || !t.dn_conv || !t.dn_p || !t.dn_pinv || !t.rs_qinv || !t.rs_ql || !t.up_convd || !t.up_qdd ||
         !t.qinv_d || !t.dn_convd || !t.dn_pd || !t.rs_one || !t.rs_ql2 || !t.rs_oned || !t.rs_qld)
         return HE_ENOMEM;
+    // the persistent NTT's slots (8 XCDs x PS_SLOTS limbs) and counters; contents
+    // need no initial value (the counters are zeroed before every launch)
+    if (hek::fused_ok(c)) {
+        c->persist.slots = (u64 *)dev_alloc(c, (size_t)8 * PS_SLOTS * N * 8);
+        if (c->persist.slots) c->owned.push_back(c->persist.slots);
+        c->persist.ctr = (unsigned *)dev_alloc(c, 4096);
+        if (c->persist.ctr) c->owned.push_back(c->persist.ctr);
+        if (!c->persist.slots || !c->persist.ctr) return HE_ENOMEM;
+    } else {
+        c->persist.on = 0;
+    }
     return HE_OK;
 }
 
@@ -1192,6 +1203,22 @@ he_status he_ctx_destroy(he_ctx *c)
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     if (c->gstream) (void)hipStreamDestroy(c->gstream);
     delete c;
+    return HE_OK;
+}
+
+he_status he_ctx_set_ntt(he_ctx *c, int persistent, int wg_per_xcd, int lag, int min_limbs)
+{
+    if (!c || persistent < 0 || persistent > 1 || wg_per_xcd < 1 || wg_per_xcd > 1024 || lag < 1 || lag >= PS_SLOTS ||
+        min_limbs < 1)
+        return HE_EINVAL;
+    if (persistent && !c->persist.slots) return HE_EINVAL;
+    if (c->capturing) return HE_EINVAL;
+    // captured graphs hold the launch shapes of the old setting
+    TRY(drop_graphs(c, 0));
+    c->persist.on = persistent;
+    c->persist.wg_per_xcd = wg_per_xcd;
+    c->persist.lag = lag;
+    c->persist.min_limbs = min_limbs;
     return HE_OK;
 }
 

@@ -52,6 +52,21 @@ struct DeviceTables {
     double *rs_qld;          // [nq][nq] q_l mod q_i
 };
 
+// Persistent two-pass NTT (plain forward / inverse transforms): per XCD,
+// PS_SLOTS limb-sized slots hold the intermediates between the passes in that
+// XCD's L2.  on = 0 (the default, by measurement: the per-task
+// synchronisation costs more than the saved HBM round trip) uses the
+// two-launch form.
+constexpr int PS_SLOTS = 4;
+struct PersistCfg {
+    int on = 0;
+    int wg_per_xcd = 64;  // workgroups per XCD of a launch
+    int lag = 2;          // first passes issued ahead of the second ones (< PS_SLOTS)
+    int min_limbs = 1;    // smaller transforms take the two-launch form
+    unsigned *ctr = nullptr;
+    u64 *slots = nullptr;
+};
+
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -69,6 +84,7 @@ struct he_ctx {
     he_free_fn free_fn = nullptr;
     void *alloc_user = nullptr;
     DeviceTables t;
+    PersistCfg persist;
     std::vector<void *> owned;  // device allocations of the tables (through the allocator)
     void *ws = nullptr;         // scratch workspace
     size_t ws_bytes = 0;

@@ -39,10 +39,17 @@ struct NttArgs {
     int zoff;  // first batch x component entry of this launch (chunked launches)
 };
 
-__device__ __forceinline__ bool ntt_locate(const NttArgs &a, u64 *&limb, int &pidx)
+// Block index of a pass: blockIdx for the one-pass-per-launch kernels, a
+// virtual one when a persistent kernel runs both passes (ntt_persist_t).
+struct VB {
+    int x, y, z;
+};
+__device__ __forceinline__ VB vb_here() { return VB{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z}; }
+
+__device__ __forceinline__ bool ntt_locate(const NttArgs &a, VB vb, u64 *&limb, int &pidx)
 {
-    const int pos = a.pos0 + (int)blockIdx.y;
-    const int z = (int)blockIdx.z + a.zoff;
+    const int pos = a.pos0 + vb.y;
+    const int z = vb.z + a.zoff;
     const int b = z / a.ncomp, c = z % a.ncomp;
     if (a.skip_digit) {
         int s0 = c * a.alpha, s1 = min(s0 + a.alpha, a.ell + 1);
@@ -51,6 +58,10 @@ __device__ __forceinline__ bool ntt_locate(const NttArgs &a, u64 *&limb, int &pi
     limb = a.base + (long long)b * a.bstride + (long long)c * a.cstride + ((long long)pos << a.logN);
     pidx = prime_of(pos, a.ell, a.nq);
     return true;
+}
+__device__ __forceinline__ bool ntt_locate(const NttArgs &a, u64 *&limb, int &pidx)
+{
+    return ntt_locate(a, vb_here(), limb, pidx);
 }
 
 // Pass over the N1 "rows" (stride N2 = N/N1) for a tile of C consecutive
@@ -560,11 +571,11 @@ __device__ __forceinline__ void conv_setup_fp(ConvConst &cc, const PrimeInfo *pi
 // (ModDown: the special primes; rescale: q_l), the target is q_pos of this
 // workgroup
 __device__ __forceinline__ void conv_setup(const NttArgs &a, const Fuse &f, const PrimeInfo *pinfo, int tp,
-                                           ConvConst &cc)
+                                           ConvConst &cc, VB vb)
 {
-    const int z = (int)blockIdx.z + a.zoff;
+    const int z = vb.z + a.zoff;
     const int b = z / a.ncomp, c = z % a.ncomp;
-    const int pos = a.pos0 + (int)blockIdx.y;  // target q_pos
+    const int pos = a.pos0 + vb.y;  // target q_pos
     cc.n = f.nsrc;
     cc.src = f.src + b * f.sbs + c * f.scs + (f.soff << a.logN);
 #pragma unroll
@@ -647,20 +658,22 @@ __device__ __forceinline__ void conv_column_d(const ConvConst &cc, long long off
 }
 
 // pass A: columns.  Thread (tau, cc) with cc fastest; LINES consecutive columns per workgroup.
+// xbuf (plain forward / inverse only): where the intermediate between the two
+// passes lives (the persistent kernel's L2-resident slot); null: in place.
 template <int LOGN, bool INV, int PRO>
-__global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
-                                                           const u64 *__restrict__ tw, const u64 *__restrict__ tws,
-                                                           const u64 *__restrict__ post, const double *__restrict__ twd,
-                                                           Fuse f)
+__device__ __forceinline__ void ntt_cols_body(const NttArgs &a, const PrimeInfo *__restrict__ pinfo,
+                                              const u64 *__restrict__ tw, const u64 *__restrict__ tws,
+                                              const u64 *__restrict__ post, const double *__restrict__ twd,
+                                              const Fuse &f, VB vb, u64 *lds, u64 *xbuf)
 {
     constexpr int LM = (LOGN + 1) / 2, N2 = 1 << (LOGN - LM);
     using S = LineShape<LM>;
-    __shared__ u64 lds[S::LINES * S::PADDED];
     u64 *limb;
     int pidx;
-    if (!ntt_locate(a, limb, pidx)) return;
+    if (!ntt_locate(a, vb, limb, pidx)) return;
+    u64 *xl = xbuf ? xbuf : limb;  // the intermediate's side of this pass
     const int cc = threadIdx.x % S::LINES, tau = threadIdx.x / S::LINES;
-    const int col = blockIdx.x * S::LINES + cc;
+    const int col = vb.x * S::LINES + cc;
     const PrimeInfo p = pinfo[pidx];
     const u64 q = p.q, q2 = 2 * q;
     const u64 *W = tw + ((long long)pidx << LOGN);
@@ -668,7 +681,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
     u64 *line = lds + cc * S::PADDED;
     ConvConst cv;
     constexpr bool CONV = PRO == PRO_MODDOWN || PRO == PRO_MDRS;
-    if (CONV) conv_setup(a, f, pinfo, pidx, cv);
+    if (CONV) conv_setup(a, f, pinfo, pidx, cv, vb);
     // PRO_MDRS (a ModDown and the rescale by q_l after it, in one transform):
     // the input is the ModDown conversion plus [P] times the rescale's centred
     // conversion of the ModDown output's last limb, conv + P x; both are
@@ -676,7 +689,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
     const u64 *lastp = nullptr;
     u64 lq = 0;
     if (PRO == PRO_MDRS) {
-        lastp = f.last + ((long long)((int)blockIdx.z + a.zoff) << LOGN);
+        lastp = f.last + ((long long)(vb.z + a.zoff) << LOGN);
         lq = pinfo[f.lpos].q;
     }
     auto mdrs_d = [&](double conv, long long off, double qd, double qinv) -> double {
@@ -717,9 +730,14 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
             fwd_stages_ds<LM, false, true>(d, tau, 0, 0, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, true);
             fwd_stages_ds<LM, false, false>(d, tau, 0, 0, Wd, qd, qinv);
+            if (xbuf) {  // L2-resident intermediate: a normal store, kept in the cache
 #pragma unroll
-            for (int k = 0; k < S::E; ++k)
-                __builtin_nontemporal_store(s51_from_d(d[k]), limb + (long long)(S::E * tau + k) * N2 + col);
+                for (int k = 0; k < S::E; ++k) xl[(long long)(S::E * tau + k) * N2 + col] = s51_from_d(d[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < S::E; ++k)
+                    __builtin_nontemporal_store(s51_from_d(d[k]), limb + (long long)(S::E * tau + k) * N2 + col);
+            }
         } else if (!INV) {
 #pragma unroll
             for (int k = 0; k < S::E; ++k) d[k] = (double)load(tau + S::T * k);
@@ -727,15 +745,20 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
             exch_d<LM>(d, dl, tau, true);
             stages_d<LM, false, false, false>(d, tau, 0, 0, Wd, qd, qinv);
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) limb[(long long)(S::E * tau + k) * N2 + col] = (u64)d[k];
+            for (int k = 0; k < S::E; ++k) xl[(long long)(S::E * tau + k) * N2 + col] = (u64)d[k];
         } else if (q < (1ull << 42)) {  // lazy inverse: input reduced by the row pass
+            if (xbuf) {
 #pragma unroll
-            for (int k = 0; k < S::E; ++k)
-                d[k] = d_from_u52(__builtin_nontemporal_load(limb + (long long)(S::E * tau + k) * N2 + col));
+                for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(xl[(long long)(S::E * tau + k) * N2 + col]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < S::E; ++k)
+                    d[k] = d_from_u52(__builtin_nontemporal_load(limb + (long long)(S::E * tau + k) * N2 + col));
+            }
             inv_stages_ds<LM, false, false>(d, tau, 0, 0, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, false);
             inv_stages_ds<LM, false, true>(d, tau, 0, 0, Wd, qd, qinv);
-            u64 sc = post ? post[2 * blockIdx.y] : p.ninv;
+            u64 sc = post ? post[2 * vb.y] : p.ninv;
             const double scd = (double)sc;
 #pragma unroll
             for (int k = 0; k < S::E; ++k)
@@ -743,11 +766,11 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
                                             limb + (long long)(tau + S::T * k) * N2 + col);
         } else {
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) d[k] = (double)limb[(long long)(S::E * tau + k) * N2 + col];
+            for (int k = 0; k < S::E; ++k) d[k] = (double)xl[(long long)(S::E * tau + k) * N2 + col];
             stages_d<LM, false, true, false>(d, tau, 0, 0, Wd, qd, qinv);
             exch_d<LM>(d, dl, tau, false);
             stages_d<LM, false, true, true>(d, tau, 0, 0, Wd, qd, qinv);
-            u64 sc = post ? post[2 * blockIdx.y] : p.ninv;
+            u64 sc = post ? post[2 * vb.y] : p.ninv;
             const double scd = (double)sc;
 #pragma unroll
             for (int k = 0; k < S::E; ++k)
@@ -763,17 +786,17 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
         to_contig<LM>(v, line, tau);
         fwd_contig<LM, false>(v, tau, 0, 0, W, Ws, q, q2);
 #pragma unroll
-        for (int k = 0; k < S::E; ++k) limb[(long long)(S::E * tau + k) * N2 + col] = v[k];
+        for (int k = 0; k < S::E; ++k) xl[(long long)(S::E * tau + k) * N2 + col] = v[k];
     } else {
 #pragma unroll
-        for (int k = 0; k < S::E; ++k) v[k] = limb[(long long)(S::E * tau + k) * N2 + col];
+        for (int k = 0; k < S::E; ++k) v[k] = xl[(long long)(S::E * tau + k) * N2 + col];
         inv_contig<LM, false>(v, tau, 0, 0, W, Ws, q, q2);
         to_strided<LM>(v, line, tau);
         inv_strided<LM, false>(v, tau, 0, 0, W, Ws, q, q2);
         u64 sc, scs;
         if (post) {
-            sc = post[2 * blockIdx.y];
-            scs = post[2 * blockIdx.y + 1];
+            sc = post[2 * vb.y];
+            scs = post[2 * vb.y + 1];
         } else {
             sc = p.ninv;
             scs = p.ninv_sh;
@@ -782,36 +805,51 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
         for (int k = 0; k < S::E; ++k) limb[(long long)(tau + S::T * k) * N2 + col] = mul_shoup(v[k], sc, scs, q);
     }
 }
+template <int LOGN, bool INV, int PRO>
+__global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
+                                                           const u64 *__restrict__ tw, const u64 *__restrict__ tws,
+                                                           const u64 *__restrict__ post, const double *__restrict__ twd,
+                                                           Fuse f)
+{
+    using S = LineShape<(LOGN + 1) / 2>;
+    __shared__ u64 lds[S::LINES * S::PADDED];
+    ntt_cols_body<LOGN, INV, PRO>(a, pinfo, tw, tws, post, twd, f, vb_here(), lds, nullptr);
+}
 
 // pass B: rows.  Thread (line, tau) with tau fastest; LINES consecutive rows per workgroup.
 // MODE: forward EPI_NONE / EPI_FINISH; inverse PRO_NONE / PRO_SRC.
+// xbuf (plain forward / inverse only): the intermediate's location (read by
+// the forward pass, written by the inverse one); null: in place.
 template <int LOGN, bool INV, int MODE>
-__global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
-                                                           const u64 *__restrict__ tw, const u64 *__restrict__ tws,
-                                                           const double *__restrict__ twd, Fuse f)
+__device__ __forceinline__ void ntt_rows_body(const NttArgs &a, const PrimeInfo *__restrict__ pinfo,
+                                              const u64 *__restrict__ tw, const u64 *__restrict__ tws,
+                                              const double *__restrict__ twd, const Fuse &f, VB vb, u64 *lds,
+                                              u64 *xbuf)
 {
     constexpr int LM = LOGN - (LOGN + 1) / 2, N1 = 1 << ((LOGN + 1) / 2);
     constexpr bool FIN = !INV && MODE == EPI_FINISH;
     constexpr bool SRC = INV && MODE == PRO_SRC;
     using S = LineShape<LM>;
-    __shared__ u64 lds[S::LINES * S::PADDED];
     u64 *limb;
     int pidx;
-    if (!ntt_locate(a, limb, pidx)) return;
+    if (!ntt_locate(a, vb, limb, pidx)) return;
     const int tau = threadIdx.x % S::T, ln = threadIdx.x / S::T;
-    const int h = blockIdx.x * S::LINES + ln;
+    const int h = vb.x * S::LINES + ln;
     const PrimeInfo p = pinfo[pidx];
     const u64 q = p.q, q2 = 2 * q;
     const u64 *W = tw + ((long long)pidx << LOGN);
     const u64 *Ws = tws + ((long long)pidx << LOGN);
     u64 *row = limb + (long long)h * S::M;
     u64 *line = lds + ln * S::PADDED;
-    const int z = (int)blockIdx.z + a.zoff;
+    const int z = vb.z + a.zoff;
     const int b = z / a.ncomp, c = z % a.ncomp;
-    const int pos = a.pos0 + (int)blockIdx.y;
+    const int pos = a.pos0 + vb.y;
     const long long roff = ((long long)pos << LOGN) + (long long)h * S::M;
     const u64 *in = row;
     if (SRC) in = f.src + b * f.sbs + c * f.scs + roff;
+    // the persistent kernel's intermediate: read it (forward) or write it (inverse) through the cache
+    u64 *xrow = xbuf ? xbuf + (long long)h * S::M : nullptr;
+    if (!INV && xbuf) in = xrow;
     // finish epilogue: out = base + (acc - x) P^{-1}
     auto store = [&](int k, u64 x) {
         const int e = tau + S::T * k;
@@ -833,9 +871,13 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
         double *dl = reinterpret_cast<double *>(line);
         double d[S::E];
         if (!INV && q < (1ull << 46)) {  // signed lazy: input is the column pass's signed intermediate
+            if (xbuf) {
 #pragma unroll
-            for (int k = 0; k < S::E; ++k)
-                d[k] = d_from_s51(__builtin_nontemporal_load(in + tau + S::T * k));
+                for (int k = 0; k < S::E; ++k) d[k] = d_from_s51(in[tau + S::T * k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < S::E; ++k) d[k] = d_from_s51(__builtin_nontemporal_load(in + tau + S::T * k));
+            }
             // finish operands are loaded before the stages, so their latency overlaps them
             u64 fa[FIN ? S::E : 1], fb[FIN ? S::E : 1];
             if (FIN) {
@@ -877,8 +919,13 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
             }
             return;
         }
+        if (!INV && xbuf) {
 #pragma unroll
-        for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(__builtin_nontemporal_load(in + tau + S::T * k));
+            for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(in[tau + S::T * k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) d[k] = d_from_u52(__builtin_nontemporal_load(in + tau + S::T * k));
+        }
         if (SRC && f.has_kmul) {  // the source times kmul, reduced to [0, q)
             const double kd = d_from_u52(int_mod(f.kmul, p));
 #pragma unroll
@@ -902,23 +949,34 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
             __syncthreads();
             exch_d<LM>(d, dl, tau, false);
             inv_stages_ds<LM, true, true>(d, tau, h, N1, Wd, qd, qinv);
+            if (xbuf) {
 #pragma unroll
-            for (int k = 0; k < S::E; ++k)
-                __builtin_nontemporal_store(u52_from_d(reduce_d(d[k], qd, qinv)), row + tau + S::T * k);
+                for (int k = 0; k < S::E; ++k) xrow[tau + S::T * k] = u52_from_d(reduce_d(d[k], qd, qinv));
+            } else {
+#pragma unroll
+                for (int k = 0; k < S::E; ++k)
+                    __builtin_nontemporal_store(u52_from_d(reduce_d(d[k], qd, qinv)), row + tau + S::T * k);
+            }
         } else {
             exch_d<LM>(d, dl, tau, true);
             stages_d<LM, true, true, false>(d, tau, h, N1, Wd, qd, qinv);
             __syncthreads();
             exch_d<LM>(d, dl, tau, false);
             stages_d<LM, true, true, true>(d, tau, h, N1, Wd, qd, qinv);
+            u64 *wr = xbuf ? xrow : row;
 #pragma unroll
-            for (int k = 0; k < S::E; ++k) __builtin_nontemporal_store((u64)d[k], row + tau + S::T * k);
+            for (int k = 0; k < S::E; ++k) wr[tau + S::T * k] = (u64)d[k];
         }
         return;
     }
     u64 v[S::E];
+    if (!INV && xbuf) {
 #pragma unroll
-    for (int k = 0; k < S::E; ++k) v[k] = __builtin_nontemporal_load(in + tau + S::T * k);
+        for (int k = 0; k < S::E; ++k) v[k] = in[tau + S::T * k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < S::E; ++k) v[k] = __builtin_nontemporal_load(in + tau + S::T * k);
+    }
     if (SRC && f.has_kmul) {
         const u64 kq = int_mod(f.kmul, p);
 #pragma unroll
@@ -938,9 +996,23 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
         __syncthreads();
         to_strided<LM>(v, line, tau);
         inv_strided<LM, true>(v, tau, h, N1, W, Ws, q, q2);
+        if (xbuf) {
 #pragma unroll
-        for (int k = 0; k < S::E; ++k) __builtin_nontemporal_store(v[k], row + tau + S::T * k);
+            for (int k = 0; k < S::E; ++k) xrow[tau + S::T * k] = v[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < S::E; ++k) __builtin_nontemporal_store(v[k], row + tau + S::T * k);
+        }
     }
+}
+template <int LOGN, bool INV, int MODE>
+__global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
+                                                           const u64 *__restrict__ tw, const u64 *__restrict__ tws,
+                                                           const double *__restrict__ twd, Fuse f)
+{
+    using S = LineShape<LOGN - (LOGN + 1) / 2>;
+    __shared__ u64 lds[S::LINES * S::PADDED];
+    ntt_rows_body<LOGN, INV, MODE>(a, pinfo, tw, tws, twd, f, vb_here(), lds, nullptr);
 }
 
 // Row pass of the extended digits' forward NTT fused with the key-switch
@@ -2316,12 +2388,170 @@ namespace hek {
 // into cache-sized chunks costs more in kernel boundaries than it saves.
 constexpr long long NTT_CHUNK_BYTES = 1ll << 40;
 
+// ------------------------------------------------------------------ persistent two-pass NTT
+// Both passes of a plain forward or inverse transform in one launch, with the
+// intermediate between them kept in the L2 of the XCD that computes it.  A
+// workgroup reads the XCD it runs on (hardware register XCC_ID) and takes
+// tasks from that XCD's ticket counter; limb g of the batch belongs to XCD
+// g mod 8.  A task is one workgroup's share (`part`) of one pass over one
+// limb; per XCD the tickets run through phases of P tasks: the first pass of
+// limbs 0 .. D-1, then alternately the second pass of limb j and the first
+// pass of limb j + D, then the remaining second passes.  Limb k's
+// intermediate lives in slot k mod PS_SLOTS of the XCD's slot buffer, so it
+// never leaves that XCD's L2 unless evicted.  A second pass waits until its
+// limb's first pass has completed (P tasks counted on the slot), a first pass
+// waits until the slot's previous limb has finished its second pass.  Every
+// wait is on tasks whose tickets were taken earlier by running workgroups of
+// the same XCD, so the waits always end: no co-residency is assumed, and one
+// workgroup per XCD alone would also finish.  Counters are zeroed by a kernel
+// before every launch (graph-safe).
+#define HWREG_XCC_ID ((20) | (0 << 6) | ((4 - 1) << 11))  // hwreg(HW_REG_XCC_ID, 0, 4)
+
+struct PersistArgs {
+    unsigned *ctr;  // per XCD a 256-byte block: ticket counter, then PS_SLOTS x (first, second) completions
+    u64 *slots;     // [8][PS_SLOTS][N]
+    int nlimb;      // limbs of the launch (npos x entries x components)
+    int npos;
+    int lag;        // D: first passes issued ahead of the second ones (1 .. PS_SLOTS - 1)
+};
+
+__global__ void persist_reset_kernel(unsigned *ctr, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0u;
+}
+
+// Wait until *p reaches need.  Every lane of the calling wave polls (one
+// request per wave) and the loop condition is made wave-uniform, so no lane
+// diverges.  Bounded: after 2^22 polls (well over a second) it gives up and
+// raises the flag word, so a wait that could not end (it cannot, by the
+// schedule's construction) ends the kernel with wrong values instead of
+// hanging the device.
+constexpr int PS_FLAG = 8 * 64;  // word index of the flag after the 8 XCDs' counter blocks
+__device__ __forceinline__ void wait_count(unsigned *p, unsigned need, unsigned *flag)
+{
+    for (unsigned it = 0;; ++it) {
+        const unsigned v = __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (v >= need) return;
+        if (it >= (1u << 22)) {
+            __hip_atomic_fetch_or(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+}
+
+// The control flow below is wave-uniform everywhere outside the pass bodies:
+// tickets and counts are read into scalars (readfirstlane), and the counter
+// updates and polls are made by wave 0 (a wave-uniform condition), every lane
+// with a nonzero increment on one lane only; so each wave executes the same
+// barriers.
+template <int LOGN, bool INV>
+__global__ __launch_bounds__(LINE_THREADS) void ntt_persist_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
+                                                              const u64 *__restrict__ tw, const u64 *__restrict__ tws,
+                                                              const u64 *__restrict__ post,
+                                                              const double *__restrict__ twd, PersistArgs ps)
+{
+    constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
+    using SA = LineShape<LA>;
+    using SB = LineShape<LB>;
+    constexpr int PA = (1 << LB) / SA::LINES;  // column-pass workgroups per limb
+    constexpr int PB = (1 << LA) / SB::LINES;  // row-pass workgroups per limb
+    constexpr int P = PA > PB ? PA : PB;
+    constexpr int WA = SA::LINES * SA::PADDED, WB = SB::LINES * SB::PADDED;
+    __shared__ u64 lds[WA > WB ? WA : WB];
+    __shared__ unsigned tk;
+    const int x = (int)(__builtin_amdgcn_s_getreg(HWREG_XCC_ID) & 7u);
+    // this XCD's counter block (its own 256 bytes): [0] tickets, [1 + 2 slot] first-pass
+    // completions, [2 + 2 slot] second-pass completions
+    unsigned *blk = ps.ctr + 64 * x;
+    const unsigned one = threadIdx.x == 0 ? 1u : 0u;
+    // wave 0 alone touches the counters (a wave-uniform condition)
+    const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64;
+    const int nk = ps.nlimb > x ? (ps.nlimb - x + 7) / 8 : 0;  // this XCD's limbs: g = 8 k + x
+    const int D = nk < ps.lag ? nk : ps.lag;
+    const unsigned total = 2u * (unsigned)nk * P;
+    Fuse f{};
+    for (;;) {
+        if (wave0) {
+            const unsigned got = atomicAdd(blk, one);  // lane 0 takes the ticket
+            if (threadIdx.x == 0) tk = got;
+        }
+        __syncthreads();
+        const unsigned t = __builtin_amdgcn_readfirstlane(tk);
+        __syncthreads();  // every wave has read tk before the next ticket overwrites it
+        if (t >= total) break;
+        const int ph = (int)(t / P), part = (int)(t % P);
+        bool first;  // the transform's first pass (forward: columns; inverse: rows)
+        int k;
+        if (ph < D) {
+            first = true;
+            k = ph;
+        } else if (ph - D < 2 * (nk - D)) {
+            const int r = ph - D;
+            first = (r & 1) != 0;
+            k = (r >> 1) + (first ? D : 0);
+        } else {
+            first = false;
+            k = nk - D + (ph - D - 2 * (nk - D));
+        }
+        const int slot = k % PS_SLOTS;
+        const unsigned gen = (unsigned)(k / PS_SLOTS);
+        unsigned *d1 = blk + 1 + 2 * slot, *d2 = d1 + 1;
+        if (wave0) {
+            if (first) {
+                if (gen > 0) wait_count(d2, gen * P, ps.ctr + PS_FLAG);  // the slot's previous limb has left it
+            } else {
+                wait_count(d1, (gen + 1) * P, ps.ctr + PS_FLAG);  // this limb's first pass is complete
+            }
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // no stale L1 lines of the slot
+        const int g = 8 * k + x;
+        const VB vb{part, g % ps.npos, g / ps.npos};
+        u64 *xb = ps.slots + ((long long)(x * PS_SLOTS + slot) << LOGN);
+        if (!INV) {
+            if (first) {
+                if (part < PA) ntt_cols_body<LOGN, false, PRO_NONE>(a, pinfo, tw, tws, nullptr, twd, f, vb, lds, xb);
+            } else if (part < PB) {
+                ntt_rows_body<LOGN, false, EPI_NONE>(a, pinfo, tw, tws, twd, f, vb, lds, xb);
+            }
+        } else {
+            if (first) {
+                if (part < PB) ntt_rows_body<LOGN, true, PRO_NONE>(a, pinfo, tw, tws, twd, f, vb, lds, xb);
+            } else if (part < PA) {
+                ntt_cols_body<LOGN, true, PRO_NONE>(a, pinfo, tw, tws, post, twd, f, vb, lds, xb);
+            }
+        }
+        // the barrier waits for every wave's stores: the task's output is in L2
+        __syncthreads();
+        if (wave0) atomicAdd(first ? d1 : d2, one);
+    }
+}
+
 template <int LOGN>
 static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, const u64 *post, int pro, int epi,
                          const Fuse &f)
 {
     constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
     const int nz = nbatch * a.ncomp;
+    if (pro == PRO_NONE && epi == EPI_NONE && c->persist.on && c->persist.slots && npos * nz >= c->persist.min_limbs) {
+        PersistArgs ps;
+        ps.ctr = c->persist.ctr;
+        ps.slots = c->persist.slots;
+        ps.nlimb = npos * nz;
+        ps.npos = npos;
+        ps.lag = c->persist.lag;
+        a.zoff = 0;
+        persist_reset_kernel<<<1, 256, 0, c->stream>>>(ps.ctr, PS_FLAG);  // counters (the flag word stays raised)
+        const dim3 grid(8 * c->persist.wg_per_xcd);
+        if (dir > 0)
+            ntt_persist_t<LOGN, false><<<grid, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh,
+                                                                            nullptr, c->t.psi_d, ps);
+        else
+            ntt_persist_t<LOGN, true><<<grid, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh,
+                                                                           post, c->t.ipsi_d, ps);
+        return;
+    }
     const long long per_z = (long long)npos << (LOGN + 3);
     int zc = (int)std::max(1LL, NTT_CHUNK_BYTES / per_z);
     if (zc > nz) zc = nz;

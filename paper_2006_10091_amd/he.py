@@ -71,6 +71,7 @@ _sig = {
     "he_ctx_set_stream": (c_int, [c_void_p, c_void_p]),
     "he_ctx_primes": (c_int, [c_void_p, _P(c_uint64), c_int]),
     "he_ctx_trim": (c_int, [c_void_p]),
+    "he_ctx_set_ntt": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
     "he_params_primes": (c_int, [_P(he_params), _P(c_uint64), c_int]),
     "he_ct_bytes": (c_size_t, [c_void_p, c_int]),
     "he_pt_bytes": (c_size_t, [c_void_p, c_int]),
@@ -266,6 +267,8 @@ class Context:
         q = np.zeros(self.np, dtype=np.uint64)
         _chk(_lib.he_ctx_primes(self.h, _u64p(q), self.np), "he_ctx_primes")
         self.primes = [int(v) for v in q]
+        from . import autotune  # the measured NTT launch shape for this ring degree, if tuned
+        self.ntt_tuned = autotune.apply(self)
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -294,6 +297,11 @@ class Context:
         per = 2 * (level + 1) * self.N
         t = self._alloc(per * count)
         return [Ciphertext(t, level, 0.0, offset=i * per) for i in range(count)]
+
+    def set_ntt(self, persistent=1, wg_per_xcd=64, lag=2, min_limbs=1):
+        """he_ctx_set_ntt: launch shape of the plain NTTs (bit-identical results)."""
+        _chk(_lib.he_ctx_set_ntt(self.h, int(persistent), int(wg_per_xcd), int(lag), int(min_limbs)),
+             "he_ctx_set_ntt")
 
     def trim(self):
         _chk(_lib.he_ctx_trim(self.h), "he_ctx_trim")

@@ -1,0 +1,49 @@
+"""The persistent two-pass NTT (both passes in one launch, the intermediate
+kept in each XCD's L2) against the two-launch form, bit for bit, over ring
+degrees, batch sizes (fewer limbs than XCDs included), launch shapes and both
+directions; and forward then inverse is the identity."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2006_10091_amd import synth  # noqa: E402
+
+SHAPES = [(64, 2), (1, 1), (13, 3), (128, 2), (96, 1)]
+
+
+@pytest.mark.parametrize("log_n", [13, 14, 15, 16])
+def test_persistent_ntt_matches_two_launch(log_n):
+    from paper_2006_10091_amd import he as H
+    ctx = H.Context(log_n, 20, 4, 4, 40)
+    N = ctx.N
+    for nl, per in ((1, 1), (3, 1), (7, 7), (24, 24), (200, 20), (774, 18)):
+        host = np.concatenate([synth.uniform_residues(nl * 10 + b, ctx.primes[:per], N).ravel()
+                               for b in range(nl // per)])
+        src = torch.from_numpy(host.view(np.int64)).cuda()
+        print("2^%d: %d limbs, period %d" % (log_n, nl, per), flush=True)
+        for d in (1, -1):
+            ref = src.clone()
+            ctx.set_ntt(0)
+            ctx.ntt(ref, nl, 0, per, d)
+            for wg, lag in SHAPES:
+                x = src.clone()
+                ctx.set_ntt(1, wg, lag)
+                ctx.ntt(x, nl, 0, per, d)
+                assert torch.equal(x, ref), (nl, per, d, wg, lag)
+        x = src.clone()
+        ctx.set_ntt(1, 64, 2)
+        ctx.ntt(x, nl, 0, per, 1)
+        ctx.ntt(x, nl, 0, per, -1)
+        assert torch.equal(x, src)
+    # the threshold: small transforms take the two-launch form, same values
+    ctx.set_ntt(1, 64, 2, min_limbs=100)
+    x = src.clone()
+    ctx.ntt(x, nl, 0, per, 1)
+    ctx.set_ntt(0)
+    y = src.clone()
+    ctx.ntt(y, nl, 0, per, 1)
+    assert torch.equal(x, y)
+    with pytest.raises(H.HEError):
+        ctx.set_ntt(1, 64, 4)  # lag below the slot count only
