@@ -93,6 +93,19 @@ typedef struct {
     double scale;
 } he_pt;
 
+/* Seeded ciphertext: the b component in device memory, the uniform a
+ * component given by (seed, index) and regenerated on use (half the bytes of
+ * an he_ct).  b: device [level+1][N], NTT order. */
+typedef struct {
+    uint64_t *b;
+    int32_t level;
+    int32_t reserved;
+    double scale;
+    uint64_t seed;
+    uint32_t index;
+    uint32_t reserved2;
+} he_ct_seeded;
+
 /* Degree-2 ciphertext (d0, d1, d2) of a product before relinearisation. */
 typedef struct {
     uint64_t *data; /* device [3][level+1][N] */
@@ -245,6 +258,18 @@ he_status he_pt_load(he_ctx *ctx, const int64_t *coeffs, int level, double scale
  * pt's level.  Errors: HE_EINVAL. */
 he_status he_encrypt(he_ctx *ctx, const he_pt *pt, const he_keys *keys, int use_sk, uint64_t seed,
                      uint32_t index, he_ct *out);
+/* Seeded secret-key encryption (Alg. 2: the server encrypts the data with
+ * sk, so the uniform part can travel, and stay in HBM, as a seed): out->b =
+ * -a*s + e + m with a drawn in the evaluation domain -- limb i's value at
+ * the root psi_i^(2k+1) is the uniform residue of coefficient k of ChaCha20
+ * stream (seed; type 10, index, i) -- and e as he_encrypt.  out->b: caller
+ * memory [pt level + 1][N]; out->seed, out->index are set.  HE_EINVAL. */
+he_status he_encrypt_seeded(he_ctx *ctx, const he_pt *pt, const he_keys *keys, uint64_t seed, uint32_t index,
+                            he_ct_seeded *out);
+/* Materialise seeded ciphertexts: out[i] = (in[i].b, a(in[i].seed,
+ * in[i].index)) at in[i]'s level (caller memory).  HE_EINVAL. */
+he_status he_ct_expand(he_ctx *ctx, const he_ct_seeded *in, int n, he_ct *out);
+
 /* Decrypt (Alg. 2: the server decrypts the worker's weights): residues of
  * b + a*s at every limb, coefficient order, to host [level+1][N]. */
 he_status he_decrypt(he_ctx *ctx, const he_ct *ct, const he_keys *keys, uint64_t *host_residues);
@@ -362,6 +387,27 @@ he_status he_lr_grad_step(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct
                           const he_pt *mask, const double coef[4], double eta_over_n,
                           double w_decay, int c, int r, int layout, const he_ct *Zrot, int n_baby,
                           const he_ct *Zk, const he_keys *keys, int mode, he_ct *W_out, he_ct *G_out);
+
+/*
+ * he_lr_grad_step on seeded data blocks (the shard that does not fit in HBM as
+ * full ciphertexts: 2^20 samples x 512 features at N = 2^16 is 16384 blocks,
+ * 384 GiB in full, 192 GiB seeded).  The blocks are taken `chunk` at a time:
+ * each chunk's uniform parts are regenerated into the workspace, then the
+ * chunk runs as he_lr_grad_step's batched form (no baby steps, no
+ * precomputed data terms) and its gradient terms join the step's sum; the
+ * once-per-step part follows the last chunk.  Bit-identical to
+ * he_lr_grad_step (mode 1) on the expanded blocks.  Z[b]: one level >= W's,
+ * one scale and seed, b-parts one uniform stride apart, index Z[0].index + b.
+ * 1 <= chunk <= n_blocks; the workspace holds one chunk
+ * (he_lr_step_bytes for `chunk` blocks plus the expanded chunk).  Other
+ * arguments and errors as he_lr_grad_step.
+ */
+he_status he_lr_grad_step_seeded(he_ctx *ctx, const he_ct_seeded *Z, int n_blocks, const he_ct *W, const he_pt *mask,
+                                 const double coef[4], double eta_over_n, double w_decay, int c, int r, int layout,
+                                 int chunk, const he_keys *keys, he_ct *W_out, he_ct *G_out);
+/* Workspace bytes he_lr_grad_step_seeded takes for weights at `level`, data
+ * at data_level and `chunk` blocks per chunk (0 for invalid arguments). */
+size_t he_lr_step_seeded_bytes(const he_ctx *ctx, int level, int data_level, int chunk, int layout);
 
 /*
  * The data terms of a gradient step (eq. (appr): the a3 and a1 (and a2)

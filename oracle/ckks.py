@@ -74,6 +74,7 @@ def lib():
         "orc_decrypt": (None, [P, c_int, u64p, i64p, u64p]),
         "orc_secret_square": (None, [P, i64p, u64p]),
         "orc_set_conv_centring": (None, [c_int]),
+        "orc_encrypt_sk_seeded": (None, [P, c_int, i64p, i64p, c_uint64, c_uint32, u64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -294,6 +295,15 @@ def encrypt_sk(P, keys, m, level, scale, seed, index):
     """Secret-key encryption (the parameter server encrypts with sk, Alg. 2)."""
     out = np.zeros((2, level + 1, P.N), dtype=np.uint64)
     lib().orc_encrypt_sk(P.cp, level, _i(np.ascontiguousarray(m, dtype=np.int64)), _i(keys.s), seed, index, _u(out))
+    return CT(out, level, scale)
+
+
+def encrypt_sk_seeded(P, keys, m, level, scale, seed, index):
+    """Secret-key encryption whose uniform part is a function of (seed, index):
+    drawn in the evaluation domain, so a holder of the seed regenerates it."""
+    out = np.zeros((2, level + 1, P.N), dtype=np.uint64)
+    lib().orc_encrypt_sk_seeded(P.cp, level, _i(np.ascontiguousarray(m, dtype=np.int64)), _i(keys.s), seed, index,
+                                _u(out))
     return CT(out, level, scale)
 
 

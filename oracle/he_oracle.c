@@ -263,7 +263,7 @@ void orc_prng_words(u64 seed, u32 type, u32 index, u32 comp, u64 first, u64 coun
 
 /* stream types (reading) */
 enum { ST_SECRET = 1, ST_PK_A = 2, ST_PK_E = 3, ST_EVK_A = 4, ST_EVK_E = 5,
-       ST_ENC_A = 6, ST_ENC_E0 = 7, ST_ENC_V = 8, ST_ENC_E1 = 9 };
+       ST_ENC_A = 6, ST_ENC_E0 = 7, ST_ENC_V = 8, ST_ENC_E1 = 9, ST_SEED_A = 10 };
 
 /* uniform residue mod q: coefficient x takes words 2x (high) and 2x+1 (low) */
 void orc_sample_uniform(u64 seed, u32 type, u32 index, u32 comp, u64 q, int logN, u64 *out)
@@ -714,6 +714,34 @@ void orc_encrypt_sk(const orc_params *P, int level, const i64 *m, const i64 *s, 
     for (int i = 0; i < n; i++) idx[i] = i;
     u64 *b = out, *a = out + (size_t)n * N;
     for (int i = 0; i < n; i++) orc_sample_uniform(seed, ST_ENC_A, ct_index, (u32)i, P->q[i], P->logN, LIMB(a, i));
+    i64 *e = (i64 *)malloc(N * 8);
+    orc_sample_cbd(seed, ST_ENC_E0, ct_index, 0, P->logN, e);
+    u64 *mr = (u64 *)malloc((size_t)n * N * 8);
+    orc_int_to_rns(P, m, 0, n, mr);
+    rlwe_b(P, n, idx, a, s, e, mr, b);
+    free(e);
+    free(mr);
+}
+
+/*
+ * Seeded secret-key encryption at level l (reading: the server's sk
+ * encryption of Alg. 2 lets the uniform part be sent as a seed).  The uniform
+ * part is drawn in the evaluation domain: for limb i its value at the root
+ * psi_i^(2k+1) (natural order k) is the uniform residue of coefficient k of
+ * stream (seed; ST_SEED_A, index, i); a = its inverse NTT.  Then, as
+ * orc_encrypt_sk: (-a*s + e + m, a), e from (seed; ST_ENC_E0, index, 0).
+ */
+void orc_encrypt_sk_seeded(const orc_params *P, int level, const i64 *m, const i64 *s, u64 seed, u32 ct_index,
+                           u64 *out)
+{
+    u64 N = (u64)1 << P->logN;
+    int n = level + 1, idx[ORC_MAXP];
+    for (int i = 0; i < n; i++) idx[i] = i;
+    u64 *b = out, *a = out + (size_t)n * N;
+    for (int i = 0; i < n; i++) {
+        orc_sample_uniform(seed, ST_SEED_A, ct_index, (u32)i, P->q[i], P->logN, LIMB(a, i));
+        orc_ntt_inv(LIMB(a, i), P->logN, P->q[i], P->psi[i]);
+    }
     i64 *e = (i64 *)malloc(N * 8);
     orc_sample_cbd(seed, ST_ENC_E0, ct_index, 0, P->logN, e);
     u64 *mr = (u64 *)malloc((size_t)n * N * 8);

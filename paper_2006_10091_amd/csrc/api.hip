@@ -1049,15 +1049,39 @@ he_status margins_impl(he_ctx *c, const he_ct *Z, int n_blocks, long long zbs, c
 }
 
 // the whole step; nchunk = 1 (plain: per-block operations) or n_blocks (batched)
+// Seeded data blocks (he_lr_grad_step_seeded): b-parts b + blk * bs at one
+// level and scale, uniform parts from (seed, index0 + blk).
+struct SeedData {
+    const u64 *b = nullptr;
+    long long bs = 0;
+    u64 seed = 0;
+    uint32_t index0 = 0;
+    int level = 0;
+    double scale = 0.0;
+};
+
+// full ciphertexts of seeded blocks [b0, b0 + nb) into E (stride 2 (level+1) N)
+void expand_seeded(he_ctx *c, const SeedData &sd, int b0, int nb, u64 *E)
+{
+    const long long lc = (long long)(sd.level + 1) * c->N;
+    hek::ewise(c, 4, sd.level, nb, 1, sd.b + b0 * sd.bs, sd.bs, 0, nullptr, 0, 0, E, 2 * lc, 0, 0);
+    hek::seeded_a(c, sd.seed, sd.index0 + (uint32_t)b0, nb, sd.level, E + lc, 2 * lc);
+}
+
 he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_blocks, long long zbs, const BabyData &bd,
                     const TermData &td, const he_ct *W, const he_pt *mask, int cols, int rows, const he_keys *keys,
-                    int chunk, he_ct *W_out, he_ct *G_out)
+                    int chunk, he_ct *W_out, he_ct *G_out, const SeedData *sd = nullptr)
 {
     const long long N = c->N;
     const int l = W->level;
     Arena ar = arena(c);
     StepBufs s;
     const bool fm = pl.layout == HE_LAYOUT_FEATURES;
+    u64 *E = nullptr;  // one chunk of seeded blocks, expanded
+    if (sd) {
+        E = ar.take((size_t)chunk * 2 * (sd->level + 1) * N);
+        if (!E) return HE_ENOMEM;
+    }
     TRY(step_alloc(c, ar, l, chunk, pl.layout, bd.n_baby, s));
     if (bd.n_baby > 1) {
         // the baby steps of W, once per step for every block: Rot(W, j u), j = 1 .. n_baby - 1
@@ -1076,6 +1100,17 @@ he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_block
         int nb = std::min(chunk, n_blocks - b0);
         long long bs = zbs;
         if (chunk == 1) bs = 0;
+        if (sd) {
+            // this chunk's blocks as full ciphertexts, then the same per-block kernels
+            expand_seeded(c, *sd, b0, nb, E);
+            const he_ct ze{E, sd->level, 0, sd->scale};
+            const long long es = 2LL * (sd->level + 1) * N;
+            if (fm)
+                TRY(step_blocks_features(c, ar, s, pl, &ze, es, 0, nb, W, cols, rows, keys, b0 > 0, bd, td));
+            else
+                TRY(step_blocks(c, ar, s, pl, &ze, es, 0, nb, W, mask, cols, keys, b0 > 0, bd, td));
+            continue;
+        }
         if (fm)
             TRY(step_blocks_features(c, ar, s, pl, Z, bs, b0, nb, W, cols, rows, keys, b0 > 0, bd, td));
         else
@@ -1438,6 +1473,46 @@ he_status he_encrypt(he_ctx *c, const he_pt *pt, const he_keys *k, int use_sk, u
     return last_error();
 }
 
+he_status he_encrypt_seeded(he_ctx *c, const he_pt *pt, const he_keys *k, uint64_t seed, uint32_t index,
+                            he_ct_seeded *out)
+{
+    if (!c || !pt || !k || !out || !pt->data || !out->b || pt->level < 0 || pt->level >= c->nq) return HE_EINVAL;
+    const int l = pt->level;
+    const size_t n = (size_t)(l + 1) * c->N;
+    TRY(ensure_ws(c, 2 * al(n) * 8 + 4096));
+    Arena ar = arena(c);
+    u64 *a = ar.take(n), *e = ar.take(n);
+    if (!a || !e) return HE_ENOMEM;
+    std::vector<int> ids = identity_positions(l + 1);
+    hek::seeded_a(c, seed, index, 1, l, a, 0);  // already in the evaluation domain
+    hek::sample_cbd(c, seed, ST_ENC_E0, index, 0, l + 1, ids.data(), e);
+    hek::ntt_batch(c, e, 0, 0, 1, 1, 0, l + 1, l, +1, nullptr, false);
+    hek::enc_combine(c, l, a, k->sk, e, pt->data, out->b);
+    out->level = l;
+    out->scale = pt->scale;
+    out->seed = seed;
+    out->index = index;
+    return last_error();
+}
+
+he_status he_ct_expand(he_ctx *c, const he_ct_seeded *in, int n, he_ct *out)
+{
+    if (!c || !in || !out || n < 0) return HE_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!in[i].b || !out[i].data || in[i].level < 0 || in[i].level >= c->nq) return HE_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        SeedData sd;
+        sd.b = in[i].b;
+        sd.seed = in[i].seed;
+        sd.index0 = in[i].index;
+        sd.level = in[i].level;
+        expand_seeded(c, sd, 0, 1, out[i].data);
+        out[i].level = in[i].level;
+        out[i].scale = in[i].scale;
+    }
+    return last_error();
+}
+
 he_status he_decrypt(he_ctx *c, const he_ct *ct, const he_keys *k, uint64_t *host)
 {
     if (!c || !ct_ok(c, ct) || !k || !host) return HE_EINVAL;
@@ -1793,6 +1868,68 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
         G_out->scale = pl.s_g;
     }
     return last_error();
+}
+
+he_status he_lr_grad_step_seeded(he_ctx *c, const he_ct_seeded *Z, int n_blocks, const he_ct *W, const he_pt *mask,
+                                 const double coef[4], double eta_over_n, double w_decay, int cols, int rows,
+                                 int layout, int chunk, const he_keys *k, he_ct *W_out, he_ct *G_out)
+{
+    if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !mask || !mask->data || !coef || !k || chunk < 1 ||
+        chunk > n_blocks)
+        return HE_EINVAL;
+    if (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES) return HE_EINVAL;
+    const bool fm = layout == HE_LAYOUT_FEATURES;
+    if (!W_out || !W_out->data || (G_out && !G_out->data)) return HE_EINVAL;
+    if (cols < 1 || rows < 1 || (cols & (cols - 1)) || (rows & (rows - 1)) || (long long)cols * rows != c->N / 2)
+        return HE_EINVAL;
+    const int l = W->level;
+    if (l < 4) return HE_ELEVEL;
+    if (mask->level != (fm ? l - 3 : l - 1)) return HE_ELEVEL;
+    SeedData sd;
+    sd.b = Z[0].b;
+    sd.level = Z[0].level;
+    sd.scale = Z[0].scale;
+    sd.seed = Z[0].seed;
+    sd.index0 = Z[0].index;
+    for (int b = 0; b < n_blocks; ++b) {
+        const he_ct_seeded &z = Z[b];
+        if (!z.b || z.level != sd.level) return z.b ? HE_ELEVEL : HE_EINVAL;
+        if (z.scale != sd.scale || z.seed != sd.seed || z.index != sd.index0 + (uint32_t)b) return HE_EINVAL;
+        if (b == 1) sd.bs = Z[1].b - Z[0].b;
+        if (b > 1 && Z[b].b - Z[b - 1].b != sd.bs) return HE_EINVAL;
+    }
+    if (sd.level < l || sd.level >= c->nq) return HE_ELEVEL;
+    if (n_blocks > 1 && sd.bs < (long long)(sd.level + 1) * c->N) return HE_EINVAL;
+    he_lr_plan pl;
+    TRY(hehost::plan_lr_step(c->q.data(), c->nq, l, sd.scale, W->scale, coef, eta_over_n, w_decay, layout, &pl));
+    if (mask->scale != pl.s_mask) return HE_ESCALE;
+    const int pm = fm ? rows : cols;
+    const int st = fm ? cols : rows;
+    const long long unit = fm ? rows : cols;
+    for (int t = 1; t < pm; t <<= 1)
+        if (!find_rot_key(k, galois_of(c, t)) || !find_rot_key(k, galois_of(c, -t))) return HE_EKEY;
+    const long long mu = fm ? rows : 1;
+    for (int t = 1; t < cols; t <<= 1)
+        if (!find_rot_key(k, galois_of(c, (long long)t * mu))) return HE_EKEY;
+    for (int t = 1; t < st; t <<= 1)
+        if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
+    TRY(ensure_ws(c, step_bytes(c, l, chunk, layout, 1) + al((size_t)chunk * 2 * (sd.level + 1) * c->N) * 8));
+    BabyData bd;
+    TermData td;
+    TRY(step_impl(c, pl, nullptr, n_blocks, 0, bd, td, W, mask, cols, rows, k, chunk, W_out, G_out, &sd));
+    W_out->level = l - 4;
+    W_out->scale = pl.s_g;
+    if (G_out) {
+        G_out->level = l - 4;
+        G_out->scale = pl.s_g;
+    }
+    return last_error();
+}
+
+size_t he_lr_step_seeded_bytes(const he_ctx *c, int level, int data_level, int chunk, int layout)
+{
+    if (!c || level < 4 || level >= c->nq || data_level < level || data_level >= c->nq || chunk < 1) return 0;
+    return step_bytes(c, level, chunk, layout, 1) + al((size_t)chunk * 2 * (data_level + 1) * c->N) * 8;
 }
 
 he_status he_lr_data_terms(he_ctx *c, const he_ct *Z, int n_blocks, int w_level, double w_scale, const double coef[4],

@@ -123,7 +123,7 @@ he_status plan_lr_infer(const u64 *q, int n_q, int level, double s_z, double s_w
 }  // namespace hehost
 
 enum { ST_SECRET = 1, ST_PK_A = 2, ST_PK_E = 3, ST_EVK_A = 4, ST_EVK_E = 5, ST_ENC_A = 6, ST_ENC_E0 = 7,
-       ST_ENC_V = 8, ST_ENC_E1 = 9 };
+       ST_ENC_V = 8, ST_ENC_E1 = 9, ST_SEED_A = 10 };
 
 // ------------------------------------------------------------------ launchers (kernels.hip)
 // Batched operands are addressed as base + b * (batch stride) + c * (component
@@ -235,6 +235,11 @@ void sample_uniform(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t
 void sample_cbd(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp, int n_pos,
                 const int *prime_of_pos, u64 *out);
 void int_to_rns(he_ctx *c, const i64 *m, int n_pos, const int *prime_of_pos, u64 *out);
+// the uniform part of seeded ciphertexts, drawn in the evaluation domain:
+// entry e (stream index index0 + e), limb i: the value at root psi_i^(2k+1) is
+// the uniform residue of coefficient k of stream (seed; ST_SEED_A, index0 + e,
+// i), stored at NTT position bitrev(k); out + e * os, limbs 0..level
+void seeded_a(he_ctx *c, u64 seed, uint32_t index0, int nent, int level, u64 *out, long long os);
 // ternary v: word x of the stream, bit 0 clear -> 0, else bit 1 ? -1 : +1
 void sample_ternary(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp, int n_pos,
                     const int *prime_of_pos, u64 *out);

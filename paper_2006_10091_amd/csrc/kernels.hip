@@ -2268,6 +2268,31 @@ __global__ __launch_bounds__(256) void cbd_kernel(u64 seed, uint32_t type, uint3
     }
 }
 
+// Uniform part of seeded ciphertexts in the evaluation domain.  Thread j0 <
+// N/4 computes ChaCha20 block b = bitrev_{logN-2}(j0), i.e. the coefficients
+// k = 4b + u (u < 4) of the stream, whose NTT positions bitrev_logN(k) =
+// bitrev_2(u) N/4 + j0 are four coalesced streams across the threads.
+__global__ __launch_bounds__(256) void seeded_a_kernel(u64 seed, uint32_t index0, const PrimeInfo *__restrict__ pinfo,
+                                                       u64 *__restrict__ out, long long os, int logN)
+{
+    const int i = blockIdx.y, e = blockIdx.z;
+    const int Q = 1 << (logN - 2);
+    const PrimeInfo p = pinfo[i];
+    u64 *o = out + (long long)e * os + ((long long)i << logN);
+    for (int j0 = blockIdx.x * 256 + threadIdx.x; j0 < Q; j0 += gridDim.x * 256) {
+        const uint32_t b = __brev((uint32_t)j0) >> (34 - logN);
+        uint32_t w[16];
+        chacha_block((uint32_t)seed, (uint32_t)(seed >> 32), b, ST_SEED_A, index0 + (uint32_t)e, (uint32_t)i, w);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const u64 hi = w[4 * u] | ((u64)w[4 * u + 1] << 32);
+            const u64 lo = w[4 * u + 2] | ((u64)w[4 * u + 3] << 32);
+            const int bu = (u >> 1) | ((u & 1) << 1);  // bitrev_2(u)
+            o[j0 + bu * Q] = reduce128(hi, lo, p);
+        }
+    }
+}
+
 // ternary with P(0) = 1/2, P(+-1) = 1/4 from word x: bit 0 clear -> 0, else bit 1 ? -1 : +1
 __global__ __launch_bounds__(256) void ternary_kernel(u64 seed, uint32_t type, uint32_t index, uint32_t comp,
                                                       PosPrimes pp, const PrimeInfo *__restrict__ pinfo,
@@ -3145,6 +3170,12 @@ void evk_combine(he_ctx *c, const u64 *a, const u64 *s, const u64 *e, const u64 
     int d0 = digit * c->alpha, d1 = std::min(d0 + c->alpha, c->nq);
     dim3 g(xblocks(c->N), c->np, 1);
     evk_kernel<<<g, 256, 0, c->stream>>>(a, s, e, sp, c->t.dn_p, c->t.pinfo, d0, d1, b, c->logN);
+}
+
+void seeded_a(he_ctx *c, u64 seed, uint32_t index0, int nent, int level, u64 *out, long long os)
+{
+    dim3 g(std::max(1, c->N / 4 / 256), level + 1, nent);
+    seeded_a_kernel<<<g, 256, 0, c->stream>>>(seed, index0, c->t.pinfo, out, os, c->logN);
 }
 
 void sample_ternary(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp, int n_pos,

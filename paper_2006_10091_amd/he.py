@@ -47,6 +47,11 @@ he_pt = he_ct
 he_ct3 = he_ct
 
 
+class he_ct_seeded(ctypes.Structure):
+    _fields_ = [("b", c_void_p), ("level", c_int32), ("reserved", c_int32), ("scale", c_double), ("seed", c_uint64),
+                ("index", c_uint32), ("reserved2", c_uint32)]
+
+
 class he_lr_plan(ctypes.Structure):
     _fields_ = [("level_in", c_int32), ("level_out", c_int32)] + \
         [(n, c_double) for n in ("s1", "s_mask", "s_m", "s_a", "t", "s_z3", "s_b3", "s_c", "s_z1", "s_b1", "s_g")] + \
@@ -85,6 +90,11 @@ _sig = {
     "he_pt_load": (c_int, [c_void_p, _P(c_int64), c_int, c_double, _P(he_pt)]),
     "he_encrypt": (c_int, [c_void_p, _P(he_pt), c_void_p, c_int, c_uint64, c_uint32, _P(he_ct)]),
     "he_decrypt": (c_int, [c_void_p, _P(he_ct), c_void_p, _P(c_uint64)]),
+    "he_encrypt_seeded": (c_int, [c_void_p, _P(he_pt), c_void_p, c_uint64, c_uint32, _P(he_ct_seeded)]),
+    "he_ct_expand": (c_int, [c_void_p, _P(he_ct_seeded), c_int, _P(he_ct)]),
+    "he_lr_grad_step_seeded": (c_int, [c_void_p, _P(he_ct_seeded), c_int, _P(he_ct), _P(he_pt), _P(c_double), c_double,
+                                       c_double, c_int, c_int, c_int, c_int, c_void_p, _P(he_ct), _P(he_ct)]),
+    "he_lr_step_seeded_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int, c_int]),
     "he_decrypt_decode": (c_int, [c_void_p, _P(he_ct), c_void_p, c_int, _P(c_double), _P(c_double)]),
     "he_ct_download": (c_int, [c_void_p, _P(he_ct), _P(c_uint64)]),
     "he_ct_upload": (c_int, [c_void_p, _P(c_uint64), c_int, c_double, _P(he_ct)]),
@@ -193,6 +203,19 @@ class Ciphertext:
 
 
 Plaintext = Ciphertext
+
+
+class SeededCiphertext:
+    """Seeded ciphertext: its b component (torch storage) and the (seed,
+    index) its uniform part is regenerated from."""
+
+    def __init__(self, tensor, level, scale, seed, index, offset=0):
+        self.tensor, self.level, self.scale, self.seed, self.index, self.offset = tensor, level, scale, seed, index, \
+            offset
+
+    def struct(self):
+        return he_ct_seeded(self.tensor.data_ptr() + 8 * self.offset, self.level, 0, self.scale, self.seed,
+                            self.index, 0)
 
 
 # he_alloc_fn / he_free_fn: the library's device memory comes from torch
@@ -347,6 +370,54 @@ class Context:
         _chk(_lib.he_encrypt(self.h, ctypes.byref(p), keys.handle, 1 if use_sk else 0, seed, index, ctypes.byref(s)),
              "he_encrypt")
         return out.update(s)
+
+    def seeded_block(self, count, level):
+        """count seeded ciphertexts' b-parts at one level in one allocation."""
+        per = (level + 1) * self.N
+        t = self._alloc(per * count)
+        return [SeededCiphertext(t, level, 0.0, 0, 0, offset=i * per) for i in range(count)]
+
+    def encrypt_seeded(self, pt, keys, seed, index, out=None):
+        """he_encrypt_seeded: b only; the uniform part is (seed, index)."""
+        out = out or self.seeded_block(1, pt.level)[0]
+        p, s = pt.struct(), out.struct()
+        _chk(_lib.he_encrypt_seeded(self.h, ctypes.byref(p), keys.handle, seed, index, ctypes.byref(s)),
+             "he_encrypt_seeded")
+        out.level, out.scale, out.seed, out.index = s.level, s.scale, s.seed, s.index
+        return out
+
+    def expand(self, xs, outs=None):
+        outs = outs or [self.ct_empty(x.level) for x in xs]
+        xa = (he_ct_seeded * len(xs))(*[x.struct() for x in xs])
+        oa = (he_ct * len(xs))(*[o.struct() for o in outs])
+        _chk(_lib.he_ct_expand(self.h, xa, len(xs), oa), "he_ct_expand")
+        for o, s_ in zip(outs, oa):
+            o.update(s_)
+        return outs
+
+    def lr_grad_step_seeded(self, Z, W, mask, coef, eta_over_n, cols, rows, keys, chunk, W_out=None, G_out=None,
+                            want_g=True, w_decay=0.0, layout=LAYOUT_ROWS):
+        """he_lr_grad_step_seeded: the step over seeded blocks, `chunk` blocks at a time."""
+        za = Z if isinstance(Z, ctypes.Array) else (he_ct_seeded * len(Z))(*[z.struct() for z in Z])
+        w, m = W.struct(), mask.struct()
+        lo = W.level - 4
+        W_out = W_out or self.ct_empty(lo)
+        if want_g:
+            G_out = G_out or self.ct_empty(lo)
+        wo = W_out.struct()
+        go = G_out.struct() if want_g else None
+        cf = np.ascontiguousarray(coef, dtype=np.float64)
+        _chk(_lib.he_lr_grad_step_seeded(self.h, za, len(za), ctypes.byref(w), ctypes.byref(m), _f64p(cf),
+                                         eta_over_n, w_decay, cols, rows, layout, chunk, keys.handle,
+                                         ctypes.byref(wo), ctypes.byref(go) if go is not None else None),
+             "he_lr_grad_step_seeded")
+        W_out.update(wo)
+        if want_g:
+            G_out.update(go)
+        return W_out, (G_out if want_g else None)
+
+    def step_seeded_bytes(self, level, data_level, chunk, layout=LAYOUT_ROWS):
+        return int(_lib.he_lr_step_seeded_bytes(self.h, level, data_level, chunk, layout))
 
     def decrypt(self, ct, keys):
         out = np.zeros((ct.level + 1, self.N), dtype=np.uint64)

@@ -750,3 +750,26 @@ def test_encrypted_step_feature_major(loss, w_decay, n_baby):
     for i in (0, 5, r - 1):
         want = (1.0 - w_decay) * wfull[:16, i] + gref
         assert np.max(np.abs(wn[:16, i] - want)) / np.max(np.abs(want)) < 2.0 ** -20
+
+
+def test_seeded_encryption_decrypts_and_its_a_is_the_stream_in_the_evaluation_domain():
+    """orc_encrypt_sk_seeded: decrypts to m within the error bound (as sk
+    encryption), its uniform part's forward NTT is the (seed, index) stream's
+    uniform residues in natural evaluation order, and another index gives
+    another a."""
+    P = O.Params(13, 5, 1, 1, 30)
+    keys = O.Keys(P, 2001)
+    m = synth.small_poly(4, P.N, 1 << 40)
+    for level in (P.L, 1):
+        ct = O.encrypt_sk_seeded(P, keys, m, level, 1.0, 77, 12)
+        got = O.crt_centered(O.decrypt_residues(P, keys, ct), P.q[: level + 1])
+        err = np.array(got, dtype=object) - m.astype(object)
+        assert max(abs(int(v)) for v in err) <= 21
+        for i in range(level + 1):
+            a = np.ascontiguousarray(ct.data[1, i])
+            O.lib().orc_ntt_fwd(_u64p(a), P.logN, P.q[i], P.psi[i])
+            u = np.zeros(P.N, dtype=np.uint64)
+            O.lib().orc_sample_uniform(77, 10, 12, i, P.q[i], P.logN, _u64p(u))
+            assert np.array_equal(a, u)
+    other = O.encrypt_sk_seeded(P, keys, m, 1, 1.0, 77, 13)
+    assert not np.array_equal(other.data[1], O.encrypt_sk_seeded(P, keys, m, 1, 1.0, 77, 12).data[1])
