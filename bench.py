@@ -53,6 +53,8 @@ def parse():
                                                           "captures every level's graph)")
     ap.add_argument("--plain-steps", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--e2e-steps", type=int, default=10,
+                    help="steps of the end-to-end figure (from the encrypted shard, everything included; 0 = skip)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--layout", choices=("both", "feature-major", "row-major"), default="both",
                     help="packings to run (value needs feature-major)")
@@ -194,6 +196,54 @@ def measure_copy_and_giant(torch, H, synth, ctx, ev, n_ct, steps, level=18):
     log("hoisted sum of %d rotations, %d entries at level %d: %.3f ms" % (len(steps), n_ct, level, t * 1e3))
 
 
+def measure_ops(torch, H, synth, ctx, ev, nb, c, r, n_baby, level=18):
+    """The step's two key-switching operations on their own, timed with HIP
+    events on the stream they run on, against their algorithmic bytes (what
+    a fully fused operation must move: inputs read once, outputs written once,
+    each evaluation key read once per launch; every intermediate excluded):
+      * mul+relin+rescale+rotate over 32 ciphertext pairs (he_batch_mul_rotate,
+        one rotation key shared): 4(l+1) limbs in, 2l out per entry, plus the
+        relinearisation and rotation keys, 2 beta (l+1+k) limbs each;
+      * the hoisted giant-step sum over the shard's blocks (he_rotate_sum):
+        2(l+1) limbs in and out per block, plus the c/n_baby - 1 giant-step
+        keys."""
+    N, k = ctx.N, ctx.n_special
+    beta = -(-(level + 1) // ctx.alpha)
+    limb = 8.0 * N
+    key = 2 * beta * (level + 1 + k) * limb
+    q = ctx.primes[: level + 1]
+    out = []
+    keys = ctx.keygen(11, [1])
+    n_ct = 32
+    xs, ys = [], []
+    for i in range(n_ct):
+        for dst_, s_ in ((xs, 100 + 4 * i), (ys, 102 + 4 * i)):
+            d = np.stack([synth.uniform_residues(s_, q, N), synth.uniform_residues(s_ + 1, q, N)])
+            dst_.append(ctx.upload(d, level, 1.0))
+    outs = [ctx.ct_empty(level - 1) for _ in range(n_ct)]
+    ctx.batch_mul_rotate(xs, ys, [1] * n_ct, keys, mode=1, outs=outs)
+    t = ev.time(lambda: ctx.batch_mul_rotate(xs, ys, [1] * n_ct, keys, mode=1, outs=outs), 3)
+    b = n_ct * (4 * (level + 1) + 2 * level) * limb + 2 * key
+    out.append({"op": "mul+relin+rescale+rotate, %d entries at level %d" % (n_ct, level), "ms": t * 1e3,
+                "algorithmic_bytes": b, "gbs": b / t / 1e9, "frac_hbm": b / t / 1e9 / HBM_PEAK_GBS})
+    del xs, ys, outs, keys
+    giant = [g * n_baby * r for g in range(1, c // n_baby)]
+    keys = ctx.keygen(11, giant)
+    xb = ctx.ct_block(nb, level)
+    for i in range(nb):
+        d = np.stack([synth.uniform_residues(300 + 2 * i, q, N), synth.uniform_residues(301 + 2 * i, q, N)])
+        ctx.upload(d, level, 1.0, out=xb[i])
+    ob = ctx.ct_block(nb, level)
+    ctx.rotate_sum(xb, giant, keys, outs=ob)
+    t = ev.time(lambda: ctx.rotate_sum(xb, giant, keys, outs=ob), 3)
+    b = nb * 4 * (level + 1) * limb + len(giant) * key
+    out.append({"op": "hoisted sum of %d rotations, %d blocks at level %d" % (len(giant), nb, level), "ms": t * 1e3,
+                "algorithmic_bytes": b, "gbs": b / t / 1e9, "frac_hbm": b / t / 1e9 / HBM_PEAK_GBS})
+    for o in out:
+        log("%s: %.3f ms, %.0f GB/s algorithmic (%.3f of HBM peak)" % (o["op"], o["ms"], o["gbs"], o["frac_hbm"]))
+    return out
+
+
 def ntt_sweep(torch, H, ev):
     """Forward / inverse NTT over B limbs of a 20 + 4 prime chain (limb i on
     prime i mod 24), each N and B timed with HIP events; algorithmic GB/s =
@@ -287,7 +337,25 @@ def bench_layout(torch, H, T, ctx, keys, X, y, coef, layout, args, Wk):
         log("%s, %s: schedule %.2f ms/step (%d steps); top-level step %.2f ms" % (
             name, key, dt / steps * 1e3, steps, res["top_level_step_ms_" + key]))
     res["batched_over_plain"] = res["steps_per_s_graph"] / res["steps_per_s_plain"]
-    del Z, workers, Zrot
+    del workers, Zrot
+    if args.e2e_steps > 0:
+        # end to end from the encrypted shard: the worker's baby-step copies of
+        # its data, the data terms and graph captures on first use of each
+        # level, and the steps with their refreshes
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        wk = T.Worker(ctx, keys, Z, coef, eta_n, c, r, mode=2, layout=layout, n_baby=n_baby)
+        sched = Schedule(wk, ps, np.zeros(d))
+        sched.iterate(args.e2e_steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res["end_to_end_s"] = dt
+        res["end_to_end_steps"] = args.e2e_steps
+        res["end_to_end_steps_per_s"] = args.e2e_steps / dt
+        log("%s: end to end, %d steps from the encrypted shard (baby-step copies, data terms, graph captures, "
+            "refreshes): %.3f s (%.2f steps/s)" % (name, args.e2e_steps, dt, args.e2e_steps / dt))
+        del wk, sched
+    del Z
     return res
 
 
@@ -341,6 +409,18 @@ def main():
     copy_gbs, ntt = measure_copy_and_ntt(torch, ctx, ev, nb)
     t_fwd, t_inv, nlimb, alg_bytes = ntt["t_fwd"], ntt["t_inv"], ntt["nlimb"], ntt["alg_bytes"]
     ntt_gbs = alg_bytes / t_fwd / 1e9
+    # VALU roofline of the transform: its butterflies at the measured peak of
+    # each butterfly form (lazy FP64 for the 40-bit primes, 64-bit Shoup for q_0)
+    L = ctx.n_q - 1
+    peak_fp = ctx.valu_peak(1, True)
+    peak_int = ctx.valu_peak(0, False)
+    per_limb = (ctx.N // 2) * Wk["logN"]
+    n_int = sum(1 for i in range(nlimb) if ctx.primes[i % (L + 1)] >= (1 << 46))
+    t_valu = per_limb * ((nlimb - n_int) / peak_fp + n_int / peak_int)
+    valu_frac = t_valu / t_fwd
+    log("VALU peak: %.1f G butterflies/s (FP64 lazy), %.1f G/s (64-bit Shoup); forward NTT at %.2f of it" % (
+        peak_fp / 1e9, peak_int / 1e9, valu_frac))
+    ops = measure_ops(torch, H, synth, ctx, ev, nb, c, r, max(args.baby, 1))
     sweep = ntt_sweep(torch, H, ev)
 
     out = {
@@ -367,6 +447,8 @@ def main():
         "batched_nograph_steps_per_s": best["steps_per_s_batched"],
         "batched_over_plain": best["batched_over_plain"],
         "decrypted_grad_rel_err": best["decrypted_grad_rel_err"],
+        "end_to_end": {k: best[k] for k in ("end_to_end_s", "end_to_end_steps", "end_to_end_steps_per_s")
+                       if k in best},
         "layouts": layouts,
         "ntt_fwd_gbs_algorithmic": ntt_gbs,
         "ntt_inv_gbs_algorithmic": alg_bytes / t_inv / 1e9,
@@ -375,31 +457,47 @@ def main():
         "ntt_fwd_frac_of_copy": ntt_gbs / copy_gbs,
         "roofline": {"bound": "hbm", "achieved": ntt_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ntt_gbs / HBM_PEAK_GBS, "traffic": NTT_TRAFFIC_BYTES.get(nlimb),
-                     "kernel": "ntt (forward, two passes) over %d limbs of N=2^16" % nlimb},
+                     "kernel": "ntt (forward, two passes) over %d limbs of N=2^16" % nlimb,
+                     "valu_frac": valu_frac, "valu_peak_bfly_per_s": {"fp64_lazy": peak_fp, "int64_shoup": peak_int}},
+        "ops": ops,
+        "ntt_tuning": ctx.ntt_tuned,
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(Wk, args.cpu_threads, nb, c, r, best["n_baby"])
     print(json.dumps(out), flush=True)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
     """The oracle on a bounded sample of the feature-major schedule: one
     mul+relin+rescale and one rotation at every level the schedule's key
     switches run at, and one hoisted giant-step sum at the top step level
-    (scaled to the other levels by the rotation times; one run each),
-    extrapolated by the schedule's counts: per block the margin
-    relinearisation and the giant steps (one hoisted sum, or log2(c / n_baby)
-    rotations); per step W's n_baby - 1 baby-step rotations, the one
-    relinearisation of the summed degree-4 terms (three key switches, each
-    timed as a mul+relin+rescale) and the sample-sum and replicate rotations.
-    The degree-2 products A and B3 (tensor and rescale),
+    (scaled to the other levels by the rotation times), each the median of 3
+    runs on all host threads, extrapolated by the schedule's counts: per block
+    the margin relinearisation and the giant steps (one hoisted sum, or
+    log2(c / n_baby) rotations); per step W's n_baby - 1 baby-step rotations,
+    the one relinearisation of the summed degree-4 terms (three key switches,
+    each timed as a mul+relin+rescale) and the sample-sum and replicate
+    rotations.  The degree-2 products A and B3 (tensor and rescale),
     plaintext products, additions, the data's baby-step copies (built once per
-    shard) and the refresh are left out, so the CPU rate is an upper bound."""
-    if threads:
-        os.environ["OMP_NUM_THREADS"] = str(threads)
-    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    shard) and the refresh are left out, so the CPU rate is an upper bound.
+    The one-thread figure scales it by the measured all-threads / one-thread
+    time ratio of a mul+relin+rescale and a rotation at the lowest step level
+    (median of 3 each)."""
     from oracle import ckks as O
     from paper_2006_10091_amd import synth
+    if threads:
+        O.lib().orc_set_threads(threads)
+    nthreads = int(O.lib().orc_max_threads())
     P = O.Params(Wk["logN"], Wk["nq"], Wk["nk"], Wk["alpha"], Wk["log_delta"])
     keys = O.Keys.__new__(O.Keys)
     keys.P, keys.seed = P, 7
@@ -424,10 +522,13 @@ def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
         return O.CT(np.stack([synth.uniform_residues(seed, P.q[: level + 1], P.N),
                               synth.uniform_residues(seed + 1, P.q[: level + 1], P.N)]), level, 1.0)
 
-    def timed(fn, *a):
-        t = time.time()
-        fn(*a)
-        return time.time() - t
+    def timed(fn):
+        ts = []
+        for _ in range(3):
+            t = time.time()
+            fn()
+            ts.append(time.time() - t)
+        return float(np.median(ts))
 
     lc, lr = int(np.log2(c // n_baby)), int(np.log2(r))
     levels = [P.L - 4 * k for k in range(REFRESH_EVERY)]
@@ -455,15 +556,26 @@ def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
         if n_baby > 1:
             t_sched += (n_baby - 1) * sample["rot%d" % l]
     t_step = t_sched / len(levels)
+    # one thread: the same operations at the lowest step level, timed again
+    lo = levels[-1]
+    x, z, xr = ct(lo, 1), ct(lo, 3), ct(lo - 1, 5)
+    O.lib().orc_set_threads(1)
+    t1 = timed(lambda: O.rescale(P, O.mul(P, x, z, keys))) + timed(lambda: O.rotate(P, xr, 1, keys))
+    O.lib().orc_set_threads(nthreads)
+    ta = sample["mul%d" % lo] + sample["rot%d" % (lo - 1)]
     return {"value": 1.0 / t_step, "unit": "steps/s", "cores": nthreads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "one_thread_value": 1.0 / (t_step * t1 / ta), "one_thread_over_all": t1 / ta,
             "sample": "one oracle mul+relin+rescale and one rotation at each level the feature-major schedule "
                       "key-switches at, and one hoisted sum of the %d giant steps at the top step level, scaled to "
-                      "the others by the rotation times (one run each; "
-                      "%.1fs of sampled work, keys %.1fs), extrapolated by the schedule's counts (steps at levels %s, "
+                      "the others by the rotation times (median of 3 runs each on %d threads; %.1fs of sampled work, "
+                      "keys %.1fs), extrapolated by the schedule's counts (steps at levels %s, "
                       "%d baby steps: %d blocks x (1 mul + %s) + %d+3+2x%d rotations per step; tensor products and "
-                      "rescales of A and B3, which need no key switch, are left out)" % (
-                          len(giant) if hoisted else 0, sum(sample.values()), t_keys, "/".join(map(str, levels)),
-                          n_baby, nb, "1 hoisted sum" if hoisted else "%d rotations" % lc, n_baby - 1, lr),
+                      "rescales of A and B3, which need no key switch, are left out); one thread: scaled by the "
+                      "1-thread / %d-thread time of a mul+relin+rescale and a rotation at level %d (%.1fx)" % (
+                          len(giant) if hoisted else 0, nthreads, 3 * sum(sample.values()), t_keys,
+                          "/".join(map(str, levels)), n_baby, nb, "1 hoisted sum" if hoisted else "%d rotations" % lc,
+                          n_baby - 1, lr, nthreads, lo, t1 / ta),
             "extrapolated": True, "sample_seconds": sample}
 
 

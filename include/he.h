@@ -531,6 +531,14 @@ he_status he_rotate_many(he_ctx *ctx, const he_ct *x, int n, const int *steps, i
  * prime_idx0 + (i % prime_period) of the chain.  Exposed for benchmarking. */
 he_status he_ntt(he_ctx *ctx, uint64_t *data, int n_limbs, int prime_idx0, int prime_period, int dir);
 
+/* The VALU roofline of the NTT (measurement): butterflies per second of the
+ * transform's butterfly on prime prime_idx with its operands in registers
+ * and no memory traffic, fp64 = 1 the lazy FP64 form (primes below 2^46),
+ * 0 the 64-bit Shoup form; timed with HIP events on the context's stream
+ * (synchronises it).  A transform's VALU fraction is its (N/2) log2 N
+ * butterflies per limb times limbs per second over this rate.  HE_EINVAL. */
+he_status he_valu_peak(he_ctx *ctx, int prime_idx, int fp64, double *bfly_per_s);
+
 const char *he_strerror(he_status s);
 
 #ifdef __cplusplus

@@ -75,6 +75,8 @@ def lib():
         "orc_secret_square": (None, [P, i64p, u64p]),
         "orc_set_conv_centring": (None, [c_int]),
         "orc_encrypt_sk_seeded": (None, [P, c_int, i64p, i64p, c_uint64, c_uint32, u64p]),
+        "orc_set_threads": (None, [c_int]),
+        "orc_max_threads": (c_int, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -17,6 +17,7 @@
  * hybrid key switching, prime rule, sampler and PRNG are the readings listed in
  * the design notes and implemented here from their textbook definitions.
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -57,6 +58,10 @@ static u64 smod(i64 v, u64 q)
 }
 
 u64 orc_mulmod(u64 a, u64 b, u64 q) { return mulmod(a, b, q); }
+
+/* threads of the oracle's parallel loops (its timing as a CPU baseline) */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_max_threads(void) { return omp_get_max_threads(); }
 u64 orc_powmod(u64 b, u64 e, u64 q) { return powmod(b, e, q); }
 
 /* deterministic Miller-Rabin for n < 2^64 (the first 12 primes as bases) */

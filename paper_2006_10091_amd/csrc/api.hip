@@ -2247,6 +2247,16 @@ he_status he_lr_margins(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W,
     return last_error();
 }
 
+he_status he_valu_peak(he_ctx *c, int prime_idx, int fp64, double *bfly_per_s)
+{
+    if (!c || !bfly_per_s || prime_idx < 0 || prime_idx >= c->np) return HE_EINVAL;
+    if (fp64 && c->q[prime_idx] >= (1ull << 46)) return HE_EINVAL;
+    const size_t n = (size_t)256 * 8 * 4 * 256;
+    TRY(ensure_ws(c, al(n) * 8 + 4096));
+    *bfly_per_s = hek::valu_bfly_rate(c, fp64 != 0, prime_idx, (u64 *)c->ws);
+    return *bfly_per_s > 0.0 ? last_error() : HE_EDEVICE;
+}
+
 he_status he_plan_lr_infer(const uint64_t *q, int n_q, int level, double s_z, double s_w, const double coef[4],
                            he_infer_plan *out)
 {

@@ -240,6 +240,10 @@ void int_to_rns(he_ctx *c, const i64 *m, int n_pos, const int *prime_of_pos, u64
 // the uniform residue of coefficient k of stream (seed; ST_SEED_A, index0 + e,
 // i), stored at NTT position bitrev(k); out + e * os, limbs 0..level
 void seeded_a(he_ctx *c, u64 seed, uint32_t index0, int nent, int level, u64 *out, long long os);
+// measured butterflies per second of the NTT's FP64 (fp) or 64-bit integer
+// butterfly with operands in registers (the VALU roofline of the transform);
+// scratch: 256 * 8 * 4 * 256 uint64 of device memory
+double valu_bfly_rate(he_ctx *c, bool fp, int pidx, u64 *scratch);
 // ternary v: word x of the stream, bit 0 clear -> 0, else bit 1 ? -1 : +1
 void sample_ternary(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t comp, int n_pos,
                     const int *prime_of_pos, u64 *out);

@@ -2413,6 +2413,71 @@ namespace hek {
 // into cache-sized chunks costs more in kernel boundaries than it saves.
 constexpr long long NTT_CHUNK_BYTES = 1ll << 40;
 
+// ------------------------------------------------------------------ VALU roofline of the butterflies
+// The NTT's two butterfly forms with operands in registers and no memory
+// traffic: FP = 1 the signed lazy FP64 form (primes below 2^46), FP = 0 the
+// Harvey-lazy Shoup form on 64-bit integers (wider primes).  Each thread runs
+// 8 independent butterfly chains for `iters` rounds; the result is stored so
+// nothing is dead code.  Butterflies per second over the launch is the
+// measured VALU peak of that instruction mix.
+template <bool FP>
+__global__ __launch_bounds__(256) void valu_bfly_kernel(const PrimeInfo *__restrict__ pinfo, int pidx, int iters,
+                                                        u64 *__restrict__ out)
+{
+    const PrimeInfo p = pinfo[pidx];
+    const u64 q = p.q, q2 = 2 * q;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (FP) {
+        const double qd = (double)q, qinv = 1.0 / qd;
+        double x[8], y[8];
+        const double w = (double)(q / 3 + t % 97);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            x[k] = (double)((t * 8 + k) % 1000);
+            y[k] = (double)((t * 8 + k) % 777);
+        }
+        for (int it = 0; it < iters; it += 16) {
+            // 16 stages of the transform's butterfly x +- lazy(y w), then one
+            // reduction per value: the transform's own mix (ranges within [-32q, 33q])
+            for (int st = 0; st < 16; ++st) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const double r = mulmod_lazy_d(y[k], w, qd, qinv);
+                    const double a = x[k];
+                    x[k] = a + r;
+                    y[k] = a - r;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                x[k] = reduce_d(x[k], qd, qinv);
+                y[k] = reduce_d(y[k], qd, qinv);
+            }
+        }
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += x[k] + y[k];
+        out[t] = (u64)acc;
+    } else {
+        u64 x[8], y[8];
+        const u64 w = q / 3 + (u64)(t % 97);
+        const u64 ws = (u64)(((u128)w << 64) / q);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            x[k] = (u64)((t * 8 + k) % 1000);
+            y[k] = (u64)((t * 8 + k) % 777);
+        }
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) ct_bfly(x[k], y[k], w, ws, q, q2);
+        }
+        u64 acc = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += x[k] ^ y[k];
+        out[t] = acc;
+    }
+}
+
 // ------------------------------------------------------------------ persistent two-pass NTT
 // Both passes of a plain forward or inverse transform in one launch, with the
 // intermediate between them kept in the L2 of the XCD that computes it.  A
@@ -3170,6 +3235,31 @@ void evk_combine(he_ctx *c, const u64 *a, const u64 *s, const u64 *e, const u64 
     int d0 = digit * c->alpha, d1 = std::min(d0 + c->alpha, c->nq);
     dim3 g(xblocks(c->N), c->np, 1);
     evk_kernel<<<g, 256, 0, c->stream>>>(a, s, e, sp, c->t.dn_p, c->t.pinfo, d0, d1, b, c->logN);
+}
+
+double valu_bfly_rate(he_ctx *c, bool fp, int pidx, u64 *scratch)
+{
+    const int blocks = 256 * 8 * 4, iters = 4096;  // 4 workgroups per CU, enough waves to fill every SIMD
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return 0.0;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return 0.0;
+    }
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {  // the first launch warms up
+        (void)hipEventRecord(e0, c->stream);
+        if (fp)
+            valu_bfly_kernel<true><<<blocks, 256, 0, c->stream>>>(c->t.pinfo, pidx, iters, scratch);
+        else
+            valu_bfly_kernel<false><<<blocks, 256, 0, c->stream>>>(c->t.pinfo, pidx, iters, scratch);
+        (void)hipEventRecord(e1, c->stream);
+        (void)hipEventSynchronize(e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms > 0.0f ? (double)blocks * 256 * 8 * iters / (ms * 1e-3) : 0.0;
 }
 
 void seeded_a(he_ctx *c, u64 seed, uint32_t index0, int nent, int level, u64 *out, long long os)

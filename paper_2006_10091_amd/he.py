@@ -128,6 +128,7 @@ _sig = {
     "he_lr_step_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int, c_int, c_int]),
     "he_lr_margins_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int]),
     "he_ntt": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
+    "he_valu_peak": (c_int, [c_void_p, c_int, c_int, _P(c_double)]),
 }
 for _n, (_r, _a) in _sig.items():
     _f = getattr(_lib, _n)
@@ -638,6 +639,12 @@ class Context:
         for o, s_ in zip(outs, oa):
             o.update(s_)
         return outs
+
+    def valu_peak(self, prime_idx, fp64=True):
+        """he_valu_peak: measured butterflies per second of the NTT's butterfly."""
+        v = c_double()
+        _chk(_lib.he_valu_peak(self.h, prime_idx, 1 if fp64 else 0, ctypes.byref(v)), "he_valu_peak")
+        return v.value
 
     def ntt(self, tensor, n_limbs, prime_idx0, period, direction):
         _chk(_lib.he_ntt(self.h, c_void_p(tensor.data_ptr()), n_limbs, prime_idx0, period, direction), "he_ntt")
