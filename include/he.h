@@ -186,7 +186,11 @@ he_status he_params_primes(const he_params *prm, uint64_t *out, int n);
  * transforming its own limbs with the intermediate kept in its L2 and `lag`
  * first passes issued ahead of the second ones (1 <= lag <= 3), for
  * transforms of at least min_limbs limbs (smaller ones take the two-launch
- * form); 0: one launch per pass (the intermediate goes through HBM).  Drops
+ * form); 2 / 3: one workgroup of 512 / 1024 threads per limb doing both
+ * passes through a scratch limb of its own (8 * wg_per_xcd workgroups, at
+ * most 512; the scratch kept in L2 / Infinity Cache; lag unused; ring
+ * degrees whose passes do not split evenly fall back to two launches);
+ * 0: one launch per pass (the intermediate goes through HBM).  Drops
  * the captured graphs.  HE_EINVAL for values out of range, during capture,
  * or persistent on a ring below 2^12.  Default: the two-launch form
  * (paper_2006_10091_amd/autotune.py measures the choices and writes the

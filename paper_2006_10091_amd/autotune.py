@@ -4,11 +4,14 @@ For each ring degree and batch size (limbs per transform) it times the
 forward and inverse transforms of uniform residues with HIP events:
   * the two-launch form (one launch per pass, the intermediate through HBM);
   * the persistent form (both passes in one launch, the intermediate kept in
-    each XCD's L2) for every workgroups-per-XCD and lag in the grid below.
+    each XCD's L2) for every workgroups-per-XCD and lag in the grid below;
+  * the workgroup-per-limb forms (mode 2: 512 threads, mode 3: 1024 threads
+    per limb, intermediate in a scratch limb per workgroup) for every
+    workgroups-per-XCD in LIMB_GRID.
 The table maps (log N, batch) to the fastest shape; per ring degree it also
-derives the context setting he_ctx_set_ntt takes: the persistent shape that
+derives the context setting he_ctx_set_ntt takes: the single-launch shape that
 wins at the largest batch, and min_limbs = the smallest measured batch from
-which the persistent form wins at every larger measured batch.  Every shape
+which that shape's mode wins at every larger measured batch.  Every shape
 gives bit-identical results (checked here on every measurement).
 
     python -m paper_2006_10091_amd.autotune [--out ntt_tuning.json] [--quick]
@@ -23,6 +26,7 @@ import numpy as np
 
 WG_GRID = (32, 64, 96, 128)
 LAG_GRID = (1, 2, 3)
+LIMB_GRID = (32, 64)
 BATCHES = {14: (24, 192, 1536, 6144), 15: (24, 192, 768, 3072), 16: (24, 120, 768, 5640)}
 DEFAULT_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "ntt_tuning.json")
 
@@ -59,7 +63,9 @@ def tune(log_ns=(14, 15, 16), quick=False, log=print):
             reps = max(3, min(50, int(2e8 // (nl * N))))
             res = []
             ref = None
-            for shape in [(0, 64, 2)] + [(1, w, g) for w in wgs for g in lags]:
+            shapes = [(0, 64, 2)] + [(1, w, g) for w in wgs for g in lags]
+            shapes += [(m, w, 2) for m in (2, 3) for w in ((32,) if quick else LIMB_GRID)]
+            for shape in shapes:
                 ctx.set_ntt(shape[0], shape[1], shape[2])
                 x.copy_(src)
                 ctx.ntt(x, nl, 0, per, 1)
@@ -76,7 +82,8 @@ def tune(log_ns=(14, 15, 16), quick=False, log=print):
             rows.append(dict(limbs=nl, best=best, two_launch=two, all=res))
             log("2^%d x %d limbs: two-launch %.0f/%.0f us, best %s %.0f/%.0f us (%.0f GB/s algorithmic)" % (
                 log_n, nl, two["fwd_us"], two["inv_us"],
-                "persistent wg %d lag %d" % (best["wg_per_xcd"], best["lag"]) if best["persistent"] else "two-launch",
+                "mode %d wg %d lag %d" % (best["persistent"], best["wg_per_xcd"], best["lag"])
+                if best["persistent"] else "two-launch",
                 best["fwd_us"], best["inv_us"], best["gbs"]))
             del src, x, ref
         table[str(log_n)] = rows
@@ -84,11 +91,12 @@ def tune(log_ns=(14, 15, 16), quick=False, log=print):
         if big["persistent"]:
             mins = rows[-1]["limbs"]
             for r in reversed(rows):
-                if r["best"]["persistent"]:
+                if r["best"]["persistent"] == big["persistent"]:
                     mins = r["limbs"]
                 else:
                     break
-            settings[str(log_n)] = dict(persistent=1, wg_per_xcd=big["wg_per_xcd"], lag=big["lag"], min_limbs=mins)
+            settings[str(log_n)] = dict(persistent=big["persistent"], wg_per_xcd=big["wg_per_xcd"], lag=big["lag"],
+                                        min_limbs=mins)
         else:
             settings[str(log_n)] = dict(persistent=0, wg_per_xcd=64, lag=2, min_limbs=1)
         del ctx

@@ -664,7 +664,7 @@ template <int LOGN, bool INV, int PRO>
 __device__ __forceinline__ void ntt_cols_body(const NttArgs &a, const PrimeInfo *__restrict__ pinfo,
                                               const u64 *__restrict__ tw, const u64 *__restrict__ tws,
                                               const u64 *__restrict__ post, const double *__restrict__ twd,
-                                              const Fuse &f, VB vb, u64 *lds, u64 *xbuf)
+                                              const Fuse &f, VB vb, u64 *lds, u64 *xbuf, int tid)
 {
     constexpr int LM = (LOGN + 1) / 2, N2 = 1 << (LOGN - LM);
     using S = LineShape<LM>;
@@ -672,7 +672,7 @@ __device__ __forceinline__ void ntt_cols_body(const NttArgs &a, const PrimeInfo 
     int pidx;
     if (!ntt_locate(a, vb, limb, pidx)) return;
     u64 *xl = xbuf ? xbuf : limb;  // the intermediate's side of this pass
-    const int cc = threadIdx.x % S::LINES, tau = threadIdx.x / S::LINES;
+    const int cc = tid % S::LINES, tau = tid / S::LINES;
     const int col = vb.x * S::LINES + cc;
     const PrimeInfo p = pinfo[pidx];
     const u64 q = p.q, q2 = 2 * q;
@@ -813,7 +813,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
 {
     using S = LineShape<(LOGN + 1) / 2>;
     __shared__ u64 lds[S::LINES * S::PADDED];
-    ntt_cols_body<LOGN, INV, PRO>(a, pinfo, tw, tws, post, twd, f, vb_here(), lds, nullptr);
+    ntt_cols_body<LOGN, INV, PRO>(a, pinfo, tw, tws, post, twd, f, vb_here(), lds, nullptr, (int)threadIdx.x);
 }
 
 // pass B: rows.  Thread (line, tau) with tau fastest; LINES consecutive rows per workgroup.
@@ -824,7 +824,7 @@ template <int LOGN, bool INV, int MODE>
 __device__ __forceinline__ void ntt_rows_body(const NttArgs &a, const PrimeInfo *__restrict__ pinfo,
                                               const u64 *__restrict__ tw, const u64 *__restrict__ tws,
                                               const double *__restrict__ twd, const Fuse &f, VB vb, u64 *lds,
-                                              u64 *xbuf)
+                                              u64 *xbuf, int tid)
 {
     constexpr int LM = LOGN - (LOGN + 1) / 2, N1 = 1 << ((LOGN + 1) / 2);
     constexpr bool FIN = !INV && MODE == EPI_FINISH;
@@ -833,7 +833,7 @@ __device__ __forceinline__ void ntt_rows_body(const NttArgs &a, const PrimeInfo 
     u64 *limb;
     int pidx;
     if (!ntt_locate(a, vb, limb, pidx)) return;
-    const int tau = threadIdx.x % S::T, ln = threadIdx.x / S::T;
+    const int tau = tid % S::T, ln = tid / S::T;
     const int h = vb.x * S::LINES + ln;
     const PrimeInfo p = pinfo[pidx];
     const u64 q = p.q, q2 = 2 * q;
@@ -1012,7 +1012,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
 {
     using S = LineShape<LOGN - (LOGN + 1) / 2>;
     __shared__ u64 lds[S::LINES * S::PADDED];
-    ntt_rows_body<LOGN, INV, MODE>(a, pinfo, tw, tws, twd, f, vb_here(), lds, nullptr);
+    ntt_rows_body<LOGN, INV, MODE>(a, pinfo, tw, tws, twd, f, vb_here(), lds, nullptr, (int)threadIdx.x);
 }
 
 // Row pass of the extended digits' forward NTT fused with the key-switch
@@ -2554,6 +2554,7 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_persist_t(NttArgs a, const P
     // this XCD's counter block (its own 256 bytes): [0] tickets, [1 + 2 slot] first-pass
     // completions, [2 + 2 slot] second-pass completions
     unsigned *blk = ps.ctr + 64 * x;
+    const int tid = (int)threadIdx.x;
     const unsigned one = threadIdx.x == 0 ? 1u : 0u;
     // wave 0 alone touches the counters (a wave-uniform condition)
     const bool wave0 = __builtin_amdgcn_readfirstlane(threadIdx.x) < 64;
@@ -2601,20 +2602,102 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_persist_t(NttArgs a, const P
         u64 *xb = ps.slots + ((long long)(x * PS_SLOTS + slot) << LOGN);
         if (!INV) {
             if (first) {
-                if (part < PA) ntt_cols_body<LOGN, false, PRO_NONE>(a, pinfo, tw, tws, nullptr, twd, f, vb, lds, xb);
+                if (part < PA) ntt_cols_body<LOGN, false, PRO_NONE>(a, pinfo, tw, tws, nullptr, twd, f, vb, lds, xb, tid);
             } else if (part < PB) {
-                ntt_rows_body<LOGN, false, EPI_NONE>(a, pinfo, tw, tws, twd, f, vb, lds, xb);
+                ntt_rows_body<LOGN, false, EPI_NONE>(a, pinfo, tw, tws, twd, f, vb, lds, xb, tid);
             }
         } else {
             if (first) {
-                if (part < PB) ntt_rows_body<LOGN, true, PRO_NONE>(a, pinfo, tw, tws, twd, f, vb, lds, xb);
+                if (part < PB) ntt_rows_body<LOGN, true, PRO_NONE>(a, pinfo, tw, tws, twd, f, vb, lds, xb, tid);
             } else if (part < PA) {
-                ntt_cols_body<LOGN, true, PRO_NONE>(a, pinfo, tw, tws, post, twd, f, vb, lds, xb);
+                ntt_cols_body<LOGN, true, PRO_NONE>(a, pinfo, tw, tws, post, twd, f, vb, lds, xb, tid);
             }
         }
         // the barrier waits for every wave's stores: the task's output is in L2
         __syncthreads();
         if (wave0) atomicAdd(first ? d1 : d2, one);
+    }
+}
+
+// ------------------------------------------------------------------ one workgroup per limb
+// Both passes of a plain transform by one workgroup of G x 256 threads: the G
+// 256-thread groups take the first pass's line groups in turns, write the
+// intermediate to the workgroup's own scratch limb, meet at a barrier, and
+// take the second pass from it.  No workgroup waits for another; the scratch
+// limb (N words per workgroup) is rewritten limb after limb, so it stays in
+// L2 or the Infinity Cache instead of making a round trip through HBM.  Both
+// passes need a multiple of G line groups, so every group executes the same
+// barriers.  G = 2 (512 threads) keeps 256 VGPRs per lane; G = 4 (1024
+// threads) caps them at 128 and spills.
+template <int LOGN, int G>
+struct LimbShape {
+    static constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
+    static constexpr int PA = (1 << LB) / LineShape<LA>::LINES, PB = (1 << LA) / LineShape<LB>::LINES;
+    static constexpr int WA = LineShape<LA>::LINES * LineShape<LA>::PADDED, WB = LineShape<LB>::LINES * LineShape<LB>::PADDED;
+    static constexpr int W = WA > WB ? WA : WB;
+    static constexpr bool OK = PA % G == 0 && PB % G == 0;
+};
+
+template <int LOGN, bool INV, int G>
+__global__ __launch_bounds__(256 * G) void ntt_limb_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
+                                                      const u64 *__restrict__ tw, const u64 *__restrict__ tws,
+                                                      const u64 *__restrict__ post, const double *__restrict__ twd,
+                                                      u64 *scratch, int nlimb, int npos)
+{
+    using LS = LimbShape<LOGN, G>;
+    static_assert(LS::OK, "line groups per pass must be a multiple of G");
+    __shared__ u64 lds[G * LS::W];
+    const int sub = (int)threadIdx.x >> 8, tid = (int)threadIdx.x & 255;
+    u64 *sl = lds + sub * LS::W;
+    u64 *xb = scratch + ((long long)blockIdx.x << LOGN);
+    Fuse f{};
+    for (int g = (int)blockIdx.x; g < nlimb; g += (int)gridDim.x) {
+        const int y = g % npos, z = g / npos;
+        // A body's last LDS read follows its last barrier, so every body call
+        // ends with a barrier before the next one writes the same LDS slice.
+        // The barrier after a pass's last call also completes the intermediate
+        // (one CU: no cache maintenance needed), and the one after the second
+        // pass keeps the scratch limb until it has been read.
+        if (!INV) {
+            for (int it = 0; it < LS::PA / G; ++it) {
+                ntt_cols_body<LOGN, false, PRO_NONE>(a, pinfo, tw, tws, nullptr, twd, f, VB{G * it + sub, y, z}, sl,
+                                                     xb, tid);
+                __syncthreads();
+            }
+            for (int it = 0; it < LS::PB / G; ++it) {
+                ntt_rows_body<LOGN, false, EPI_NONE>(a, pinfo, tw, tws, twd, f, VB{G * it + sub, y, z}, sl, xb, tid);
+                __syncthreads();
+            }
+        } else {
+            for (int it = 0; it < LS::PB / G; ++it) {
+                ntt_rows_body<LOGN, true, PRO_NONE>(a, pinfo, tw, tws, twd, f, VB{G * it + sub, y, z}, sl, xb, tid);
+                __syncthreads();
+            }
+            for (int it = 0; it < LS::PA / G; ++it) {
+                ntt_cols_body<LOGN, true, PRO_NONE>(a, pinfo, tw, tws, post, twd, f, VB{G * it + sub, y, z}, sl, xb,
+                                                    tid);
+                __syncthreads();
+            }
+        }
+    }
+}
+
+template <int LOGN, int G>
+static bool limb_launch(he_ctx *c, const NttArgs &a, int nlimb, int npos, int dir, const u64 *post)
+{
+    if constexpr (!LimbShape<LOGN, G>::OK) {
+        return false;
+    } else {
+        const int grid = std::min(nlimb, std::min(8 * c->persist.wg_per_xcd, c->persist.limb_wgs));
+        if (dir > 0)
+            ntt_limb_t<LOGN, false, G><<<grid, 256 * G, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh,
+                                                                        nullptr, c->t.psi_d,
+                                                                        c->persist.limb_scratch, nlimb, npos);
+        else
+            ntt_limb_t<LOGN, true, G><<<grid, 256 * G, 0, c->stream>>>(a, c->t.pinfo, c->t.ipsi, c->t.ipsi_sh, post,
+                                                                       c->t.ipsi_d, c->persist.limb_scratch, nlimb,
+                                                                       npos);
+        return true;
     }
 }
 
@@ -2624,7 +2707,15 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
 {
     constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
     const int nz = nbatch * a.ncomp;
-    if (pro == PRO_NONE && epi == EPI_NONE && c->persist.on && c->persist.slots && npos * nz >= c->persist.min_limbs) {
+    if (pro == PRO_NONE && epi == EPI_NONE && c->persist.on >= 2 && c->persist.limb_scratch &&
+        npos * nz >= c->persist.min_limbs) {
+        a.zoff = 0;
+        const bool done = c->persist.on == 2 ? limb_launch<LOGN, 2>(c, a, npos * nz, npos, dir, post)
+                                             : limb_launch<LOGN, 4>(c, a, npos * nz, npos, dir, post);
+        if (done) return;
+    }
+    if (pro == PRO_NONE && epi == EPI_NONE && c->persist.on == 1 && c->persist.slots &&
+        npos * nz >= c->persist.min_limbs) {
         PersistArgs ps;
         ps.ctr = c->persist.ctr;
         ps.slots = c->persist.slots;

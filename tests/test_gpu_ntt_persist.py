@@ -1,7 +1,10 @@
-"""The persistent two-pass NTT (both passes in one launch, the intermediate
-kept in each XCD's L2) against the two-launch form, bit for bit, over ring
-degrees, batch sizes (fewer limbs than XCDs included), launch shapes and both
-directions; and forward then inverse is the identity."""
+"""The single-launch NTT forms against the two-launch form, bit for bit, over
+ring degrees, batch sizes (fewer limbs than XCDs included), launch shapes and
+both directions; and forward then inverse is the identity:
+  * the persistent form (both passes in one launch, the intermediate kept in
+    each XCD's L2, workgroups handing limbs over through per-XCD tickets);
+  * the workgroup-per-limb forms (512 or 1024 threads transform a whole limb
+    through a scratch limb of their own, no inter-workgroup waits)."""
 import numpy as np
 import pytest
 
@@ -47,3 +50,31 @@ def test_persistent_ntt_matches_two_launch(log_n):
     assert torch.equal(x, y)
     with pytest.raises(H.HEError):
         ctx.set_ntt(1, 64, 4)  # lag below the slot count only
+
+
+@pytest.mark.parametrize("log_n", [12, 13, 14, 15, 16])
+def test_workgroup_per_limb_ntt_matches_two_launch(log_n):
+    from paper_2006_10091_amd import he as H
+    ctx = H.Context(log_n, 20, 4, 4, 40)
+    N = ctx.N
+    for nl, per in ((1, 1), (5, 5), (24, 24), (300, 20), (774, 18)):
+        host = np.concatenate([synth.uniform_residues(nl * 10 + b, ctx.primes[:per], N).ravel()
+                               for b in range(nl // per)])
+        src = torch.from_numpy(host.view(np.int64)).cuda()
+        print("2^%d: %d limbs, period %d" % (log_n, nl, per), flush=True)
+        for d in (1, -1):
+            ref = src.clone()
+            ctx.set_ntt(0)
+            ctx.ntt(ref, nl, 0, per, d)
+            for mode, wg in ((2, 32), (2, 64), (2, 1), (3, 32), (3, 7)):
+                x = src.clone()
+                ctx.set_ntt(mode, wg)
+                ctx.ntt(x, nl, 0, per, d)
+                assert torch.equal(x, ref), (nl, per, d, mode, wg)
+        for mode in (2, 3):
+            x = src.clone()
+            ctx.set_ntt(mode, 32)
+            ctx.ntt(x, nl, 0, per, 1)
+            ctx.ntt(x, nl, 0, per, -1)
+            assert torch.equal(x, src)
+    ctx.set_ntt(0)
