@@ -50,7 +50,7 @@ typedef enum {
     HE_ENOMEM = 2,  /* device or host allocation failed */
     HE_ELEVEL = 3,  /* not enough levels / level mismatch */
     HE_ESCALE = 4,  /* scale mismatch or scale plan out of range */
-    HE_EKEY = 5,    /* required evaluation key absent */
+    HE_EKEY = 5,    /* required evaluation key absent, or keys of another parameter set */
     HE_EDEVICE = 6  /* HIP runtime error */
 } he_status;
 
@@ -207,6 +207,12 @@ size_t he_ct3_bytes(const he_ctx *ctx, int level);
 
 /* ---------------------------------------------------------------- keys */
 
+/* A key set is valid for every context of its parameter set (ring degree,
+ * prime chain and digit width, as he_ctx_create derives them from
+ * he_params): contexts of one parameter set may share one key set, as
+ * serving lanes on their own streams do.  Every call that takes keys returns
+ * HE_EKEY for a key set of another parameter set. */
+
 /* Bytes of the key buffer for n_rot rotation keys (secret key, the keys for
  * s^2, s^3 and s^4, the public key [2][n_q][N] and the rotation keys, each
  * evaluation key [dnum][2][n_q+n_special][N]). */
@@ -223,8 +229,11 @@ size_t he_keys_bytes(const he_ctx *ctx, int n_rot);
  * (free with he_keys_destroy; the buffer stays the caller's). */
 he_status he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *rot_steps, int n_rot,
                     void *key_buf, size_t key_buf_bytes, he_keys **out);
-/* Release a key handle; graphs captured with it are dropped (the buffer stays
- * the caller's). */
+/* Release a key handle; graphs its context captured with it are dropped (the
+ * buffer stays the caller's).  Release keys before the context that made
+ * them.  Graphs that other contexts captured with them are never replayed
+ * again (their cache entries name the key set's generation) and go with
+ * those contexts or their next he_ctx_trim. */
 he_status he_keys_destroy(he_keys *keys);
 /* Download a key for inspection, coefficient order: which = -2 secret
  * ([n_q+n_special][N]), -5 the public key ([2][n_q][N]), -1 relinearisation

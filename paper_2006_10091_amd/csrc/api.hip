@@ -1303,6 +1303,16 @@ size_t he_keys_bytes(const he_ctx *c, int n_rot)
     return (size_t)c->np * c->N * 8 + evk * (3 + (size_t)n_rot) + pk;
 }
 
+// Keys are valid for every context of their parameter set (ring degree,
+// prime chain, digit width): their layout and residues depend on nothing else.
+static bool keys_ok(const he_ctx *c, const he_keys *k)
+{
+    if (k->logN != c->logN || k->nq != c->nq || k->nk != c->nk || k->alpha != c->alpha) return false;
+    for (int i = 0; i < c->np; ++i)
+        if (k->q[i] != c->q[i]) return false;
+    return true;
+}
+
 he_status he_keygen(he_ctx *c, uint64_t seed, const int32_t *rot_steps, int n_rot, void *key_buf,
                     size_t key_buf_bytes, he_keys **out)
 {
@@ -1317,6 +1327,11 @@ he_status he_keygen(he_ctx *c, uint64_t seed, const int32_t *rot_steps, int n_ro
     if (!k) return HE_ENOMEM;
     static std::atomic<uint64_t> next_gen{1};
     k->ctx = c;
+    k->logN = c->logN;
+    k->nq = c->nq;
+    k->nk = c->nk;
+    k->alpha = c->alpha;
+    for (int i = 0; i < c->np; ++i) k->q[i] = c->q[i];
     k->gen = next_gen++;
     k->sk = (u64 *)key_buf;
     k->rlk = k->sk + (size_t)np * N;
@@ -1383,6 +1398,7 @@ he_status he_keys_destroy(he_keys *k)
 he_status he_keys_download(he_ctx *c, const he_keys *k, int64_t which, uint64_t *host)
 {
     if (!c || !k || !host) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     const size_t N = c->N;
     const int np = c->np;
     const u64 *src;
@@ -1445,6 +1461,7 @@ he_status he_encrypt(he_ctx *c, const he_pt *pt, const he_keys *k, int use_sk, u
                      he_ct *out)
 {
     if (!c || !pt || !k || !out || !pt->data || !out->data || pt->level < 0 || pt->level >= c->nq) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     const int l = pt->level;
     const size_t N = c->N;
     const size_t n = (size_t)(l + 1) * N;
@@ -1484,6 +1501,7 @@ he_status he_encrypt_seeded(he_ctx *c, const he_pt *pt, const he_keys *k, uint64
                             he_ct_seeded *out)
 {
     if (!c || !pt || !k || !out || !pt->data || !out->b || pt->level < 0 || pt->level >= c->nq) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     const int l = pt->level;
     const size_t n = (size_t)(l + 1) * c->N;
     TRY(ensure_ws(c, 2 * al(n) * 8 + 4096));
@@ -1523,6 +1541,7 @@ he_status he_ct_expand(he_ctx *c, const he_ct_seeded *in, int n, he_ct *out)
 he_status he_decrypt(he_ctx *c, const he_ct *ct, const he_keys *k, uint64_t *host)
 {
     if (!c || !ct_ok(c, ct) || !k || !host) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     const int l = ct->level;
     const size_t N = c->N;
     TRY(ensure_ws(c, al((size_t)(l + 1) * N) * 8 + 4096));
@@ -1538,6 +1557,7 @@ he_status he_decrypt(he_ctx *c, const he_ct *ct, const he_keys *k, uint64_t *hos
 he_status he_decrypt_decode(he_ctx *c, const he_ct *ct, const he_keys *k, int n, double *re, double *im)
 {
     if (!c || !ct_ok(c, ct) || !k || !re || n < 0 || n > c->N / 2) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     const size_t N = c->N;
     std::vector<u64> res((size_t)(ct->level + 1) * N);
     TRY(he_decrypt(c, ct, k, res.data()));
@@ -1603,6 +1623,7 @@ he_status he_mul(he_ctx *c, const he_ct *x, const he_ct *y, he_ct3 *out)
 he_status he_relin(he_ctx *c, const he_ct3 *in, const he_keys *k, he_ct *out)
 {
     if (!c || !in || !in->data || !k || !out || !out->data || in->level < 0 || in->level >= c->nq) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     const int l = in->level;
     TRY(ensure_ws(c, ks_scratch(c, l, 1) * 8 + 4096));
     Arena ar = arena(c);
@@ -1630,6 +1651,7 @@ he_status he_rescale(he_ctx *c, const he_ct *in, he_ct *out)
 he_status he_rotate(he_ctx *c, const he_ct *in, int steps, const he_keys *k, he_ct *out)
 {
     if (!c || !ct_ok(c, in) || !k || !out || !out->data || out->data == in->data) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     const int l = in->level;
     const u64 g = galois_of(c, steps);
     const double sc = in->scale;
@@ -1651,6 +1673,7 @@ he_status he_rotate(he_ctx *c, const he_ct *in, int steps, const he_keys *k, he_
 he_status he_rotate_noalloc(he_ctx *c, const he_ct *in, int steps, const he_keys *k, he_ct *out)
 {
     if (!c || !ct_ok(c, in) || !k || !out || !out->data || out->data == in->data) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     if (!c->noalloc) return HE_EDEVICE;
     const int l = in->level;
     const u64 g = galois_of(c, steps);
@@ -1772,6 +1795,7 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
 {
     if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !mask || !mask->data || !coef || !k || mode < 0 || mode > 2)
         return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     if (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES) return HE_EINVAL;
     const bool fm = layout == HE_LAYOUT_FEATURES;
     if (n_baby < 1 || n_baby > HE_MAXBABY || (n_baby & (n_baby - 1)) || (n_baby > 1 && (n_baby > cols || !Zrot)))
@@ -1884,6 +1908,7 @@ he_status he_lr_grad_step_seeded(he_ctx *c, const he_ct_seeded *Z, int n_blocks,
     if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !mask || !mask->data || !coef || !k || chunk < 1 ||
         chunk > n_blocks)
         return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     if (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES) return HE_EINVAL;
     const bool fm = layout == HE_LAYOUT_FEATURES;
     if (!W_out || !W_out->data || (G_out && !G_out->data)) return HE_EINVAL;
@@ -1988,6 +2013,7 @@ he_status he_rotate_many(he_ctx *c, const he_ct *x, int n, const int *steps, int
                          he_ct *out)
 {
     if (!c || !x || n < 1 || !steps || n_steps < 1 || !k || !out) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     const int l = x[0].level;
     const long long N = c->N, lc = (long long)(l + 1) * N;
     long long xs = 0, os = 0;
@@ -2052,6 +2078,7 @@ he_status he_rotate_sum(he_ctx *c, const he_ct *x, int n, const int *steps, int 
                         he_ct *out)
 {
     if (!c || !x || n < 1 || !steps || n_steps < 1 || n_steps > hek::HE_MAXMULTI || !k || !out) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     const int l = x[0].level;
     const long long N = c->N, lc = (long long)(l + 1) * N;
     long long xs = 0, os = 0;
@@ -2089,6 +2116,7 @@ he_status he_batch_mul_rotate(he_ctx *c, const he_ct *x, const he_ct *y, const i
                               int mode, he_ct *out)
 {
     if (!c || !x || !y || !steps || !k || !out || n < 1 || mode < 0 || mode > 2) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     std::vector<u64> gal(n);
     std::map<int, std::vector<int>> groups;
     for (int i = 0; i < n; ++i) {
@@ -2141,6 +2169,7 @@ he_status margins_args(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, 
 {
     if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !k || !out || !out[0].data || mode < 0 || mode > 2)
         return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
     if (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES) return HE_EINVAL;
     if (cols < 1 || rows < 1 || (cols & (cols - 1)) || (rows & (rows - 1)) || (long long)cols * rows != c->N / 2)
         return HE_EINVAL;

@@ -99,7 +99,9 @@ struct he_ctx {
 };
 
 struct he_keys {
-    he_ctx *ctx;
+    he_ctx *ctx;                    // the context that made them (its graphs are dropped with them)
+    int logN, nq, nk, alpha;        // the parameter set they are valid for:
+    u64 q[HE_MAXP];                 // any context with this ring and chain may use them
     uint64_t gen;                   // unique per key set (graph-cache key; never reused)
     u64 *sk;                        // [np][N] NTT
     u64 *rlk;                       // [dnum][2][np][N] NTT: s^2 -> s

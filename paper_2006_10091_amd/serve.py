@@ -2,32 +2,42 @@
 
 Requests arrive as a Poisson stream.  Each is either a gradient step (eq.
 (appr) + eq. (update) on the request's blocks) or an inference (the margins
-w.x_i, he_lr_margins).  A request has its own shard size n, feature count d
-(padded to c = 2^ceil(log2 d)) and ring degree N.  Keys, the encrypted data
-pools and the weights are resident in HBM; a request's blocks are the first
-ceil(n / r) blocks of its (N, c) pool.
+w.x_i, he_lr_margins, with the served model W).  A request has its own shard
+size n, feature count d (padded to c = 2^ceil(log2 d)) and ring degree N.
+Keys, the encrypted data pools and the models are resident in HBM; a
+request's blocks are the first ceil(n / r) blocks of its (N, c) pool.
 
-Continuous batching: each ring degree has `lanes` execution lanes.  A lane is
-a library context of its own, bound to its own HIP stream, with its own
-workspace and its own copy of the keys (same seed, so every lane computes
-bit-identical results).  The loop runs on the host:
-- move the requests whose arrival time has passed into the queue;
-- admit: for each ring degree, the oldest queued request of that degree is
-  launched on a free lane of that degree when its bytes fit the budget.  Its
-  bytes are the workspace for its block count (he_lr_step_bytes /
-  he_lr_margins_bytes) plus its outputs.  The budget is a fraction of the
-  free HBM after keys and pools.  Ring degrees do not block each other; within
-  one degree, admission is in arrival order;
-- poll the lanes' completion events and release lanes and bytes.
-So requests that arrive while others run are admitted as lanes and memory
-free up, and their kernels overlap on the device.  Latency = completion -
-arrival; the run reports p50 / p99 latency and throughput.
+Lanes: each ring degree has `lanes` execution lanes.  A lane is a library
+context of its own, bound to its own HIP stream; the lanes of a ring degree
+share one key set (a key set is valid for every context of its parameter
+set).  The loop runs on the host:
+- move the requests whose arrival time has passed into their ring's queue;
+- admit: for each ring degree, while a lane is free, the oldest queued request
+  leads the next launch.  An inference leader takes along the queued
+  inferences of the same (N, c) in arrival order, up to `merge_blocks` blocks
+  in all: they share the served model, so their blocks are staged side by
+  side and their margins are one block-batched call.  A gradient step runs
+  alone (its plan, mask and sums are the request's own).  The launch is
+  admitted when its bytes fit the budget next to the launches in flight
+  (a merged launch sheds its last members until it fits);
+- poll the lanes' completion events; on completion the launch's staging,
+  outputs and workspace go back to the allocator and its bytes to the budget.
+A launch's bytes are what it really allocates: its library workspace
+(he_lr_step_bytes / he_lr_margins_bytes, drawn through the context's
+allocator at the call and given back by he_ctx_trim on completion), its
+staged blocks and its outputs.  The budget is a fraction of the device memory
+left after keys, pools and lanes.  Latency = completion - arrival; the run
+reports p50 / p99 latency, throughput and the launches' sizes.
+
+Gradient steps take the feature-major packing where the plan allows it (one
+mask and replication per step instead of per block), else the row-major one.
 
 Usage: python -m paper_2006_10091_amd.serve [--requests 2000] [--rate 200]
-       [--lanes 2] [--budget-frac 0.8]
+       [--lanes 4] [--merge-blocks 256] [--budget-frac 0.8]
 """
 import argparse
 import collections
+import itertools
 import json
 import math
 import sys
@@ -42,6 +52,8 @@ CHAIN = dict(n_q=8, n_special=2, alpha=2, log_delta=40)  # one step or one infer
 LOG_NS = (15, 16)
 N_RANGE = (512, 16384)
 D_RANGE = (16, 512)
+COEF = [0.5, -0.1501204134, 0.0, 0.0015930174]  # the step's loss polynomial
+MERGE_BLOCKS = 256
 
 Request = collections.namedtuple("Request", "rid arrival kind log_n n d c r nb")
 
@@ -68,18 +80,35 @@ def percentile(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if xs else float("nan")
 
 
-def run_loop(requests, backend, lanes_per_n, budget, clock=time.perf_counter, idle=2e-4):
+def take_batch(queue, merge_blocks):
+    """The launch the queue's oldest request leads: itself, and for an
+    inference the later queued inferences of the same feature width in
+    arrival order while the blocks stay within merge_blocks."""
+    head = queue[0]
+    batch = [head]
+    if merge_blocks and head.kind == "infer":
+        total = head.nb
+        for q in itertools.islice(queue, 1, None):
+            if q.kind == "infer" and q.c == head.c and total + q.nb <= merge_blocks:
+                batch.append(q)
+                total += q.nb
+    return batch
+
+
+def run_loop(requests, backend, lanes_per_n, budget, merge_blocks=0, clock=time.perf_counter, idle=2e-4):
     """The continuous-batching loop over a backend with
-    bytes(req) / launch(lane, req) -> handle / done(handle) -> bool /
-    finish(handle, req).  Returns per-request (admit, complete) times
-    relative to the run's start, and the peak bytes in flight."""
+    bytes(batch) / launch(lane, batch) -> handle / done(handle) -> bool /
+    finish(handle, batch).  Returns per-request (admit, complete) times
+    relative to the run's start, the peak bytes in flight and the launches
+    (lists of request ids)."""
     pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
     queues = {k: collections.deque() for k in lanes_per_n}
     free = {k: list(range(v)) for k, v in lanes_per_n.items()}
-    running = []  # (lane key, lane index, handle, request, bytes)
+    running = []  # (lane key, lane index, handle, batch, bytes)
     in_flight = 0
     peak = 0
     times = {}
+    launches = []
     t0 = clock()
     total = len(requests)
     while len(times) < total or running:
@@ -90,26 +119,35 @@ def run_loop(requests, backend, lanes_per_n, budget, clock=time.perf_counter, id
         progressed = False
         for k, qu in queues.items():
             while qu and free[k]:
-                q = qu[0]
-                b = backend.bytes(q)
+                batch = take_batch(qu, merge_blocks)
+                b = backend.bytes(batch)
+                while len(batch) > 1 and in_flight + b > budget:
+                    batch.pop()
+                    b = backend.bytes(batch)
                 if b > budget:
-                    raise ValueError("request %d needs %d bytes, over the whole budget %d" % (q.rid, b, budget))
+                    raise ValueError("request %d needs %d bytes, over the whole budget %d" % (batch[0].rid, b, budget))
                 if in_flight + b > budget:
                     break  # waits for memory; the other ring degree is not blocked
-                qu.popleft()
+                for q in batch:
+                    qu.remove(q)
                 lane = free[k].pop()
-                h = backend.launch((k, lane), q)
-                running.append((k, lane, h, q, b))
+                h = backend.launch((k, lane), batch)
+                running.append((k, lane, h, batch, b))
+                launches.append([q.rid for q in batch])
                 in_flight += b
                 peak = max(peak, in_flight)
-                times[q.rid] = [clock() - t0, None]
+                t = clock() - t0
+                for q in batch:
+                    times[q.rid] = [t, None]
                 progressed = True
         still = []
         for item in running:
-            k, lane, h, q, b = item
+            k, lane, h, batch, b = item
             if backend.done(h):
-                times[q.rid][1] = clock() - t0
-                backend.finish(h, q)
+                t = clock() - t0
+                for q in batch:
+                    times[q.rid][1] = t
+                backend.finish(h, batch)
                 free[k].append(lane)
                 in_flight -= b
                 progressed = True
@@ -123,10 +161,10 @@ def run_loop(requests, backend, lanes_per_n, budget, clock=time.perf_counter, id
                     time.sleep(min(wait, 0.01))
             else:
                 time.sleep(idle)
-    return times, peak
+    return times, peak, launches
 
 
-def summarise(requests, times):
+def summarise(requests, times, launches=None):
     lat = [times[q.rid][1] - q.arrival for q in requests]
     qwait = [times[q.rid][0] - q.arrival for q in requests]
     span = max(t[1] for t in times.values()) - min(q.arrival for q in requests)
@@ -138,11 +176,26 @@ def summarise(requests, times):
         lk = [times[q.rid][1] - q.arrival for q in requests if q.kind == kind]
         out[kind + "_p50_ms"] = percentile(lk, 50) * 1e3
         out[kind + "_p99_ms"] = percentile(lk, 99) * 1e3
+    if launches is not None:
+        out["launches"] = len(launches)
+        out["requests_per_launch"] = len(requests) / max(1, len(launches))
+        out["max_requests_per_launch"] = max((len(x) for x in launches), default=0)
     return out
 
 
+def step_layout(q, primes):
+    """Feature-major where the plan accepts the request's 1/n, else row-major."""
+    L = CHAIN["n_q"] - 1
+    d = float(2 ** CHAIN["log_delta"])
+    try:
+        H.plan_lr_step(primes, CHAIN["n_q"], L, d, d, COEF, 1.0 / q.n, 0.0, H.LAYOUT_FEATURES)
+        return H.LAYOUT_FEATURES
+    except H.HEError:
+        return H.LAYOUT_ROWS
+
+
 class GpuBackend:
-    """Lanes, pools and outputs on the GPU."""
+    """Lanes, key sets, pools and models on the GPU."""
 
     def __init__(self, requests, lanes, mode=1, keep_results=False, seed=6006, distinct=8):
         import torch
@@ -150,105 +203,174 @@ class GpuBackend:
         self.mode, self.keep = mode, keep_results
         self.results = {}
         self.lanes = {}
-        need = collections.defaultdict(int)  # (log_n, c) -> max blocks
-        maxnb = collections.defaultdict(int)  # log_n -> max blocks
+        self.keys = {}
+        L = self.L = CHAIN["n_q"] - 1
+        chain = (CHAIN["n_q"], CHAIN["n_special"], CHAIN["alpha"], CHAIN["log_delta"])
+        primes = {log_n: H.params_primes(log_n, *chain) for log_n in {q.log_n for q in requests}}
+        self.layout = {q.rid: step_layout(q, primes[q.log_n]) for q in requests if q.kind == "grad"}
+        need = collections.defaultdict(int)  # (log_n, c, layout) -> most blocks of a request
         steps = collections.defaultdict(set)
         for q in requests:
-            need[(q.log_n, q.c)] = max(need[(q.log_n, q.c)], q.nb)
-            maxnb[q.log_n] = max(maxnb[q.log_n], q.nb)
-            steps[q.log_n] |= set(H.rotation_steps(q.c, q.r))
-        L = CHAIN["n_q"] - 1
-        for log_n in sorted(maxnb):
+            lay = self.layout.get(q.rid, H.LAYOUT_ROWS)
+            need[(q.log_n, q.c, lay)] = max(need[(q.log_n, q.c, lay)], q.nb)
+            steps[q.log_n] |= set(H.rotation_steps(q.c, q.r, lay))
+        for log_n in sorted(primes):
             for j in range(lanes):
                 stream = torch.cuda.Stream()
-                ctx = H.Context(log_n, CHAIN["n_q"], CHAIN["n_special"], CHAIN["alpha"], CHAIN["log_delta"],
-                                stream=stream.cuda_stream)
-                keys = ctx.keygen(2004 + log_n, sorted(steps[log_n]))
-                outs = dict(W=ctx.ct_empty(L - 4), G=ctx.ct_empty(L - 4), M=ctx.ct_block(maxnb[log_n], L - 1))
-                self.lanes[(log_n, j)] = dict(ctx=ctx, stream=stream, keys=keys, outs=outs)
-        # data pools: `distinct` encoded blocks per (N, c), encrypted into every pool slot
+                ctx = H.Context(log_n, *chain, stream=stream.cuda_stream)
+                self.lanes[(log_n, j)] = dict(ctx=ctx, stream=stream)
+            # one key set per ring degree, shared by its lanes
+            self.keys[log_n] = self.lanes[(log_n, 0)]["ctx"].keygen(2004 + log_n, sorted(steps[log_n]))
+        # data pools: `distinct` plaintext blocks per (N, c, layout), encrypted into
+        # every pool slot; one served model W per (N, c, layout)
         self.pools = {}
         g = synth.rng(seed)
-        for (log_n, c), nb in sorted(need.items()):
+        for (log_n, c, lay), nb in sorted(need.items()):
             ctx = self.lanes[(log_n, 0)]["ctx"]
-            keys = self.lanes[(log_n, 0)]["keys"]
+            keys = self.keys[log_n]
             S = ctx.S
             r = S // c
             pts = []
             for _ in range(min(distinct, nb)):
                 X = g.uniform(0.0, 1.0, size=(r, c))
                 y = np.where(g.uniform(size=r) < 0.5, 1.0, -1.0)
-                pts.append(ctx.pt_load(ctx.encode((y[:, None] * X).reshape(S), ctx.delta), L, ctx.delta))
+                Zp = y[:, None] * X
+                Zp = Zp.T if lay == H.LAYOUT_FEATURES else Zp  # slot j r + i, else i c + j
+                pts.append(ctx.pt_load(ctx.encode(Zp.reshape(S), ctx.delta), L, ctx.delta))
             Z = ctx.ct_block(nb, L)
             for i in range(nb):
-                ctx.encrypt(pts[i % len(pts)], keys, seed, (c << 16) + i, out=Z[i])
+                ctx.encrypt(pts[i % len(pts)], keys, seed, (c << 17) + (lay << 16) + i, out=Z[i])
             w = g.uniform(-0.05, 0.05, size=c)
-            W = ctx.encrypt(ctx.pt_load(ctx.encode(H.pack_weights(w, S, c), ctx.delta), L, ctx.delta), keys, seed,
-                            (c << 16) + 0xFFFF)
-            pl = ctx.plan_lr_step(L, ctx.delta, ctx.delta, [0.5, -0.15, 0.0, 0.0016], 1.0 / 512)
-            mask = ctx.pt_load(ctx.encode(H.column0_mask(S, c), pl["s_mask"]), L - 1, pl["s_mask"])
-            self.pools[(log_n, c)] = dict(Z=Z, W=W, mask=mask)
+            W = ctx.encrypt(ctx.pt_load(ctx.encode(H.pack_weights(w, S, c, lay), ctx.delta), L, ctx.delta), keys,
+                            seed, (c << 17) + (lay << 16) + 0xFFFF)
+            self.pools[(log_n, c, lay)] = dict(Z=Z, W=W, masks={})
+        # step masks: row-major, one per pool (its scale does not depend on n);
+        # feature-major, one per shard size (its scale carries eta / n)
+        for q in requests:
+            if q.kind != "grad":
+                continue
+            lay = self.layout[q.rid]
+            pool = self.pools[(q.log_n, q.c, lay)]
+            key = q.n if lay == H.LAYOUT_FEATURES else 0
+            if key not in pool["masks"]:
+                ctx = self.lanes[(q.log_n, 0)]["ctx"]
+                pl = ctx.plan_lr_step(L, ctx.delta, ctx.delta, COEF, 1.0 / q.n, layout=lay)
+                ml = H.mask_level(L, lay)
+                pool["masks"][key] = ctx.pt_load(ctx.encode(H.step_mask(ctx.S, q.c, lay), pl["s_mask"]), ml,
+                                                 pl["s_mask"])
         torch.cuda.synchronize()
-        self.coef = [0.5, -0.1501204134, 0.0, 0.0015930174]
 
-    def bytes(self, q):
+    def ct_bytes(self, log_n, level):
+        return 2 * (level + 1) * (1 << log_n) * 8
+
+    def bytes(self, batch):
+        """What the launch allocates: library workspace, staged blocks, outputs."""
+        q = batch[0]
         ctx = self.lanes[(q.log_n, 0)]["ctx"]
-        L = CHAIN["n_q"] - 1
+        L = self.L
         if q.kind == "grad":
-            return ctx.step_bytes(L, q.nb, H.LAYOUT_ROWS, self.mode) + 2 * (2 * (L - 3) * ctx.N * 8)
-        return ctx.margins_bytes(L, q.nb, self.mode) + q.nb * 2 * L * ctx.N * 8
+            return ctx.step_bytes(L, q.nb, self.layout[q.rid], self.mode) + 2 * self.ct_bytes(q.log_n, L - 4)
+        nb = sum(x.nb for x in batch)
+        return ctx.margins_bytes(L, nb, self.mode) + nb * (self.ct_bytes(q.log_n, L) + self.ct_bytes(q.log_n, L - 1))
 
-    def launch(self, lane_key, q):
+    def launch(self, lane_key, batch):
+        torch = self.torch
         lane = self.lanes[lane_key]
-        ctx, outs = lane["ctx"], lane["outs"]
-        pool = self.pools[(q.log_n, q.c)]
-        Z = pool["Z"][: q.nb]
+        ctx, stream = lane["ctx"], lane["stream"]
+        keys = self.keys[lane_key[0]]
+        q = batch[0]
+        L = self.L
+        held = {}
         if q.kind == "grad":
-            ctx.lr_grad_step(Z, pool["W"], pool["mask"], self.coef, 1.0 / q.n, q.c, q.r, lane["keys"],
-                             mode=self.mode, W_out=outs["W"], G_out=outs["G"])
+            lay = self.layout[q.rid]
+            pool = self.pools[(q.log_n, q.c, lay)]
+            mask = pool["masks"][q.n if lay == H.LAYOUT_FEATURES else 0]
+            held["W"], held["G"] = ctx.ct_empty(L - 4), ctx.ct_empty(L - 4)
+            ctx.lr_grad_step(pool["Z"][: q.nb], pool["W"], mask, COEF, 1.0 / q.n, q.c, q.r, keys, mode=self.mode,
+                             W_out=held["W"], G_out=held["G"], layout=lay)
         else:
-            ctx.lr_margins(Z, pool["W"], q.c, q.r, lane["keys"], mode=self.mode, out=outs["M"][: q.nb])
-        ev = self.torch.cuda.Event()
-        ev.record(lane["stream"])
-        return (lane_key, ev)
+            pool = self.pools[(q.log_n, q.c, H.LAYOUT_ROWS)]
+            nb = sum(x.nb for x in batch)
+            # stage the requests' blocks side by side (a request's own upload
+            # would land here), then one block-batched margins call
+            Z = ctx.ct_block(nb, L)
+            per = 2 * (L + 1) * ctx.N
+            src = pool["Z"][0].tensor
+            with torch.cuda.stream(stream):
+                off = 0
+                for x in batch:
+                    Z[0].tensor[off * per:(off + x.nb) * per].copy_(src[: x.nb * per])
+                    off += x.nb
+            for z in Z:
+                z.scale = pool["Z"][0].scale
+            held["Z"], held["M"] = Z, ctx.ct_block(nb, L - 1)
+            ctx.lr_margins(Z, pool["W"], q.c, q.r, keys, mode=self.mode, out=held["M"])
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        return (lane_key, ev, held)
 
     def done(self, h):
         return h[1].query()
 
-    def finish(self, h, q):
-        if not self.keep:
-            return
+    def finish(self, h, batch):
         lane = self.lanes[h[0]]
-        ctx, outs = lane["ctx"], lane["outs"]
-        if q.kind == "grad":
-            self.results[q.rid] = (ctx.download(outs["W"]), ctx.download(outs["G"]))
-        else:
-            self.results[q.rid] = tuple(ctx.download(m) for m in outs["M"][: q.nb])
+        ctx, held = lane["ctx"], h[2]
+        if self.keep:
+            if batch[0].kind == "grad":
+                self.results[batch[0].rid] = (ctx.download(held["W"]), ctx.download(held["G"]))
+            else:
+                off = 0
+                for x in batch:
+                    self.results[x.rid] = tuple(ctx.download(m) for m in held["M"][off:off + x.nb])
+                    off += x.nb
+        held.clear()  # staging and outputs back to the allocator
+        ctx.trim()  # and the workspace (the launch has completed)
 
     def free_bytes_after_setup(self):
-        free, _ = self.torch.cuda.mem_get_info()
-        return free
+        """Device memory free now, counting the allocator's cached blocks."""
+        torch = self.torch
+        free, _ = torch.cuda.mem_get_info()
+        return free + torch.cuda.memory_reserved() - torch.cuda.memory_allocated()
 
 
-def serve(requests, lanes=2, mode=1, budget_frac=0.8, budget=None, keep_results=False, warm=True):
-    """Set up the GPU backend for `requests`, warm each lane once on its
-    largest request of each kind (workspace growth), run the loop."""
+def serve(requests, lanes=4, mode=1, budget_frac=0.8, budget=None, keep_results=False, warm=True,
+          merge_blocks=MERGE_BLOCKS):
+    """Set up the GPU backend for `requests`, warm up (first-call costs: the
+    smallest request of every ring, kind, width and packing once, and one
+    request on every lane), run the loop."""
     be = GpuBackend(requests, lanes, mode=mode, keep_results=keep_results)
     if warm:
+        keep, be.keep = be.keep, False
+        first = {}
+        for q in sorted(requests, key=lambda q: q.nb):
+            first.setdefault((q.log_n, q.kind, q.c, be.layout.get(q.rid)), q)
+        runs = [((q.log_n, 0), q) for q in first.values()]
         for log_n in {q.log_n for q in requests}:
-            for kind in ("grad", "infer"):
-                qs = [q for q in requests if q.log_n == log_n and q.kind == kind]
-                if qs:
-                    big = max(qs, key=lambda q: q.nb)
-                    for j in range(lanes):
-                        be.launch((log_n, j), big)
+            small = min((q for q in requests if q.log_n == log_n), key=lambda q: q.nb)
+            runs += [((log_n, j), small) for j in range(1, lanes)]
+        for lane, q in runs:
+            h = be.launch(lane, [q])
+            h[1].synchronize()
+            be.finish(h, [q])
+        be.keep = keep
         be.torch.cuda.synchronize()
     if budget is None:
         budget = int(budget_frac * be.free_bytes_after_setup())
     lanes_per_n = {k: lanes for k in sorted({q.log_n for q in requests})}
-    times, peak = run_loop(requests, be, lanes_per_n, budget)
-    stats = summarise(requests, times)
-    stats.update(lanes_per_ring=lanes, mode=mode, budget_bytes=budget, peak_bytes_in_flight=peak)
+    base = be.torch.cuda.memory_allocated()
+    be.torch.cuda.reset_peak_memory_stats()
+    m0 = be.torch.cuda.memory_stats()
+    times, peak, launches = run_loop(requests, be, lanes_per_n, budget, merge_blocks=merge_blocks)
+    m1 = be.torch.cuda.memory_stats()
+    stats = summarise(requests, times, launches)
+    # the allocator's own work during the loop: device allocations and frees
+    # (each free synchronises the device) and retries after running out
+    for k in ("num_device_alloc", "num_device_free", "num_alloc_retries"):
+        stats["allocator_" + k] = m1.get(k, 0) - m0.get(k, 0)
+    stats.update(lanes_per_ring=lanes, mode=mode, budget_bytes=budget, peak_bytes_in_flight=peak,
+                 peak_bytes_allocated=be.torch.cuda.max_memory_allocated() - base, merge_blocks=merge_blocks,
+                 feature_major_steps=sum(1 for v in be.layout.values() if v == H.LAYOUT_FEATURES),
+                 steps=len(be.layout))
     return stats, be, times
 
 
@@ -256,12 +378,14 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate", type=float, default=200.0)
-    ap.add_argument("--lanes", type=int, default=2)
+    ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--mode", type=int, default=1)
+    ap.add_argument("--merge-blocks", type=int, default=MERGE_BLOCKS)
     ap.add_argument("--budget-frac", type=float, default=0.8)
     args = ap.parse_args(argv)
     reqs = make_requests(args.requests, args.rate)
-    stats, _, _ = serve(reqs, lanes=args.lanes, mode=args.mode, budget_frac=args.budget_frac)
+    stats, _, _ = serve(reqs, lanes=args.lanes, mode=args.mode, budget_frac=args.budget_frac,
+                        merge_blocks=args.merge_blocks)
     stats["rate_req_per_s"] = args.rate
     print(json.dumps(stats), flush=True)
     return stats
