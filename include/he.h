@@ -507,6 +507,49 @@ he_status he_batch_mul_rotate(he_ctx *ctx, const he_ct *x, const he_ct *y, const
                               const he_keys *keys, int mode, he_ct *out);
 
 /*
+ * A batch of independent operations described one by one (Sec. 3's
+ * homomorphic operations: multiplication with relinearisation, the rounding
+ * "scaling" step, rotation, addition), of any mix of kinds and levels:
+ *   HE_OP_MUL         out = RS(relin(x (x) y))            level(x) - 1
+ *   HE_OP_MUL_ROTATE  out = Rot(RS(relin(x (x) y)), steps) level(x) - 1
+ *   HE_OP_ROTATE      out = Rot(x, steps)                   level(x)
+ *   HE_OP_RESCALE     out = RS(x)                           level(x) - 1
+ *   HE_OP_ADD         out = x + y                           level(x)
+ * Rot is a left rotation of the slots by `steps` (Galois element 5^steps).
+ * Scales: MUL* x.scale * y.scale / q_level, RESCALE x.scale / q_level, else
+ * x.scale; every op's out.level and out.scale are written on return.
+ * y is read by MUL, MUL_ROTATE and ADD (same level as x; ADD: same scale) and
+ * ignored otherwise.  out.data: caller memory of a ciphertext at the output
+ * level; no output may overlap another output or any input of the batch (the
+ * operations are independent: none reads another's result).
+ * How it runs: a device-side table of the operations' operands drives the
+ * elementwise phases -- the tensor products of every MUL / MUL_ROTATE, the
+ * staging of ROTATE / RESCALE inputs, every ADD and the copy of every result
+ * to its out -- each one launch over all operations of all levels; the key
+ * switches and rescalings run per level, all operations of one level
+ * together (rotations up to 32 per launch, each with its own key).
+ * mode 0: one operation per launch group; 1: grouped; 2: grouped and
+ * captured into a HIP graph on first use for these operations and buffers,
+ * replayed afterwards (the table is uploaded before each replay).  All modes
+ * give bit-identical outputs, equal to the single-operation calls.
+ * Errors, before any launch: HE_EINVAL (bad op code or pointers, overlapping
+ * outputs), HE_ELEVEL (level below what the op consumes, x / y levels
+ * differ), HE_ESCALE (ADD of different scales), HE_EKEY (a rotation key or
+ * the relinearisation key's parameter set).
+ */
+enum { HE_OP_MUL = 1, HE_OP_MUL_ROTATE = 2, HE_OP_ROTATE = 3, HE_OP_RESCALE = 4, HE_OP_ADD = 5 };
+typedef struct {
+    int32_t op;     /* HE_OP_* */
+    int32_t steps;  /* rotation steps (MUL_ROTATE, ROTATE) */
+    he_ct x, y;     /* operands (device) */
+    he_ct out;      /* result (device, caller memory); level and scale set on return */
+} he_op;
+he_status he_batch_submit(he_ctx *ctx, he_op *ops, int n, const he_keys *keys, int mode);
+/* Device workspace (bytes) he_batch_submit takes for these operations in
+ * `mode` (admission control); 0 for invalid arguments. */
+size_t he_batch_submit_bytes(const he_ctx *ctx, const he_op *ops, int n, int mode);
+
+/*
  * Hoisted sum of rotations (Sec. 3 rotations; the feature-major giant steps of
  * he_lr_grad_step): out[i] = x[i] + sum_s Rot(x[i], steps[s]) for n
  * ciphertexts, as one key switch each: x's a-part is raised to Q_l u P once,

@@ -8,7 +8,10 @@ as inputs.  One context (and key set) per N, each with 21 ciphertext primes
 and 4 special primes (scale 2^40, 4 primes per digit).  Each context's share
 runs through he_batch_mul_rotate: entries of one level together, up to 32 per
 launch, each with its own rotation key; in the graph form one captured graph
-per context replays the whole share.
+per context replays the whole share.  The same share also runs as a list of
+operation descriptors through he_batch_submit (HE_OP_MUL_ROTATE entries):
+its tensor products and result copies are one table-driven launch each over
+all levels.
 
 Usage: python -m paper_2006_10091_amd.batch_ops [--ops 256] [--reps 3]
 """
@@ -65,6 +68,15 @@ class Batch:
             ctx.batch_mul_rotate(self.x[log_n], self.y[log_n], steps, self.keys[log_n], mode=mode,
                                  outs=self.out[log_n])
 
+    def run_submit(self, mode):
+        """The same operations as descriptors through he_batch_submit."""
+        if not hasattr(self, "_desc"):
+            self._desc = {log_n: [(H.OP_MUL_ROTATE, self.ops[i][2], x, y, o)
+                                  for i, x, y, o in zip(self.idx[log_n], self.x[log_n], self.y[log_n], self.out[log_n])]
+                          for log_n in self.ctx}
+        for log_n, ctx in self.ctx.items():
+            ctx.batch_submit(self._desc[log_n], self.keys[log_n], mode=mode)
+
     def outputs(self):
         res = [None] * len(self.ops)
         for log_n, ctx in self.ctx.items():
@@ -83,8 +95,10 @@ def main(argv=None):
     b = Batch(ops)
     ref = None
     result = {"ops": args.ops, "per_n": {str(1 << k): sum(1 for o in ops if o[0] == k) for k in LOG_NS}}
-    for mode, name in ((0, "plain"), (1, "batched"), (2, "graph")):
-        b.run(mode)  # first run: workspace growth, graph capture
+    forms = ((0, "plain", b.run), (1, "batched", b.run), (2, "graph", b.run), (1, "submit", b.run_submit),
+             (2, "submit_graph", b.run_submit))
+    for mode, name, run in forms:
+        run(mode)  # first run: workspace growth, graph capture
         torch.cuda.synchronize()
         out = b.outputs()
         if ref is None:
@@ -92,7 +106,7 @@ def main(argv=None):
         assert all(np.array_equal(a, r) for a, r in zip(out, ref)), name
         t0 = time.perf_counter()
         for _ in range(args.reps):
-            b.run(mode)
+            run(mode)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.reps
         result[name + "_ms_per_batch"] = dt * 1e3

@@ -1237,6 +1237,11 @@ he_status he_ctx_destroy(he_ctx *c)
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    if (c->sub_ev) {
+        (void)hipEventSynchronize(c->sub_ev);
+        (void)hipEventDestroy(c->sub_ev);
+    }
+    if (c->sub_host) (void)hipHostFree(c->sub_host);
     delete c;
     return HE_OK;
 }
@@ -2143,6 +2148,297 @@ he_status he_batch_mul_rotate(he_ctx *c, const he_ct *x, const he_ct *y, const i
     for (int i = 0; i < n; ++i) {
         out[i].level = x[i].level - 1;
         out[i].scale = x[i].scale * y[i].scale / (double)c->q[x[i].level];
+    }
+    return last_error();
+}
+
+// ------------------------------------------------------------------ descriptor batches (he_batch_submit)
+// The plan of one submission: operations grouped by kind and input level, the
+// staging regions of each group (uniform strides, so the batched key
+// switches and rescalings take them) and the device operand tables of the
+// elementwise phases.
+struct SubmitPlan {
+    int chunk = 1;
+    std::vector<u64> gal;                   // per op: Galois element of its rotation (1: none)
+    std::map<int, std::vector<int>> mul;    // x level -> MUL_ROTATE ops, then MUL ops
+    std::map<int, int> mul_rot;             // x level -> how many MUL_ROTATE ops lead the group
+    std::map<int, std::vector<int>> rot;    // x level -> ROTATE ops with a key switch
+    std::map<int, std::vector<int>> resc;   // x level -> RESCALE ops
+    std::vector<int> add, copy;             // ADD ops; ROTATE ops by a multiple of the slot count
+    size_t table_u64 = 0, staging_u64 = 0, scratch_u64 = 0;
+};
+
+static int out_level(const he_op &o)
+{
+    return (o.op == HE_OP_MUL || o.op == HE_OP_MUL_ROTATE || o.op == HE_OP_RESCALE) ? o.x.level - 1 : o.x.level;
+}
+
+// k = NULL: sizing only (the rotation keys are not checked)
+static he_status submit_plan(const he_ctx *c, const he_op *ops, int n, const he_keys *k, int mode, SubmitPlan &pl)
+{
+    if (!c || !ops || n < 1 || mode < 0 || mode > 2) return HE_EINVAL;
+    pl.chunk = mode == 0 ? 1 : 1 << 30;
+    pl.gal.assign(n, 1);
+    struct Span {
+        uintptr_t lo, hi;
+        bool out;
+    };
+    std::vector<Span> spans;
+    const size_t N = c->N;
+    for (int i = 0; i < n; ++i) {
+        const he_op &o = ops[i];
+        if (o.op < HE_OP_MUL || o.op > HE_OP_ADD || !ct_ok(c, &o.x) || !o.out.data) return HE_EINVAL;
+        const int l = o.x.level;
+        const bool two = o.op == HE_OP_MUL || o.op == HE_OP_MUL_ROTATE || o.op == HE_OP_ADD;
+        if (two && !ct_ok(c, &o.y)) return HE_EINVAL;
+        if (two && o.y.level != l) return HE_ELEVEL;
+        if (o.op == HE_OP_ADD && o.x.scale != o.y.scale) return HE_ESCALE;
+        if (out_level(o) < 0) return HE_ELEVEL;
+        if (o.op == HE_OP_MUL_ROTATE || o.op == HE_OP_ROTATE) {
+            pl.gal[i] = galois_of(c, o.steps);
+            if (k && pl.gal[i] != 1 && !find_rot_key(k, pl.gal[i])) return HE_EKEY;
+        }
+        const size_t in_b = (size_t)2 * (l + 1) * N * 8, out_b = (size_t)2 * (out_level(o) + 1) * N * 8;
+        spans.push_back({(uintptr_t)o.x.data, (uintptr_t)o.x.data + in_b, false});
+        if (two) spans.push_back({(uintptr_t)o.y.data, (uintptr_t)o.y.data + in_b, false});
+        spans.push_back({(uintptr_t)o.out.data, (uintptr_t)o.out.data + out_b, true});
+        if (o.op == HE_OP_MUL || o.op == HE_OP_MUL_ROTATE) pl.mul_rot.emplace(l, 0);
+        switch (o.op) {
+        case HE_OP_MUL_ROTATE:
+            if (pl.gal[i] != 1) {
+                pl.mul[l].insert(pl.mul[l].begin() + pl.mul_rot[l], i);
+                ++pl.mul_rot[l];
+                break;
+            }
+            // a rotation by a multiple of the slot count is the product alone
+            pl.mul[l].push_back(i);
+            break;
+        case HE_OP_MUL: pl.mul[l].push_back(i); break;
+        case HE_OP_ROTATE:
+            if (pl.gal[i] != 1) pl.rot[l].push_back(i);
+            else pl.copy.push_back(i);
+            break;
+        case HE_OP_RESCALE: pl.resc[l].push_back(i); break;
+        default: pl.add.push_back(i); break;
+        }
+    }
+    // no output overlaps another output or an input (inputs may be shared)
+    std::sort(spans.begin(), spans.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
+    uintptr_t all_end = 0, out_end = 0;
+    for (const Span &sp : spans) {
+        if (sp.out ? sp.lo < all_end : sp.lo < out_end) return HE_EINVAL;
+        all_end = std::max(all_end, sp.hi);
+        if (sp.out) out_end = std::max(out_end, sp.hi);
+    }
+    // sizes: operand tables, staging, and the largest group's scratch
+    size_t ntab = pl.add.size() + pl.copy.size();
+    size_t stg = 0, scr = 0;
+    for (const auto &g : pl.mul) {
+        const int l = g.first, B = (int)g.second.size(), Br = pl.mul_rot[l];
+        ntab += 2 * B;  // tensor, copy out
+        stg += al((size_t)B * 3 * (l + 1) * N) + al((size_t)B * 2 * l * N) + al((size_t)Br * 2 * l * N);
+        scr = std::max(scr, relin_rescale_scratch(c, l, std::min(B, pl.chunk)));
+        if (Br) scr = std::max(scr, rotate_scratch(c, l - 1, std::min({Br, pl.chunk, hek::HE_MAXMULTI})));
+    }
+    for (const auto &g : pl.rot) {
+        const int l = g.first, B = (int)g.second.size();
+        ntab += 2 * B;  // stage in, copy out
+        stg += 2 * al((size_t)B * 2 * (l + 1) * N);
+        scr = std::max(scr, rotate_scratch(c, l, std::min({B, pl.chunk, hek::HE_MAXMULTI})));
+    }
+    for (const auto &g : pl.resc) {
+        const int l = g.first, B = (int)g.second.size();
+        ntab += 2 * B;
+        stg += al((size_t)B * 2 * (l + 1) * N) + al((size_t)B * 2 * l * N);
+        scr = std::max(scr, rescale_scratch(c, l, std::min(B, pl.chunk)));
+    }
+    pl.table_u64 = al(ntab * sizeof(hek::OpDesc) / 8);
+    pl.staging_u64 = stg;
+    pl.scratch_u64 = scr;
+    return HE_OK;
+}
+
+static size_t submit_bytes(const SubmitPlan &pl) { return (pl.table_u64 + pl.staging_u64 + pl.scratch_u64) * 8 + 4096; }
+
+// The staging regions and operand tables of a plan laid out in the workspace
+// (the tables first, at its start, then the staging, then the scratch arena).
+struct SubmitLayout {
+    std::vector<hek::OpDesc> tab;  // host copy: tensor | stage in | add | copy out
+    int n_tensor = 0, n_in = 0, n_add = 0, n_out = 0, max_limbs = 0;
+    std::map<int, u64 *> T3, R, RO, Rin, Rout, Sin, Sout;
+};
+
+static he_status submit_layout(he_ctx *c, const he_op *ops, const SubmitPlan &pl, Arena &ar, SubmitLayout &ly)
+{
+    const long long N = c->N;
+    ar.off = pl.table_u64 * 8;
+    for (const auto &g : pl.mul) {
+        const int l = g.first, B = (int)g.second.size(), Br = pl.mul_rot.at(l);
+        ly.T3[l] = ar.take((size_t)B * 3 * (l + 1) * N);
+        ly.R[l] = ar.take((size_t)B * 2 * l * N);
+        ly.RO[l] = Br ? ar.take((size_t)Br * 2 * l * N) : nullptr;
+        if (!ly.T3[l] || !ly.R[l] || (Br && !ly.RO[l])) return HE_ENOMEM;
+    }
+    for (const auto &g : pl.rot) {
+        const int l = g.first, B = (int)g.second.size();
+        ly.Rin[l] = ar.take((size_t)B * 2 * (l + 1) * N);
+        ly.Rout[l] = ar.take((size_t)B * 2 * (l + 1) * N);
+        if (!ly.Rin[l] || !ly.Rout[l]) return HE_ENOMEM;
+    }
+    for (const auto &g : pl.resc) {
+        const int l = g.first, B = (int)g.second.size();
+        ly.Sin[l] = ar.take((size_t)B * 2 * (l + 1) * N);
+        ly.Sout[l] = ar.take((size_t)B * 2 * l * N);
+        if (!ly.Sin[l] || !ly.Sout[l]) return HE_ENOMEM;
+    }
+    std::vector<hek::OpDesc> tensor, in, add, out;
+    auto lim = [&](int limbs) { ly.max_limbs = std::max(ly.max_limbs, limbs); return limbs; };
+    for (const auto &g : pl.mul) {
+        const int l = g.first, Br = pl.mul_rot.at(l);
+        for (size_t b = 0; b < g.second.size(); ++b) {
+            const he_op &o = ops[g.second[b]];
+            tensor.push_back({o.x.data, o.y.data, ly.T3[l] + b * 3 * (l + 1) * N, lim(l + 1), 0});
+            const u64 *res = (int)b < Br ? ly.RO[l] + b * 2 * l * N : ly.R[l] + b * 2 * l * N;
+            out.push_back({res, nullptr, o.out.data, lim(l), 0});
+        }
+    }
+    for (const auto &g : pl.rot) {
+        const int l = g.first;
+        for (size_t b = 0; b < g.second.size(); ++b) {
+            const he_op &o = ops[g.second[b]];
+            in.push_back({o.x.data, nullptr, ly.Rin[l] + b * 2 * (l + 1) * N, lim(l + 1), 0});
+            out.push_back({ly.Rout[l] + b * 2 * (l + 1) * N, nullptr, o.out.data, l + 1, 0});
+        }
+    }
+    for (const auto &g : pl.resc) {
+        const int l = g.first;
+        for (size_t b = 0; b < g.second.size(); ++b) {
+            const he_op &o = ops[g.second[b]];
+            in.push_back({o.x.data, nullptr, ly.Sin[l] + b * 2 * (l + 1) * N, lim(l + 1), 0});
+            out.push_back({ly.Sout[l] + b * 2 * l * N, nullptr, o.out.data, l, 0});
+        }
+    }
+    for (int i : pl.add) add.push_back({ops[i].x.data, ops[i].y.data, ops[i].out.data, lim(ops[i].x.level + 1), 0});
+    for (int i : pl.copy) out.push_back({ops[i].x.data, nullptr, ops[i].out.data, lim(ops[i].x.level + 1), 0});
+    ly.n_tensor = (int)tensor.size();
+    ly.n_in = (int)in.size();
+    ly.n_add = (int)add.size();
+    ly.n_out = (int)out.size();
+    ly.tab = tensor;
+    ly.tab.insert(ly.tab.end(), in.begin(), in.end());
+    ly.tab.insert(ly.tab.end(), add.begin(), add.end());
+    ly.tab.insert(ly.tab.end(), out.begin(), out.end());
+    return HE_OK;
+}
+
+static he_status submit_impl(he_ctx *c, const he_op *ops, const SubmitPlan &pl, const SubmitLayout &ly,
+                             const he_keys *k, size_t scratch_off)
+{
+    const long long N = c->N;
+    const hek::OpDesc *tab = (const hek::OpDesc *)c->ws;
+    // elementwise phases over every operation of every level: one launch each
+    hek::desc_ew(c, 6, tab, ly.n_tensor, ly.max_limbs);
+    hek::desc_ew(c, 4, tab + ly.n_tensor, ly.n_in, ly.max_limbs);
+    hek::desc_ew(c, 0, tab + ly.n_tensor + ly.n_in, ly.n_add, ly.max_limbs);
+    Arena ar = arena(c);
+    ar.off = scratch_off;
+    const int rchunk = std::min(pl.chunk, hek::HE_MAXMULTI);
+    // products: relinearise and rescale per level, then the MUL_ROTATE rotations
+    for (const auto &g : pl.mul) {
+        const int l = g.first, B = (int)g.second.size(), Br = pl.mul_rot.at(l);
+        const long long t3 = 3LL * (l + 1) * N, r2 = 2LL * l * N;
+        for (int s0 = 0; s0 < B; s0 += pl.chunk) {
+            const int b = std::min(pl.chunk, B - s0);
+            TRY(relin_rescale_apply(c, ar, l, b, ly.T3.at(l) + s0 * t3, t3, k->rlk, ly.R.at(l) + s0 * r2, r2));
+        }
+        for (int s0 = 0; s0 < Br; s0 += rchunk) {
+            const int b = std::min(rchunk, Br - s0);
+            hek::EntryGal eg;
+            hek::EntryKeys ek;
+            for (int j = 0; j < b; ++j) {
+                eg.g[j] = pl.gal[g.second[s0 + j]];
+                ek.k[j] = find_rot_key(k, eg.g[j]);
+            }
+            TRY(rotate_multi_apply(c, ar, l - 1, b, ly.R.at(l) + s0 * r2, r2, eg, ek, ly.RO.at(l) + s0 * r2, r2));
+        }
+    }
+    for (const auto &g : pl.rot) {
+        const int l = g.first, B = (int)g.second.size();
+        const long long c2 = 2LL * (l + 1) * N;
+        for (int s0 = 0; s0 < B; s0 += rchunk) {
+            const int b = std::min(rchunk, B - s0);
+            hek::EntryGal eg;
+            hek::EntryKeys ek;
+            for (int j = 0; j < b; ++j) {
+                eg.g[j] = pl.gal[g.second[s0 + j]];
+                ek.k[j] = find_rot_key(k, eg.g[j]);
+            }
+            TRY(rotate_multi_apply(c, ar, l, b, ly.Rin.at(l) + s0 * c2, c2, eg, ek, ly.Rout.at(l) + s0 * c2, c2));
+        }
+    }
+    for (const auto &g : pl.resc) {
+        const int l = g.first, B = (int)g.second.size();
+        const long long c2 = 2LL * (l + 1) * N, r2 = 2LL * l * N;
+        for (int s0 = 0; s0 < B; s0 += pl.chunk) {
+            const int b = std::min(pl.chunk, B - s0);
+            TRY(rescale_apply(c, ar, l, b, ly.Sin.at(l) + s0 * c2, c2, ly.Sout.at(l) + s0 * r2, r2));
+        }
+    }
+    // every result to its out: one launch
+    hek::desc_ew(c, 4, tab + ly.n_tensor + ly.n_in + ly.n_add, ly.n_out, ly.max_limbs);
+    return last_error();
+}
+
+size_t he_batch_submit_bytes(const he_ctx *c, const he_op *ops, int n, int mode)
+{
+    SubmitPlan pl;
+    return submit_plan(c, ops, n, nullptr, mode, pl) == HE_OK ? submit_bytes(pl) : 0;
+}
+
+he_status he_batch_submit(he_ctx *c, he_op *ops, int n, const he_keys *k, int mode)
+{
+    if (!c || !ops || n < 1 || !k) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
+    SubmitPlan pl;
+    TRY(submit_plan(c, ops, n, k, mode, pl));
+    TRY(ensure_ws(c, submit_bytes(pl)));
+    Arena ar = arena(c);
+    SubmitLayout ly;
+    TRY(submit_layout(c, ops, pl, ar, ly));
+    const size_t scratch_off = ar.off;
+    // the operand tables, uploaded before the work (and before a replay) from
+    // the context's pinned staging buffer, which the previous upload must have
+    // left first
+    const size_t tb = ly.tab.size() * sizeof(hek::OpDesc);
+    if (!c->sub_ev) HIPCHK(hipEventCreateWithFlags(&c->sub_ev, hipEventDisableTiming));
+    HIPCHK(hipEventSynchronize(c->sub_ev));
+    if (c->sub_host_bytes < tb) {
+        if (c->sub_host) (void)hipHostFree(c->sub_host);
+        c->sub_host = nullptr;
+        c->sub_host_bytes = 0;
+        HIPCHK(hipHostMalloc(&c->sub_host, tb, hipHostMallocDefault));
+        c->sub_host_bytes = tb;
+    }
+    std::memcpy(c->sub_host, ly.tab.data(), tb);
+    HIPCHK(hipMemcpyAsync(c->ws, c->sub_host, tb, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->sub_ev, c->stream));
+    if (mode == 2) {
+        std::ostringstream key;
+        key << "submit:" << n << ':' << k->gen << ':' << (const void *)k->sk << ':' << (const void *)c->ws;
+        for (int i = 0; i < n; ++i)
+            key << ':' << ops[i].op << ',' << pl.gal[i] << ',' << (const void *)ops[i].x.data << ','
+                << (const void *)ops[i].y.data << ',' << (const void *)ops[i].out.data << ',' << ops[i].x.level;
+        TRY(run_graph(c, key.str(), k->gen, [&] { return submit_impl(c, ops, pl, ly, k, scratch_off); }));
+    } else {
+        TRY(submit_impl(c, ops, pl, ly, k, scratch_off));
+    }
+    for (int i = 0; i < n; ++i) {
+        he_op &o = ops[i];
+        const int l = o.x.level;
+        o.out.level = out_level(o);
+        if (o.op == HE_OP_MUL || o.op == HE_OP_MUL_ROTATE) o.out.scale = o.x.scale * o.y.scale / (double)c->q[l];
+        else if (o.op == HE_OP_RESCALE) o.out.scale = o.x.scale / (double)c->q[l];
+        else o.out.scale = o.x.scale;
     }
     return last_error();
 }

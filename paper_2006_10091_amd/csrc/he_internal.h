@@ -96,6 +96,11 @@ struct he_ctx {
     bool capturing = false;
     hipStream_t gstream = nullptr;  // private stream of the captured step
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // he_batch_submit's operand-table upload: pinned host staging, and the
+    // event after its last copy (the buffer is rewritten only once it passed)
+    void *sub_host = nullptr;
+    size_t sub_host_bytes = 0;
+    hipEvent_t sub_ev = nullptr;
 };
 
 struct he_keys {
@@ -182,6 +187,17 @@ void ks_inner_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const
 // per-entry evaluation keys / Galois elements for a batch of up to HE_MAXMULTI
 // entries (passed by value as kernel arguments)
 constexpr int HE_MAXMULTI = 32;
+// one entry of a device-side operand table (he_batch_submit): x, y inputs and
+// o output of one ciphertext-sized elementwise operation over `limbs` limbs
+// (primes q_0 ..), component stride limbs * N on each side
+struct OpDesc {
+    const u64 *x, *y;
+    u64 *o;
+    int limbs, pad;
+};
+// op 0: o = x + y (two components); 4: o = x (two components); 6: the tensor
+// o[3] = (x0 y0, x0 y1 + x1 y0, x1 y1).  One launch over n table entries.
+void desc_ew(he_ctx *c, int op, const OpDesc *tab, int n, int max_limbs);
 struct EntryKeys {
     const u64 *k[HE_MAXMULTI];
 };

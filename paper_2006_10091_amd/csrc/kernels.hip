@@ -1220,6 +1220,41 @@ __global__ __launch_bounds__(256) void tensor_kernel(const u64 *__restrict__ x, 
     }
 }
 
+// Elementwise operations driven by a device-side operand table: workgroup
+// (x, limb, entry) reads entry blockIdx.z's pointers and limb count, so one
+// launch covers operations of any mix of levels (workgroups past an entry's
+// limbs return at once).  OP 0 add, 4 copy, 6 tensor (see OpDesc).
+template <int OP>
+__global__ __launch_bounds__(256) void desc_ew_kernel(const hek::OpDesc *__restrict__ tab,
+                                                      const PrimeInfo *__restrict__ pinfo, int logN)
+{
+    const hek::OpDesc d = tab[blockIdx.z];
+    const int i = blockIdx.y;
+    if (i >= d.limbs) return;
+    const PrimeInfo p = pinfo[i];
+    const long long li = (long long)i << logN, lc = (long long)d.limbs << logN;
+    const int N = 1 << logN;
+    const u64 *x0 = d.x + li, *x1 = x0 + lc;
+    u64 *o0 = d.o + li, *o1 = o0 + lc;
+    for (int t = blockIdx.x * 256 + threadIdx.x; t < N; t += gridDim.x * 256) {
+        if (OP == 4) {
+            o0[t] = x0[t];
+            o1[t] = x1[t];
+        } else {
+            const u64 *y0 = d.y + li, *y1 = y0 + lc;
+            if (OP == 0) {
+                o0[t] = add_mod(x0[t], y0[t], p.q);
+                o1[t] = add_mod(x1[t], y1[t], p.q);
+            } else {
+                const u64 a0 = x0[t], a1 = x1[t], b0 = y0[t], b1 = y1[t];
+                o0[t] = mul_mod(a0, b0, p);
+                o1[t] = add_mod(mul_mod(a0, b1, p), mul_mod(a1, b0, p), p.q);
+                o1[t + lc] = mul_mod(a1, b1, p);
+            }
+        }
+    }
+}
+
 // The gradient terms of nb blocks summed into one degree-4 ciphertext at level
 // lp (limbs 0..lp), straight into g (accumulated onto g when acc):
 //   g += sum_b A_b (x) B3_b + M_b (x) Z1_b + k0 Z_b  (+ A_b (x) Z2_b when z2)
@@ -3022,6 +3057,15 @@ void tensor_b(he_ctx *c, int level, int B, const u64 *x, long long xb, long long
 {
     dim3 g(xblocks(c->N), level + 1, B);
     tensor_kernel<<<g, 256, 0, c->stream>>>(x, xb, xc, y, yb, yc, o, ob, oc, c->t.pinfo, c->logN);
+}
+
+void desc_ew(he_ctx *c, int op, const OpDesc *tab, int n, int max_limbs)
+{
+    if (n < 1) return;
+    dim3 g(xblocks(c->N), max_limbs, n);
+    if (op == 0) desc_ew_kernel<0><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN);
+    else if (op == 4) desc_ew_kernel<4><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN);
+    else desc_ew_kernel<6><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN);
 }
 
 void terms_sum_b(he_ctx *c, int lp, int nb, const u64 *A, const u64 *B3, long long as, const u64 *Z1, const u64 *Z2,

@@ -47,6 +47,13 @@ he_pt = he_ct
 he_ct3 = he_ct
 
 
+class he_op(ctypes.Structure):
+    _fields_ = [("op", c_int32), ("steps", c_int32), ("x", he_ct), ("y", he_ct), ("out", he_ct)]
+
+
+OP_MUL, OP_MUL_ROTATE, OP_ROTATE, OP_RESCALE, OP_ADD = 1, 2, 3, 4, 5
+
+
 class he_ct_seeded(ctypes.Structure):
     _fields_ = [("b", c_void_p), ("level", c_int32), ("reserved", c_int32), ("scale", c_double), ("seed", c_uint64),
                 ("index", c_uint32), ("reserved2", c_uint32)]
@@ -119,6 +126,8 @@ _sig = {
     "he_rotate_sum": (c_int, [c_void_p, _P(he_ct), c_int, _P(c_int32), c_int, c_void_p, _P(he_ct)]),
     "he_batch_mul_rotate": (c_int, [c_void_p, _P(he_ct), _P(he_ct), _P(c_int32), c_int, c_void_p, c_int,
                                     _P(he_ct)]),
+    "he_batch_submit": (c_int, [c_void_p, _P(he_op), c_int, c_void_p, c_int]),
+    "he_batch_submit_bytes": (ctypes.c_size_t, [c_void_p, _P(he_op), c_int, c_int]),
     "he_lr_margins": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), c_int, c_int, c_int, c_void_p, c_int,
                               _P(he_ct)]),
     "he_lr_infer": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), c_int, c_int, c_int, _P(c_double), c_void_p,
@@ -639,6 +648,33 @@ class Context:
         for o, s_ in zip(outs, oa):
             o.update(s_)
         return outs
+
+    @staticmethod
+    def op_out_level(op, x):
+        return x.level - 1 if op in (OP_MUL, OP_MUL_ROTATE, OP_RESCALE) else x.level
+
+    def op_array(self, ops):
+        """he_op array of [(op, steps, x, y, out)] (y None where unused; out
+        allocated at the op's output level when None); returns (array, outs)."""
+        outs = [o if o is not None else self.ct_empty(self.op_out_level(op, x)) for op, _, x, _, o in ops]
+        arr = (he_op * len(ops))()
+        for a, (op, steps, x, y, _), o in zip(arr, ops, outs):
+            a.op, a.steps, a.x, a.out = op, int(steps), x.struct(), o.struct()
+            if y is not None:
+                a.y = y.struct()
+        return arr, outs
+
+    def batch_submit(self, ops, keys, mode=1):
+        """he_batch_submit over [(op, steps, x, y, out)]; returns the outs."""
+        arr, outs = self.op_array(ops)
+        _chk(_lib.he_batch_submit(self.h, arr, len(ops), keys.handle, mode), "he_batch_submit")
+        for o, a in zip(outs, arr):
+            o.update(a.out)
+        return outs
+
+    def batch_submit_bytes(self, ops, mode=1):
+        arr, _ = self.op_array(ops)
+        return int(_lib.he_batch_submit_bytes(self.h, arr, len(ops), mode))
 
     def valu_peak(self, prime_idx, fp64=True):
         """he_valu_peak: measured butterflies per second of the NTT's butterfly."""
