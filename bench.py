@@ -61,8 +61,10 @@ def parse():
     ap.add_argument("--baby", type=int, default=16,
                     help="baby steps of the margin sum, both packings (1 = rotations only)")
     ap.add_argument("--ntt-counters", action="store_true",
-                    help="run only the calibration copy and the NTT batch (a target for rocprofv3 --pmc passes, "
-                         "which cannot follow the step's graph launches); prints no bench line")
+                    help="run only the calibration copy and the NTT batch (the target of rocprofv3 --pmc passes: "
+                         "counters are taken over isolated kernels, never over the step, since a FETCH_SIZE pass "
+                         "over the whole bench once ended in a host-thread SIGSEGV whose cause is not "
+                         "established); prints no bench line")
     ap.add_argument("--giant-counters", action="store_true",
                     help="run only the calibration copy and the hoisted giant-step sum over the shard's blocks "
                          "(for rocprofv3 --pmc)")
