@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--giant-counters", action="store_true",
                     help="run only the calibration copy and the hoisted giant-step sum over the shard's blocks "
                          "(for rocprofv3 --pmc)")
+    ap.add_argument("--schedule-only", action="store_true",
+                    help="run only the headline schedule (feature-major, graph form): one warm-up refresh period, "
+                         "then --steps timed steps between two marker fills (a target for rocprofv3 "
+                         "--kernel-trace: the markers delimit the timed steps); prints no bench line")
     ap.add_argument("--ks-counters", action="store_true",
                     help="run only the calibration copy and 3 batched multiply-relinearise-rescale-rotate launches "
                          "over 32 ciphertexts at level 18 (key-switch kernels at the step's top-level shape, "
@@ -361,6 +365,28 @@ def bench_layout(torch, H, T, ctx, keys, X, y, coef, layout, args, Wk):
     return res
 
 
+def schedule_only(torch, H, T, ctx, keys, X, y, coef, args, Wk):
+    """The headline schedule alone, its timed steps between two marker kernels."""
+    layout = H.LAYOUT_FEATURES
+    n, d = X.shape
+    Z, c, r = T.encrypt_shard(ctx, keys, X, y, Wk["seed_enc"], layout)
+    ps = T.ParameterServer(ctx, keys, d, c, Wk["seed_enc"], layout=layout)
+    Zrot = ctx.rotate_data(Z, H.baby_unit(layout, r), args.baby, keys) if args.baby > 1 else None
+    wk = T.Worker(ctx, keys, Z, coef, 1.0 / n, c, r, mode=2, layout=layout, n_baby=args.baby, Zrot=Zrot)
+    sched = Schedule(wk, ps, np.zeros(d))
+    sched.iterate(REFRESH_EVERY)
+    marker = torch.zeros(1 << 20, device="cuda")
+    torch.cuda.synchronize()
+    marker.fill_(1.0)
+    t0 = time.perf_counter()
+    sched.iterate(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    marker.fill_(2.0)
+    torch.cuda.synchronize()
+    log("schedule only: %d steps, %.2f ms/step (between the two marker fills)" % (args.steps, dt / args.steps * 1e3))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -400,6 +426,9 @@ def main():
     torch.cuda.synchronize()
     log("keygen: 3 relinearisation + %d rotation keys (%.1fs)" % (len(steps), time.time() - t0))
     coef = coef_binomial()
+    if args.schedule_only:
+        schedule_only(torch, H, T, ctx, keys, X, y, coef, args, Wk)
+        return
 
     layouts = {}
     for layout, name in ((H.LAYOUT_FEATURES, "feature-major"), (H.LAYOUT_ROWS, "row-major")):

@@ -230,8 +230,8 @@ size_t he_keys_bytes(const he_ctx *ctx, int n_rot);
 he_status he_keygen(he_ctx *ctx, uint64_t seed, const int32_t *rot_steps, int n_rot,
                     void *key_buf, size_t key_buf_bytes, he_keys **out);
 /* Release a key handle; graphs its context captured with it are dropped (the
- * buffer stays the caller's).  Release keys before the context that made
- * them.  Graphs that other contexts captured with them are never replayed
+ * buffer stays the caller's).  Keys and the context that made them may be
+ * released in either order.  Graphs that other contexts captured with them are never replayed
  * again (their cache entries name the key set's generation) and go with
  * those contexts or their next he_ctx_trim. */
 he_status he_keys_destroy(he_keys *keys);

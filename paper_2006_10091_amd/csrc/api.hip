@@ -1242,6 +1242,7 @@ he_status he_ctx_destroy(he_ctx *c)
         (void)hipEventDestroy(c->sub_ev);
     }
     if (c->sub_host) (void)hipHostFree(c->sub_host);
+    for (he_keys *k : c->keys_made) k->ctx = nullptr;  // released later, they no longer reach this context
     delete c;
     return HE_OK;
 }
@@ -1385,6 +1386,7 @@ he_status he_keygen(he_ctx *c, uint64_t seed, const int32_t *rot_steps, int n_ro
     }
     HIPCHK(hipStreamSynchronize(c->stream));  // the host secret buffer is released below
     TRY(last_error());
+    c->keys_made.insert(k.get());
     *out = k.release();
     return HE_OK;
 }
@@ -1394,7 +1396,11 @@ he_status he_keys_destroy(he_keys *k)
     if (!k) return HE_EINVAL;
     // graphs captured with these keys hold their device addresses: a later key
     // set may be given the same host handle or buffer
-    const he_status st = k->ctx ? drop_graphs(k->ctx, k->gen) : HE_OK;
+    he_status st = HE_OK;
+    if (k->ctx) {  // the making context is still alive (its destroy clears ctx)
+        st = drop_graphs(k->ctx, k->gen);
+        k->ctx->keys_made.erase(k);
+    }
     delete k;
     if (st != HE_OK) return st;
     return HE_OK;

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -101,10 +102,13 @@ struct he_ctx {
     void *sub_host = nullptr;
     size_t sub_host_bytes = 0;
     hipEvent_t sub_ev = nullptr;
+    // key sets this context made and that are not yet released: their
+    // back-pointer is cleared when the context goes first
+    std::set<he_keys *> keys_made;
 };
 
 struct he_keys {
-    he_ctx *ctx;                    // the context that made them (its graphs are dropped with them)
+    he_ctx *ctx;                    // the context that made them (its graphs are dropped with them); NULL once it is destroyed
     int logN, nq, nk, alpha;        // the parameter set they are valid for:
     u64 q[HE_MAXP];                 // any context with this ring and chain may use them
     uint64_t gen;                   // unique per key set (graph-cache key; never reused)

@@ -155,3 +155,27 @@ def test_graph_cache_after_keys_replaced(env):
             assert np.array_equal(ctx.download(Wn), oWn.data), order[:3]
             assert np.array_equal(ctx.download(g), og.data)
         del gk
+
+
+def test_keys_released_after_their_context():
+    """A context and its keys may be released in either order: with the
+    context destroyed first (an order Python's cycle collector may take), the
+    keys are still released cleanly, graphs captured with them included."""
+    from paper_2006_10091_amd import he as H
+    ctx = H.Context(*SMALL40)
+    keys = ctx.keygen(5, [1])
+    q = ctx.primes[:4]
+    x = ctx.upload(np.stack([synth.uniform_residues(3, q, ctx.N), synth.uniform_residues(4, q, ctx.N)]), 3, 1.0)
+    ctx.batch_submit([(H.OP_ROTATE, 1, x, None, None)], keys, mode=2)  # a graph that names these keys
+    torch.cuda.synchronize()
+    h, kh = ctx.h, keys.handle
+    ctx.h, keys.handle = None, None  # the binding's destructors will not release them again
+    assert H._lib.he_ctx_destroy(h) == 0
+    assert H._lib.he_keys_destroy(kh) == 0
+    # and the other order, for completeness
+    ctx2 = H.Context(*SMALL40)
+    k2 = ctx2.keygen(5, [1])
+    h2, kh2 = ctx2.h, k2.handle
+    ctx2.h, k2.handle = None, None
+    assert H._lib.he_keys_destroy(kh2) == 0
+    assert H._lib.he_ctx_destroy(h2) == 0
