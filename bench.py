@@ -39,7 +39,9 @@ HBM_PEAK_GBS = 8000.0
 # what the same counter reads for the 1 GiB calibration copy below
 # (profiles/ntt_forward_5640_limbs_pmc.md).  None whenever the NTT kernels have
 # changed since the counters were taken.
-NTT_TRAFFIC_BYTES = {5640: (2 * 1444210 + 2 * 1449510 + 2887680 + 2887680) * 1024}
+# counted HBM bytes per forward transform (FETCH_SIZE x2 calibration + WRITE_SIZE, KiB per dispatch, both
+# passes) by limb count, from rocprofv3 --pmc over --ntt-counters in the tuned (XCD-grouped) block order
+NTT_TRAFFIC_BYTES = {5640: (2 * 1444250 + 2 * 1449696 + 2887681 + 2887680) * 1024}
 COPY_BYTES = 1 << 30
 REFRESH_EVERY = 4
 

@@ -190,7 +190,11 @@ he_status he_params_primes(const he_params *prm, uint64_t *out, int n);
  * passes through a scratch limb of its own (8 * wg_per_xcd workgroups, at
  * most 512; the scratch kept in L2 / Infinity Cache; lag unused; ring
  * degrees whose passes do not split evenly fall back to two launches);
- * 0: one launch per pass (the intermediate goes through HBM).  Drops
+ * 0: one launch per pass (the intermediate goes through HBM); 4 / 5: the
+ * same with the column passes / both passes taking their workgroups in an
+ * XCD-grouped order (XCD k runs the k-th eighth of the blocks, so the strips
+ * of one limb run on one XCD together), for every transform of the context,
+ * fused ones included; wg_per_xcd, lag and min_limbs unused.  Drops
  * the captured graphs.  HE_EINVAL for values out of range, during capture,
  * or persistent on a ring below 2^12.  Default: the two-launch form
  * (paper_2006_10091_amd/autotune.py measures the choices and writes the

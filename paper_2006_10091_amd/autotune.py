@@ -7,10 +7,12 @@ forward and inverse transforms of uniform residues with HIP events:
     each XCD's L2) for every workgroups-per-XCD and lag in the grid below;
   * the workgroup-per-limb forms (mode 2: 512 threads, mode 3: 1024 threads
     per limb, intermediate in a scratch limb per workgroup) for every
-    workgroups-per-XCD in LIMB_GRID.
+    workgroups-per-XCD in LIMB_GRID;
+  * the two-launch form with XCD-grouped block order (mode 4: column passes,
+    mode 5: both passes).
 The table maps (log N, batch) to the fastest shape; per ring degree it also
-derives the context setting he_ctx_set_ntt takes: the single-launch shape that
-wins at the largest batch, and min_limbs = the smallest measured batch from
+derives the context setting he_ctx_set_ntt takes: the shape that wins at the
+largest batch, and min_limbs = the smallest measured batch from
 which that shape's mode wins at every larger measured batch.  Every shape
 gives bit-identical results (checked here on every measurement).
 
@@ -65,6 +67,7 @@ def tune(log_ns=(14, 15, 16), quick=False, log=print):
             ref = None
             shapes = [(0, 64, 2)] + [(1, w, g) for w in wgs for g in lags]
             shapes += [(m, w, 2) for m in (2, 3) for w in ((32,) if quick else LIMB_GRID)]
+            shapes += [(4, 64, 2), (5, 64, 2)]  # two launches, XCD-grouped block order
             for shape in shapes:
                 ctx.set_ntt(shape[0], shape[1], shape[2])
                 x.copy_(src)

@@ -1249,12 +1249,12 @@ he_status he_ctx_destroy(he_ctx *c)
 
 he_status he_ctx_set_ntt(he_ctx *c, int persistent, int wg_per_xcd, int lag, int min_limbs)
 {
-    if (!c || persistent < 0 || persistent > 3 || wg_per_xcd < 1 || wg_per_xcd > 1024 || lag < 1 || lag >= PS_SLOTS ||
+    if (!c || persistent < 0 || persistent > 5 || wg_per_xcd < 1 || wg_per_xcd > 1024 || lag < 1 || lag >= PS_SLOTS ||
         min_limbs < 1)
         return HE_EINVAL;
     if (persistent == 1 && !c->persist.slots) return HE_EINVAL;
     if (c->capturing) return HE_EINVAL;
-    if (persistent >= 2 && !c->persist.limb_scratch) {
+    if ((persistent == 2 || persistent == 3) && !c->persist.limb_scratch) {
         // the one-workgroup-per-limb form's scratch limbs, made on first use
         if (!c->persist.slots || c->logN < 12) return HE_EINVAL;
         c->persist.limb_scratch = (u64 *)dev_alloc(c, (size_t)c->persist.limb_wgs * c->N * 8);

@@ -66,6 +66,8 @@ struct PersistCfg {
     int min_limbs = 1;    // smaller transforms take the two-launch form
     unsigned *ctr = nullptr;
     u64 *slots = nullptr;
+    // on = 4 / 5: two launches, the column passes / both passes taking their
+    // blocks in XCD-grouped order (every NTT launch, fused passes included).
     // on = 2 / 3: one workgroup of 512 / 1024 threads per limb (both passes),
     // each with a scratch limb; 8 * wg_per_xcd workgroups, at most limb_wgs
     int limb_wgs = 512;

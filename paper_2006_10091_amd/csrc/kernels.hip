@@ -37,6 +37,7 @@ struct NttArgs {
     int ell, nq;
     int logN, logN1;
     int zoff;  // first batch x component entry of this launch (chunked launches)
+    int xcd;   // 1: column passes, 2: both passes take their blocks XCD-grouped (vb_xcd)
 };
 
 // Block index of a pass: blockIdx for the one-pass-per-launch kernels, a
@@ -45,6 +46,19 @@ struct VB {
     int x, y, z;
 };
 __device__ __forceinline__ VB vb_here() { return VB{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z}; }
+// Workgroups are dealt to the 8 XCDs in turn by linear id.  This bijection
+// gives XCD k the contiguous eighth k of the (x fastest) block order, so the
+// x-neighbours of one limb -- its 16 column strips -- run on one XCD one after
+// another and fetch each row of the limb close together in time.  Grids whose
+// size is not a multiple of 8 keep their order.
+__device__ __forceinline__ VB vb_xcd()
+{
+    const unsigned gx = gridDim.x, gy = gridDim.y, total = gx * gy * gridDim.z;
+    if (total & 7u) return vb_here();
+    const unsigned id = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned j = (id & 7u) * (total >> 3) + (id >> 3);
+    return VB{(int)(j % gx), (int)((j / gx) % gy), (int)(j / (gx * gy))};
+}
 
 __device__ __forceinline__ bool ntt_locate(const NttArgs &a, VB vb, u64 *&limb, int &pidx)
 {
@@ -813,7 +827,8 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const Prim
 {
     using S = LineShape<(LOGN + 1) / 2>;
     __shared__ u64 lds[S::LINES * S::PADDED];
-    ntt_cols_body<LOGN, INV, PRO>(a, pinfo, tw, tws, post, twd, f, vb_here(), lds, nullptr, (int)threadIdx.x);
+    ntt_cols_body<LOGN, INV, PRO>(a, pinfo, tw, tws, post, twd, f, a.xcd ? vb_xcd() : vb_here(), lds, nullptr,
+                                  (int)threadIdx.x);
 }
 
 // pass B: rows.  Thread (line, tau) with tau fastest; LINES consecutive rows per workgroup.
@@ -1012,7 +1027,8 @@ __global__ __launch_bounds__(LINE_THREADS) void ntt_rows_t(NttArgs a, const Prim
 {
     using S = LineShape<LOGN - (LOGN + 1) / 2>;
     __shared__ u64 lds[S::LINES * S::PADDED];
-    ntt_rows_body<LOGN, INV, MODE>(a, pinfo, tw, tws, twd, f, vb_here(), lds, nullptr, (int)threadIdx.x);
+    ntt_rows_body<LOGN, INV, MODE>(a, pinfo, tw, tws, twd, f, a.xcd == 2 ? vb_xcd() : vb_here(), lds, nullptr,
+                                   (int)threadIdx.x);
 }
 
 // Row pass of the extended digits' forward NTT fused with the key-switch
@@ -2742,8 +2758,8 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
 {
     constexpr int LA = (LOGN + 1) / 2, LB = LOGN - LA;
     const int nz = nbatch * a.ncomp;
-    if (pro == PRO_NONE && epi == EPI_NONE && c->persist.on >= 2 && c->persist.limb_scratch &&
-        npos * nz >= c->persist.min_limbs) {
+    if (pro == PRO_NONE && epi == EPI_NONE && (c->persist.on == 2 || c->persist.on == 3) &&
+        c->persist.limb_scratch && npos * nz >= c->persist.min_limbs) {
         a.zoff = 0;
         const bool done = c->persist.on == 2 ? limb_launch<LOGN, 2>(c, a, npos * nz, npos, dir, post)
                                              : limb_launch<LOGN, 4>(c, a, npos * nz, npos, dir, post);
@@ -2768,6 +2784,7 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
                                                                            post, c->t.ipsi_d, ps);
         return;
     }
+    a.xcd = c->persist.on >= 4 ? c->persist.on - 3 : 0;
     const long long per_z = (long long)npos << (LOGN + 3);
     int zc = (int)std::max(1LL, NTT_CHUNK_BYTES / per_z);
     if (zc > nz) zc = nz;
@@ -2850,6 +2867,7 @@ void ntt_batch(he_ctx *c, u64 *base, long long bstride, long long cstride, int n
     a.logN = c->logN;
     a.logN1 = (c->logN + 1) / 2;
     a.zoff = 0;
+    a.xcd = 0;  // set by the launcher from the context
     ntt_launch(c, a, nbatch, npos, dir, post);
 }
 
@@ -2869,6 +2887,7 @@ static NttArgs make_args(he_ctx *c, u64 *base, long long bstride, long long cstr
     a.logN = c->logN;
     a.logN1 = (c->logN + 1) / 2;
     a.zoff = 0;
+    a.xcd = c->persist.on >= 4 ? c->persist.on - 3 : 0;
     return a;
 }
 
