@@ -406,6 +406,36 @@ he_status he_lr_grad_step(he_ctx *ctx, const he_ct *Z, int n_blocks, const he_ct
                           const he_ct *Zk, const he_keys *keys, int mode, he_ct *W_out, he_ct *G_out);
 
 /*
+ * Several independent gradient steps (eq. (appr) + eq. (update), one per
+ * request: workers' shards, or serving requests) that share the context, the
+ * packing, c, r and their weights' level; each request has its own blocks,
+ * weights, mask, Table 2 coefficients, eta/n, regulariser and outputs, with
+ * the arguments and meaning of he_lr_grad_step (no baby steps, no data terms).
+ * mode 1: each request's per-block part runs on its own blocks, then the
+ * once-per-step tail (the relinearisation of the summed degree-4 terms, the
+ * rescale, the slot sums, mask and replication, the W update) runs once for
+ * all requests, every kernel over all of them together; mode 0: each request
+ * as he_lr_grad_step's plain form.  Each request's W' and g are bit-identical
+ * to its own he_lr_grad_step.  Errors before any launch: those of
+ * he_lr_grad_step for any request, HE_ELEVEL when the weights' levels
+ * differ.
+ */
+typedef struct {
+    const he_ct *Z;      /* the request's blocks (uniform stride) */
+    int32_t n_blocks;
+    const he_ct *W;      /* weights; every request's at one level */
+    const he_pt *mask;   /* its step mask (scale from he_plan_lr_step with its eta/n) */
+    const double *coef;  /* [4] */
+    double eta_over_n, w_decay;
+    he_ct *W_out, *G_out;  /* G_out may be NULL */
+} he_lr_request;
+he_status he_lr_grad_step_multi(he_ctx *ctx, const he_lr_request *reqs, int n_req, int c, int r, int layout,
+                                const he_keys *keys, int mode);
+/* Device workspace (bytes) of he_lr_grad_step_multi for n_req requests of at
+ * most max_blocks blocks each, weights at `level`; 0 for invalid arguments. */
+size_t he_lr_grad_step_multi_bytes(const he_ctx *ctx, int level, int max_blocks, int n_req, int layout, int mode);
+
+/*
  * he_lr_grad_step on seeded data blocks (the shard that does not fit in HBM as
  * full ciphertexts: 2^20 samples x 512 features at N = 2^16 is 16384 blocks,
  * 384 GiB in full, 192 GiB seeded).  The blocks are taken `chunk` at a time:

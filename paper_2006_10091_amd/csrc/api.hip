@@ -905,18 +905,25 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
 }
 
 // log2(count) rotate-and-add rounds x += Rot(x, t * unit), t = 1, 2, .., count/2,
-// on one ciphertext at `level` (component stride (level+1) N); tmp: same size
-he_status rotate_sum(he_ctx *c, Arena &ar, int level, u64 *x, u64 *tmp, long long unit, int count,
-                     const he_keys *keys)
+// on B ciphertexts at `level` (batch stride xs, component stride (level+1) N),
+// every round one batched rotation of all B
+he_status rotate_sum_b(he_ctx *c, Arena &ar, int level, int B, u64 *x, long long xs, long long unit, int count,
+                       const he_keys *keys)
 {
-    const long long x1 = (long long)(level + 1) * c->N;
     for (int t = 1; t < count; t <<= 1) {
         const u64 gal = galois_of(c, (long long)t * unit);
         const u64 *key = find_rot_key(keys, gal);
         if (!key) return HE_EKEY;
-        TRY(rotate_apply(c, ar, level, 1, x, 2 * x1, gal, key, x, 2 * x1, x));  // x += Rot(x)
+        TRY(rotate_apply(c, ar, level, B, x, xs, gal, key, x, xs, x));  // x += Rot(x)
     }
     return HE_OK;
+}
+// the same on one ciphertext (tmp unused: the rounds run in place)
+he_status rotate_sum(he_ctx *c, Arena &ar, int level, u64 *x, u64 *tmp, long long unit, int count,
+                     const he_keys *keys)
+{
+    (void)tmp;
+    return rotate_sum_b(c, ar, level, 1, x, 2LL * (level + 1) * c->N, unit, count, keys);
 }
 
 // Run `body` captured into a HIP graph on first use of `key` and replayed
@@ -1799,10 +1806,19 @@ he_status uniform_group(const he_ctx *c, const he_ct *x, int n, int level, doubl
     return HE_OK;
 }
 
-he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, const he_pt *mask,
-                          const double coef[4], double eta_over_n, double w_decay, int cols, int rows, int layout,
-                          const he_ct *Zrot, int n_baby, const he_ct *Zk, const he_keys *k, int mode, he_ct *W_out,
-                          he_ct *G_out)
+// The step's arguments checked before any launch (level, scale, stride and
+// key errors), with its plan, block stride and baby / term data.
+struct StepArgs {
+    he_lr_plan pl;
+    long long zbs = 0;
+    BabyData bd;
+    TermData td;
+};
+
+static he_status step_args(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, const he_pt *mask,
+                           const double coef[4], double eta_over_n, double w_decay, int cols, int rows, int layout,
+                           const he_ct *Zrot, int n_baby, const he_ct *Zk, const he_keys *k, int mode,
+                           const he_ct *W_out, const he_ct *G_out, StepArgs &sa)
 {
     if (!c || !Z || n_blocks < 1 || !ct_ok(c, W) || !mask || !mask->data || !coef || !k || mode < 0 || mode > 2)
         return HE_EINVAL;
@@ -1828,8 +1844,9 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
     }
     if (lz < l) return HE_ELEVEL;
     if (mode > 0 && n_blocks > 1 && zbs < 2LL * (lz + 1) * c->N) return HE_EINVAL;
+    sa.zbs = zbs;
     // baby-step copies: Zrot[b * (n_baby - 1) + j - 1] = Rot(Z[b], j rows), one level, one scale, uniform strides
-    BabyData bd;
+    BabyData &bd = sa.bd;
     bd.n_baby = n_baby;
     if (n_baby > 1) {
         const int m = n_baby - 1, lr = Zrot[0].level;
@@ -1847,11 +1864,11 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
         if (m > 1 && bd.zrs < 2 * bd.zrc) return HE_EINVAL;
         if (n_blocks > 1 && bd.zrb < (long long)m * 2 * bd.zrc) return HE_EINVAL;
     }
-    he_lr_plan pl;
+    he_lr_plan &pl = sa.pl;
     TRY(hehost::plan_lr_step(c->q.data(), c->nq, l, sz, W->scale, coef, eta_over_n, w_decay, layout, &pl));
     if (mask->scale != pl.s_mask) return HE_ESCALE;
     // precomputed data terms (he_lr_data_terms for this plan): Z3 group, Z1 group, Z2 group when k2 != 0
-    TermData td;
+    TermData &td = sa.td;
     if (Zk) {
         long long s3, s1, s2;
         TRY(uniform_group(c, Zk, n_blocks, z3_level(l, fm), pl.s_z3, s3));
@@ -1885,6 +1902,23 @@ he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *
     }
     for (int t = 1; t < st; t <<= 1)
         if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
+    return HE_OK;
+}
+
+he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, const he_pt *mask,
+                          const double coef[4], double eta_over_n, double w_decay, int cols, int rows, int layout,
+                          const he_ct *Zrot, int n_baby, const he_ct *Zk, const he_keys *k, int mode, he_ct *W_out,
+                          he_ct *G_out)
+{
+    StepArgs sa;
+    TRY(step_args(c, Z, n_blocks, W, mask, coef, eta_over_n, w_decay, cols, rows, layout, Zrot, n_baby, Zk, k, mode,
+                  W_out, G_out, sa));
+    const he_lr_plan &pl = sa.pl;
+    const long long zbs = sa.zbs;
+    const BabyData &bd = sa.bd;
+    const TermData &td = sa.td;
+    const int l = W->level;
+    const int lz = Z[0].level;
     const int chunk = mode == 0 ? 1 : n_blocks;
     TRY(ensure_ws(c, step_bytes(c, l, chunk, layout, n_baby)));
     if (mode == 2) {
@@ -2445,6 +2479,182 @@ he_status he_batch_submit(he_ctx *c, he_op *ops, int n, const he_keys *k, int mo
         if (o.op == HE_OP_MUL || o.op == HE_OP_MUL_ROTATE) o.out.scale = o.x.scale * o.y.scale / (double)c->q[l];
         else if (o.op == HE_OP_RESCALE) o.out.scale = o.x.scale / (double)c->q[l];
         else o.out.scale = o.x.scale;
+    }
+    return last_error();
+}
+
+// ------------------------------------------------------------------ several requests' steps, tails batched
+// Per request the per-block part of the step runs as in he_lr_grad_step (its
+// own plan, mask and blocks), into its own degree-4 term sum; the once-per-step
+// tail then runs once for all requests: the three relinearisation key switches
+// (one batched call per key), the rescale, the rotate-and-add rounds of every
+// request together, the masks and W updates through a device operand table.
+// Every kernel treats each entry on its own, so each request's W' and g are
+// bit-identical to its own he_lr_grad_step in mode 1.
+struct MultiBufs {
+    u64 *G5, *ksx, *U0, *G, *Gm, *Wk, *Wr;
+    hek::OpDesc *tab;
+};
+
+static size_t multi_tail_u64(const he_ctx *c, int l, int n, int layout, size_t *tab_u64 = nullptr)
+{
+    const size_t N = c->N;
+    const bool fm = layout == HE_LAYOUT_FEATURES;
+    const int lg = fm ? l - 2 : l - 3;
+    const size_t x1 = (size_t)(lg + 1) * N;
+    const size_t tb = al((size_t)4 * n * sizeof(hek::OpDesc) / 8 + 1);
+    if (tab_u64) *tab_u64 = tb;
+    size_t u = tb + al((size_t)n * 5 * x1) + al((size_t)3 * n * 2 * x1) + al((size_t)n * 2 * x1);
+    u += al((size_t)n * 2 * lg * N) + (fm ? al((size_t)n * 2 * (l - 3) * N) : 0);
+    u += al((size_t)n * 2 * (l - 2) * N) + al((size_t)n * 2 * (l - 3) * N);
+    // the batched tail's scratch: a key switch of n entries at lg, rotations and rescales of n
+    size_t scr = std::max(ks_scratch(c, lg, n), rescale_scratch(c, lg, n));
+    scr = std::max(scr, rotate_scratch(c, lg - 1, n));
+    scr = std::max(scr, rescale_scratch(c, l - 3, n));
+    return u + scr;
+}
+
+static size_t multi_bytes(const he_ctx *c, int l, int max_blocks, int n, int layout, int mode)
+{
+    return step_bytes(c, l, mode == 0 ? 1 : max_blocks, layout, 1) + multi_tail_u64(c, l, n, layout) * 8 + 4096;
+}
+
+static he_status multi_impl(he_ctx *c, const he_lr_request *rq, int n, const std::vector<StepArgs> &sa, int cols,
+                            int rows, int layout, const he_keys *k, int max_blocks)
+{
+    const long long N = c->N;
+    const int l = rq[0].W->level;
+    const bool fm = layout == HE_LAYOUT_FEATURES;
+    const int lg = fm ? l - 2 : l - 3;
+    const long long x1 = (long long)(lg + 1) * N, r1 = (long long)lg * N, g1 = (long long)(l - 3) * N;
+    const long long w1 = (long long)(l - 2) * N;
+    Arena ar = arena(c);
+    StepBufs s;
+    TRY(step_alloc(c, ar, l, max_blocks, layout, 1, s));
+    MultiBufs m;
+    size_t tab_u64 = 0;
+    (void)multi_tail_u64(c, l, n, layout, &tab_u64);
+    m.tab = (hek::OpDesc *)ar.take(tab_u64);
+    m.G5 = ar.take((size_t)n * 5 * x1);
+    m.ksx = ar.take((size_t)3 * n * 2 * x1);
+    m.U0 = ar.take((size_t)n * 2 * x1);
+    m.G = ar.take((size_t)n * 2 * r1);
+    m.Gm = fm ? ar.take((size_t)n * 2 * g1) : nullptr;
+    m.Wk = ar.take((size_t)n * 2 * w1);
+    m.Wr = ar.take((size_t)n * 2 * g1);
+    if (!m.tab || !m.G5 || !m.ksx || !m.U0 || !m.G || (fm && !m.Gm) || !m.Wk || !m.Wr) return HE_ENOMEM;
+    // per request: the per-block part into its own term sum
+    for (int i = 0; i < n; ++i) {
+        s.G5 = m.G5 + (long long)i * 5 * x1;
+        const BabyData bd;
+        const TermData td;
+        if (fm)
+            TRY(step_blocks_features(c, ar, s, sa[i].pl, rq[i].Z, sa[i].zbs, 0, rq[i].n_blocks, rq[i].W, cols, rows, k,
+                                     false, bd, td));
+        else
+            TRY(step_blocks(c, ar, s, sa[i].pl, rq[i].Z, sa[i].zbs, 0, rq[i].n_blocks, rq[i].W, rq[i].mask, cols, k,
+                            false, bd, td));
+    }
+    // the operand tables of the tail: masks (feature-major), G copies, kW W, W' = RS(kW W) + g
+    std::vector<hek::OpDesc> tab;
+    u64 *gfin = fm ? m.Gm : m.G;
+    const long long gs = fm ? 2 * g1 : 2 * r1;  // batch stride of the final g (level l-4 either way)
+    if (fm)
+        for (int i = 0; i < n; ++i) tab.push_back({m.G + i * 2 * r1, rq[i].mask->data, m.G + i * 2 * r1, l - 2, 0, 0});
+    const int t_mask = 0, t_copy = (int)tab.size();
+    int n_copy = 0;
+    for (int i = 0; i < n; ++i)
+        if (rq[i].G_out) {
+            tab.push_back({gfin + i * gs, nullptr, rq[i].G_out->data, l - 3, 0, 0});
+            ++n_copy;
+        }
+    const int t_kw = (int)tab.size();
+    for (int i = 0; i < n; ++i) tab.push_back({rq[i].W->data, nullptr, m.Wk + i * 2 * w1, l - 2, l + 1, sa[i].pl.kw});
+    const int t_add = (int)tab.size();
+    for (int i = 0; i < n; ++i) tab.push_back({m.Wr + i * 2 * g1, gfin + i * gs, rq[i].W_out->data, l - 3, 0, 0});
+    const size_t tb = tab.size() * sizeof(hek::OpDesc);
+    if (!c->sub_ev) HIPCHK(hipEventCreateWithFlags(&c->sub_ev, hipEventDisableTiming));
+    HIPCHK(hipEventSynchronize(c->sub_ev));
+    if (c->sub_host_bytes < tb) {
+        if (c->sub_host) (void)hipHostFree(c->sub_host);
+        c->sub_host = nullptr;
+        c->sub_host_bytes = 0;
+        HIPCHK(hipHostMalloc(&c->sub_host, tb, hipHostMallocDefault));
+        c->sub_host_bytes = tb;
+    }
+    std::memcpy(c->sub_host, tab.data(), tb);
+    HIPCHK(hipMemcpyAsync(m.tab, c->sub_host, tb, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipEventRecord(c->sub_ev, c->stream));
+    // one relinearisation of every request's degree-4 sum: the key switches of
+    // g2, g3, g4 (one batched call per key), then (g0, g1) plus their sum
+    const u64 *rk[3] = {k->rlk, k->rlk3, k->rlk4};
+    for (int e = 0; e < 3; ++e)
+        TRY(ks_apply(c, ar, lg, n, m.G5 + (2 + e) * x1, 5 * x1, rk[e], nullptr, 0, 0, 0, m.ksx + (long long)e * n * 2 * x1,
+                     2 * x1, x1));
+    hek::ewise(c, 0, lg, n, 2, m.G5, 5 * x1, x1, m.ksx, 2 * x1, x1, m.U0, 2 * x1, x1, 0);
+    for (int e = 1; e < 3; ++e)
+        hek::ewise(c, 0, lg, n, 2, m.U0, 2 * x1, x1, m.ksx + (long long)e * n * 2 * x1, 2 * x1, x1, m.U0, 2 * x1, x1,
+                   0);
+    TRY(rescale_apply(c, ar, lg, n, m.U0, 2 * x1, m.G, 2 * r1));
+    if (fm) {
+        // sum inside each feature block, mask slots j r, rescale, replicate
+        TRY(rotate_sum_b(c, ar, l - 3, n, m.G, 2 * r1, 1, rows, k));
+        hek::desc_ew(c, 3, m.tab + t_mask, n, l - 2);
+        TRY(rescale_apply(c, ar, l - 3, n, m.G, 2 * r1, m.Gm, 2 * g1));
+        TRY(rotate_sum_b(c, ar, l - 4, n, m.Gm, 2 * g1, -1, rows, k));
+    } else {
+        TRY(rotate_sum_b(c, ar, l - 4, n, m.G, 2 * r1, cols, rows, k));  // row sum
+    }
+    hek::desc_ew(c, 4, m.tab + t_copy, n_copy, l - 3);
+    // W' = RS(kW W) + g
+    hek::desc_ew(c, 2, m.tab + t_kw, n, l - 2);
+    TRY(rescale_apply(c, ar, l - 3, n, m.Wk, 2 * w1, m.Wr, 2 * g1));
+    hek::desc_ew(c, 0, m.tab + t_add, n, l - 3);
+    return last_error();
+}
+
+size_t he_lr_grad_step_multi_bytes(const he_ctx *c, int level, int max_blocks, int n_req, int layout, int mode)
+{
+    if (!c || level < 4 || level >= c->nq || max_blocks < 1 || n_req < 1 || mode < 0 || mode > 1 ||
+        (layout != HE_LAYOUT_ROWS && layout != HE_LAYOUT_FEATURES))
+        return 0;
+    if (mode == 0) return step_bytes(c, level, 1, layout, 1);
+    return multi_bytes(c, level, max_blocks, n_req, layout, mode);
+}
+
+he_status he_lr_grad_step_multi(he_ctx *c, const he_lr_request *rq, int n_req, int cols, int rows, int layout,
+                                const he_keys *k, int mode)
+{
+    if (!c || !rq || n_req < 1 || !k || mode < 0 || mode > 1) return HE_EINVAL;
+    std::vector<StepArgs> sa(n_req);
+    int max_blocks = 1;
+    for (int i = 0; i < n_req; ++i) {
+        if (!rq[i].W) return HE_EINVAL;
+        TRY(step_args(c, rq[i].Z, rq[i].n_blocks, rq[i].W, rq[i].mask, rq[i].coef, rq[i].eta_over_n, rq[i].w_decay,
+                      cols, rows, layout, nullptr, 1, nullptr, k, 1, rq[i].W_out, rq[i].G_out, sa[i]));
+        if (rq[i].W->level != rq[0].W->level) return HE_ELEVEL;
+        max_blocks = std::max(max_blocks, rq[i].n_blocks);
+    }
+    const int l = rq[0].W->level;
+    if (mode == 0) {  // each request on its own (the reference form)
+        TRY(ensure_ws(c, step_bytes(c, l, 1, layout, 1)));
+        for (int i = 0; i < n_req; ++i) {
+            const BabyData bd;
+            const TermData td;
+            TRY(step_impl(c, sa[i].pl, rq[i].Z, rq[i].n_blocks, sa[i].zbs, bd, td, rq[i].W, rq[i].mask, cols, rows,
+                          k, 1, rq[i].W_out, rq[i].G_out));
+        }
+    } else {
+        TRY(ensure_ws(c, multi_bytes(c, l, max_blocks, n_req, layout, mode)));
+        TRY(multi_impl(c, rq, n_req, sa, cols, rows, layout, k, max_blocks));
+    }
+    for (int i = 0; i < n_req; ++i) {
+        rq[i].W_out->level = l - 4;
+        rq[i].W_out->scale = sa[i].pl.s_g;
+        if (rq[i].G_out) {
+            rq[i].G_out->level = l - 4;
+            rq[i].G_out->scale = sa[i].pl.s_g;
+        }
     }
     return last_error();
 }

@@ -193,16 +193,20 @@ void ks_inner_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const
 // per-entry evaluation keys / Galois elements for a batch of up to HE_MAXMULTI
 // entries (passed by value as kernel arguments)
 constexpr int HE_MAXMULTI = 32;
-// one entry of a device-side operand table (he_batch_submit): x, y inputs and
-// o output of one ciphertext-sized elementwise operation over `limbs` limbs
-// (primes q_0 ..), component stride limbs * N on each side
+// one entry of a device-side operand table (he_batch_submit, the batched
+// step's tail): x, y inputs and o output of one ciphertext-sized elementwise
+// operation over `limbs` limbs (primes q_0 ..), component stride limbs * N
+// (x's: xl * N when xl > 0); k: the entry's integer for op 2
 struct OpDesc {
     const u64 *x, *y;
     u64 *o;
-    int limbs, pad;
+    int limbs, xl;
+    i64 k;
 };
-// op 0: o = x + y (two components); 4: o = x (two components); 6: the tensor
-// o[3] = (x0 y0, x0 y1 + x1 y0, x1 y1).  One launch over n table entries.
+// op 0: o = x + y (two components); 2: o = k x (two components); 3: o = x y
+// with y one plaintext [limbs][N] (both components); 4: o = x (two
+// components); 6: the tensor o[3] = (x0 y0, x0 y1 + x1 y0, x1 y1).  One launch
+// over n table entries.
 void desc_ew(he_ctx *c, int op, const OpDesc *tab, int n, int max_limbs);
 struct EntryKeys {
     const u64 *k[HE_MAXMULTI];

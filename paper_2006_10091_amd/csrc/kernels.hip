@@ -1249,13 +1249,22 @@ __global__ __launch_bounds__(256) void desc_ew_kernel(const hek::OpDesc *__restr
     if (i >= d.limbs) return;
     const PrimeInfo p = pinfo[i];
     const long long li = (long long)i << logN, lc = (long long)d.limbs << logN;
+    const long long xc = d.xl > 0 ? (long long)d.xl << logN : lc;
     const int N = 1 << logN;
-    const u64 *x0 = d.x + li, *x1 = x0 + lc;
+    const u64 *x0 = d.x + li, *x1 = x0 + xc;
     u64 *o0 = d.o + li, *o1 = o0 + lc;
+    const u64 kq = OP == 2 ? int_mod(d.k, p) : 0;
     for (int t = blockIdx.x * 256 + threadIdx.x; t < N; t += gridDim.x * 256) {
         if (OP == 4) {
             o0[t] = x0[t];
             o1[t] = x1[t];
+        } else if (OP == 2) {
+            o0[t] = mul_mod(x0[t], kq, p);
+            o1[t] = mul_mod(x1[t], kq, p);
+        } else if (OP == 3) {
+            const u64 m = d.y[li + t];
+            o0[t] = mul_mod(x0[t], m, p);
+            o1[t] = mul_mod(x1[t], m, p);
         } else {
             const u64 *y0 = d.y + li, *y1 = y0 + lc;
             if (OP == 0) {
@@ -3082,9 +3091,13 @@ void desc_ew(he_ctx *c, int op, const OpDesc *tab, int n, int max_limbs)
 {
     if (n < 1) return;
     dim3 g(xblocks(c->N), max_limbs, n);
-    if (op == 0) desc_ew_kernel<0><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN);
-    else if (op == 4) desc_ew_kernel<4><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN);
-    else desc_ew_kernel<6><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN);
+    switch (op) {
+    case 0: desc_ew_kernel<0><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN); break;
+    case 2: desc_ew_kernel<2><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN); break;
+    case 3: desc_ew_kernel<3><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN); break;
+    case 4: desc_ew_kernel<4><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN); break;
+    default: desc_ew_kernel<6><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN); break;
+    }
 }
 
 void terms_sum_b(he_ctx *c, int lp, int nb, const u64 *A, const u64 *B3, long long as, const u64 *Z1, const u64 *Z2,

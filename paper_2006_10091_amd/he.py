@@ -47,6 +47,12 @@ he_pt = he_ct
 he_ct3 = he_ct
 
 
+class he_lr_request(ctypes.Structure):
+    _fields_ = [("Z", POINTER(he_ct)), ("n_blocks", c_int32), ("W", POINTER(he_ct)), ("mask", POINTER(he_ct)),
+                ("coef", POINTER(c_double)), ("eta_over_n", c_double), ("w_decay", c_double),
+                ("W_out", POINTER(he_ct)), ("G_out", POINTER(he_ct))]
+
+
 class he_op(ctypes.Structure):
     _fields_ = [("op", c_int32), ("steps", c_int32), ("x", he_ct), ("y", he_ct), ("out", he_ct)]
 
@@ -127,6 +133,8 @@ _sig = {
     "he_batch_mul_rotate": (c_int, [c_void_p, _P(he_ct), _P(he_ct), _P(c_int32), c_int, c_void_p, c_int,
                                     _P(he_ct)]),
     "he_batch_submit": (c_int, [c_void_p, _P(he_op), c_int, c_void_p, c_int]),
+    "he_lr_grad_step_multi": (c_int, [c_void_p, _P(he_lr_request), c_int, c_int, c_int, c_int, c_void_p, c_int]),
+    "he_lr_grad_step_multi_bytes": (ctypes.c_size_t, [c_void_p, c_int, c_int, c_int, c_int, c_int]),
     "he_batch_submit_bytes": (ctypes.c_size_t, [c_void_p, _P(he_op), c_int, c_int]),
     "he_lr_margins": (c_int, [c_void_p, _P(he_ct), c_int, _P(he_ct), c_int, c_int, c_int, c_void_p, c_int,
                               _P(he_ct)]),
@@ -545,6 +553,47 @@ class Context:
         if want_g:
             G_out.update(go)
         return W_out, (G_out if want_g else None)
+
+    def lr_grad_step_multi(self, requests, cols, rows, keys, mode=1, layout=LAYOUT_ROWS):
+        """he_lr_grad_step_multi over requests = [dict(Z=, W=, mask=, coef=, eta_over_n=, w_decay=0.0,
+        W_out=None, G_out=None)] (outputs allocated when None; G_out=False: no g); returns [(W', g)]."""
+        n = len(requests)
+        arr = (he_lr_request * n)()
+        keep = []
+        outs = []
+        for a, rq in zip(arr, requests):
+            zs = ct_array(rq["Z"])
+            w, m = rq["W"].struct(), rq["mask"].struct()
+            cf = np.ascontiguousarray(rq["coef"], dtype=np.float64)
+            lo = max(rq["W"].level - 4, 0)
+            Wo = rq.get("W_out") or self.ct_empty(lo)
+            Go = rq.get("G_out")
+            Go = None if Go is False else (Go or self.ct_empty(lo))
+            wo = Wo.struct()
+            go = Go.struct() if Go is not None else None
+            keep += [zs, w, m, cf, wo, go]
+            a.Z = ctypes.cast(zs, POINTER(he_ct))
+            a.n_blocks = len(rq["Z"])
+            a.W = ctypes.pointer(w)
+            a.mask = ctypes.pointer(m)
+            a.coef = _f64p(cf)
+            a.eta_over_n = rq["eta_over_n"]
+            a.w_decay = rq.get("w_decay", 0.0)
+            a.W_out = ctypes.pointer(wo)
+            a.G_out = ctypes.pointer(go) if go is not None else None
+            outs.append((Wo, wo, Go, go))
+        _chk(_lib.he_lr_grad_step_multi(self.h, arr, n, cols, rows, layout, keys.handle, mode),
+             "he_lr_grad_step_multi")
+        res = []
+        for Wo, wo, Go, go in outs:
+            Wo.update(wo)
+            if Go is not None:
+                Go.update(go)
+            res.append((Wo, Go))
+        return res
+
+    def step_multi_bytes(self, level, max_blocks, n_req, layout=LAYOUT_ROWS, mode=1):
+        return int(_lib.he_lr_grad_step_multi_bytes(self.h, level, max_blocks, n_req, layout, mode))
 
     def lr_data_terms(self, Z, w_level, w_scale, coef, eta_over_n, w_decay=0.0, layout=LAYOUT_ROWS):
         """he_lr_data_terms: RS(k3 Z), RS(k1 Z) (and RS(k2 Z) when coef[2] != 0)
