@@ -13,13 +13,16 @@ share one key set (a key set is valid for every context of its parameter
 set).  The loop runs on the host:
 - move the requests whose arrival time has passed into their ring's queue;
 - admit: for each ring degree, while a lane is free, the oldest queued request
-  leads the next launch.  An inference leader takes along the queued
-  inferences of the same (N, c) in arrival order, up to `merge_blocks` blocks
-  in all: they share the served model, so their blocks are staged side by
-  side and their margins are one block-batched call.  A gradient step runs
-  alone (its plan, mask and sums are the request's own).  The launch is
-  admitted when its bytes fit the budget next to the launches in flight
-  (a merged launch sheds its last members until it fits);
+  leads the next launch and takes along the later queued requests of its
+  kind and (N, c) (gradient steps: also of its packing) in arrival order, up
+  to `merge_blocks` blocks and 16 requests in all.  Merged inferences share
+  the served model, so their blocks are staged side by side and their
+  margins are one block-batched call.  Merged gradient steps keep their own
+  blocks, weights, masks and eta/n; he_lr_grad_step_multi runs each one's
+  per-block part and then their once-per-step tails together (the tail's
+  key switches are latency-bound, so a batch of them costs about what one
+  does).  The launch is admitted when its bytes fit the budget next to the
+  launches in flight (a merged launch sheds its last members until it fits);
 - poll the lanes' completion events; on completion the launch's staging,
   outputs and workspace go back to the allocator and its bytes to the budget.
 A launch's bytes are what it really allocates: its library workspace
@@ -54,6 +57,7 @@ N_RANGE = (512, 16384)
 D_RANGE = (16, 512)
 COEF = [0.5, -0.1501204134, 0.0, 0.0015930174]  # the step's loss polynomial
 MERGE_BLOCKS = 256
+MAX_MERGE = 16  # requests per merged launch
 
 Request = collections.namedtuple("Request", "rid arrival kind log_n n d c r nb")
 
@@ -80,22 +84,30 @@ def percentile(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if xs else float("nan")
 
 
-def take_batch(queue, merge_blocks):
-    """The launch the queue's oldest request leads: itself, and for an
-    inference the later queued inferences of the same feature width in
-    arrival order while the blocks stay within merge_blocks."""
+def same_width(q):
+    return (q.kind, q.c)
+
+
+def take_batch(queue, merge_blocks, merge_key=same_width, max_requests=MAX_MERGE):
+    """The launch the queue's oldest request leads: itself and the later
+    queued requests with its merge key (kind and feature width; the backend
+    adds the packing of gradient steps), in arrival order, while the blocks
+    stay within merge_blocks and the requests within max_requests."""
     head = queue[0]
     batch = [head]
-    if merge_blocks and head.kind == "infer":
-        total = head.nb
+    if merge_blocks:
+        key, total = merge_key(head), head.nb
         for q in itertools.islice(queue, 1, None):
-            if q.kind == "infer" and q.c == head.c and total + q.nb <= merge_blocks:
+            if len(batch) >= max_requests:
+                break
+            if merge_key(q) == key and total + q.nb <= merge_blocks:
                 batch.append(q)
                 total += q.nb
     return batch
 
 
-def run_loop(requests, backend, lanes_per_n, budget, merge_blocks=0, clock=time.perf_counter, idle=2e-4):
+def run_loop(requests, backend, lanes_per_n, budget, merge_blocks=0, clock=time.perf_counter, idle=2e-4,
+             merge_key=same_width):
     """The continuous-batching loop over a backend with
     bytes(batch) / launch(lane, batch) -> handle / done(handle) -> bool /
     finish(handle, batch).  Returns per-request (admit, complete) times
@@ -119,7 +131,7 @@ def run_loop(requests, backend, lanes_per_n, budget, merge_blocks=0, clock=time.
         progressed = False
         for k, qu in queues.items():
             while qu and free[k]:
-                batch = take_batch(qu, merge_blocks)
+                batch = take_batch(qu, merge_blocks, merge_key)
                 b = backend.bytes(batch)
                 while len(batch) > 1 and in_flight + b > budget:
                     batch.pop()
@@ -177,9 +189,12 @@ def summarise(requests, times, launches=None):
         out[kind + "_p50_ms"] = percentile(lk, 50) * 1e3
         out[kind + "_p99_ms"] = percentile(lk, 99) * 1e3
     if launches is not None:
+        kind = {q.rid: q.kind for q in requests}
         out["launches"] = len(launches)
         out["requests_per_launch"] = len(requests) / max(1, len(launches))
         out["max_requests_per_launch"] = max((len(x) for x in launches), default=0)
+        for k in ("grad", "infer"):
+            out["merged_launches_" + k] = sum(1 for x in launches if len(x) > 1 and kind[x[0]] == k)
     return out
 
 
@@ -260,6 +275,10 @@ class GpuBackend:
                                                  pl["s_mask"])
         torch.cuda.synchronize()
 
+    def merge_key(self, q):
+        """Requests that may share a launch: kind and width, and a step's packing."""
+        return (q.kind, q.c, self.layout.get(q.rid))
+
     def ct_bytes(self, log_n, level):
         return 2 * (level + 1) * (1 << log_n) * 8
 
@@ -269,7 +288,11 @@ class GpuBackend:
         ctx = self.lanes[(q.log_n, 0)]["ctx"]
         L = self.L
         if q.kind == "grad":
-            return ctx.step_bytes(L, q.nb, self.layout[q.rid], self.mode) + 2 * self.ct_bytes(q.log_n, L - 4)
+            lay = self.layout[q.rid]
+            outs = 2 * len(batch) * self.ct_bytes(q.log_n, L - 4)
+            if len(batch) == 1:
+                return ctx.step_bytes(L, q.nb, lay, self.mode) + outs
+            return ctx.step_multi_bytes(L, max(x.nb for x in batch), len(batch), lay, self.mode) + outs
         nb = sum(x.nb for x in batch)
         return ctx.margins_bytes(L, nb, self.mode) + nb * (self.ct_bytes(q.log_n, L) + self.ct_bytes(q.log_n, L - 1))
 
@@ -284,10 +307,18 @@ class GpuBackend:
         if q.kind == "grad":
             lay = self.layout[q.rid]
             pool = self.pools[(q.log_n, q.c, lay)]
-            mask = pool["masks"][q.n if lay == H.LAYOUT_FEATURES else 0]
-            held["W"], held["G"] = ctx.ct_empty(L - 4), ctx.ct_empty(L - 4)
-            ctx.lr_grad_step(pool["Z"][: q.nb], pool["W"], mask, COEF, 1.0 / q.n, q.c, q.r, keys, mode=self.mode,
-                             W_out=held["W"], G_out=held["G"], layout=lay)
+            reqs = []
+            for x in batch:
+                mask = pool["masks"][x.n if lay == H.LAYOUT_FEATURES else 0]
+                held[("W", x.rid)], held[("G", x.rid)] = ctx.ct_empty(L - 4), ctx.ct_empty(L - 4)
+                reqs.append(dict(Z=pool["Z"][: x.nb], W=pool["W"], mask=mask, coef=COEF, eta_over_n=1.0 / x.n,
+                                 W_out=held[("W", x.rid)], G_out=held[("G", x.rid)]))
+            if len(batch) == 1:
+                r0 = reqs[0]
+                ctx.lr_grad_step(r0["Z"], r0["W"], r0["mask"], COEF, r0["eta_over_n"], q.c, q.r, keys,
+                                 mode=self.mode, W_out=r0["W_out"], G_out=r0["G_out"], layout=lay)
+            else:
+                ctx.lr_grad_step_multi(reqs, q.c, q.r, keys, mode=self.mode, layout=lay)
         else:
             pool = self.pools[(q.log_n, q.c, H.LAYOUT_ROWS)]
             nb = sum(x.nb for x in batch)
@@ -317,7 +348,8 @@ class GpuBackend:
         ctx, held = lane["ctx"], h[2]
         if self.keep:
             if batch[0].kind == "grad":
-                self.results[batch[0].rid] = (ctx.download(held["W"]), ctx.download(held["G"]))
+                for x in batch:
+                    self.results[x.rid] = (ctx.download(held[("W", x.rid)]), ctx.download(held[("G", x.rid)]))
             else:
                 off = 0
                 for x in batch:
@@ -360,7 +392,8 @@ def serve(requests, lanes=4, mode=1, budget_frac=0.8, budget=None, keep_results=
     base = be.torch.cuda.memory_allocated()
     be.torch.cuda.reset_peak_memory_stats()
     m0 = be.torch.cuda.memory_stats()
-    times, peak, launches = run_loop(requests, be, lanes_per_n, budget, merge_blocks=merge_blocks)
+    times, peak, launches = run_loop(requests, be, lanes_per_n, budget, merge_blocks=merge_blocks,
+                                     merge_key=be.merge_key)
     m1 = be.torch.cuda.memory_stats()
     stats = summarise(requests, times, launches)
     # the allocator's own work during the loop: device allocations and frees

@@ -77,14 +77,17 @@ def _req(rid, kind, c, nb, log_n=16, t=0.0):
     return SV.Request(rid, t, kind, log_n, nb * ((1 << (log_n - 1)) // c), c, c, (1 << (log_n - 1)) // c, nb)
 
 
-def test_take_batch_merges_same_width_inferences_only():
+def test_take_batch_merges_same_kind_and_width_only():
     from collections import deque
     qu = deque([_req(0, "infer", 64, 10), _req(1, "grad", 64, 5), _req(2, "infer", 128, 5), _req(3, "infer", 64, 20),
-                _req(4, "infer", 64, 30), _req(5, "infer", 64, 1)])
+                _req(4, "infer", 64, 30), _req(5, "infer", 64, 1), _req(6, "grad", 64, 7), _req(7, "grad", 32, 2)])
     assert [q.rid for q in SV.take_batch(qu, 40)] == [0, 3, 5]  # 10 + 20 + 1; 30 more would pass 40
     assert [q.rid for q in SV.take_batch(qu, 0)] == [0]
+    assert [q.rid for q in SV.take_batch(qu, 1000, max_requests=2)] == [0, 3]
     qu.popleft()
-    assert [q.rid for q in SV.take_batch(qu, 1000)] == [1]  # a gradient step runs alone
+    assert [q.rid for q in SV.take_batch(qu, 1000)] == [1, 6]  # gradient steps of one width merge too
+    # a merge key that also tells packings apart (the backend's) keeps them apart
+    assert [q.rid for q in SV.take_batch(qu, 1000, merge_key=lambda q: (q.kind, q.c, q.rid % 2))] == [1]
 
 
 def test_loop_merges_queued_inferences_and_keeps_leaders_in_order():
@@ -97,7 +100,7 @@ def test_loop_merges_queued_inferences_and_keeps_leaders_in_order():
     for x in launches:
         qs = [by[r] for r in x]
         if len(qs) > 1:
-            assert all(q.kind == "infer" and q.c == qs[0].c for q in qs) and sum(q.nb for q in qs) <= 24
+            assert all(q.kind == qs[0].kind and q.c == qs[0].c for q in qs) and sum(q.nb for q in qs) <= 24
             assert [q.rid for q in qs] == sorted(q.rid for q in qs)
         assert len({times[q.rid][0] for q in qs}) == 1 and len({times[q.rid][1] for q in qs}) == 1
     # leaders (the oldest queued request when admitted) go in arrival order, and
@@ -128,7 +131,7 @@ def test_serving_results_identical_alone_and_in_the_mix():
     # overlap: some launch was admitted before an earlier one had completed
     ordered = sorted(reqs, key=lambda q: times[q.rid][0])
     assert any(times[b.rid][0] < times[a.rid][1] for a, b in zip(ordered, ordered[1:]))
-    assert stats["max_requests_per_launch"] > 1  # inferences were merged
+    assert stats["merged_launches_grad"] > 0 and stats["merged_launches_infer"] > 0  # both kinds merged
     assert stats["feature_major_steps"] > 0
     # what the loop allocated stayed within its budget (allocator rounding aside)
     assert stats["peak_bytes_allocated"] <= stats["budget_bytes"] + (64 << 20)
