@@ -51,7 +51,7 @@ import numpy as np
 from . import he as H
 from . import synth
 
-CHAIN = dict(n_q=8, n_special=2, alpha=2, log_delta=40)  # one step or one inference per request
+CHAIN = dict(n_q=8, n_special=4, alpha=4, log_delta=40)  # one step or one inference per request
 LOG_NS = (15, 16)
 N_RANGE = (512, 16384)
 D_RANGE = (16, 512)
@@ -368,8 +368,9 @@ class GpuBackend:
 def serve(requests, lanes=4, mode=1, budget_frac=0.8, budget=None, keep_results=False, warm=True,
           merge_blocks=MERGE_BLOCKS):
     """Set up the GPU backend for `requests`, warm up (first-call costs: the
-    smallest request of every ring, kind, width and packing once, and one
-    request on every lane), run the loop."""
+    smallest request of every ring, kind, width and packing once, the largest
+    of every ring and kind once, so that the allocator's cache holds blocks
+    of the largest workspace, and one request on every lane), run the loop."""
     be = GpuBackend(requests, lanes, mode=mode, keep_results=keep_results)
     if warm:
         keep, be.keep = be.keep, False
@@ -377,6 +378,11 @@ def serve(requests, lanes=4, mode=1, budget_frac=0.8, budget=None, keep_results=
         for q in sorted(requests, key=lambda q: q.nb):
             first.setdefault((q.log_n, q.kind, q.c, be.layout.get(q.rid)), q)
         runs = [((q.log_n, 0), q) for q in first.values()]
+        for log_n in {q.log_n for q in requests}:
+            for kind in ("grad", "infer"):
+                qs = [q for q in requests if q.log_n == log_n and q.kind == kind]
+                if qs:
+                    runs.append(((log_n, 0), max(qs, key=lambda q: q.nb)))
         for log_n in {q.log_n for q in requests}:
             small = min((q for q in requests if q.log_n == log_n), key=lambda q: q.nb)
             runs += [((log_n, j), small) for j in range(1, lanes)]

@@ -31,7 +31,7 @@ def test_every_declared_symbol_is_exported():
 
 
 @pytest.mark.parametrize("cfg", [(13, 5, 1, 1, 30), (16, 20, 4, 4, 40), (16, 24, 6, 6, 40),
-                                 (14, 21, 4, 4, 40), (15, 8, 2, 2, 40)])
+                                 (14, 21, 4, 4, 40), (15, 8, 2, 2, 40), (15, 8, 4, 4, 40)])
 def test_prime_chain_matches_oracle(cfg):
     assert H.params_primes(*cfg) == O.Params(*cfg).q
 

@@ -15,7 +15,7 @@ from paper_2006_10091_amd import he as H  # noqa: E402
 from paper_2006_10091_amd import synth  # noqa: E402
 
 SMALL40 = (13, 5, 2, 2, 40)
-SERVE = (15, 8, 2, 2, 40)
+SERVE = (15, 8, 4, 4, 40)  # the serving chain (paper_2006_10091_amd.serve.CHAIN)
 COEF = [0.5, -0.1501204134, 0.0, 0.0015930174]
 
 

@@ -158,7 +158,7 @@ def test_serving_results_identical_alone_and_in_the_mix():
 @pytest.mark.gpu
 @pytest.mark.parametrize("layout", ["rows", "features"])
 def test_serving_chain_step_and_margins_bit_exact(layout):
-    """The serving parameters (8 + 2 primes, two-prime digits, N = 2^15): one
+    """The serving parameters (8 + 4 primes, four-prime digits, N = 2^15): one
     gradient step in the packing a serving lane picks for it (row-major, or
     feature-major where the plan allows it) and one margins call, bit for bit
     against the oracle."""
