@@ -130,6 +130,44 @@ class Schedule:
                 self.W = self.ps.refresh(self.W)
 
 
+def trace_period(torch, ctx, wk, ps, d):
+    """One refresh period of the schedule (REFRESH_EVERY steps and the
+    refresh) in the batched form with every launch bracketed by HIP events on
+    the context's stream (he_ctx_trace): per kernel kind, launches, time and
+    the algorithmic bytes and modular products the library records for each
+    launch.  Run after the timed region; the events add a few microseconds per
+    launch, so the period's own time is that of the untraced runs."""
+    sched = Schedule(wk, ps, np.zeros(d))
+    sched.iterate(REFRESH_EVERY)
+    torch.cuda.synchronize()
+    ctx.trace(True)
+    t0 = time.perf_counter()
+    sched.iterate(REFRESH_EVERY)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.trace(False)
+    return {"steps": REFRESH_EVERY, "wall_ms_traced": wall * 1e3, "stats": ctx.trace_read()}
+
+
+def kernel_table(tr, peak_fp, peak_int):
+    """Per kernel kind of a traced period: share of kernel time, algorithmic
+    GB/s against the HBM peak, and the modular products' time at the measured
+    butterfly rates (one product = one butterfly) over the kernel time."""
+    tot = sum(st["ms"] for st in tr["stats"])
+    rows = []
+    for st in sorted(tr["stats"], key=lambda x: -x["ms"]):
+        t = st["ms"] * 1e-3
+        row = {"kernel": st["name"], "launches": st["launches"], "ms": st["ms"], "share": st["ms"] / tot,
+               "avg_us": st["ms"] * 1e3 / st["launches"]}
+        if st["bytes"] > 0 and t > 0:
+            row["gbs"] = st["bytes"] / t / 1e9
+            row["frac_hbm"] = row["gbs"] / HBM_PEAK_GBS
+        if st["mm_fp64"] + st["mm_int"] > 0 and t > 0:
+            row["frac_valu"] = (st["mm_fp64"] / peak_fp + st["mm_int"] / peak_int) / t
+        rows.append(row)
+    return {"steps": tr["steps"], "wall_ms_traced": tr["wall_ms_traced"], "kernel_ms": tot, "rows": rows}
+
+
 def measure_copy_and_ntt(torch, ctx, ev, nb):
     """HBM copy rate, then the forward and inverse NTT over the step's
     key-switching digit batch (nb blocks x dnum digits x (L+1+k) limbs), each
@@ -344,6 +382,8 @@ def bench_layout(torch, H, T, ctx, keys, X, y, coef, layout, args, Wk):
             res["ms_per_step"] = dt / steps * 1e3
         log("%s, %s: schedule %.2f ms/step (%d steps); top-level step %.2f ms" % (
             name, key, dt / steps * 1e3, steps, res["top_level_step_ms_" + key]))
+    if layout == H.LAYOUT_FEATURES:
+        res["trace"] = trace_period(torch, ctx, workers[1], ps, d)
     res["batched_over_plain"] = res["steps_per_s_graph"] / res["steps_per_s_plain"]
     del workers, Zrot
     if args.e2e_steps > 0:
@@ -453,6 +493,13 @@ def main():
     valu_frac = t_valu / t_fwd
     log("VALU peak: %.1f G butterflies/s (FP64 lazy), %.1f G/s (64-bit Shoup); forward NTT at %.2f of it" % (
         peak_fp / 1e9, peak_int / 1e9, valu_frac))
+    kernels = None
+    if "trace" in best:
+        kernels = kernel_table(best.pop("trace"), peak_fp, peak_int)
+        for row in kernels["rows"][:8]:
+            log("  %-50s %4d launches %8.2f ms %5.1f%%  %s" % (
+                row["kernel"], row["launches"], row["ms"], 100 * row["share"],
+                " ".join("%s %.3f" % (k, row[k]) for k in ("frac_hbm", "frac_valu") if k in row)))
     ops = measure_ops(torch, H, synth, ctx, ev, nb, c, r, max(args.baby, 1))
     sweep = ntt_sweep(torch, H, ev)
 
@@ -493,6 +540,7 @@ def main():
                      "kernel": "ntt (forward, two passes) over %d limbs of N=2^16" % nlimb,
                      "valu_frac": valu_frac, "valu_peak_bfly_per_s": {"fp64_lazy": peak_fp, "int64_shoup": peak_int}},
         "ops": ops,
+        "kernels": kernels,
         "ntt_tuning": ctx.ntt_tuned,
     }
     if not args.no_cpu:

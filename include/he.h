@@ -629,6 +629,51 @@ he_status he_ntt(he_ctx *ctx, uint64_t *data, int n_limbs, int prime_idx0, int p
  * butterflies per limb times limbs per second over this rate.  HE_EINVAL. */
 he_status he_valu_peak(he_ctx *ctx, int prime_idx, int fp64, double *bfly_per_s);
 
+/* ---------------------------------------------------------------- kernel trace (measurement) */
+
+/* Kernel kinds of the trace.  The NTT's two passes are kept apart by their
+ * fused prologue or epilogue: MD_CONV is a forward column pass whose prologue
+ * forms a ModDown or rescale conversion (Sec. 3's ModDown and rescale),
+ * MD_FINISH the row pass storing (base + acc - conversion) P^-1; KS_COLS and
+ * KS_ROWS are the key switch's digit transform and the row pass fused with
+ * the key inner product. */
+enum {
+    HE_K_NTT_FWD_COLS = 0, HE_K_NTT_FWD_ROWS, HE_K_NTT_INV_ROWS, HE_K_NTT_INV_COLS, HE_K_NTT_ONE_LAUNCH,
+    HE_K_MD_CONV, HE_K_MD_FINISH, HE_K_MD_LAST, HE_K_KS_COLS, HE_K_KS_ROWS, HE_K_MODUP,
+    HE_K_GIANT_FP64, HE_K_GIANT_INT, HE_K_ROT_INNER, HE_K_BABY_SUM, HE_K_TERMS_SUM, HE_K_TENSOR,
+    HE_K_ELEMENTWISE, HE_K_AUTOMORPH, HE_K_OTHER, HE_K_COUNT
+};
+
+/* One kernel kind's launches since the trace was switched on. */
+typedef struct {
+    int kind;          /* HE_K_* */
+    int launches;
+    double ms;         /* summed HIP-event time of its launches */
+    double bytes;      /* summed algorithmic bytes: each operand of a launch
+                        * read or written once (intermediates a fused pass
+                        * consumes count as its operands) */
+    double mm_fp64;    /* modular products (butterflies count one each) at
+                        * primes below 2^46, done in FP64 */
+    double mm_int;     /* the same at wider primes (64-bit integer forms) */
+} he_kernel_stat;
+
+/* on != 0: from now on every launch of the context (outside graph capture,
+ * where nothing is recorded) is bracketed by two HIP events on the
+ * context's stream and recorded with its kind and work; earlier records are
+ * dropped.  on = 0: recording stops (records are kept for he_ctx_trace_read).
+ * The events add a few microseconds per launch: the trace is for
+ * measurement runs, not for timing the whole.  HE_EINVAL. */
+he_status he_ctx_trace(he_ctx *ctx, int on);
+
+/* Synchronises the context's stream, sums the records per kind into out
+ * (caller's host array of max entries; kinds with no launch are left out,
+ * in kind order) and clears them; *n = the entries written.  HE_EDEVICE when
+ * an event failed while recording; HE_EINVAL. */
+he_status he_ctx_trace_read(he_ctx *ctx, he_kernel_stat *out, int max, int *n);
+
+/* Name of a kernel kind ("?" when out of range). */
+const char *he_kernel_kind_name(int kind);
+
 const char *he_strerror(he_status s);
 
 #ifdef __cplusplus

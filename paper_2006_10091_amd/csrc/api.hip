@@ -1250,6 +1250,11 @@ he_status he_ctx_destroy(he_ctx *c)
     }
     if (c->sub_host) (void)hipHostFree(c->sub_host);
     for (he_keys *k : c->keys_made) k->ctx = nullptr;  // released later, they no longer reach this context
+    for (const KRec &r : c->kt.recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : c->kt.pool) (void)hipEventDestroy(e);
     delete c;
     return HE_OK;
 }
@@ -2376,10 +2381,16 @@ static he_status submit_impl(he_ctx *c, const he_op *ops, const SubmitPlan &pl, 
 {
     const long long N = c->N;
     const hek::OpDesc *tab = (const hek::OpDesc *)c->ws;
+    auto limbs = [&](int i0, int n) {
+        double s = 0.0;
+        for (int i = i0; i < i0 + n; ++i) s += ly.tab[i].limbs;
+        return s;
+    };
+    const int o_in = ly.n_tensor, o_add = o_in + ly.n_in, o_out = o_add + ly.n_add;
     // elementwise phases over every operation of every level: one launch each
-    hek::desc_ew(c, 6, tab, ly.n_tensor, ly.max_limbs);
-    hek::desc_ew(c, 4, tab + ly.n_tensor, ly.n_in, ly.max_limbs);
-    hek::desc_ew(c, 0, tab + ly.n_tensor + ly.n_in, ly.n_add, ly.max_limbs);
+    hek::desc_ew(c, 6, tab, ly.n_tensor, ly.max_limbs, limbs(0, ly.n_tensor));
+    hek::desc_ew(c, 4, tab + o_in, ly.n_in, ly.max_limbs, limbs(o_in, ly.n_in));
+    hek::desc_ew(c, 0, tab + o_add, ly.n_add, ly.max_limbs, limbs(o_add, ly.n_add));
     Arena ar = arena(c);
     ar.off = scratch_off;
     const int rchunk = std::min(pl.chunk, hek::HE_MAXMULTI);
@@ -2425,7 +2436,7 @@ static he_status submit_impl(he_ctx *c, const he_op *ops, const SubmitPlan &pl, 
         }
     }
     // every result to its out: one launch
-    hek::desc_ew(c, 4, tab + ly.n_tensor + ly.n_in + ly.n_add, ly.n_out, ly.max_limbs);
+    hek::desc_ew(c, 4, tab + o_out, ly.n_out, ly.max_limbs, limbs(o_out, ly.n_out));
     return last_error();
 }
 
@@ -2793,6 +2804,63 @@ he_status he_lr_margins(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W,
         out[b].scale = so;
     }
     return last_error();
+}
+
+// ---------------------------------------------------------------- kernel trace
+
+he_status he_ctx_trace(he_ctx *c, int on)
+{
+    if (!c || c->capturing) return HE_EINVAL;
+    if (on) {
+        for (const KRec &r : c->kt.recs) {
+            c->kt.pool.push_back(r.a);
+            c->kt.pool.push_back(r.b);
+        }
+        c->kt.recs.clear();
+        c->kt.failed = false;
+    }
+    c->kt.on = on != 0;
+    return HE_OK;
+}
+
+he_status he_ctx_trace_read(he_ctx *c, he_kernel_stat *out, int max, int *n)
+{
+    if (!c || !n || max < 0 || (max > 0 && !out)) return HE_EINVAL;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    he_kernel_stat acc[HE_K_COUNT];
+    for (int k = 0; k < HE_K_COUNT; ++k) acc[k] = he_kernel_stat{k, 0, 0.0, 0.0, 0.0, 0.0};
+    bool failed = c->kt.failed;
+    for (const KRec &r : c->kt.recs) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) failed = true;
+        he_kernel_stat &a = acc[r.kind >= 0 && r.kind < HE_K_COUNT ? r.kind : HE_K_OTHER];
+        a.launches += 1;
+        a.ms += ms;
+        a.bytes += r.bytes;
+        a.mm_fp64 += r.mm_fp;
+        a.mm_int += r.mm_int;
+        c->kt.pool.push_back(r.a);
+        c->kt.pool.push_back(r.b);
+    }
+    c->kt.recs.clear();
+    c->kt.failed = false;
+    int w = 0;
+    for (int k = 0; k < HE_K_COUNT && w < max; ++k)
+        if (acc[k].launches) out[w++] = acc[k];
+    *n = w;
+    return failed ? HE_EDEVICE : HE_OK;
+}
+
+const char *he_kernel_kind_name(int kind)
+{
+    static const char *names[HE_K_COUNT] = {
+        "ntt forward column pass", "ntt forward row pass", "ntt inverse row pass", "ntt inverse column pass",
+        "ntt, both passes in one launch", "moddown/rescale conversion + forward column pass",
+        "forward row pass + moddown/rescale finish", "moddown last limb", "key-switch digits' column pass",
+        "key-switch row pass + key inner product", "modup conversion", "hoisted rotation sum, FP64 positions",
+        "hoisted rotation sum, 60-bit positions", "rotation inner products (shared modup)", "baby-step products",
+        "gradient terms sum", "tensor product", "elementwise", "automorphism", "other"};
+    return kind >= 0 && kind < HE_K_COUNT ? names[kind] : "?";
 }
 
 he_status he_valu_peak(he_ctx *c, int prime_idx, int fp64, double *bfly_per_s)

@@ -74,6 +74,20 @@ struct PersistCfg {
     u64 *limb_scratch = nullptr;  // [limb_wgs][N]
 };
 
+// Kernel trace (he_ctx_trace): one record per launch outside capture, its
+// events on the context's stream; events are reused once read
+struct KRec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes, mm_fp, mm_int;
+};
+struct KTrace {
+    bool on = false;
+    bool failed = false;  // an event call failed while recording
+    std::vector<KRec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -107,6 +121,7 @@ struct he_ctx {
     // key sets this context made and that are not yet released: their
     // back-pointer is cleared when the context goes first
     std::set<he_keys *> keys_made;
+    KTrace kt;
 };
 
 struct he_keys {
@@ -206,8 +221,9 @@ struct OpDesc {
 // op 0: o = x + y (two components); 2: o = k x (two components); 3: o = x y
 // with y one plaintext [limbs][N] (both components); 4: o = x (two
 // components); 6: the tensor o[3] = (x0 y0, x0 y1 + x1 y0, x1 y1).  One launch
-// over n table entries.
-void desc_ew(he_ctx *c, int op, const OpDesc *tab, int n, int max_limbs);
+// over n table entries; limbs: the entries' limbs summed (for the kernel
+// trace; negative: n * max_limbs).
+void desc_ew(he_ctx *c, int op, const OpDesc *tab, int n, int max_limbs, double limbs = -1.0);
 struct EntryKeys {
     const u64 *k[HE_MAXMULTI];
 };

@@ -2473,6 +2473,78 @@ namespace hek {
 // into cache-sized chunks costs more in kernel boundaries than it saves.
 constexpr long long NTT_CHUNK_BYTES = 1ll << 40;
 
+// ------------------------------------------------------------------ kernel trace
+// A launch's record while the context's trace is on (never under capture):
+// an event before the launch on the context's stream, one after it (at the
+// end of the scope), and the launch's algorithmic work.
+struct KSpan {
+    he_ctx *c;
+    long idx = -1;
+    KSpan(he_ctx *cx, int kind, double bytes, double mm_fp = 0.0, double mm_int = 0.0) : c(cx)
+    {
+        KTrace &t = c->kt;
+        if (!t.on || c->capturing) return;
+        hipEvent_t e[2];
+        for (hipEvent_t &x : e) {
+            if (!t.pool.empty()) {
+                x = t.pool.back();
+                t.pool.pop_back();
+            } else if (hipEventCreate(&x) != hipSuccess) {
+                t.failed = true;
+                return;
+            }
+        }
+        if (hipEventRecord(e[0], c->stream) != hipSuccess) t.failed = true;
+        t.recs.push_back(KRec{kind, e[0], e[1], bytes, mm_fp, mm_int});
+        idx = (long)t.recs.size() - 1;
+    }
+    ~KSpan()
+    {
+        if (idx >= 0 && hipEventRecord(c->kt.recs[idx].b, c->stream) != hipSuccess) c->kt.failed = true;
+    }
+    KSpan(const KSpan &) = delete;
+    KSpan &operator=(const KSpan &) = delete;
+};
+
+// positions [pos0, pos0 + npos) of the basis at level ell (q_0..q_ell, then
+// the special primes) whose prime is below 2^46 (FP64 arithmetic)
+static int fp_pos(const he_ctx *c, int ell, int pos0, int npos)
+{
+    int n = 0;
+    for (int t = pos0; t < pos0 + npos; ++t) {
+        const int p = t <= ell ? t : c->nq + t - ell - 1;
+        if (p >= 0 && p < c->np && c->q[p] < (1ull << 46)) ++n;
+    }
+    return n;
+}
+
+// limbs that nzc batch x component entries (from a.zoff) of a transform over
+// npos positions take, and the FP64 ones among them (skip_digit: component c
+// leaves out the positions of digit c)
+static void ntt_limbs(const he_ctx *c, const NttArgs &a, int npos, int nzc, double *limbs, double *fpl)
+{
+    *limbs = *fpl = 0.0;
+    if (!c->kt.on || c->capturing) return;  // only a recorded launch needs them
+    const int f = fp_pos(c, a.ell, a.pos0, npos);
+    double l = 0.0, fl = 0.0;
+    for (int z = 0; z < nzc; ++z) {
+        int ns = 0, nsf = 0;
+        if (a.skip_digit) {
+            const int comp = (a.zoff + z) % a.ncomp;
+            const int s0 = std::max(comp * a.alpha, a.pos0);
+            const int s1 = std::min(std::min(comp * a.alpha + a.alpha, a.ell + 1), a.pos0 + npos);
+            if (s1 > s0) {
+                ns = s1 - s0;
+                nsf = fp_pos(c, a.ell, s0, ns);
+            }
+        }
+        l += npos - ns;
+        fl += f - nsf;
+    }
+    *limbs = l;
+    *fpl = fl;
+}
+
 // ------------------------------------------------------------------ VALU roofline of the butterflies
 // The NTT's two butterfly forms with operands in registers and no memory
 // traffic: FP = 1 the signed lazy FP64 form (primes below 2^46), FP = 0 the
@@ -2749,6 +2821,10 @@ static bool limb_launch(he_ctx *c, const NttArgs &a, int nlimb, int npos, int di
         return false;
     } else {
         const int grid = std::min(nlimb, std::min(8 * c->persist.wg_per_xcd, c->persist.limb_wgs));
+        double l, fl;
+        ntt_limbs(c, a, npos, nlimb / npos, &l, &fl);
+        const double bf = (double)(1 << (LOGN - 1)) * LOGN;
+        KSpan ks(c, HE_K_NTT_ONE_LAUNCH, 2.0 * l * (8 << LOGN), fl * bf, (l - fl) * bf);
         if (dir > 0)
             ntt_limb_t<LOGN, false, G><<<grid, 256 * G, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh,
                                                                         nullptr, c->t.psi_d,
@@ -2785,6 +2861,10 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
         a.zoff = 0;
         persist_reset_kernel<<<1, 256, 0, c->stream>>>(ps.ctr, PS_FLAG);  // counters (the flag word stays raised)
         const dim3 grid(8 * c->persist.wg_per_xcd);
+        double l, fl;
+        ntt_limbs(c, a, npos, nz, &l, &fl);
+        const double bf = (double)(1 << (LOGN - 1)) * LOGN;
+        KSpan ks(c, HE_K_NTT_ONE_LAUNCH, 2.0 * l * (8 << LOGN), fl * bf, (l - fl) * bf);
         if (dir > 0)
             ntt_persist_t<LOGN, false><<<grid, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh,
                                                                             nullptr, c->t.psi_d, ps);
@@ -2804,7 +2884,25 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
         dim3 gc((1 << (LOGN - LA)) / LineShape<LA>::LINES, npos, nzc);
         dim3 gr((1 << LA) / LineShape<LB>::LINES, npos, nzc);
         hipStream_t st = c->stream;
+        // each pass's algorithmic work: its operands once, its butterflies and
+        // the products of its fused prologue / epilogue
+        double l, fl;
+        ntt_limbs(c, a, npos, nzc, &l, &fl);
+        const double L8 = 8.0 * (1 << LOGN), NN = (double)(1 << LOGN), HB = NN / 2;
+        const int nsrc = pro == PRO_MDRS ? f.nsrc + 1 : f.nsrc;
+        const bool conv = dir > 0 && (pro == PRO_MODDOWN || pro == PRO_MDRS);
+        const double pro_b = conv ? (double)nzc * nsrc * L8 + l * L8 : 2.0 * l * L8;
+        const double pro_m = conv ? NN * nsrc : 0.0;
+        double epi_b = 2.0 * l * L8, epi_m = 0.0;
+        if (epi == EPI_FINISH) {
+            epi_b = 3.0 * l * L8;  // intermediate, acc, out
+            if (f.nbase > 0) epi_b += l * L8 * std::min(f.nbase, a.ncomp) / a.ncomp;
+            if (f.add) epi_b += l * L8;
+            epi_m = NN * (1 + (f.post ? 1 : 0) + (f.has_kacc ? 1 : 0));
+        }
         if (dir > 0) {
+            KSpan k1(c, conv ? HE_K_MD_CONV : HE_K_NTT_FWD_COLS, pro_b, fl * (HB * LA + pro_m),
+                     (l - fl) * (HB * LA + pro_m));
             if (pro == PRO_MODDOWN)
                 ntt_cols_t<LOGN, false, PRO_MODDOWN><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh,
                                                                                  nullptr, c->t.psi_d, f);
@@ -2814,6 +2912,10 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
             else
                 ntt_cols_t<LOGN, false, PRO_NONE><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh, nullptr,
                                                                               c->t.psi_d, f);
+        }
+        if (dir > 0) {
+            KSpan k2(c, epi == EPI_FINISH ? HE_K_MD_FINISH : HE_K_NTT_FWD_ROWS, epi_b, fl * (HB * LB + epi_m),
+                     (l - fl) * (HB * LB + epi_m));
             if (epi == EPI_FINISH)
                 ntt_rows_t<LOGN, false, EPI_FINISH><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh,
                                                                                 c->t.psi_d, f);
@@ -2821,12 +2923,18 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
                 ntt_rows_t<LOGN, false, EPI_NONE><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh,
                                                                               c->t.psi_d, f);
         } else {
-            if (pro == PRO_SRC)
-                ntt_rows_t<LOGN, true, PRO_SRC><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.ipsi, c->t.ipsi_sh,
-                                                                            c->t.ipsi_d, f);
-            else
-                ntt_rows_t<LOGN, true, PRO_NONE><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.ipsi, c->t.ipsi_sh,
-                                                                             c->t.ipsi_d, f);
+            {
+                const double km = f.has_kmul ? NN : 0.0;
+                KSpan k1(c, HE_K_NTT_INV_ROWS, 2.0 * l * L8, fl * (HB * LB + km), (l - fl) * (HB * LB + km));
+                if (pro == PRO_SRC)
+                    ntt_rows_t<LOGN, true, PRO_SRC><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.ipsi, c->t.ipsi_sh,
+                                                                                c->t.ipsi_d, f);
+                else
+                    ntt_rows_t<LOGN, true, PRO_NONE><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.ipsi, c->t.ipsi_sh,
+                                                                                 c->t.ipsi_d, f);
+            }
+            const double pm = post ? NN : 0.0;
+            KSpan k2(c, HE_K_NTT_INV_COLS, 2.0 * l * L8, fl * (HB * LA + pm), (l - fl) * (HB * LA + pm));
             ntt_cols_t<LOGN, true, PRO_NONE><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.ipsi, c->t.ipsi_sh, post,
                                                                          c->t.ipsi_d, f);
         }
@@ -2851,6 +2959,7 @@ static void ntt_launch(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, cons
     const int C = std::min(NTT_TILE >> a.logN1, N2);
     const int R = std::min(NTT_TILE / N2, N1);
     dim3 gc(N2 / C, npos, nbatch * a.ncomp), gr(N1 / R, npos, nbatch * a.ncomp);
+    KSpan ks(c, HE_K_OTHER, 0.0);
     if (dir > 0) {
         ntt_cols<false><<<gc, NTT_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh, nullptr);
         ntt_rows<false><<<gr, NTT_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh);
@@ -2909,11 +3018,25 @@ static void ks_fused_t(he_ctx *c, NttArgs a, int B, int beta, int nb, const KsAr
     Fuse f{};
     a.zoff = 0;
     dim3 gc((1 << (LOGN - LA)) / LineShape<LA>::LINES, nb, B * beta);
-    ntt_cols_t<LOGN, false, PRO_NONE><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh,
-                                                                          nullptr, c->t.psi_d, f);
+    // the digits' transformed limbs (each digit's own positions are already
+    // in NTT form and skipped), then the row pass reading them, those own
+    // positions from d2 and the keys, writing acc
+    double l, fl;
+    ntt_limbs(c, a, nb, B * beta, &l, &fl);
+    const double L8 = 8.0 * (1 << LOGN), NN = (double)(1 << LOGN), HB = NN / 2;
+    {
+        KSpan ks(c, HE_K_KS_COLS, 2.0 * l * L8, fl * HB * LA, (l - fl) * HB * LA);
+        ntt_cols_t<LOGN, false, PRO_NONE><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh,
+                                                                              nullptr, c->t.psi_d, f);
+    }
     KsArgs kk = k;
     kk.nent = B;
     dim3 gr(B * ((1 << LA) / LineShape<LB>::LINES) * nb, 1, 1);
+    const double keys = (k.per_entry ? B : 1) * 2.0 * beta * nb;
+    const int fpn = fp_pos(c, k.ell, 0, nb);
+    const double ip = (double)B * NN * 2 * beta;  // inner-product products per position
+    KSpan ks(c, HE_K_KS_ROWS, (l + (double)B * (k.ell + 1) + keys + 2.0 * B * nb) * L8, fl * HB * LB + fpn * ip,
+             (l - fl) * HB * LB + (nb - fpn) * ip);
     ntt_rows_ks_t<LOGN><<<gr, LINE_THREADS, 0, c->stream>>>(kk, c->t.pinfo, c->t.psi, c->t.psi_sh, c->t.psi_d);
 }
 
@@ -3054,6 +3177,15 @@ void intt_last(he_ctx *c, int level, int B, int ncomp, const u64 *in, long long 
 static void ew(he_ctx *c, int op, const EwArgs &a, int npos, int nbatch, i64 k)
 {
     dim3 g(xblocks(c->N), npos, nbatch * a.ncomp);
+    // operands once: x and o per component; y per component (sums), one
+    // plaintext per entry (op 3; once when it is shared), none otherwise
+    const double lim = (double)npos * nbatch * a.ncomp, L8 = 8.0 * c->N;
+    double yl = 0.0;
+    if (op == 0 || op == 1) yl = lim;
+    else if (op == 3) yl = (double)npos * (a.yb ? nbatch : 1);
+    const double fl = (double)fp_pos(c, a.ell, a.pos0, npos) / npos;
+    const double mm = (op == 2 || op == 3) ? lim * c->N : 0.0;
+    KSpan ks(c, HE_K_ELEMENTWISE, (2.0 * lim + yl) * L8, mm * fl, mm * (1.0 - fl));
     switch (op) {
     case 0: ew_kernel<0><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
     case 1: ew_kernel<1><<<g, 256, 0, c->stream>>>(a, c->t.pinfo, k); break;
@@ -3084,13 +3216,22 @@ void tensor_b(he_ctx *c, int level, int B, const u64 *x, long long xb, long long
               long long yc, u64 *o, long long ob, long long oc)
 {
     dim3 g(xblocks(c->N), level + 1, B);
+    const double lim = (double)(level + 1) * B, fl = fp_pos(c, level, 0, level + 1) / (double)(level + 1);
+    KSpan ks(c, HE_K_TENSOR, 7.0 * lim * 8.0 * c->N, 4.0 * lim * c->N * fl, 4.0 * lim * c->N * (1.0 - fl));
     tensor_kernel<<<g, 256, 0, c->stream>>>(x, xb, xc, y, yb, yc, o, ob, oc, c->t.pinfo, c->logN);
 }
 
-void desc_ew(he_ctx *c, int op, const OpDesc *tab, int n, int max_limbs)
+void desc_ew(he_ctx *c, int op, const OpDesc *tab, int n, int max_limbs, double limbs)
 {
     if (n < 1) return;
     dim3 g(xblocks(c->N), max_limbs, n);
+    // operand limbs per entry limb: x, o (two components each; the tensor's
+    // o three), y two (sum, tensor) or one (plaintext)
+    const double per = op == 0 ? 6.0 : op == 3 ? 5.0 : op == 6 ? 7.0 : 4.0;
+    const double mper = op == 2 || op == 3 ? 2.0 : op == 6 ? 4.0 : 0.0;
+    const double lim = limbs >= 0.0 ? limbs : (double)n * max_limbs;
+    const double fl = (double)fp_pos(c, max_limbs - 1, 0, max_limbs) / max_limbs;
+    KSpan ks(c, HE_K_ELEMENTWISE, per * lim * 8.0 * c->N, mper * lim * c->N * fl, mper * lim * c->N * (1.0 - fl));
     switch (op) {
     case 0: desc_ew_kernel<0><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN); break;
     case 2: desc_ew_kernel<2><<<g, 256, 0, c->stream>>>(tab, c->t.pinfo, c->logN); break;
@@ -3106,6 +3247,13 @@ void terms_sum_b(he_ctx *c, int lp, int nb, const u64 *A, const u64 *B3, long lo
 {
     TermArgs a{A, B3, as, Z1, Z2, ps, pc, M, ms, mc, Z, zs, zc, G, k0, nb, accumulate ? 1 : 0, c->logN};
     dim3 g(c->N / 256, lp + 1, 1);
+    // per block: A, B3 (3 components each), Z1, Z (2), Z2 (2, when given), M
+    // (2, per block or shared); G's 5 components written (and read when accumulating)
+    const double per_blk = 10.0 + (Z2 ? 2.0 : 0.0) + (ms ? 2.0 : 0.0);
+    const double lim = (lp + 1.0) * (per_blk * nb + (ms ? 0.0 : 2.0) + (accumulate ? 10.0 : 5.0));
+    const double fl = fp_pos(c, lp, 0, lp + 1) / (lp + 1.0);
+    const double mm = (lp + 1.0) * nb * c->N * (15.0 + (Z2 ? 6.0 : 0.0));
+    KSpan ks(c, HE_K_TERMS_SUM, lim * 8.0 * c->N, mm * fl, mm * (1.0 - fl));
     terms_sum_kernel<<<g, 256, 0, c->stream>>>(a, c->t.pinfo);
 }
 
@@ -3115,6 +3263,12 @@ void baby_sum_b(he_ctx *c, int level, int nblk, int nbaby, const u64 *z, long lo
 {
     BabyArgs a{z, zb, zc, zr, zrb, zrs, zrc, w, wc, wr, wrs, wrc, o, ob, oc, nbaby, nblk, c->logN};
     dim3 g(c->N / 256, level + 1, (nblk + BABY_CHUNK - 1) / BABY_CHUNK);
+    // every block's nbaby data copies (2 components) and W's nbaby rotations
+    // read once, each block's degree-2 product written
+    const double lim = (level + 1.0) * (2.0 * nbaby * nblk + 2.0 * nbaby + 3.0 * nblk);
+    const double fl = fp_pos(c, level, 0, level + 1) / (level + 1.0);
+    const double mm = (level + 1.0) * nblk * nbaby * 4.0 * c->N;
+    KSpan ks(c, HE_K_BABY_SUM, lim * 8.0 * c->N, mm * fl, mm * (1.0 - fl));
     switch (nbaby) {
     case 2: baby_sum_kernel<2><<<g, 256, 0, c->stream>>>(a, c->t.pinfo); break;
     case 4: baby_sum_kernel<4><<<g, 256, 0, c->stream>>>(a, c->t.pinfo); break;
@@ -3127,6 +3281,18 @@ void modup_b(he_ctx *c, int level, int B, const u64 *y, long long ys, u64 *ext, 
 {
     const int beta = (level + 1 + c->alpha - 1) / c->alpha;
     dim3 g((c->N / 2 + 255) / 256, B * beta, 1);
+    // y read once, every digit's positions outside it written; digit j of
+    // alpha_j members takes alpha_j products per target
+    const int nb = level + 1 + c->nk;
+    double mf = 0.0, mi = 0.0;
+    for (int j = 0; j < beta; ++j) {
+        const int j0 = j * c->alpha, aj = std::min(c->alpha, level + 1 - j0);
+        const int f = fp_pos(c, level, 0, nb) - fp_pos(c, level, j0, aj);
+        mf += (double)aj * f;
+        mi += (double)aj * (nb - aj - f);
+    }
+    KSpan ks(c, HE_K_MODUP, (double)B * ((level + 1) + (double)beta * nb - (level + 1)) * 8.0 * c->N,
+             mf * B * c->N, mi * B * c->N);
 #define HE_MODUP(A)                                                                                                     \
     modup_kernel<A><<<g, 256, 0, c->stream>>>(y, ys, ext, es, ds, c->t.pinfo, c->t.up_conv, c->t.up_qd, c->t.up_convd, \
                                               c->t.up_qdd, c->t.qinv_d, level, c->alpha, c->nq, c->np, c->nk, beta,     \
@@ -3151,6 +3317,10 @@ void ks_inner_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s, const
 {
     const int beta = (level + 1 + c->alpha - 1) / c->alpha;
     dim3 g(xblocks(c->N, 2), level + 1 + c->nk, 1);
+    const int nb = level + 1 + c->nk, f = fp_pos(c, level, 0, nb);
+    const double ip = (double)B * c->N * 2 * beta;
+    KSpan ks(c, HE_K_OTHER, ((double)B * beta * nb + 2.0 * beta * nb + 2.0 * B * nb) * 8.0 * c->N, f * ip,
+             (nb - f) * ip);
     ks_inner_kernel<<<g, 256, 0, c->stream>>>(d2, d2s, ext, es, ds, key, acc, as, c->t.pinfo, B, level, c->alpha,
                                               c->nq, c->np, beta, c->logN);
 }
@@ -3160,6 +3330,9 @@ void ks_inner_multi_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s,
 {
     const int beta = (level + 1 + c->alpha - 1) / c->alpha;
     dim3 g(xblocks(c->N, 2), level + 1 + c->nk, B);
+    const int nb = level + 1 + c->nk, f = fp_pos(c, level, 0, nb);
+    const double ip = (double)B * c->N * 2 * beta;
+    KSpan ks(c, HE_K_OTHER, ((double)B * beta * nb * 3.0 + 2.0 * B * nb) * 8.0 * c->N, f * ip, (nb - f) * ip);
     ks_inner_multi_kernel<<<g, 256, 0, c->stream>>>(d2, d2s, ext, es, ds, keys, acc, as, c->t.pinfo, level,
                                                     c->alpha, c->nq, c->np, beta, c->logN);
 }
@@ -3167,6 +3340,7 @@ void ks_inner_multi_b(he_ctx *c, int level, int B, const u64 *d2, long long d2s,
 void moddown_conv_b(he_ctx *c, int level, int B, const u64 *acc, long long as, u64 *conv, long long cs)
 {
     dim3 g((c->N + 255) / 256, B * 2, 1);
+    KSpan ks(c, HE_K_OTHER, 2.0 * B * (c->nk + level + 1.0) * 8.0 * c->N);
     moddown_conv_kernel<<<g, 256, 0, c->stream>>>(acc, as, conv, cs, c->t.pinfo, c->t.dn_conv, c->t.dn_p, level,
                                                   c->nq, c->nk, c->logN);
 }
@@ -3176,6 +3350,8 @@ void moddown_finish_b(he_ctx *c, int level, int B, const u64 *acc, long long as,
                       long long ocs, const u64 *add, long long ads, long long adcs)
 {
     dim3 g(xblocks(c->N), level + 1, B * 2);
+    KSpan ks(c, HE_K_OTHER, 2.0 * B * (level + 1.0) * (3.0 + (nbase > 0 ? nbase / 2.0 : 0.0) + (add ? 1.0 : 0.0)) *
+                                8.0 * c->N);
     moddown_finish_kernel<<<g, 256, 0, c->stream>>>(acc, as, conv, cs, base, bs, bcs, nbase, out, os, ocs, add, ads,
                                                     adcs, c->t.pinfo, c->t.dn_pinv, level, c->nk, c->logN);
 }
@@ -3183,6 +3359,7 @@ void moddown_finish_b(he_ctx *c, int level, int B, const u64 *acc, long long as,
 void rescale_bcast_b(he_ctx *c, int level, int B, const u64 *lastc, u64 *tmp, int ncomp)
 {
     dim3 g(xblocks(c->N), level, B * ncomp);
+    KSpan ks(c, HE_K_OTHER, (double)B * ncomp * (1.0 + level) * 8.0 * c->N);
     rescale_bcast_kernel<<<g, 256, 0, c->stream>>>(lastc, tmp, c->t.pinfo, c->t.rs_ql, level, c->nq, c->logN);
 }
 
@@ -3190,6 +3367,7 @@ void rescale_finish_b(he_ctx *c, int level, int B, const u64 *in, long long is, 
                       long long os, int ncomp)
 {
     dim3 g(xblocks(c->N, 1), B, 1);
+    KSpan ks(c, HE_K_OTHER, 3.0 * B * ncomp * level * 8.0 * c->N);
     rescale_finish_kernel<<<g, 256, 0, c->stream>>>(in, is, tmp, out, os, c->t.pinfo, c->t.rs_qinv, level, c->nq,
                                                     c->logN, ncomp);
 }
@@ -3198,7 +3376,27 @@ void automorph_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, long lon
                  long long oc, u64 g)
 {
     dim3 gr(xblocks(c->N), nl, B * 2);
+    KSpan ks(c, HE_K_AUTOMORPH, 4.0 * B * nl * 8.0 * c->N);
     automorph_kernel<<<gr, 256, 0, c->stream>>>(in, ib, ic, out, ob, oc, g, c->logN);
+}
+
+// the hoisted sum's algorithmic work over the positions whose prime is (fp)
+// or is not below 2^46: per position, every entry's beta digits read once,
+// the ng keys' beta digits of both components once, the two accumulator
+// components written; on q_0..q_l also the input's b part read and the
+// base's two components written (the digit at the position's own digit is
+// the input's a part, counted with the digits)
+static void giant_work(const he_ctx *c, int level, int B, int ng, bool fp, double *bytes, double *mm)
+{
+    const int beta = (level + 1 + c->alpha - 1) / c->alpha, nb = level + 1 + c->nk;
+    double lim = 0.0, pos = 0.0;
+    for (int t = 0; t < nb; ++t) {
+        if ((fp_pos(c, level, t, 1) == 1) != fp) continue;
+        lim += (double)B * beta + 2.0 * beta * ng + 2.0 * B + (t <= level ? 3.0 * B : 0.0);
+        pos += 1.0;
+    }
+    *bytes = lim * 8.0 * c->N;
+    *mm = pos * B * c->N * ng * beta * 2.0;
 }
 
 static void giant_gather_b(he_ctx *c, int level, int B, const u64 *ext, long long es, long long ds, const u64 *x,
@@ -3229,6 +3427,10 @@ static void giant_gather_b(he_ctx *c, int level, int B, const u64 *ext, long lon
     a.ngroups = (B + GIANT_EPT - 1) / GIANT_EPT;
     a.logN = c->logN;
     const long long nwg = (long long)a.ngroups * (c->N / 256) * a.nb;
+    double bf, mf, bi, mi;
+    giant_work(c, level, B, ng, true, &bf, &mf);
+    giant_work(c, level, B, ng, false, &bi, &mi);
+    KSpan ks(c, HE_K_OTHER, bf + bi, mf, mi);
     giant_gather_kernel<<<dim3((unsigned)nwg, 1, 1), 256, 0, c->stream>>>(a, c->t.pinfo);
 }
 
@@ -3272,12 +3474,20 @@ void giant_sum_b(he_ctx *c, int level, int B, const u64 *ext, long long es, long
     a.acc = acc;
     a.out = out;
     a.nent = B;
+    double bf, mf, bi, mi;
+    giant_work(c, level, B, ng, true, &bf, &mf);
+    giant_work(c, level, B, ng, false, &bi, &mi);
     switch (beta) {
-#define HE_GIANT(BT)                                                                                  \
-    case BT:                                                                                          \
-        giant_perm_kernel<true, BT><<<nwg, GP_TK * GP_LANES, lds, c->stream>>>(a, c->t.pinfo);  \
-        giant_perm_kernel<false, BT><<<nwg, GP_TK * GP_LANES, lds, c->stream>>>(a, c->t.pinfo); \
-        break
+#define HE_GIANT(BT)                                                                                      \
+    case BT: {                                                                                            \
+        {                                                                                                 \
+            KSpan ks(c, HE_K_GIANT_FP64, bf, mf, 0.0);                                                    \
+            giant_perm_kernel<true, BT><<<nwg, GP_TK * GP_LANES, lds, c->stream>>>(a, c->t.pinfo);        \
+        }                                                                                                 \
+        KSpan ks(c, HE_K_GIANT_INT, bi, 0.0, mi);                                                         \
+        giant_perm_kernel<false, BT><<<nwg, GP_TK * GP_LANES, lds, c->stream>>>(a, c->t.pinfo);           \
+        break;                                                                                            \
+    }
         HE_GIANT(1);
         HE_GIANT(2);
         HE_GIANT(3);
@@ -3311,6 +3521,11 @@ void rot_inner_b(he_ctx *c, int level, int n, const u64 *ext, long long ds, cons
     a.nb = level + 1 + c->nk;
     a.logN = c->logN;
     const long long nwg = (long long)n * a.nb * (c->N / 256);
+    // the one input's digits read once, n rotations' keys, n accumulators written
+    const int f = fp_pos(c, level, 0, a.nb);
+    const double ip = (double)n * c->N * 2 * a.beta;
+    KSpan ks(c, HE_K_ROT_INNER, ((double)a.beta * a.nb + n * 2.0 * a.beta * a.nb + n * 2.0 * a.nb) * 8.0 * c->N,
+             f * ip, (a.nb - f) * ip);
     rot_inner_kernel<<<dim3((unsigned)nwg, 1, 1), 256, 0, c->stream>>>(a, c->t.pinfo);
 }
 
@@ -3318,6 +3533,10 @@ void md_last_b(he_ctx *c, int level, int B, const u64 *bl, const u64 *al, const 
                long long acs, u64 *last)
 {
     dim3 g(c->N / 256, B * 2, 1);
+    // per component: base's and acc's limbs l, acc's special limbs, the output limb
+    const double mm = 2.0 * B * c->N * (c->nk + 1.0);
+    const bool fq = c->q[level] < (1ull << 46);
+    KSpan ks(c, HE_K_MD_LAST, 2.0 * B * (3.0 + c->nk) * 8.0 * c->N, fq ? mm : 0.0, fq ? 0.0 : mm);
     md_last_kernel<<<g, 256, 0, c->stream>>>(bl, al, acc, as, acs, last, c->t.pinfo, c->t.dn_conv, c->t.dn_p,
                                             c->t.dn_pinv, level, c->nq, c->nk, c->logN);
 }
@@ -3365,6 +3584,7 @@ void automorph_multi_b(he_ctx *c, int B, int nl, const u64 *in, long long ib, lo
                        long long oc, const EntryGal &gals)
 {
     dim3 gr(xblocks(c->N), nl, B * 2);
+    KSpan ks(c, HE_K_AUTOMORPH, 4.0 * B * nl * 8.0 * c->N);
     automorph_multi_kernel<<<gr, 256, 0, c->stream>>>(in, ib, ic, out, ob, oc, gals, c->logN);
 }
 
@@ -3372,6 +3592,7 @@ void batch_sum(he_ctx *c, int level, int B, const u64 *in, long long ib, long lo
                bool accumulate, int ncomp)
 {
     dim3 g(xblocks(c->N), level + 1, ncomp);
+    KSpan ks(c, HE_K_ELEMENTWISE, (B + (accumulate ? 2.0 : 1.0)) * ncomp * (level + 1.0) * 8.0 * c->N);
     batch_sum_kernel<<<g, 256, 0, c->stream>>>(in, ib, ic, B, out, oc, accumulate ? 1 : 0, c->t.pinfo, c->logN);
 }
 
@@ -3379,6 +3600,7 @@ void sample_uniform(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t
                     const int *prime_of_pos, u64 *out)
 {
     dim3 g(std::max(1, c->N / 4 / 256), n_pos, 1);
+    KSpan ks(c, HE_K_OTHER, ((double)n_pos) * 8.0 * c->N);
     uniform_kernel<<<g, 256, 0, c->stream>>>(seed, type, index, comp_base, make_pp(n_pos, prime_of_pos), c->t.pinfo,
                                              out, c->logN);
 }
@@ -3387,6 +3609,7 @@ void sample_cbd(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t com
                 const int *prime_of_pos, u64 *out)
 {
     dim3 g(std::max(1, c->N / 8 / 256), 1, 1);
+    KSpan ks(c, HE_K_OTHER, ((double)n_pos) * 8.0 * c->N);
     cbd_kernel<<<g, 256, 0, c->stream>>>(seed, type, index, comp, make_pp(n_pos, prime_of_pos), c->t.pinfo, out,
                                          c->logN);
 }
@@ -3394,6 +3617,7 @@ void sample_cbd(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t com
 void int_to_rns(he_ctx *c, const i64 *m, int n_pos, const int *prime_of_pos, u64 *out)
 {
     dim3 g(xblocks(c->N), n_pos, 1);
+    KSpan ks(c, HE_K_OTHER, (1.0 + n_pos) * 8.0 * c->N);
     int_to_rns_kernel<<<g, 256, 0, c->stream>>>(m, make_pp(n_pos, prime_of_pos), c->t.pinfo, out, c->logN);
 }
 
@@ -3401,6 +3625,7 @@ void evk_combine(he_ctx *c, const u64 *a, const u64 *s, const u64 *e, const u64 
 {
     int d0 = digit * c->alpha, d1 = std::min(d0 + c->alpha, c->nq);
     dim3 g(xblocks(c->N), c->np, 1);
+    KSpan ks(c, HE_K_OTHER, (5.0 * c->np) * 8.0 * c->N);
     evk_kernel<<<g, 256, 0, c->stream>>>(a, s, e, sp, c->t.dn_p, c->t.pinfo, d0, d1, b, c->logN);
 }
 
@@ -3432,6 +3657,7 @@ double valu_bfly_rate(he_ctx *c, bool fp, int pidx, u64 *scratch)
 void seeded_a(he_ctx *c, u64 seed, uint32_t index0, int nent, int level, u64 *out, long long os)
 {
     dim3 g(std::max(1, c->N / 4 / 256), level + 1, nent);
+    KSpan ks(c, HE_K_OTHER, ((double)nent * (level + 1)) * 8.0 * c->N);
     seeded_a_kernel<<<g, 256, 0, c->stream>>>(seed, index0, c->t.pinfo, out, os, c->logN);
 }
 
@@ -3439,6 +3665,7 @@ void sample_ternary(he_ctx *c, u64 seed, uint32_t type, uint32_t index, uint32_t
                     const int *prime_of_pos, u64 *out)
 {
     dim3 g(std::max(1, c->N / 8 / 256), 1, 1);
+    KSpan ks(c, HE_K_OTHER, ((double)n_pos) * 8.0 * c->N);
     ternary_kernel<<<g, 256, 0, c->stream>>>(seed, type, index, comp, make_pp(n_pos, prime_of_pos), c->t.pinfo, out,
                                              c->logN);
 }
@@ -3447,18 +3674,21 @@ void encpk_combine(he_ctx *c, int level, const u64 *v, const u64 *pk, const u64 
                    u64 *b, u64 *a)
 {
     dim3 g(xblocks(c->N), level + 1, 1);
+    KSpan ks(c, HE_K_OTHER, (8.0 * (level + 1)) * 8.0 * c->N);
     encpk_kernel<<<g, 256, 0, c->stream>>>(v, pk, (long long)c->nq * c->N, e0, e1, m, c->t.pinfo, b, a, c->logN);
 }
 
 void enc_combine(he_ctx *c, int level, const u64 *a, const u64 *s, const u64 *e, const u64 *m, u64 *b)
 {
     dim3 g(xblocks(c->N), level + 1, 1);
+    KSpan ks(c, HE_K_OTHER, (5.0 * (level + 1)) * 8.0 * c->N);
     enc_kernel<<<g, 256, 0, c->stream>>>(a, s, e, m, c->t.pinfo, b, c->logN);
 }
 
 void dec_combine(he_ctx *c, int level, const u64 *ct, const u64 *s, u64 *out)
 {
     dim3 g(xblocks(c->N), level + 1, 1);
+    KSpan ks(c, HE_K_OTHER, (4.0 * (level + 1)) * 8.0 * c->N);
     dec_kernel<<<g, 256, 0, c->stream>>>(ct, s, c->t.pinfo, out, level, c->logN);
 }
 

@@ -77,6 +77,16 @@ class he_infer_plan(ctypes.Structure):
         [(n, c_double) for n in ("s_u", "s_u2", "s_h", "s_p")] + [(n, c_int64) for n in ("k3", "k2c", "k1", "k0c")]
 
 
+class he_kernel_stat(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("launches", c_int32), ("ms", c_double), ("bytes", c_double),
+                ("mm_fp64", c_double), ("mm_int", c_double)]
+
+
+# kernel kinds of the trace (HE_K_*)
+(K_NTT_FWD_COLS, K_NTT_FWD_ROWS, K_NTT_INV_ROWS, K_NTT_INV_COLS, K_NTT_ONE_LAUNCH, K_MD_CONV, K_MD_FINISH,
+ K_MD_LAST, K_KS_COLS, K_KS_ROWS, K_MODUP, K_GIANT_FP64, K_GIANT_INT, K_ROT_INNER, K_BABY_SUM, K_TERMS_SUM,
+ K_TENSOR, K_ELEMENTWISE, K_AUTOMORPH, K_OTHER, K_COUNT) = range(21)
+
 LAYOUT_ROWS, LAYOUT_FEATURES = 0, 1  # HE_LAYOUT_ROWS / HE_LAYOUT_FEATURES
 NOALLOC_SCRATCH_BYTES = 64 << 20  # HE_NOALLOC_SCRATCH_BYTES
 
@@ -146,6 +156,9 @@ _sig = {
     "he_lr_margins_bytes": (c_size_t, [c_void_p, c_int, c_int, c_int]),
     "he_ntt": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int]),
     "he_valu_peak": (c_int, [c_void_p, c_int, c_int, _P(c_double)]),
+    "he_ctx_trace": (c_int, [c_void_p, c_int]),
+    "he_ctx_trace_read": (c_int, [c_void_p, _P(he_kernel_stat), c_int, _P(c_int)]),
+    "he_kernel_kind_name": (ctypes.c_char_p, [c_int]),
 }
 for _n, (_r, _a) in _sig.items():
     _f = getattr(_lib, _n)
@@ -730,6 +743,19 @@ class Context:
         v = c_double()
         _chk(_lib.he_valu_peak(self.h, prime_idx, 1 if fp64 else 0, ctypes.byref(v)), "he_valu_peak")
         return v.value
+
+    def trace(self, on=True):
+        """he_ctx_trace: record every launch (outside capture) with HIP events."""
+        _chk(_lib.he_ctx_trace(self.h, 1 if on else 0), "he_ctx_trace")
+
+    def trace_read(self):
+        """he_ctx_trace_read: per kernel kind, launches, ms, algorithmic bytes
+        and modular products since tracing was switched on (clears them)."""
+        arr = (he_kernel_stat * K_COUNT)()
+        n = c_int()
+        _chk(_lib.he_ctx_trace_read(self.h, arr, K_COUNT, ctypes.byref(n)), "he_ctx_trace_read")
+        return [dict(kind=a.kind, name=_lib.he_kernel_kind_name(a.kind).decode(), launches=a.launches, ms=a.ms,
+                     bytes=a.bytes, mm_fp64=a.mm_fp64, mm_int=a.mm_int) for a in arr[:n.value]]
 
     def ntt(self, tensor, n_limbs, prime_idx0, period, direction):
         _chk(_lib.he_ntt(self.h, c_void_p(tensor.data_ptr()), n_limbs, prime_idx0, period, direction), "he_ntt")

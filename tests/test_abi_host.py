@@ -159,3 +159,15 @@ def test_noalloc_scratch_size_matches_header():
     src = open(os.path.join(ROOT, "include", "he.h")).read()
     m = re.search(r"#define HE_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", src)
     assert m and int(m.group(1)) << int(m.group(2)) == H.NOALLOC_SCRATCH_BYTES
+
+
+def test_kernel_trace_names_and_argument_checks():
+    """Every kernel kind of the trace has a distinct name; out-of-range kinds
+    and a missing context are refused without a device call."""
+    names = [H._lib.he_kernel_kind_name(k).decode() for k in range(H.K_COUNT)]
+    assert len(set(names)) == H.K_COUNT and "?" not in names
+    assert H._lib.he_kernel_kind_name(H.K_COUNT).decode() == "?"
+    assert H._lib.he_kernel_kind_name(-1).decode() == "?"
+    assert H._lib.he_ctx_trace(None, 1) != 0
+    n = H.ctypes.c_int()
+    assert H._lib.he_ctx_trace_read(None, None, 0, H.ctypes.byref(n)) != 0
