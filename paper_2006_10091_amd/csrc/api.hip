@@ -1561,20 +1561,26 @@ he_status he_ct_expand(he_ctx *c, const he_ct_seeded *in, int n, he_ct *out)
     return last_error();
 }
 
-he_status he_decrypt(he_ctx *c, const he_ct *ct, const he_keys *k, uint64_t *host)
+// the first nl limbs (coefficient form) of the decryption, to host
+static he_status decrypt_limbs(he_ctx *c, const he_ct *ct, const he_keys *k, int nl, uint64_t *host)
 {
-    if (!c || !ct_ok(c, ct) || !k || !host) return HE_EINVAL;
-    if (!keys_ok(c, k)) return HE_EKEY;
     const int l = ct->level;
     const size_t N = c->N;
     TRY(ensure_ws(c, al((size_t)(l + 1) * N) * 8 + 4096));
     Arena ar = arena(c);
     u64 *m = ar.take((size_t)(l + 1) * N);
     hek::dec_combine(c, l, ct->data, k->sk, m);
-    hek::ntt_batch(c, m, 0, 0, 1, 1, 0, l + 1, l, -1, nullptr, false);
-    HIPCHK(hipMemcpyAsync(host, m, (size_t)(l + 1) * N * 8, hipMemcpyDeviceToHost, c->stream));
+    hek::ntt_batch(c, m, 0, 0, 1, 1, 0, nl, l, -1, nullptr, false);
+    HIPCHK(hipMemcpyAsync(host, m, (size_t)nl * N * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     return last_error();
+}
+
+he_status he_decrypt(he_ctx *c, const he_ct *ct, const he_keys *k, uint64_t *host)
+{
+    if (!c || !ct_ok(c, ct) || !k || !host) return HE_EINVAL;
+    if (!keys_ok(c, k)) return HE_EKEY;
+    return decrypt_limbs(c, ct, k, ct->level + 1, host);
 }
 
 he_status he_decrypt_decode(he_ctx *c, const he_ct *ct, const he_keys *k, int n, double *re, double *im)
@@ -1582,22 +1588,18 @@ he_status he_decrypt_decode(he_ctx *c, const he_ct *ct, const he_keys *k, int n,
     if (!c || !ct_ok(c, ct) || !k || !re || n < 0 || n > c->N / 2) return HE_EINVAL;
     if (!keys_ok(c, k)) return HE_EKEY;
     const size_t N = c->N;
-    std::vector<u64> res((size_t)(ct->level + 1) * N);
-    TRY(he_decrypt(c, ct, k, res.data()));
-    std::vector<double> m(N);
+    // the message is centred below q0 q1 / 2: the first two limbs determine it
+    const int nl = std::min(2, ct->level + 1);
+    thread_local std::vector<u64> res;
+    thread_local std::vector<double> m;
+    res.resize((size_t)nl * N);
+    m.resize(N);
+    TRY(decrypt_limbs(c, ct, k, nl, res.data()));
     const u64 q0 = c->q[0];
-    if (ct->level == 0) {
+    if (nl == 1) {
         for (size_t x = 0; x < N; ++x) m[x] = res[x] > q0 / 2 ? -(double)(q0 - res[x]) : (double)res[x];
     } else {
-        const u64 q1 = c->q[1];
-        const u64 q0inv = hehost::invmod(q0 % q1, q1);
-        const u128 Q = (u128)q0 * q1;
-        for (size_t x = 0; x < N; ++x) {
-            u64 r0 = res[x], r1 = res[N + x];
-            u64 d = hehost::mulmod((r1 + q1 - r0 % q1) % q1, q0inv, q1);
-            u128 v = (u128)r0 + (u128)q0 * d;
-            m[x] = v > Q / 2 ? -(double)(Q - v) : (double)v;
-        }
+        hehost::crt2_centred(res.data(), res.data() + N, N, q0, c->q[1], m.data());
     }
     hehost::decode(c->logN, m.data(), ct->scale, n, re, im);
     return HE_OK;

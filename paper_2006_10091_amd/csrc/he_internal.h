@@ -148,6 +148,7 @@ void chacha20_block(const uint32_t key[8], uint32_t counter, const uint32_t nonc
 void sample_hwt(u64 seed, int logN, int h, i64 *out);
 int encode(int logN, const double *re, const double *im, int n, double scale, i64 *out);
 void decode(int logN, const double *m, double scale, int n, double *re, double *im);
+void crt2_centred(const u64 *r0, const u64 *r1, size_t N, u64 q0, u64 q1, double *m);
 he_status plan_lr_step(const u64 *q, int n_q, int level, double s_z, double s_w, const double coef[4],
                        double eta_over_n, double w_decay, int layout, he_lr_plan *o);
 he_status plan_lr_infer(const u64 *q, int n_q, int level, double s_z, double s_w, const double coef[4],

@@ -3,17 +3,104 @@
 // on the host), FP64 canonical-embedding encode/decode, and the FP64 scale
 // schedule of the gradient step.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
 #include <complex>
+#include <condition_variable>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <thread>
 #include <cstring>
+#include <unistd.h>
 #include <vector>
 
 #include "he_internal.h"
 
 namespace hehost {
+
+// A fixed set of worker threads for the host transforms (the refresh runs
+// a decode and an encode back to back).  run(n, f) calls f(0) .. f(n-1) on
+// the workers and the calling thread and returns once every worker has
+// finished this job, so no worker touches a job after run() returns.  Idle
+// workers spin for a short while after a job, then sleep.  A caller that
+// finds the pool busy (another thread's transform), or runs in a child
+// process forked after the workers started (which has none of them), runs
+// its items itself.
+class HostPool {
+public:
+    explicit HostPool(int workers) : pid_(getpid())
+    {
+        for (int i = 0; i < workers; ++i) th_.emplace_back([this] { loop(); });
+    }
+    int threads() const { return getpid() == pid_ ? (int)th_.size() + 1 : 1; }
+    void run(int n, const std::function<void(int)> &f)
+    {
+        std::unique_lock<std::mutex> one(run_mu_, std::try_to_lock);
+        if (!one.owns_lock() || th_.empty() || n <= 1 || getpid() != pid_) {
+            for (int i = 0; i < n; ++i) f(i);
+            return;
+        }
+        fn_ = &f;
+        n_ = n;
+        next_.store(0);
+        done_.store(0);
+        {
+            std::lock_guard<std::mutex> l(mu_);
+            gen_.fetch_add(1);
+        }
+        cv_.notify_all();
+        for (int i; (i = next_.fetch_add(1)) < n;) f(i);
+        while (done_.load() < (int)th_.size()) std::this_thread::yield();
+    }
+
+private:
+    void loop()
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            const auto t0 = std::chrono::steady_clock::now();
+            while (gen_.load() == seen && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(2)) {
+            }
+            if (gen_.load() == seen) {
+                std::unique_lock<std::mutex> l(mu_);
+                cv_.wait(l, [&] { return gen_.load() != seen; });
+            }
+            seen = gen_.load();
+            const int n = n_;
+            const std::function<void(int)> *f = fn_;
+            for (int i; (i = next_.fetch_add(1)) < n;) (*f)(i);
+            done_.fetch_add(1);
+        }
+    }
+    const pid_t pid_;
+    std::vector<std::thread> th_;
+    std::mutex mu_, run_mu_;
+    std::condition_variable cv_;
+    std::atomic<uint64_t> gen_{0};
+    std::atomic<int> next_{0}, done_{0};
+    int n_ = 0;
+    const std::function<void(int)> *fn_ = nullptr;
+};
+
+// the process's pool (never destroyed: its threads wait until the process ends)
+static HostPool &pool()
+{
+    static HostPool *p = new HostPool(std::max(0, std::min(8, (int)std::thread::hardware_concurrency()) - 1));
+    return *p;
+}
+
+// f(i0, i1) over [0, n) in chunks of the pool
+static void parallel_range(size_t n, const std::function<void(size_t, size_t)> &f)
+{
+    const int T = n >= 4096 ? pool().threads() : 1;
+    const size_t step = (n + T - 1) / T;
+    pool().run(T, [&](int t) {
+        const size_t a = std::min(n, (size_t)t * step), b = std::min(n, a + step);
+        if (a < b) f(a, b);
+    });
+}
 
 u64 mulmod(u64 a, u64 b, u64 q) { return (u64)(((u128)a * b) % q); }
 
@@ -173,35 +260,39 @@ static const std::vector<std::complex<double>> &fft_twiddles(size_t M, int sign)
     return w;
 }
 
+// One radix-2 butterfly of stage `half` (the complex product written out; the
+// library is built without contraction, so it rounds as std::complex's
+// operator* does for finite operands)
+static inline void butterfly(double *d, const double *w, size_t s, size_t k, size_t half)
+{
+    double *x = d + 2 * (s + k), *y = d + 2 * (s + k + half);
+    const double wr = w[2 * k], wi = w[2 * k + 1];
+    const double vr = y[0] * wr - y[1] * wi, vi = y[0] * wi + y[1] * wr;
+    const double ur = x[0], ui = x[1];
+    x[0] = ur + vr;
+    x[1] = ui + vi;
+    y[0] = ur - vr;
+    y[1] = ui - vi;
+}
+
 // Butterflies of the radix-2 stages len = len0 .. len1 (powers of two) on the
 // elements [lo, hi) of d (interleaved re, im), a whole number of len1 blocks.
 static void fft_stages(double *d, const double *wd, size_t lo, size_t hi, size_t len0, size_t len1)
 {
-    // the complex product written out (the library is built without
-    // contraction, so it rounds as std::complex's operator* does for finite
-    // operands)
     for (size_t len = len0; len <= len1; len <<= 1) {
         const size_t half = len / 2;
         const double *w = wd + 2 * (half - 1);
         for (size_t s = lo; s < hi; s += len)
-            for (size_t k = 0; k < half; ++k) {
-                double *x = d + 2 * (s + k), *y = d + 2 * (s + k + half);
-                const double wr = w[2 * k], wi = w[2 * k + 1];
-                const double vr = y[0] * wr - y[1] * wi, vi = y[0] * wi + y[1] * wr;
-                const double ur = x[0], ui = x[1];
-                x[0] = ur + vr;
-                x[1] = ui + vi;
-                y[0] = ur - vr;
-                y[1] = ui - vi;
-            }
+            for (size_t k = 0; k < half; ++k) butterfly(d, w, s, k, half);
     }
 }
 
 // In-place radix-2 complex FFT of size M (power of two):
 // A[k] = sum_n a[n] exp(sign * 2 pi i k n / M).  After the bit reversal the
 // stages up to length M / T act on T contiguous blocks of their own, one per
-// thread; the last log2 T stages run on the calling thread.  Every butterfly
-// is computed as in a one-thread run, so the result does not depend on T.
+// thread of the pool; each of the last log2 T stages is split by butterflies
+// over the threads.  Every butterfly is computed as in a one-thread run, so
+// the result does not depend on T.
 static void fft(std::vector<std::complex<double>> &a, int sign, bool reversed = false)
 {
     const size_t M = a.size();
@@ -215,17 +306,22 @@ static void fft(std::vector<std::complex<double>> &a, int sign, bool reversed = 
     const std::vector<std::complex<double>> &tw = fft_twiddles(M, sign);
     double *d = reinterpret_cast<double *>(a.data());
     const double *wd = reinterpret_cast<const double *>(tw.data());
-    const size_t T = M >= ((size_t)1 << 14) ? 4 : 1;
+    size_t T = 1;
+    if (M >= ((size_t)1 << 14))
+        while (2 * T <= (size_t)pool().threads()) T *= 2;
     if (T == 1) {
         fft_stages(d, wd, 0, M, 2, M);
         return;
     }
     const size_t blk = M / T;
-    std::vector<std::thread> th;
-    for (size_t t = 1; t < T; ++t) th.emplace_back(fft_stages, d, wd, t * blk, (t + 1) * blk, (size_t)2, blk);
-    fft_stages(d, wd, 0, blk, 2, blk);
-    for (auto &x : th) x.join();
-    fft_stages(d, wd, 0, M, 2 * blk, M);
+    pool().run((int)T, [&](int t) { fft_stages(d, wd, t * blk, (t + 1) * blk, 2, blk); });
+    for (size_t len = 2 * blk; len <= M; len <<= 1) {
+        const size_t half = len / 2, per = M / 2 / T;  // butterflies per thread
+        const double *w = wd + 2 * (half - 1);
+        pool().run((int)T, [&](int t) {
+            for (size_t j = t * per; j < (t + 1) * per; ++j) butterfly(d, w, (j / half) * len, j % half, half);
+        });
+    }
 }
 
 // Powers zeta^i, i < N, of zeta = exp(sign i pi / N), kept per (N, sign).
@@ -253,52 +349,88 @@ static inline size_t brev_idx(size_t i, int logN)
     return (size_t)(__builtin_bitreverse32((uint32_t)i) >> (32 - logN));
 }
 
-// the working vector of one thread, kept between calls (no fresh page faults)
+// the working vector of one thread, kept between calls (no fresh page
+// faults); its contents are left to the caller
 static std::vector<std::complex<double>> &fft_buffer(size_t N)
 {
     thread_local std::vector<std::complex<double>> buf;
-    buf.assign(N, 0.0);
+    buf.resize(N);
     return buf;
 }
 
+// 5^j mod M (M a power of two): the exponent of slot j's root
+static size_t slot_exp(size_t j, size_t M) { return (size_t)powmod(5, j, M); }
+
+// The loops below run in chunks over the pool; each element is computed as
+// in a one-thread run.
 int encode(int logN, const double *re, const double *im, int n, double scale, i64 *out)
 {
     const size_t N = (size_t)1 << logN, M = 2 * N;
     std::vector<std::complex<double>> &V = fft_buffer(N);
-    size_t e = 1;
-    for (int j = 0; j < n; ++j) {
-        std::complex<double> z(re[j], im ? im[j] : 0.0);
-        V[brev_idx((e - 1) / 2, logN)] = z * scale;
-        V[brev_idx((M - e - 1) / 2, logN)] = std::conj(z) * scale;
-        e = (e * 5) % M;
-    }
+    parallel_range(N, [&](size_t i0, size_t i1) { std::fill(V.begin() + i0, V.begin() + i1, 0.0); });
+    // slot j and its conjugate: distinct positions for distinct j
+    parallel_range((size_t)n, [&](size_t j0, size_t j1) {
+        size_t e = slot_exp(j0, M);
+        for (size_t j = j0; j < j1; ++j) {
+            std::complex<double> z(re[j], im ? im[j] : 0.0);
+            V[brev_idx((e - 1) / 2, logN)] = z * scale;
+            V[brev_idx((M - e - 1) / 2, logN)] = std::conj(z) * scale;
+            e = (e * 5) % M;
+        }
+    });
     fft(V, -1, true);
     const std::vector<std::complex<double>> &tw = twist(N, -1);
-    for (size_t i = 0; i < N; ++i) {
-        const double v = (V[i].real() * tw[i].real() - V[i].imag() * tw[i].imag()) / (double)N;
-        const double a = std::fabs(v);
-        if (!(a < 4.611686018427388e18)) return -1;  // 2^62
-        // half away from zero: floor(|v| + 0.5) is exact below 2^52; above, v is an integer
-        const double r = a < 4503599627370496.0 ? std::floor(a + 0.5) : a;
-        out[i] = (i64)(v < 0 ? -r : r);
-    }
-    return 0;
+    std::atomic<int> bad{0};
+    parallel_range(N, [&](size_t i0, size_t i1) {
+        for (size_t i = i0; i < i1; ++i) {
+            const double v = (V[i].real() * tw[i].real() - V[i].imag() * tw[i].imag()) / (double)N;
+            const double a = std::fabs(v);
+            if (!(a < 4.611686018427388e18)) {  // 2^62
+                bad.store(1);
+                return;
+            }
+            // half away from zero: floor(|v| + 0.5) is exact below 2^52; above, v is an integer
+            const double r = a < 4503599627370496.0 ? std::floor(a + 0.5) : a;
+            out[i] = (i64)(v < 0 ? -r : r);
+        }
+    });
+    return bad.load() ? -1 : 0;
 }
 
 void decode(int logN, const double *m, double scale, int n, double *re, double *im)
 {
     const size_t N = (size_t)1 << logN, M = 2 * N;
     const std::vector<std::complex<double>> &tw = twist(N, +1);
-    std::vector<std::complex<double>> &A = fft_buffer(N);
-    for (size_t i = 0; i < N; ++i) A[brev_idx(i, logN)] = m[i] * tw[i];
+    std::vector<std::complex<double>> &A = fft_buffer(N);  // every entry written
+    parallel_range(N, [&](size_t i0, size_t i1) {
+        for (size_t i = i0; i < i1; ++i) A[brev_idx(i, logN)] = m[i] * tw[i];
+    });
     fft(A, +1, true);
-    size_t e = 1;
-    for (int j = 0; j < n; ++j) {
-        const size_t k = (e - 1) / 2;
-        re[j] = A[k].real() / scale;
-        if (im) im[j] = A[k].imag() / scale;
-        e = (e * 5) % M;
-    }
+    parallel_range((size_t)n, [&](size_t j0, size_t j1) {
+        size_t e = slot_exp(j0, M);
+        for (size_t j = j0; j < j1; ++j) {
+            const size_t k = (e - 1) / 2;
+            re[j] = A[k].real() / scale;
+            if (im) im[j] = A[k].imag() / scale;
+            e = (e * 5) % M;
+        }
+    });
+}
+
+// Centred CRT of the first two limbs r0 (mod q0), r1 (mod q1) of N
+// coefficients, each rounded to the nearest double: v = r0 + q0 d with
+// d = (r1 - r0) q0^-1 mod q1, then v - q0 q1 when v > q0 q1 / 2.
+void crt2_centred(const u64 *r0, const u64 *r1, size_t N, u64 q0, u64 q1, double *m)
+{
+    const u64 q0inv = invmod(q0 % q1, q1);
+    const u128 Q = (u128)q0 * q1;
+    parallel_range(N, [&](size_t x0, size_t x1) {
+        for (size_t x = x0; x < x1; ++x) {
+            const u64 d = mulmod((r1[x] + q1 - r0[x] % q1) % q1, q0inv, q1);
+            const u128 v = (u128)r0[x] + (u128)q0 * d;
+            m[x] = v > Q / 2 ? -(double)(Q - v) : (double)v;
+        }
+    });
 }
 
 // Target scale T of the gradient terms, a power of two: the largest with

@@ -7,6 +7,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <sys/wait.h>
+#include <thread>
+#include <unistd.h>
 #include <vector>
 
 #include "he_internal.h"
@@ -83,6 +87,80 @@ int main()
         std::vector<double> big(S > 0 ? S : 1, std::ldexp(1.0, 70));
         std::vector<i64> m(N);
         CHECK(encode(logN, big.data(), nullptr, S > 0 ? S : 1, 1.0, m.data()) != 0);
+    }
+
+    // the transforms run their loops over a thread pool: the result does not
+    // depend on it.  A child forked here has no pool workers and runs every
+    // loop on its one thread; its encode and decode equal the parent's bit
+    // for bit, and so do those of callers that overlap (all but one of them
+    // find the pool busy and run alone).
+    {
+        const int logN = 16, N = 1 << logN, S = N / 2;
+        std::vector<double> re(S), im(S), md(N), dre(S), dim(S);
+        for (int j = 0; j < S; ++j) {
+            re[j] = std::sin(0.013 * j) * 3.0;
+            im[j] = std::cos(0.007 * j);
+        }
+        std::vector<i64> m(N);
+        CHECK(encode(logN, re.data(), im.data(), S, std::ldexp(1.0, 40), m.data()) == 0);
+        for (int i = 0; i < N; ++i) md[i] = (double)m[i] + 0.25 * (i % 3);
+        decode(logN, md.data(), std::ldexp(1.0, 40), S, dre.data(), dim.data());
+        int fd[2];
+        CHECK(pipe(fd) == 0);
+        const pid_t pid = fork();
+        CHECK(pid >= 0);
+        if (pid == 0) {
+            std::vector<i64> mc(N);
+            std::vector<double> cre(S), cim(S);
+            int same = encode(logN, re.data(), im.data(), S, std::ldexp(1.0, 40), mc.data()) == 0 && mc == m;
+            decode(logN, md.data(), std::ldexp(1.0, 40), S, cre.data(), cim.data());
+            same = same && cre == dre && cim == dim;
+            const char r = same ? 'y' : 'n';
+            (void)!write(fd[1], &r, 1);
+            _exit(0);
+        }
+        char r = 0;
+        CHECK(read(fd[0], &r, 1) == 1);
+        int st = 0;
+        CHECK(waitpid(pid, &st, 0) == pid && WIFEXITED(st));
+        CHECK(r == 'y');
+        close(fd[0]);
+        close(fd[1]);
+        std::vector<std::vector<i64>> outs(4, std::vector<i64>(N));
+        std::vector<std::thread> th;
+        for (int t = 0; t < 4; ++t)
+            th.emplace_back([&, t] { CHECK(encode(logN, re.data(), im.data(), S, std::ldexp(1.0, 40), outs[t].data()) == 0); });
+        for (auto &t : th) t.join();
+        for (auto &o : outs) CHECK(o == m);
+    }
+
+    // the decryption's centred CRT of two limbs: residues of known integers w,
+    // |w| < q0 q1 / 2 (small, near the bound, random), come back as w rounded
+    // to the nearest double
+    {
+        const u64 q0 = (1ull << 60) - 93, q1 = (1ull << 40) - 87;
+        const u128 H = ((u128)q0 * q1) / 2;
+        const size_t N = 1 << 14;
+        std::vector<u64> r0(N), r1(N);
+        std::vector<u128> w(N);
+        std::vector<bool> neg(N);
+        u64 x = 88172645463325252ull;
+        auto next = [&] {
+            x ^= x << 13, x ^= x >> 7, x ^= x << 17;
+            return x;
+        };
+        for (size_t i = 0; i < N; ++i) {
+            if (i < 4) w[i] = i;
+            else if (i < 8) w[i] = H - (i - 4);
+            else w[i] = (((u128)next() << 64) | next()) % (H + 1);
+            neg[i] = (next() & 1) && w[i] != 0;
+            const u128 Q = (u128)q0 * q1, v = neg[i] ? Q - w[i] : w[i];
+            r0[i] = (u64)(v % q0);
+            r1[i] = (u64)(v % q1);
+        }
+        std::vector<double> mm(N);
+        crt2_centred(r0.data(), r1.data(), N, q0, q1, mm.data());
+        for (size_t i = 0; i < N; ++i) CHECK(mm[i] == (neg[i] ? -(double)w[i] : (double)w[i]));
     }
 
     // scale plans: both layouts, every level, losses with a2 = 0 and a2 != 0,
