@@ -432,7 +432,7 @@ def schedule_only(torch, H, T, ctx, keys, X, y, coef, args, Wk):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is designed, not built"}))
+        print(json.dumps({"error": "bench.py runs on one GPU only; sharding over several GPUs is designed, not implemented"}))
         sys.exit(2)
     import torch
     from paper_2006_10091_amd import he as H

@@ -650,8 +650,9 @@ typedef struct {
     int launches;
     double ms;         /* summed HIP-event time of its launches */
     double bytes;      /* summed algorithmic bytes: each operand of a launch
-                        * read or written once (intermediates a fused pass
-                        * consumes count as its operands) */
+                        * read or written once; the intermediate between the
+                        * two passes of a transform is not counted, so a
+                        * plain transform's passes move 16 N bytes a limb */
     double mm_fp64;    /* modular products (butterflies count one each) at
                         * primes below 2^46, done in FP64 */
     double mm_int;     /* the same at wider primes (64-bit integer forms) */

@@ -1,6 +1,6 @@
 """Compile the C part of the oracle (he_oracle.c -> liboracle.so) with gcc.
 
-Test infrastructure: building the checker is not using it.
+Test infrastructure: compiling it here does not put it on the product path.
 """
 import os
 import subprocess

@@ -448,8 +448,8 @@ def _step_features(P, keys, Z, W, mask_m, c, r, pl, Zrot=None, n_baby=1):
 
 # ---------------------------------------------------------------- paper-order circuit
 def lr_grad_step_plain(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_decay=0.0, layout=ROWS):
-    """The same step in the order Sec. 3 and Sec. 4 state it, with no schedule
-    of this build's: every ciphertext product is relinearised and rescaled
+    """The same step in the order Sec. 3 and Sec. 4 state it, with none of the
+    fused schedule above: every ciphertext product is relinearised and rescaled
     before it is used (Sec. 3, multiplication then scaling), every slot sum is
     a sequence of rotate-and-adds, each block's gradient terms C, B1, k0 Z
     (and B2) are rescaled on their own before the cross-block sum of

@@ -2884,18 +2884,20 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
         dim3 gc((1 << (LOGN - LA)) / LineShape<LA>::LINES, npos, nzc);
         dim3 gr((1 << LA) / LineShape<LB>::LINES, npos, nzc);
         hipStream_t st = c->stream;
-        // each pass's algorithmic work: its operands once, its butterflies and
-        // the products of its fused prologue / epilogue
+        // each pass's algorithmic work: its operands read or written once,
+        // the intermediate between the two passes excluded (so the two
+        // passes of a plain transform move 16 N bytes a limb together), its
+        // butterflies and the products of its fused prologue / epilogue
         double l, fl;
         ntt_limbs(c, a, npos, nzc, &l, &fl);
         const double L8 = 8.0 * (1 << LOGN), NN = (double)(1 << LOGN), HB = NN / 2;
         const int nsrc = pro == PRO_MDRS ? f.nsrc + 1 : f.nsrc;
         const bool conv = dir > 0 && (pro == PRO_MODDOWN || pro == PRO_MDRS);
-        const double pro_b = conv ? (double)nzc * nsrc * L8 + l * L8 : 2.0 * l * L8;
+        const double pro_b = conv ? (double)nzc * nsrc * L8 : l * L8;  // sources, or the input
         const double pro_m = conv ? NN * nsrc : 0.0;
-        double epi_b = 2.0 * l * L8, epi_m = 0.0;
+        double epi_b = l * L8, epi_m = 0.0;  // the output
         if (epi == EPI_FINISH) {
-            epi_b = 3.0 * l * L8;  // intermediate, acc, out
+            epi_b = 2.0 * l * L8;  // acc, out
             if (f.nbase > 0) epi_b += l * L8 * std::min(f.nbase, a.ncomp) / a.ncomp;
             if (f.add) epi_b += l * L8;
             epi_m = NN * (1 + (f.post ? 1 : 0) + (f.has_kacc ? 1 : 0));
@@ -2925,7 +2927,7 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
         } else {
             {
                 const double km = f.has_kmul ? NN : 0.0;
-                KSpan k1(c, HE_K_NTT_INV_ROWS, 2.0 * l * L8, fl * (HB * LB + km), (l - fl) * (HB * LB + km));
+                KSpan k1(c, HE_K_NTT_INV_ROWS, l * L8, fl * (HB * LB + km), (l - fl) * (HB * LB + km));
                 if (pro == PRO_SRC)
                     ntt_rows_t<LOGN, true, PRO_SRC><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.ipsi, c->t.ipsi_sh,
                                                                                 c->t.ipsi_d, f);
@@ -2934,7 +2936,7 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
                                                                                  c->t.ipsi_d, f);
             }
             const double pm = post ? NN : 0.0;
-            KSpan k2(c, HE_K_NTT_INV_COLS, 2.0 * l * L8, fl * (HB * LA + pm), (l - fl) * (HB * LA + pm));
+            KSpan k2(c, HE_K_NTT_INV_COLS, l * L8, fl * (HB * LA + pm), (l - fl) * (HB * LA + pm));
             ntt_cols_t<LOGN, true, PRO_NONE><<<gc, LINE_THREADS, 0, st>>>(a, pi, c->t.ipsi, c->t.ipsi_sh, post,
                                                                          c->t.ipsi_d, f);
         }
@@ -3019,13 +3021,14 @@ static void ks_fused_t(he_ctx *c, NttArgs a, int B, int beta, int nb, const KsAr
     a.zoff = 0;
     dim3 gc((1 << (LOGN - LA)) / LineShape<LA>::LINES, nb, B * beta);
     // the digits' transformed limbs (each digit's own positions are already
-    // in NTT form and skipped), then the row pass reading them, those own
-    // positions from d2 and the keys, writing acc
+    // in NTT form and skipped): the column pass reads them, the row pass
+    // (the intermediate between them excluded) reads those own positions
+    // from d2 and the keys, and writes acc
     double l, fl;
     ntt_limbs(c, a, nb, B * beta, &l, &fl);
     const double L8 = 8.0 * (1 << LOGN), NN = (double)(1 << LOGN), HB = NN / 2;
     {
-        KSpan ks(c, HE_K_KS_COLS, 2.0 * l * L8, fl * HB * LA, (l - fl) * HB * LA);
+        KSpan ks(c, HE_K_KS_COLS, l * L8, fl * HB * LA, (l - fl) * HB * LA);
         ntt_cols_t<LOGN, false, PRO_NONE><<<gc, LINE_THREADS, 0, c->stream>>>(a, c->t.pinfo, c->t.psi, c->t.psi_sh,
                                                                               nullptr, c->t.psi_d, f);
     }
@@ -3035,7 +3038,7 @@ static void ks_fused_t(he_ctx *c, NttArgs a, int B, int beta, int nb, const KsAr
     const double keys = (k.per_entry ? B : 1) * 2.0 * beta * nb;
     const int fpn = fp_pos(c, k.ell, 0, nb);
     const double ip = (double)B * NN * 2 * beta;  // inner-product products per position
-    KSpan ks(c, HE_K_KS_ROWS, (l + (double)B * (k.ell + 1) + keys + 2.0 * B * nb) * L8, fl * HB * LB + fpn * ip,
+    KSpan ks(c, HE_K_KS_ROWS, ((double)B * (k.ell + 1) + keys + 2.0 * B * nb) * L8, fl * HB * LB + fpn * ip,
              (l - fl) * HB * LB + (nb - fpn) * ip);
     ntt_rows_ks_t<LOGN><<<gr, LINE_THREADS, 0, c->stream>>>(kk, c->t.pinfo, c->t.psi, c->t.psi_sh, c->t.psi_d);
 }

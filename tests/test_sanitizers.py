@@ -1,6 +1,6 @@
 """The oracle (oracle/he_oracle.c) and libhe's host arithmetic (csrc/host.cpp)
 built with AddressSanitizer and UndefinedBehaviorSanitizer and run on the CPU
-through the drivers in tests/sanitize/: every exported routine over the ring
+through the programs in tests/sanitize/: every exported routine over the ring
 degrees and parameters used, with edge and refused inputs.  Host code only:
 the HIP build is host-only (no device code is compiled), and the sanitizer
 flags are host-side flags."""
