@@ -666,10 +666,10 @@ typedef struct {
  * measurement runs, not for timing the whole.  HE_EINVAL. */
 he_status he_ctx_trace(he_ctx *ctx, int on);
 
-/* Synchronises the context's stream, sums the records per kind into out
- * (caller's host array of max entries; kinds with no launch are left out,
- * in kind order) and clears them; *n = the entries written.  HE_EDEVICE when
- * an event failed while recording; HE_EINVAL. */
+/* Waits for every recorded launch (and the context's stream), sums the
+ * records per kind into out (caller's host array of max entries; kinds with
+ * no launch are left out, in kind order) and clears them; *n = the entries
+ * written.  HE_EDEVICE when an event failed while recording; HE_EINVAL. */
 he_status he_ctx_trace_read(he_ctx *ctx, he_kernel_stat *out, int max, int *n);
 
 /* Name of a kernel kind ("?" when out of range). */

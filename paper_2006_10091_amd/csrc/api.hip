@@ -2834,7 +2834,8 @@ he_status he_ctx_trace_read(he_ctx *c, he_kernel_stat *out, int max, int *n)
     bool failed = c->kt.failed;
     for (const KRec &r : c->kt.recs) {
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) failed = true;
+        // records made on an earlier stream of the context complete on their own
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) failed = true;
         he_kernel_stat &a = acc[r.kind >= 0 && r.kind < HE_K_COUNT ? r.kind : HE_K_OTHER];
         a.launches += 1;
         a.ms += ms;

@@ -2485,11 +2485,12 @@ struct KSpan {
         KTrace &t = c->kt;
         if (!t.on || c->capturing) return;
         hipEvent_t e[2];
-        for (hipEvent_t &x : e) {
+        for (int i = 0; i < 2; ++i) {
             if (!t.pool.empty()) {
-                x = t.pool.back();
+                e[i] = t.pool.back();
                 t.pool.pop_back();
-            } else if (hipEventCreate(&x) != hipSuccess) {
+            } else if (hipEventCreate(&e[i]) != hipSuccess) {
+                if (i == 1) t.pool.push_back(e[0]);
                 t.failed = true;
                 return;
             }
