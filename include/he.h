@@ -561,7 +561,10 @@ he_status he_batch_mul_rotate(he_ctx *ctx, const he_ct *x, const he_ct *y, const
  * staging of ROTATE / RESCALE inputs, every ADD and the copy of every result
  * to its out -- each one launch over all operations of all levels; the key
  * switches and rescalings run per level, all operations of one level
- * together (rotations up to 32 per launch, each with its own key).
+ * together (rotations up to 32 per launch, each with its own key).  In modes
+ * 1 and 2 the level groups, which share no data, are dealt to 4 streams of
+ * the context (largest first, to the least loaded), each with a scratch area
+ * of its own, between a fork from and a join back to the context's stream.
  * mode 0: one operation per launch group; 1: grouped; 2: grouped and
  * captured into a HIP graph on first use for these operations and buffers,
  * replayed afterwards (the table is uploaded before each replay).  All modes

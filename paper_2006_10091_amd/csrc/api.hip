@@ -9,6 +9,7 @@
 #include <mutex>
 #include <new>
 #include <map>
+#include <functional>
 #include <sstream>
 
 #include "he_internal.h"
@@ -1249,6 +1250,11 @@ he_status he_ctx_destroy(he_ctx *c)
         (void)hipEventDestroy(c->sub_ev);
     }
     if (c->sub_host) (void)hipHostFree(c->sub_host);
+    for (int i = 0; i < he_ctx::SUBMIT_LANES; ++i) {
+        if (c->lane[i]) (void)hipStreamDestroy(c->lane[i]);
+        if (c->lane_ev[i]) (void)hipEventDestroy(c->lane_ev[i]);
+    }
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     for (he_keys *k : c->keys_made) k->ctx = nullptr;  // released later, they no longer reach this context
     for (const KRec &r : c->kt.recs) {
         (void)hipEventDestroy(r.a);
@@ -2213,6 +2219,7 @@ struct SubmitPlan {
     std::map<int, std::vector<int>> resc;   // x level -> RESCALE ops
     std::vector<int> add, copy;             // ADD ops; ROTATE ops by a multiple of the slot count
     size_t table_u64 = 0, staging_u64 = 0, scratch_u64 = 0;
+    int lanes = 1;                          // streams the groups are spread over, each with its own scratch
 };
 
 static int out_level(const he_op &o)
@@ -2302,10 +2309,15 @@ static he_status submit_plan(const he_ctx *c, const he_op *ops, int n, const he_
     pl.table_u64 = al(ntab * sizeof(hek::OpDesc) / 8);
     pl.staging_u64 = stg;
     pl.scratch_u64 = scr;
+    const int groups = (int)(pl.mul.size() + pl.rot.size() + pl.resc.size());
+    pl.lanes = mode == 0 ? 1 : std::max(1, std::min(he_ctx::SUBMIT_LANES, groups));
     return HE_OK;
 }
 
-static size_t submit_bytes(const SubmitPlan &pl) { return (pl.table_u64 + pl.staging_u64 + pl.scratch_u64) * 8 + 4096; }
+static size_t submit_bytes(const SubmitPlan &pl)
+{
+    return (pl.table_u64 + pl.staging_u64 + (size_t)pl.lanes * al(pl.scratch_u64)) * 8 + 4096;
+}
 
 // The staging regions and operand tables of a plan laid out in the workspace
 // (the tables first, at its start, then the staging, then the scratch arena).
@@ -2393,50 +2405,102 @@ static he_status submit_impl(he_ctx *c, const he_op *ops, const SubmitPlan &pl, 
     hek::desc_ew(c, 6, tab, ly.n_tensor, ly.max_limbs, limbs(0, ly.n_tensor));
     hek::desc_ew(c, 4, tab + o_in, ly.n_in, ly.max_limbs, limbs(o_in, ly.n_in));
     hek::desc_ew(c, 0, tab + o_add, ly.n_add, ly.max_limbs, limbs(o_add, ly.n_add));
-    Arena ar = arena(c);
-    ar.off = scratch_off;
     const int rchunk = std::min(pl.chunk, hek::HE_MAXMULTI);
+    // The level groups share no data: each is one task, and the tasks are
+    // dealt to pl.lanes streams (largest first, each to the least loaded
+    // lane), each lane with a scratch arena of its own.  A lane runs its tasks
+    // in order, so its arena is reused as on one stream.
+    struct Task {
+        double cost;
+        std::function<he_status(Arena &)> run;
+    };
+    std::vector<Task> tasks;
     // products: relinearise and rescale per level, then the MUL_ROTATE rotations
     for (const auto &g : pl.mul) {
         const int l = g.first, B = (int)g.second.size(), Br = pl.mul_rot.at(l);
-        const long long t3 = 3LL * (l + 1) * N, r2 = 2LL * l * N;
-        for (int s0 = 0; s0 < B; s0 += pl.chunk) {
-            const int b = std::min(pl.chunk, B - s0);
-            TRY(relin_rescale_apply(c, ar, l, b, ly.T3.at(l) + s0 * t3, t3, k->rlk, ly.R.at(l) + s0 * r2, r2));
-        }
-        for (int s0 = 0; s0 < Br; s0 += rchunk) {
-            const int b = std::min(rchunk, Br - s0);
-            hek::EntryGal eg;
-            hek::EntryKeys ek;
-            for (int j = 0; j < b; ++j) {
-                eg.g[j] = pl.gal[g.second[s0 + j]];
-                ek.k[j] = find_rot_key(k, eg.g[j]);
+        const std::vector<int> *idx = &g.second;
+        tasks.push_back({(double)(B + Br) * (l + 1 + c->nk), [&, l, B, Br, idx](Arena &ar) -> he_status {
+            const long long t3 = 3LL * (l + 1) * N, r2 = 2LL * l * N;
+            for (int s0 = 0; s0 < B; s0 += pl.chunk) {
+                const int b = std::min(pl.chunk, B - s0);
+                TRY(relin_rescale_apply(c, ar, l, b, ly.T3.at(l) + s0 * t3, t3, k->rlk, ly.R.at(l) + s0 * r2, r2));
             }
-            TRY(rotate_multi_apply(c, ar, l - 1, b, ly.R.at(l) + s0 * r2, r2, eg, ek, ly.RO.at(l) + s0 * r2, r2));
-        }
+            for (int s0 = 0; s0 < Br; s0 += rchunk) {
+                const int b = std::min(rchunk, Br - s0);
+                hek::EntryGal eg;
+                hek::EntryKeys ek;
+                for (int j = 0; j < b; ++j) {
+                    eg.g[j] = pl.gal[(*idx)[s0 + j]];
+                    ek.k[j] = find_rot_key(k, eg.g[j]);
+                }
+                TRY(rotate_multi_apply(c, ar, l - 1, b, ly.R.at(l) + s0 * r2, r2, eg, ek, ly.RO.at(l) + s0 * r2,
+                                       r2));
+            }
+            return HE_OK;
+        }});
     }
     for (const auto &g : pl.rot) {
         const int l = g.first, B = (int)g.second.size();
-        const long long c2 = 2LL * (l + 1) * N;
-        for (int s0 = 0; s0 < B; s0 += rchunk) {
-            const int b = std::min(rchunk, B - s0);
-            hek::EntryGal eg;
-            hek::EntryKeys ek;
-            for (int j = 0; j < b; ++j) {
-                eg.g[j] = pl.gal[g.second[s0 + j]];
-                ek.k[j] = find_rot_key(k, eg.g[j]);
+        const std::vector<int> *idx = &g.second;
+        tasks.push_back({(double)B * (l + 1 + c->nk), [&, l, B, idx](Arena &ar) -> he_status {
+            const long long c2 = 2LL * (l + 1) * N;
+            for (int s0 = 0; s0 < B; s0 += rchunk) {
+                const int b = std::min(rchunk, B - s0);
+                hek::EntryGal eg;
+                hek::EntryKeys ek;
+                for (int j = 0; j < b; ++j) {
+                    eg.g[j] = pl.gal[(*idx)[s0 + j]];
+                    ek.k[j] = find_rot_key(k, eg.g[j]);
+                }
+                TRY(rotate_multi_apply(c, ar, l, b, ly.Rin.at(l) + s0 * c2, c2, eg, ek, ly.Rout.at(l) + s0 * c2,
+                                       c2));
             }
-            TRY(rotate_multi_apply(c, ar, l, b, ly.Rin.at(l) + s0 * c2, c2, eg, ek, ly.Rout.at(l) + s0 * c2, c2));
-        }
+            return HE_OK;
+        }});
     }
     for (const auto &g : pl.resc) {
         const int l = g.first, B = (int)g.second.size();
-        const long long c2 = 2LL * (l + 1) * N, r2 = 2LL * l * N;
-        for (int s0 = 0; s0 < B; s0 += pl.chunk) {
-            const int b = std::min(pl.chunk, B - s0);
-            TRY(rescale_apply(c, ar, l, b, ly.Sin.at(l) + s0 * c2, c2, ly.Sout.at(l) + s0 * r2, r2));
+        tasks.push_back({0.25 * B * (l + 1), [&, l, B](Arena &ar) -> he_status {
+            const long long c2 = 2LL * (l + 1) * N, r2 = 2LL * l * N;
+            for (int s0 = 0; s0 < B; s0 += pl.chunk) {
+                const int b = std::min(pl.chunk, B - s0);
+                TRY(rescale_apply(c, ar, l, b, ly.Sin.at(l) + s0 * c2, c2, ly.Sout.at(l) + s0 * r2, r2));
+            }
+            return HE_OK;
+        }});
+    }
+    const int K = pl.lanes;
+    std::vector<Arena> lane_ar(K, arena(c));
+    const size_t sb = al(pl.scratch_u64) * 8;  // 256-byte multiples: every lane's arena starts aligned
+    for (int i = 0; i < K; ++i) {
+        lane_ar[i].off = scratch_off + i * sb;
+        lane_ar[i].cap = scratch_off + (i + 1) * sb;
+    }
+    std::vector<int> order(tasks.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return tasks[a].cost > tasks[b].cost; });
+    hipStream_t main = c->stream;
+    if (K > 1) {
+        HIPCHK(hipEventRecord(c->fork_ev, main));
+        for (int i = 0; i < K; ++i) HIPCHK(hipStreamWaitEvent(c->lane[i], c->fork_ev, 0));
+    }
+    std::vector<double> load(K, 0.0);
+    he_status st = HE_OK;
+    for (int t : order) {
+        const int i = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[i] += tasks[t].cost;
+        c->stream = K > 1 ? c->lane[i] : main;
+        st = tasks[t].run(lane_ar[i]);
+        c->stream = main;
+        if (st != HE_OK) break;
+    }
+    if (K > 1) {  // joined even after an error, so that no lane is left behind (or outside a capture)
+        for (int i = 0; i < K; ++i) {
+            HIPCHK(hipEventRecord(c->lane_ev[i], c->lane[i]));
+            HIPCHK(hipStreamWaitEvent(main, c->lane_ev[i], 0));
         }
     }
+    TRY(st);
     // every result to its out: one launch
     hek::desc_ew(c, 4, tab + o_out, ly.n_out, ly.max_limbs, limbs(o_out, ly.n_out));
     return last_error();
@@ -2475,6 +2539,13 @@ he_status he_batch_submit(he_ctx *c, he_op *ops, int n, const he_keys *k, int mo
     std::memcpy(c->sub_host, ly.tab.data(), tb);
     HIPCHK(hipMemcpyAsync(c->ws, c->sub_host, tb, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipEventRecord(c->sub_ev, c->stream));
+    if (pl.lanes > 1 && !c->fork_ev) {  // the lanes' streams and events, made once (outside any capture)
+        HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+        for (int i = 0; i < he_ctx::SUBMIT_LANES; ++i) {
+            HIPCHK(hipStreamCreateWithFlags(&c->lane[i], hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&c->lane_ev[i], hipEventDisableTiming));
+        }
+    }
     if (mode == 2) {
         std::ostringstream key;
         key << "submit:" << n << ':' << k->gen << ':' << (const void *)k->sk << ':' << (const void *)c->ws;

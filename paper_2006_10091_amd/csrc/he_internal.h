@@ -118,6 +118,11 @@ struct he_ctx {
     void *sub_host = nullptr;
     size_t sub_host_bytes = 0;
     hipEvent_t sub_ev = nullptr;
+    // he_batch_submit's lanes: independent operation groups run on these
+    // streams (default priority) between a fork and a join event
+    static constexpr int SUBMIT_LANES = 4;
+    hipStream_t lane[SUBMIT_LANES] = {};
+    hipEvent_t lane_ev[SUBMIT_LANES] = {}, fork_ev = nullptr;
     // key sets this context made and that are not yet released: their
     // back-pointer is cleared when the context goes first
     std::set<he_keys *> keys_made;

@@ -7,6 +7,8 @@
 * the 256-operation mixed workload over N in {2^14, 2^15, 2^16}: all forms
   agree bit for bit, the graph replays agree with the first run, and one
   entry per N is checked against the oracle;
+* the same workload with each ring degree's share on its own stream (the
+  shares concurrent) equals the one-stream run bit for bit;
 * errors are reported before any launch.
 """
 import numpy as np
@@ -74,6 +76,26 @@ def test_c3_workload_forms_agree_and_sampled_oracle():
     for log_n in (14, 15, 16):
         i = b.idx[log_n][0]
         assert np.array_equal(ref[i], _oracle_entry(b, i, cache)), (log_n, i)
+
+
+def test_c3_workload_on_concurrent_streams_matches_serial():
+    """Each ring degree's share on a stream of its own (the shares run
+    concurrently): every form's outputs equal the one-stream plain form's."""
+    ops = BO.draw_ops(96, seed=4004)
+    ref = None
+    for streams in (False, True):
+        b = BO.Batch(ops, seed=5005, streams=streams)
+        for mode, run in ((0, b.run), (1, b.run), (2, b.run), (2, b.run), (1, b.run_submit), (2, b.run_submit)):
+            if streams and mode == 0:
+                continue
+            run(mode)
+            torch.cuda.synchronize()
+            got = b.outputs()
+            if ref is None:
+                ref = got
+            assert all(np.array_equal(a, r) for a, r in zip(got, ref)), (streams, mode)
+        del b
+        torch.cuda.synchronize()
 
 
 def test_batch_errors():
