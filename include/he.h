@@ -532,6 +532,9 @@ size_t he_lr_margins_bytes(const he_ctx *ctx, int level, int n_blocks, int mode)
  * caller memory holding a ciphertext at level(x[i]) - 1, distinct from every
  * input.  Entries of one level run together, up to 32 per launch, each with
  * its own rotation key; keys needs the relinearisation key and every step.
+ * In modes 1 and 2 the groups are dealt to 4 streams of the context, each
+ * with a workspace region of its own, forked from and joined back to the
+ * context's stream.
  * mode 0: one entry at a time; 1: grouped by level; 2: grouped, captured
  * into a HIP graph on first use for these buffers and replayed.  All modes
  * give bit-identical outputs.  Errors (before any launch): HE_EINVAL,

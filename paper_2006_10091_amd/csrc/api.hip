@@ -979,6 +979,64 @@ he_status run_graph(he_ctx *c, const std::string &key, uint64_t keys_gen, F body
 // ------------------------------------------------------------------ batched mul -> relin -> rescale -> rotate
 // Entries of one level run together, up to HE_MAXMULTI per launch, each with
 // its own rotation key; inputs are read in place, outputs staged and copied.
+// ------------------------------------------------------------------ lanes of independent groups
+// Batches whose groups share no data run them on the context's lane streams
+// (default priority), forked from and joined back to the context's stream;
+// inside a capture the lanes become parallel branches of the graph.
+static he_status lanes_ready(he_ctx *c)
+{
+    if (c->fork_ev) return HE_OK;
+    if (c->capturing) return HE_EINVAL;  // made once, outside any capture
+    HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    for (int i = 0; i < he_ctx::SUBMIT_LANES; ++i) {
+        HIPCHK(hipStreamCreateWithFlags(&c->lane[i], hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&c->lane_ev[i], hipEventDisableTiming));
+    }
+    return HE_OK;
+}
+
+static he_status lanes_fork(he_ctx *c, int K)
+{
+    if (K < 2) return HE_OK;
+    HIPCHK(hipEventRecord(c->fork_ev, c->stream));
+    for (int i = 0; i < K; ++i) HIPCHK(hipStreamWaitEvent(c->lane[i], c->fork_ev, 0));
+    return HE_OK;
+}
+
+static he_status lanes_join(he_ctx *c, int K)
+{
+    if (K < 2) return HE_OK;
+    for (int i = 0; i < K; ++i) {
+        HIPCHK(hipEventRecord(c->lane_ev[i], c->lane[i]));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->lane_ev[i], 0));
+    }
+    return HE_OK;
+}
+
+// Runs tasks (cost, body(lane)) on K lanes: largest first, each to the least
+// loaded lane; body runs with c->stream set to its lane's stream (the
+// context's own stream when K = 1).  The lanes are joined even after an error.
+static he_status lanes_run(he_ctx *c, int K, std::vector<std::pair<double, std::function<he_status(int)>>> &tasks)
+{
+    std::vector<int> order(tasks.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return tasks[a].first > tasks[b].first; });
+    TRY(lanes_fork(c, K));
+    hipStream_t main = c->stream;
+    std::vector<double> load(K, 0.0);
+    he_status st = HE_OK;
+    for (int t : order) {
+        const int i = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[i] += tasks[t].first;
+        c->stream = K > 1 ? c->lane[i] : main;
+        st = tasks[t].second(i);
+        c->stream = main;
+        if (st != HE_OK) break;
+    }
+    TRY(lanes_join(c, K));
+    return st;
+}
+
 size_t batch_bytes(const he_ctx *c, int l, int B)
 {
     const size_t N = c->N;
@@ -987,35 +1045,45 @@ size_t batch_bytes(const he_ctx *c, int l, int B)
     return n * 8 + 4096;
 }
 
+// The level groups (in chunks) of he_batch_mul_rotate as tasks on K lanes,
+// lane i with the scratch [i * per, (i + 1) * per) of the workspace.
 he_status batch_impl(he_ctx *c, const he_ct *x, const he_ct *y, const u64 *gal, const he_keys *k, int chunk,
-                     const std::map<int, std::vector<int>> &groups, he_ct *out)
+                     const std::map<int, std::vector<int>> &groups, he_ct *out, int K, size_t per)
 {
     const long long N = c->N;
+    std::vector<std::pair<double, std::function<he_status(int)>>> tasks;
     for (const auto &gr : groups) {
         const int l = gr.first;
-        const std::vector<int> &idx = gr.second;
-        const long long lc = (long long)(l + 1) * N, rc = (long long)l * N;
-        for (size_t s0 = 0; s0 < idx.size(); s0 += chunk) {
-            const int B = (int)std::min<size_t>(chunk, idx.size() - s0);
-            Arena ar = arena(c);
-            u64 *T3 = ar.take((size_t)B * 3 * lc);
-            u64 *R = ar.take((size_t)B * 2 * rc);
-            u64 *Ob = ar.take((size_t)B * 2 * rc);
-            if (!T3 || !R || !Ob) return HE_ENOMEM;
-            hek::EntryKeys keys;
-            hek::EntryGal gals;
-            for (int b = 0; b < B; ++b) {
-                const int i = idx[s0 + b];
-                hek::tensor_b(c, l, 1, x[i].data, 0, lc, y[i].data, 0, lc, T3 + b * 3 * lc, 3 * lc, lc);
-                keys.k[b] = find_rot_key(k, gal[i]);
-                gals.g[b] = gal[i];
-            }
-            TRY(relin_rescale_apply(c, ar, l, B, T3, 3 * lc, k->rlk, R, 2 * rc));
-            TRY(rotate_multi_apply(c, ar, l - 1, B, R, 2 * rc, gals, keys, Ob, 2 * rc));
-            for (int b = 0; b < B; ++b)
-                hek::ewise(c, 4, l - 1, 1, 2, Ob + b * 2 * rc, 0, rc, nullptr, 0, 0, out[idx[s0 + b]].data, 0, rc, 0);
+        const std::vector<int> *idx = &gr.second;
+        for (size_t s0 = 0; s0 < idx->size(); s0 += chunk) {
+            const int B = (int)std::min<size_t>(chunk, idx->size() - s0);
+            tasks.push_back({(double)B * (l + 1 + c->nk), [=](int lane) -> he_status {
+                const long long lc = (long long)(l + 1) * N, rc = (long long)l * N;
+                Arena ar;
+                ar.base = (char *)c->ws + (size_t)lane * per;
+                ar.cap = per;
+                u64 *T3 = ar.take((size_t)B * 3 * lc);
+                u64 *R = ar.take((size_t)B * 2 * rc);
+                u64 *Ob = ar.take((size_t)B * 2 * rc);
+                if (!T3 || !R || !Ob) return HE_ENOMEM;
+                hek::EntryKeys keys;
+                hek::EntryGal gals;
+                for (int b = 0; b < B; ++b) {
+                    const int i = (*idx)[s0 + b];
+                    hek::tensor_b(c, l, 1, x[i].data, 0, lc, y[i].data, 0, lc, T3 + b * 3 * lc, 3 * lc, lc);
+                    keys.k[b] = find_rot_key(k, gal[i]);
+                    gals.g[b] = gal[i];
+                }
+                TRY(relin_rescale_apply(c, ar, l, B, T3, 3 * lc, k->rlk, R, 2 * rc));
+                TRY(rotate_multi_apply(c, ar, l - 1, B, R, 2 * rc, gals, keys, Ob, 2 * rc));
+                for (int b = 0; b < B; ++b)
+                    hek::ewise(c, 4, l - 1, 1, 2, Ob + b * 2 * rc, 0, rc, nullptr, 0, 0, out[(*idx)[s0 + b]].data, 0,
+                               rc, 0);
+                return HE_OK;
+            }});
         }
     }
+    TRY(lanes_run(c, K, tasks));
     return last_error();
 }
 
@@ -2186,17 +2254,26 @@ he_status he_batch_mul_rotate(he_ctx *c, const he_ct *x, const he_ct *y, const i
     }
     const int chunk = mode == 0 ? 1 : hek::HE_MAXMULTI;
     size_t need = 0;
-    for (const auto &g : groups) need = std::max(need, batch_bytes(c, g.first, std::min(chunk, (int)g.second.size())));
-    TRY(ensure_ws(c, need));
+    int ntask = 0;
+    for (const auto &g : groups) {
+        need = std::max(need, batch_bytes(c, g.first, std::min(chunk, (int)g.second.size())));
+        ntask += ((int)g.second.size() + chunk - 1) / chunk;
+    }
+    // modes 1 and 2: the groups on up to 4 lanes, each with a scratch region of its own
+    const int K = mode == 0 ? 1 : std::max(1, std::min(he_ctx::SUBMIT_LANES, ntask));
+    const size_t per = (need + 255) & ~(size_t)255;
+    TRY(ensure_ws(c, K * per));
+    if (K > 1) TRY(lanes_ready(c));
     if (mode == 2) {
         std::ostringstream key;
         key << "batch:" << n << ':' << k->gen << ':' << (const void *)k->sk << ':' << (const void *)c->ws;
         for (int i = 0; i < n; ++i)
             key << ':' << (const void *)x[i].data << ',' << (const void *)y[i].data << ',' << (const void *)out[i].data
                 << ',' << x[i].level << ',' << gal[i];
-        TRY(run_graph(c, key.str(), k->gen, [&] { return batch_impl(c, x, y, gal.data(), k, chunk, groups, out); }));
+        TRY(run_graph(c, key.str(), k->gen,
+                      [&] { return batch_impl(c, x, y, gal.data(), k, chunk, groups, out, K, per); }));
     } else {
-        TRY(batch_impl(c, x, y, gal.data(), k, chunk, groups, out));
+        TRY(batch_impl(c, x, y, gal.data(), k, chunk, groups, out, K, per));
     }
     for (int i = 0; i < n; ++i) {
         out[i].level = x[i].level - 1;
@@ -2410,16 +2487,19 @@ static he_status submit_impl(he_ctx *c, const he_op *ops, const SubmitPlan &pl, 
     // dealt to pl.lanes streams (largest first, each to the least loaded
     // lane), each lane with a scratch arena of its own.  A lane runs its tasks
     // in order, so its arena is reused as on one stream.
-    struct Task {
-        double cost;
-        std::function<he_status(Arena &)> run;
-    };
-    std::vector<Task> tasks;
+    std::vector<Arena> lane_ar(pl.lanes, arena(c));
+    const size_t sb = al(pl.scratch_u64) * 8;  // 256-byte multiples: every lane's arena starts aligned
+    for (int i = 0; i < pl.lanes; ++i) {
+        lane_ar[i].off = scratch_off + i * sb;
+        lane_ar[i].cap = scratch_off + (i + 1) * sb;
+    }
+    std::vector<std::pair<double, std::function<he_status(int)>>> tasks;
     // products: relinearise and rescale per level, then the MUL_ROTATE rotations
     for (const auto &g : pl.mul) {
         const int l = g.first, B = (int)g.second.size(), Br = pl.mul_rot.at(l);
         const std::vector<int> *idx = &g.second;
-        tasks.push_back({(double)(B + Br) * (l + 1 + c->nk), [&, l, B, Br, idx](Arena &ar) -> he_status {
+        tasks.push_back({(double)(B + Br) * (l + 1 + c->nk), [&, l, B, Br, idx](int lane) -> he_status {
+            Arena &ar = lane_ar[lane];
             const long long t3 = 3LL * (l + 1) * N, r2 = 2LL * l * N;
             for (int s0 = 0; s0 < B; s0 += pl.chunk) {
                 const int b = std::min(pl.chunk, B - s0);
@@ -2442,7 +2522,8 @@ static he_status submit_impl(he_ctx *c, const he_op *ops, const SubmitPlan &pl, 
     for (const auto &g : pl.rot) {
         const int l = g.first, B = (int)g.second.size();
         const std::vector<int> *idx = &g.second;
-        tasks.push_back({(double)B * (l + 1 + c->nk), [&, l, B, idx](Arena &ar) -> he_status {
+        tasks.push_back({(double)B * (l + 1 + c->nk), [&, l, B, idx](int lane) -> he_status {
+            Arena &ar = lane_ar[lane];
             const long long c2 = 2LL * (l + 1) * N;
             for (int s0 = 0; s0 < B; s0 += rchunk) {
                 const int b = std::min(rchunk, B - s0);
@@ -2460,7 +2541,8 @@ static he_status submit_impl(he_ctx *c, const he_op *ops, const SubmitPlan &pl, 
     }
     for (const auto &g : pl.resc) {
         const int l = g.first, B = (int)g.second.size();
-        tasks.push_back({0.25 * B * (l + 1), [&, l, B](Arena &ar) -> he_status {
+        tasks.push_back({0.25 * B * (l + 1), [&, l, B](int lane) -> he_status {
+            Arena &ar = lane_ar[lane];
             const long long c2 = 2LL * (l + 1) * N, r2 = 2LL * l * N;
             for (int s0 = 0; s0 < B; s0 += pl.chunk) {
                 const int b = std::min(pl.chunk, B - s0);
@@ -2469,38 +2551,7 @@ static he_status submit_impl(he_ctx *c, const he_op *ops, const SubmitPlan &pl, 
             return HE_OK;
         }});
     }
-    const int K = pl.lanes;
-    std::vector<Arena> lane_ar(K, arena(c));
-    const size_t sb = al(pl.scratch_u64) * 8;  // 256-byte multiples: every lane's arena starts aligned
-    for (int i = 0; i < K; ++i) {
-        lane_ar[i].off = scratch_off + i * sb;
-        lane_ar[i].cap = scratch_off + (i + 1) * sb;
-    }
-    std::vector<int> order(tasks.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return tasks[a].cost > tasks[b].cost; });
-    hipStream_t main = c->stream;
-    if (K > 1) {
-        HIPCHK(hipEventRecord(c->fork_ev, main));
-        for (int i = 0; i < K; ++i) HIPCHK(hipStreamWaitEvent(c->lane[i], c->fork_ev, 0));
-    }
-    std::vector<double> load(K, 0.0);
-    he_status st = HE_OK;
-    for (int t : order) {
-        const int i = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[i] += tasks[t].cost;
-        c->stream = K > 1 ? c->lane[i] : main;
-        st = tasks[t].run(lane_ar[i]);
-        c->stream = main;
-        if (st != HE_OK) break;
-    }
-    if (K > 1) {  // joined even after an error, so that no lane is left behind (or outside a capture)
-        for (int i = 0; i < K; ++i) {
-            HIPCHK(hipEventRecord(c->lane_ev[i], c->lane[i]));
-            HIPCHK(hipStreamWaitEvent(main, c->lane_ev[i], 0));
-        }
-    }
-    TRY(st);
+    TRY(lanes_run(c, pl.lanes, tasks));
     // every result to its out: one launch
     hek::desc_ew(c, 4, tab + o_out, ly.n_out, ly.max_limbs, limbs(o_out, ly.n_out));
     return last_error();
@@ -2539,13 +2590,7 @@ he_status he_batch_submit(he_ctx *c, he_op *ops, int n, const he_keys *k, int mo
     std::memcpy(c->sub_host, ly.tab.data(), tb);
     HIPCHK(hipMemcpyAsync(c->ws, c->sub_host, tb, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipEventRecord(c->sub_ev, c->stream));
-    if (pl.lanes > 1 && !c->fork_ev) {  // the lanes' streams and events, made once (outside any capture)
-        HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
-        for (int i = 0; i < he_ctx::SUBMIT_LANES; ++i) {
-            HIPCHK(hipStreamCreateWithFlags(&c->lane[i], hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&c->lane_ev[i], hipEventDisableTiming));
-        }
-    }
+    if (pl.lanes > 1) TRY(lanes_ready(c));
     if (mode == 2) {
         std::ostringstream key;
         key << "submit:" << n << ':' << k->gen << ':' << (const void *)k->sk << ':' << (const void *)c->ws;
