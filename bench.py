@@ -74,6 +74,11 @@ def parse():
                     help="run only the headline schedule (feature-major, graph form): one warm-up refresh period, "
                          "then --steps timed steps between two marker fills (a target for rocprofv3 "
                          "--kernel-trace: the markers delimit the timed steps); prints no bench line")
+    ap.add_argument("--configs", action="store_true",
+                    help="CPU baseline of the other configurations (the oracle beside the GPU): the small workload's "
+                         "full step, a 16-operation sample of the 256 mixed operations, per-request and per-block "
+                         "samples of serving and of the large shard, each extrapolated and labelled; prints one "
+                         "JSON line of them instead of the bench line")
     ap.add_argument("--ks-counters", action="store_true",
                     help="run only the calibration copy and 3 batched multiply-relinearise-rescale-rotate launches "
                          "over 32 ciphertexts at level 18 (key-switch kernels at the step's top-level shape, "
@@ -440,6 +445,9 @@ def main():
     from paper_2006_10091_amd import train as T
 
     torch.cuda.set_device(0)
+    if args.configs:
+        print(json.dumps({"config_baselines": config_baselines(torch, H, args.cpu_threads)}), flush=True)
+        return
     Wk = synth.WORKLOADS["image"]
     ctx = H.Context(Wk["logN"], Wk["nq"], Wk["nk"], Wk["alpha"], Wk["log_delta"])
     S = ctx.S
@@ -546,6 +554,188 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(Wk, args.cpu_threads, nb, c, r, best["n_baby"])
     print(json.dumps(out), flush=True)
+
+
+def config_baselines(torch, H, threads):
+    """The oracle (all host threads; median of 3 where the run is short, one
+    run for the larger samples) beside the GPU on the configurations other
+    than the bench's own:
+      * small workload (2048 x 16, N=2^13): one full gradient step, oracle
+        and GPU (graph form, median of 20), and the oracle on one thread;
+      * 256 mixed operations: the oracle on the first 16 of the seeded
+        operations (mixed N and levels), extrapolated to 256; the GPU on all
+        256 (he_batch_submit, median of 5);
+      * serving: the oracle's row-major step and inference (the margins) for
+        the median request (n = 2896 rows, d = 90 features) at N = 2^15 and
+        2^16 on the 8 + 4 chain, from 1- and 2-block runs (per block, plus
+        the fixed part) scaled to the request's blocks;
+      * large shard (2^20 x 512, 24 + 6 primes): the oracle's step at level
+        23 from 1- and 2-block runs, scaled to 16384 blocks; the GPU on 64
+        seeded blocks (one chunk) at level 23, scaled the same way.
+    Every extrapolated figure says so."""
+    from oracle import ckks as O
+    from oracle import lr as LR
+    from paper_2006_10091_amd import batch_ops as BO
+    from paper_2006_10091_amd import large_shard as LS
+    from paper_2006_10091_amd import synth
+    if threads:
+        O.lib().orc_set_threads(threads)
+    nth = int(O.lib().orc_max_threads())
+    coef = coef_binomial()
+    out = {"cores": nth, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(), "kind": "oracle"}
+
+    def med(fn, k=3):
+        ts = []
+        for _ in range(k):
+            t = time.time()
+            fn()
+            ts.append(time.time() - t)
+        return float(np.median(ts))
+
+    def oracle_step_time(P, ok, X, y, level, eta_n):
+        """seconds of the oracle's row-major step on the blocks of X at level"""
+        blocks, c, r = LR.pack_blocks(X, y, P.S)
+        Z = [O.encrypt_sk(P, ok, O.encode(blocks[i], P.delta, P.N), level, P.delta, 5, i) for i in range(len(blocks))]
+        W = O.encrypt_sk(P, ok, O.encode(LR.pack_weights(np.zeros(X.shape[1]), P.S, c), P.delta, P.N), level,
+                         P.delta, 5, 1 << 20)
+        pl = LR.plan_lr_step(P.q, level, P.delta, P.delta, coef, eta_n)
+        mm = O.encode(LR.column_mask(P.S, c), pl["s_mask"], P.N)
+        t = time.time()
+        LR.lr_grad_step(P, ok, Z, W, mm, coef, eta_n, c, r, plan=pl)
+        return time.time() - t
+
+    # small workload: one full step
+    Wk = synth.WORKLOADS["small"]
+    cfg = (Wk["logN"], Wk["nq"], Wk["nk"], Wk["alpha"], Wk["log_delta"])
+    P = O.Params(*cfg)
+    X, y = synth.small_data()
+    blocks, c, r = LR.pack_blocks(X, y, P.S)
+    steps = LR.rotation_steps(c, r)
+    ok = O.Keys(P, Wk["seed_keys"], rot_steps=steps)
+    eta_n = 1.0 / X.shape[0]
+    w0 = synth.initial_weights("small", X.shape[1], Wk["seed_w"])
+    ms = [O.encode(blocks[i], P.delta, P.N) for i in range(blocks.shape[0])]
+    mw = O.encode(LR.pack_weights(w0, P.S, c), P.delta, P.N)
+    oZ = [O.encrypt_sk(P, ok, m, P.L, P.delta, 5, i) for i, m in enumerate(ms)]
+    oW = O.encrypt_sk(P, ok, mw, P.L, P.delta, 5, 1000)
+    pl = LR.plan_lr_step(P.q, P.L, P.delta, P.delta, coef, eta_n)
+    mm = O.encode(LR.column_mask(P.S, c), pl["s_mask"], P.N)
+    t_cpu = med(lambda: LR.lr_grad_step(P, ok, oZ, oW, mm, coef, eta_n, c, r, plan=pl))
+    O.lib().orc_set_threads(1)
+    t_cpu1 = med(lambda: LR.lr_grad_step(P, ok, oZ, oW, mm, coef, eta_n, c, r, plan=pl))
+    O.lib().orc_set_threads(nth)
+    ctx = H.Context(*cfg)
+    gk = ctx.keygen(Wk["seed_keys"], steps)
+    gZ = ctx.ct_block(len(ms), P.L)
+    for i, m in enumerate(ms):
+        ctx.encrypt(ctx.pt_load(m, P.L, P.delta), gk, 5, i, out=gZ[i])
+    gW = ctx.encrypt(ctx.pt_load(mw, P.L, P.delta), gk, 5, 1000)
+    gm = ctx.pt_load(mm, P.L - 1, pl["s_mask"])
+
+    def gstep():
+        ctx.lr_grad_step(gZ, gW, gm, coef, eta_n, c, r, gk, mode=2)
+        torch.cuda.synchronize()
+    gstep()
+    t_gpu = med(gstep, 20)
+    out["small_step"] = {"blocks": len(ms), "cpu_s": t_cpu, "cpu_s_one_thread": t_cpu1, "gpu_ms": t_gpu * 1e3,
+                         "gpu_over_cpu": t_cpu / t_gpu, "runs": "median of 3 (CPU), 20 (GPU)"}
+    log("small workload, one step: oracle %.3f s (%.3f s one thread), GPU %.3f ms" % (t_cpu, t_cpu1, t_gpu * 1e3))
+    del ctx, gk, gZ, gW, gm
+
+    # 256 mixed operations: the oracle on the first 16
+    log("configurations: 256 mixed operations ..." )
+    ops = BO.draw_ops(256)
+    b = BO.Batch(ops)
+    b.run_submit(1)
+    torch.cuda.synchronize()
+
+    def gbatch():
+        b.run_submit(1)
+        torch.cuda.synchronize()
+    t_gpu = med(gbatch, 5)
+    cache = {}
+    t_cpu = 0.0
+    for i in range(16):
+        log_n, level, step = ops[i]
+        key = ("P", log_n)
+        if key not in cache:
+            cache[key] = O.Params(log_n, BO.CHAIN["n_q"], BO.CHAIN["n_special"], BO.CHAIN["alpha"],
+                                  BO.CHAIN["log_delta"])
+        Pn = cache[key]
+        okn = O.Keys(Pn, 2003 + log_n, rot_steps=[step])
+        j = b.idx[log_n].index(i)
+        x = O.CT(b.ctx[log_n].download(b.x[log_n][j]), level, 1.0)
+        z = O.CT(b.ctx[log_n].download(b.y[log_n][j]), level, 1.0)
+        t = time.time()
+        O.rotate(Pn, O.rescale(Pn, O.mul(Pn, x, z, okn)), step, okn)
+        t_cpu += time.time() - t
+    out["mixed_ops"] = {"ops": 256, "cpu_ops_timed": 16, "cpu_s_per_op": t_cpu / 16,
+                        "cpu_ops_per_s": 16 / t_cpu, "gpu_ms_per_256": t_gpu * 1e3, "gpu_ops_per_s": 256 / t_gpu,
+                        "extrapolated": True, "runs": "one run per sampled op (CPU), median of 5 (GPU)"}
+    log("256 mixed operations: oracle %.3f s per op (16 timed, extrapolated: %.1f ops/s), GPU %.2f ms (%.0f ops/s)"
+        % (t_cpu / 16, 16 / t_cpu, t_gpu * 1e3, 256 / t_gpu))
+    del b
+
+    # serving: the median request, step and inference, at both ring degrees
+    log("configurations: serving requests ..." )
+    n_med, d_med = 2896, 90
+    g = synth.rng(7007)
+    Xr = g.uniform(-1, 1, (n_med, d_med))
+    yr = np.where(Xr @ g.standard_normal(d_med) >= 0, 1.0, -1.0)
+    reqs = {}
+    for log_n in (15, 16):
+        cfg = (log_n, 8, 4, 4, 40)
+        Pn = O.Params(*cfg)
+        c = 1 << int(np.ceil(np.log2(d_med)))
+        r = Pn.S // c
+        nblk = -(-n_med // r)
+        okn = O.Keys(Pn, 2100 + log_n, rot_steps=LR.rotation_steps(c, r))
+        t1 = oracle_step_time(Pn, okn, Xr[:r], yr[:r], Pn.L, 1.0 / n_med)
+        t2 = oracle_step_time(Pn, okn, Xr[:2 * r], yr[:2 * r], Pn.L, 1.0 / n_med)
+        reqs["step_2^%d" % log_n] = {"blocks": nblk, "cpu_s": t1 + (nblk - 1) * max(t2 - t1, 0.0)}
+        bl, _, _ = LR.pack_blocks(Xr[:2 * r], yr[:2 * r], Pn.S)
+        Zi = [O.encrypt_sk(Pn, okn, O.encode(bl[k], Pn.delta, Pn.N), Pn.L, Pn.delta, 5, k) for k in range(2)]
+        Wi = O.encrypt_sk(Pn, okn, O.encode(LR.pack_weights(np.zeros(d_med), Pn.S, c), Pn.delta, Pn.N), Pn.L,
+                          Pn.delta, 5, 99)
+        t = time.time()
+        LR.lr_margins(Pn, okn, Zi[:1], Wi, c, r)
+        ti1 = time.time() - t
+        t = time.time()
+        LR.lr_margins(Pn, okn, Zi, Wi, c, r)
+        ti2 = time.time() - t
+        reqs["inference_2^%d" % log_n] = {"blocks": nblk, "cpu_s": ti1 + (nblk - 1) * max(ti2 - ti1, 0.0)}
+    mean = float(np.mean([v["cpu_s"] for v in reqs.values()]))
+    out["serving"] = {"request": "median shape n=%d, d=%d; 8+4 primes" % (n_med, d_med), "per_request": reqs,
+                      "cpu_requests_per_s": 1.0 / mean, "extrapolated": True,
+                      "runs": "1- and 2-block runs scaled to the request's blocks (one run each)"}
+    log("serving, median request: oracle %.2f s mean over step/inference x N (%.3f req/s, extrapolated)" % (
+        mean, 1.0 / mean))
+
+    # large shard: per-block cost at level 23
+    log("configurations: large shard ..." )
+    Wl = synth.WORKLOADS["large"]
+    cfg = (Wl["logN"], Wl["nq"], Wl["nk"], Wl["alpha"], Wl["log_delta"])
+    Pl = O.Params(*cfg)
+    c = Wl["d"]
+    r = Pl.S // c
+    Xs, ys = synth.large_block(Wl["seed_data"], 0, 2 * r, c)
+    eta_n = 1.0 / Wl["n"]
+    okl = O.Keys(Pl, Wl["seed_keys"], rot_steps=LR.rotation_steps(c, r))
+    t1 = oracle_step_time(Pl, okl, Xs[:r], ys[:r], Pl.L, eta_n)
+    t2 = oracle_step_time(Pl, okl, Xs, ys, Pl.L, eta_n)
+    nb = Wl["n"] // r
+    cpu_step = t1 + (nb - 1) * max(t2 - t1, 0.0)
+    res = LS.run(n_blocks=64, steps=1, chunk=64)
+    gpu_step = res["ms_per_step"] * 1e-3 * nb / 64
+    out["large_shard"] = {"blocks": nb, "level": Pl.L, "cpu_s_per_step": cpu_step, "cpu_steps_per_s": 1.0 / cpu_step,
+                          "gpu_s_per_step_64_blocks": res["ms_per_step"] * 1e-3,
+                          "gpu_s_per_step_scaled": gpu_step, "gpu_over_cpu": cpu_step / gpu_step,
+                          "extrapolated": True,
+                          "runs": "oracle: 1- and 2-block steps at level %d scaled to %d blocks; GPU: one 64-block "
+                                  "chunk scaled the same way" % (Pl.L, nb)}
+    log("large shard step at level %d: oracle %.0f s (extrapolated from 1- and 2-block runs), GPU %.1f s (64 blocks "
+        "scaled)" % (Pl.L, cpu_step, gpu_step))
+    return out
 
 
 def cpu_model():
