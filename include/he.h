@@ -366,11 +366,17 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  * (slots i*c) at W's level - 1, for HE_LAYOUT_FEATURES the indicator of
  * slots j*r at W's level - 3; keys with the relinearisation key and the
  * rotations: rows -- +-2^k (2^k < c) and c*2^k (2^k < r); features -- r*2^k
- * (2^k < c) and +-2^k (2^k < r).  Row-major: per block, column sum, mask and
- * replicate, polynomial; row sum once per step.  Feature-major: per block, a
- * cyclic sum over the feature blocks leaves m_i in every slot of sample i, then
- * the polynomial; once per step, the sum inside each feature block, the mask
- * and the replication over the block.  In the polynomial, A = M^2 and
+ * (2^k < c) and +-j*2^b for the index groups of the slot sums below.
+ * Row-major: per block, column sum, mask and replicate, polynomial; row sum
+ * once per step.  Feature-major: per block, a cyclic sum over the feature
+ * blocks leaves m_i in every slot of sample i, then the polynomial; once per
+ * step, the sum inside each feature block, the mask and the replication over
+ * the block.  Those two slot sums over r = 2^k slots are taken as one hoisted
+ * sum (one ModUp, one ModDown) per group of index bits: the k bits in
+ * ceil(k/3) groups of sizes differing by at most one, smaller groups on the
+ * low bits; a group of s bits from bit b adds the rotations +-j*2^b,
+ * j = 1 .. 2^s - 1 (r = 128: {1,2,3}, {4,8,12}, {16,..,112}).  In the
+ * polynomial, A = M^2 and
  * B3 = M (a3 Z) are rescaled but not relinearised; the terms (degree 4 in the
  * secret) are summed over the blocks and relinearised once per step with the
  * keys for s^2, s^3 and s^4, then rescaled.
@@ -647,7 +653,7 @@ enum {
     HE_K_NTT_FWD_COLS = 0, HE_K_NTT_FWD_ROWS, HE_K_NTT_INV_ROWS, HE_K_NTT_INV_COLS, HE_K_NTT_ONE_LAUNCH,
     HE_K_MD_CONV, HE_K_MD_FINISH, HE_K_MD_LAST, HE_K_KS_COLS, HE_K_KS_ROWS, HE_K_MODUP,
     HE_K_GIANT_FP64, HE_K_GIANT_INT, HE_K_ROT_INNER, HE_K_BABY_SUM, HE_K_TERMS_SUM, HE_K_TENSOR,
-    HE_K_ELEMENTWISE, HE_K_AUTOMORPH, HE_K_OTHER, HE_K_COUNT
+    HE_K_ELEMENTWISE, HE_K_AUTOMORPH, HE_K_GIANT_GATHER, HE_K_OTHER, HE_K_COUNT
 };
 
 /* One kernel kind's launches since the trace was switched on. */

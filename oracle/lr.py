@@ -282,12 +282,37 @@ def giant_hoisted(c, layout, n_baby):
     return layout == FEATURES and 1 < n_baby < c and c // n_baby <= GIANT_MAX
 
 
+def slot_sum_groups(r):
+    """Reading 28: the feature-major step's two slot sums over r = 2^k slots
+    (inside each feature block, and the replication) are taken as one
+    hoisted sum per group of index bits.  The k bits split into
+    ceil(k / 3) groups whose sizes differ by at most one, the smaller
+    groups on the low bits; a group of s bits starting at bit b contributes
+    the rotations j * 2^b for j = 1 .. 2^s - 1.  Summing over every group in
+    turn covers each index i < r exactly once (its base-2^s digits)."""
+    k = 0
+    while (1 << k) < r:
+        k += 1
+    groups = []
+    if k == 0:
+        return groups
+    ng = -(-k // 3)
+    sizes = [k // ng] * ng
+    for i in range(k % ng):
+        sizes[ng - 1 - i] += 1
+    b = 0
+    for s in sizes:
+        groups.append([j * (1 << b) for j in range(1, 1 << s)])
+        b += s
+    return groups
+
+
 def rotation_steps(c, r, layout=ROWS, n_baby=1):
     """Rotation steps used by the step.  Row-major: +-2^k (k < log2 c) and
-    c*2^k (k < log2 r).  Feature-major: r*2^k (k < log2 c) and +-2^k
-    (k < log2 r).  With n_baby > 1 baby steps also b*u for b < n_baby (u = r
-    feature-major, 1 row-major), and for a hoisted giant sum the steps
-    g n_baby r, g < c / n_baby."""
+    c*2^k (k < log2 r).  Feature-major: r*2^k (k < log2 c) and +-t for the
+    steps t of slot_sum_groups(r).  With n_baby > 1 baby steps also b*u for
+    b < n_baby (u = r feature-major, 1 row-major), and for a hoisted giant
+    sum the steps g n_baby r, g < c / n_baby."""
     if layout == FEATURES:
         st = [b * r for b in range(3, n_baby) if b & (b - 1)]
         if giant_hoisted(c, layout, n_baby):
@@ -296,10 +321,9 @@ def rotation_steps(c, r, layout=ROWS, n_baby=1):
         while t < c:
             st.append(t * r)
             t *= 2
-        t = 1
-        while t < r:
-            st += [t, -t]
-            t *= 2
+        for grp in slot_sum_groups(r):
+            for t in grp:
+                st += [t, -t]
         return st
     st = [b for b in range(3, n_baby) if b & (b - 1)]
     t = 1
@@ -432,16 +456,12 @@ def _step_features(P, keys, Z, W, mask_m, c, r, pl, Zrot=None, n_baby=1):
         G = Gb if G is None else O.add_n(P, l - 2, G, Gb)
     # one relinearisation and one rescale of the summed terms
     G = O.rescale(P, O.relin_n(P, G, pl["sC"] * float(P.q[l - 2]), l - 2, keys), scale=pl["sC"])
-    t = 1
-    while t < r:  # sum over the samples inside each feature block
-        G = O.add(P, G, O.rotate(P, G, t, keys))
-        t *= 2
+    for grp in slot_sum_groups(r):  # sum over the samples inside each feature block (reading 28)
+        G = O.rotate_sum_hoisted(P, G, grp, keys)
     G = O.CT(G.data, G.level, pl["s_gsum"])
     g = O.rescale(P, O.mul_plain(P, G, mask_m, pl["s_mask"]), scale=pl["s_g"])
-    t = 1
-    while t < r:  # replicate g_j over its feature block
-        g = O.add(P, g, O.rotate(P, g, -t, keys))
-        t *= 2
+    for grp in slot_sum_groups(r):  # replicate g_j over its feature block
+        g = O.rotate_sum_hoisted(P, g, [-t for t in grp], keys)
     Wn = O.rescale(P, O.mul_int(P, O.drop(W, l - 3), pl["kW"]), scale=pl["s_g"])
     return O.add(P, Wn, g), g
 

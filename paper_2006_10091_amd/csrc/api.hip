@@ -927,6 +927,58 @@ he_status rotate_sum(he_ctx *c, Arena &ar, int level, u64 *x, u64 *tmp, long lon
     return rotate_sum_b(c, ar, level, 1, x, 2LL * (level + 1) * c->N, unit, count, keys);
 }
 
+// The rotation-index groups of a slot sum over count = 2^k slots: the k bits
+// of the index in ceil(k / 3) groups, sizes as even as possible (the smaller
+// ones first), low bits first.  Group i is {b0, s}: it adds the rotations by
+// j 2^b0, j = 1 .. 2^s - 1.  Returns the number of groups (at most 11).
+static int slot_sum_groups(int count, int (*g)[2])
+{
+    int k = 0;
+    while ((1 << k) < count) ++k;
+    if (k == 0) return 0;
+    const int ng = (k + 2) / 3, q = k / ng, rem = k % ng;
+    int b0 = 0;
+    for (int i = 0; i < ng; ++i) {
+        const int sz = q + (i >= ng - rem ? 1 : 0);
+        g[i][0] = b0;
+        g[i][1] = sz;
+        b0 += sz;
+    }
+    return ng;
+}
+
+// x <- sum_{i < count} Rot(x, sign i) on B ciphertexts at `level` (batch
+// stride xs; count a power of two), one hoisted sum per index group of
+// slot_sum_groups: the group's rotations share one ModUp and one ModDown.  The
+// running sum alternates between x and tmp (B ciphertexts, batch stride ts)
+// and ends in x.
+he_status slot_sum_hoisted(he_ctx *c, Arena &ar, int level, int B, u64 *x, long long xs, u64 *tmp, long long ts,
+                           int sign, int count, const he_keys *keys)
+{
+    int grp[11][2];
+    const int ng = slot_sum_groups(count, grp);
+    u64 *in = x, *out = tmp;
+    long long is = xs, os = ts;
+    for (int i = 0; i < ng; ++i) {
+        const int n = (1 << grp[i][1]) - 1;
+        hek::EntryGal eg;
+        hek::EntryKeys ek;
+        for (int j = 1; j <= n; ++j) {
+            eg.g[j - 1] = galois_of(c, (long long)sign * ((long long)j << grp[i][0]));
+            ek.k[j - 1] = find_rot_key(keys, eg.g[j - 1]);
+            if (!ek.k[j - 1]) return HE_EKEY;
+        }
+        TRY(rotate_sum_hoisted_apply(c, ar, level, B, in, is, eg, ek, n, out, os));
+        std::swap(in, out);
+        std::swap(is, os);
+    }
+    if (in != x) {
+        const long long lc = (long long)(level + 1) * c->N;
+        hek::ewise(c, 4, level, B, 2, in, is, lc, nullptr, 0, 0, x, xs, lc, 0);
+    }
+    return last_error();
+}
+
 // Run `body` captured into a HIP graph on first use of `key` and replayed
 // after that, on the context's private stream ordered after and before the
 // caller's stream by events.  Buffers must not move between replays (the key
@@ -1219,10 +1271,10 @@ he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_block
         // sum inside each feature block (level l-3), mask slots j r, rescale to
         // level l-4, replicate over the block
         const long long h1 = (long long)(l - 2) * N;
-        TRY(rotate_sum(c, ar, l - 3, s.G, s.Rg, 1, rows, keys));
+        TRY(slot_sum_hoisted(c, ar, l - 3, 1, s.G, 2 * h1, s.Rg, 2 * h1, +1, rows, keys));
         hek::ewise(c, 3, l - 3, 1, 2, s.G, 2 * h1, h1, mask->data, 0, 0, s.G, 2 * h1, h1, 0);
         TRY(rescale_apply(c, ar, l - 3, 1, s.G, 2 * h1, s.Gm, 2 * g1));
-        TRY(rotate_sum(c, ar, l - 4, s.Gm, s.Rg, -1, rows, keys));
+        TRY(slot_sum_hoisted(c, ar, l - 4, 1, s.Gm, 2 * g1, s.Rg, 2 * g1, -1, rows, keys));
         g = s.Gm;
     } else {
         // row sum: G += Rot(G, t * cols), t = 1, 2, .., rows/2   (level l-4)
@@ -2727,10 +2779,11 @@ static he_status multi_impl(he_ctx *c, const he_lr_request *rq, int n, const std
     TRY(rescale_apply(c, ar, lg, n, m.U0, 2 * x1, m.G, 2 * r1));
     if (fm) {
         // sum inside each feature block, mask slots j r, rescale, replicate
-        TRY(rotate_sum_b(c, ar, l - 3, n, m.G, 2 * r1, 1, rows, k));
+        // (m.Wk, written only by the W update below, holds the sums' other half)
+        TRY(slot_sum_hoisted(c, ar, l - 3, n, m.G, 2 * r1, m.Wk, 2 * r1, +1, rows, k));
         hek::desc_ew(c, 3, m.tab + t_mask, n, l - 2);
         TRY(rescale_apply(c, ar, l - 3, n, m.G, 2 * r1, m.Gm, 2 * g1));
-        TRY(rotate_sum_b(c, ar, l - 4, n, m.Gm, 2 * g1, -1, rows, k));
+        TRY(slot_sum_hoisted(c, ar, l - 4, n, m.Gm, 2 * g1, m.Wk, 2 * g1, -1, rows, k));
     } else {
         TRY(rotate_sum_b(c, ar, l - 4, n, m.G, 2 * r1, cols, rows, k));  // row sum
     }
@@ -2978,7 +3031,8 @@ const char *he_kernel_kind_name(int kind)
         "forward row pass + moddown/rescale finish", "moddown last limb", "key-switch digits' column pass",
         "key-switch row pass + key inner product", "modup conversion", "hoisted rotation sum, FP64 positions",
         "hoisted rotation sum, 60-bit positions", "rotation inner products (shared modup)", "baby-step products",
-        "gradient terms sum", "tensor product", "elementwise", "automorphism", "other"};
+        "gradient terms sum", "tensor product", "elementwise", "automorphism",
+        "hoisted rotation sum, gathered (steps not tile-local)", "other"};
     return kind >= 0 && kind < HE_K_COUNT ? names[kind] : "?";
 }
 

@@ -3434,7 +3434,7 @@ static void giant_gather_b(he_ctx *c, int level, int B, const u64 *ext, long lon
     double bf, mf, bi, mi;
     giant_work(c, level, B, ng, true, &bf, &mf);
     giant_work(c, level, B, ng, false, &bi, &mi);
-    KSpan ks(c, HE_K_OTHER, bf + bi, mf, mi);
+    KSpan ks(c, HE_K_GIANT_GATHER, bf + bi, mf, mi);
     giant_gather_kernel<<<dim3((unsigned)nwg, 1, 1), 256, 0, c->stream>>>(a, c->t.pinfo);
 }
 

@@ -85,7 +85,7 @@ class he_kernel_stat(ctypes.Structure):
 # kernel kinds of the trace (HE_K_*)
 (K_NTT_FWD_COLS, K_NTT_FWD_ROWS, K_NTT_INV_ROWS, K_NTT_INV_COLS, K_NTT_ONE_LAUNCH, K_MD_CONV, K_MD_FINISH,
  K_MD_LAST, K_KS_COLS, K_KS_ROWS, K_MODUP, K_GIANT_FP64, K_GIANT_INT, K_ROT_INNER, K_BABY_SUM, K_TERMS_SUM,
- K_TENSOR, K_ELEMENTWISE, K_AUTOMORPH, K_OTHER, K_COUNT) = range(21)
+ K_TENSOR, K_ELEMENTWISE, K_AUTOMORPH, K_GIANT_GATHER, K_OTHER, K_COUNT) = range(22)
 
 LAYOUT_ROWS, LAYOUT_FEATURES = 0, 1  # HE_LAYOUT_ROWS / HE_LAYOUT_FEATURES
 NOALLOC_SCRATCH_BYTES = 64 << 20  # HE_NOALLOC_SCRATCH_BYTES
@@ -838,19 +838,45 @@ def giant_hoisted(layout, c, n_baby):
     return layout == LAYOUT_FEATURES and 1 < n_baby < c and c // n_baby <= GIANT_MAX
 
 
+def slot_sum_groups(count):
+    """The rotation-index groups of he_lr_grad_step's feature-major slot sums
+    over count = 2^k slots (one hoisted sum per group): the k bits of the
+    index in ceil(k / 3) groups, sizes as even as possible (the smaller ones
+    first), low bits first; a group of s bits from bit b0 holds the
+    rotations j 2^b0, j = 1 .. 2^s - 1."""
+    k = int(count).bit_length() - 1
+    if k <= 0:
+        return []
+    ng = (k + 2) // 3
+    q, rem = divmod(k, ng)
+    out, b0 = [], 0
+    for i in range(ng):
+        size = q + (1 if i >= ng - rem else 0)
+        out.append([j << b0 for j in range(1, 1 << size)])
+        b0 += size
+    return out
+
+
 def rotation_steps(c, r, layout=LAYOUT_ROWS, n_baby=1):
     """Rotation keys the step needs (with n_baby baby steps also j u, j < n_baby,
     u = baby_unit(layout, r); with a hoisted giant sum also g n_baby r,
-    g < c / n_baby)."""
+    g < c / n_baby).  Row-major: +-2^k (k < log2 c) and c 2^k (k < log2 r);
+    feature-major: r 2^k (k < log2 c) and +-t for every t of
+    slot_sum_groups(r)."""
     pm, st, unit = (r, c, r) if layout == LAYOUT_FEATURES else (c, r, c)
     mu = baby_unit(layout, r)
     out = [j * mu for j in range(3, n_baby) if j & (j - 1)]
     if giant_hoisted(layout, c, n_baby):
         out += [g * n_baby * r for g in range(3, c // n_baby) if g & (g - 1)]
-    t = 1
-    while t < pm:
-        out += [t, -t]
-        t *= 2
+    if layout == LAYOUT_FEATURES:
+        for grp in slot_sum_groups(pm):
+            for t in grp:
+                out += [t, -t]
+    else:
+        t = 1
+        while t < pm:
+            out += [t, -t]
+            t *= 2
     t = 1
     while t < st:
         out.append(t * unit)

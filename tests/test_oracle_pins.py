@@ -666,16 +666,60 @@ def test_feature_major_packing_is_the_transpose():
     assert pw[0 * r + 7] == 1.0 and pw[9 * r + 200] == 10.0 and pw[12 * r] == 0.0
     assert np.flatnonzero(LR.feature_mask(4096, r)).tolist() == [j * r for j in range(16)]
     st = LR.rotation_steps(c, r, LR.FEATURES)
-    assert st[:4] == [256, 512, 1024, 2048] and sorted(st[4:]) == sorted([t * s for t in (1, 2, 4, 8, 16, 32, 64, 128)
-                                                                          for s in (1, -1)])
+    # the slot sums over r = 256 = 2^8 slots: index bits in groups of 2, 3, 3
+    slot = [1, 2, 3, 4, 8, 12, 16, 20, 24, 28, 32, 64, 96, 128, 160, 192, 224]
+    assert st[:4] == [256, 512, 1024, 2048] and sorted(st[4:]) == sorted([t * s for t in slot for s in (1, -1)])
+    assert LR.slot_sum_groups(256) == [slot[:3], slot[3:10], slot[10:]]
     # baby steps b r for every b < n_baby, giant steps g n_baby r for every g < c / n_baby (hoisted)
     st8 = LR.rotation_steps(c, r, LR.FEATURES, 8)
-    assert {b * r for b in range(1, 8)} <= set(st8) and 8 * r in st8 and len(st8) == len(set(st8)) == 7 + 1 + 16
+    assert {b * r for b in range(1, 8)} <= set(st8) and 8 * r in st8 and len(st8) == len(set(st8)) == 7 + 1 + 34
     st4 = LR.rotation_steps(c, r, LR.FEATURES, 4)
     assert {b * r for b in range(1, 4)} | {g * 4 * r for g in range(1, 4)} <= set(st4)
-    assert len(st4) == len(set(st4)) == 3 + 3 + 16
+    assert len(st4) == len(set(st4)) == 3 + 3 + 34
     assert LR.giant_hoisted(c, LR.FEATURES, 4) and not LR.giant_hoisted(c, LR.FEATURES, 16)
     assert not LR.giant_hoisted(c, LR.ROWS, 4) and not LR.giant_hoisted(256, LR.FEATURES, 8)
+
+
+def test_slot_sum_groups_cover_every_index_once():
+    """Reading 28's grouping: for r = 2^k, summing Rot(., t) over each
+    group in turn adds every rotation index i < r exactly once (each i is
+    one combination of the groups' digits), the groups' sizes differ by at
+    most one with the smaller groups on the low bits, and there are
+    ceil(k / 3) of them."""
+    for k in range(0, 12):
+        r = 1 << k
+        groups = LR.slot_sum_groups(r)
+        assert len(groups) == -(-k // 3)
+        counts = {0: 1}
+        for g in groups:
+            nxt = {}
+            for i, m in counts.items():
+                for t in [0] + g:
+                    nxt[i + t] = nxt.get(i + t, 0) + m
+            counts = nxt
+        assert counts == {i: 1 for i in range(r)}, k
+        sizes = [len(g).bit_length() for g in groups]
+        assert sizes == sorted(sizes) and (not sizes or max(sizes) - min(sizes) <= 1)
+
+
+def test_grouped_slot_sums_decrypt_to_the_block_sums():
+    """The feature-major step's slot sum as grouped hoisted sums (reading 28)
+    decrypts to the same values as the plain rotate-and-add doubling: in
+    every slot, the sum of the next r slots (cyclically), within the key
+    switch noise; and the replication (negative steps) the same backwards."""
+    P = O.Params(*SMALL40)
+    r = 64
+    keys = O.Keys(P, 11, rot_steps=sorted({t * s for g in LR.slot_sum_groups(r) for t in g for s in (1, -1)}))
+    g0 = np.random.default_rng(5)
+    v = g0.uniform(-1, 1, P.S)
+    x = O.encrypt_sk(P, keys, O.encode(v, P.delta, P.N), 3, P.delta, 9, 0)
+    for sign in (1, -1):
+        y = x
+        for grp in LR.slot_sum_groups(r):
+            y = O.rotate_sum_hoisted(P, y, [sign * t for t in grp], keys)
+        got = O.decrypt(P, keys, y).real
+        want = sum(np.roll(v, -sign * i) for i in range(r))
+        assert np.max(np.abs(got - want)) < 1e-6, sign
 
 
 def test_baby_giant_margins_equal_the_rotation_sum():
