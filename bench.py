@@ -508,7 +508,7 @@ def main():
             log("  %-50s %4d launches %8.2f ms %5.1f%%  %s" % (
                 row["kernel"], row["launches"], row["ms"], 100 * row["share"],
                 " ".join("%s %.3f" % (k, row[k]) for k in ("frac_hbm", "frac_valu") if k in row)))
-    ops = measure_ops(torch, H, synth, ctx, ev, nb, c, r, max(args.baby, 1))
+    ops = measure_ops(torch, H, synth, ctx, ev, nb, c, r, 16)  # the headline's giant sum, whatever --baby
     sweep = ntt_sweep(torch, H, ev)
 
     out = {

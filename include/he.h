@@ -365,18 +365,21 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  * he_plan_lr_step gives as s_mask: for HE_LAYOUT_ROWS the column-0 indicator
  * (slots i*c) at W's level - 1, for HE_LAYOUT_FEATURES the indicator of
  * slots j*r at W's level - 3; keys with the relinearisation key and the
- * rotations: rows -- +-2^k (2^k < c) and c*2^k (2^k < r); features -- r*2^k
- * (2^k < c) and +-j*2^b for the index groups of the slot sums below.
- * Row-major: per block, column sum, mask and replicate, polynomial; row sum
- * once per step.  Feature-major: per block, a cyclic sum over the feature
- * blocks leaves m_i in every slot of sample i, then the polynomial; once per
- * step, the sum inside each feature block, the mask and the replication over
- * the block.  Those two slot sums over r = 2^k slots are taken as one hoisted
- * sum (one ModUp, one ModDown) per group of index bits: the k bits in
- * ceil(k/3) groups of sizes differing by at most one, smaller groups on the
- * low bits; a group of s bits from bit b adds the rotations +-j*2^b,
- * j = 1 .. 2^s - 1 (r = 128: {1,2,3}, {4,8,12}, {16,..,112}).  In the
- * polynomial, A = M^2 and
+ * rotations the slot sums below take (he_lr_grad_step checks them all before
+ * any launch, HE_EKEY when one is absent).
+ * Row-major: per block, the column sum, mask and replication over the row,
+ * polynomial; the row sum once per step.  Feature-major: per block, a cyclic
+ * sum over the feature blocks leaves m_i in every slot of sample i, then the
+ * polynomial; once per step, the sum inside each feature block, the mask and
+ * the replication over the block.  A slot sum of 2^k rotations by multiples
+ * of a unit u (row-major: column sum u = n_baby over c / n_baby terms,
+ * replication u = -1 over c, row sum u = c over r; feature-major: sample sum
+ * u = 1 and replication u = -1 over r) is taken as one hoisted sum (one
+ * ModUp, one ModDown) per group of index bits: the k bits in ceil(k/3) groups
+ * of sizes differing by at most one, smaller groups on the low bits; a group
+ * of s bits from bit b adds the rotations j*2^b*u, j = 1 .. 2^s - 1 (2^k = 128:
+ * {1,2,3}, {4,8,12}, {16,..,112} times u).  The keys are those rotations.  In
+ * the polynomial, A = M^2 and
  * B3 = M (a3 Z) are rescaled but not relinearised; the terms (degree 4 in the
  * secret) are summed over the blocks and relinearised once per step with the
  * keys for s^2, s^3 and s^4, then rescaled.
@@ -388,13 +391,15 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  * j = 1 .. n_baby - 1 (he_rotate_many; one level >= W's, Z's scale, uniform
  * strides in that order; NULL when n_baby = 1); the step rotates W by j u once
  * for all blocks, sums the n_baby products per block without relinearising,
- * and relinearises and rescales once: per block log2(c / n_baby) rotations
- * instead of log2 c.  keys then also hold the rotations j u (j < n_baby).
+ * and relinearises and rescales once; the column or giant sum then runs over
+ * c / n_baby terms instead of c.  keys then also hold the rotations j u
+ * (j < n_baby).
  * Feature-major with 1 < n_baby < c and c / n_baby <= 16, the giant steps
  * g n_baby r (0 < g < c / n_baby; they form a group of rotations, c r = N/2)
  * are taken as one hoisted sum, x + sum_g Rot(x, g n_baby r): one ModUp of
  * x's a-part, every rotation's inner product summed in Q u P, one ModDown;
- * keys then hold every g n_baby r instead of the powers of two from n_baby r.
+ * keys then hold every g n_baby r.  Otherwise the feature-major giant sum is
+ * rotate-and-add doubling over r n_baby 2^k (n_baby 2^k < c).
  * Zk (nullable): the step's data terms precomputed by he_lr_data_terms for
  * the same Z, W level and scale, coef, eta_over_n, w_decay and layout
  * (checked: levels, scales and uniform strides; HE_ESCALE when a scale differs);

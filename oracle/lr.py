@@ -308,11 +308,14 @@ def slot_sum_groups(r):
 
 
 def rotation_steps(c, r, layout=ROWS, n_baby=1):
-    """Rotation steps used by the step.  Row-major: +-2^k (k < log2 c) and
-    c*2^k (k < log2 r).  Feature-major: r*2^k (k < log2 c) and +-t for the
-    steps t of slot_sum_groups(r).  With n_baby > 1 baby steps also b*u for
-    b < n_baby (u = r feature-major, 1 row-major), and for a hoisted giant
-    sum the steps g n_baby r, g < c / n_baby."""
+    """Rotation steps used by the step (reading 28 for the slot sums).
+    Row-major: the baby steps b < n_baby, n_baby * t for the steps t of
+    slot_sum_groups(c / n_baby) (the column sum), -t for those of
+    slot_sum_groups(c) (the replication), c * t for those of
+    slot_sum_groups(r) (the row sum).  Feature-major: r*2^k (k < log2 c) and
+    +-t for the steps t of slot_sum_groups(r), with n_baby > 1 also b*r for
+    b < n_baby, and for a hoisted giant sum the steps g n_baby r,
+    g < c / n_baby."""
     if layout == FEATURES:
         st = [b * r for b in range(3, n_baby) if b & (b - 1)]
         if giant_hoisted(c, layout, n_baby):
@@ -325,16 +328,15 @@ def rotation_steps(c, r, layout=ROWS, n_baby=1):
             for t in grp:
                 st += [t, -t]
         return st
-    st = [b for b in range(3, n_baby) if b & (b - 1)]
-    t = 1
-    while t < c:
-        st += [t, -t]
-        t *= 2
-    t = 1
-    while t < r:
-        st.append(t * c)
-        t *= 2
-    return st
+    nb = max(n_baby, 1)
+    st = set(b for b in range(1, nb))
+    for grp in slot_sum_groups(c // nb):
+        st.update(nb * t for t in grp)
+    for grp in slot_sum_groups(c):
+        st.update(-t for t in grp)
+    for grp in slot_sum_groups(r):
+        st.update(c * t for t in grp)
+    return sorted(st)
 
 
 # ---------------------------------------------------------------- encrypted step
@@ -361,14 +363,11 @@ def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_dec
         else:
             u = O.rescale(P, O.mul(P, O.drop(zb, l), W, keys), scale=pl["s1"])
             t = 1
-        while t < c:
-            u = O.add(P, u, O.rotate(P, u, t, keys))
-            t *= 2
+        for grp in slot_sum_groups(c // t):  # column sum (reading 28)
+            u = O.rotate_sum_hoisted(P, u, [t * s for s in grp], keys)
         M = O.rescale(P, O.mul_plain(P, u, mask_m, pl["s_mask"]), scale=pl["sM"])
-        t = 1
-        while t < c:
-            M = O.add(P, M, O.rotate(P, M, -t, keys))
-            t *= 2
+        for grp in slot_sum_groups(c):  # replicate column 0 over the row
+            M = O.rotate_sum_hoisted(P, M, [-s for s in grp], keys)
         A = _rs_product(P, M, M)
         Z3 = O.rescale(P, O.mul_int(P, O.drop(zb, l - 1), pl["k3"]), scale=pl["sZ3"])
         B3 = _rs_product(P, M, Z3)
@@ -380,10 +379,8 @@ def lr_grad_step(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None, w_dec
         G = Gb if G is None else O.add_n(P, l - 3, G, Gb)
     # one relinearisation and one rescale of the summed terms
     G = O.rescale(P, O.relin_n(P, G, pl["sC"] * float(P.q[l - 3]), l - 3, keys), scale=pl["sC"])
-    t = 1
-    while t < r:
-        G = O.add(P, G, O.rotate(P, G, t * c, keys))
-        t *= 2
+    for grp in slot_sum_groups(r):  # row sum
+        G = O.rotate_sum_hoisted(P, G, [c * s for s in grp], keys)
     g = O.CT(G.data, G.level, pl["s_g"])
     Wn = O.rescale(P, O.mul_int(P, O.drop(W, l - 3), pl["kW"]), scale=pl["s_g"])
     return O.add(P, Wn, g), g

@@ -90,16 +90,7 @@ class Run:
         self.ranges = minibatches(n, batch)
         blocks0, c, r = H.pack_blocks(Xtr[: min(batch, n)], ytr[: min(batch, n)], ctx.S)
         self.c, self.r = c, r
-        steps = []
-        t = 1
-        while t < c:
-            steps += [t, -t]
-            t *= 2
-        t = 1
-        while t < r:
-            steps.append(t * c)
-            t *= 2
-        self.keys = ctx.keygen(seed_keys, steps)
+        self.keys = ctx.keygen(seed_keys, H.rotation_steps(c, r))  # the row-major step's rotations
         L = ctx.n_q - 1
         self.Z = []
         idx = 0

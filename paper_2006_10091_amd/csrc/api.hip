@@ -761,6 +761,9 @@ struct TermData {
     long long z3s = 0, z1s = 0;
 };
 
+he_status slot_sum_hoisted(he_ctx *c, Arena &ar, int level, int B, u64 *x, long long xs, u64 *tmp, long long ts,
+                           long long unit, int count, const he_keys *keys);
+
 he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, const he_ct *Z, long long zbs, int b0,
                       int nb, const he_ct *W, const he_pt *mask, int cols, const he_keys *keys, bool accumulate,
                       const BabyData &bd, const TermData &td)
@@ -784,21 +787,15 @@ he_status step_blocks(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_plan &pl, c
         // D1: u = RS(relin(Z (x) W)), level l-1
         TRY(mul_relin_rescale(c, ar, s, l, nb, zp, zbs, zc, W->data, 0, wc, keys->rlk, s.U));
     }
-    // column sum: u += Rot(u, t), t = t0, 2 t0, .., cols/2
-    for (int t = t0; t < cols; t <<= 1) {
-        const u64 *key = find_rot_key(keys, galois_of(c, t));
-        if (!key) return HE_EKEY;
-        TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, galois_of(c, t), key, s.U, 2 * u1, s.U));  // U += Rot(U)
-    }
+    // column sum: u = sum_{j < cols / t0} Rot(u, j t0), grouped hoisted sums
+    // (s.R, unused by this layout, holds every other partial sum)
+    TRY(slot_sum_hoisted(c, ar, l - 1, nb, s.U, 2 * u1, s.R, 2 * u1, t0, cols / t0, keys));
     // mask column 0, rescale: M at level l-2
     hek::ewise(c, 3, l - 1, nb, 2, s.U, 2 * u1, u1, mask->data, 0, 0, s.U, 2 * u1, u1, 0);
     TRY(rescale_apply(c, ar, l - 1, nb, s.U, 2 * u1, s.M, 2 * (l - 1) * N));
     const long long m1 = (long long)(l - 1) * N;
-    for (int t = 1; t < cols; t <<= 1) {
-        const u64 *key = find_rot_key(keys, galois_of(c, -t));
-        if (!key) return HE_EKEY;
-        TRY(rotate_apply(c, ar, l - 2, nb, s.M, 2 * m1, galois_of(c, -t), key, s.M, 2 * m1, s.M));  // M += Rot(M)
-    }
+    // replicate column 0 over the row: M = sum_{j < cols} Rot(M, -j)
+    TRY(slot_sum_hoisted(c, ar, l - 2, nb, s.M, 2 * m1, s.R, 2 * m1, -1, cols, keys));
     // A = RS(M^2) ; Z3 = RS(k3 Z), B3 = RS(M Z3), degree 2 ; Z1 = RS(k1 Z)   (level l-3)
     TRY(mul_rescale3(c, ar, s, l - 2, nb, s.M, 2 * m1, m1, s.M, 2 * m1, m1, s.A));
     const u64 *z3p = s.Z3;
@@ -905,27 +902,6 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
     return last_error();
 }
 
-// log2(count) rotate-and-add rounds x += Rot(x, t * unit), t = 1, 2, .., count/2,
-// on B ciphertexts at `level` (batch stride xs, component stride (level+1) N),
-// every round one batched rotation of all B
-he_status rotate_sum_b(he_ctx *c, Arena &ar, int level, int B, u64 *x, long long xs, long long unit, int count,
-                       const he_keys *keys)
-{
-    for (int t = 1; t < count; t <<= 1) {
-        const u64 gal = galois_of(c, (long long)t * unit);
-        const u64 *key = find_rot_key(keys, gal);
-        if (!key) return HE_EKEY;
-        TRY(rotate_apply(c, ar, level, B, x, xs, gal, key, x, xs, x));  // x += Rot(x)
-    }
-    return HE_OK;
-}
-// the same on one ciphertext (tmp unused: the rounds run in place)
-he_status rotate_sum(he_ctx *c, Arena &ar, int level, u64 *x, u64 *tmp, long long unit, int count,
-                     const he_keys *keys)
-{
-    (void)tmp;
-    return rotate_sum_b(c, ar, level, 1, x, 2LL * (level + 1) * c->N, unit, count, keys);
-}
 
 // The rotation-index groups of a slot sum over count = 2^k slots: the k bits
 // of the index in ceil(k / 3) groups, sizes as even as possible (the smaller
@@ -947,13 +923,13 @@ static int slot_sum_groups(int count, int (*g)[2])
     return ng;
 }
 
-// x <- sum_{i < count} Rot(x, sign i) on B ciphertexts at `level` (batch
-// stride xs; count a power of two), one hoisted sum per index group of
-// slot_sum_groups: the group's rotations share one ModUp and one ModDown.  The
-// running sum alternates between x and tmp (B ciphertexts, batch stride ts)
-// and ends in x.
+// x <- sum_{i < count} Rot(x, i unit) on B ciphertexts at `level` (batch
+// stride xs; count a power of two; unit may be negative), one hoisted sum per
+// index group of slot_sum_groups: the group's rotations share one ModUp and
+// one ModDown.  The running sum alternates between x and tmp (B ciphertexts,
+// batch stride ts) and ends in x.
 he_status slot_sum_hoisted(he_ctx *c, Arena &ar, int level, int B, u64 *x, long long xs, u64 *tmp, long long ts,
-                           int sign, int count, const he_keys *keys)
+                           long long unit, int count, const he_keys *keys)
 {
     int grp[11][2];
     const int ng = slot_sum_groups(count, grp);
@@ -964,7 +940,7 @@ he_status slot_sum_hoisted(he_ctx *c, Arena &ar, int level, int B, u64 *x, long 
         hek::EntryGal eg;
         hek::EntryKeys ek;
         for (int j = 1; j <= n; ++j) {
-            eg.g[j - 1] = galois_of(c, (long long)sign * ((long long)j << grp[i][0]));
+            eg.g[j - 1] = galois_of(c, unit * ((long long)j << grp[i][0]));
             ek.k[j - 1] = find_rot_key(keys, eg.g[j - 1]);
             if (!ek.k[j - 1]) return HE_EKEY;
         }
@@ -977,6 +953,46 @@ he_status slot_sum_hoisted(he_ctx *c, Arena &ar, int level, int B, u64 *x, long 
         hek::ewise(c, 4, level, B, 2, in, is, lc, nullptr, 0, 0, x, xs, lc, 0);
     }
     return last_error();
+}
+
+// the rotations slot_sum_hoisted(unit, count) takes, all present in k
+static bool slot_sum_keys(he_ctx *c, const he_keys *k, long long unit, int count)
+{
+    int grp[11][2];
+    const int ng = slot_sum_groups(count, grp);
+    for (int i = 0; i < ng; ++i)
+        for (int j = 1; j < 1 << grp[i][1]; ++j)
+            if (!find_rot_key(k, galois_of(c, unit * ((long long)j << grp[i][0])))) return false;
+    return true;
+}
+
+// Every rotation key a gradient step of this layout and baby-step count
+// takes.  Feature-major: the margins' baby steps j rows (j < n_baby) and
+// giant steps (one hoisted sum of g n_baby rows, else doubling from n_baby
+// rows), the sample sum over the rows and the replication (grouped sums of
+// unit +1 and -1).  Row-major: baby steps j (j < n_baby), the column sum
+// (grouped, unit n_baby, cols / n_baby terms), the replication (unit -1, cols
+// terms) and the once-per-step row sum (unit cols, rows terms).
+he_status step_keys(he_ctx *c, const he_keys *k, int layout, int cols, int rows, int n_baby)
+{
+    const bool fm = layout == HE_LAYOUT_FEATURES;
+    const long long mu = fm ? rows : 1;
+    for (int j = 1; j < n_baby; ++j)
+        if (!find_rot_key(k, galois_of(c, (long long)j * mu))) return HE_EKEY;
+    bool ok;
+    if (fm) {
+        ok = slot_sum_keys(c, k, 1, rows) && slot_sum_keys(c, k, -1, rows);
+        if (giant_hoisted(layout, cols, n_baby)) {
+            for (int g = 1; g < cols / n_baby; ++g)
+                ok = ok && find_rot_key(k, galois_of(c, (long long)g * n_baby * rows));
+        } else {
+            for (int t = n_baby; t < cols; t <<= 1) ok = ok && find_rot_key(k, galois_of(c, (long long)t * rows));
+        }
+    } else {
+        ok = slot_sum_keys(c, k, n_baby, cols / n_baby) && slot_sum_keys(c, k, -1, cols) &&
+             slot_sum_keys(c, k, cols, rows);
+    }
+    return ok ? HE_OK : HE_EKEY;
 }
 
 // Run `body` captured into a HIP graph on first use of `key` and replayed
@@ -1277,8 +1293,9 @@ he_status step_impl(he_ctx *c, const he_lr_plan &pl, const he_ct *Z, int n_block
         TRY(slot_sum_hoisted(c, ar, l - 4, 1, s.Gm, 2 * g1, s.Rg, 2 * g1, -1, rows, keys));
         g = s.Gm;
     } else {
-        // row sum: G += Rot(G, t * cols), t = 1, 2, .., rows/2   (level l-4)
-        TRY(rotate_sum(c, ar, l - 4, s.G, s.Rg, cols, rows, keys));
+        // row sum: G = sum_{j < rows} Rot(G, j cols), grouped hoisted sums   (level l-4)
+        const long long o1 = (long long)(l - 3) * N;
+        TRY(slot_sum_hoisted(c, ar, l - 4, 1, s.G, 2 * o1, s.Rg, 2 * o1, cols, rows, keys));
     }
     if (G_out) hek::ewise(c, 4, l - 4, 1, 2, g, 2 * g1, g1, nullptr, 0, 0, G_out->data, 2 * g1, g1, 0);
     // W' = RS(kW W) + g
@@ -2017,25 +2034,7 @@ static he_status step_args(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct 
         }
     }
     // every key the step needs, checked before any launch
-    const int pm = fm ? rows : cols;   // the +-2^k rotations
-    const int st = fm ? cols : rows;   // the unit * 2^k rotations
-    const long long unit = fm ? rows : cols;
-    for (int t = 1; t < pm; t <<= 1)
-        if (!find_rot_key(k, galois_of(c, t)) || !find_rot_key(k, galois_of(c, -t))) return HE_EKEY;
-    // the margin sum: baby steps j u (j < n_baby; u = rows feature-major, 1 row-major), giant steps
-    const long long mu = fm ? rows : 1;
-    for (int j = 1; j < n_baby; ++j)
-        if (!find_rot_key(k, galois_of(c, (long long)j * mu))) return HE_EKEY;
-    if (giant_hoisted(layout, cols, n_baby)) {
-        for (int g = 1; g < cols / n_baby; ++g)
-            if (!find_rot_key(k, galois_of(c, (long long)g * n_baby * mu))) return HE_EKEY;
-    } else {
-        for (int t = n_baby; t < cols; t <<= 1)
-            if (!find_rot_key(k, galois_of(c, (long long)t * mu))) return HE_EKEY;
-    }
-    for (int t = 1; t < st; t <<= 1)
-        if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
-    return HE_OK;
+    return step_keys(c, k, layout, cols, rows, n_baby);
 }
 
 he_status he_lr_grad_step(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, const he_pt *mask,
@@ -2113,16 +2112,7 @@ he_status he_lr_grad_step_seeded(he_ctx *c, const he_ct_seeded *Z, int n_blocks,
     he_lr_plan pl;
     TRY(hehost::plan_lr_step(c->q.data(), c->nq, l, sd.scale, W->scale, coef, eta_over_n, w_decay, layout, &pl));
     if (mask->scale != pl.s_mask) return HE_ESCALE;
-    const int pm = fm ? rows : cols;
-    const int st = fm ? cols : rows;
-    const long long unit = fm ? rows : cols;
-    for (int t = 1; t < pm; t <<= 1)
-        if (!find_rot_key(k, galois_of(c, t)) || !find_rot_key(k, galois_of(c, -t))) return HE_EKEY;
-    const long long mu = fm ? rows : 1;
-    for (int t = 1; t < cols; t <<= 1)
-        if (!find_rot_key(k, galois_of(c, (long long)t * mu))) return HE_EKEY;
-    for (int t = 1; t < st; t <<= 1)
-        if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
+    TRY(step_keys(c, k, layout, cols, rows, 1));
     TRY(ensure_ws(c, step_bytes(c, l, chunk, layout, 1) + al((size_t)chunk * 2 * (sd.level + 1) * c->N) * 8));
     BabyData bd;
     TermData td;
@@ -2785,7 +2775,7 @@ static he_status multi_impl(he_ctx *c, const he_lr_request *rq, int n, const std
         TRY(rescale_apply(c, ar, l - 3, n, m.G, 2 * r1, m.Gm, 2 * g1));
         TRY(slot_sum_hoisted(c, ar, l - 4, n, m.Gm, 2 * g1, m.Wk, 2 * g1, -1, rows, k));
     } else {
-        TRY(rotate_sum_b(c, ar, l - 4, n, m.G, 2 * r1, cols, rows, k));  // row sum
+        TRY(slot_sum_hoisted(c, ar, l - 4, n, m.G, 2 * r1, m.Wk, 2 * r1, cols, rows, k));  // row sum
     }
     hek::desc_ew(c, 4, m.tab + t_copy, n_copy, l - 3);
     // W' = RS(kW W) + g

@@ -860,25 +860,27 @@ def slot_sum_groups(count):
 def rotation_steps(c, r, layout=LAYOUT_ROWS, n_baby=1):
     """Rotation keys the step needs (with n_baby baby steps also j u, j < n_baby,
     u = baby_unit(layout, r); with a hoisted giant sum also g n_baby r,
-    g < c / n_baby).  Row-major: +-2^k (k < log2 c) and c 2^k (k < log2 r);
-    feature-major: r 2^k (k < log2 c) and +-t for every t of
-    slot_sum_groups(r)."""
-    pm, st, unit = (r, c, r) if layout == LAYOUT_FEATURES else (c, r, c)
+    g < c / n_baby).  Row-major: the baby steps j < n_baby, n_baby t for
+    every t of slot_sum_groups(c / n_baby) (the column sum), -t for every t
+    of slot_sum_groups(c) (the replication) and c t for every t of
+    slot_sum_groups(r) (the row sum); feature-major: r 2^k (k < log2 c) and
+    +-t for every t of slot_sum_groups(r)."""
     mu = baby_unit(layout, r)
-    out = [j * mu for j in range(3, n_baby) if j & (j - 1)]
-    if giant_hoisted(layout, c, n_baby):
-        out += [g * n_baby * r for g in range(3, c // n_baby) if g & (g - 1)]
     if layout == LAYOUT_FEATURES:
-        for grp in slot_sum_groups(pm):
+        out = [j * mu for j in range(3, n_baby) if j & (j - 1)]
+        if giant_hoisted(layout, c, n_baby):
+            out += [g * n_baby * r for g in range(3, c // n_baby) if g & (g - 1)]
+        for grp in slot_sum_groups(r):
             for t in grp:
                 out += [t, -t]
-    else:
         t = 1
-        while t < pm:
-            out += [t, -t]
+        while t < c:
+            out.append(t * r)
             t *= 2
-    t = 1
-    while t < st:
-        out.append(t * unit)
-        t *= 2
-    return out
+        return out
+    nb = max(n_baby, 1)
+    out = set(range(1, nb))
+    out |= {nb * t for grp in slot_sum_groups(c // nb) for t in grp}
+    out |= {-t for grp in slot_sum_groups(c) for t in grp}
+    out |= {c * t for grp in slot_sum_groups(r) for t in grp}
+    return sorted(out)

@@ -106,11 +106,18 @@ def test_inference_errors(env):
 def test_tables_and_workspace_come_from_torch(env):
     """Every device byte the context holds is a torch allocation made through
     the allocator callback; trimming gives the workspace back."""
+    import gc
     from paper_2006_10091_amd import he as H
-    before = torch.cuda.memory_allocated()
-    ctx = H.Context(*SMALL40)
-    held = ctx.mem.bytes
-    assert held > 0 and torch.cuda.memory_allocated() - before >= held
+    gc.collect()  # a cycle collected while the context is built would free earlier tests' tensors
+    gc.disable()
+    try:
+        before = torch.cuda.memory_allocated()
+        ctx = H.Context(*SMALL40)
+        held = ctx.mem.bytes
+        grew = torch.cuda.memory_allocated() - before
+    finally:
+        gc.enable()
+    assert held > 0 and grew >= held
     keys = ctx.keygen(5, [1])
     a, _ = ctx.upload(np.zeros((2, 5, ctx.N), dtype=np.uint64), 4, 1.0), None
     ctx.rotate(a, 1, keys)

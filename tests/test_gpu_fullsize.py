@@ -37,7 +37,7 @@ def env():
     ctx = H.Context(*CFG)
     X, y = synth.image_data(W["seed_data"], W["n"])
     blocks, c, r = H.pack_blocks(X, y, ctx.S)
-    steps = sorted(set(LR.rotation_steps(c, r, LR.ROWS, 16)) | set(LR.rotation_steps(c, r, LR.FEATURES, 16)))
+    steps = sorted({t for lay in (LR.ROWS, LR.FEATURES) for nb in (1, 16) for t in LR.rotation_steps(c, r, lay, nb)})
     gk = ctx.keygen(W["seed_keys"], steps)
     return dict(H=H, P=P, ctx=ctx, X=X, y=y, blocks=blocks, c=c, r=r, steps=steps, gk=gk)
 

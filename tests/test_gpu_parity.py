@@ -38,7 +38,10 @@ def small():
     ctx = H.Context(*cfg)
     X, y = synth.small_data()
     blocks, c, r = LR.pack_blocks(X, y, P.S)
-    steps = sorted(set(LR.rotation_steps(c, r, LR.ROWS, 16)) | set(LR.rotation_steps(c, r, LR.FEATURES)))
+    steps = set(LR.rotation_steps(c, r, LR.FEATURES))
+    for nb in (1, 4, 8, 16):  # the row-major baby-step counts the tests take
+        steps |= set(LR.rotation_steps(c, r, LR.ROWS, nb))
+    steps = sorted(steps)
     okeys = O.Keys(P, W["seed_keys"], rot_steps=steps)
     gkeys = ctx.keygen(W["seed_keys"], steps)
     return dict(W=W, P=P, ctx=ctx, X=X, y=y, blocks=blocks, c=c, r=r, okeys=okeys, gkeys=gkeys, H=H)
@@ -314,6 +317,13 @@ def test_lr_step_error_paths(small, small_step):
     with pytest.raises(H.HEError) as e:
         ctx.lr_grad_step(s["gZ"], s["gW"], mask, s["coef"], s["eta_n"], c, r, few)
     assert e.value.status == 5  # HE_EKEY: rotations missing
+    # keys that only the grouped slot sums take (no power of two): column sum 3,
+    # replication -12, row sum 3 c; each missing one is refused up front
+    for gone in (3, -12, 3 * c):
+        part = ctx.keygen(2001, [t for t in LR.rotation_steps(c, r, LR.ROWS, 1) if t != gone])
+        with pytest.raises(H.HEError) as e:
+            ctx.lr_grad_step(s["gZ"], s["gW"], mask, s["coef"], s["eta_n"], c, r, part)
+        assert e.value.status == 5, gone
     # data terms of another plan (here another eta / n: another Z3 scale) are refused
     eta2 = s["eta_n"] * 64
     assert LR.plan_lr_step(P.q, P.L, P.delta, P.delta, s["coef"], eta2)["sZ3"] != s["pl"]["sZ3"]
@@ -583,10 +593,15 @@ def test_lr_step_feature_major_errors(small, small40):
     with pytest.raises(H.HEError) as e:
         ctx.lr_grad_step(Z, Wc, mask, coef, 1 / 256, c, r, small["gkeys"], layout=2)
     assert e.value.status == 1
-    rk = ctx.keygen(3, LR.rotation_steps(c, r))  # row-major keys lack -16 .. -128
+    rk = ctx.keygen(3, LR.rotation_steps(c, r))  # row-major keys lack -16 .. -224
     with pytest.raises(H.HEError) as e:
         ctx.lr_grad_step(Z, Wc, mask, coef, 1 / 256, c, r, rk, layout=H.LAYOUT_FEATURES)
     assert e.value.status == 5
+    for gone in (12, -12):  # taken only by the grouped sample sum and replication
+        part = ctx.keygen(3, [t for t in LR.rotation_steps(c, r, LR.FEATURES) if t != gone])
+        with pytest.raises(H.HEError) as e:
+            ctx.lr_grad_step(Z, Wc, mask, coef, 1 / 256, c, r, part, layout=H.LAYOUT_FEATURES)
+        assert e.value.status == 5, gone
 
 
 # ------------------------------------------------------------------ rings below 2^12 (unfused kernels)
