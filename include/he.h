@@ -399,7 +399,7 @@ he_status he_plan_lr_step(const uint64_t *q, int n_q, int level, double s_z, dou
  * are taken as one hoisted sum, x + sum_g Rot(x, g n_baby r): one ModUp of
  * x's a-part, every rotation's inner product summed in Q u P, one ModDown;
  * keys then hold every g n_baby r.  Otherwise the feature-major giant sum is
- * rotate-and-add doubling over r n_baby 2^k (n_baby 2^k < c).
+ * a grouped sum of unit n_baby r over c / n_baby terms, as the slot sums.
  * Zk (nullable): the step's data terms precomputed by he_lr_data_terms for
  * the same Z, W level and scale, coef, eta_over_n, w_decay and layout
  * (checked: levels, scales and uniform strides; HE_ESCALE when a scale differs);
@@ -487,9 +487,11 @@ he_status he_lr_data_terms(he_ctx *ctx, const he_ct *Z, int n_blocks, int w_leve
 /*
  * Encrypted inference on one worker's blocks: the margins m_i = w.x_i of
  * eq. (appr) (the first half of the step, for scoring data with the current
- * weights).  Per block: u = RS(relin(Z_b (x) W)), then the margin sum -- row
- * major: rotations 1, 2, .., c/2 (m_i at slot i*c); feature major: rotations
- * r, 2r, .., (c/2) r (m_i at every slot j*r + i).  Z, W, c, r, layout as for
+ * weights).  Per block: u = RS(relin(Z_b (x) W)), then the margin sum
+ * u = sum_{j < c} Rot(u, j unit) -- row major: unit 1 (m_i at slot i*c);
+ * feature major: unit r (m_i at every slot j*r + i) -- as grouped hoisted
+ * sums, the grouping of he_lr_grad_step's slot sums (keys: j*2^b*unit for
+ * each group).  Z, W, c, r, layout as for
  * he_lr_grad_step (W at any level >= 1, Z at a level >= W's); out[0..n_blocks)
  * caller memory for ciphertexts at W's level - 1, one uniform stride apart;
  * scale Z.scale * W.scale / q_level.  mode 0 / 1 / 2 as for he_lr_grad_step

@@ -283,9 +283,10 @@ def giant_hoisted(c, layout, n_baby):
 
 
 def slot_sum_groups(r):
-    """Reading 28: the feature-major step's two slot sums over r = 2^k slots
-    (inside each feature block, and the replication) are taken as one
-    hoisted sum per group of index bits.  The k bits split into
+    """Reading 28: every sum of the rotations by 0, u, 2u, .., (r - 1) u
+    (r = 2^k; the margin, column, row and feature-block slot sums and the
+    replications) is taken as one hoisted sum per group of index bits, the
+    rotations of a group scaled by u.  The k bits split into
     ceil(k / 3) groups whose sizes differ by at most one, the smaller
     groups on the low bits; a group of s bits starting at bit b contributes
     the rotations j * 2^b for j = 1 .. 2^s - 1.  Summing over every group in
@@ -312,23 +313,20 @@ def rotation_steps(c, r, layout=ROWS, n_baby=1):
     Row-major: the baby steps b < n_baby, n_baby * t for the steps t of
     slot_sum_groups(c / n_baby) (the column sum), -t for those of
     slot_sum_groups(c) (the replication), c * t for those of
-    slot_sum_groups(r) (the row sum).  Feature-major: r*2^k (k < log2 c) and
-    +-t for the steps t of slot_sum_groups(r), with n_baby > 1 also b*r for
-    b < n_baby, and for a hoisted giant sum the steps g n_baby r,
-    g < c / n_baby."""
-    if layout == FEATURES:
-        st = [b * r for b in range(3, n_baby) if b & (b - 1)]
-        if giant_hoisted(c, layout, n_baby):
-            st += [g * n_baby * r for g in range(3, c // n_baby) if g & (g - 1)]
-        t = 1
-        while t < c:
-            st.append(t * r)
-            t *= 2
-        for grp in slot_sum_groups(r):
-            for t in grp:
-                st += [t, -t]
-        return st
+    slot_sum_groups(r) (the row sum).  Feature-major: the baby steps b r
+    (b < n_baby), the giant steps g n_baby r (g < c / n_baby) when hoisted,
+    else n_baby r t for the steps t of slot_sum_groups(c / n_baby), and +-t
+    for those of slot_sum_groups(r).  With n_baby = 1 the set also holds the
+    margins of lr_margins / lr_infer in the same layout."""
     nb = max(n_baby, 1)
+    if layout == FEATURES:
+        st = set(b * r for b in range(1, nb))
+        if giant_hoisted(c, layout, nb):
+            st.update(g * nb * r for g in range(1, c // nb))
+        else:
+            st.update(nb * r * t for grp in slot_sum_groups(c // nb) for t in grp)
+        st.update(s * t for grp in slot_sum_groups(r) for t in grp for s in (1, -1))
+        return sorted(st)
     st = set(b for b in range(1, nb))
     for grp in slot_sum_groups(c // nb):
         st.update(nb * t for t in grp)
@@ -437,10 +435,9 @@ def _step_features(P, keys, Z, W, mask_m, c, r, pl, Zrot=None, n_baby=1):
             t = 1
         if giant_hoisted(c, FEATURES, n_baby):  # margins: the giant steps as one key switch
             u = O.rotate_sum_hoisted(P, u, [g * n_baby * r for g in range(1, c // n_baby)], keys)
-            t = c
-        while t < c:  # margins: cyclic sum over the feature blocks
-            u = O.add(P, u, O.rotate(P, u, t * r, keys))
-            t *= 2
+        else:  # margins: cyclic sum over the feature blocks t r, 2 t r, .., grouped (reading 28)
+            for grp in slot_sum_groups(c // t):
+                u = O.rotate_sum_hoisted(P, u, [t * r * s for s in grp], keys)
         M = u
         A = _rs_product(P, M, M)
         Z3 = O.rescale(P, O.mul_int(P, O.drop(zb, l), pl["k3"]), scale=pl["sZ3"])
@@ -533,17 +530,15 @@ def lr_grad_step_plain(P, keys, Z, W, mask_m, coef, eta_over_n, c, r, plan=None,
 # ---------------------------------------------------------------- encrypted inference
 def lr_margins(P, keys, Z, W, c, r, layout=ROWS):
     """The margins m_i = w.z_i per block (eq. (appr)'s inner products):
-    u = RS(relin(Z (x) W)), then rotate-and-add by t u, t = 1 .. c/2 (u = r
-    feature-major, 1 row-major)."""
+    u = RS(relin(Z (x) W)), then the sum of Rot(u, j unit) over j < c (unit
+    = r feature-major, 1 row-major) as grouped hoisted sums (reading 28)."""
     l = W.level
     unit = r if layout == FEATURES else 1
     out = []
     for zb in Z:
         u = O.rescale(P, O.mul(P, O.drop(zb, l), W, keys))
-        t = 1
-        while t < c:
-            u = O.add(P, u, O.rotate(P, u, t * unit, keys))
-            t *= 2
+        for grp in slot_sum_groups(c):
+            u = O.rotate_sum_hoisted(P, u, [unit * s for s in grp], keys)
         out.append(u)
     return out
 

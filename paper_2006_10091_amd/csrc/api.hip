@@ -866,12 +866,8 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
         TRY(rotate_sum_hoisted_apply(c, ar, l - 1, nb, s.U, 2 * u1, eg, ek, ng, s.R, 2 * u1));
         M = s.R;
     } else {
-        for (int t = t0; t < cols; t <<= 1) {
-            const u64 gal = galois_of(c, (long long)t * rows);
-            const u64 *key = find_rot_key(keys, gal);
-            if (!key) return HE_EKEY;
-            TRY(rotate_apply(c, ar, l - 1, nb, s.U, 2 * u1, gal, key, s.U, 2 * u1, s.U));  // U += Rot(U)
-        }
+        // U = sum_{j < cols / t0} Rot(U, j t0 rows), grouped hoisted sums (s.R: the other partial sums)
+        TRY(slot_sum_hoisted(c, ar, l - 1, nb, s.U, 2 * u1, s.R, 2 * u1, (long long)t0 * rows, cols / t0, keys));
     }
     // A = RS(M^2) ; Z3 = RS(k3 Z), B3 = RS(M Z3), degree 2 ; Z1 = RS(k1 Z)   (level l-2)
     TRY(mul_rescale3(c, ar, s, l - 1, nb, M, 2 * u1, u1, M, 2 * u1, u1, s.A));
@@ -968,9 +964,9 @@ static bool slot_sum_keys(he_ctx *c, const he_keys *k, long long unit, int count
 
 // Every rotation key a gradient step of this layout and baby-step count
 // takes.  Feature-major: the margins' baby steps j rows (j < n_baby) and
-// giant steps (one hoisted sum of g n_baby rows, else doubling from n_baby
-// rows), the sample sum over the rows and the replication (grouped sums of
-// unit +1 and -1).  Row-major: baby steps j (j < n_baby), the column sum
+// giant steps (one hoisted sum of g n_baby rows, else a grouped sum of unit
+// n_baby rows over cols / n_baby terms), the sample sum over the rows and the
+// replication (grouped sums of unit +1 and -1).  Row-major: baby steps j (j < n_baby), the column sum
 // (grouped, unit n_baby, cols / n_baby terms), the replication (unit -1, cols
 // terms) and the once-per-step row sum (unit cols, rows terms).
 he_status step_keys(he_ctx *c, const he_keys *k, int layout, int cols, int rows, int n_baby)
@@ -986,7 +982,7 @@ he_status step_keys(he_ctx *c, const he_keys *k, int layout, int cols, int rows,
             for (int g = 1; g < cols / n_baby; ++g)
                 ok = ok && find_rot_key(k, galois_of(c, (long long)g * n_baby * rows));
         } else {
-            for (int t = n_baby; t < cols; t <<= 1) ok = ok && find_rot_key(k, galois_of(c, (long long)t * rows));
+            ok = ok && slot_sum_keys(c, k, (long long)n_baby * rows, cols / n_baby);
         }
     } else {
         ok = slot_sum_keys(c, k, n_baby, cols / n_baby) && slot_sum_keys(c, k, -1, cols) &&
@@ -1165,7 +1161,8 @@ size_t margins_bytes(const he_ctx *c, int l, int nb)
 }
 
 // u = RS(relin(Z_b (x) W)) written straight into out (uniform batch stride
-// obs), then the margin sum in place: rotations by t * unit, t = 1 .. count/2
+// obs), then the margin sum in place: u = sum_{j < count} Rot(u, j unit) as
+// grouped hoisted sums (R holds every other partial sum)
 he_status margins_impl(he_ctx *c, const he_ct *Z, int n_blocks, long long zbs, const he_ct *W, long long unit,
                        int count, const he_keys *keys, int chunk, u64 *out, long long obs, size_t ws_off = 0)
 {
@@ -1182,12 +1179,7 @@ he_status margins_impl(he_ctx *c, const he_ct *Z, int n_blocks, long long zbs, c
         u64 *u = out + b0 * obs;
         hek::tensor_b(c, l, nb, Z[b0].data, chunk == 1 ? 0 : zbs, zc, W->data, 0, wc, T3, 3 * lc, lc);
         TRY(relin_rescale_apply(c, ar, l, nb, T3, 3 * lc, keys->rlk, u, obs));
-        for (int t = 1; t < count; t <<= 1) {
-            const u64 gal = galois_of(c, (long long)t * unit);
-            const u64 *key = find_rot_key(keys, gal);
-            if (!key) return HE_EKEY;
-            TRY(rotate_apply(c, ar, l - 1, nb, u, obs, gal, key, u, obs, u));  // u += Rot(u)
-        }
+        TRY(slot_sum_hoisted(c, ar, l - 1, nb, u, obs, R, 2 * u1, unit, count, keys));
     }
     return last_error();
 }
@@ -2874,10 +2866,7 @@ he_status margins_args(he_ctx *c, const he_ct *Z, int n_blocks, const he_ct *W, 
     }
     if (lz < l) return HE_ELEVEL;
     if (n_blocks > 1 && (zbs < 2LL * (lz + 1) * c->N || obs < 2LL * (out_level + 1) * c->N)) return HE_EINVAL;
-    const long long unit = layout == HE_LAYOUT_FEATURES ? rows : 1;
-    for (int t = 1; t < cols; t <<= 1)
-        if (!find_rot_key(k, galois_of(c, (long long)t * unit))) return HE_EKEY;
-    return HE_OK;
+    return slot_sum_keys(c, k, layout == HE_LAYOUT_FEATURES ? rows : 1, cols) ? HE_OK : HE_EKEY;
 }
 
 // p(u) of he_lr_infer for nb blocks: u [nb][2][l][N] (level l-1, batch stride

@@ -839,8 +839,9 @@ def giant_hoisted(layout, c, n_baby):
 
 
 def slot_sum_groups(count):
-    """The rotation-index groups of he_lr_grad_step's feature-major slot sums
-    over count = 2^k slots (one hoisted sum per group): the k bits of the
+    """The rotation-index groups of a slot sum over count = 2^k multiples of
+    a unit (he_lr_grad_step's and he_lr_margins' sums; one hoisted sum per
+    group, its rotations scaled by the unit): the k bits of the
     index in ceil(k / 3) groups, sizes as even as possible (the smaller ones
     first), low bits first; a group of s bits from bit b0 holds the
     rotations j 2^b0, j = 1 .. 2^s - 1."""
@@ -863,22 +864,21 @@ def rotation_steps(c, r, layout=LAYOUT_ROWS, n_baby=1):
     g < c / n_baby).  Row-major: the baby steps j < n_baby, n_baby t for
     every t of slot_sum_groups(c / n_baby) (the column sum), -t for every t
     of slot_sum_groups(c) (the replication) and c t for every t of
-    slot_sum_groups(r) (the row sum); feature-major: r 2^k (k < log2 c) and
-    +-t for every t of slot_sum_groups(r)."""
+    slot_sum_groups(r) (the row sum); feature-major: without a hoisted giant
+    sum n_baby r t for every t of slot_sum_groups(c / n_baby) (the margin
+    sum), and +-t for every t of slot_sum_groups(r) (the sample sum and the
+    replication).  With n_baby = 1 the set also serves he_lr_margins and
+    he_lr_infer in the same layout."""
     mu = baby_unit(layout, r)
-    if layout == LAYOUT_FEATURES:
-        out = [j * mu for j in range(3, n_baby) if j & (j - 1)]
-        if giant_hoisted(layout, c, n_baby):
-            out += [g * n_baby * r for g in range(3, c // n_baby) if g & (g - 1)]
-        for grp in slot_sum_groups(r):
-            for t in grp:
-                out += [t, -t]
-        t = 1
-        while t < c:
-            out.append(t * r)
-            t *= 2
-        return out
     nb = max(n_baby, 1)
+    if layout == LAYOUT_FEATURES:
+        out = {j * mu for j in range(1, nb)}
+        if giant_hoisted(layout, c, nb):
+            out |= {g * nb * r for g in range(1, c // nb)}
+        else:
+            out |= {nb * r * t for grp in slot_sum_groups(c // nb) for t in grp}
+        out |= {s * t for grp in slot_sum_groups(r) for t in grp for s in (1, -1)}
+        return sorted(out)
     out = set(range(1, nb))
     out |= {nb * t for grp in slot_sum_groups(c // nb) for t in grp}
     out |= {-t for grp in slot_sum_groups(c) for t in grp}

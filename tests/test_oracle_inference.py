@@ -37,7 +37,7 @@ def test_inference_decrypts_to_the_polynomial_of_the_margins(layout, loss):
     pw = LR.pack_weights_features if layout == LR.FEATURES else LR.pack_weights
     blocks, c, r = pack(X, y, P.S)
     unit = r if layout == LR.FEATURES else 1
-    keys = O.Keys(P, 5, rot_steps=[t * unit for t in (1, 2, 4, 8)])
+    keys = O.Keys(P, 5, rot_steps=[t * unit for g in LR.slot_sum_groups(c) for t in g])  # grouped margin sum
     if loss == "hinge":
         coef = [0.5875, -0.1005, 0.0008, -0.00039]  # Table 2's hinge row (nonzero m^2 term)
     else:

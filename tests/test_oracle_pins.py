@@ -668,7 +668,9 @@ def test_feature_major_packing_is_the_transpose():
     st = LR.rotation_steps(c, r, LR.FEATURES)
     # the slot sums over r = 256 = 2^8 slots: index bits in groups of 2, 3, 3
     slot = [1, 2, 3, 4, 8, 12, 16, 20, 24, 28, 32, 64, 96, 128, 160, 192, 224]
-    assert st[:4] == [256, 512, 1024, 2048] and sorted(st[4:]) == sorted([t * s for t in slot for s in (1, -1)])
+    # the margin sum over c = 16 feature blocks: groups {1, 2, 3}, {4, 8, 12} times r
+    assert st == sorted({t * r for t in (1, 2, 3, 4, 8, 12)} | {t * s for t in slot for s in (1, -1)})
+    assert LR.slot_sum_groups(16) == [[1, 2, 3], [4, 8, 12]]
     assert LR.slot_sum_groups(256) == [slot[:3], slot[3:10], slot[10:]]
     # baby steps b r for every b < n_baby, giant steps g n_baby r for every g < c / n_baby (hoisted)
     st8 = LR.rotation_steps(c, r, LR.FEATURES, 8)
