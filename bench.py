@@ -757,8 +757,10 @@ def cpu_baseline(Wk, threads, nb, c, r, n_baby=1):
     the margin relinearisation and the giant steps (one hoisted sum, or
     log2(c / n_baby) rotations); per step W's n_baby - 1 baby-step rotations,
     the one relinearisation of the summed degree-4 terms (three key switches,
-    each timed as a mul+relin+rescale) and the sample-sum and replicate
-    rotations.  The degree-2 products A and B3 (tensor and rescale),
+    each timed as a mul+relin+rescale) and the sample sum and replication,
+    counted as log2 r rotations each (the oracle takes them, and the giant
+    sum when not hoisted, as grouped sums of more key-switch products, so
+    this undercounts its time).  The degree-2 products A and B3 (tensor and rescale),
     plaintext products, additions, the data's baby-step copies (built once per
     shard) and the refresh are left out, so the CPU rate is an upper bound.
     The one-thread figure scales it by the measured all-threads / one-thread
