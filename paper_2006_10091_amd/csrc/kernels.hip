@@ -819,11 +819,14 @@ __device__ __forceinline__ void ntt_cols_body(const NttArgs &a, const PrimeInfo 
         for (int k = 0; k < S::E; ++k) limb[(long long)(tau + S::T * k) * N2 + col] = mul_shoup(v[k], sc, scs, q);
     }
 }
+// 4 waves per SIMD, the LDS bound of the 2^14..2^16 shapes: the ModDown
+// prologue variants would take 137-140 VGPRs (3 waves) and fit in 128 with a
+// 40-byte spill, measured 3% faster; the row pass's finish epilogue is not
+// capped (166 VGPRs; at 128 it spills 132 bytes and ran 27% slower)
 template <int LOGN, bool INV, int PRO>
-__global__ __launch_bounds__(LINE_THREADS) void ntt_cols_t(NttArgs a, const PrimeInfo *__restrict__ pinfo,
-                                                           const u64 *__restrict__ tw, const u64 *__restrict__ tws,
-                                                           const u64 *__restrict__ post, const double *__restrict__ twd,
-                                                           Fuse f)
+__global__ __launch_bounds__(LINE_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void ntt_cols_t(
+    NttArgs a, const PrimeInfo *__restrict__ pinfo, const u64 *__restrict__ tw, const u64 *__restrict__ tws,
+    const u64 *__restrict__ post, const double *__restrict__ twd, Fuse f)
 {
     using S = LineShape<(LOGN + 1) / 2>;
     __shared__ u64 lds[S::LINES * S::PADDED];
