@@ -506,8 +506,10 @@ __device__ __forceinline__ u64 reduce4q(u64 v, u64 q, u64 q2)
 //                                  limb's prime (ModDown: the special primes; rescale: q_l)
 //   pass B (inverse) PRO_SRC     : read the limb from another buffer (out-of-place)
 //   pass B epilogue  EPI_FINISH  : store base + (acc - x) P^{-1} instead of x
+//   pass B epilogue  EPI_FIN_ACC : the same with no base and no addend (rescales):
+//                                  fewer loads and registers
 enum { PRO_NONE = 0, PRO_MODDOWN = 2, PRO_SRC = 3, PRO_MDRS = 5 };
-enum { EPI_NONE = 0, EPI_FINISH = 1 };
+enum { EPI_NONE = 0, EPI_FINISH = 1, EPI_FIN_ACC = 2 };
 
 struct Fuse {
     const u64 *src;      // conversion sources (acc / last limbs) or source limbs (PRO_SRC)
@@ -835,7 +837,7 @@ __global__ __launch_bounds__(LINE_THREADS) __attribute__((amdgpu_waves_per_eu(4)
 }
 
 // pass B: rows.  Thread (line, tau) with tau fastest; LINES consecutive rows per workgroup.
-// MODE: forward EPI_NONE / EPI_FINISH; inverse PRO_NONE / PRO_SRC.
+// MODE: forward EPI_NONE / EPI_FINISH / EPI_FIN_ACC; inverse PRO_NONE / PRO_SRC.
 // xbuf (plain forward / inverse only): the intermediate's location (read by
 // the forward pass, written by the inverse one); null: in place.
 template <int LOGN, bool INV, int MODE>
@@ -845,7 +847,8 @@ __device__ __forceinline__ void ntt_rows_body(const NttArgs &a, const PrimeInfo 
                                               u64 *xbuf, int tid)
 {
     constexpr int LM = LOGN - (LOGN + 1) / 2, N1 = 1 << ((LOGN + 1) / 2);
-    constexpr bool FIN = !INV && MODE == EPI_FINISH;
+    constexpr bool FIN = !INV && (MODE == EPI_FINISH || MODE == EPI_FIN_ACC);
+    constexpr bool BASE = MODE == EPI_FINISH;  // base and addend may be present
     constexpr bool SRC = INV && MODE == PRO_SRC;
     using S = LineShape<LM>;
     u64 *limb;
@@ -875,8 +878,8 @@ __device__ __forceinline__ void ntt_rows_body(const NttArgs &a, const PrimeInfo 
             u64 av = f.acc[b * f.as + c * f.acs + roff + e];
             if (f.has_kacc) av = mul_mod(av, int_mod(f.kacc, p), p);
             u64 r = mul_shoup(sub_mod(av, x, q), f.pinv[2 * pos], f.pinv[2 * pos + 1], q);
-            if (c < f.nbase) r = add_mod(r, f.base[b * f.bs + c * f.bcs + roff + e], q);
-            if (f.add) r = add_mod(r, f.add[b * f.ads + c * f.adcs + roff + e], q);
+            if (BASE && c < f.nbase) r = add_mod(r, f.base[b * f.bs + c * f.bcs + roff + e], q);
+            if (BASE && f.add) r = add_mod(r, f.add[b * f.ads + c * f.adcs + roff + e], q);
             if (f.post) r = mul_shoup(r, f.post[2 * pos], f.post[2 * pos + 1], q);
             f.out[b * f.os + c * f.ocs + roff + e] = r;
         } else {
@@ -897,7 +900,7 @@ __device__ __forceinline__ void ntt_rows_body(const NttArgs &a, const PrimeInfo 
                 for (int k = 0; k < S::E; ++k) d[k] = d_from_s51(__builtin_nontemporal_load(in + tau + S::T * k));
             }
             // finish operands are loaded before the stages, so their latency overlaps them
-            u64 fa[FIN ? S::E : 1], fb[FIN ? S::E : 1];
+            u64 fa[FIN ? S::E : 1], fb[BASE ? S::E : 1];
             if (FIN) {
                 // fb = base + addend (each below q, so the sum is below 2q)
                 const u64 *ap = f.acc + b * f.as + c * f.acs + roff + tau;
@@ -906,7 +909,7 @@ __device__ __forceinline__ void ntt_rows_body(const NttArgs &a, const PrimeInfo 
 #pragma unroll
                 for (int k = 0; k < S::E; ++k) {
                     fa[k] = ap[S::T * k];
-                    fb[k] = (c < f.nbase ? bp[S::T * k] : 0) + (f.add ? dp[S::T * k] : 0);
+                    if (BASE) fb[k] = (c < f.nbase ? bp[S::T * k] : 0) + (f.add ? dp[S::T * k] : 0);
                 }
             }
             fwd_stages_ds<LM, true, true>(d, tau, h, N1, Wd, qd, qinv);
@@ -925,7 +928,8 @@ __device__ __forceinline__ void ntt_rows_body(const NttArgs &a, const PrimeInfo 
                     const double x = reduce_d(d[k], qd, qinv);
                     // kacc acc is a lazy product in (-q, 2q); minus x it stays within (-2q, 2q)
                     const double av = f.has_kacc ? mulmod_lazy_d(d_from_u52(fa[k]), ka, qd, qinv) : d_from_u52(fa[k]);
-                    const double r = mulmod_lazy_d(av - x, pinv, qd, qinv) + d_from_u52(fb[k]);
+                    double r = mulmod_lazy_d(av - x, pinv, qd, qinv);
+                    if (BASE) r += d_from_u52(fb[k]);
                     if (f.post)
                         op[S::T * k] = u52_from_d(reduce_d(mulmod_lazy_d(r, postd, qd, qinv), qd, qinv));
                     else
@@ -2922,7 +2926,10 @@ static void ntt_launch_t(he_ctx *c, NttArgs a, int nbatch, int npos, int dir, co
         if (dir > 0) {
             KSpan k2(c, epi == EPI_FINISH ? HE_K_MD_FINISH : HE_K_NTT_FWD_ROWS, epi_b, fl * (HB * LB + epi_m),
                      (l - fl) * (HB * LB + epi_m));
-            if (epi == EPI_FINISH)
+            if (epi == EPI_FINISH && f.nbase == 0 && !f.add)
+                ntt_rows_t<LOGN, false, EPI_FIN_ACC><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh,
+                                                                                 c->t.psi_d, f);
+            else if (epi == EPI_FINISH)
                 ntt_rows_t<LOGN, false, EPI_FINISH><<<gr, LINE_THREADS, 0, st>>>(a, pi, c->t.psi, c->t.psi_sh,
                                                                                 c->t.psi_d, f);
             else
