@@ -898,7 +898,6 @@ he_status step_blocks_features(he_ctx *c, Arena &ar, StepBufs &s, const he_lr_pl
     return last_error();
 }
 
-
 // The rotation-index groups of a slot sum over count = 2^k slots: the k bits
 // of the index in ceil(k / 3) groups, sizes as even as possible (the smaller
 // ones first), low bits first.  Group i is {b0, s}: it adds the rotations by
@@ -966,9 +965,10 @@ static bool slot_sum_keys(he_ctx *c, const he_keys *k, long long unit, int count
 // takes.  Feature-major: the margins' baby steps j rows (j < n_baby) and
 // giant steps (one hoisted sum of g n_baby rows, else a grouped sum of unit
 // n_baby rows over cols / n_baby terms), the sample sum over the rows and the
-// replication (grouped sums of unit +1 and -1).  Row-major: baby steps j (j < n_baby), the column sum
-// (grouped, unit n_baby, cols / n_baby terms), the replication (unit -1, cols
-// terms) and the once-per-step row sum (unit cols, rows terms).
+// replication (grouped sums of unit +1 and -1).  Row-major: baby steps j
+// (j < n_baby), the column sum (grouped, unit n_baby, cols / n_baby terms),
+// the replication (unit -1, cols terms) and the once-per-step row sum (unit
+// cols, rows terms).
 he_status step_keys(he_ctx *c, const he_keys *k, int layout, int cols, int rows, int n_baby)
 {
     const bool fm = layout == HE_LAYOUT_FEATURES;
