@@ -25,6 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 STATUS = {0: "HE_OK", 1: "HE_EINVAL", 2: "HE_ENOMEM", 3: "HE_ELEVEL", 4: "HE_ESCALE", 5: "HE_EKEY",
           6: "HE_EDEVICE"}
+HE_ENOMEM = 2  # a device allocation failed
 
 
 class HEError(RuntimeError):

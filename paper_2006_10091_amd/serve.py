@@ -106,13 +106,24 @@ def take_batch(queue, merge_blocks, merge_key=same_width, max_requests=MAX_MERGE
     return batch
 
 
+class DeviceMemoryFull(Exception):
+    """Raised by a backend's launch when the device could not hold the
+    launch's allocations although the budget admitted it (the allocator's
+    fragmentation across lanes' streams); nothing of the launch is left
+    running and its requests stay queued."""
+
+
 def run_loop(requests, backend, lanes_per_n, budget, merge_blocks=0, clock=time.perf_counter, idle=2e-4,
-             merge_key=same_width):
+             merge_key=same_width, stats=None):
     """The continuous-batching loop over a backend with
     bytes(batch) / launch(lane, batch) -> handle / done(handle) -> bool /
     finish(handle, batch).  Returns per-request (admit, complete) times
     relative to the run's start, the peak bytes in flight and the launches
-    (lists of request ids)."""
+    (lists of request ids).  A launch refused with DeviceMemoryFull while
+    others run leaves its requests at the head of their queue, and no ring
+    admits anything until a running launch completes (stats, when given,
+    counts these waits as memory_waits); refused with nothing running, it
+    is an error."""
     pending = collections.deque(sorted(requests, key=lambda q: q.arrival))
     queues = {k: collections.deque() for k in lanes_per_n}
     free = {k: list(range(v)) for k, v in lanes_per_n.items()}
@@ -123,6 +134,8 @@ def run_loop(requests, backend, lanes_per_n, budget, merge_blocks=0, clock=time.
     launches = []
     t0 = clock()
     total = len(requests)
+    mem_wait = False  # a launch was refused for memory: wait for a completion
+    waits = 0
     while len(times) < total or running:
         now = clock() - t0
         while pending and pending[0].arrival <= now:
@@ -130,7 +143,7 @@ def run_loop(requests, backend, lanes_per_n, budget, merge_blocks=0, clock=time.
             queues[q.log_n].append(q)
         progressed = False
         for k, qu in queues.items():
-            while qu and free[k]:
+            while qu and free[k] and not mem_wait:
                 batch = take_batch(qu, merge_blocks, merge_key)
                 b = backend.bytes(batch)
                 while len(batch) > 1 and in_flight + b > budget:
@@ -140,10 +153,18 @@ def run_loop(requests, backend, lanes_per_n, budget, merge_blocks=0, clock=time.
                     raise ValueError("request %d needs %d bytes, over the whole budget %d" % (batch[0].rid, b, budget))
                 if in_flight + b > budget:
                     break  # waits for memory; the other ring degree is not blocked
+                lane = free[k].pop()
+                try:
+                    h = backend.launch((k, lane), batch)
+                except DeviceMemoryFull:
+                    free[k].append(lane)
+                    if not running:
+                        raise
+                    mem_wait = True  # the batch stays queued, in order
+                    waits += 1
+                    break
                 for q in batch:
                     qu.remove(q)
-                lane = free[k].pop()
-                h = backend.launch((k, lane), batch)
                 running.append((k, lane, h, batch, b))
                 launches.append([q.rid for q in batch])
                 in_flight += b
@@ -162,6 +183,7 @@ def run_loop(requests, backend, lanes_per_n, budget, merge_blocks=0, clock=time.
                 backend.finish(h, batch)
                 free[k].append(lane)
                 in_flight -= b
+                mem_wait = False
                 progressed = True
             else:
                 still.append(item)
@@ -173,6 +195,8 @@ def run_loop(requests, backend, lanes_per_n, budget, merge_blocks=0, clock=time.
                     time.sleep(min(wait, 0.01))
             else:
                 time.sleep(idle)
+    if stats is not None:
+        stats["memory_waits"] = waits
     return times, peak, launches
 
 
@@ -297,6 +321,17 @@ class GpuBackend:
         return ctx.margins_bytes(L, nb, self.mode) + nb * (self.ct_bytes(q.log_n, L) + self.ct_bytes(q.log_n, L - 1))
 
     def launch(self, lane_key, batch):
+        try:
+            return self._launch(lane_key, batch)
+        except (H.HEError, self.torch.cuda.OutOfMemoryError) as e:
+            if isinstance(e, H.HEError) and e.status != H.HE_ENOMEM:
+                raise
+            # nothing was launched after the failed allocation; what was
+            # staged on the lane's stream finishes before its buffers go
+            self.lanes[lane_key]["stream"].synchronize()
+            raise DeviceMemoryFull(str(e)) from e
+
+    def _launch(self, lane_key, batch):
         torch = self.torch
         lane = self.lanes[lane_key]
         ctx, stream = lane["ctx"], lane["stream"]
@@ -398,10 +433,12 @@ def serve(requests, lanes=4, mode=1, budget_frac=0.8, budget=None, keep_results=
     base = be.torch.cuda.memory_allocated()
     be.torch.cuda.reset_peak_memory_stats()
     m0 = be.torch.cuda.memory_stats()
+    loop_stats = {}
     times, peak, launches = run_loop(requests, be, lanes_per_n, budget, merge_blocks=merge_blocks,
-                                     merge_key=be.merge_key)
+                                     merge_key=be.merge_key, stats=loop_stats)
     m1 = be.torch.cuda.memory_stats()
     stats = summarise(requests, times, launches)
+    stats.update(loop_stats)
     # the allocator's own work during the loop: device allocations and frees
     # (each free synchronises the device) and retries after running out
     for k in ("num_device_alloc", "num_device_free", "num_alloc_retries"):

@@ -119,6 +119,43 @@ def test_merged_launch_sheds_members_to_fit_the_budget():
     assert peak <= 25 and [len(x) for x in launches] == [2, 2]
 
 
+class TightBackend(FakeBackend):
+    """The device holds `cap` bytes whatever the budget says: a launch that
+    does not fit next to the running ones is refused with DeviceMemoryFull."""
+
+    def __init__(self, dur, nbytes, cap):
+        super().__init__(dur, nbytes)
+        self.cap, self.live, self.refused = cap, 0, []
+
+    def launch(self, lane, batch):
+        b = self.bytes(batch)
+        if self.live + b > self.cap:
+            self.refused.append([q.rid for q in batch])
+            raise SV.DeviceMemoryFull("over the device")
+        self.live += b
+        return super().launch(lane, batch)
+
+    def finish(self, h, batch):
+        self.live -= self.bytes(batch)
+        super().finish(h, batch)
+
+
+def test_launch_refused_for_memory_waits_for_a_completion_and_keeps_order():
+    # the budget admits two 10-byte launches at once, the device holds one
+    reqs = [_req(i, "infer", 64, 10) for i in range(4)]
+    be = TightBackend(lambda q: 0.003, lambda q: q.nb, cap=15)
+    st = {}
+    times, peak, launches = SV.run_loop(reqs, be, {16: 2}, budget=25, stats=st)
+    assert sorted(times) == [0, 1, 2, 3] and all(t[1] is not None for t in times.values())
+    assert launches == [[0], [1], [2], [3]]  # in queue order, one at a time
+    assert be.refused and st["memory_waits"] == len(be.refused)
+    for a, b in zip(launches, launches[1:]):  # each launch waited for the previous one's completion
+        assert times[b[0]][0] >= times[a[0]][1] - 1e-9
+    # refused with nothing running: an error, not a wait
+    with pytest.raises(SV.DeviceMemoryFull):
+        SV.run_loop(reqs[:1], TightBackend(lambda q: 0.0, lambda q: q.nb, cap=5), {16: 1}, budget=100)
+
+
 @pytest.mark.gpu
 def test_serving_results_identical_alone_and_in_the_mix():
     pytest.importorskip("torch")
