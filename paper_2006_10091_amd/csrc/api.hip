@@ -2650,7 +2650,7 @@ he_status he_batch_submit(he_ctx *c, he_op *ops, int n, const he_keys *k, int mo
 // Per request the per-block part of the step runs as in he_lr_grad_step (its
 // own plan, mask and blocks), into its own degree-4 term sum; the once-per-step
 // tail then runs once for all requests: the three relinearisation key switches
-// (one batched call per key), the rescale, the rotate-and-add rounds of every
+// (one batched call per key), the rescale, the grouped slot sums of every
 // request together, the masks and W updates through a device operand table.
 // Every kernel treats each entry on its own, so each request's W' and g are
 // bit-identical to its own he_lr_grad_step in mode 1.
